@@ -1,0 +1,234 @@
+"""FP64 CPU oracle of the RaRa-clipped Gaussian-splatting renderer.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only code allowed to import this package.  The
+renderer (``paper_2506_20202_amd``) never imports it and shares no code with
+it; the seeded input generators in ``paper_2506_20202_amd.scenes`` are the one
+shared module, and they contain none of the method's arithmetic.
+
+The arithmetic lives in ``rara_oracle.c`` (plain double-precision C, each
+function citing the passage of the paper it follows); this module marshals
+numpy arrays to it and assembles the per-pixel "event" report used to mask
+pixels where a float32 renderer may legitimately take the other side of a
+discontinuity (the 1/255 alpha skip, the 1e-4 transmittance stop, a ray
+grazing the traced ellipsoid, a centre within 1e-6 of a label boundary, a
+footprint within 1e-6 of an integer).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "_rara_oracle.so")
+_lib = None
+
+INVISIBLE, VISIBLE, CUTOFF = 0, 1, 2
+KAPPA = 3.0
+TILE = 16
+EV_ALPHA_MIN, EV_T_MIN, EV_SILHOUETTE, EV_INSIDE, EV_LABEL, EV_RECT = 1, 2, 4, 8, 16, 32
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int
+_D = ctypes.c_double
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        src = os.path.join(_HERE, "rara_oracle.c")
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(_SO)
+        L.oracle_classify.argtypes = [_I64, _P, _P, _P, _I32, _P, _P, _P]
+        L.oracle_classify.restype = _I32
+        L.oracle_project.argtypes = [_I64, _I32, _P, _P, _P, _P, _P, _I32, _I32, _D, _P, _I32,
+                                     _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+        L.oracle_project.restype = None
+        L.oracle_weight.argtypes = [_P, _P, _P, _P, _P, _D, _D, _P]
+        L.oracle_weight.restype = _D
+        L.oracle_lists.argtypes = [_I64, _P, _P, _P, _I32, _I32, _P, _P]
+        L.oracle_lists.restype = _I64
+        L.oracle_composite.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _I32, _P, _I32, _I32, _P,
+                                       _P, _P, _D, _I32, _I64, _I64, _D, _P, _P, _P, _P, _P, _P]
+        L.oracle_composite.restype = None
+        L.oracle_minv.argtypes = [_P, _P, _P]
+        L.oracle_rotation.argtypes = [_P, _P]
+        L.oracle_sh_basis.argtypes = [_I32, _D, _D, _D, _P]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"], "oracle arrays must be contiguous"
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def cam_array(cam) -> np.ndarray:
+    wc = np.asarray(cam.world_to_cam, np.float32).reshape(3, 4)
+    return np.concatenate([wc[:, :3].reshape(-1), wc[:, 3], np.array([cam.fx, cam.fy, cam.cx, cam.cy], np.float32)]
+                          ).astype(np.float32)
+
+
+def camera_centre(cam) -> np.ndarray:
+    wc = np.asarray(cam.world_to_cam, np.float32).astype(np.float64).reshape(3, 4)
+    return -wc[:, :3].T @ wc[:, 3]
+
+
+# ------------------------------------------------------------- primitives ----
+
+def classify(scene, plane):
+    """Sec. 3.2 labels (uint8 [n]), signed distances d_ep and radii 3 max(sigma)."""
+    n = scene.n
+    label = np.empty(n, np.uint8)
+    dep = np.empty(n, np.float64)
+    rad = np.empty(n, np.float64)
+    pa = plane.as_array()
+    ok = lib().oracle_classify(n, _p(scene.mean), _p(scene.scale), _p(pa), int(bool(plane.enabled)),
+                               _p(label), _p(dep), _p(rad))
+    if not ok:
+        raise ValueError("plane normal has zero length")
+    return label, dep, rad
+
+
+def project(scene, cam, label, project_all: bool = False) -> dict:
+    """EWA projection, footprint, tile rectangle and colour per Gaussian."""
+    n = scene.n
+    out = dict(
+        drawn=np.zeros(n, np.uint8), mean2d=np.zeros((n, 2)), cov2d=np.zeros((n, 3)), conic=np.zeros((n, 3)),
+        depth=np.zeros(n), depth32=np.zeros(n, np.float32), radius=np.zeros(n, np.int32),
+        rect=np.zeros((n, 4), np.int32), tiles_touched=np.zeros(n, np.int32), rgb=np.zeros((n, 3)),
+        minv=np.zeros((n, 9)), lam_max=np.zeros(n))
+    lib().oracle_project(n, scene.sh_degree, _p(scene.mean), _p(scene.scale), _p(scene.quat), _p(scene.sh),
+                         _p(cam_array(cam)), cam.width, cam.height, float(cam.near), _p(label), int(project_all),
+                         _p(out["drawn"]), _p(out["mean2d"]), _p(out["cov2d"]), _p(out["conic"]), _p(out["depth"]),
+                         _p(out["depth32"]), _p(out["radius"]), _p(out["rect"]), _p(out["tiles_touched"]),
+                         _p(out["rgb"]), _p(out["minv"]), _p(out["lam_max"]))
+    return out
+
+
+def tile_lists(proj: dict, cam):
+    """Per-tile id lists sorted by (float32 depth, index); offsets [T+1], ids [P]."""
+    tx, ty = (cam.width + TILE - 1) // TILE, (cam.height + TILE - 1) // TILE
+    n = proj["drawn"].shape[0]
+    offsets = np.zeros(tx * ty + 1, np.int64)
+    P = int(proj["tiles_touched"].astype(np.int64).sum())
+    ids = np.zeros(max(P, 1), np.int32)
+    got = lib().oracle_lists(n, _p(proj["drawn"]), _p(proj["rect"]), _p(proj["depth32"]), tx, ty,
+                             _p(offsets), _p(ids))
+    assert got == P
+    return offsets, ids[:P]
+
+
+def minv(quat, scale) -> np.ndarray:
+    q = np.ascontiguousarray(quat, np.float64)
+    s = np.ascontiguousarray(scale, np.float64)
+    m = np.zeros(9)
+    lib().oracle_minv(_p(q), _p(s), _p(m))
+    return m.reshape(3, 3)
+
+
+def rotation(quat) -> np.ndarray:
+    q = np.ascontiguousarray(quat, np.float64)
+    R = np.zeros(9)
+    lib().oracle_rotation(_p(q), _p(R))
+    return R.reshape(3, 3)
+
+
+def sh_basis(degree: int, direction) -> np.ndarray:
+    d = np.asarray(direction, np.float64)
+    Y = np.zeros(16)
+    lib().oracle_sh_basis(int(degree), float(d[0]), float(d[1]), float(d[2]), _p(Y))
+    return Y[: (degree + 1) ** 2]
+
+
+def weight(e, v, mu, quat, scale, plane_n, plane_d, kappa: float = KAPPA):
+    """Eq. (11) decay weight of one ray r(t) = e + t v (v normalised) and one
+    Gaussian; returns (w, info) with info = (disc/4A, t1, t2, t_p)."""
+    nn = np.asarray(plane_n, np.float64)
+    L = float(np.linalg.norm(nn))
+    nn = np.ascontiguousarray(nn / L)
+    d = float(plane_d) / L
+    v = np.asarray(v, np.float64)
+    v = np.ascontiguousarray(v / np.linalg.norm(v))
+    e = np.ascontiguousarray(e, np.float64)
+    mu = np.ascontiguousarray(mu, np.float64)
+    mi = np.ascontiguousarray(minv(quat, scale).reshape(-1))
+    info = np.zeros(4)
+    w = lib().oracle_weight(_p(e), _p(v), _p(mu), _p(mi), _p(nn), d, float(kappa), _p(info))
+    return w, info
+
+
+# ------------------------------------------------------------ full render ----
+
+def render(scene, cam, plane, bg=(0.0, 0.0, 0.0), kappa: float = KAPPA, trace_visible: bool = False,
+           tiles=None, tau_sil: float = 1e-3, events: bool = True) -> dict:
+    """Full oracle frame.  ``tiles`` = (first, last) row-major tile range to
+    composite (default: all).  Returns labels, projection, lists, image
+    [3][H][W], final_T, n_contrib, n_walked, per-pixel event flags and counters."""
+    label, dep, rad = classify(scene, plane)
+    proj = project(scene, cam, label)
+    offsets, ids = tile_lists(proj, cam)
+    W, H = cam.width, cam.height
+    T = (W + TILE - 1) // TILE * ((H + TILE - 1) // TILE)
+    t0, t1 = (0, T) if tiles is None else tiles
+    image = np.zeros((3, H, W))
+    final_T = np.ones(H * W)
+    n_contrib = np.zeros(H * W, np.int32)
+    n_walked = np.zeros(H * W, np.int32)
+    flags = np.zeros(H * W, np.uint32)
+    counters = np.zeros(8, np.int64)
+    bgv = np.asarray(bg, np.float32)
+    lib().oracle_composite(scene.n, _p(label), _p(proj["mean2d"]), _p(proj["conic"]), _p(scene.opacity),
+                           _p(proj["rgb"]), _p(scene.mean), _p(proj["minv"]), _p(plane.as_array()),
+                           int(bool(plane.enabled)), _p(cam_array(cam)), W, H, _p(bgv), _p(offsets), _p(ids),
+                           float(kappa), int(trace_visible), int(t0), int(t1), float(tau_sil), _p(image),
+                           _p(final_T), _p(n_contrib), _p(n_walked), _p(flags), _p(counters))
+    out = dict(label=label, d_ep=dep, radius3=rad, proj=proj, offsets=offsets, ids=ids, image=image,
+               final_T=final_T.reshape(H, W), n_contrib=n_contrib.reshape(H, W),
+               n_walked=n_walked.reshape(H, W), flags=flags.reshape(H, W), counters=counters)
+    if events:
+        out.update(boundary_events(scene, cam, plane, label, dep, rad))
+        out["flags"] = out["flags"] | out["boundary_mask"]
+    return out
+
+
+def boundary_events(scene, cam, plane, label, dep, rad, tol: float = 1e-6) -> dict:
+    """Gaussians within ``tol`` of a label, footprint or near-plane boundary,
+    and the per-pixel mask of the tiles their footprints cover."""
+    n = scene.n
+    lab_b = np.zeros(n, bool)
+    if plane.enabled:
+        lab_b = (np.abs(dep - rad) <= tol) | (np.abs(dep + rad) <= tol)
+    allp = project(scene, cam, label, project_all=True)
+    r3 = 3.0 * np.sqrt(np.maximum(allp["lam_max"], 0.0))
+
+    def near_int(x):
+        return np.abs(x - np.round(x)) <= tol * np.maximum(1.0, np.abs(x))
+
+    rr = np.ceil(r3)
+    valid = allp["lam_max"] > 0
+    rect_b = valid & (near_int(r3) | near_int(allp["mean2d"][:, 0] - rr) | near_int(allp["mean2d"][:, 0] + rr)
+                      | near_int(allp["mean2d"][:, 1] - rr) | near_int(allp["mean2d"][:, 1] + rr))
+    near_b = np.abs(allp["depth"] - cam.near) <= tol
+    W, H = cam.width, cam.height
+    mask = np.zeros((H, W), np.uint32)
+    for i in np.nonzero(lab_b | rect_b | near_b)[0]:
+        x0, y0, x1, y1 = allp["rect"][i]
+        if x1 <= x0 or y1 <= y0:
+            # not drawn even when projected: use a radius-sized box around the centre
+            mx, my = allp["mean2d"][i]
+            r = rr[i] + 1 if valid[i] else 0
+            x0, x1 = int(max(0, (mx - r) // TILE)), int(min((W - 1) // TILE, (mx + r) // TILE) + 1)
+            y0, y1 = int(max(0, (my - r) // TILE)), int(min((H - 1) // TILE, (my + r) // TILE) + 1)
+            if x1 <= x0 or y1 <= y0:
+                continue
+        bit = EV_LABEL if lab_b[i] else EV_RECT
+        mask[y0 * TILE:y1 * TILE, x0 * TILE:x1 * TILE] |= bit
+    return dict(n_label_boundary=int(lab_b.sum()), n_rect_boundary=int(rect_b.sum()),
+                n_near_boundary=int(near_b.sum()), boundary_mask=mask)

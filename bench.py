@@ -1,0 +1,265 @@
+"""Benchmark: RaRa-clipped frames per second on the general-scene workload
+(1,000,000 Gaussians, SH degree 3, 1920x1080, 16 orbit views x 16 plane
+offsets swept through the scene), scene resident in HBM, image left on the
+device.  One step = one full frame (preprocess + bin/sort + render) for the
+next (view, offset) of the sweep.
+
+Prints one JSON line.  Besides the contract fields it reports the plain
+(unclipped) frame rate over the same views, per-stage times from HIP events
+on the launch stream, Gaussian-pixel evaluations per second, the roofline of
+the dominant kernel and the FP64 oracle timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RaRa-clipped FPS @1080p/1M Gaussians; served p50/p99 latency vs plain"
+
+# Algorithmic work per Gaussian-pixel evaluation of the blend (FMA = 2 flops,
+# exp/sqrt/reciprocal = 1): offset 2, quadratic form 8, exp and opacity 2,
+# clamp and skip test 2, transmittance 3, colour 7  -> 24.
+# CUTOFF extra: delta 9, D 3, P 3, P.D 5, D.D 5, s_m 2, closest point 6,
+# |.|^2 5, h 3, near-root test 2, plane rate 4, midpoint value 4, weight 5 -> 56.
+FLOPS_EVAL = 24
+FLOPS_CUT = 56
+PEAK_FP32 = 157.3e12
+PEAK_HBM = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=256)
+    ap.add_argument("--warmup", type=int, default=16)
+    ap.add_argument("--workload", default="general", choices=["general", "strands"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=0, help="only run this many frames (for profilers)")
+    return ap.parse_args()
+
+
+def workload(name):
+    from paper_2506_20202_amd import scenes
+    if name == "general":
+        sc = scenes.general_scene(1)
+        cams = scenes.general_views()
+        planes = scenes.plane_sweep(sc, scenes.general_plane_normal(1), count=16)
+        frames = [(cams[v], planes[o]) for o in range(16) for v in range(16)]
+        desc = {"workload": "general scene, 1,000,000 Gaussians (64 clusters), SH3, 1920x1080, "
+                            "16 orbit views x 16 plane offsets", "gaussians": sc.n, "width": 1920, "height": 1080,
+                "views": 16, "plane_offsets": 16}
+    else:
+        sc = scenes.strand_scene(2)
+        cams = scenes.strand_views()
+        frames = [(cams[v], p) for v in range(8) for p in scenes.strand_planes(v)]
+        desc = {"workload": "strand scene, 100,000 strands x 32 = 3,200,000 Gaussians, SH1, 1024x1024, "
+                            "8 views x 4 oblique planes", "gaussians": sc.n, "width": 1024, "height": 1024,
+                "views": 8, "plane_offsets": 4}
+    return sc, frames, desc
+
+
+def count_evals(fr, n):
+    """Gaussian-pixel evaluations the method performs in the frame just
+    rendered: per pixel, the list entries examined before termination, and
+    how many of those are CUTOFF Gaussians (measurement only)."""
+    import torch
+    P = int(fr.bins.num_pairs.item())
+    W, H = fr.width, fr.height
+    walked = fr.out.n_walked.to(torch.int64)
+    E = int(walked.sum().item())
+    if P == 0:
+        return E, 0
+    vals = fr.bins.vals[:P].to(torch.int64)
+    cut = (fr.proj.label[vals] == 2).to(torch.int64)
+    csum = torch.zeros(P + 1, dtype=torch.int64, device=cut.device)
+    csum[1:] = torch.cumsum(cut, 0)
+    tx = (W + 15) // 16
+    ranges = fr.bins.ranges.view(-1, 2).to(torch.int64)
+    ys, xs = torch.meshgrid(torch.arange(H, device=cut.device), torch.arange(W, device=cut.device), indexing="ij")
+    tile = (ys // 16) * tx + (xs // 16)
+    start = ranges[tile, 0]
+    Ecut = int((csum[start + walked] - csum[start]).sum().item())
+    return E, Ecut
+
+
+def cpu_baseline(sc, cam, plane, budget_s):
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    lab, dep, rad = oracle.classify(sc, plane)
+    proj = oracle.project(sc, cam, lab)
+    offs, ids = oracle.tile_lists(proj, cam)
+    t_prep = time.perf_counter() - t0
+    T = len(offs) - 1
+    tx = (cam.width + 15) // 16
+    rows = (cam.height + 15) // 16
+    # calibrate on one tile row in the middle, then sample evenly spaced rows
+    import ctypes
+    L = oracle.lib()
+
+    def comp(t0_, t1_):
+        W, H = cam.width, cam.height
+        image = np.zeros((3, H, W)); fT = np.ones(H * W); nc = np.zeros(H * W, np.int32)
+        nw = np.zeros(H * W, np.int32); fl = np.zeros(H * W, np.uint32); cnt = np.zeros(8, np.int64)
+        bg = np.zeros(3, np.float32)
+        s = time.perf_counter()
+        L.oracle_composite(sc.n, oracle._p(lab), oracle._p(proj["mean2d"]), oracle._p(proj["conic"]),
+                           oracle._p(sc.opacity), oracle._p(proj["rgb"]), oracle._p(sc.mean), oracle._p(proj["minv"]),
+                           oracle._p(plane.as_array()), int(plane.enabled), oracle._p(oracle.cam_array(cam)), W, H,
+                           oracle._p(bg), oracle._p(offs), oracle._p(ids), 3.0, 0, int(t0_), int(t1_), 1e-3,
+                           oracle._p(image), oracle._p(fT), oracle._p(nc), oracle._p(nw), oracle._p(fl),
+                           oracle._p(cnt))
+        return time.perf_counter() - s, cnt
+    mid = rows // 2
+    t_row, _ = comp(mid * tx, (mid + 1) * tx)
+    nrows = int(max(1, min(rows, (budget_s - t_prep) / max(t_row, 1e-6))))
+    step = max(1, rows // nrows)
+    picked = list(range(0, rows, step))[:nrows]
+    t_comp, evals = 0.0, 0
+    for r in picked:
+        dt, cnt = comp(r * tx, (r + 1) * tx)
+        t_comp += dt
+        evals += int(cnt[0])
+    frac = len(picked) / rows
+    frame_s = t_prep + t_comp / frac
+    return {"value": 1.0 / frame_s, "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "sample": f"one frame (view 0, mid-sweep plane): full classify/project/sort "
+                      f"({t_prep:.2f} s) + composite of {len(picked)} of {rows} tile rows "
+                      f"({t_comp:.2f} s), composite scaled to the full frame",
+            "geval_per_s": evals / t_comp / 1e9 if t_comp > 0 else None}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2506_20202_amd import renderer as R
+
+    dev = torch.device("cuda:0")
+    t_setup = time.perf_counter()
+    sc, frames, desc = workload(args.workload)
+    ds = R.DeviceScene.from_scene(sc, dev)
+    W, H = frames[0][0].width, frames[0][0].height
+    print(f"[bench] scene n={sc.n} ready in {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
+
+    # capacity from one pass over every frame of the sweep (outside the timed region)
+    fr = R.Frame(sc.n, W, H, 8 * sc.n, dev)
+    maxP = 0
+    for cam, pl in frames:
+        R.render_checked(ds, fr, cam, pl)
+        maxP = max(maxP, int(fr.bins.num_pairs.item()))
+    plain_frames = [(cam, type(pl)(pl.n, pl.d, False)) for cam, pl in frames]
+    if not args.no_plain:
+        for cam, pl in plain_frames[:: max(1, len(frames) // 16)]:
+            R.render_checked(ds, fr, cam, pl)
+            maxP = max(maxP, int(fr.bins.num_pairs.item()))
+    fr.grow(int(maxP * 1.05) + 4096)
+    print(f"[bench] max pairs {maxP}, capacity {fr.capacity}", file=sys.stderr, flush=True)
+
+    steps = args.profile_steps if args.profile_steps else args.steps
+    stream = torch.cuda.current_stream(dev)
+
+    def run(frame_list, k0, k):
+        for i in range(k):
+            cam, pl = frame_list[(k0 + i) % len(frame_list)]
+            R.enqueue_frame(ds, fr, cam, pl)
+
+    run(frames, 0, args.warmup)
+    torch.cuda.synchronize()
+    if args.profile_steps:
+        run(frames, 0, steps)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_steps": steps}))
+        return
+
+    # ---- timed region: K clipped frames back to back ----
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    run(frames, 0, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = ev0.elapsed_time(ev1)
+    fps = steps / (ms_total / 1e3)
+    print(f"[bench] clipped: {fps:.1f} FPS ({ms_total / steps:.3f} ms/frame)", file=sys.stderr, flush=True)
+    assert int(fr.bins.overflow.item()) == 0
+
+    plain = None
+    if not args.no_plain:
+        run(plain_frames, 0, args.warmup)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        run(plain_frames, 0, steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_plain = ev0.elapsed_time(ev1)
+        plain = steps / (ms_plain / 1e3)
+        print(f"[bench] plain: {plain:.1f} FPS", file=sys.stderr, flush=True)
+
+    # ---- per-stage times (HIP events on the launch stream) and work counts ----
+    stage_ms = {"preprocess": 0.0, "bin_sort": 0.0, "render": 0.0}
+    E_tot, Ecut_tot, P_tot, n_live = 0, 0, 0, 0
+    nst = min(steps, len(frames))
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for i in range(nst):
+        cam, pl = frames[i % len(frames)]
+        evs[0].record(stream)
+        R.enqueue_frame(ds, fr, cam, pl, stages=("pre",))
+        evs[1].record(stream)
+        R.enqueue_frame(ds, fr, cam, pl, stages=("bin",))
+        evs[2].record(stream)
+        R.enqueue_frame(ds, fr, cam, pl, stages=("render",))
+        evs[3].record(stream)
+        torch.cuda.synchronize()
+        stage_ms["preprocess"] += evs[0].elapsed_time(evs[1])
+        stage_ms["bin_sort"] += evs[1].elapsed_time(evs[2])
+        stage_ms["render"] += evs[2].elapsed_time(evs[3])
+        E, Ec = count_evals(fr, sc.n)
+        E_tot += E
+        Ecut_tot += Ec
+        P_tot += int(fr.bins.num_pairs.item())
+        n_live += int((fr.proj.label != 0).sum().item())
+    for k in stage_ms:
+        stage_ms[k] /= nst
+    render_s = stage_ms["render"] / 1e3
+    flops = (E_tot * FLOPS_EVAL + Ecut_tot * FLOPS_CUT) / nst
+    achieved = flops / render_s
+    roofline = {"bound": "alu", "kernel": "blend_kernel (rara_render)", "achieved": achieved / 1e12,
+                "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                "flops_per_launch": flops, "evals_per_launch": E_tot / nst, "cutoff_evals_per_launch": Ecut_tot / nst,
+                "avg_launch_ms": stage_ms["render"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cam, pl = frames[8 * 16 if args.workload == "general" else 1]
+        cpu = cpu_baseline(sc, cam, pl, args.cpu_seconds)
+        print(f"[bench] oracle: {cpu['value']:.4f} frames/s on {cpu['cores']} threads", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC, "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": ms_total / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": dict(desc, parallelism="single GPU", pair_capacity=fr.capacity),
+        "plain_fps": plain, "clipped_over_plain_frame_time": (plain / fps) if plain else None,
+        "stage_ms": stage_ms, "pairs_per_frame": P_tot / nst, "live_gaussians_per_frame": n_live / nst,
+        "geval_per_s": E_tot / nst / render_s / 1e9,
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * rara.h -- C ABI of the MI355X (gfx950) RaRa-clipped Gaussian-splatting
+ * renderer ("RaRa Clipper: A Clipper for Gaussian Splatting Based on Ray
+ * Tracer and Rasterizer", arXiv 2506.20202).
+ *
+ * One frame is three calls on one HIP stream:
+ *   rara_preprocess  classify + project every Gaussian          (Sec. 3.2, eqs. 9-10)
+ *   rara_bin_sort    tile binning and tile|depth radix sort      (Sec. 3.1, depth order)
+ *   rara_render      per-tile front-to-back blend with the RaRa
+ *                    decay weight for CUTOFF Gaussians           (eqs. 2, 4-8, 11, 12; Alg. 1)
+ * and the differentiable path adds
+ *   rara_render_backward  gradients of a pixel loss w.r.t. the Gaussians and
+ *                    the plane (not in the paper, which is render-only).
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers owned by the caller; the library
+ *     allocates nothing and keeps no state between calls.  Struct arguments
+ *     are read on the host during the call only.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *     enqueues work; results are ready when the stream reaches them.
+ *   - Argument errors are reported synchronously (RARA_ERR_INVALID) before
+ *     anything is enqueued.  A failed kernel launch returns RARA_ERR_HIP.
+ *     Pair-capacity overflow is a device-side condition: see rara_bin_sort.
+ *   - Units: scale is the linear standard deviation sigma (not log), opacity
+ *     is the density delta after any activation, quat need not be unit length
+ *     (it is normalised), the plane need not be normalised ((n, d)/|n| is
+ *     used, |n| = 0 is rejected).  Camera: x right, y down, z forward; pixel
+ *     (i, j) has its centre at image coordinate (i, j) = (fx x/z + cx,
+ *     fy y/z + cy).
+ *   - Tiles are 16 x 16 pixels, row-major, tiles_x = ceil(W/16).
+ *   - No exception, longjmp or abort crosses this interface.
+ */
+#ifndef RARA_H
+#define RARA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RARA_OK = 0,
+    RARA_ERR_INVALID = 1,     /* bad argument (null pointer, size, plane, workspace too small) */
+    RARA_ERR_CAPACITY = 2,    /* reserved for callers: device overflow flag was found set   */
+    RARA_ERR_HIP = 3,         /* a HIP runtime call or kernel launch failed                 */
+    RARA_ERR_UNSUPPORTED = 4  /* e.g. sh_degree > 3, image larger than 65535 tiles a side   */
+} rara_status;
+
+/* Labels of Sec. 3.2 (written by rara_preprocess, one byte per Gaussian). */
+enum { RARA_LABEL_INVISIBLE = 0, RARA_LABEL_VISIBLE = 1, RARA_LABEL_CUTOFF = 2 };
+
+/* Gaussians (Sec. 3.1: centre mu, covariance R S^2 R^T, opacity density
+ * delta, colour c as real spherical harmonics of degree sh_degree <= 3).
+ * Structure-of-arrays float32, n columns each:
+ *   mean [3][n], scale [3][n], quat [4][n] (w, x, y, z), opacity [n],
+ *   sh [(sh_degree+1)^2][3][n] (coefficient-major, then RGB channel). */
+typedef struct {
+    int64_t n;
+    int32_t sh_degree;
+    const float* mean;
+    const float* scale;
+    const float* quat;
+    const float* opacity;
+    const float* sh;
+} rara_gaussians;
+
+/* Pinhole camera (Algorithm 1's pose T and resolution W x H): world point x
+ * maps to R_c x + t_c with world_to_cam = [R_c | t_c] row-major 3x4.
+ * Gaussians with camera depth <= near_z are not drawn. */
+typedef struct {
+    float world_to_cam[12];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float near_z;
+} rara_camera;
+
+/* Clipping plane of eq. (3): n.x + d = 0, the half-space n points into is
+ * visible.  enabled = 0 renders without clipping (every label VISIBLE). */
+typedef struct {
+    float n[3];
+    float d;
+    int32_t enabled;
+} rara_plane;
+
+/* Per-Gaussian results of rara_preprocess (caller-allocated, n entries each).
+ *   label [n] uint8            Sec. 3.2 label of every Gaussian.
+ *   splat [n] 48-byte records  written for drawn Gaussians only:
+ *        double mean2d[2]      projected centre (pixels)
+ *        float  conic[3]       inverse 2D covariance (a, b, c) = [[a, b], [b, c]]
+ *        float  opacity        delta
+ *        float  rgb[3]         colour, clamped at 0
+ *        uint32 label
+ *   ray  [n] 48-byte records   written for drawn CUTOFF Gaussians only: the
+ *        whitened-space ray set-up of eq. (4) (12 floats; layout private to the
+ *        library, consumed by rara_render / rara_render_backward).
+ *   depth [n] float            camera depth of drawn Gaussians.
+ *   rect  [n][4] uint16        tile rectangle tx0, ty0, tx1, ty1 (half-open).
+ *   tiles_touched [n] uint32   (tx1-tx0)(ty1-ty0) if drawn, else 0.
+ * A Gaussian is drawn when it is not INVISIBLE, its depth exceeds near_z and
+ * its footprint ceil(3 sqrt(lambda_max)) px box meets the image. */
+typedef struct {
+    uint8_t* label;
+    void* splat;
+    void* ray;
+    float* depth;
+    uint16_t* rect;
+    uint32_t* tiles_touched;
+} rara_projected;
+
+/* Binned, depth-sorted (tile, Gaussian) pairs (caller-allocated).
+ *   keys [pair_capacity] uint64  (tile << 32) | float32 bits of depth, sorted ascending,
+ *                                ties in Gaussian-index order.
+ *   vals [pair_capacity] uint32  Gaussian index of each key.
+ *   ranges [tiles][2] uint32     [start, end) of each tile's pairs.
+ *   num_pairs [1] int64          total pairs P of the frame (written even on overflow).
+ *   overflow  [1] int32          set to 1 when P > pair_capacity, else 0. */
+typedef struct {
+    uint64_t* keys;
+    uint32_t* vals;
+    uint32_t* ranges;
+    int64_t* num_pairs;
+    int32_t* overflow;
+} rara_binned;
+
+/* Gradients (caller-allocated; overwritten, not accumulated):
+ *   mean [3][n], scale [3][n], quat [4][n], opacity [n], sh [(D+1)^2][3][n]
+ *   with respect to the raw rara_gaussians inputs, and plane [4] with
+ *   respect to the raw (n, d) of rara_plane. */
+typedef struct {
+    float* mean;
+    float* scale;
+    float* quat;
+    float* opacity;
+    float* sh;
+    float* plane;
+} rara_grads;
+
+/* Workspace kinds for rara_workspace_bytes. */
+enum { RARA_WS_BIN_SORT = 0, RARA_WS_BACKWARD = 1 };
+
+/* Bytes of device workspace needed by rara_bin_sort (which = RARA_WS_BIN_SORT)
+ * or rara_render_backward (RARA_WS_BACKWARD) for n Gaussians, the given pair
+ * capacity and image size.  Returns 0 for invalid arguments. */
+size_t rara_workspace_bytes(int32_t which, int64_t n, int64_t pair_capacity, int32_t width, int32_t height);
+
+/* Sec. 3.2 (classification, Algorithm 1 step 1) and Sec. 3.4 eqs. (9)-(10)
+ * (EWA projection) for all g->n Gaussians, plus colour, footprint and the
+ * cutoff ray set-up.  Fills every array of *out (see rara_projected).
+ * Errors: RARA_ERR_INVALID for n < 0, null pointers (when n > 0), a
+ * non-positive image size or near_z, |plane n| = 0 with the plane enabled;
+ * RARA_ERR_UNSUPPORTED for sh_degree outside 0..3 or more than 65535 tiles per
+ * side. */
+rara_status rara_preprocess(const rara_gaussians* g, const rara_camera* cam, const rara_plane* plane,
+                            const rara_projected* out, void* stream);
+
+/* Tile binning and depth sort (the "sorted by depth" order of Sec. 3.1, per
+ * 16x16 tile): exclusive scan of tiles_touched, one (tile|depth, index) pair
+ * per drawn Gaussian and covered tile, LSD radix sort on the significant key
+ * bits, and per-tile ranges.  Needs `ws_bytes` >= rara_workspace_bytes(
+ * RARA_WS_BIN_SORT, n, pair_capacity, W, H) bytes of device workspace.
+ * Overflow: if the frame has more than pair_capacity pairs, *num_pairs holds
+ * the required count, *overflow is 1, no pair is written and rara_render
+ * leaves its outputs untouched; the caller checks after synchronising and
+ * retries with a larger capacity.
+ * Errors: RARA_ERR_INVALID for null pointers, n < 0, pair_capacity outside
+ * [1, 2^31), or a workspace that is too small. */
+rara_status rara_bin_sort(const rara_projected* proj, int64_t n, const rara_camera* cam, int64_t pair_capacity,
+                          void* workspace, size_t ws_bytes, const rara_binned* out, void* stream);
+
+/* Front-to-back compositing (eq. 2) per pixel over its tile's sorted list,
+ * with alpha = min(0.99, delta exp(-1/2 dx^T conic dx) w) (eq. 12 and
+ * Algorithm 1 step 3), skip when alpha < 1/255, stop before transmittance
+ * would drop below 1e-4.  w = 1 for VISIBLE Gaussians; for CUTOFF Gaussians
+ * w is eq. (11): the visible fraction of the pixel ray's chord through the
+ * 3-sigma ellipsoid (eqs. 4-8), and 1 when the ray meets it in fewer than two
+ * points with t >= 0.
+ * Outputs (device, caller-allocated): image [3][H][W] float = C + T bg,
+ * final_T [H][W] float, n_contrib [H][W] uint32 (1-based index in the tile
+ * list of the last composited Gaussian, used by the backward), and optional
+ * n_walked [H][W] uint32 (entries examined; may be NULL).  bg is a host
+ * array of 3 floats.
+ * Errors: RARA_ERR_INVALID for null pointers or a camera that differs in size
+ * from the one binned (not detectable: the caller must pass the same camera). */
+rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned* bins, const rara_camera* cam,
+                        const rara_plane* plane, const float* bg, float* image, float* final_T,
+                        uint32_t* n_contrib, uint32_t* n_walked, void* stream);
+
+/* Gradient of a scalar loss L given dL/dimage [3][H][W] (device), through the
+ * blend (re-walking each tile list from n_contrib back to front, with the
+ * transmittance rebuilt by division) and the clip weight of eq. (11), then
+ * through projection and colour to the raw inputs and the plane.  Uses the
+ * same g, cam, plane, proj, bins, final_T and n_contrib as the forward frame.
+ * Needs `ws_bytes` >= rara_workspace_bytes(RARA_WS_BACKWARD, n, ...) bytes.
+ * Every array of *grads is overwritten.
+ * Errors: as rara_render, plus RARA_ERR_INVALID for a short workspace. */
+rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam, const rara_plane* plane,
+                                 const rara_projected* proj, const rara_binned* bins, const float* final_T,
+                                 const uint32_t* n_contrib, const float* dL_dimage, const rara_grads* grads,
+                                 void* workspace, size_t ws_bytes, void* stream);
+
+/* Static description of a status code (never NULL). */
+const char* rara_status_string(rara_status s);
+
+/* Library version string, e.g. "rara 0.1 gfx950". */
+const char* rara_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RARA_H */

@@ -1,0 +1,144 @@
+"""ctypes binding of librara.so (include/rara.h).  Argument marshalling only:
+every step of the renderer runs in the library's HIP kernels.  Raises
+RuntimeError when the library has not been built -- there is no fallback."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librara.so")
+
+RARA_OK, RARA_ERR_INVALID, RARA_ERR_CAPACITY, RARA_ERR_HIP, RARA_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
+RARA_WS_BIN_SORT, RARA_WS_BACKWARD = 0, 1
+LABEL_INVISIBLE, LABEL_VISIBLE, LABEL_CUTOFF = 0, 1, 2
+SPLAT_BYTES = 48
+RAY_BYTES = 48
+
+_P = ctypes.c_void_p
+
+
+class Gaussians(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("mean", _P), ("scale", _P), ("quat", _P),
+                ("opacity", _P), ("sh", _P)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("world_to_cam", ctypes.c_float * 12), ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("near_z", ctypes.c_float)]
+
+
+class Plane(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_float * 3), ("d", ctypes.c_float), ("enabled", ctypes.c_int32)]
+
+
+class Projected(ctypes.Structure):
+    _fields_ = [("label", _P), ("splat", _P), ("ray", _P), ("depth", _P), ("rect", _P), ("tiles_touched", _P)]
+
+
+class Binned(ctypes.Structure):
+    _fields_ = [("keys", _P), ("vals", _P), ("ranges", _P), ("num_pairs", _P), ("overflow", _P)]
+
+
+class Grads(ctypes.Structure):
+    _fields_ = [("mean", _P), ("scale", _P), ("quat", _P), ("opacity", _P), ("sh", _P), ("plane", _P)]
+
+
+EXPORTS = ["rara_preprocess", "rara_bin_sort", "rara_render", "rara_render_backward", "rara_workspace_bytes",
+           "rara_status_string", "rara_version"]
+
+_lib = None
+
+
+class RaraError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__(f"{fn} failed: {status_string(status)} ({status})")
+        self.status = status
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"librara.so is not built ({LIB_PATH}); run __graft_entry__.build() "
+                               "or python -m paper_2506_20202_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        PG, PC, PP = ctypes.POINTER(Gaussians), ctypes.POINTER(Camera), ctypes.POINTER(Plane)
+        PJ, PB, PR = ctypes.POINTER(Projected), ctypes.POINTER(Binned), ctypes.POINTER(Grads)
+        L.rara_preprocess.argtypes = [PG, PC, PP, PJ, _P]
+        L.rara_bin_sort.argtypes = [PJ, ctypes.c_int64, PC, ctypes.c_int64, _P, ctypes.c_size_t, PB, _P]
+        L.rara_render.argtypes = [PJ, ctypes.c_int64, PB, PC, PP, ctypes.POINTER(ctypes.c_float), _P, _P, _P, _P, _P]
+        L.rara_render_backward.argtypes = [PG, PC, PP, PJ, PB, _P, _P, _P, PR, _P, ctypes.c_size_t, _P]
+        L.rara_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                           ctypes.c_int32]
+        L.rara_workspace_bytes.restype = ctypes.c_size_t
+        L.rara_status_string.argtypes = [ctypes.c_int]
+        L.rara_status_string.restype = ctypes.c_char_p
+        L.rara_version.restype = ctypes.c_char_p
+        for f in ("rara_preprocess", "rara_bin_sort", "rara_render", "rara_render_backward"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().rara_status_string(int(status)).decode()
+
+
+def version() -> str:
+    return lib().rara_version().decode()
+
+
+def _check(fn: str, status: int):
+    if status != RARA_OK:
+        raise RaraError(fn, status)
+
+
+def make_camera(cam) -> Camera:
+    c = Camera()
+    wc = [float(v) for v in list(cam.world_to_cam.reshape(-1))]
+    c.world_to_cam = (ctypes.c_float * 12)(*wc)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.near_z = float(cam.near)
+    return c
+
+
+def make_plane(plane) -> Plane:
+    p = Plane()
+    p.n = (ctypes.c_float * 3)(*[float(v) for v in plane.n])
+    p.d = float(plane.d)
+    p.enabled = 1 if plane.enabled else 0
+    return p
+
+
+def workspace_bytes(which: int, n: int, pair_capacity: int, width: int, height: int) -> int:
+    return int(lib().rara_workspace_bytes(which, n, pair_capacity, width, height))
+
+
+def preprocess(g: Gaussians, cam: Camera, plane: Plane, out: Projected, stream: int):
+    _check("rara_preprocess", lib().rara_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(plane),
+                                                    ctypes.byref(out), _P(stream)))
+
+
+def bin_sort(proj: Projected, n: int, cam: Camera, pair_capacity: int, workspace: int, ws_bytes: int,
+             out: Binned, stream: int):
+    _check("rara_bin_sort", lib().rara_bin_sort(ctypes.byref(proj), n, ctypes.byref(cam), pair_capacity,
+                                                _P(workspace), ws_bytes, ctypes.byref(out), _P(stream)))
+
+
+def render(proj: Projected, n: int, bins: Binned, cam: Camera, plane: Plane, bg, image: int, final_T: int,
+           n_contrib: int, n_walked: int, stream: int):
+    bgc = (ctypes.c_float * 3)(*[float(v) for v in bg])
+    _check("rara_render", lib().rara_render(ctypes.byref(proj), n, ctypes.byref(bins), ctypes.byref(cam),
+                                            ctypes.byref(plane), bgc, _P(image), _P(final_T), _P(n_contrib),
+                                            _P(n_walked or None), _P(stream)))
+
+
+def render_backward(g: Gaussians, cam: Camera, plane: Plane, proj: Projected, bins: Binned, final_T: int,
+                    n_contrib: int, dL_dimage: int, grads: Grads, workspace: int, ws_bytes: int, stream: int):
+    _check("rara_render_backward",
+           lib().rara_render_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(plane), ctypes.byref(proj),
+                                      ctypes.byref(bins), _P(final_T), _P(n_contrib), _P(dL_dimage),
+                                      ctypes.byref(grads), _P(workspace), ws_bytes, _P(stream)))

@@ -1,0 +1,194 @@
+// C ABI entry points (declared in include/rara.h): argument validation,
+// per-frame constants computed once on the host in double precision, and the
+// kernel launches.  Nothing here allocates or synchronises.
+#include <cmath>
+#include <cstring>
+
+#include "rara_internal.h"
+
+using namespace rara;
+
+namespace {
+
+bool make_cam(const rara_camera* c, CamParams* p)
+{
+    if (!c || c->width <= 0 || c->height <= 0 || !(c->near_z > 0.0f) || !(c->fx > 0.0f) || !(c->fy > 0.0f))
+        return false;
+    for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k) p->R[3 * r + k] = (double)c->world_to_cam[4 * r + k];
+        p->t[r] = (double)c->world_to_cam[4 * r + 3];
+    }
+    for (int k = 0; k < 3; ++k) p->e[k] = -(p->R[k] * p->t[0] + p->R[3 + k] * p->t[1] + p->R[6 + k] * p->t[2]);
+    p->fx = c->fx;
+    p->fy = c->fy;
+    p->cx = c->cx;
+    p->cy = c->cy;
+    p->near_z = c->near_z;
+    p->W = c->width;
+    p->H = c->height;
+    p->limx = kGuard * (p->W / 2.0) / p->fx;
+    p->limy = kGuard * (p->H / 2.0) / p->fy;
+    p->tiles_x = (c->width + kTile - 1) / kTile;
+    p->tiles_y = (c->height + kTile - 1) / kTile;
+    return true;
+}
+
+bool make_plane(const rara_plane* pl, PlaneParams* p)
+{
+    if (!pl) return false;
+    p->enabled = pl->enabled ? 1 : 0;
+    p->n[0] = p->n[1] = p->n[2] = 0.0;
+    p->d = 0.0;
+    if (!p->enabled) return true;
+    const double n0 = pl->n[0], n1 = pl->n[1], n2 = pl->n[2];
+    const double len = std::sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    if (!(len > 0.0) || !std::isfinite(len) || !std::isfinite((double)pl->d)) return false;
+    p->n[0] = n0 / len;
+    p->n[1] = n1 / len;
+    p->n[2] = n2 / len;
+    p->d = (double)pl->d / len;
+    return true;
+}
+
+int ceil_log2(int64_t v)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < v) ++b;
+    return b;
+}
+
+bool proj_ok(const rara_projected* p)
+{
+    return p && p->label && p->splat && p->ray && p->depth && p->rect && p->tiles_touched;
+}
+
+ProjPtrs proj_ptrs(const rara_projected* p)
+{
+    return ProjPtrs{p->label, static_cast<Splat*>(p->splat), static_cast<RayRec*>(p->ray), p->depth, p->rect,
+                    p->tiles_touched};
+}
+
+}  // namespace
+
+size_t rara::bin_workspace_layout(int64_t n, int64_t cap, BinWorkspace* ws, char* base)
+{
+    auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+    int64_t scan_blocks = (n + kScanBlock - 1) / kScanBlock;
+    if (scan_blocks < 1) scan_blocks = 1;
+    int64_t sort_blocks = (cap + kSortTile - 1) / kSortTile;
+    if (sort_blocks < 1) sort_blocks = 1;
+    size_t off = 0;
+    BinWorkspace w;
+    w.scan_blocks = scan_blocks;
+    w.sort_blocks = sort_blocks;
+    w.block_sums = reinterpret_cast<uint32_t*>(base + off);
+    off += align((size_t)scan_blocks * 4);
+    w.keys_alt = reinterpret_cast<uint64_t*>(base + off);
+    off += align((size_t)cap * 8);
+    w.vals_alt = reinterpret_cast<uint32_t*>(base + off);
+    off += align((size_t)cap * 4);
+    w.hist = reinterpret_cast<uint32_t*>(base + off);
+    off += align((size_t)kRadix * sort_blocks * 4);
+    w.digit_totals = reinterpret_cast<uint32_t*>(base + off);
+    off += align((size_t)kRadix * 4);
+    if (ws) *ws = w;
+    return off;
+}
+
+extern "C" {
+
+const char* rara_status_string(rara_status s)
+{
+    switch (s) {
+    case RARA_OK: return "ok";
+    case RARA_ERR_INVALID: return "invalid argument";
+    case RARA_ERR_CAPACITY: return "pair capacity exceeded";
+    case RARA_ERR_HIP: return "HIP runtime error";
+    case RARA_ERR_UNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+const char* rara_version(void) { return "rara 0.1 gfx950"; }
+
+size_t rara_workspace_bytes(int32_t which, int64_t n, int64_t pair_capacity, int32_t width, int32_t height)
+{
+    if (n < 0 || width <= 0 || height <= 0) return 0;
+    if (which == RARA_WS_BIN_SORT) {
+        if (pair_capacity < 1 || pair_capacity >= (int64_t(1) << 31)) return 0;
+        return bin_workspace_layout(n, pair_capacity, nullptr, nullptr);
+    }
+    if (which == RARA_WS_BACKWARD) {
+        return backward_workspace_bytes(n, width, height);
+    }
+    return 0;
+}
+
+rara_status rara_preprocess(const rara_gaussians* g, const rara_camera* cam, const rara_plane* plane,
+                            const rara_projected* out, void* stream)
+{
+    if (!g || g->n < 0 || !out) return RARA_ERR_INVALID;
+    if (g->sh_degree < 0 || g->sh_degree > 3) return RARA_ERR_UNSUPPORTED;
+    CamParams cp;
+    PlaneParams pp;
+    if (!make_cam(cam, &cp) || !make_plane(plane, &pp)) return RARA_ERR_INVALID;
+    if (cp.tiles_x > 65535 || cp.tiles_y > 65535) return RARA_ERR_UNSUPPORTED;
+    if (g->n == 0) return RARA_OK;
+    if (!g->mean || !g->scale || !g->quat || !g->opacity || !g->sh || !proj_ok(out)) return RARA_ERR_INVALID;
+    GaussPtrs gp{g->n, g->sh_degree, g->mean, g->scale, g->quat, g->opacity, g->sh};
+    const hipError_t e = launch_preprocess(gp, cp, pp, proj_ptrs(out), static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
+}
+
+rara_status rara_bin_sort(const rara_projected* proj, int64_t n, const rara_camera* cam, int64_t pair_capacity,
+                          void* workspace, size_t ws_bytes, const rara_binned* out, void* stream)
+{
+    if (!proj || n < 0 || !out || !workspace) return RARA_ERR_INVALID;
+    if (pair_capacity < 1 || pair_capacity >= (int64_t(1) << 31)) return RARA_ERR_INVALID;
+    if (n > 0 && !proj_ok(proj)) return RARA_ERR_INVALID;
+    if (!out->keys || !out->vals || !out->ranges || !out->num_pairs || !out->overflow) return RARA_ERR_INVALID;
+    CamParams cp;
+    if (!make_cam(cam, &cp)) return RARA_ERR_INVALID;
+    BinWorkspace ws;
+    const size_t need = bin_workspace_layout(n, pair_capacity, &ws, static_cast<char*>(workspace));
+    if (ws_bytes < need) return RARA_ERR_INVALID;
+    const int num_tiles = cp.tiles_x * cp.tiles_y;
+    const int key_bits = 31 + ceil_log2(num_tiles);
+    const int passes = (key_bits + kRadixBits - 1) / kRadixBits;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_bin(proj_ptrs(proj), n, cp, pair_capacity, ws, *out, (passes & 1) != 0, s);
+    if (e == hipSuccess) e = launch_sort(ws, pair_capacity, *out, passes, s);
+    if (e == hipSuccess) e = launch_ranges(*out, pair_capacity, num_tiles, s);
+    return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
+}
+
+rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned* bins, const rara_camera* cam,
+                        const rara_plane* plane, const float* bg, float* image, float* final_T, uint32_t* n_contrib,
+                        uint32_t* n_walked, void* stream)
+{
+    if (!proj || n < 0 || !bins || !bg || !image || !final_T || !n_contrib) return RARA_ERR_INVALID;
+    if (!proj->splat || !proj->ray || !bins->vals || !bins->ranges || !bins->overflow) return RARA_ERR_INVALID;
+    CamParams cp;
+    PlaneParams pp;
+    if (!make_cam(cam, &cp) || !make_plane(plane, &pp)) return RARA_ERR_INVALID;
+    RenderParams rp;
+    rp.W = cp.W;
+    rp.H = cp.H;
+    rp.tiles_x = cp.tiles_x;
+    rp.tiles_y = cp.tiles_y;
+    rp.num_tiles = cp.tiles_x * cp.tiles_y;
+    rp.plane_enabled = pp.enabled;
+    // per-pixel rate of the plane value: (R_c n)_{x,y} / f_{x,y}
+    const double rn0 = cp.R[0] * pp.n[0] + cp.R[1] * pp.n[1] + cp.R[2] * pp.n[2];
+    const double rn1 = cp.R[3] * pp.n[0] + cp.R[4] * pp.n[1] + cp.R[5] * pp.n[2];
+    rp.ax = (float)(rn0 / cp.fx);
+    rp.ay = (float)(rn1 / cp.fy);
+    rp.bg[0] = bg[0];
+    rp.bg[1] = bg[1];
+    rp.bg[2] = bg[2];
+    const hipError_t e = launch_blend(static_cast<const Splat*>(proj->splat), static_cast<const RayRec*>(proj->ray),
+                                      *bins, rp, image, final_T, n_contrib, n_walked, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,169 @@
+// Tile binning: exclusive prefix sum of tiles_touched and emission of one
+// (tile|depth, index) pair per drawn Gaussian and covered tile; per-tile
+// [start, end) ranges after the sort.
+//
+// The scan is reduce-then-scan over 256-Gaussian chunks.  Inside a chunk the
+// prefix is a wavefront-ballot scan: bit b of every lane's count is gathered
+// with one 64-lane ballot, and mbcnt (popcount of the ballot below the lane)
+// times 2^b is added to the lane's prefix; the loop stops at the highest bit
+// any lane still holds.  Four wave totals are combined through LDS.
+#include "rara_internal.h"
+
+namespace rara {
+
+namespace {
+
+__device__ inline uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Exclusive prefix of v over the 64 lanes of the wave and the wave total.
+__device__ inline uint32_t wave_ballot_scan(uint32_t v, uint32_t& total)
+{
+    uint32_t prefix = 0, tot = 0;
+    uint32_t rem = v;
+    for (int b = 0; b < 32; ++b) {
+        const uint64_t m = __ballot(rem & 1u);
+        prefix += lanes_below(m) << b;
+        tot += (uint32_t)__popcll(m) << b;
+        rem >>= 1;
+        if (__ballot(rem != 0u) == 0ull) break;
+    }
+    total = tot;
+    return prefix;
+}
+
+// Exclusive prefix over a 256-thread block (4 waves) and the block total.
+__device__ inline uint32_t block_ballot_scan(uint32_t v, uint32_t& total)
+{
+    __shared__ uint32_t wave_tot[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t wt;
+    const uint32_t p = wave_ballot_scan(v, wt);
+    if (lane == 0) wave_tot[wave] = wt;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wave_tot[w];
+    total = wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+    return before + p;
+}
+
+__global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t* __restrict__ tt, int64_t n,
+                                                          uint32_t* __restrict__ block_sums)
+{
+    const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    const uint32_t v = i < n ? tt[i] : 0u;
+    uint32_t total;
+    block_ballot_scan(v, total);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// Single-workgroup exclusive scan of the chunk sums; writes the pair count and
+// the overflow flag.
+__global__ __launch_bounds__(1024) void scan_blocks_kernel(uint32_t* __restrict__ sums, int64_t nb, int64_t cap,
+                                                           int64_t* __restrict__ num_pairs,
+                                                           int32_t* __restrict__ overflow)
+{
+    __shared__ uint64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t lo = t * per, hi = lo + per < nb ? lo + per : nb;
+    uint64_t acc = 0;
+    for (int64_t k = lo; k < hi; ++k) acc += sums[k];
+    part[t] = acc;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the 1024 partial sums
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint64_t add = t >= off ? part[t - off] : 0ull;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    uint64_t run = t > 0 ? part[t - 1] : 0ull;
+    for (int64_t k = lo; k < hi; ++k) {
+        const uint32_t v = sums[k];
+        sums[k] = (uint32_t)run;
+        run += v;
+    }
+    if (t == 1023) {
+        const uint64_t P = part[1023];
+        *num_pairs = (int64_t)P;
+        *overflow = P > (uint64_t)cap ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ tt, const uint16_t* __restrict__ rect,
+                                                   const float* __restrict__ depth, int64_t n,
+                                                   const uint32_t* __restrict__ block_off, int tiles_x,
+                                                   const int32_t* __restrict__ overflow, uint64_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    const uint32_t v = i < n ? tt[i] : 0u;
+    uint32_t total;
+    const uint32_t pre = block_ballot_scan(v, total);
+    if (*overflow) return;
+    if (v == 0) return;
+    uint32_t off = block_off[blockIdx.x] + pre;
+    const ushort4 rc = *reinterpret_cast<const ushort4*>(rect + 4 * i);
+    const uint64_t dbits = (uint64_t)__float_as_uint(depth[i]);
+    for (int y = rc.y; y < rc.w; ++y)
+        for (int x = rc.x; x < rc.z; ++x) {
+            const uint64_t tile = (uint64_t)(y * tiles_x + x);
+            keys[off] = (tile << 32) | dbits;
+            vals[off] = (uint32_t)i;
+            ++off;
+        }
+}
+
+__global__ __launch_bounds__(256) void ranges_clear_kernel(uint32_t* __restrict__ ranges, int num_tiles)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < num_tiles) reinterpret_cast<uint2*>(ranges)[t] = make_uint2(0u, 0u);
+}
+
+__global__ __launch_bounds__(256) void ranges_mark_kernel(const uint64_t* __restrict__ keys,
+                                                          const int64_t* __restrict__ num_pairs,
+                                                          const int32_t* __restrict__ overflow,
+                                                          uint32_t* __restrict__ ranges, uint32_t num_tiles)
+{
+    if (*overflow) return;
+    const int64_t P = *num_pairs;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t tile = (uint32_t)(keys[i] >> 32);
+        if (tile >= num_tiles) continue;
+        if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != tile) ranges[2 * tile] = (uint32_t)i;
+        if (i == P - 1 || (uint32_t)(keys[i + 1] >> 32) != tile) ranges[2 * tile + 1] = (uint32_t)(i + 1);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int64_t cap, const BinWorkspace& ws,
+                      const rara_binned& out, bool emit_to_alt, hipStream_t s)
+{
+    const int64_t nb = n > 0 ? ws.scan_blocks : 0;   // no chunks: the pair count is 0
+    if (n > 0) hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, n,
+                                  ws.block_sums);
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, ws.block_sums, nb, cap, out.num_pairs,
+                       out.overflow);
+    if (n > 0)
+        hipLaunchKernelGGL(emit_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, proj.rect, proj.depth, n,
+                           ws.block_sums, cam.tiles_x, out.overflow, emit_to_alt ? ws.keys_alt : out.keys,
+                           emit_to_alt ? ws.vals_alt : out.vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL(ranges_clear_kernel, dim3((num_tiles + 255) / 256), dim3(256), 0, s, out.ranges, num_tiles);
+    int64_t blocks = (cap + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(ranges_mark_kernel, dim3((unsigned)blocks), dim3(256), 0, s, out.keys, out.num_pairs,
+                       out.overflow, out.ranges, (uint32_t)num_tiles);
+    return hipGetLastError();
+}
+
+}  // namespace rara

@@ -1,0 +1,114 @@
+// Internal declarations of the gfx950 RaRa renderer: record layouts, launch
+// parameter blocks and the launch helpers each .hip file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rara.h"
+
+namespace rara {
+
+constexpr int kTile = 16;               // 16x16-pixel screen tiles
+constexpr float kAlphaMax = 0.99f;      // Algorithm 1 step 3 clamp
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 1e-4f;
+constexpr double kDilation = 0.3;       // px^2 added to the projected covariance
+constexpr double kGuard = 1.3;          // Jacobian guard band (fraction of the half-FOV)
+constexpr float kKappa2 = 9.0f;         // traced ellipsoid |M^-1 (x - mu)|^2 = 3^2
+constexpr float kLog2e = 1.4426950408889634f;
+
+// Projected splat, 48 bytes (see rara_projected in rara.h).
+struct alignas(16) Splat {
+    double mx, my;
+    float ca, cb, cc, op;
+    float r, g, b;
+    uint32_t label;
+};
+static_assert(sizeof(Splat) == 48, "splat record must be 48 bytes");
+
+// Whitened-space ray set-up of a CUTOFF Gaussian, 48 bytes.  With the pixel
+// offset (dx, dy) = pixel - mean2d, the pixel ray r(t) = e + t v has camera
+// depth t, and in unit-sphere space (M^-1 = S^-1 R^T, eq. 4)
+//   M^-1 (r(t) - mu) = z delta + s D,  t = z + s,
+//   delta = gx dx + gy dy,  D = d0 + delta,
+// with d0 = M^-1 (mu - e) / z and gx, gy = M^-1 R_c^T e_{x,y} / f_{x,y}.
+// The plane value along the ray is  d_ep + z (ax dx + ay dy) + s g,
+// g = g0 + ax dx + ay dy, g0 = n.(mu - e)/z, (ax, ay) = (R_c n)_{x,y} / f_{x,y}.
+struct alignas(16) RayRec {
+    float d0[3];
+    float gx[3];
+    float gy[3];
+    float z, dep, g0;
+};
+static_assert(sizeof(RayRec) == 48, "ray record must be 48 bytes");
+
+struct CamParams {
+    double R[9], t[3], e[3];
+    double fx, fy, cx, cy, near_z, limx, limy;
+    int W, H, tiles_x, tiles_y;
+};
+
+struct PlaneParams {
+    double n[3];
+    double d;
+    int enabled;
+};
+
+struct GaussPtrs {
+    int64_t n;
+    int sh_degree;
+    const float* mean;
+    const float* scale;
+    const float* quat;
+    const float* opacity;
+    const float* sh;
+};
+
+struct ProjPtrs {
+    uint8_t* label;
+    Splat* splat;
+    RayRec* ray;
+    float* depth;
+    uint16_t* rect;
+    uint32_t* tiles_touched;
+};
+
+struct RenderParams {
+    int W, H, tiles_x, tiles_y, num_tiles;
+    int plane_enabled;
+    float ax, ay;
+    float bg[3];
+};
+
+// ---- bin/sort workspace carve-up -------------------------------------------
+constexpr int kScanBlock = 256;      // Gaussians per scan chunk
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;       // keys per thread per sort tile
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+struct BinWorkspace {
+    uint32_t* block_sums;   // [scan_blocks]
+    uint64_t* keys_alt;     // [cap]
+    uint32_t* vals_alt;     // [cap]
+    uint32_t* hist;         // [kRadix][sort_blocks]
+    uint32_t* digit_totals; // [kRadix]
+    int64_t scan_blocks, sort_blocks;
+};
+
+size_t bin_workspace_layout(int64_t n, int64_t cap, BinWorkspace* ws, char* base);
+size_t backward_workspace_bytes(int64_t n, int32_t width, int32_t height);
+
+// ---- launch helpers (each returns the hipGetLastError of its launches) ----
+hipError_t launch_preprocess(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl, const ProjPtrs& out,
+                             hipStream_t s);
+hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int64_t cap, const BinWorkspace& ws,
+                      const rara_binned& out, bool emit_to_alt, hipStream_t s);
+hipError_t launch_sort(const BinWorkspace& ws, int64_t cap, const rara_binned& out, int passes, hipStream_t s);
+hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, hipStream_t s);
+hipError_t launch_blend(const Splat* splat, const RayRec* ray, const rara_binned& bins, const RenderParams& p,
+                        float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked, hipStream_t s);
+
+}  // namespace rara

@@ -1,0 +1,174 @@
+"""CPU tests of the C ABI: the library loads, exports every function the
+header declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rara.h")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2506_20202_amd import binding, build
+    if not os.path.exists(binding.LIB_PATH):
+        build.build()
+    return binding
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rara_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("rara_preprocess", "rara_bin_sort", "rara_render", "rara_render_backward", "rara_workspace_bytes",
+              "rara_status_string"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(B):
+    lib = B.lib()
+    nm = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\s[TW]\s+(\S+)", nm))
+    for f in declared_functions():
+        assert f in exported, f
+        assert hasattr(lib, f)
+    assert set(B.EXPORTS) <= set(declared_functions())
+
+
+def test_header_compiles_as_c(tmp_path):
+    src = tmp_path / "t.c"
+    src.write_text('#include "rara.h"\nint main(void){ rara_camera c; rara_plane p; (void)c; (void)p; '
+                   'return (int)sizeof(rara_projected) == 0; }\n')
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER), str(src), "-o",
+                    str(tmp_path / "t")], check=True)
+
+
+def test_status_strings_and_version(B):
+    assert B.status_string(B.RARA_OK) == "ok"
+    assert "invalid" in B.status_string(B.RARA_ERR_INVALID)
+    assert B.status_string(99) == "unknown status"
+    assert "gfx950" in B.version()
+
+
+def test_workspace_sizes(B):
+    assert B.workspace_bytes(B.RARA_WS_BIN_SORT, 1000, 0, 128, 128) == 0
+    assert B.workspace_bytes(B.RARA_WS_BIN_SORT, -1, 10, 128, 128) == 0
+    assert B.workspace_bytes(B.RARA_WS_BIN_SORT, 1000, 1 << 31, 128, 128) == 0
+    a = B.workspace_bytes(B.RARA_WS_BIN_SORT, 1000, 10_000, 128, 128)
+    b = B.workspace_bytes(B.RARA_WS_BIN_SORT, 1000, 100_000, 128, 128)
+    assert 0 < a < b
+    assert b >= 100_000 * 12     # ping-pong keys and values
+    assert B.workspace_bytes(7, 1000, 10_000, 128, 128) == 0
+
+
+def _cam(B, w=128, h=128):
+    from paper_2506_20202_amd import scenes
+    return B.make_camera(scenes.tiny_camera(w, h))
+
+
+def test_argument_validation_before_any_launch(B):
+    lib = B.lib()
+    g = B.Gaussians()
+    g.n, g.sh_degree = 10, 0
+    cam = _cam(B)
+    pl = B.Plane()
+    pl.n = (ctypes.c_float * 3)(0.0, 0.0, 1.0)
+    pl.enabled = 1
+    out = B.Projected()
+    # null Gaussian arrays
+    assert lib.rara_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(pl), ctypes.byref(out), None) \
+        == B.RARA_ERR_INVALID
+    # SH degree out of range
+    g.sh_degree = 4
+    assert lib.rara_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(pl), ctypes.byref(out), None) \
+        == B.RARA_ERR_UNSUPPORTED
+    g.sh_degree = 0
+    # zero plane normal with clipping enabled
+    pl0 = B.Plane()
+    pl0.enabled = 1
+    assert lib.rara_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(pl0), ctypes.byref(out), None) \
+        == B.RARA_ERR_INVALID
+    # bad camera
+    bad = _cam(B)
+    bad.width = 0
+    assert lib.rara_preprocess(ctypes.byref(g), ctypes.byref(bad), ctypes.byref(pl), ctypes.byref(out), None) \
+        == B.RARA_ERR_INVALID
+    bad = _cam(B)
+    bad.near_z = 0.0
+    assert lib.rara_preprocess(ctypes.byref(g), ctypes.byref(bad), ctypes.byref(pl), ctypes.byref(out), None) \
+        == B.RARA_ERR_INVALID
+    # negative n
+    g.n = -1
+    assert lib.rara_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(pl), ctypes.byref(out), None) \
+        == B.RARA_ERR_INVALID
+    # n == 0 is a valid no-op
+    g.n = 0
+    assert lib.rara_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(pl), ctypes.byref(out), None) \
+        == B.RARA_OK
+    # bin_sort: capacity and workspace checks
+    bins = B.Binned()
+    assert lib.rara_bin_sort(ctypes.byref(out), 10, ctypes.byref(cam), 100, None, 0, ctypes.byref(bins), None) \
+        == B.RARA_ERR_INVALID
+    fake = ctypes.c_void_p(0x1000)
+    bins.keys = bins.vals = bins.ranges = bins.num_pairs = bins.overflow = 0x1000
+    assert lib.rara_bin_sort(ctypes.byref(out), 0, ctypes.byref(cam), 100, fake, 16, ctypes.byref(bins), None) \
+        == B.RARA_ERR_INVALID   # workspace too small
+    assert lib.rara_bin_sort(ctypes.byref(out), 0, ctypes.byref(cam), 0, fake, 1 << 30, ctypes.byref(bins), None) \
+        == B.RARA_ERR_INVALID   # capacity < 1
+    # render: null outputs
+    bg = (ctypes.c_float * 3)(0, 0, 0)
+    assert lib.rara_render(ctypes.byref(out), 0, ctypes.byref(bins), ctypes.byref(cam), ctypes.byref(pl), bg, None,
+                           None, None, None, None) == B.RARA_ERR_INVALID
+
+
+def test_constants_agree_between_oracle_and_kernels():
+    """The oracle and the kernels are written separately; their conventions
+    (thresholds, dilation, guard band, tile size, kappa) must agree."""
+    internal = open(os.path.join(ROOT, "paper_2506_20202_amd", "csrc", "rara_internal.h")).read()
+    orc = open(os.path.join(ROOT, "oracle", "rara_oracle.c")).read()
+
+    def k(name):
+        return float(re.search(r"constexpr \w+ " + name + r" = ([0-9.e+-]+)", internal).group(1).rstrip("f"))
+
+    def o(name):
+        m = re.search(r"#define " + name + r" \(?([0-9.e+-]+)(?: / ([0-9.]+))?", orc)
+        v = float(m.group(1))
+        return v / float(m.group(2)) if m.group(2) else v
+
+    assert k("kTile") == o("OR_TILE")
+    assert abs(k("kAlphaMax") - o("OR_ALPHA_MAX")) < 1e-7
+    assert k("kTMin") == o("OR_T_MIN")
+    assert k("kDilation") == o("OR_DILATION")
+    assert k("kGuard") == o("OR_GUARD")
+    assert k("kKappa2") == 9.0
+    import oracle
+    assert oracle.KAPPA ** 2 == 9.0
+
+
+def test_sh_constants_agree_with_closed_forms():
+    """The kernel's SH normalisations (decimal literals) equal the closed forms
+    the oracle evaluates."""
+    src = open(os.path.join(ROOT, "paper_2506_20202_amd", "csrc", "preprocess.hip")).read()
+    lits = sorted(set(float(x) for x in re.findall(r"(\d\.\d{10,})", src)))
+    forms = sorted(set([np.sqrt(1 / (4 * np.pi)), np.sqrt(3 / (4 * np.pi)), np.sqrt(15 / (4 * np.pi)),
+                        np.sqrt(5 / (16 * np.pi)), np.sqrt(15 / (16 * np.pi)), np.sqrt(35 / (32 * np.pi)),
+                        np.sqrt(105 / (4 * np.pi)), np.sqrt(21 / (32 * np.pi)), np.sqrt(7 / (16 * np.pi)),
+                        np.sqrt(105 / (16 * np.pi))]))
+    assert len(lits) == len(forms)
+    np.testing.assert_allclose(lits, forms, rtol=1e-15)
+
+
+def test_product_path_fails_loudly_without_library(monkeypatch):
+    from paper_2506_20202_amd import binding
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "LIB_PATH", "/nonexistent/librara.so")
+    with pytest.raises(RuntimeError, match="not built"):
+        binding.lib()

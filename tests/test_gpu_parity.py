@@ -1,0 +1,193 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bar: labels, drawn sets, tile rectangles, float32 depth keys and per-tile
+lists identical; projected floats to float32 rounding; image max |error| over
+clamp(RGB, 0, 1) <= 1e-3 on every pixel the oracle does not flag as a
+discontinuity event (alpha at the 1/255 skip, transmittance at the 1e-4 stop,
+a ray grazing the traced ellipsoid, a Gaussian within 1e-6 of a label or
+footprint boundary).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_20202_amd import scenes
+from tests import gpu_helpers as H
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-3
+
+
+def _tile_pixel_mask(cam, t0, t1):
+    tx = (cam.width + 15) // 16
+    m = np.zeros((cam.height, cam.width), bool)
+    for t in range(t0, t1):
+        y, x = divmod(t, tx)
+        m[y * 16:(y + 1) * 16, x * 16:(x + 1) * 16] = True
+    return m
+
+
+def _full_check(sc, cam, pl, bg=(0.0, 0.0, 0.0)):
+    o = oracle.render(sc, cam, pl, bg=bg)
+    g = H.gpu_frame(sc, cam, pl, bg=bg)
+    nb = o["n_label_boundary"] + o["n_rect_boundary"] + o["n_near_boundary"]
+    H.check_projection(g, o, n_boundary_ok=nb)
+    assert g["P"] == len(o["ids"])
+    if nb == 0:
+        H.check_lists(g, o)
+    err, flagged, _ = H.image_error(g["image"], o)
+    print(f"n={sc.n} {cam.width}x{cam.height} P={g['P']} max_err={err:.2e} flagged={flagged:.4f} "
+          f"cutoff={(o['label'] == 2).sum()} counters={o['counters'].tolist()}", flush=True)
+    assert err <= TOL
+    assert flagged < 0.05
+    return g, o
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_tiny_scene_parity(seed):
+    _full_check(scenes.tiny_scene(seed), scenes.tiny_camera(), scenes.tiny_plane(seed))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_small_large_gaussians_parity(seed):
+    """A few large Gaussians covering many tiles, most of them CUTOFF."""
+    sc = scenes.small_scene(seed, n=24)
+    cam = scenes.small_camera(96)
+    rng = np.random.default_rng(70 + seed)
+    n = rng.standard_normal(3)
+    _full_check(sc, cam, scenes.Plane((n / np.linalg.norm(n)).astype(np.float32), float(rng.uniform(-0.1, 0.1))))
+
+
+def test_ragged_image_and_background():
+    """Image size not a multiple of the tile; nonzero background."""
+    sc = scenes.tiny_scene(7)
+    cam = scenes.tiny_camera(100, 75)
+    _full_check(sc, cam, scenes.tiny_plane(7), bg=(0.2, 0.4, 0.6))
+
+
+def test_plain_render_parity():
+    sc = scenes.tiny_scene(8)
+    _full_check(sc, scenes.tiny_camera(), scenes.Plane(np.array([0, 0, 1], np.float32), 0.0, enabled=False))
+
+
+def test_plane_beyond_scene_is_bitwise_plain():
+    """Table 2 / I1 on the GPU: the clipped image with the plane in front of
+    every Gaussian equals the unclipped GPU image bit for bit."""
+    sc = scenes.tiny_scene(0)
+    cam = scenes.tiny_camera()
+    n = scenes.tiny_plane(0).n
+    front = scenes.plane_sweep(sc, n, count=2)[0]
+    a = H.gpu_frame(sc, cam, front)
+    b = H.gpu_frame(sc, cam, scenes.Plane(n, 0.0, enabled=False))
+    assert (a["label"] == 1).all()
+    np.testing.assert_array_equal(a["image"], b["image"])
+    np.testing.assert_array_equal(a["final_T"], b["final_T"])
+
+
+def test_plane_behind_scene_gives_background():
+    sc = scenes.tiny_scene(0)
+    cam = scenes.tiny_camera()
+    back = scenes.plane_sweep(sc, scenes.tiny_plane(0).n, count=2)[-1]
+    g = H.gpu_frame(sc, cam, back, bg=(0.25, 0.5, 0.75))
+    assert (g["label"] == 0).all() and g["P"] == 0
+    np.testing.assert_array_equal(g["image"], np.broadcast_to(np.array([0.25, 0.5, 0.75], np.float32)[:, None, None],
+                                                              g["image"].shape).astype(np.float64))
+
+
+def test_forward_is_deterministic():
+    sc = scenes.tiny_scene(9)
+    cam = scenes.tiny_camera()
+    pl = scenes.tiny_plane(9)
+    a = H.gpu_frame(sc, cam, pl)
+    b = H.gpu_frame(sc, cam, pl)
+    for k in ("image", "final_T", "n_contrib", "keys", "vals"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_empty_scene():
+    sc = scenes.tiny_scene(0).subset(np.arange(0))
+    g = H.gpu_frame(sc, scenes.tiny_camera(), scenes.tiny_plane(0), bg=(0.1, 0.1, 0.1))
+    assert g["P"] == 0
+    np.testing.assert_allclose(g["image"], 0.1, atol=1e-7)
+
+
+def test_single_gaussian_closed_form():
+    """One on-axis Gaussian cut through its centre by a plane along the view
+    ray: alpha at the centre pixel is delta / 2."""
+    y00 = 1 / (2 * np.sqrt(np.pi))
+    sc = scenes.Scene(np.zeros((3, 1), np.float32), np.full((3, 1), 0.05, np.float32),
+                      np.array([[1], [0], [0], [0]], np.float32), np.array([0.8], np.float32),
+                      np.full((1, 3, 1), 0.5 / y00, np.float32), 0)
+    cam = scenes.tiny_camera(129, 129)
+    g = H.gpu_frame(sc, cam, scenes.Plane(np.array([0, 0, 1], np.float32), 0.0))
+    assert g["label"][0] == 2
+    np.testing.assert_allclose(g["image"][:, 64, 64], 0.4 * 1.0, atol=2e-6)
+
+
+def test_capacity_overflow_reported_and_frame_untouched():
+    import torch
+    from paper_2506_20202_amd import renderer as R
+    sc = scenes.tiny_scene(0)
+    cam = scenes.tiny_camera()
+    pl = scenes.tiny_plane(0)
+    o = oracle.render(sc, cam, pl, events=False)
+    P = len(o["ids"])
+    ds = R.DeviceScene.from_scene(sc, torch.device("cuda:0"))
+    fr = R.Frame(sc.n, cam.width, cam.height, P // 2, torch.device("cuda:0"))
+    fr.out.image.fill_(-7.0)
+    R.enqueue_frame(ds, fr, cam, pl)
+    torch.cuda.synchronize()
+    assert int(fr.bins.overflow.item()) == 1
+    assert int(fr.bins.num_pairs.item()) == P
+    assert (fr.out.image == -7.0).all()
+    out = R.render_checked(ds, fr, cam, pl)
+    assert int(fr.bins.overflow.item()) == 0 and fr.capacity >= P
+
+
+def test_general_scene_1080p_sampled():
+    """The 1M-Gaussian general scene at 1920x1080, mid-sweep plane: every
+    label, rectangle and tile list checked; the image checked on two bands of
+    tiles the oracle composites."""
+    sc = scenes.general_scene(1)
+    cam = scenes.general_views()[0]
+    pl = scenes.plane_sweep(sc, scenes.general_plane_normal(1))[8]
+    tx = cam.tiles[0]
+    bands = [(30 * tx, 32 * tx), (50 * tx + 20, 50 * tx + 80)]
+    g = H.gpu_frame(sc, cam, pl, capacity=12_000_000)
+    o = oracle.render(sc, cam, pl, tiles=bands[0], events=True)
+    nb = o["n_label_boundary"] + o["n_rect_boundary"] + o["n_near_boundary"]
+    H.check_projection(g, o, n_boundary_ok=nb)
+    assert g["P"] == len(o["ids"])
+    if nb == 0:
+        H.check_lists(g, o)
+    for t0, t1 in bands:
+        ob = oracle.render(sc, cam, pl, tiles=(t0, t1), events=True)
+        m = _tile_pixel_mask(cam, t0, t1)
+        err = np.abs(np.clip(g["image"], 0, 1) - np.clip(ob["image"], 0, 1)).max(axis=0)
+        ok = m & (ob["flags"] == 0)
+        print(f"band {t0}-{t1}: max_err={err[ok].max():.2e} flagged={(m & (ob['flags'] != 0)).sum()}/{m.sum()}",
+              flush=True)
+        assert err[ok].max() <= TOL
+
+
+def test_strand_scene_sampled():
+    """3.2M strand Gaussians (40:1:1) at 1024x1024 with an oblique plane:
+    labels and lists exact, image on a band of tiles through the cut."""
+    sc = scenes.strand_scene(2)
+    cam = scenes.strand_views()[0]
+    pl = scenes.strand_planes(0)[1]
+    g = H.gpu_frame(sc, cam, pl, capacity=40_000_000)
+    tx = cam.tiles[0]
+    band = (28 * tx, 30 * tx)
+    o = oracle.render(sc, cam, pl, tiles=band, events=True)
+    nb = o["n_label_boundary"] + o["n_rect_boundary"] + o["n_near_boundary"]
+    H.check_projection(g, o, n_boundary_ok=nb)
+    assert g["P"] == len(o["ids"])
+    H.check_lists(g, o, tiles=range(band[0], band[1]))
+    m = _tile_pixel_mask(cam, *band)
+    err = np.abs(np.clip(g["image"], 0, 1) - np.clip(o["image"], 0, 1)).max(axis=0)
+    ok = m & (o["flags"] == 0)
+    print(f"strands: P={g['P']} cutoff={(o['label'] == 2).sum()} max_err={err[ok].max():.2e} "
+          f"flagged={(m & (o['flags'] != 0)).sum()}/{m.sum()}", flush=True)
+    assert err[ok].max() <= TOL

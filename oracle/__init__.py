@@ -194,13 +194,13 @@ def render(scene, cam, plane, bg=(0.0, 0.0, 0.0), kappa: float = KAPPA, trace_vi
                n_walked=n_walked.reshape(H, W), flags=flags.reshape(H, W), counters=counters)
     if events:
         out.update(boundary_events(scene, cam, plane, label, dep, rad))
-        out["flags"] = out["flags"] | out["boundary_mask"]
     return out
 
 
 def boundary_events(scene, cam, plane, label, dep, rad, tol: float = 1e-6) -> dict:
-    """Gaussians within ``tol`` of a label, footprint or near-plane boundary,
-    and the per-pixel mask of the tiles their footprints cover."""
+    """Gaussians within ``tol`` of a label, footprint or near-plane boundary
+    (where a float rounding difference may legitimately flip the decision),
+    with their tile rectangles."""
     n = scene.n
     lab_b = np.zeros(n, bool)
     if plane.enabled:
@@ -216,19 +216,15 @@ def boundary_events(scene, cam, plane, label, dep, rad, tol: float = 1e-6) -> di
     rect_b = valid & (near_int(r3) | near_int(allp["mean2d"][:, 0] - rr) | near_int(allp["mean2d"][:, 0] + rr)
                       | near_int(allp["mean2d"][:, 1] - rr) | near_int(allp["mean2d"][:, 1] + rr))
     near_b = np.abs(allp["depth"] - cam.near) <= tol
-    W, H = cam.width, cam.height
-    mask = np.zeros((H, W), np.uint32)
-    for i in np.nonzero(lab_b | rect_b | near_b)[0]:
-        x0, y0, x1, y1 = allp["rect"][i]
-        if x1 <= x0 or y1 <= y0:
-            # not drawn even when projected: use a radius-sized box around the centre
-            mx, my = allp["mean2d"][i]
-            r = rr[i] + 1 if valid[i] else 0
-            x0, x1 = int(max(0, (mx - r) // TILE)), int(min((W - 1) // TILE, (mx + r) // TILE) + 1)
-            y0, y1 = int(max(0, (my - r) // TILE)), int(min((H - 1) // TILE, (my + r) // TILE) + 1)
-            if x1 <= x0 or y1 <= y0:
-                continue
-        bit = EV_LABEL if lab_b[i] else EV_RECT
-        mask[y0 * TILE:y1 * TILE, x0 * TILE:x1 * TILE] |= bit
+    ids = np.nonzero(lab_b | rect_b | near_b)[0]
     return dict(n_label_boundary=int(lab_b.sum()), n_rect_boundary=int(rect_b.sum()),
-                n_near_boundary=int(near_b.sum()), boundary_mask=mask)
+                n_near_boundary=int(near_b.sum()), boundary_ids=ids, boundary_rects=allp["rect"][ids])
+
+
+def tile_mask(cam, rects) -> np.ndarray:
+    """Pixel mask of the union of tile rectangles (tx0, ty0, tx1, ty1)."""
+    m = np.zeros((cam.height, cam.width), bool)
+    for x0, y0, x1, y1 in np.asarray(rects).reshape(-1, 4):
+        if x1 > x0 and y1 > y0:
+            m[y0 * TILE:y1 * TILE, x0 * TILE:x1 * TILE] = True
+    return m

@@ -38,7 +38,7 @@ class Projected(ctypes.Structure):
 
 
 class Binned(ctypes.Structure):
-    _fields_ = [("keys", _P), ("vals", _P), ("ranges", _P), ("num_pairs", _P), ("overflow", _P)]
+    _fields_ = [("keys", _P), ("vals", _P), ("ranges", _P), ("num_pairs", _P), ("overflow", _P), ("work", _P)]
 
 
 class Grads(ctypes.Structure):

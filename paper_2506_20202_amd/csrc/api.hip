@@ -146,7 +146,8 @@ rara_status rara_bin_sort(const rara_projected* proj, int64_t n, const rara_came
     if (!proj || n < 0 || !out || !workspace) return RARA_ERR_INVALID;
     if (pair_capacity < 1 || pair_capacity >= (int64_t(1) << 31)) return RARA_ERR_INVALID;
     if (n > 0 && !proj_ok(proj)) return RARA_ERR_INVALID;
-    if (!out->keys || !out->vals || !out->ranges || !out->num_pairs || !out->overflow) return RARA_ERR_INVALID;
+    if (!out->keys || !out->vals || !out->ranges || !out->num_pairs || !out->overflow || !out->work)
+        return RARA_ERR_INVALID;
     CamParams cp;
     if (!make_cam(cam, &cp)) return RARA_ERR_INVALID;
     BinWorkspace ws;
@@ -159,6 +160,7 @@ rara_status rara_bin_sort(const rara_projected* proj, int64_t n, const rara_came
     hipError_t e = launch_bin(proj_ptrs(proj), n, cp, pair_capacity, ws, *out, (passes & 1) != 0, s);
     if (e == hipSuccess) e = launch_sort(ws, pair_capacity, *out, passes, s);
     if (e == hipSuccess) e = launch_ranges(*out, pair_capacity, num_tiles, s);
+    if (e == hipSuccess) e = launch_plan(*out, num_tiles, s);
     return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
 }
 
@@ -167,7 +169,8 @@ rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned
                         uint32_t* n_walked, void* stream)
 {
     if (!proj || n < 0 || !bins || !bg || !image || !final_T || !n_contrib) return RARA_ERR_INVALID;
-    if (!proj->splat || !proj->ray || !bins->vals || !bins->ranges || !bins->overflow) return RARA_ERR_INVALID;
+    if (!proj->splat || !proj->ray || !bins->vals || !bins->ranges || !bins->overflow || !bins->work)
+        return RARA_ERR_INVALID;
     CamParams cp;
     PlaneParams pp;
     if (!make_cam(cam, &cp) || !make_plane(plane, &pp)) return RARA_ERR_INVALID;

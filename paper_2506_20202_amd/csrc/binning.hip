@@ -138,7 +138,79 @@ __global__ __launch_bounds__(256) void ranges_mark_kernel(const uint64_t* __rest
     }
 }
 
+// Exclusive count of set flags over a 1024-thread block (16 waves) and the total.
+__device__ inline uint32_t block_flag_scan(bool f, uint32_t& total, uint32_t* wave_cnt)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t m = __ballot(f);
+    if (lane == 0) wave_cnt[wave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+        const uint32_t c = wave_cnt[w];
+        before += w < wave ? c : 0u;
+        tot += c;
+    }
+    __syncthreads();
+    total = tot;
+    return before + lanes_below(m);
+}
+
+// Blend schedule: tiles whose list has at least kHeavyList entries (the first
+// kMaxHeavy of them in tile order) become four quadrant units placed first, so
+// the longest walks start earliest and run on four waves; every other tile is
+// one unit.  Deterministic (ballot compaction in tile order).
+__global__ __launch_bounds__(1024) void plan_kernel(const uint2* __restrict__ ranges, int num_tiles,
+                                                    uint32_t* __restrict__ work)
+{
+    __shared__ uint32_t wave_cnt[16];
+    const int tid = threadIdx.x;
+    uint32_t H = 0;
+    for (int c = 0; c < num_tiles; c += 1024) {
+        const int t = c + tid;
+        bool heavy = false;
+        if (t < num_tiles) {
+            const uint2 r = ranges[t];
+            heavy = r.y - r.x >= kHeavyList;
+        }
+        uint32_t tot;
+        block_flag_scan(heavy, tot, wave_cnt);
+        H += tot;
+    }
+    if (H > (uint32_t)kMaxHeavy) H = kMaxHeavy;
+    uint32_t hbase = 0, lbase = 0;
+    for (int c = 0; c < num_tiles; c += 1024) {
+        const int t = c + tid;
+        bool heavy = false;
+        if (t < num_tiles) {
+            const uint2 r = ranges[t];
+            heavy = r.y - r.x >= kHeavyList;
+        }
+        uint32_t htot;
+        const uint32_t hr = block_flag_scan(heavy, htot, wave_cnt);
+        const bool split = heavy && hbase + hr < H;
+        uint32_t stot;
+        block_flag_scan(split, stot, wave_cnt);
+        const bool whole = t < num_tiles && !split;
+        uint32_t ltot;
+        const uint32_t lr = block_flag_scan(whole, ltot, wave_cnt);
+        if (split)
+            for (uint32_t q = 0; q < 4; ++q) work[4 * (hbase + hr) + q] = ((uint32_t)t << 3) | q;
+        if (whole) work[4 * H + lbase + lr] = ((uint32_t)t << 3) | 4u;
+        hbase += stot;
+        lbase += ltot;
+    }
+    if (tid == 0) work[4 * num_tiles] = 4 * H + ((uint32_t)num_tiles - H);
+}
+
 }  // namespace
+
+hipError_t launch_plan(const rara_binned& out, int num_tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, reinterpret_cast<const uint2*>(out.ranges), num_tiles,
+                       out.work);
+    return hipGetLastError();
+}
 
 hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int64_t cap, const BinWorkspace& ws,
                       const rara_binned& out, bool emit_to_alt, hipStream_t s)

@@ -32,16 +32,6 @@ namespace {
 
 constexpr int kBatch = 64;
 
-// Workgroups are dispatched round-robin over the 8 XCDs; hand each XCD a
-// contiguous run of tiles so that neighbouring tiles (which share splats) hit
-// the same L2.
-__device__ inline int xcd_tile(int bid, int nblocks)
-{
-    const int xcd = bid & 7, local = bid >> 3;
-    const int q = nblocks >> 3, r = nblocks & 7;
-    return xcd * q + (xcd < r ? xcd : r) + local;
-}
-
 struct CutRec {
     float4 a;   // d0.xyz, gx.x
     float4 b;   // gx.yz, gy.xy
@@ -73,121 +63,208 @@ __device__ inline float chord_weight(const CutRec& k, float dx, float dy, float 
     return __builtin_amdgcn_fmed3f(w, 0.0f, 1.0f);
 }
 
+// One pixel's front-to-back update with one list entry, straight-line.
+// alpha = min(0.99, a0 w); entries with a positive exponent or alpha < 1/255
+// are skipped; an entry that would take T below 1e-4 terminates the pixel
+// without being composited.  A terminated pixel keeps -T (its sign marks it
+// dead; the magnitude is its final transmittance).
+__device__ inline void composite(float a0, float w, bool pw_ok, float cr, float cg, float cb, uint32_t k1,
+                                 float& T, float& C0, float& C1, float& C2, uint32_t& last, uint32_t& walked)
+{
+    const float alpha = fminf(kAlphaMax, a0 * w);
+    const bool ok = pw_ok && (alpha >= kAlphaMin);
+    const float tT = T * (1.0f - alpha);
+    const bool term = ok && (tT < kTMin);
+    const bool acc = ok && !term;
+    const float wt = acc ? alpha * T : 0.0f;
+    C0 = fmaf(wt, cr, C0);
+    C1 = fmaf(wt, cg, C1);
+    C2 = fmaf(wt, cb, C2);
+    T = acc ? tT : (term ? -T : T);
+    last = acc ? k1 : last;
+    walked = term ? k1 : walked;
+}
+
+// Pixels of one work unit: a whole 16x16 tile (kSlots = 4, each lane owns the
+// same pixel of the four 8x8 quadrants) or a single quadrant of a tile with a
+// long list (kSlots = 1), so that such tiles are walked by four waves at once.
+template <int kSlots, bool kWalked>
+__device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
+                                  const uint32_t* __restrict__ vals, const uint2 rg, int tile, int quad,
+                                  const RenderParams& p, float4 (*s_a)[kBatch], float4 (*s_b)[kBatch],
+                                  float4 (*s_c)[kBatch], CutRec (*s_cut)[kBatch], float* __restrict__ image,
+                                  float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
+                                  uint32_t* __restrict__ n_walked)
+{
+    const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
+    const int lane = threadIdx.x;
+    const int lx = lane & 7, ly = lane >> 3;
+
+    float lpx[kSlots], lpy[kSlots];
+    float T[kSlots], C0[kSlots], C1[kSlots], C2[kSlots];
+    uint32_t last[kSlots], walked[kSlots];
+    int qof[kSlots];
+#pragma unroll
+    for (int q = 0; q < kSlots; ++q) {
+        const int qq = kSlots == 4 ? q : quad;
+        qof[q] = qq;
+        lpx[q] = (float)((qq & 1) * 8 + lx);
+        lpy[q] = (float)((qq >> 1) * 8 + ly);
+        const bool inside = (tx * kTile + (qq & 1) * 8 + lx < p.W) && (ty * kTile + (qq >> 1) * 8 + ly < p.H);
+        T[q] = inside ? 1.0f : -1.0f;   // the sign marks a live pixel
+        C0[q] = C1[q] = C2[q] = 0.0f;
+        last[q] = walked[q] = 0u;
+    }
+
+    const double ox = (double)(tx * kTile), oy = (double)(ty * kTile);
+    const float kq = -0.5f * kLog2e;
+    const bool plane_on = p.plane_enabled != 0;
+
+    Splat nx;
+    float4 nr0, nr1, nr2;
+    bool have = false;
+    uint32_t my_mask = 0u;
+    auto fetch = [&](uint32_t base) {
+        const uint32_t idx = base + lane;
+        have = idx < rg.y;
+        if (have) {
+            const uint32_t id = vals[idx];
+            nx = splats[id];
+            if (nx.label == RARA_LABEL_CUTOFF && plane_on) {
+                const float4* rr = reinterpret_cast<const float4*>(rays + id);
+                nr0 = rr[0];
+                nr1 = rr[1];
+                nr2 = rr[2];
+            }
+        }
+    };
+    auto stage = [&](int buf) {
+        my_mask = 0u;
+        if (have) {
+            const float mx = (float)(nx.mx - ox), my = (float)(nx.my - oy);
+            s_a[buf][lane] = make_float4(mx, my, nx.ca * kq, -nx.cb * kLog2e);
+            s_b[buf][lane] = make_float4(nx.cc * kq, nx.op, nx.r, nx.g);
+            // Quadrants of the tile the entry can reach with alpha >= 1/255:
+            // delta exp(-m/2) >= 1/255 needs Mahalanobis^2 m <= 2 ln(255 delta),
+            // whose ellipse has axis half-widths sqrt(m Vhat_00), sqrt(m Vhat_11).
+            // Padded (1 % + 0.1 px) so float rounding can only widen the box;
+            // an entry is never skipped for a pixel it could reach.
+            const float s255 = 255.0f * nx.op;
+            if (s255 > 1.0f) {
+                const float m2 = 2.0f * __logf(s255) * 1.001f + 1e-3f;
+                const float idet = 1.0f / (nx.ca * nx.cc - nx.cb * nx.cb);
+                const float hx = sqrtf(m2 * nx.cc * idet) * 1.01f + 0.1f;
+                const float hy = sqrtf(m2 * nx.ca * idet) * 1.01f + 0.1f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float qx = (float)((q & 1) * 8), qy = (float)((q >> 1) * 8);
+                    const bool hit = (mx - hx <= qx + 7.0f) && (mx + hx >= qx) && (my - hy <= qy + 7.0f) &&
+                                     (my + hy >= qy);
+                    my_mask |= hit ? (1u << q) : 0u;
+                }
+            }
+            s_c[buf][lane] = make_float4(nx.b, __uint_as_float(nx.label | (my_mask << 8)), 0.0f, 0.0f);
+            if (nx.label == RARA_LABEL_CUTOFF && plane_on) {
+                CutRec c;
+                c.a = nr0;
+                c.b = nr1;
+                c.c = nr2;
+                s_cut[buf][lane] = c;
+            }
+        }
+    };
+    // quadrants (bit qof[q]) that still hold a live pixel, wave-uniform
+    auto live_quads = [&]() -> uint32_t {
+        uint32_t m = 0u;
+#pragma unroll
+        for (int q = 0; q < kSlots; ++q) m |= __ballot(T[q] > 0.0f) != 0ull ? (1u << qof[q]) : 0u;
+        return m;
+    };
+
+    uint32_t live = live_quads();
+    if (rg.x < rg.y && live) fetch(rg.x);
+    int buf = 0;
+    for (uint32_t base = rg.x; base < rg.y && live; base += kBatch, buf ^= 1) {
+        stage(buf);
+        __syncthreads();
+        if (base + kBatch < rg.y) fetch(base + kBatch);   // overlaps with the compositing below
+        // only entries that reach a quadrant with live pixels are visited, in list order
+        uint64_t todo = __ballot((my_mask & live) != 0u);   // my_mask is 0 past the list end
+        while (todo) {
+            const int j = (int)__builtin_ctzll(todo);
+            todo &= todo - 1ull;
+            const float4 a = s_a[buf][j], b = s_b[buf][j];
+            const float4 c = s_c[buf][j];
+            const uint32_t k1 = base - rg.x + (uint32_t)j + 1u;
+            const uint32_t lm = __builtin_amdgcn_readfirstlane(__float_as_uint(c.y));
+            const bool cut = plane_on && ((lm & 0xffu) == RARA_LABEL_CUTOFF);
+            // exponent dx (A dx + B dy) + C dy^2, dy terms shared by slots of one row
+            const float dxa = lpx[0] - a.x, dya = lpy[0] - a.y;
+            const float dxb = lpx[kSlots - 1] - a.x, dyb = lpy[kSlots - 1] - a.y;
+            const float Bya = a.w * dya, Byb = a.w * dyb;
+            const float Cya = b.x * dya * dya, Cyb = b.x * dyb * dyb;
+#pragma unroll
+            for (int q = 0; q < kSlots; ++q) {
+                if (((lm >> (8 + qof[q])) & 1u) && T[q] > 0.0f) {
+                    const bool xb = kSlots == 4 ? (q & 1) : false;
+                    const bool yb = kSlots == 4 ? (q >> 1) : false;
+                    const float dx = xb ? dxb : dxa;
+                    const float dy = yb ? dyb : dya;
+                    const float pw = fmaf(dx, fmaf(a.z, dx, yb ? Byb : Bya), yb ? Cyb : Cya);
+                    const float a0 = b.y * __builtin_amdgcn_exp2f(pw);
+                    float w = 1.0f;
+                    if (cut) w = chord_weight(s_cut[buf][j], dx, dy, p.ax, p.ay);
+                    composite(a0, w, pw <= 0.0f, b.z, b.w, c.x, k1, T[q], C0[q], C1[q], C2[q], last[q], walked[q]);
+                }
+            }
+            live = live_quads();
+            if (!live) break;
+        }
+    }
+
+    const int64_t HW = (int64_t)p.H * p.W;
+#pragma unroll
+    for (int q = 0; q < kSlots; ++q) {
+        const int px = tx * kTile + (int)lpx[q], py = ty * kTile + (int)lpy[q];
+        if (px >= p.W || py >= p.H) continue;
+        const int64_t pix = (int64_t)py * p.W + px;
+        const float Tq = fabsf(T[q]);
+        image[pix] = C0[q] + Tq * p.bg[0];
+        image[HW + pix] = C1[q] + Tq * p.bg[1];
+        image[2 * HW + pix] = C2[q] + Tq * p.bg[2];
+        final_T[pix] = Tq;
+        n_contrib[pix] = last[q];
+        // a pixel still alive at the end examined the whole list
+        if (kWalked) n_walked[pix] = T[q] > 0.0f ? rg.y - rg.x : walked[q];
+    }
+}
+
+// One wave per work unit.  work[] (written by the binning stage) lists the
+// quadrant units of tiles with long lists first, then whole tiles; work[4T]
+// holds the number of units.
+template <bool kWalked>
 __global__ __launch_bounds__(64) void blend_kernel(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
                                                    const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
+                                                   const uint32_t* __restrict__ work,
                                                    const int32_t* __restrict__ overflow, RenderParams p,
                                                    float* __restrict__ image, float* __restrict__ final_T,
                                                    uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
 {
     if (*overflow) return;
-    const int tile = xcd_tile(blockIdx.x, p.num_tiles);
-    const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
-    const int lane = threadIdx.x;
-    const int lx = lane & 7, ly = lane >> 3;
-
-    __shared__ float4 s_a[kBatch], s_b[kBatch], s_c[kBatch];
-    __shared__ CutRec s_cut[kBatch];
-
-    float lpx[4], lpy[4];
-    bool alive[4];
-    float T[4], C0[4], C1[4], C2[4];
-    uint32_t last[4], walked[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int ox = (q & 1) * 8 + lx, oy = (q >> 1) * 8 + ly;
-        lpx[q] = (float)ox;
-        lpy[q] = (float)oy;
-        alive[q] = (tx * kTile + ox < p.W) && (ty * kTile + oy < p.H);
-        T[q] = 1.0f;
-        C0[q] = C1[q] = C2[q] = 0.0f;
-        last[q] = walked[q] = 0u;
-    }
-
+    const uint32_t n_units = work[4 * p.num_tiles];
+    if (blockIdx.x >= n_units) return;
+    const uint32_t unit = work[blockIdx.x];
+    const int tile = (int)(unit >> 3), mode = (int)(unit & 7u);
+    if (tile >= p.num_tiles || mode > 4) return;
+    __shared__ float4 s_a[2][kBatch], s_b[2][kBatch], s_c[2][kBatch];
+    __shared__ CutRec s_cut[2][kBatch];
     const uint2 rg = ranges[tile];
-    const double ox = (double)(tx * kTile), oy = (double)(ty * kTile);
-    const float kq = -0.5f * kLog2e;
-    bool any_alive = __ballot(alive[0] || alive[1] || alive[2] || alive[3]) != 0ull;
-
-    for (uint32_t base = rg.x; base < rg.y && any_alive; base += kBatch) {
-        const uint32_t idx = base + lane;
-        if (idx < rg.y) {
-            const uint32_t id = vals[idx];
-            const Splat s = splats[id];
-            s_a[lane] = make_float4((float)(s.mx - ox), (float)(s.my - oy), s.ca * kq, -s.cb * kLog2e);
-            s_b[lane] = make_float4(s.cc * kq, s.op, s.r, s.g);
-            s_c[lane] = make_float4(s.b, __uint_as_float(s.label), 0.0f, 0.0f);
-            if (s.label == RARA_LABEL_CUTOFF && p.plane_enabled) {
-                const float4* rr = reinterpret_cast<const float4*>(rays + id);
-                CutRec c;
-                c.a = rr[0];
-                c.b = rr[1];
-                c.c = rr[2];
-                s_cut[lane] = c;
-            }
-        }
-        __syncthreads();
-        const int cnt = (int)(rg.y - base < (uint32_t)kBatch ? rg.y - base : (uint32_t)kBatch);
-        for (int j = 0; j < cnt; ++j) {
-            const float4 a = s_a[j], b = s_b[j];
-            const float4 c = s_c[j];
-            const uint32_t k1 = base - rg.x + (uint32_t)j + 1u;
-            const bool cut = (__float_as_uint(c.y) == RARA_LABEL_CUTOFF) && p.plane_enabled;
-            if (cut) {
-                const CutRec cr = s_cut[j];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (!alive[q]) continue;
-                    walked[q] = k1;
-                    const float dx = lpx[q] - a.x, dy = lpy[q] - a.y;
-                    const float pw = a.z * dx * dx + b.x * dy * dy + a.w * dx * dy;
-                    if (pw > 0.0f) continue;
-                    float alpha = b.y * __builtin_amdgcn_exp2f(pw);
-                    if (alpha < kAlphaMin) continue;   // w <= 1 cannot lift it above the threshold
-                    alpha = fminf(kAlphaMax, alpha * chord_weight(cr, dx, dy, p.ax, p.ay));
-                    if (alpha < kAlphaMin) continue;
-                    const float tT = T[q] * (1.0f - alpha);
-                    if (tT < kTMin) { alive[q] = false; continue; }
-                    const float wt = alpha * T[q];
-                    C0[q] += wt * b.z; C1[q] += wt * b.w; C2[q] += wt * c.x;
-                    T[q] = tT;
-                    last[q] = k1;
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (!alive[q]) continue;
-                    walked[q] = k1;
-                    const float dx = lpx[q] - a.x, dy = lpy[q] - a.y;
-                    const float pw = a.z * dx * dx + b.x * dy * dy + a.w * dx * dy;
-                    if (pw > 0.0f) continue;
-                    const float alpha = fminf(kAlphaMax, b.y * __builtin_amdgcn_exp2f(pw));
-                    if (alpha < kAlphaMin) continue;
-                    const float tT = T[q] * (1.0f - alpha);
-                    if (tT < kTMin) { alive[q] = false; continue; }
-                    const float wt = alpha * T[q];
-                    C0[q] += wt * b.z; C1[q] += wt * b.w; C2[q] += wt * c.x;
-                    T[q] = tT;
-                    last[q] = k1;
-                }
-            }
-            if (__ballot(alive[0] || alive[1] || alive[2] || alive[3]) == 0ull) { any_alive = false; break; }
-        }
-        __syncthreads();
-    }
-
-    const int64_t HW = (int64_t)p.H * p.W;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int px = tx * kTile + (q & 1) * 8 + lx, py = ty * kTile + (q >> 1) * 8 + ly;
-        if (px >= p.W || py >= p.H) continue;
-        const int64_t pix = (int64_t)py * p.W + px;
-        image[pix] = C0[q] + T[q] * p.bg[0];
-        image[HW + pix] = C1[q] + T[q] * p.bg[1];
-        image[2 * HW + pix] = C2[q] + T[q] * p.bg[2];
-        final_T[pix] = T[q];
-        n_contrib[pix] = last[q];
-        if (n_walked) n_walked[pix] = walked[q];
-    }
+    if (mode == 4)
+        blend_unit<4, kWalked>(splats, rays, vals, rg, tile, 0, p, s_a, s_b, s_c, s_cut, image, final_T, n_contrib,
+                               n_walked);
+    else
+        blend_unit<1, kWalked>(splats, rays, vals, rg, tile, mode, p, s_a, s_b, s_c, s_cut, image, final_T, n_contrib,
+                               n_walked);
 }
 
 }  // namespace
@@ -195,9 +272,15 @@ __global__ __launch_bounds__(64) void blend_kernel(const Splat* __restrict__ spl
 hipError_t launch_blend(const Splat* splat, const RayRec* ray, const rara_binned& bins, const RenderParams& p,
                         float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked, hipStream_t s)
 {
-    hipLaunchKernelGGL(blend_kernel, dim3((unsigned)p.num_tiles), dim3(64), 0, s, splat, ray, bins.vals,
-                       reinterpret_cast<const uint2*>(bins.ranges), bins.overflow, p, image, final_T, n_contrib,
-                       n_walked);
+    const unsigned grid = (unsigned)work_grid(p.num_tiles);
+    if (n_walked)
+        hipLaunchKernelGGL(blend_kernel<true>, dim3(grid), dim3(64), 0, s, splat, ray, bins.vals,
+                           reinterpret_cast<const uint2*>(bins.ranges), bins.work, bins.overflow, p, image, final_T,
+                           n_contrib, n_walked);
+    else
+        hipLaunchKernelGGL(blend_kernel<false>, dim3(grid), dim3(64), 0, s, splat, ray, bins.vals,
+                           reinterpret_cast<const uint2*>(bins.ranges), bins.work, bins.overflow, p, image, final_T,
+                           n_contrib, n_walked);
     return hipGetLastError();
 }
 

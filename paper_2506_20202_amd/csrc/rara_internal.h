@@ -81,6 +81,14 @@ struct RenderParams {
     float bg[3];
 };
 
+// ---- blend work list --------------------------------------------------------
+// Tiles whose list holds at least kHeavyList entries are blended as four
+// quadrant units (one wave each) and scheduled first; at most kMaxHeavy tiles
+// per frame are split.  work[] has 4 * tiles + 1 entries.
+constexpr uint32_t kHeavyList = 1536;
+constexpr int kMaxHeavy = 2048;
+inline int64_t work_grid(int64_t tiles) { return tiles + 3 * (tiles < kMaxHeavy ? tiles : kMaxHeavy); }
+
 // ---- bin/sort workspace carve-up -------------------------------------------
 constexpr int kScanBlock = 256;      // Gaussians per scan chunk
 constexpr int kSortThreads = 256;
@@ -108,6 +116,7 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
                       const rara_binned& out, bool emit_to_alt, hipStream_t s);
 hipError_t launch_sort(const BinWorkspace& ws, int64_t cap, const rara_binned& out, int passes, hipStream_t s);
 hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, hipStream_t s);
+hipError_t launch_plan(const rara_binned& out, int num_tiles, hipStream_t s);
 hipError_t launch_blend(const Splat* splat, const RayRec* ray, const rara_binned& bins, const RenderParams& p,
                         float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked, hipStream_t s);
 

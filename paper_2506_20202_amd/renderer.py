@@ -87,6 +87,7 @@ class BinBuffers:
         self.ranges = torch.empty(tiles * 2, dtype=torch.int32, device=device)
         self.num_pairs = torch.zeros(1, dtype=torch.int64, device=device)
         self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
+        self.work = torch.empty(4 * tiles + 1, dtype=torch.int32, device=device)
         self.ws_bytes = B.workspace_bytes(B.RARA_WS_BIN_SORT, n, self.capacity, width, height)
         if self.ws_bytes == 0:
             raise ValueError("invalid bin/sort workspace request")
@@ -96,6 +97,7 @@ class BinBuffers:
         b = B.Binned()
         b.keys, b.vals, b.ranges = _ptr(self.keys), _ptr(self.vals), _ptr(self.ranges)
         b.num_pairs, b.overflow = _ptr(self.num_pairs), _ptr(self.overflow)
+        b.work = _ptr(self.work)
         return b
 
     def nbytes(self) -> int:

@@ -45,30 +45,55 @@ def tile_list(res, tile):
     return res["vals"][s:e]
 
 
-def check_projection(g, o, n_boundary_ok=0):
-    """Labels, drawn set, rectangles, depths, projected floats."""
-    lab_mis = np.nonzero(g["label"] != o["label"])[0]
-    assert len(lab_mis) <= n_boundary_ok, f"label mismatches {len(lab_mis)} at {lab_mis[:10]}"
+def check_projection(g, o):
+    """Labels, drawn sets, rectangles and float32 depths identical to the
+    oracle except for Gaussians the oracle counts as within 1e-6 of a label,
+    footprint or near-plane boundary; projected floats to float32 rounding.
+    Returns the pixel mask of tiles touched by the (allowed) mismatches."""
+    import oracle
     drawn = o["proj"]["drawn"].astype(bool)
     gd = g["tiles_touched"] > 0
+    mism = (g["label"] != o["label"]) | (gd != drawn)
     both = drawn & gd
-    assert (gd != drawn).sum() <= n_boundary_ok, f"drawn mismatches {(gd != drawn).sum()}"
-    np.testing.assert_array_equal(g["tiles_touched"][both], o["proj"]["tiles_touched"][both])
-    np.testing.assert_array_equal(g["rect"][both], o["proj"]["rect"][both])
-    np.testing.assert_array_equal(g["depth"][both], o["proj"]["depth32"][both])
-    np.testing.assert_allclose(g["splat_mean2d"][both], o["proj"]["mean2d"][both], rtol=1e-12, atol=1e-9)
-    np.testing.assert_allclose(g["splat_conic"][both], o["proj"]["conic"][both], rtol=2e-6, atol=1e-9)
-    np.testing.assert_allclose(g["splat_rgb"][both], o["proj"]["rgb"][both], rtol=2e-6, atol=1e-6)
-    return both
+    mism[both] |= (g["rect"][both] != o["proj"]["rect"][both]).any(axis=1)
+    mism[both] |= g["depth"][both] != o["proj"]["depth32"][both]
+    bad = np.nonzero(mism)[0]
+    allowed = set(o.get("boundary_ids", np.zeros(0, int)).tolist())
+    outside = [i for i in bad if i not in allowed]
+    assert not outside, f"{len(outside)} Gaussians differ off every boundary, first {outside[:10]}"
+    ok = both & ~mism
+    np.testing.assert_array_equal(g["tiles_touched"][ok], o["proj"]["tiles_touched"][ok])
+    np.testing.assert_allclose(g["splat_mean2d"][ok], o["proj"]["mean2d"][ok], rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(g["splat_conic"][ok], o["proj"]["conic"][ok], rtol=2e-6, atol=1e-9)
+    np.testing.assert_allclose(g["splat_rgb"][ok], o["proj"]["rgb"][ok], rtol=2e-6, atol=1e-6)
+    rects = []
+    for i in bad:
+        rects.append(o["proj"]["rect"][i])
+        rects.append(g["rect"][i] if gd[i] else np.zeros(4, np.int32))
+        k = np.nonzero(o["boundary_ids"] == i)[0]
+        if len(k):
+            rects.append(o["boundary_rects"][k[0]])
+    return bad, (np.array(rects).reshape(-1, 4) if rects else np.zeros((0, 4), np.int32))
 
 
-def check_lists(g, o, tiles=None):
+def tiles_of(rects, tiles_x):
+    out = set()
+    for x0, y0, x1, y1 in rects:
+        for y in range(y0, y1):
+            for x in range(x0, x1):
+                out.add(y * tiles_x + x)
+    return out
+
+
+def check_lists(g, o, tiles=None, skip=()):
     """Per-tile lists identical to the oracle's (ids and order)."""
     offs, ids = o["offsets"], o["ids"]
     T = len(offs) - 1
     tiles = range(T) if tiles is None else tiles
     bad = []
     for t in tiles:
+        if t in skip:
+            continue
         ref = ids[offs[t]:offs[t + 1]]
         got = tile_list(g, t)
         if len(ref) != len(got) or not np.array_equal(ref, got):
@@ -76,11 +101,16 @@ def check_lists(g, o, tiles=None):
     assert not bad, f"{len(bad)} tile lists differ, first {bad[:5]}"
 
 
-def image_error(g_img, o):
-    """Max abs error over clamp(RGB, 0, 1) on pixels without oracle events,
-    and the fraction of pixels flagged."""
+def image_error(g_img, o, exclude=None, region=None):
+    """Max abs error over clamp(RGB, 0, 1) on pixels without oracle events
+    (and outside ``exclude``, inside ``region``), and the flagged fraction."""
     a = np.clip(g_img, 0, 1)
     b = np.clip(o["image"], 0, 1)
     err = np.abs(a - b).max(axis=0)
     ok = o["flags"] == 0
+    if exclude is not None:
+        ok &= ~exclude
+    if region is not None:
+        ok &= region
+        return float(err[ok].max() if ok.any() else 0.0), float(1 - ok.sum() / max(region.sum(), 1)), err
     return float(err[ok].max() if ok.any() else 0.0), float(1 - ok.mean()), err

@@ -118,7 +118,7 @@ def test_argument_validation_before_any_launch(B):
     assert lib.rara_bin_sort(ctypes.byref(out), 10, ctypes.byref(cam), 100, None, 0, ctypes.byref(bins), None) \
         == B.RARA_ERR_INVALID
     fake = ctypes.c_void_p(0x1000)
-    bins.keys = bins.vals = bins.ranges = bins.num_pairs = bins.overflow = 0x1000
+    bins.keys = bins.vals = bins.ranges = bins.num_pairs = bins.overflow = bins.work = 0x1000
     assert lib.rara_bin_sort(ctypes.byref(out), 0, ctypes.byref(cam), 100, fake, 16, ctypes.byref(bins), None) \
         == B.RARA_ERR_INVALID   # workspace too small
     assert lib.rara_bin_sort(ctypes.byref(out), 0, ctypes.byref(cam), 0, fake, 1 << 30, ctypes.byref(bins), None) \

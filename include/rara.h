@@ -194,15 +194,18 @@ rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned
 /* Gradient of a scalar loss L given dL/dimage [3][H][W] (device), through the
  * blend (re-walking each tile list from n_contrib back to front, with the
  * transmittance rebuilt by division) and the clip weight of eq. (11), then
- * through projection and colour to the raw inputs and the plane.  Uses the
- * same g, cam, plane, proj, bins, final_T and n_contrib as the forward frame.
- * Needs `ws_bytes` >= rara_workspace_bytes(RARA_WS_BACKWARD, n, ...) bytes.
- * Every array of *grads is overwritten.
- * Errors: as rara_render, plus RARA_ERR_INVALID for a short workspace. */
+ * through projection and colour to the raw inputs and the plane.  g, cam,
+ * plane, bg, proj, bins, final_T and n_contrib must be those of the forward
+ * frame.  Needs `ws_bytes` >= rara_workspace_bytes(RARA_WS_BACKWARD, n, ...)
+ * bytes of device workspace.  Every array of *grads is overwritten (Gaussians
+ * that were not drawn get zero).  Gradients use float atomics, so repeated
+ * runs agree to rounding, not bit for bit.
+ * Errors: as rara_render, plus RARA_ERR_INVALID for a short workspace or null
+ * gradient arrays. */
 rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam, const rara_plane* plane,
-                                 const rara_projected* proj, const rara_binned* bins, const float* final_T,
-                                 const uint32_t* n_contrib, const float* dL_dimage, const rara_grads* grads,
-                                 void* workspace, size_t ws_bytes, void* stream);
+                                 const float* bg, const rara_projected* proj, const rara_binned* bins,
+                                 const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
+                                 const rara_grads* grads, void* workspace, size_t ws_bytes, void* stream);
 
 /* Static description of a status code (never NULL). */
 const char* rara_status_string(rara_status s);

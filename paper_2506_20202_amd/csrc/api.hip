@@ -194,4 +194,43 @@ rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned
     return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
 }
 
+rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam, const rara_plane* plane,
+                                 const float* bg, const rara_projected* proj, const rara_binned* bins,
+                                 const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
+                                 const rara_grads* grads, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!g || g->n < 0 || !bg || !proj || !bins || !final_T || !n_contrib || !dL_dimage || !grads || !workspace)
+        return RARA_ERR_INVALID;
+    if (g->sh_degree < 0 || g->sh_degree > 3) return RARA_ERR_UNSUPPORTED;
+    if (!proj_ok(proj) || !bins->vals || !bins->ranges || !bins->overflow || !bins->work) return RARA_ERR_INVALID;
+    if (!grads->plane || (g->n > 0 && (!grads->mean || !grads->scale || !grads->quat || !grads->opacity || !grads->sh)))
+        return RARA_ERR_INVALID;
+    if (g->n > 0 && (!g->mean || !g->scale || !g->quat || !g->opacity || !g->sh)) return RARA_ERR_INVALID;
+    CamParams cp;
+    PlaneParams pp;
+    if (!make_cam(cam, &cp) || !make_plane(plane, &pp)) return RARA_ERR_INVALID;
+    if (ws_bytes < backward_workspace_bytes(g->n, cp.W, cp.H)) return RARA_ERR_INVALID;
+    RenderParams rp;
+    rp.W = cp.W;
+    rp.H = cp.H;
+    rp.tiles_x = cp.tiles_x;
+    rp.tiles_y = cp.tiles_y;
+    rp.num_tiles = cp.tiles_x * cp.tiles_y;
+    rp.plane_enabled = pp.enabled;
+    const double rn0 = cp.R[0] * pp.n[0] + cp.R[1] * pp.n[1] + cp.R[2] * pp.n[2];
+    const double rn1 = cp.R[3] * pp.n[0] + cp.R[4] * pp.n[1] + cp.R[5] * pp.n[2];
+    rp.ax = (float)(rn0 / cp.fx);
+    rp.ay = (float)(rn1 / cp.fy);
+    rp.bg[0] = bg[0];
+    rp.bg[1] = bg[1];
+    rp.bg[2] = bg[2];
+    const double len = pp.enabled ? std::sqrt((double)plane->n[0] * plane->n[0] + (double)plane->n[1] * plane->n[1] +
+                                              (double)plane->n[2] * plane->n[2])
+                                  : 1.0;
+    GaussPtrs gp{g->n, g->sh_degree, g->mean, g->scale, g->quat, g->opacity, g->sh};
+    const hipError_t e = launch_backward(gp, cp, pp, len, proj_ptrs(proj), *bins, rp, final_T, n_contrib, dL_dimage,
+                                         *grads, workspace, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
+}
+
 }  // extern "C"

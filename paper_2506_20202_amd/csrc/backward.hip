@@ -1,21 +1,626 @@
-// Backward pass of the clipped blend and of the projection (placeholder until
-// the gradient kernels land: reports RARA_ERR_UNSUPPORTED).
-#include "rara_internal.h"
+// Backward pass of the clipped frame (not in the paper, which is render-only):
+// gradients of a scalar loss L, given dL/dimage, with respect to the raw
+// Gaussian inputs (mean, scale, quaternion, opacity, SH) and the raw plane
+// (n, d).
+//
+//   blend_backward  per work unit (the forward's schedule), walk the tile list
+//                   back to front from each pixel's n_contrib, rebuilding the
+//                   transmittance by division (alpha <= 0.99 keeps it bounded)
+//                   and re-evaluating alpha and the clip weight with the
+//                   forward's own arithmetic, so that the composite / skip
+//                   decisions are the forward's bit for bit.  Per entry the
+//                   per-pixel gradients are summed over the wave and added to
+//                   21 per-Gaussian accumulators with one atomic each.
+//   project_backward per Gaussian, FP64 chain rule from (mean2d, conic,
+//                   opacity, colour, ray set-up) to (mean, scale, quaternion,
+//                   opacity, SH) and the plane, through the EWA projection of
+//                   eqs. (9)-(10), the SH colour and eq. (4)'s whitening.
+//   plane_finalize  plane gradient from the normalised (n, d) and the
+//                   per-view pixel-rate terms to the raw (n, d).
+#include "blend_common.h"
 
 namespace rara {
+
+namespace {
+
+// accumulator rows, each [n] floats
+enum {
+    A_MX = 0, A_MY, A_CA, A_CB, A_CC, A_OP, A_R, A_G, A_B,
+    A_D0, A_GX = A_D0 + 3, A_GY = A_GX + 3, A_Z = A_GY + 3, A_DEP, A_G0, kAccRows
+};
+// plane accumulators: dn_hat[3], dd_hat, dax, day
+constexpr int kPlaneAcc = 8;
+
+__device__ inline float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline uint32_t wave_max(uint32_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+struct BackParams {
+    RenderParams rp;
+    int64_t n;
+};
+
+// Backward of the interior branch of the clip weight: given dL/dw, the
+// gradients of the staged ray set-up (g[0..11] = d0, gx, gy, z, dep, g0), of
+// the pixel offset, and of the per-view plane rates (ax, ay).
+__device__ inline void chord_backward(const CutRec& k, const Chord& c, float dx, float dy, float ax, float ay,
+                                      float dw, float* g, float& ddx, float& ddy, float& dax, float& day)
+{
+    const float gx[3] = {k.a.w, k.b.x, k.b.y};
+    const float gy[3] = {k.b.z, k.b.w, k.c.x};
+    const float z = k.c.y;
+    // w = 1/2 + phim inv, inv = 1 / (2 |g| hs)
+    const float dphim = dw * c.inv;
+    const float dden = -dw * c.phim * c.inv * c.inv;
+    const float sg = c.gg > 0.0f ? 1.0f : -1.0f;
+    float dgg = dden * 2.0f * c.hs * sg;
+    float dhs = dden * 2.0f * fabsf(c.gg);
+    // phim = dep + z u + sm g
+    const float ddep = dphim;
+    float dz = dphim * c.u;
+    float du = dphim * z;
+    float dsm = dphim * c.gg;
+    dgg += dphim * c.sm;
+    const float dg0 = dgg;   // g = g0 + u
+    du += dgg;
+    dax += du * dx;
+    day += du * dy;
+    ddx += du * ax;
+    ddy += du * ay;
+    // hs = sqrt(h2 / DD)
+    const float dh2 = dhs * 0.5f * c.iDD / c.hs;
+    float dDD = -dhs * 0.5f * c.hs * c.iDD;
+    // h2 = 9 - Q.Q ; Q = P + sm D
+    float dP[3], dD[3];
+    for (int i = 0; i < 3; ++i) {
+        const float dQ = -2.0f * c.Q[i] * dh2;
+        dP[i] = dQ;
+        dsm += dQ * c.D[i];
+        dD[i] = c.sm * dQ;
+    }
+    // sm = -PD / DD
+    const float dPD = -dsm * c.iDD;
+    dDD += dsm * c.PD * c.iDD * c.iDD;
+    for (int i = 0; i < 3; ++i) {
+        dP[i] += dPD * c.D[i];
+        dD[i] += dPD * c.P[i] + 2.0f * dDD * c.D[i];
+    }
+    // P = z e ; D = d0 + e ; e = gx dx + gy dy
+    for (int i = 0; i < 3; ++i) {
+        dz += dP[i] * c.e[i];
+        const float de = z * dP[i] + dD[i];
+        g[i] += dD[i];            // d0
+        g[3 + i] += de * dx;      // gx
+        g[6 + i] += de * dy;      // gy
+        ddx += de * gx[i];
+        ddy += de * gy[i];
+    }
+    g[9] += dz;
+    g[10] += ddep;
+    g[11] += dg0;
+}
+
+template <int kSlots>
+__device__ inline void blend_back_unit(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
+                                       const uint32_t* __restrict__ vals, const uint2 rg, int tile, int quad,
+                                       const BackParams& bp, const float* __restrict__ final_T,
+                                       const uint32_t* __restrict__ n_contrib, const float* __restrict__ dL_dimage,
+                                       float* __restrict__ acc, float* __restrict__ plane_acc,
+                                       float4 (*s_a), float4 (*s_b), float4 (*s_c), CutRec (*s_cut))
+{
+    const RenderParams& p = bp.rp;
+    const int64_t n = bp.n;
+    const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
+    const int lane = threadIdx.x;
+    const int lx = lane & 7, ly = lane >> 3;
+    const int64_t HW = (int64_t)p.H * p.W;
+
+    float lpx[kSlots], lpy[kSlots], T[kSlots], Tfin[kSlots], dC[kSlots][3], ac[kSlots][3], la[kSlots],
+        lc[kSlots][3], bgdot[kSlots];
+    uint32_t nc[kSlots];
+    int qof[kSlots];
+    uint32_t kmax = 0;
+#pragma unroll
+    for (int q = 0; q < kSlots; ++q) {
+        const int qq = kSlots == 4 ? q : quad;
+        qof[q] = qq;
+        const int ox = (qq & 1) * 8 + lx, oy = (qq >> 1) * 8 + ly;
+        lpx[q] = (float)ox;
+        lpy[q] = (float)oy;
+        const int px = tx * kTile + ox, py = ty * kTile + oy;
+        const bool inside = px < p.W && py < p.H;
+        const int64_t pix = (int64_t)py * p.W + px;
+        T[q] = inside ? final_T[pix] : 0.0f;
+        Tfin[q] = T[q];
+        nc[q] = inside ? n_contrib[pix] : 0u;
+        kmax = nc[q] > kmax ? nc[q] : kmax;
+        bgdot[q] = 0.0f;
+        for (int ch = 0; ch < 3; ++ch) {
+            dC[q][ch] = inside ? dL_dimage[ch * HW + pix] : 0.0f;
+            ac[q][ch] = 0.0f;
+            lc[q][ch] = 0.0f;
+            bgdot[q] += p.bg[ch] * dC[q][ch];
+        }
+        la[q] = 0.0f;
+    }
+    kmax = __builtin_amdgcn_readfirstlane(wave_max(kmax));
+    if (kmax > rg.y - rg.x) kmax = rg.y - rg.x;   // n_contrib never exceeds the list length
+    const bool plane_on = p.plane_enabled != 0;
+    const double ox = (double)(tx * kTile), oy = (double)(ty * kTile);
+    float pax = 0.0f, pay = 0.0f;
+
+    for (uint32_t hi = rg.x + kmax; hi > rg.x;) {
+        const uint32_t lo = hi - rg.x > (uint32_t)kBatch ? hi - kBatch : rg.x;
+        const uint32_t cnt = hi - lo;
+        uint32_t my_mask = 0u;
+        __syncthreads();
+        if ((uint32_t)lane < cnt) {
+            const uint32_t id = vals[lo + lane];
+            const Splat sp = splats[id];
+            stage_entry(sp, ox, oy, s_a[lane], s_b[lane], s_c[lane], my_mask, id);
+            if (sp.label == RARA_LABEL_CUTOFF && plane_on) {
+                const float4* rr = reinterpret_cast<const float4*>(rays + id);
+                CutRec c;
+                c.a = rr[0];
+                c.b = rr[1];
+                c.c = rr[2];
+                s_cut[lane] = c;
+            }
+        }
+        __syncthreads();
+        uint64_t todo = __ballot(my_mask != 0u);
+        while (todo) {
+            const int j = 63 - (int)__builtin_clzll(todo);
+            todo &= ~(1ull << j);
+            const float4 a = s_a[j], b = s_b[j], c = s_c[j];
+            const uint32_t lm = __builtin_amdgcn_readfirstlane(__float_as_uint(c.y));
+            const uint32_t id = __builtin_amdgcn_readfirstlane(__float_as_uint(c.z));
+            const uint32_t k1 = lo - rg.x + (uint32_t)j + 1u;
+            const bool cut = plane_on && ((lm & 0xffu) == RARA_LABEL_CUTOFF);
+            CutRec cr;
+            if (cut) cr = s_cut[j];
+            float g_mx = 0.f, g_my = 0.f, g_ca = 0.f, g_cb = 0.f, g_cc = 0.f, g_op = 0.f;
+            float g_col[3] = {0.f, 0.f, 0.f};
+            float g_ray[12];
+            for (int r = 0; r < 12; ++r) g_ray[r] = 0.f;
+            bool contributed = false;
+#pragma unroll
+            for (int q = 0; q < kSlots; ++q) {
+                if (((lm >> (8 + qof[q])) & 1u) && k1 <= nc[q]) {
+                    const float dx = lpx[q] - a.x, dy = lpy[q] - a.y;
+                    const float pw = entry_power(a, b, dx, dy);
+                    const float G2 = __builtin_amdgcn_exp2f(pw);
+                    const float a0 = b.y * G2;
+                    Chord ch;
+                    float w = 1.0f;
+                    if (cut) {
+                        chord_eval(cr, dx, dy, p.ax, p.ay, ch);
+                        w = ch.w;
+                    }
+                    const float aw = a0 * w;
+                    const float alpha = fminf(kAlphaMax, aw);
+                    if (pw <= 0.0f && alpha >= kAlphaMin) {
+                        contributed = true;
+                        T[q] = T[q] / (1.0f - alpha);
+                        const float col[3] = {b.z, b.w, c.x};
+                        float dLda = 0.0f;
+                        for (int k = 0; k < 3; ++k) {
+                            ac[q][k] = la[q] * lc[q][k] + (1.0f - la[q]) * ac[q][k];
+                            lc[q][k] = col[k];
+                            dLda += (col[k] - ac[q][k]) * dC[q][k];
+                            g_col[k] += alpha * T[q] * dC[q][k];
+                        }
+                        dLda *= T[q];
+                        la[q] = alpha;
+                        dLda += (-Tfin[q] / (1.0f - alpha)) * bgdot[q];
+                        if (aw < kAlphaMax) {
+                            const float dLda0 = dLda * w;
+                            g_op += dLda0 * G2;
+                            const float dpow = dLda0 * a0;   // d alpha0 / d power = alpha0
+                            g_ca += dpow * (-0.5f * dx * dx);
+                            g_cb += dpow * (-dx * dy);
+                            g_cc += dpow * (-0.5f * dy * dy);
+                            // d power / d dx = -(ca dx + cb dy) from the base-2 scaled staged conic
+                            float ddx = dpow * (2.0f * a.z * dx + a.w * dy) * (1.0f / kLog2e);
+                            float ddy = dpow * (a.w * dx + 2.0f * b.x * dy) * (1.0f / kLog2e);
+                            if (cut && ch.kind == 4)
+                                chord_backward(cr, ch, dx, dy, p.ax, p.ay, dLda * a0, g_ray, ddx, ddy, pax, pay);
+                            g_mx -= ddx;
+                            g_my -= ddy;
+                        }
+                    }
+                }
+            }
+            if (__ballot(contributed) != 0ull) {
+                const float v9[9] = {g_mx, g_my, g_ca, g_cb, g_cc, g_op, g_col[0], g_col[1], g_col[2]};
+#pragma unroll
+                for (int r = 0; r < 9; ++r) {
+                    const float s = wave_sum(v9[r]);
+                    if (lane == 0 && s != 0.0f) atomicAdd(acc + (int64_t)r * n + id, s);
+                }
+                if (cut) {
+#pragma unroll
+                    for (int r = 0; r < 12; ++r) {
+                        const float s = wave_sum(g_ray[r]);
+                        if (lane == 0 && s != 0.0f) atomicAdd(acc + (int64_t)(A_D0 + r) * n + id, s);
+                    }
+                }
+            }
+        }
+        hi = lo;
+    }
+    const float sx = wave_sum(pax), sy = wave_sum(pay);
+    if (lane == 0 && (sx != 0.0f || sy != 0.0f)) {
+        atomicAdd(plane_acc + 4, sx);
+        atomicAdd(plane_acc + 5, sy);
+    }
+}
+
+__global__ __launch_bounds__(64) void blend_backward_kernel(const Splat* __restrict__ splats,
+                                                            const RayRec* __restrict__ rays,
+                                                            const uint32_t* __restrict__ vals,
+                                                            const uint2* __restrict__ ranges,
+                                                            const uint32_t* __restrict__ work,
+                                                            const int32_t* __restrict__ overflow, BackParams bp,
+                                                            const float* __restrict__ final_T,
+                                                            const uint32_t* __restrict__ n_contrib,
+                                                            const float* __restrict__ dL_dimage,
+                                                            float* __restrict__ acc, float* __restrict__ plane_acc)
+{
+    if (*overflow) return;
+    const int T = bp.rp.num_tiles;
+    const uint32_t n_units = work[4 * T];
+    if (blockIdx.x >= n_units) return;
+    const uint32_t unit = work[blockIdx.x];
+    const int tile = (int)(unit >> 3), mode = (int)(unit & 7u);
+    if (tile >= T || mode > 4) return;
+    __shared__ float4 s_a[kBatch], s_b[kBatch], s_c[kBatch];
+    __shared__ CutRec s_cut[kBatch];
+    const uint2 rg = ranges[tile];
+    if (mode == 4)
+        blend_back_unit<4>(splats, rays, vals, rg, tile, 0, bp, final_T, n_contrib, dL_dimage, acc, plane_acc, s_a,
+                           s_b, s_c, s_cut);
+    else
+        blend_back_unit<1>(splats, rays, vals, rg, tile, mode, bp, final_T, n_contrib, dL_dimage, acc, plane_acc,
+                           s_a, s_b, s_c, s_cut);
+}
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(float* __restrict__ p, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+// d Y_k / d(x, y, z) of the degree <= 3 real SH basis (same convention and
+// constants as the forward), accumulated as ddir += sum_k dY_k grad Y_k.
+__device__ inline void sh_backward(int deg, double x, double y, double z, const double* dY, double* dd)
+{
+    const double c1 = 0.4886025119029199;
+    dd[0] = dd[1] = dd[2] = 0.0;
+    if (deg < 1) return;
+    dd[1] += -c1 * dY[1];
+    dd[2] += c1 * dY[2];
+    dd[0] += -c1 * dY[3];
+    if (deg < 2) return;
+    const double c4 = 1.0925484305920792, c6 = 0.31539156525252005, c8 = 0.5462742152960396;
+    dd[0] += c4 * y * dY[4];
+    dd[1] += c4 * x * dY[4];
+    dd[1] += -c4 * z * dY[5];
+    dd[2] += -c4 * y * dY[5];
+    dd[0] += -2.0 * c6 * x * dY[6];
+    dd[1] += -2.0 * c6 * y * dY[6];
+    dd[2] += 4.0 * c6 * z * dY[6];
+    dd[0] += -c4 * z * dY[7];
+    dd[2] += -c4 * x * dY[7];
+    dd[0] += 2.0 * c8 * x * dY[8];
+    dd[1] += -2.0 * c8 * y * dY[8];
+    if (deg < 3) return;
+    const double c9 = 0.5900435899266435, c10 = 2.890611442640554, c11 = 0.4570457994644658,
+                 c12 = 0.3731763325901154, c14 = 1.445305721320277;
+    const double xx = x * x, yy = y * y, zz = z * z;
+    dd[0] += -c9 * 6.0 * x * y * dY[9];
+    dd[1] += -c9 * (3.0 * xx - 3.0 * yy) * dY[9];
+    dd[0] += c10 * y * z * dY[10];
+    dd[1] += c10 * x * z * dY[10];
+    dd[2] += c10 * x * y * dY[10];
+    dd[0] += 2.0 * c11 * x * y * dY[11];
+    dd[1] += -c11 * (4.0 * zz - xx - 3.0 * yy) * dY[11];
+    dd[2] += -c11 * 8.0 * y * z * dY[11];
+    dd[0] += -6.0 * c12 * x * z * dY[12];
+    dd[1] += -6.0 * c12 * y * z * dY[12];
+    dd[2] += c12 * (6.0 * zz - 3.0 * xx - 3.0 * yy) * dY[12];
+    dd[0] += -c11 * (4.0 * zz - 3.0 * xx - yy) * dY[13];
+    dd[1] += 2.0 * c11 * x * y * dY[13];
+    dd[2] += -8.0 * c11 * x * z * dY[13];
+    dd[0] += 2.0 * c14 * x * z * dY[14];
+    dd[1] += -2.0 * c14 * y * z * dY[14];
+    dd[2] += c14 * (xx - yy) * dY[14];
+    dd[0] += -c9 * (3.0 * xx - 3.0 * yy) * dY[15];
+    dd[1] += 6.0 * c9 * x * y * dY[15];
+}
+
+__device__ inline void sh_values(int deg, double x, double y, double z, double* Y)
+{
+    Y[0] = 0.28209479177387814;
+    if (deg < 1) return;
+    Y[1] = -0.4886025119029199 * y;
+    Y[2] = 0.4886025119029199 * z;
+    Y[3] = -0.4886025119029199 * x;
+    if (deg < 2) return;
+    const double xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = 1.0925484305920792 * x * y;
+    Y[5] = -1.0925484305920792 * y * z;
+    Y[6] = 0.31539156525252005 * (2.0 * zz - xx - yy);
+    Y[7] = -1.0925484305920792 * x * z;
+    Y[8] = 0.5462742152960396 * (xx - yy);
+    if (deg < 3) return;
+    Y[9] = -0.5900435899266435 * y * (3.0 * xx - yy);
+    Y[10] = 2.890611442640554 * x * y * z;
+    Y[11] = -0.4570457994644658 * y * (4.0 * zz - xx - yy);
+    Y[12] = 0.3731763325901154 * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+    Y[13] = -0.4570457994644658 * x * (4.0 * zz - xx - yy);
+    Y[14] = 1.445305721320277 * z * (xx - yy);
+    Y[15] = -0.5900435899266435 * x * (xx - 3.0 * yy);
+}
+
+struct GradPtrs {
+    float *mean, *scale, *quat, *opacity, *sh;
+};
+
+__global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamParams cam, PlaneParams pl,
+                                                               const uint8_t* __restrict__ label,
+                                                               const uint32_t* __restrict__ tiles_touched,
+                                                               const float* __restrict__ acc, GradPtrs out,
+                                                               float* __restrict__ plane_acc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = g.n;
+    const int ncoef = (g.sh_degree + 1) * (g.sh_degree + 1);
+    double pn[4] = {0.0, 0.0, 0.0, 0.0};   // d n_hat, d d_hat contributed by this Gaussian
+    if (i < n) {
+        double dmu[3] = {0.0, 0.0, 0.0}, ds[3] = {0.0, 0.0, 0.0}, dqv[4] = {0.0, 0.0, 0.0, 0.0};
+        double gop = 0.0;
+        const bool drawn = tiles_touched[i] > 0;
+        if (drawn) {
+            const double mu[3] = {g.mean[i], g.mean[n + i], g.mean[2 * n + i]};
+            const double s[3] = {g.scale[i], g.scale[n + i], g.scale[2 * n + i]};
+            double q4[4] = {g.quat[i], g.quat[n + i], g.quat[2 * n + i], g.quat[3 * n + i]};
+            const double qlen = sqrt(q4[0] * q4[0] + q4[1] * q4[1] + q4[2] * q4[2] + q4[3] * q4[3]);
+            const double qw = q4[0] / qlen, qx = q4[1] / qlen, qy = q4[2] / qlen, qz = q4[3] / qlen;
+            const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
+                                 2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
+                                 2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
+            const double* Rc = cam.R;
+            double t[3];
+            for (int a = 0; a < 3; ++a) t[a] = Rc[3 * a] * mu[0] + Rc[3 * a + 1] * mu[1] + Rc[3 * a + 2] * mu[2] + cam.t[a];
+            const double z = t[2], iz = 1.0 / z;
+            const double ur = t[0] * iz, vr = t[1] * iz;
+            const bool ux = fabs(ur) <= cam.limx, vy = fabs(vr) <= cam.limy;
+            const double u = fmin(cam.limx, fmax(-cam.limx, ur)), v = fmin(cam.limy, fmax(-cam.limy, vr));
+            const double j00 = cam.fx * iz, j02 = -cam.fx * u * iz, j11 = cam.fy * iz, j12 = -cam.fy * v * iz;
+            double T0[3], T1[3], TR0[3], TR1[3], K0[3], K1[3];
+            for (int c = 0; c < 3; ++c) {
+                T0[c] = j00 * Rc[c] + j02 * Rc[6 + c];
+                T1[c] = j11 * Rc[3 + c] + j12 * Rc[6 + c];
+            }
+            for (int c = 0; c < 3; ++c) {
+                TR0[c] = T0[0] * R[c] + T0[1] * R[3 + c] + T0[2] * R[6 + c];
+                TR1[c] = T1[0] * R[c] + T1[1] * R[3 + c] + T1[2] * R[6 + c];
+                K0[c] = TR0[c] * s[c];
+                K1[c] = TR1[c] * s[c];
+            }
+            const double v00 = K0[0] * K0[0] + K0[1] * K0[1] + K0[2] * K0[2] + kDilation;
+            const double v01 = K0[0] * K1[0] + K0[1] * K1[1] + K0[2] * K1[2];
+            const double v11 = K1[0] * K1[0] + K1[1] * K1[1] + K1[2] * K1[2] + kDilation;
+            const double det = v00 * v11 - v01 * v01;
+            const double id2 = 1.0 / (det * det);
+            const double gmx = acc[A_MX * n + i], gmy = acc[A_MY * n + i];
+            const double gca = acc[A_CA * n + i], gcb = acc[A_CB * n + i], gcc = acc[A_CC * n + i];
+            gop = acc[A_OP * n + i];
+            // conic (a, b, c) = (v11, -v01, v00) / det  ->  Vhat
+            const double dv00 = (-gca * v11 * v11 + gcb * v01 * v11 - gcc * v01 * v01) * id2;
+            const double dv11 = (-gca * v01 * v01 + gcb * v01 * v00 - gcc * v00 * v00) * id2;
+            const double dv01 = (2.0 * gca * v11 * v01 - gcb * (det + 2.0 * v01 * v01) + 2.0 * gcc * v00 * v01) * id2;
+            double dR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            double dT0[3] = {0, 0, 0}, dT1[3] = {0, 0, 0};
+            for (int c = 0; c < 3; ++c) {
+                const double dK0 = 2.0 * dv00 * K0[c] + dv01 * K1[c];
+                const double dK1 = 2.0 * dv11 * K1[c] + dv01 * K0[c];
+                ds[c] += dK0 * TR0[c] + dK1 * TR1[c];
+                const double dTR0 = dK0 * s[c], dTR1 = dK1 * s[c];
+                for (int m = 0; m < 3; ++m) {
+                    dR[3 * m + c] += T0[m] * dTR0 + T1[m] * dTR1;
+                    dT0[m] += dTR0 * R[3 * m + c];
+                    dT1[m] += dTR1 * R[3 * m + c];
+                }
+            }
+            double dj00 = 0, dj02 = 0, dj11 = 0, dj12 = 0;
+            for (int m = 0; m < 3; ++m) {
+                dj00 += dT0[m] * Rc[m];
+                dj02 += dT0[m] * Rc[6 + m];
+                dj11 += dT1[m] * Rc[3 + m];
+                dj12 += dT1[m] * Rc[6 + m];
+            }
+            double dt[3] = {0, 0, 0};
+            dt[2] += -cam.fx * iz * iz * dj00 - cam.fy * iz * iz * dj11;
+            if (ux) {
+                dt[0] += -cam.fx * iz * iz * dj02;
+                dt[2] += 2.0 * cam.fx * t[0] * iz * iz * iz * dj02;
+            } else {
+                dt[2] += cam.fx * u * iz * iz * dj02;
+            }
+            if (vy) {
+                dt[1] += -cam.fy * iz * iz * dj12;
+                dt[2] += 2.0 * cam.fy * t[1] * iz * iz * iz * dj12;
+            } else {
+                dt[2] += cam.fy * v * iz * iz * dj12;
+            }
+            // projected centre
+            dt[0] += gmx * cam.fx * iz;
+            dt[2] -= gmx * cam.fx * t[0] * iz * iz;
+            dt[1] += gmy * cam.fy * iz;
+            dt[2] -= gmy * cam.fy * t[1] * iz * iz;
+
+            // colour
+            const double dvec[3] = {mu[0] - cam.e[0], mu[1] - cam.e[1], mu[2] - cam.e[2]};
+            const double dlen = sqrt(dvec[0] * dvec[0] + dvec[1] * dvec[1] + dvec[2] * dvec[2]);
+            const double dir[3] = {dvec[0] / dlen, dvec[1] / dlen, dvec[2] / dlen};
+            double Y[16], dY[16];
+            sh_values(g.sh_degree, dir[0], dir[1], dir[2], Y);
+            for (int k = 0; k < ncoef; ++k) dY[k] = 0.0;
+            for (int ch = 0; ch < 3; ++ch) {
+                const double gcol = acc[(A_R + ch) * n + i];
+                double raw = 0.5;
+                for (int k = 0; k < ncoef; ++k) raw += Y[k] * (double)g.sh[((int64_t)k * 3 + ch) * n + i];
+                const bool pass = raw >= 0.0;
+                for (int k = 0; k < ncoef; ++k) {
+                    const int64_t o = ((int64_t)k * 3 + ch) * n + i;
+                    out.sh[o] = pass ? (float)(gcol * Y[k]) : 0.0f;
+                    if (pass) dY[k] += gcol * (double)g.sh[o];
+                }
+            }
+            double ddir[3];
+            sh_backward(g.sh_degree, dir[0], dir[1], dir[2], dY, ddir);
+            const double dd = ddir[0] * dir[0] + ddir[1] * dir[1] + ddir[2] * dir[2];
+            for (int a = 0; a < 3; ++a) dmu[a] += (ddir[a] - dir[a] * dd) / dlen;
+
+            // whitened ray set-up of CUTOFF Gaussians
+            if (pl.enabled && label[i] == RARA_LABEL_CUTOFF) {
+                double gd0[3], ggx[3], ggy[3];
+                for (int a = 0; a < 3; ++a) {
+                    gd0[a] = acc[(A_D0 + a) * n + i];
+                    ggx[a] = acc[(A_GX + a) * n + i];
+                    ggy[a] = acc[(A_GY + a) * n + i];
+                }
+                const double gz = acc[A_Z * n + i], gdep = acc[A_DEP * n + i], gg0 = acc[A_G0 * n + i];
+                const double v0[3] = {dvec[0] * iz, dvec[1] * iz, dvec[2] * iz};
+                double dv0[3] = {pl.n[0] * gg0, pl.n[1] * gg0, pl.n[2] * gg0};
+                for (int a = 0; a < 3; ++a) {
+                    const double ia = 1.0 / s[a];
+                    double dsa = 0.0;
+                    for (int b2 = 0; b2 < 3; ++b2) {
+                        const double mab = R[3 * b2 + a] * ia;   // M^-1[a][b] = R[b][a] / s[a]
+                        const double dM = gd0[a] * v0[b2] + ggx[a] * Rc[b2] / cam.fx + ggy[a] * Rc[3 + b2] / cam.fy;
+                        dv0[b2] += mab * gd0[a];
+                        dR[3 * b2 + a] += dM * ia;
+                        dsa -= dM * mab * ia;
+                    }
+                    ds[a] += dsa;
+                }
+                dt[2] += gz;
+                for (int a = 0; a < 3; ++a) {
+                    dmu[a] += pl.n[a] * gdep + dv0[a] * iz;
+                    pn[a] += mu[a] * gdep + v0[a] * gg0;
+                }
+                pn[3] += gdep;
+                dt[2] -= (dvec[0] * dv0[0] + dvec[1] * dv0[1] + dvec[2] * dv0[2]) * iz * iz;
+            }
+            // t = R_c mu + t_c
+            for (int a = 0; a < 3; ++a) dmu[a] += Rc[a] * dt[0] + Rc[3 + a] * dt[1] + Rc[6 + a] * dt[2];
+            // R(q_hat) -> q_hat -> q
+            const double r_ = qw, x = qx, y = qy, zq = qz;
+            double dq[4];
+            dq[0] = -2 * zq * dR[1] + 2 * y * dR[2] + 2 * zq * dR[3] - 2 * x * dR[5] - 2 * y * dR[6] + 2 * x * dR[7];
+            dq[1] = 2 * y * dR[1] + 2 * zq * dR[2] + 2 * y * dR[3] - 4 * x * dR[4] - 2 * r_ * dR[5] + 2 * zq * dR[6] +
+                    2 * r_ * dR[7] - 4 * x * dR[8];
+            dq[2] = -4 * y * dR[0] + 2 * x * dR[1] + 2 * r_ * dR[2] + 2 * x * dR[3] + 2 * zq * dR[5] - 2 * r_ * dR[6] +
+                    2 * zq * dR[7] - 4 * y * dR[8];
+            dq[3] = -4 * zq * dR[0] - 2 * r_ * dR[1] + 2 * x * dR[2] + 2 * r_ * dR[3] - 4 * zq * dR[4] + 2 * y * dR[5] +
+                    2 * x * dR[6] + 2 * y * dR[7];
+            const double qn[4] = {qw, qx, qy, qz};
+            const double dot = dq[0] * qn[0] + dq[1] * qn[1] + dq[2] * qn[2] + dq[3] * qn[3];
+            for (int k = 0; k < 4; ++k) dqv[k] = (dq[k] - qn[k] * dot) / qlen;
+        } else {
+            for (int k = 0; k < ncoef; ++k)
+                for (int ch = 0; ch < 3; ++ch) out.sh[((int64_t)k * 3 + ch) * n + i] = 0.0f;
+        }
+        for (int a = 0; a < 3; ++a) {
+            out.mean[a * n + i] = (float)dmu[a];
+            out.scale[a * n + i] = (float)ds[a];
+        }
+        for (int k = 0; k < 4; ++k) out.quat[k * n + i] = (float)dqv[k];
+        out.opacity[i] = (float)gop;
+    }
+    // plane terms: block sum, one atomic per block and component
+    __shared__ float red[4][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = 0; k < 4; ++k) {
+        const float s = wave_sum((float)pn[k]);
+        if (lane == 0) red[k][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const float s = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+        if (s != 0.0f) atomicAdd(plane_acc + threadIdx.x, s);
+    }
+}
+
+// raw plane gradient: n_hat = n / |n|, d_hat = d / |n|; the pixel-rate terms
+// (ax, ay) = (R_c n_hat)_{x,y} / f_{x,y}.
+__global__ void plane_finalize_kernel(CamParams cam, PlaneParams pl, double len, const float* __restrict__ plane_acc,
+                                      float* __restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (!pl.enabled) {
+        out[0] = out[1] = out[2] = out[3] = 0.0f;
+        return;
+    }
+    double dn[3];
+    for (int a = 0; a < 3; ++a)
+        dn[a] = plane_acc[a] + cam.R[a] * plane_acc[4] / cam.fx + cam.R[3 + a] * plane_acc[5] / cam.fy;
+    const double dd = plane_acc[3];
+    const double dot = dn[0] * pl.n[0] + dn[1] * pl.n[1] + dn[2] * pl.n[2];
+    for (int a = 0; a < 3; ++a) out[a] = (float)((dn[a] - pl.n[a] * dot - pl.n[a] * pl.d * dd) / len);
+    out[3] = (float)(dd / len);
+}
+
+}  // namespace
+
 size_t backward_workspace_bytes(int64_t n, int32_t width, int32_t height)
 {
-    (void)n; (void)width; (void)height;
-    return 256;
+    (void)width;
+    (void)height;
+    const size_t acc = ((size_t)kAccRows * (size_t)(n > 0 ? n : 1) * 4 + 255) & ~size_t(255);
+    return acc + 256;
 }
-}  // namespace rara
 
-extern "C" rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam, const rara_plane* plane,
-                                            const rara_projected* proj, const rara_binned* bins, const float* final_T,
-                                            const uint32_t* n_contrib, const float* dL_dimage, const rara_grads* grads,
-                                            void* workspace, size_t ws_bytes, void* stream)
+hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl, double plane_len,
+                           const ProjPtrs& proj, const rara_binned& bins, const RenderParams& rp,
+                           const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
+                           const rara_grads& grads, void* workspace, hipStream_t s)
 {
-    (void)g; (void)cam; (void)plane; (void)proj; (void)bins; (void)final_T; (void)n_contrib; (void)dL_dimage;
-    (void)grads; (void)workspace; (void)ws_bytes; (void)stream;
-    return RARA_ERR_UNSUPPORTED;
+    const int64_t n = g.n > 0 ? g.n : 1;
+    float* acc = static_cast<float*>(workspace);
+    const size_t acc_bytes = ((size_t)kAccRows * (size_t)n * 4 + 255) & ~size_t(255);
+    float* plane_acc = reinterpret_cast<float*>(static_cast<char*>(workspace) + acc_bytes);
+    const int64_t count = (int64_t)(acc_bytes / 4) + kPlaneAcc;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, acc, count);
+    BackParams bp{rp, g.n};
+    hipLaunchKernelGGL(blend_backward_kernel, dim3((unsigned)work_grid(rp.num_tiles)), dim3(64), 0, s, proj.splat,
+                       proj.ray, bins.vals, reinterpret_cast<const uint2*>(bins.ranges), bins.work, bins.overflow, bp,
+                       final_T, n_contrib, dL_dimage, acc, plane_acc);
+    if (g.n > 0) {
+        GradPtrs gp{grads.mean, grads.scale, grads.quat, grads.opacity, grads.sh};
+        hipLaunchKernelGGL(project_backward_kernel, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g, cam, pl,
+                           proj.label, proj.tiles_touched, acc, gp, plane_acc);
+    }
+    hipLaunchKernelGGL(plane_finalize_kernel, dim3(1), dim3(64), 0, s, cam, pl, plane_len, plane_acc, grads.plane);
+    return hipGetLastError();
 }
+
+}  // namespace rara

@@ -24,44 +24,11 @@
 // the chord is clamp(1/2 + phi_m / (2 |g| h), 0, 1).  Every term stays of the
 // order of the Gaussian's own size, so FP32 keeps its accuracy even for the
 // 40:1 strand Gaussians (the expanded B^2 - 4AC cancels catastrophically).
-#include "rara_internal.h"
+#include "blend_common.h"
 
 namespace rara {
 
 namespace {
-
-constexpr int kBatch = 64;
-
-struct CutRec {
-    float4 a;   // d0.xyz, gx.x
-    float4 b;   // gx.yz, gy.xy
-    float4 c;   // gy.z, z, dep, g0
-};
-
-__device__ inline float chord_weight(const CutRec& k, float dx, float dy, float ax, float ay)
-{
-    const float gx0 = k.a.w, gx1 = k.b.x, gx2 = k.b.y;
-    const float gy0 = k.b.z, gy1 = k.b.w, gy2 = k.c.x;
-    const float z = k.c.y, dep = k.c.z, g0 = k.c.w;
-    const float e0 = gx0 * dx + gy0 * dy, e1 = gx1 * dx + gy1 * dy, e2 = gx2 * dx + gy2 * dy;
-    const float D0 = k.a.x + e0, D1 = k.a.y + e1, D2 = k.a.z + e2;
-    const float P0 = z * e0, P1 = z * e1, P2 = z * e2;
-    const float DD = D0 * D0 + D1 * D1 + D2 * D2;
-    const float PD = P0 * D0 + P1 * D1 + P2 * D2;
-    const float iDD = __builtin_amdgcn_rcpf(DD);
-    const float sm = -PD * iDD;
-    const float Q0 = P0 + sm * D0, Q1 = P1 + sm * D1, Q2 = P2 + sm * D2;
-    const float h2 = kKappa2 - (Q0 * Q0 + Q1 * Q1 + Q2 * Q2);
-    if (!(h2 > 0.0f)) return 1.0f;                       // miss / tangent: fewer than two intersections
-    const float hs = __builtin_amdgcn_sqrtf(h2 * iDD);   // chord half-length in camera depth
-    if (z + sm - hs < 0.0f) return 1.0f;                 // near intersection behind the camera
-    const float u = ax * dx + ay * dy;
-    const float gg = g0 + u;
-    const float phim = dep + z * u + sm * gg;
-    if (gg == 0.0f) return phim >= 0.0f ? 1.0f : 0.0f;
-    const float w = 0.5f + phim * __builtin_amdgcn_rcpf(2.0f * fabsf(gg) * hs);
-    return __builtin_amdgcn_fmed3f(w, 0.0f, 1.0f);
-}
 
 // One pixel's front-to-back update with one list entry, straight-line.
 // alpha = min(0.99, a0 w); entries with a positive exponent or alpha < 1/255
@@ -117,18 +84,19 @@ __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec
     }
 
     const double ox = (double)(tx * kTile), oy = (double)(ty * kTile);
-    const float kq = -0.5f * kLog2e;
     const bool plane_on = p.plane_enabled != 0;
 
     Splat nx;
     float4 nr0, nr1, nr2;
     bool have = false;
+    uint32_t cur_id = 0u;
     uint32_t my_mask = 0u;
     auto fetch = [&](uint32_t base) {
         const uint32_t idx = base + lane;
         have = idx < rg.y;
         if (have) {
             const uint32_t id = vals[idx];
+            cur_id = id;
             nx = splats[id];
             if (nx.label == RARA_LABEL_CUTOFF && plane_on) {
                 const float4* rr = reinterpret_cast<const float4*>(rays + id);
@@ -141,29 +109,7 @@ __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec
     auto stage = [&](int buf) {
         my_mask = 0u;
         if (have) {
-            const float mx = (float)(nx.mx - ox), my = (float)(nx.my - oy);
-            s_a[buf][lane] = make_float4(mx, my, nx.ca * kq, -nx.cb * kLog2e);
-            s_b[buf][lane] = make_float4(nx.cc * kq, nx.op, nx.r, nx.g);
-            // Quadrants of the tile the entry can reach with alpha >= 1/255:
-            // delta exp(-m/2) >= 1/255 needs Mahalanobis^2 m <= 2 ln(255 delta),
-            // whose ellipse has axis half-widths sqrt(m Vhat_00), sqrt(m Vhat_11).
-            // Padded (1 % + 0.1 px) so float rounding can only widen the box;
-            // an entry is never skipped for a pixel it could reach.
-            const float s255 = 255.0f * nx.op;
-            if (s255 > 1.0f) {
-                const float m2 = 2.0f * __logf(s255) * 1.001f + 1e-3f;
-                const float idet = 1.0f / (nx.ca * nx.cc - nx.cb * nx.cb);
-                const float hx = sqrtf(m2 * nx.cc * idet) * 1.01f + 0.1f;
-                const float hy = sqrtf(m2 * nx.ca * idet) * 1.01f + 0.1f;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float qx = (float)((q & 1) * 8), qy = (float)((q >> 1) * 8);
-                    const bool hit = (mx - hx <= qx + 7.0f) && (mx + hx >= qx) && (my - hy <= qy + 7.0f) &&
-                                     (my + hy >= qy);
-                    my_mask |= hit ? (1u << q) : 0u;
-                }
-            }
-            s_c[buf][lane] = make_float4(nx.b, __uint_as_float(nx.label | (my_mask << 8)), 0.0f, 0.0f);
+            stage_entry(nx, ox, oy, s_a[buf][lane], s_b[buf][lane], s_c[buf][lane], my_mask, cur_id);
             if (nx.label == RARA_LABEL_CUTOFF && plane_on) {
                 CutRec c;
                 c.a = nr0;
@@ -198,11 +144,8 @@ __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec
             const uint32_t k1 = base - rg.x + (uint32_t)j + 1u;
             const uint32_t lm = __builtin_amdgcn_readfirstlane(__float_as_uint(c.y));
             const bool cut = plane_on && ((lm & 0xffu) == RARA_LABEL_CUTOFF);
-            // exponent dx (A dx + B dy) + C dy^2, dy terms shared by slots of one row
             const float dxa = lpx[0] - a.x, dya = lpy[0] - a.y;
             const float dxb = lpx[kSlots - 1] - a.x, dyb = lpy[kSlots - 1] - a.y;
-            const float Bya = a.w * dya, Byb = a.w * dyb;
-            const float Cya = b.x * dya * dya, Cyb = b.x * dyb * dyb;
 #pragma unroll
             for (int q = 0; q < kSlots; ++q) {
                 if (((lm >> (8 + qof[q])) & 1u) && T[q] > 0.0f) {
@@ -210,7 +153,7 @@ __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec
                     const bool yb = kSlots == 4 ? (q >> 1) : false;
                     const float dx = xb ? dxb : dxa;
                     const float dy = yb ? dyb : dya;
-                    const float pw = fmaf(dx, fmaf(a.z, dx, yb ? Byb : Bya), yb ? Cyb : Cya);
+                    const float pw = entry_power(a, b, dx, dy);
                     const float a0 = b.y * __builtin_amdgcn_exp2f(pw);
                     float w = 1.0f;
                     if (cut) w = chord_weight(s_cut[buf][j], dx, dy, p.ax, p.ay);

@@ -117,6 +117,10 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
 hipError_t launch_sort(const BinWorkspace& ws, int64_t cap, const rara_binned& out, int passes, hipStream_t s);
 hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, hipStream_t s);
 hipError_t launch_plan(const rara_binned& out, int num_tiles, hipStream_t s);
+hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl, double plane_len,
+                           const ProjPtrs& proj, const rara_binned& bins, const RenderParams& rp,
+                           const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
+                           const rara_grads& grads, void* workspace, hipStream_t s);
 hipError_t launch_blend(const Splat* splat, const RayRec* ray, const rara_binned& bins, const RenderParams& p,
                         float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked, hipStream_t s);
 

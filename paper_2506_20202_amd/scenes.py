@@ -417,3 +417,26 @@ def small_scene(seed: int = 0, n: int = 12, spread: float = 0.35, logscale_mean:
 
 def small_camera(size: int = 32) -> Camera:
     return pinhole((0.3, -0.4, -3.0), (0.0, 0.0, 0.0), size, size, 30.0)
+
+
+def grad_scene(seed: int = 4, n: int = 200, sh_degree: int = 3) -> Scene:
+    """General-scene statistics shrunk to a few hundred Gaussians in view of a
+    64x64 camera (means N(0, 0.5^2), log-scale N(-2.5, 0.5), opacity
+    logistic(N(0, 1.5)), SH coefficients N(0, 0.3)); used for gradient checks."""
+    rng = np.random.default_rng(60_000 + seed)
+    mean = rng.normal(0.0, 0.5, (3, n))
+    scale = np.exp(rng.normal(-2.5, 0.5, (3, n)))
+    quat = _unit_quats(rng, n)
+    opacity = _logistic(rng.normal(0.0, 1.5, n))
+    sh = rng.normal(0.0, 0.3, ((sh_degree + 1) ** 2, 3, n))
+    return Scene(_f32(mean), _f32(scale), _f32(quat), _f32(opacity), _f32(sh), sh_degree)
+
+
+def grad_camera(size: int = 64) -> Camera:
+    return pinhole((1.0, 0.8, -4.0), (0.0, 0.0, 0.0), size, size, 50.0)
+
+
+def grad_plane(seed: int = 4) -> Plane:
+    rng = np.random.default_rng(70_000 + seed)
+    n = _unit_vectors(rng, 1)[0]
+    return Plane(_f32(n), float(np.float32(rng.uniform(-0.1, 0.1))), True)

@@ -35,7 +35,7 @@ def _grads_ref(sc, cam, pl, wimg, bg=(0.0, 0.0, 0.0)):
     p = TR.params_from_scene(sc, pl)
     img = TR.render(p, sc, cam, pl.enabled, st, bg=bg)
     (img * torch.tensor(wimg)).sum().backward()
-    return {k: v.grad.numpy() for k, v in p.items()}, img
+    return {k: (v.grad.numpy() if v.grad is not None else np.zeros(v.shape)) for k, v in p.items()}, img
 
 
 def _compare(g, r, groups):

@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0, help="only run this many frames (for profilers)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="with --profile-steps: also run one plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -155,6 +157,25 @@ def main():
     W, H = frames[0][0].width, frames[0][0].height
     print(f"[bench] scene n={sc.n} ready in {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
 
+    steps = args.profile_steps if args.profile_steps else args.steps
+    stream = torch.cuda.current_stream(dev)
+    if args.profile_steps:
+        # profiler runs: fixed capacity, no capacity sweep, only the frames asked for
+        fr = R.Frame(sc.n, W, H, 16 * sc.n, dev, walked=False)
+        for i in range(args.warmup + steps):
+            cam, pl = frames[(4 * i) % len(frames)]   # every plane offset, four views
+            R.enqueue_frame(ds, fr, cam, pl)
+        torch.cuda.synchronize()
+        assert int(fr.bins.overflow.item()) == 0
+        if args.calibrate_copy:
+            src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+        print(json.dumps({"profile_steps": steps, "warmup": args.warmup, "copy_bytes": (256 << 20) if args.calibrate_copy else 0}))
+        return
+
     # capacity from one pass over every frame of the sweep (outside the timed region)
     fr = R.Frame(sc.n, W, H, 8 * sc.n, dev)
     maxP = 0
@@ -169,9 +190,6 @@ def main():
     fr.grow(int(maxP * 1.05) + 4096)
     print(f"[bench] max pairs {maxP}, capacity {fr.capacity}", file=sys.stderr, flush=True)
 
-    steps = args.profile_steps if args.profile_steps else args.steps
-    stream = torch.cuda.current_stream(dev)
-
     def run(frame_list, k0, k):
         for i in range(k):
             cam, pl = frame_list[(k0 + i) % len(frame_list)]
@@ -179,11 +197,6 @@ def main():
 
     run(frames, 0, args.warmup)
     torch.cuda.synchronize()
-    if args.profile_steps:
-        run(frames, 0, steps)
-        torch.cuda.synchronize()
-        print(json.dumps({"profile_steps": steps}))
-        return
 
     # ---- timed region: K clipped frames back to back ----
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -73,22 +73,34 @@ ProjPtrs proj_ptrs(const rara_projected* p)
 size_t rara::bin_workspace_layout(int64_t n, int64_t cap, BinWorkspace* ws, char* base)
 {
     auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
-    int64_t scan_blocks = (n + kScanBlock - 1) / kScanBlock;
-    if (scan_blocks < 1) scan_blocks = 1;
-    int64_t sort_blocks = (cap + kSortTile - 1) / kSortTile;
-    if (sort_blocks < 1) sort_blocks = 1;
+    const int64_t nn = n > 0 ? n : 1;
+    int64_t scan_blocks = (nn + kScanBlock - 1) / kScanBlock;
+    const int64_t depth_blocks = (nn + kSortTile - 1) / kSortTile;
+    int64_t tile_blocks = (cap + kSortTile - 1) / kSortTile;
+    if (tile_blocks < 1) tile_blocks = 1;
+    const int64_t hist_cols = depth_blocks > tile_blocks ? depth_blocks : tile_blocks;
     size_t off = 0;
     BinWorkspace w;
     w.scan_blocks = scan_blocks;
-    w.sort_blocks = sort_blocks;
+    w.depth_blocks = depth_blocks;
+    w.tile_blocks = tile_blocks;
     w.block_sums = reinterpret_cast<uint32_t*>(base + off);
     off += align((size_t)scan_blocks * 4);
-    w.keys_alt = reinterpret_cast<uint64_t*>(base + off);
-    off += align((size_t)cap * 8);
-    w.vals_alt = reinterpret_cast<uint32_t*>(base + off);
+    w.dcount = reinterpret_cast<int64_t*>(base + off);
+    w.dover = reinterpret_cast<int32_t*>(base + off + 8);
+    off += 256;
+    for (int b = 0; b < 2; ++b) {
+        w.dkeys[b] = reinterpret_cast<uint32_t*>(base + off);
+        off += align((size_t)nn * 4);
+        w.dvals[b] = reinterpret_cast<uint32_t*>(base + off);
+        off += align((size_t)nn * 4);
+    }
+    w.tkeys = reinterpret_cast<uint32_t*>(base + off);
+    off += align((size_t)cap * 4);
+    w.tvals = reinterpret_cast<uint32_t*>(base + off);
     off += align((size_t)cap * 4);
     w.hist = reinterpret_cast<uint32_t*>(base + off);
-    off += align((size_t)kRadix * sort_blocks * 4);
+    off += align((size_t)kRadix * hist_cols * 4);
     w.digit_totals = reinterpret_cast<uint32_t*>(base + off);
     off += align((size_t)kRadix * 4);
     if (ws) *ws = w;
@@ -154,11 +166,10 @@ rara_status rara_bin_sort(const rara_projected* proj, int64_t n, const rara_came
     const size_t need = bin_workspace_layout(n, pair_capacity, &ws, static_cast<char*>(workspace));
     if (ws_bytes < need) return RARA_ERR_INVALID;
     const int num_tiles = cp.tiles_x * cp.tiles_y;
-    const int key_bits = 31 + ceil_log2(num_tiles);
-    const int passes = (key_bits + kRadixBits - 1) / kRadixBits;
+    int tile_passes = (ceil_log2(num_tiles) + kRadixBits - 1) / kRadixBits;
+    if (tile_passes < 1) tile_passes = 1;   // the last pass also writes the 64-bit keys
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = launch_bin(proj_ptrs(proj), n, cp, pair_capacity, ws, *out, (passes & 1) != 0, s);
-    if (e == hipSuccess) e = launch_sort(ws, pair_capacity, *out, passes, s);
+    hipError_t e = launch_bin(proj_ptrs(proj), n, cp, pair_capacity, ws, *out, tile_passes, s);
     if (e == hipSuccess) e = launch_ranges(*out, pair_capacity, num_tiles, s);
     if (e == hipSuccess) e = launch_plan(*out, num_tiles, s);
     return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;

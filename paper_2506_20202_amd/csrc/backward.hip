@@ -282,9 +282,8 @@ __global__ __launch_bounds__(64) void blend_backward_kernel(const Splat* __restr
 {
     if (*overflow) return;
     const int T = bp.rp.num_tiles;
-    const uint32_t n_units = work[4 * T];
-    if (blockIdx.x >= n_units) return;
-    const uint32_t unit = work[blockIdx.x];
+    uint32_t unit;
+    if (!unit_of_block(blockIdx.x, work, T, unit)) return;
     const int tile = (int)(unit >> 3), mode = (int)(unit & 7u);
     if (tile >= T || mode > 4) return;
     __shared__ float4 s_a[kBatch], s_b[kBatch], s_c[kBatch];

@@ -1,6 +1,18 @@
-// Tile binning: exclusive prefix sum of tiles_touched and emission of one
-// (tile|depth, index) pair per drawn Gaussian and covered tile; per-tile
-// [start, end) ranges after the sort.
+// Tile binning and the tile|depth sort.
+//
+// The pairs are ordered by the 64-bit key (tile << 32 | float32 depth bits),
+// ties by Gaussian index, with a stable LSD radix sort.  LSD handles the low
+// (depth) digits first, and all pairs of one Gaussian share its depth, so the
+// depth passes run on the drawn Gaussians before expansion:
+//   1. compact the drawn Gaussians (index order) with their depth bits;
+//   2. four 8-bit LSD passes on the depth bits (stable: ties stay in index order);
+//   3. exclusive scan of tiles_touched in that order and emission of one
+//      (tile, index) pair per covered tile -- the pairs are now in depth order;
+//   4. ceil(log2(tiles) / 8) stable LSD passes on the tile digits, the last one
+//      writing the 64-bit keys;
+//   5. per-tile [start, end) ranges and the blend schedule.
+// This is the same permutation as sorting the expanded pairs by all their key
+// bits, with the four depth passes over ~P / 5 items instead of P.
 //
 // The scan is reduce-then-scan over 256-Gaussian chunks.  Inside a chunk the
 // prefix is a wavefront-ballot scan: bit b of every lane's count is gathered
@@ -49,14 +61,37 @@ __device__ inline uint32_t block_ballot_scan(uint32_t v, uint32_t& total)
     return before + p;
 }
 
-__global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t* __restrict__ tt, int64_t n,
-                                                          uint32_t* __restrict__ block_sums)
+// Per-256-chunk sums.  kMode 0: tiles_touched[i]; 1: [tiles_touched[i] > 0];
+// 2: tiles_touched[order[k]] for k < *count (depth order).
+template <int kMode>
+__global__ __launch_bounds__(256) void chunk_sum_kernel(const uint32_t* __restrict__ tt,
+                                                        const uint32_t* __restrict__ order, int64_t n,
+                                                        const int64_t* __restrict__ count,
+                                                        uint32_t* __restrict__ block_sums)
 {
-    const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
-    const uint32_t v = i < n ? tt[i] : 0u;
+    const int64_t k = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    const int64_t lim = kMode == 2 ? *count : n;
+    uint32_t v = 0u;
+    if (k < lim) v = kMode == 0 ? tt[k] : (kMode == 1 ? (tt[k] > 0u ? 1u : 0u) : tt[order[k]]);
     uint32_t total;
     block_ballot_scan(v, total);
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// Drawn Gaussians in index order with their depth bits (positive floats order
+// like their bit patterns).
+__global__ __launch_bounds__(256) void compact_kernel(const uint32_t* __restrict__ tt, const float* __restrict__ depth,
+                                                      int64_t n, const uint32_t* __restrict__ block_off,
+                                                      uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals)
+{
+    const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    const bool drawn = i < n && tt[i] > 0u;
+    uint32_t total;
+    const uint32_t pre = block_ballot_scan(drawn ? 1u : 0u, total);
+    if (!drawn) return;
+    const uint32_t off = block_off[blockIdx.x] + pre;
+    dkeys[off] = __float_as_uint(depth[i]);
+    dvals[off] = (uint32_t)i;
 }
 
 // Single-workgroup exclusive scan of the chunk sums; writes the pair count and
@@ -93,26 +128,28 @@ __global__ __launch_bounds__(1024) void scan_blocks_kernel(uint32_t* __restrict_
     }
 }
 
+// One (tile, index) pair per covered tile, Gaussians taken in depth order.
 __global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ tt, const uint16_t* __restrict__ rect,
-                                                   const float* __restrict__ depth, int64_t n,
+                                                   const uint32_t* __restrict__ order,
+                                                   const int64_t* __restrict__ count,
                                                    const uint32_t* __restrict__ block_off, int tiles_x,
-                                                   const int32_t* __restrict__ overflow, uint64_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ vals)
+                                                   const int32_t* __restrict__ overflow, uint32_t* __restrict__ tkeys,
+                                                   uint32_t* __restrict__ tvals)
 {
-    const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
-    const uint32_t v = i < n ? tt[i] : 0u;
+    const int64_t k = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    const bool valid = k < *count;
+    const uint32_t id = valid ? order[k] : 0u;
+    const uint32_t v = valid ? tt[id] : 0u;
     uint32_t total;
     const uint32_t pre = block_ballot_scan(v, total);
     if (*overflow) return;
     if (v == 0) return;
     uint32_t off = block_off[blockIdx.x] + pre;
-    const ushort4 rc = *reinterpret_cast<const ushort4*>(rect + 4 * i);
-    const uint64_t dbits = (uint64_t)__float_as_uint(depth[i]);
+    const ushort4 rc = *reinterpret_cast<const ushort4*>(rect + 4 * (int64_t)id);
     for (int y = rc.y; y < rc.w; ++y)
         for (int x = rc.x; x < rc.z; ++x) {
-            const uint64_t tile = (uint64_t)(y * tiles_x + x);
-            keys[off] = (tile << 32) | dbits;
-            vals[off] = (uint32_t)i;
+            tkeys[off] = (uint32_t)(y * tiles_x + x);
+            tvals[off] = id;
             ++off;
         }
 }
@@ -157,9 +194,11 @@ __device__ inline uint32_t block_flag_scan(bool f, uint32_t& total, uint32_t* wa
 }
 
 // Blend schedule: tiles whose list has at least kHeavyList entries (the first
-// kMaxHeavy of them in tile order) become four quadrant units placed first, so
-// the longest walks start earliest and run on four waves; every other tile is
-// one unit.  Deterministic (ballot compaction in tile order).
+// kMaxHeavy of them in tile order) become four quadrant units, dispatched
+// first so the longest walks start earliest and run on four waves; every
+// other tile is one unit.  work[4h + q] = quadrant q of split tile h,
+// work[4H + l] = l-th whole tile (tile order), work[4T] = H.  Deterministic
+// (ballot compaction in tile order).
 __global__ __launch_bounds__(1024) void plan_kernel(const uint2* __restrict__ ranges, int num_tiles,
                                                     uint32_t* __restrict__ work)
 {
@@ -200,7 +239,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(const uint2* __restrict__ ra
         hbase += stot;
         lbase += ltot;
     }
-    if (tid == 0) work[4 * num_tiles] = 4 * H + ((uint32_t)num_tiles - H);
+    if (tid == 0) work[4 * num_tiles] = H;
 }
 
 }  // namespace
@@ -213,18 +252,43 @@ hipError_t launch_plan(const rara_binned& out, int num_tiles, hipStream_t s)
 }
 
 hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int64_t cap, const BinWorkspace& ws,
-                      const rara_binned& out, bool emit_to_alt, hipStream_t s)
+                      const rara_binned& out, int tile_passes, hipStream_t s)
 {
-    const int64_t nb = n > 0 ? ws.scan_blocks : 0;   // no chunks: the pair count is 0
-    if (n > 0) hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, n,
-                                  ws.block_sums);
+    const int64_t nb = n > 0 ? ws.scan_blocks : 0;   // no chunks: every count is 0
+    // 1. drawn Gaussians in index order
+    if (n > 0)
+        hipLaunchKernelGGL(chunk_sum_kernel<1>, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, nullptr, n,
+                           nullptr, ws.block_sums);
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, ws.block_sums, nb, INT64_MAX, ws.dcount,
+                       ws.dover);
+    if (n > 0)
+        hipLaunchKernelGGL(compact_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, proj.depth, n,
+                           ws.block_sums, ws.dkeys[0], ws.dvals[0]);
+    // 2. depth order (four passes: the result is back in buffer 0)
+    hipError_t e = sort_passes(ws.dkeys[0], ws.dvals[0], ws.dkeys[1], ws.dvals[1], 4, ws.dcount, nullptr,
+                               ws.depth_blocks, ws.hist, ws.digit_totals, nullptr, nullptr, nullptr, s);
+    if (e != hipSuccess) return e;
+    // 3. pair offsets in depth order, pair count, overflow flag, emission
+    if (n > 0)
+        hipLaunchKernelGGL(chunk_sum_kernel<2>, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, ws.dvals[0],
+                           n, ws.dcount, ws.block_sums);
     hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, ws.block_sums, nb, cap, out.num_pairs,
                        out.overflow);
+    // the last tile pass must read the workspace buffer, never out.keys, which
+    // it writes; the other buffer lives in out.keys (cap x (u32, u32) fits)
+    uint32_t* alias_k = reinterpret_cast<uint32_t*>(out.keys);
+    uint32_t* alias_v = alias_k + cap;
+    const bool last_reads_a = ((tile_passes - 1) & 1) == 0;
+    uint32_t* ka = last_reads_a ? ws.tkeys : alias_k;
+    uint32_t* va = last_reads_a ? ws.tvals : alias_v;
+    uint32_t* kb = last_reads_a ? alias_k : ws.tkeys;
+    uint32_t* vb = last_reads_a ? alias_v : ws.tvals;
     if (n > 0)
-        hipLaunchKernelGGL(emit_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, proj.rect, proj.depth, n,
-                           ws.block_sums, cam.tiles_x, out.overflow, emit_to_alt ? ws.keys_alt : out.keys,
-                           emit_to_alt ? ws.vals_alt : out.vals);
-    return hipGetLastError();
+        hipLaunchKernelGGL(emit_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, proj.rect, ws.dvals[0],
+                           ws.dcount, ws.block_sums, cam.tiles_x, out.overflow, ka, va);
+    // 4. tile digits; the last pass writes the 64-bit keys and the values
+    return sort_passes(ka, va, kb, vb, tile_passes, out.num_pairs, out.overflow, ws.tile_blocks, ws.hist,
+                       ws.digit_totals, out.keys, out.vals, proj.depth, s);
 }
 
 hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, hipStream_t s)

@@ -182,9 +182,7 @@ __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec
     }
 }
 
-// One wave per work unit.  work[] (written by the binning stage) lists the
-// quadrant units of tiles with long lists first, then whole tiles; work[4T]
-// holds the number of units.
+// One wave per work unit (see unit_of_block for the schedule).
 template <bool kWalked>
 __global__ __launch_bounds__(64) void blend_kernel(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
                                                    const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
@@ -194,9 +192,8 @@ __global__ __launch_bounds__(64) void blend_kernel(const Splat* __restrict__ spl
                                                    uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
 {
     if (*overflow) return;
-    const uint32_t n_units = work[4 * p.num_tiles];
-    if (blockIdx.x >= n_units) return;
-    const uint32_t unit = work[blockIdx.x];
+    uint32_t unit;
+    if (!unit_of_block(blockIdx.x, work, p.num_tiles, unit)) return;
     const int tile = (int)(unit >> 3), mode = (int)(unit & 7u);
     if (tile >= p.num_tiles || mode > 4) return;
     __shared__ float4 s_a[2][kBatch], s_b[2][kBatch], s_c[2][kBatch];

@@ -84,10 +84,11 @@ struct RenderParams {
 // ---- blend work list --------------------------------------------------------
 // Tiles whose list holds at least kHeavyList entries are blended as four
 // quadrant units (one wave each) and scheduled first; at most kMaxHeavy tiles
-// per frame are split.  work[] has 4 * tiles + 1 entries.
+// per frame are split.  work[] has 4 * tiles + 1 entries; the blend grid adds
+// room for the XCD-aligned padding of the schedule.
 constexpr uint32_t kHeavyList = 1536;
 constexpr int kMaxHeavy = 2048;
-inline int64_t work_grid(int64_t tiles) { return tiles + 3 * (tiles < kMaxHeavy ? tiles : kMaxHeavy); }
+inline int64_t work_grid(int64_t tiles) { return tiles + 3 * (tiles < kMaxHeavy ? tiles : kMaxHeavy) + 64; }
 
 // ---- bin/sort workspace carve-up -------------------------------------------
 constexpr int kScanBlock = 256;      // Gaussians per scan chunk
@@ -98,12 +99,16 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
 struct BinWorkspace {
-    uint32_t* block_sums;   // [scan_blocks]
-    uint64_t* keys_alt;     // [cap]
-    uint32_t* vals_alt;     // [cap]
-    uint32_t* hist;         // [kRadix][sort_blocks]
-    uint32_t* digit_totals; // [kRadix]
-    int64_t scan_blocks, sort_blocks;
+    uint32_t* block_sums;    // [scan_blocks]
+    int64_t* dcount;         // drawn-Gaussian count
+    int32_t* dover;          // unused overflow slot of that count
+    uint32_t* dkeys[2];      // depth keys, ping-pong [n]
+    uint32_t* dvals[2];      // Gaussian indices, ping-pong [n]
+    uint32_t* tkeys;         // tile keys [cap]
+    uint32_t* tvals;         // Gaussian indices [cap]
+    uint32_t* hist;          // [kRadix][max(depth_blocks, tile_blocks)]
+    uint32_t* digit_totals;  // [kRadix]
+    int64_t scan_blocks, depth_blocks, tile_blocks;
 };
 
 size_t bin_workspace_layout(int64_t n, int64_t cap, BinWorkspace* ws, char* base);
@@ -113,8 +118,10 @@ size_t backward_workspace_bytes(int64_t n, int32_t width, int32_t height);
 hipError_t launch_preprocess(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl, const ProjPtrs& out,
                              hipStream_t s);
 hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int64_t cap, const BinWorkspace& ws,
-                      const rara_binned& out, bool emit_to_alt, hipStream_t s);
-hipError_t launch_sort(const BinWorkspace& ws, int64_t cap, const rara_binned& out, int passes, hipStream_t s);
+                      const rara_binned& out, int tile_passes, hipStream_t s);
+hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int passes, const int64_t* count,
+                       const int32_t* overflow, int64_t blocks, uint32_t* hist, uint32_t* digit_totals,
+                       uint64_t* final_keys, uint32_t* final_vals, const float* depth, hipStream_t s);
 hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, hipStream_t s);
 hipError_t launch_plan(const rara_binned& out, int num_tiles, hipStream_t s);
 hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl, double plane_len,

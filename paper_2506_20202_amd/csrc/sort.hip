@@ -1,6 +1,7 @@
-// Stable LSD radix sort of (uint64 tile|depth key, uint32 index) pairs, 8-bit
-// digits, only over the significant key bits (31 depth bits -- depths are
-// positive floats -- plus ceil(log2(tiles)) tile bits).
+// Stable LSD radix sort passes (8-bit digits) of (uint32 key, uint32 value)
+// pairs, used twice per frame by the binning stage: on the depth keys of the
+// drawn Gaussians and on the tile keys of the emitted (tile, Gaussian) pairs.
+// The last tile pass writes the 64-bit (tile << 32 | float32 depth bits) keys.
 //
 // Each pass is reduce-then-scan, with no inter-workgroup waiting:
 //   upsweep  - per 4096-key tile, a 256-bin digit histogram;
@@ -9,7 +10,7 @@
 //              on the 8 digit bits, wave-private running counters), stages
 //              keys and values in LDS in digit order, and writes each digit
 //              run contiguously to its global position.
-// The pair count lives in device memory (written by the binning stage); the
+// The item count lives in device memory (written by the previous stage); the
 // grids are sized from the capacity and tiles past the count exit at once.
 #include "rara_internal.h"
 
@@ -38,13 +39,13 @@ __device__ inline uint64_t match_digit(uint32_t digit, bool valid)
     return peers;
 }
 
-__global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint64_t* __restrict__ keys,
-                                                                     const int64_t* __restrict__ num_pairs,
+__global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint32_t* __restrict__ keys,
+                                                                     const int64_t* __restrict__ num_items,
                                                                      const int32_t* __restrict__ overflow, int shift,
                                                                      uint32_t* __restrict__ hist, int64_t stride)
 {
-    if (*overflow) return;
-    const int64_t P = *num_pairs;
+    if (overflow && *overflow) return;
+    const int64_t P = *num_items;
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     if (base >= P) return;
     __shared__ uint32_t counts[kWaves][kRadix];
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint6
     for (int r = 0; r < kWaveKeys / 64; ++r) {
         const int64_t idx = wbase + r * 64 + lane;
         const bool valid = idx < P;
-        const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & (kRadix - 1) : 0u;
+        const uint32_t d = valid ? (keys[idx] >> shift) & (kRadix - 1) : 0u;
         const uint64_t peers = match_digit(d, valid);
         if (valid && lanes_below(peers) == 0) counts[wave][d] += (uint32_t)__popcll(peers);
     }
@@ -70,12 +71,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint6
 // One workgroup per digit: exclusive scan of hist[d][0..tiles) in place and the
 // digit's total.
 __global__ __launch_bounds__(256) void radix_scan_kernel(uint32_t* __restrict__ hist, int64_t stride,
-                                                         const int64_t* __restrict__ num_pairs,
+                                                         const int64_t* __restrict__ num_items,
                                                          const int32_t* __restrict__ overflow,
                                                          uint32_t* __restrict__ digit_totals)
 {
-    if (*overflow) return;
-    const int64_t P = *num_pairs;
+    if (overflow && *overflow) return;
+    const int64_t P = *num_items;
     const int64_t tiles = (P + kSortTile - 1) / kSortTile;
     uint32_t* row = hist + (int64_t)blockIdx.x * stride;
     __shared__ uint32_t part[256];
@@ -101,17 +102,21 @@ __global__ __launch_bounds__(256) void radix_scan_kernel(uint32_t* __restrict__ 
     if (t == 255) digit_totals[blockIdx.x] = part[255];
 }
 
+// kFinal: keys_out is ignored and the 64-bit (key << 32 | depth bits of the
+// value's Gaussian) key is written to final_keys instead.
+template <bool kFinal>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
-    const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint64_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, const int64_t* __restrict__ num_pairs, const int32_t* __restrict__ overflow,
-    int shift, const uint32_t* __restrict__ hist, int64_t stride, const uint32_t* __restrict__ digit_totals)
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out, const int64_t* __restrict__ num_items, const int32_t* __restrict__ overflow,
+    int shift, const uint32_t* __restrict__ hist, int64_t stride, const uint32_t* __restrict__ digit_totals,
+    uint64_t* __restrict__ final_keys, const float* __restrict__ depth)
 {
-    if (*overflow) return;
-    const int64_t P = *num_pairs;
+    if (overflow && *overflow) return;
+    const int64_t P = *num_items;
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     if (base >= P) return;
 
-    __shared__ uint64_t s_keys[kSortTile];
+    __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
     __shared__ uint32_t counts[kWaves][kRadix];   // running per-wave digit counts, then per-wave starts
     __shared__ uint32_t local_start[kRadix];      // start of each digit run inside the tile
@@ -125,21 +130,21 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 
     // 1. stable rank of every key within (wave, digit)
     const int64_t wbase = base + (int64_t)wave * kWaveKeys;
-    uint64_t key[kSortItems];
+    uint32_t key[kSortItems];
     uint32_t val[kSortItems];
     uint32_t packed[kSortItems];   // digit | rank-within-wave-digit << 8 ; 0xffffffff = invalid
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t idx = wbase + r * 64 + lane;
         const bool valid = idx < P;
-        key[r] = valid ? keys_in[idx] : 0ull;
+        key[r] = valid ? keys_in[idx] : 0u;
         val[r] = valid ? vals_in[idx] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t idx = wbase + r * 64 + lane;
         const bool valid = idx < P;
-        const uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
+        const uint32_t d = (key[r] >> shift) & (kRadix - 1);
         const uint64_t peers = match_digit(d, valid);
         uint32_t rank = 0;
         if (valid) {
@@ -202,36 +207,44 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const int64_t cnt64 = P - base < kSortTile ? P - base : kSortTile;
     const int cnt = (int)cnt64;
     for (int k = tid; k < cnt; k += kSortThreads) {
-        const uint64_t kk = s_keys[k];
-        const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
+        const uint32_t kk = s_keys[k];
+        const uint32_t d = (kk >> shift) & (kRadix - 1);
         const uint32_t g = global_start[d] + ((uint32_t)k - local_start[d]);
-        keys_out[g] = kk;
-        vals_out[g] = s_vals[k];
+        const uint32_t v = s_vals[k];
+        if (kFinal)
+            final_keys[g] = ((uint64_t)kk << 32) | (uint64_t)__float_as_uint(depth[v]);
+        else
+            keys_out[g] = kk;
+        vals_out[g] = v;
     }
 }
 
 }  // namespace
 
-hipError_t launch_sort(const BinWorkspace& ws, int64_t cap, const rara_binned& out, int passes, hipStream_t s)
+hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int passes, const int64_t* count,
+                       const int32_t* overflow, int64_t blocks, uint32_t* hist, uint32_t* digit_totals,
+                       uint64_t* final_keys, uint32_t* final_vals, const float* depth, hipStream_t s)
 {
-    const int64_t blocks = ws.sort_blocks;
-    const int64_t stride = ws.sort_blocks;
-    // pass p reads src, writes dst; the last pass lands in out
+    // pass p reads (ka, va) when p is even and (kb, vb) when odd; with final_keys
+    // the last pass writes (final_keys, final_vals) instead of the other buffer
     for (int p = 0; p < passes; ++p) {
-        const bool to_out = ((passes - 1 - p) % 2) == 0;
-        const uint64_t* kin = to_out ? ws.keys_alt : out.keys;
-        const uint32_t* vin = to_out ? ws.vals_alt : out.vals;
-        uint64_t* kout = to_out ? out.keys : ws.keys_alt;
-        uint32_t* vout = to_out ? out.vals : ws.vals_alt;
+        const bool even = (p & 1) == 0;
+        const uint32_t* kin = even ? ka : kb;
+        const uint32_t* vin = even ? va : vb;
+        uint32_t* kout = even ? kb : ka;
+        uint32_t* vout = even ? vb : va;
         const int shift = p * kRadixBits;
-        hipLaunchKernelGGL(radix_upsweep_kernel, dim3((unsigned)blocks), dim3(kSortThreads), 0, s, kin, out.num_pairs,
-                           out.overflow, shift, ws.hist, stride);
-        hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadix), dim3(256), 0, s, ws.hist, stride, out.num_pairs,
-                           out.overflow, ws.digit_totals);
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)blocks), dim3(kSortThreads), 0, s, kin, vin, kout, vout,
-                           out.num_pairs, out.overflow, shift, ws.hist, stride, ws.digit_totals);
+        hipLaunchKernelGGL(radix_upsweep_kernel, dim3((unsigned)blocks), dim3(kSortThreads), 0, s, kin, count, overflow,
+                           shift, hist, blocks);
+        hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadix), dim3(256), 0, s, hist, blocks, count, overflow,
+                           digit_totals);
+        if (final_keys && p == passes - 1)
+            hipLaunchKernelGGL(radix_scatter_kernel<true>, dim3((unsigned)blocks), dim3(kSortThreads), 0, s, kin, vin,
+                               kout, final_vals, count, overflow, shift, hist, blocks, digit_totals, final_keys, depth);
+        else
+            hipLaunchKernelGGL(radix_scatter_kernel<false>, dim3((unsigned)blocks), dim3(kSortThreads), 0, s, kin, vin,
+                               kout, vout, count, overflow, shift, hist, blocks, digit_totals, nullptr, nullptr);
     }
-    (void)cap;
     return hipGetLastError();
 }
 

@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=240)
+    ap.add_argument("--serve-load", type=float, default=0.5, help="arrival rate as a fraction of saturation")
     ap.add_argument("--profile-steps", type=int, default=0, help="only run this many frames (for profilers)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="with --profile-steps: also run one plain 256 MiB device copy (counter calibration)")
@@ -139,6 +142,85 @@ def cpu_baseline(sc, cam, plane, budget_s):
                       f"({t_prep:.2f} s) + composite of {len(picked)} of {rows} tile rows "
                       f"({t_comp:.2f} s), composite scaled to the full frame",
             "geval_per_s": evals / t_comp / 1e9 if t_comp > 0 else None}
+
+
+def serve_bench(args):
+    """Serving mix over multi-layer scenes: 3 resident scenes (5 shells of
+    200k/300k/400k Gaussians, SH 0/2/3), requests with a random scene, a
+    resolution from {512^2, 1024^2, 1920x1080, 2048^2}, a camera on a sphere of
+    radius 5 and a random plane; Poisson arrivals at a fraction of the
+    measured saturation rate; the same stream with clipping off for plain."""
+    import torch
+    from paper_2506_20202_amd import scenes
+    from paper_2506_20202_amd.serve import Engine
+    rng = np.random.default_rng(3)
+    defs = [("A", scenes.multilayer_scene(31, per_shell=200_000, sh_degree=0)),
+            ("B", scenes.multilayer_scene(32, per_shell=300_000, sh_degree=2)),
+            ("C", scenes.multilayer_scene(33, per_shell=400_000, sh_degree=3))]
+    sizes = [(512, 512), (1024, 1024), (1920, 1080), (2048, 2048)]
+    resident = 0
+    eng = Engine(hbm_budget=0, max_slots=16)
+    for name, sc in defs:
+        eng.add_scene(name, sc)
+    resident = eng.ex.resident_bytes()
+    budget = resident + (8 << 30)
+    eng.sched.budget = budget
+
+    def make(nreq):
+        out = []
+        for _ in range(nreq):
+            name, sc = defs[int(rng.integers(3))]
+            W, H = sizes[int(rng.integers(4))]
+            out.append((name, scenes.random_camera_on_sphere(rng, 5.0, W, H), scenes.random_plane_through(rng, sc)))
+        return out
+
+    # warm-up: every shape class once (slots and graphs built)
+    for name, _ in defs:
+        for W, H in sizes:
+            eng.submit(name, scenes.random_camera_on_sphere(rng, 5.0, W, H), scenes.random_plane_through(rng, defs[0][1]))
+    eng.run_until_idle()
+    # saturation: a burst of requests all queued at once
+    burst = make(96)
+    t0 = time.perf_counter()
+    for r in burst:
+        eng.submit(*r)
+    eng.run_until_idle()
+    sat = len(burst) / (time.perf_counter() - t0)
+    rate = args.serve_load * sat
+    stream = make(args.serve_requests)
+    gaps = rng.exponential(1.0 / rate, len(stream))
+
+    def run(reqs, clipped):
+        eng.sched.latencies.clear()
+        eng.sched.completed.clear()
+        eng.start()
+        t_start = time.perf_counter()
+        t = t_start
+        futs = []
+        for (name, cam, pl), gap in zip(reqs, gaps):
+            t += gap
+            while time.perf_counter() < t:
+                pass
+            p = pl if clipped else type(pl)(pl.n, pl.d, False)
+            futs.append(eng.submit(name, cam, p, arrival=t))
+        for f in futs:
+            f.result(timeout=300)
+        wall = time.perf_counter() - t_start
+        eng.stop()
+        st = eng.stats()
+        mpix = sum(c.width * c.height for _, c, _ in reqs) / 1e6
+        return {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+                "throughput_req_s": len(reqs) / wall, "throughput_mpix_s": mpix / wall,
+                "max_inflight": st["max_inflight"], "retries": st["retries"], "evictions": st["evictions"]}
+
+    clipped = run(stream, True)
+    plain = run(stream, False)
+    eng.close()
+    return {"workload": "3 resident multi-layer scenes (1.0M SH0, 1.5M SH2, 2.0M SH3), resolutions "
+                        "512^2/1024^2/1920x1080/2048^2, camera on a radius-5 sphere, random plane",
+            "requests": len(stream), "saturation_req_s": sat, "offered_load_req_s": rate,
+            "load_fraction": args.serve_load, "hbm_budget_gib": budget / 2 ** 30, "graphs": True,
+            "clipped": clipped, "plain": plain}
 
 
 def main():
@@ -261,6 +343,12 @@ def main():
         cpu = cpu_baseline(sc, cam, pl, args.cpu_seconds)
         print(f"[bench] oracle: {cpu['value']:.4f} frames/s on {cpu['cores']} threads", file=sys.stderr, flush=True)
 
+    serving = None
+    if not args.no_serve:
+        serving = serve_bench(args)
+        print(f"[bench] serving: clipped p50 {serving['clipped']['p50_ms']:.2f} ms p99 {serving['clipped']['p99_ms']:.2f} ms"
+              f" at {serving['offered_load_req_s']:.0f} req/s", file=sys.stderr, flush=True)
+
     out = {
         "metric": METRIC, "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
         "ms_per_step": ms_total / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -269,7 +357,7 @@ def main():
         "plain_fps": plain, "clipped_over_plain_frame_time": (plain / fps) if plain else None,
         "stage_ms": stage_ms, "pairs_per_frame": P_tot / nst, "live_gaussians_per_frame": n_live / nst,
         "geval_per_s": E_tot / nst / render_s / 1e9,
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "serving": serving,
     }
     print(json.dumps(out))
 

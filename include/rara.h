@@ -14,8 +14,9 @@
  *
  * Conventions shared by every entry point
  *   - All array arguments are DEVICE pointers owned by the caller; the library
- *     allocates nothing and keeps no state between calls.  Struct arguments
- *     are read on the host during the call only.
+ *     allocates no device memory and keeps no state between calls (frame
+ *     graphs, below, are explicit host-side handles).  Struct arguments are
+ *     read on the host during the call only.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only
  *     enqueues work; results are ready when the stream reaches them.
  *   - Argument errors are reported synchronously (RARA_ERR_INVALID) before
@@ -206,6 +207,27 @@ rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam
                                  const float* bg, const rara_projected* proj, const rara_binned* bins,
                                  const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
                                  const rara_grads* grads, void* workspace, size_t ws_bytes, void* stream);
+
+/* Frame graphs (for serving many requests of one shape): the kernels of one
+ * frame (rara_preprocess + rara_bin_sort + rara_render) captured once into a
+ * HIP graph for fixed Gaussians, image size, buffers and pair capacity.  Each
+ * rara_frame_graph_launch rewrites the camera- and plane-dependent kernel
+ * arguments in the instantiated graph and enqueues it: one launch per frame.
+ * The results are those of the three calls with the same arguments.
+ * `shape` fixes the image size (a launch with another size is rejected); its
+ * pose only serves the capture.  n_walked may be NULL.  The handle owns a HIP
+ * graph and host memory (no device memory); one handle must not be launched
+ * on two streams at once.  Errors: RARA_ERR_INVALID for bad or mismatched
+ * arguments (n must be > 0), RARA_ERR_HIP if capture, instantiation, update
+ * or launch fails. */
+typedef struct rara_frame_graph rara_frame_graph;
+rara_status rara_frame_graph_create(const rara_gaussians* g, const rara_camera* shape, const rara_projected* proj,
+                                    const rara_binned* bins, int64_t pair_capacity, void* workspace, size_t ws_bytes,
+                                    float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked,
+                                    rara_frame_graph** out);
+rara_status rara_frame_graph_launch(rara_frame_graph* fg, const rara_camera* cam, const rara_plane* plane,
+                                    const float* bg, void* stream);
+void rara_frame_graph_destroy(rara_frame_graph* fg);
 
 /* Static description of a status code (never NULL). */
 const char* rara_status_string(rara_status s);

@@ -46,7 +46,8 @@ class Grads(ctypes.Structure):
 
 
 EXPORTS = ["rara_preprocess", "rara_bin_sort", "rara_render", "rara_render_backward", "rara_workspace_bytes",
-           "rara_status_string", "rara_version"]
+           "rara_status_string", "rara_version", "rara_frame_graph_create", "rara_frame_graph_launch",
+           "rara_frame_graph_destroy"]
 
 _lib = None
 
@@ -77,7 +78,13 @@ def lib():
         L.rara_status_string.argtypes = [ctypes.c_int]
         L.rara_status_string.restype = ctypes.c_char_p
         L.rara_version.restype = ctypes.c_char_p
-        for f in ("rara_preprocess", "rara_bin_sort", "rara_render", "rara_render_backward"):
+        L.rara_frame_graph_create.argtypes = [PG, PC, PJ, PB, ctypes.c_int64, _P, ctypes.c_size_t, _P, _P, _P, _P,
+                                              ctypes.POINTER(_P)]
+        L.rara_frame_graph_launch.argtypes = [_P, PC, PP, ctypes.POINTER(ctypes.c_float), _P]
+        L.rara_frame_graph_destroy.argtypes = [_P]
+        L.rara_frame_graph_destroy.restype = None
+        for f in ("rara_preprocess", "rara_bin_sort", "rara_render", "rara_render_backward", "rara_frame_graph_create",
+                  "rara_frame_graph_launch"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -144,3 +151,24 @@ def render_backward(g: Gaussians, cam: Camera, plane: Plane, bg, proj: Projected
            lib().rara_render_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(plane), bgc, ctypes.byref(proj),
                                       ctypes.byref(bins), _P(final_T), _P(n_contrib), _P(dL_dimage),
                                       ctypes.byref(grads), _P(workspace), ws_bytes, _P(stream)))
+
+
+def frame_graph_create(g: Gaussians, shape: Camera, proj: Projected, bins: Binned, pair_capacity: int, workspace: int,
+                       ws_bytes: int, image: int, final_T: int, n_contrib: int, n_walked: int) -> int:
+    h = _P()
+    _check("rara_frame_graph_create",
+           lib().rara_frame_graph_create(ctypes.byref(g), ctypes.byref(shape), ctypes.byref(proj), ctypes.byref(bins),
+                                         pair_capacity, _P(workspace), ws_bytes, _P(image), _P(final_T),
+                                         _P(n_contrib), _P(n_walked or None), ctypes.byref(h)))
+    return h.value
+
+
+def frame_graph_launch(handle: int, cam: Camera, plane: Plane, bg, stream: int):
+    bgc = (ctypes.c_float * 3)(*[float(v) for v in bg])
+    _check("rara_frame_graph_launch", lib().rara_frame_graph_launch(_P(handle), ctypes.byref(cam), ctypes.byref(plane),
+                                                                    bgc, _P(stream)))
+
+
+def frame_graph_destroy(handle: int):
+    if handle:
+        lib().rara_frame_graph_destroy(_P(handle))

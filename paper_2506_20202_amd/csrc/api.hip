@@ -70,6 +70,29 @@ ProjPtrs proj_ptrs(const rara_projected* p)
 
 }  // namespace
 
+bool rara::make_cam_params(const rara_camera* c, CamParams* p) { return make_cam(c, p); }
+bool rara::make_plane_params(const rara_plane* pl, PlaneParams* p) { return make_plane(pl, p); }
+
+RenderParams rara::make_render_params(const CamParams& cp, const PlaneParams& pp, const float* bg)
+{
+    RenderParams rp;
+    rp.W = cp.W;
+    rp.H = cp.H;
+    rp.tiles_x = cp.tiles_x;
+    rp.tiles_y = cp.tiles_y;
+    rp.num_tiles = cp.tiles_x * cp.tiles_y;
+    rp.plane_enabled = pp.enabled;
+    // per-pixel rate of the plane value along the pixel ray: (R_c n)_{x,y} / f_{x,y}
+    const double rn0 = cp.R[0] * pp.n[0] + cp.R[1] * pp.n[1] + cp.R[2] * pp.n[2];
+    const double rn1 = cp.R[3] * pp.n[0] + cp.R[4] * pp.n[1] + cp.R[5] * pp.n[2];
+    rp.ax = (float)(rn0 / cp.fx);
+    rp.ay = (float)(rn1 / cp.fy);
+    rp.bg[0] = bg[0];
+    rp.bg[1] = bg[1];
+    rp.bg[2] = bg[2];
+    return rp;
+}
+
 size_t rara::bin_workspace_layout(int64_t n, int64_t cap, BinWorkspace* ws, char* base)
 {
     auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -185,21 +208,7 @@ rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned
     CamParams cp;
     PlaneParams pp;
     if (!make_cam(cam, &cp) || !make_plane(plane, &pp)) return RARA_ERR_INVALID;
-    RenderParams rp;
-    rp.W = cp.W;
-    rp.H = cp.H;
-    rp.tiles_x = cp.tiles_x;
-    rp.tiles_y = cp.tiles_y;
-    rp.num_tiles = cp.tiles_x * cp.tiles_y;
-    rp.plane_enabled = pp.enabled;
-    // per-pixel rate of the plane value: (R_c n)_{x,y} / f_{x,y}
-    const double rn0 = cp.R[0] * pp.n[0] + cp.R[1] * pp.n[1] + cp.R[2] * pp.n[2];
-    const double rn1 = cp.R[3] * pp.n[0] + cp.R[4] * pp.n[1] + cp.R[5] * pp.n[2];
-    rp.ax = (float)(rn0 / cp.fx);
-    rp.ay = (float)(rn1 / cp.fy);
-    rp.bg[0] = bg[0];
-    rp.bg[1] = bg[1];
-    rp.bg[2] = bg[2];
+    const RenderParams rp = make_render_params(cp, pp, bg);
     const hipError_t e = launch_blend(static_cast<const Splat*>(proj->splat), static_cast<const RayRec*>(proj->ray),
                                       *bins, rp, image, final_T, n_contrib, n_walked, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
@@ -221,20 +230,7 @@ rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam
     PlaneParams pp;
     if (!make_cam(cam, &cp) || !make_plane(plane, &pp)) return RARA_ERR_INVALID;
     if (ws_bytes < backward_workspace_bytes(g->n, cp.W, cp.H)) return RARA_ERR_INVALID;
-    RenderParams rp;
-    rp.W = cp.W;
-    rp.H = cp.H;
-    rp.tiles_x = cp.tiles_x;
-    rp.tiles_y = cp.tiles_y;
-    rp.num_tiles = cp.tiles_x * cp.tiles_y;
-    rp.plane_enabled = pp.enabled;
-    const double rn0 = cp.R[0] * pp.n[0] + cp.R[1] * pp.n[1] + cp.R[2] * pp.n[2];
-    const double rn1 = cp.R[3] * pp.n[0] + cp.R[4] * pp.n[1] + cp.R[5] * pp.n[2];
-    rp.ax = (float)(rn0 / cp.fx);
-    rp.ay = (float)(rn1 / cp.fy);
-    rp.bg[0] = bg[0];
-    rp.bg[1] = bg[1];
-    rp.bg[2] = bg[2];
+    const RenderParams rp = make_render_params(cp, pp, bg);
     const double len = pp.enabled ? std::sqrt((double)plane->n[0] * plane->n[0] + (double)plane->n[1] * plane->n[1] +
                                               (double)plane->n[2] * plane->n[2])
                                   : 1.0;

@@ -209,6 +209,11 @@ __global__ __launch_bounds__(64) void blend_kernel(const Splat* __restrict__ spl
 
 }  // namespace
 
+const void* blend_kernel_handle(bool walked)
+{
+    return walked ? reinterpret_cast<const void*>(&blend_kernel<true>) : reinterpret_cast<const void*>(&blend_kernel<false>);
+}
+
 hipError_t launch_blend(const Splat* splat, const RayRec* ray, const rara_binned& bins, const RenderParams& p,
                         float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked, hipStream_t s)
 {

@@ -161,6 +161,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(GaussPtrs g, CamParams 
 
 }  // namespace
 
+const void* preprocess_kernel_handle() { return reinterpret_cast<const void*>(&preprocess_kernel); }
+
 hipError_t launch_preprocess(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl, const ProjPtrs& out,
                              hipStream_t s)
 {

@@ -124,6 +124,12 @@ hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, i
                        uint64_t* final_keys, uint32_t* final_vals, const float* depth, hipStream_t s);
 hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, hipStream_t s);
 hipError_t launch_plan(const rara_binned& out, int num_tiles, hipStream_t s);
+const void* preprocess_kernel_handle();
+const void* blend_kernel_handle(bool walked);
+// host-side parameter blocks shared by the ABI entry points and frame graphs
+bool make_cam_params(const rara_camera* c, CamParams* p);
+bool make_plane_params(const rara_plane* pl, PlaneParams* p);
+RenderParams make_render_params(const CamParams& cp, const PlaneParams& pp, const float* bg);
 hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl, double plane_len,
                            const ProjPtrs& proj, const rara_binned& bins, const RenderParams& rp,
                            const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,

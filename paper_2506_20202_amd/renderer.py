@@ -172,3 +172,32 @@ def splat_fields(proj: ProjectedBuffers) -> dict:
     f = raw[:, 16:48].copy().view(np.float32).reshape(-1, 8)
     lab = raw[:, 44:48].copy().view(np.uint32).reshape(-1)
     return dict(mean2d=mean2d, conic=f[:, 0:3].copy(), opacity=f[:, 3].copy(), rgb=f[:, 4:7].copy(), label=lab)
+
+
+class FrameGraph:
+    """A captured frame (rara_frame_graph) bound to one DeviceScene and one
+    Frame; ``launch`` replays it for a new camera pose and plane."""
+
+    def __init__(self, scene: DeviceScene, frame: Frame, shape_cam):
+        self.scene, self.frame = scene, frame
+        o = frame.out
+        self.handle = B.frame_graph_create(scene.struct(), B.make_camera(shape_cam), frame.proj.struct(),
+                                           frame.bins.struct(), frame.capacity, _ptr(frame.bins.workspace),
+                                           frame.bins.ws_bytes, _ptr(o.image), _ptr(o.final_T), _ptr(o.n_contrib),
+                                           _ptr(o.n_walked))
+
+    def launch(self, cam, plane, bg=(0.0, 0.0, 0.0), stream=None):
+        if stream is None:
+            stream = torch.cuda.current_stream(self.scene.mean.device)
+        B.frame_graph_launch(self.handle, B.make_camera(cam), B.make_plane(plane), bg, int(stream.cuda_stream))
+
+    def close(self):
+        if self.handle:
+            B.frame_graph_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,353 @@
+"""Serving: a continuous-batching request loop over resident scenes.
+
+Requests (scene, camera, clip plane, background) arrive at any time.  The
+scheduler keeps a pool of execution slots.  A slot owns the device buffers of
+one shape class (scene, image size, pair capacity), a HIP stream and a
+captured frame graph, so a request is one graph launch.  Admission is
+first-come first-served:
+
+  * the request at the head of the queue takes an idle slot of its shape;
+  * otherwise a new slot is built when the HBM budget (resident scenes plus
+    every slot's buffers) allows it, evicting idle slots of other shapes,
+    least recently used first;
+  * otherwise the queue waits until a running request completes.
+
+Requests admitted while others run go onto their own slot streams, so their
+kernels overlap on the device.  A frame that overflows its slot's pair
+capacity is re-run on a slot built with a larger capacity.  Latency is taken
+from the arrival time to the moment the loop sees the completion event.
+
+The policy (``Scheduler``) is independent of the GPU: ``GpuExecutor`` drives
+the C ABI, and the tests drive the same policy with a fake executor and a
+virtual clock.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import itertools
+import threading
+import time
+from concurrent.futures import Future
+from typing import Any, Callable, Deque, Dict, List, Optional, Tuple
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    scene: str
+    cam: Any
+    plane: Any
+    bg: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    arrival: float = 0.0
+    rid: int = -1
+    future: Optional[Future] = None
+    attempts: int = 0
+    start: float = 0.0
+
+    @property
+    def shape(self):
+        return (self.scene, int(self.cam.width), int(self.cam.height))
+
+
+@dataclasses.dataclass
+class Slot:
+    shape: Tuple[str, int, int]
+    capacity: int
+    nbytes: int
+    handle: Any
+    request: Optional[Request] = None
+    last_used: float = 0.0
+    sid: int = 0
+
+
+@dataclasses.dataclass
+class Completion:
+    ok: bool
+    overflow: bool = False
+    num_pairs: int = 0
+    result: Any = None
+    error: Optional[str] = None
+
+
+class Scheduler:
+    """Admission, slots, HBM budget, retries and latency bookkeeping."""
+
+    def __init__(self, executor, hbm_budget: int, max_slots: int = 8, clock: Callable[[], float] = time.perf_counter,
+                 capacity_of: Optional[Callable[[Tuple[str, int, int]], int]] = None, grow: float = 1.5):
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.max_slots = int(max_slots)
+        self.clock = clock
+        self.capacity_of = capacity_of or (lambda shape: 1 << 20)
+        self.grow = grow
+        self.queue: Deque[Request] = collections.deque()
+        self.slots: List[Slot] = []
+        self.capacity_hint: Dict[Tuple[str, int, int], int] = {}
+        self.latencies: List[float] = []
+        self.completed: List[Request] = []
+        self.failed: List[Request] = []
+        self.retries = 0
+        self.evictions = 0
+        self.max_inflight = 0
+        self._sid = itertools.count()
+        self._rid = itertools.count()
+
+    # ---- memory ----
+    def used_bytes(self) -> int:
+        return self.ex.resident_bytes() + sum(s.nbytes for s in self.slots)
+
+    def submit(self, req: Request) -> Future:
+        if req.future is None:
+            req.future = Future()
+        if req.rid < 0:
+            req.rid = next(self._rid)
+        if not req.arrival:
+            req.arrival = self.clock()
+        need = self.ex.slot_bytes(req.shape, self._capacity(req.shape))
+        if self.ex.resident_bytes() + need > self.budget:
+            req.future.set_exception(MemoryError(f"request {req.rid}: a {req.shape} slot needs {need} bytes, "
+                                                 f"more than the HBM budget leaves"))
+            self.failed.append(req)
+            return req.future
+        self.queue.append(req)
+        return req.future
+
+    def _capacity(self, shape) -> int:
+        return self.capacity_hint.get(shape) or int(self.capacity_of(shape))
+
+    # ---- one scheduling step ----
+    def step(self) -> bool:
+        """Retire finished requests, then admit from the head of the queue.
+        Returns True when anything changed."""
+        changed = False
+        for s in self.slots:
+            if s.request is None:
+                continue
+            c = self.ex.poll(s.handle)
+            if c is None:
+                continue
+            changed = True
+            req = s.request
+            s.request = None
+            s.last_used = self.clock()
+            if c.ok and not c.overflow:
+                lat = self.clock() - req.arrival
+                self.latencies.append(lat)
+                self.completed.append(req)
+                req.future.set_result(c.result)
+            elif c.overflow:
+                # the pair capacity of this shape was too small: re-queue at the
+                # head with a larger capacity; the undersized slot is released
+                self.retries += 1
+                req.attempts += 1
+                self.capacity_hint[req.shape] = max(int(c.num_pairs * self.grow) + 1024,
+                                                    int(s.capacity * self.grow))
+                self._drop(s)
+                if req.attempts > 4:
+                    self.failed.append(req)
+                    req.future.set_exception(RuntimeError(f"request {req.rid}: pair capacity kept overflowing"))
+                else:
+                    self.queue.appendleft(req)
+            else:
+                self.failed.append(req)
+                req.future.set_exception(RuntimeError(c.error or "render failed"))
+        while self.queue:
+            req = self.queue[0]
+            slot = self._slot_for(req)
+            if slot is None:
+                break
+            self.queue.popleft()
+            slot.request = req
+            req.start = self.clock()
+            slot.last_used = req.start
+            self.ex.launch(slot.handle, req)
+            changed = True
+        inflight = sum(1 for s in self.slots if s.request is not None)
+        self.max_inflight = max(self.max_inflight, inflight)
+        return changed
+
+    def _drop(self, s: Slot):
+        self.ex.destroy_slot(s.handle)
+        self.slots.remove(s)
+
+    def _slot_for(self, req: Request) -> Optional[Slot]:
+        cap = self._capacity(req.shape)
+        for s in self.slots:
+            if s.request is None and s.shape == req.shape and s.capacity >= cap:
+                return s
+        need = self.ex.slot_bytes(req.shape, cap)
+        # evict idle slots (least recently used first) until the new one fits
+        idle = sorted((s for s in self.slots if s.request is None), key=lambda s: s.last_used)
+        while (self.used_bytes() + need > self.budget or len(self.slots) >= self.max_slots) and idle:
+            self._drop(idle.pop(0))
+            self.evictions += 1
+        if self.used_bytes() + need > self.budget or len(self.slots) >= self.max_slots:
+            return None
+        handle = self.ex.create_slot(req.shape, cap)
+        s = Slot(req.shape, cap, need, handle, sid=next(self._sid))
+        self.slots.append(s)
+        return s
+
+    def idle(self) -> bool:
+        return not self.queue and all(s.request is None for s in self.slots)
+
+    def close(self):
+        for s in list(self.slots):
+            self._drop(s)
+
+    # ---- statistics ----
+    def stats(self) -> dict:
+        lat = np.asarray(self.latencies) * 1e3
+        out = dict(completed=len(self.completed), failed=len(self.failed), retries=self.retries,
+                   evictions=self.evictions, max_inflight=self.max_inflight, slots=len(self.slots))
+        if lat.size:
+            out.update(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                       mean_ms=float(lat.mean()), max_ms=float(lat.max()))
+        return out
+
+
+class GpuExecutor:
+    """Slots on the GPU: per slot a Frame (device buffers), a captured
+    FrameGraph, its own stream, a completion event and pinned words for the
+    overflow flag and the pair count."""
+
+    def __init__(self, device=None, use_graphs: bool = True):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device or "cuda:0")
+        self.scenes: Dict[str, Any] = {}
+        self.use_graphs = use_graphs
+
+    def add_scene(self, name: str, scene):
+        from . import renderer as R
+        self.scenes[name] = R.DeviceScene.from_scene(scene, self.device)
+
+    def resident_bytes(self) -> int:
+        return sum(s.nbytes() for s in self.scenes.values())
+
+    def slot_bytes(self, shape, capacity) -> int:
+        from . import binding as B
+        name, W, H = shape
+        n = self.scenes[name].n
+        tiles = ((W + 15) // 16) * ((H + 15) // 16)
+        proj = n * (1 + B.SPLAT_BYTES + B.RAY_BYTES + 4 + 8 + 4)
+        bins = capacity * 12 + tiles * 24 + B.workspace_bytes(B.RARA_WS_BIN_SORT, n, capacity, W, H)
+        img = W * H * (4 * 3 + 4 + 4) + W * H * 12   # frame outputs + one result copy
+        return proj + bins + img
+
+    def create_slot(self, shape, capacity):
+        from . import renderer as R
+        name, W, H = shape
+        scene = self.scenes[name]
+        fr = R.Frame(scene.n, W, H, capacity, self.device, walked=False)
+        st = self.torch.cuda.Stream(self.device)
+        h = dict(frame=fr, stream=st, scene=scene, graph=None, event=None, status=None, result=None, req=None)
+        h["status"] = self.torch.zeros(2, dtype=self.torch.int64, pin_memory=True)
+        if self.use_graphs:
+            from .scenes import pinhole
+            shape_cam = pinhole((0.0, 0.0, -5.0), (0.0, 0.0, 0.0), W, H, 50.0)
+            h["graph"] = R.FrameGraph(scene, fr, shape_cam)
+        return h
+
+    def destroy_slot(self, h):
+        if h.get("graph") is not None:
+            h["graph"].close()
+        h.clear()
+
+    def launch(self, h, req: Request):
+        from . import renderer as R
+        torch = self.torch
+        st = h["stream"]
+        fr = h["frame"]
+        with torch.cuda.stream(st):
+            if h["graph"] is not None:
+                h["graph"].launch(req.cam, req.plane, req.bg, st)
+            else:
+                R.enqueue_frame(h["scene"], fr, req.cam, req.plane, req.bg, stream=st)
+            h["result"] = fr.out.image.clone()
+            words = torch.stack([fr.bins.overflow.to(torch.int64)[0], fr.bins.num_pairs[0]])
+            h["status"].copy_(words, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(st)
+            h["result"].record_stream(st)
+        h["event"] = ev
+        h["req"] = req
+
+    def poll(self, h) -> Optional[Completion]:
+        ev = h.get("event")
+        if ev is None or not ev.query():
+            return None
+        h["event"] = None
+        over, pairs = (int(v) for v in h["status"].tolist())
+        res = h["result"]
+        h["result"] = None
+        return Completion(ok=True, overflow=bool(over), num_pairs=pairs, result=res)
+
+
+class Engine:
+    """Scheduler + GPU executor + a background loop thread."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 8, device=None, use_graphs: bool = True,
+                 capacity_of: Optional[Callable] = None):
+        self.ex = GpuExecutor(device, use_graphs)
+        self.sched = Scheduler(self.ex, hbm_budget, max_slots, capacity_of=capacity_of or self._capacity_guess)
+        self._lock = threading.Lock()
+        self._stop = threading.Event()
+        self._thread: Optional[threading.Thread] = None
+
+    def _capacity_guess(self, shape) -> int:
+        name, W, H = shape
+        n = self.ex.scenes[name].n
+        # pairs ~ (drawn Gaussians) x (tiles per footprint): start at 4 per
+        # Gaussian plus one per pixel tile row, grow on overflow
+        return int(4 * n + 64 * ((W + 15) // 16) * ((H + 15) // 16)) + 4096
+
+    def add_scene(self, name, scene):
+        self.ex.add_scene(name, scene)
+
+    def submit(self, scene: str, cam, plane, bg=(0.0, 0.0, 0.0), arrival: Optional[float] = None) -> Future:
+        req = Request(scene, cam, plane, tuple(bg), arrival=arrival or time.perf_counter())
+        with self._lock:
+            return self.sched.submit(req)
+
+    def start(self):
+        self._stop.clear()
+        self._thread = threading.Thread(target=self._loop, name="rara-serve", daemon=True)
+        self._thread.start()
+
+    def _loop(self):
+        dev = self.ex.device
+        self.ex.torch.cuda.set_device(dev)
+        while not self._stop.is_set():
+            with self._lock:
+                changed = self.sched.step()
+            if not changed:
+                time.sleep(20e-6)
+
+    def run_until_idle(self, timeout: float = 600.0):
+        t0 = time.perf_counter()
+        while True:
+            with self._lock:
+                self.sched.step()
+                if self.sched.idle():
+                    return
+            if time.perf_counter() - t0 > timeout:
+                raise TimeoutError("serving loop did not drain")
+            time.sleep(20e-6)
+
+    def stop(self):
+        self._stop.set()
+        if self._thread is not None:
+            self._thread.join(timeout=60)
+            self._thread = None
+
+    def close(self):
+        self.stop()
+        with self._lock:
+            self.sched.close()
+
+    def stats(self):
+        with self._lock:
+            return self.sched.stats()

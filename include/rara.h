@@ -210,16 +210,22 @@ rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam
 
 /* Frame graphs (for serving many requests of one shape): the kernels of one
  * frame (rara_preprocess + rara_bin_sort + rara_render) captured once into a
- * HIP graph for fixed Gaussians, image size, buffers and pair capacity.  Each
- * rara_frame_graph_launch rewrites the camera- and plane-dependent kernel
- * arguments in the instantiated graph and enqueues it: one launch per frame.
- * The results are those of the three calls with the same arguments.
- * `shape` fixes the image size (a launch with another size is rejected); its
- * pose only serves the capture.  n_walked may be NULL.  The handle owns a HIP
- * graph and host memory (no device memory); one handle must not be launched
- * on two streams at once.  Errors: RARA_ERR_INVALID for bad or mismatched
- * arguments (n must be > 0), RARA_ERR_HIP if capture, instantiation, update
- * or launch fails. */
+ * HIP graph for fixed Gaussians, image size, buffers and pair capacity.  The
+ * camera pose, plane and background of a request live in a small device
+ * block owned by the handle; rara_frame_graph_launch copies them there on
+ * `stream` (from pinned staging memory) and enqueues the graph after the copy
+ * on the same stream: one copy and one graph launch per frame.  The results
+ * are those of the three calls with the same arguments.  `shape` fixes the
+ * image size (a launch with another size is rejected); its pose only serves
+ * the capture.  n_walked may be NULL.  The handle owns a HIP graph, a
+ * FrameParams-sized device block, pinned staging memory and two events.
+ * Launches of one handle must go to one stream (each replay overwrites the
+ * same outputs); a launch waits on the host only until the previous launch's
+ * parameter copy has run.  rara_frame_graph_destroy waits for the last replay
+ * to finish before it frees anything.  Errors: RARA_ERR_INVALID for bad or
+ * mismatched arguments (n must be > 0), RARA_ERR_UNSUPPORTED for an SH degree
+ * above 3 or more than 65535 tile columns or rows, RARA_ERR_HIP if an
+ * allocation, the capture, the instantiation, the copy or the launch fails. */
 typedef struct rara_frame_graph rara_frame_graph;
 rara_status rara_frame_graph_create(const rara_gaussians* g, const rara_camera* shape, const rara_projected* proj,
                                     const rara_binned* bins, int64_t pair_capacity, void* workspace, size_t ws_bytes,

@@ -184,14 +184,12 @@ __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec
 
 // One wave per work unit (see unit_of_block for the schedule).
 template <bool kWalked>
-__global__ __launch_bounds__(64) void blend_kernel(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
-                                                   const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
-                                                   const uint32_t* __restrict__ work,
-                                                   const int32_t* __restrict__ overflow, RenderParams p,
-                                                   float* __restrict__ image, float* __restrict__ final_T,
-                                                   uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
+__device__ __forceinline__ void blend_block(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
+                                            const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
+                                            const uint32_t* __restrict__ work, const RenderParams& p,
+                                            float* __restrict__ image, float* __restrict__ final_T,
+                                            uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
 {
-    if (*overflow) return;
     uint32_t unit;
     if (!unit_of_block(blockIdx.x, work, p.num_tiles, unit)) return;
     const int tile = (int)(unit >> 3), mode = (int)(unit & 7u);
@@ -207,12 +205,36 @@ __global__ __launch_bounds__(64) void blend_kernel(const Splat* __restrict__ spl
                                n_walked);
 }
 
-}  // namespace
-
-const void* blend_kernel_handle(bool walked)
+template <bool kWalked>
+__global__ __launch_bounds__(64) void blend_kernel(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
+                                                   const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
+                                                   const uint32_t* __restrict__ work,
+                                                   const int32_t* __restrict__ overflow, RenderParams p,
+                                                   float* __restrict__ image, float* __restrict__ final_T,
+                                                   uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
 {
-    return walked ? reinterpret_cast<const void*>(&blend_kernel<true>) : reinterpret_cast<const void*>(&blend_kernel<false>);
+    if (*overflow) return;
+    blend_block<kWalked>(splats, rays, vals, ranges, work, p, image, final_T, n_contrib, n_walked);
 }
+
+// Frame-graph variant: render parameters read from device memory.
+template <bool kWalked>
+__global__ __launch_bounds__(64) void blend_fp_kernel(const Splat* __restrict__ splats,
+                                                      const RayRec* __restrict__ rays,
+                                                      const uint32_t* __restrict__ vals,
+                                                      const uint2* __restrict__ ranges,
+                                                      const uint32_t* __restrict__ work,
+                                                      const int32_t* __restrict__ overflow,
+                                                      const FrameParams* __restrict__ fp, float* __restrict__ image,
+                                                      float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
+                                                      uint32_t* __restrict__ n_walked)
+{
+    if (*overflow) return;
+    const RenderParams p = fp->render;
+    blend_block<kWalked>(splats, rays, vals, ranges, work, p, image, final_T, n_contrib, n_walked);
+}
+
+}  // namespace
 
 hipError_t launch_blend(const Splat* splat, const RayRec* ray, const rara_binned& bins, const RenderParams& p,
                         float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked, hipStream_t s)
@@ -226,6 +248,21 @@ hipError_t launch_blend(const Splat* splat, const RayRec* ray, const rara_binned
         hipLaunchKernelGGL(blend_kernel<false>, dim3(grid), dim3(64), 0, s, splat, ray, bins.vals,
                            reinterpret_cast<const uint2*>(bins.ranges), bins.work, bins.overflow, p, image, final_T,
                            n_contrib, n_walked);
+    return hipGetLastError();
+}
+
+hipError_t launch_blend_fp(const Splat* splat, const RayRec* ray, const rara_binned& bins, const FrameParams* fp,
+                           int num_tiles, float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked,
+                           hipStream_t s)
+{
+    const unsigned grid = (unsigned)work_grid(num_tiles);
+    const uint2* ranges = reinterpret_cast<const uint2*>(bins.ranges);
+    if (n_walked)
+        hipLaunchKernelGGL(blend_fp_kernel<true>, dim3(grid), dim3(64), 0, s, splat, ray, bins.vals, ranges, bins.work,
+                           bins.overflow, fp, image, final_T, n_contrib, n_walked);
+    else
+        hipLaunchKernelGGL(blend_fp_kernel<false>, dim3(grid), dim3(64), 0, s, splat, ray, bins.vals, ranges,
+                           bins.work, bins.overflow, fp, image, final_T, n_contrib, n_walked);
     return hipGetLastError();
 }
 

@@ -1,11 +1,16 @@
 // Frame graphs: every kernel of one frame (preprocess, binning, sort, schedule,
 // blend) captured once into a HIP graph for a fixed shape (the Gaussians, the
-// image size, the buffers and the pair capacity), then replayed per request
-// with only the camera- and plane-dependent kernel arguments rewritten in the
-// instantiated graph.  One graph launch replaces the ~25 launches of a frame.
+// image size, the buffers and the pair capacity), then replayed per request.
+//
+// The per-request values (camera pose, clip plane, background) live in a small
+// device-resident FrameParams block.  The captured preprocess and blend
+// kernels read that block through a pointer, so no kernel argument of the
+// instantiated graph ever changes.  A launch writes the block into pinned
+// staging memory, copies it to the device on the caller's stream and then
+// enqueues the graph on the same stream: the copy and the replay are ordered
+// by the stream alone.  One graph launch replaces the ~25 launches of a frame.
 #include <cstdlib>
 #include <cstring>
-#include <vector>
 
 #include "rara_internal.h"
 
@@ -14,21 +19,11 @@ using namespace rara;
 struct rara_frame_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t pre_node = nullptr, blend_node = nullptr;
-    hipKernelNodeParams pre{}, blend{};
-    // arguments that stay fixed for the shape
-    GaussPtrs g{};
-    ProjPtrs proj{};
-    const Splat* splat = nullptr;
-    const RayRec* ray = nullptr;
-    const uint32_t* vals = nullptr;
-    const uint2* ranges = nullptr;
-    const uint32_t* work = nullptr;
-    const int32_t* overflow = nullptr;
-    float* image = nullptr;
-    float* final_T = nullptr;
-    uint32_t* n_contrib = nullptr;
-    uint32_t* n_walked = nullptr;
+    FrameParams* dev_params = nullptr;    // device copy read by the graph's kernels
+    FrameParams* host_params = nullptr;   // pinned staging of the next copy
+    hipEvent_t staged = nullptr;          // the last staging copy has been consumed
+    hipEvent_t done = nullptr;            // the last replay has finished
+    bool launched = false;
     int W = 0, H = 0;
 };
 
@@ -37,9 +32,20 @@ namespace {
 void destroy(rara_frame_graph* fg)
 {
     if (!fg) return;
+    // the buffers below are freed only once the last replay has finished
+    if (fg->launched && fg->done) (void)hipEventSynchronize(fg->done);
     if (fg->exec) (void)hipGraphExecDestroy(fg->exec);
     if (fg->graph) (void)hipGraphDestroy(fg->graph);
+    if (fg->staged) (void)hipEventDestroy(fg->staged);
+    if (fg->done) (void)hipEventDestroy(fg->done);
+    if (fg->dev_params) (void)hipFree(fg->dev_params);
+    if (fg->host_params) (void)hipHostFree(fg->host_params);
     delete fg;
+}
+
+bool proj_complete(const rara_projected* p)
+{
+    return p->label && p->splat && p->ray && p->depth && p->rect && p->tiles_touched;
 }
 
 }  // namespace
@@ -51,58 +57,54 @@ rara_status rara_frame_graph_create(const rara_gaussians* g, const rara_camera* 
                                     float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked,
                                     rara_frame_graph** out)
 {
-    if (!g || !shape || !proj || !bins || !image || !final_T || !n_contrib || !out || g->n <= 0)
-        return RARA_ERR_INVALID;
+    if (!out) return RARA_ERR_INVALID;
     *out = nullptr;
+    if (!g || !shape || !proj || !bins || !image || !final_T || !n_contrib || g->n <= 0) return RARA_ERR_INVALID;
+    if (g->sh_degree < 0 || g->sh_degree > 3) return RARA_ERR_UNSUPPORTED;
+    if (!g->mean || !g->scale || !g->quat || !g->opacity || !g->sh || !proj_complete(proj)) return RARA_ERR_INVALID;
+    if (!bins->vals || !bins->ranges || !bins->overflow || !bins->work) return RARA_ERR_INVALID;
     CamParams cp;
     if (!make_cam_params(shape, &cp)) return RARA_ERR_INVALID;
-    rara_plane placeholder;
-    placeholder.n[0] = 0.0f;
-    placeholder.n[1] = 0.0f;
-    placeholder.n[2] = 1.0f;
-    placeholder.d = 0.0f;
-    placeholder.enabled = 1;
-    const float bg0[3] = {0.0f, 0.0f, 0.0f};
+    if (cp.tiles_x > 65535 || cp.tiles_y > 65535) return RARA_ERR_UNSUPPORTED;
 
-    hipStream_t s = nullptr;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return RARA_ERR_HIP;
     rara_frame_graph* fg = new rara_frame_graph();
+    fg->W = cp.W;
+    fg->H = cp.H;
+    if (hipMalloc(reinterpret_cast<void**>(&fg->dev_params), sizeof(FrameParams)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&fg->host_params), sizeof(FrameParams), hipHostMallocDefault) !=
+            hipSuccess ||
+        hipEventCreateWithFlags(&fg->staged, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&fg->done, hipEventDisableTiming) != hipSuccess) {
+        destroy(fg);
+        return RARA_ERR_HIP;
+    }
+
+    const GaussPtrs gp{g->n, g->sh_degree, g->mean, g->scale, g->quat, g->opacity, g->sh};
+    const ProjPtrs pp{proj->label, static_cast<Splat*>(proj->splat), static_cast<RayRec*>(proj->ray), proj->depth,
+                      proj->rect, proj->tiles_touched};
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        destroy(fg);
+        return RARA_ERR_HIP;
+    }
     rara_status st = RARA_OK;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) st = RARA_ERR_HIP;
     if (st == RARA_OK) {
-        rara_status a = rara_preprocess(g, shape, &placeholder, proj, s);
+        rara_status a = launch_preprocess_fp(gp, fg->dev_params, pp, s) == hipSuccess ? RARA_OK : RARA_ERR_HIP;
+        // binning depends on the camera only through the image size
         rara_status b = a == RARA_OK ? rara_bin_sort(proj, g->n, shape, pair_capacity, workspace, ws_bytes, bins, s) : a;
-        rara_status c = b == RARA_OK ? rara_render(proj, g->n, bins, shape, &placeholder, bg0, image, final_T,
-                                                   n_contrib, n_walked, s)
-                                     : b;
+        rara_status c = b;
+        if (c == RARA_OK)
+            c = launch_blend_fp(static_cast<const Splat*>(proj->splat), static_cast<const RayRec*>(proj->ray), *bins,
+                                fg->dev_params, cp.tiles_x * cp.tiles_y, image, final_T, n_contrib, n_walked,
+                                s) == hipSuccess
+                    ? RARA_OK
+                    : RARA_ERR_HIP;
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(s, &graph);
         fg->graph = graph;
         if (c != RARA_OK) st = c;
         else if (e != hipSuccess || !graph) st = RARA_ERR_HIP;
-    }
-    if (st == RARA_OK) {
-        size_t count = 0;
-        if (hipGraphGetNodes(fg->graph, nullptr, &count) != hipSuccess) st = RARA_ERR_HIP;
-        std::vector<hipGraphNode_t> nodes(count);
-        if (st == RARA_OK && count && hipGraphGetNodes(fg->graph, nodes.data(), &count) != hipSuccess)
-            st = RARA_ERR_HIP;
-        const void* pre_fn = preprocess_kernel_handle();
-        const void* blend_fn = blend_kernel_handle(n_walked != nullptr);
-        for (size_t k = 0; st == RARA_OK && k < count; ++k) {
-            hipGraphNodeType type;
-            if (hipGraphNodeGetType(nodes[k], &type) != hipSuccess || type != hipGraphNodeTypeKernel) continue;
-            hipKernelNodeParams kp{};
-            if (hipGraphKernelNodeGetParams(nodes[k], &kp) != hipSuccess) continue;
-            if (kp.func == pre_fn) {
-                fg->pre_node = nodes[k];
-                fg->pre = kp;
-            } else if (kp.func == blend_fn) {
-                fg->blend_node = nodes[k];
-                fg->blend = kp;
-            }
-        }
-        if (st == RARA_OK && (!fg->pre_node || !fg->blend_node)) st = RARA_ERR_HIP;
     }
     if (st == RARA_OK && hipGraphInstantiate(&fg->exec, fg->graph, nullptr, nullptr, 0) != hipSuccess)
         st = RARA_ERR_HIP;
@@ -111,21 +113,6 @@ rara_status rara_frame_graph_create(const rara_gaussians* g, const rara_camera* 
         destroy(fg);
         return st;
     }
-    fg->g = GaussPtrs{g->n, g->sh_degree, g->mean, g->scale, g->quat, g->opacity, g->sh};
-    fg->proj = ProjPtrs{proj->label, static_cast<Splat*>(proj->splat), static_cast<RayRec*>(proj->ray), proj->depth,
-                        proj->rect, proj->tiles_touched};
-    fg->splat = static_cast<const Splat*>(proj->splat);
-    fg->ray = static_cast<const RayRec*>(proj->ray);
-    fg->vals = bins->vals;
-    fg->ranges = reinterpret_cast<const uint2*>(bins->ranges);
-    fg->work = bins->work;
-    fg->overflow = bins->overflow;
-    fg->image = image;
-    fg->final_T = final_T;
-    fg->n_contrib = n_contrib;
-    fg->n_walked = n_walked;
-    fg->W = cp.W;
-    fg->H = cp.H;
     *out = fg;
     return RARA_OK;
 }
@@ -134,25 +121,20 @@ rara_status rara_frame_graph_launch(rara_frame_graph* fg, const rara_camera* cam
                                     const float* bg, void* stream)
 {
     if (!fg || !cam || !plane || !bg) return RARA_ERR_INVALID;
-    CamParams cp;
-    PlaneParams pp;
-    if (!make_cam_params(cam, &cp) || !make_plane_params(plane, &pp)) return RARA_ERR_INVALID;
-    if (cp.W != fg->W || cp.H != fg->H) return RARA_ERR_INVALID;
-    // preprocess_kernel(GaussPtrs, CamParams, PlaneParams, ProjPtrs)
-    void* pre_args[4] = {&fg->g, &cp, &pp, &fg->proj};
-    hipKernelNodeParams pk = fg->pre;
-    pk.kernelParams = pre_args;
-    pk.extra = nullptr;
-    if (hipGraphExecKernelNodeSetParams(fg->exec, fg->pre_node, &pk) != hipSuccess) return RARA_ERR_HIP;
-    // blend_kernel(splats, rays, vals, ranges, work, overflow, RenderParams, image, final_T, n_contrib, n_walked)
-    RenderParams rp = make_render_params(cp, pp, bg);
-    void* blend_args[11] = {&fg->splat, &fg->ray, &fg->vals, &fg->ranges, &fg->work, &fg->overflow,
-                            &rp, &fg->image, &fg->final_T, &fg->n_contrib, &fg->n_walked};
-    hipKernelNodeParams bk = fg->blend;
-    bk.kernelParams = blend_args;
-    bk.extra = nullptr;
-    if (hipGraphExecKernelNodeSetParams(fg->exec, fg->blend_node, &bk) != hipSuccess) return RARA_ERR_HIP;
-    return hipGraphLaunch(fg->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? RARA_OK : RARA_ERR_HIP;
+    FrameParams fp;
+    if (!make_cam_params(cam, &fp.cam) || !make_plane_params(plane, &fp.plane)) return RARA_ERR_INVALID;
+    if (fp.cam.W != fg->W || fp.cam.H != fg->H) return RARA_ERR_INVALID;
+    fp.render = make_render_params(fp.cam, fp.plane, bg);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // the staging block may be rewritten once the previous copy out of it ran
+    if (fg->launched && hipEventSynchronize(fg->staged) != hipSuccess) return RARA_ERR_HIP;
+    std::memcpy(fg->host_params, &fp, sizeof(FrameParams));
+    if (hipMemcpyAsync(fg->dev_params, fg->host_params, sizeof(FrameParams), hipMemcpyHostToDevice, s) != hipSuccess)
+        return RARA_ERR_HIP;
+    if (hipEventRecord(fg->staged, s) != hipSuccess) return RARA_ERR_HIP;
+    fg->launched = true;
+    if (hipGraphLaunch(fg->exec, s) != hipSuccess) return RARA_ERR_HIP;
+    return hipEventRecord(fg->done, s) == hipSuccess ? RARA_OK : RARA_ERR_HIP;
 }
 
 void rara_frame_graph_destroy(rara_frame_graph* fg) { destroy(fg); }

@@ -41,11 +41,10 @@ __device__ inline void sh_eval(int deg, double x, double y, double z, double* Y)
     Y[15] = -0.5900435899266435 * x * (xx - 3.0 * yy);
 }
 
-__global__ __launch_bounds__(256) void preprocess_kernel(GaussPtrs g, CamParams cam, PlaneParams pl, ProjPtrs out)
+__device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl,
+                                               const ProjPtrs& out, int64_t i)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = g.n;
-    if (i >= n) return;
 
     const double mu[3] = {g.mean[i], g.mean[n + i], g.mean[2 * n + i]};
     const double s[3] = {g.scale[i], g.scale[n + i], g.scale[2 * n + i]};
@@ -159,9 +158,24 @@ __global__ __launch_bounds__(256) void preprocess_kernel(GaussPtrs g, CamParams 
     out.tiles_touched[i] = touched;
 }
 
-}  // namespace
+__global__ __launch_bounds__(256) void preprocess_kernel(GaussPtrs g, CamParams cam, PlaneParams pl, ProjPtrs out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < g.n) preprocess_one(g, cam, pl, out, i);
+}
 
-const void* preprocess_kernel_handle() { return reinterpret_cast<const void*>(&preprocess_kernel); }
+// Frame-graph variant: camera and plane read from device memory.
+__global__ __launch_bounds__(256) void preprocess_fp_kernel(GaussPtrs g, const FrameParams* __restrict__ fp,
+                                                            ProjPtrs out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const CamParams cam = fp->cam;
+    const PlaneParams pl = fp->plane;
+    preprocess_one(g, cam, pl, out, i);
+}
+
+}  // namespace
 
 hipError_t launch_preprocess(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl, const ProjPtrs& out,
                              hipStream_t s)
@@ -169,6 +183,14 @@ hipError_t launch_preprocess(const GaussPtrs& g, const CamParams& cam, const Pla
     if (g.n == 0) return hipSuccess;
     const int64_t blocks = (g.n + 255) / 256;
     hipLaunchKernelGGL(preprocess_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, pl, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess_fp(const GaussPtrs& g, const FrameParams* fp, const ProjPtrs& out, hipStream_t s)
+{
+    if (g.n == 0) return hipSuccess;
+    const int64_t blocks = (g.n + 255) / 256;
+    hipLaunchKernelGGL(preprocess_fp_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g, fp, out);
     return hipGetLastError();
 }
 

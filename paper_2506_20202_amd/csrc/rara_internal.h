@@ -81,6 +81,16 @@ struct RenderParams {
     float bg[3];
 };
 
+// Everything a frame reads that depends on the camera pose, the clip plane or
+// the background.  Frame graphs keep one of these in device memory and
+// rewrite it with a stream-ordered copy before each replay; their kernels read
+// it through a pointer, so the graph's kernel arguments never change.
+struct FrameParams {
+    CamParams cam;
+    PlaneParams plane;
+    RenderParams render;
+};
+
 // ---- blend work list --------------------------------------------------------
 // Tiles whose list holds at least kHeavyList entries are blended as four
 // quadrant units (one wave each) and scheduled first; at most kMaxHeavy tiles
@@ -124,8 +134,11 @@ hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, i
                        uint64_t* final_keys, uint32_t* final_vals, const float* depth, hipStream_t s);
 hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, hipStream_t s);
 hipError_t launch_plan(const rara_binned& out, int num_tiles, hipStream_t s);
-const void* preprocess_kernel_handle();
-const void* blend_kernel_handle(bool walked);
+// the same kernels reading their per-frame parameters from device memory
+hipError_t launch_preprocess_fp(const GaussPtrs& g, const FrameParams* fp, const ProjPtrs& out, hipStream_t s);
+hipError_t launch_blend_fp(const Splat* splat, const RayRec* ray, const rara_binned& bins, const FrameParams* fp,
+                           int num_tiles, float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked,
+                           hipStream_t s);
 // host-side parameter blocks shared by the ABI entry points and frame graphs
 bool make_cam_params(const rara_camera* c, CamParams* p);
 bool make_plane_params(const rara_plane* pl, PlaneParams* p);

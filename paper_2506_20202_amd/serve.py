@@ -122,7 +122,7 @@ class Scheduler:
         """Retire finished requests, then admit from the head of the queue.
         Returns True when anything changed."""
         changed = False
-        for s in self.slots:
+        for s in list(self.slots):          # an overflowing slot is dropped inside the loop
             if s.request is None:
                 continue
             c = self.ex.poll(s.handle)
@@ -243,6 +243,9 @@ class GpuExecutor:
         scene = self.scenes[name]
         fr = R.Frame(scene.n, W, H, capacity, self.device, walked=False)
         st = self.torch.cuda.Stream(self.device)
+        # the buffers were allocated (and the scene uploaded) on the current
+        # stream: order the slot stream after that work
+        st.wait_stream(self.torch.cuda.current_stream(self.device))
         h = dict(frame=fr, stream=st, scene=scene, graph=None, event=None, status=None, result=None, req=None)
         h["status"] = self.torch.zeros(2, dtype=self.torch.int64, pin_memory=True)
         if self.use_graphs:
@@ -252,6 +255,10 @@ class GpuExecutor:
         return h
 
     def destroy_slot(self, h):
+        # the frame buffers return to the allocator of the stream they were
+        # allocated on: nothing may still run on the slot stream
+        if h.get("stream") is not None:
+            h["stream"].synchronize()
         if h.get("graph") is not None:
             h["graph"].close()
         h.clear()

@@ -71,11 +71,14 @@ def test_served_results_equal_alone(use_graphs):
     print(f"graphs={use_graphs} stats={st}", flush=True)
     assert st["completed"] == len(reqs) and st["failed"] == 0
     assert st["max_inflight"] >= 2
-    for (name, cam, pl), f in zip(reqs, futs):
-        img = f.result(timeout=0)
-        ref = _alone(eng.ex.scenes[name], cam, pl)
-        assert torch.equal(img, ref)
+    bad = []
+    for k, ((name, cam, pl), f) in enumerate(zip(reqs, futs)):
+        img, ref = f.result(timeout=0), _alone(eng.ex.scenes[name], cam, pl)
+        if not torch.equal(img, ref):
+            d = (img - ref).abs()
+            bad.append((k, name, cam.width, cam.height, float(d.max()), int((d > 0).sum())))
     eng.close()
+    assert not bad, f"served != alone for (request, scene, W, H, max diff, differing values): {bad}"
 
 
 def test_overflow_is_retried_with_larger_capacity():
@@ -87,7 +90,13 @@ def test_overflow_is_retried_with_larger_capacity():
     futs = [eng.submit(*r) for r in reqs]
     eng.run_until_idle(timeout=300)
     st = eng.stats()
+    print(f"stats={st} hints={eng.sched.capacity_hint}", flush=True)
     assert st["retries"] >= 1 and st["completed"] == 4
-    for (name, cam, pl), f in zip(reqs, futs):
-        assert torch.equal(f.result(timeout=0), _alone(eng.ex.scenes[name], cam, pl))
+    bad = []
+    for k, ((name, cam, pl), f) in enumerate(zip(reqs, futs)):
+        img, ref = f.result(timeout=0), _alone(eng.ex.scenes[name], cam, pl)
+        if not torch.equal(img, ref):
+            d = (img - ref).abs()
+            bad.append((k, cam.width, cam.height, float(d.max()), int((d > 0).sum())))
     eng.close()
+    assert not bad, f"served != alone for (request, W, H, max diff, differing values): {bad}"

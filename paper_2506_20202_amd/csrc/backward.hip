@@ -170,7 +170,7 @@ __device__ inline void blend_back_unit(const Splat* __restrict__ splats, const R
         if ((uint32_t)lane < cnt) {
             const uint32_t id = vals[lo + lane];
             const Splat sp = splats[id];
-            stage_entry(sp, ox, oy, s_a[lane], s_b[lane], s_c[lane], my_mask, id);
+            stage_entry(sp, ox, oy, kSlots == 4 ? 0xfu : (1u << quad), s_a[lane], s_b[lane], s_c[lane], my_mask, id);
             if (sp.label == RARA_LABEL_CUTOFF && plane_on) {
                 const float4* rr = reinterpret_cast<const float4*>(rays + id);
                 CutRec c;

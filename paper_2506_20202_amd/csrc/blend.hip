@@ -30,55 +30,69 @@ namespace rara {
 
 namespace {
 
-// One pixel's front-to-back update with one list entry, straight-line.
-// alpha = min(0.99, a0 w); entries with a positive exponent or alpha < 1/255
-// are skipped; an entry that would take T below 1e-4 terminates the pixel
-// without being composited.  A terminated pixel keeps -T (its sign marks it
-// dead; the magnitude is its final transmittance).
-__device__ inline void composite(float a0, float w, bool pw_ok, float cr, float cg, float cb, uint32_t k1,
-                                 float& T, float& C0, float& C1, float& C2, uint32_t& last, uint32_t& walked)
+// One pixel's front-to-back update with one list entry, straight-line and
+// without lane masks.  alpha = min(0.99, a0 w), a0 = delta 2^pw; entries with
+// pw > 0 or alpha below the pixel's threshold `thr` are skipped (thr = 1/255
+// while the pixel is live; a finished pixel has thr = 2, above any alpha, so
+// it is left unchanged).  An entry that would take T below 1e-4 finishes the
+// pixel without being composited: T keeps its value, the final transmittance.
+// A live pixel always has T >= 1e-4, so a skipped entry (alpha = 0, new
+// T = T) can never finish it.
+__device__ inline void composite(float pw, float op, float w, float cr, float cg, float cb, uint32_t k1, float& T,
+                                 float& thr, float& C0, float& C1, float& C2, uint32_t& last, uint32_t& walked)
 {
-    const float alpha = fminf(kAlphaMax, a0 * w);
-    const bool ok = pw_ok && (alpha >= kAlphaMin);
-    const float tT = T * (1.0f - alpha);
-    const bool term = ok && (tT < kTMin);
-    const bool acc = ok && !term;
-    const float wt = acc ? alpha * T : 0.0f;
+    const float e = __builtin_amdgcn_exp2f(pw > 0.0f ? -INFINITY : pw);
+    float alpha = fminf(kAlphaMax, (op * e) * w);
+    alpha = alpha >= thr ? alpha : 0.0f;
+    const float tT = fmaf(-alpha, T, T);
+    const bool term = tT < kTMin;
+    const float wt = term ? 0.0f : alpha * T;
     C0 = fmaf(wt, cr, C0);
     C1 = fmaf(wt, cg, C1);
     C2 = fmaf(wt, cb, C2);
-    T = acc ? tT : (term ? -T : T);
-    last = acc ? k1 : last;
+    T = term ? T : tT;
+    thr = term ? 2.0f : thr;
+    last = wt > 0.0f ? k1 : last;
     walked = term ? k1 : walked;
 }
 
 // Pixels of one work unit: a whole 16x16 tile (kSlots = 4, each lane owns the
 // same pixel of the four 8x8 quadrants) or a single quadrant of a tile with a
 // long list (kSlots = 1), so that such tiles are walked by four waves at once.
+//
+// The list is walked in batches of 64 entries.  Each lane gathers one entry,
+// stages it in LDS and tests which of the unit's quadrants the entry can
+// reach; per batch, one ballot per quadrant (and one for CUTOFF entries)
+// turns those tests into wave-uniform bit sets, so the entry loop itself does
+// no per-entry mask reads or lane-mask branches.  Every 16 entries the
+// quadrants that still hold a live pixel are re-taken and the walk ends when
+// none is left.
 template <int kSlots, bool kWalked>
 __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
                                   const uint32_t* __restrict__ vals, const uint2 rg, int tile, int quad,
-                                  const RenderParams& p, float4 (*s_a)[kBatch], float4 (*s_b)[kBatch],
-                                  float4 (*s_c)[kBatch], CutRec (*s_cut)[kBatch], float* __restrict__ image,
-                                  float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
-                                  uint32_t* __restrict__ n_walked)
+                                  const RenderParams& p, float4* s_a, float4* s_b, float4* s_c, CutRec* s_cut,
+                                  float* __restrict__ image, float* __restrict__ final_T,
+                                  uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
 {
     const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
     const int lane = threadIdx.x;
     const int lx = lane & 7, ly = lane >> 3;
 
     float lpx[kSlots], lpy[kSlots];
-    float T[kSlots], C0[kSlots], C1[kSlots], C2[kSlots];
+    float T[kSlots], thr[kSlots], C0[kSlots], C1[kSlots], C2[kSlots];
     uint32_t last[kSlots], walked[kSlots];
     int qof[kSlots];
+    uint32_t want = 0u;
 #pragma unroll
     for (int q = 0; q < kSlots; ++q) {
         const int qq = kSlots == 4 ? q : quad;
         qof[q] = qq;
+        want |= 1u << qq;
         lpx[q] = (float)((qq & 1) * 8 + lx);
         lpy[q] = (float)((qq >> 1) * 8 + ly);
         const bool inside = (tx * kTile + (qq & 1) * 8 + lx < p.W) && (ty * kTile + (qq >> 1) * 8 + ly < p.H);
-        T[q] = inside ? 1.0f : -1.0f;   // the sign marks a live pixel
+        T[q] = 1.0f;
+        thr[q] = inside ? kAlphaMin : 2.0f;   // pixels outside the image never take part
         C0[q] = C1[q] = C2[q] = 0.0f;
         last[q] = walked[q] = 0u;
     }
@@ -90,7 +104,6 @@ __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec
     float4 nr0, nr1, nr2;
     bool have = false;
     uint32_t cur_id = 0u;
-    uint32_t my_mask = 0u;
     auto fetch = [&](uint32_t base) {
         const uint32_t idx = base + lane;
         have = idx < rg.y;
@@ -106,58 +119,70 @@ __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec
             }
         }
     };
-    auto stage = [&](int buf) {
-        my_mask = 0u;
-        if (have) {
-            stage_entry(nx, ox, oy, s_a[buf][lane], s_b[buf][lane], s_c[buf][lane], my_mask, cur_id);
-            if (nx.label == RARA_LABEL_CUTOFF && plane_on) {
-                CutRec c;
-                c.a = nr0;
-                c.b = nr1;
-                c.c = nr2;
-                s_cut[buf][lane] = c;
-            }
-        }
-    };
     // quadrants (bit qof[q]) that still hold a live pixel, wave-uniform
     auto live_quads = [&]() -> uint32_t {
         uint32_t m = 0u;
 #pragma unroll
-        for (int q = 0; q < kSlots; ++q) m |= __ballot(T[q] > 0.0f) != 0ull ? (1u << qof[q]) : 0u;
+        for (int q = 0; q < kSlots; ++q) m |= __ballot(thr[q] < 1.0f) != 0ull ? (1u << qof[q]) : 0u;
         return m;
     };
 
     uint32_t live = live_quads();
     if (rg.x < rg.y && live) fetch(rg.x);
-    int buf = 0;
-    for (uint32_t base = rg.x; base < rg.y && live; base += kBatch, buf ^= 1) {
-        stage(buf);
+    for (uint32_t base = rg.x; base < rg.y && live; base += kBatch) {
+        uint32_t my_mask = 0u;
+        bool my_cut = false;
+        __syncthreads();   // the previous batch has been read
+        if (have) {
+            stage_entry(nx, ox, oy, want, s_a[lane], s_b[lane], s_c[lane], my_mask, cur_id);
+            my_cut = nx.label == RARA_LABEL_CUTOFF && plane_on;
+            if (my_cut) {
+                CutRec c;
+                c.a = nr0;
+                c.b = nr1;
+                c.c = nr2;
+                s_cut[lane] = c;
+            }
+        }
         __syncthreads();
         if (base + kBatch < rg.y) fetch(base + kBatch);   // overlaps with the compositing below
-        // only entries that reach a quadrant with live pixels are visited, in list order
-        uint64_t todo = __ballot((my_mask & live) != 0u);   // my_mask is 0 past the list end
-        while (todo) {
-            const int j = (int)__builtin_ctzll(todo);
-            todo &= todo - 1ull;
-            const float4 a = s_a[buf][j], b = s_b[buf][j];
-            const float4 c = s_c[buf][j];
-            const uint32_t k1 = base - rg.x + (uint32_t)j + 1u;
-            const uint32_t lm = __builtin_amdgcn_readfirstlane(__float_as_uint(c.y));
-            const bool cut = plane_on && ((lm & 0xffu) == RARA_LABEL_CUTOFF);
-            const float dxa = lpx[0] - a.x, dya = lpy[0] - a.y;
-            const float dxb = lpx[kSlots - 1] - a.x, dyb = lpy[kSlots - 1] - a.y;
+        uint64_t qb[kSlots];
+#pragma unroll
+        for (int q = 0; q < kSlots; ++q) qb[q] = __ballot((my_mask >> qof[q]) & 1u);
+        const uint64_t cutb = __ballot(my_cut);
+        const uint32_t kofs = base - rg.x + 1u;
+        for (int chunk = 0; chunk < kBatch; chunk += 16) {
+            // entries of this chunk that reach a quadrant with live pixels, in list order
+            uint64_t ql[kSlots];
+            uint64_t todo = 0ull;
 #pragma unroll
             for (int q = 0; q < kSlots; ++q) {
-                if (((lm >> (8 + qof[q])) & 1u) && T[q] > 0.0f) {
-                    const bool xb = kSlots == 4 ? (q & 1) : false;
-                    const bool yb = kSlots == 4 ? (q >> 1) : false;
-                    const float dx = xb ? dxb : dxa;
-                    const float dy = yb ? dyb : dya;
-                    const float pw = entry_power(a, b, dx, dy);
-                    const float a0 = b.y * __builtin_amdgcn_exp2f(pw);
-                    float w = 1.0f;
-                    if (cut) w = chord_weight(s_cut[buf][j], dx, dy, p.ax, p.ay);
-                    composite(a0, w, pw <= 0.0f, b.z, b.w, c.x, k1, T[q], C0[q], C1[q], C2[q], last[q], walked[q]);
+                ql[q] = ((live >> qof[q]) & 1u) ? qb[q] : 0ull;
+                todo |= ql[q];
+            }
+            todo &= 0xffffull << chunk;
+            while (todo) {
+                const int j = (int)__builtin_ctzll(todo);
+                todo &= todo - 1ull;
+                const float4 a = s_a[j], b = s_b[j];
+                const float cb_ = s_c[j].x;
+                const bool cut = (cutb >> j) & 1ull;
+                const uint32_t k1 = kofs + (uint32_t)j;
+                const float dxa = lpx[0] - a.x, dya = lpy[0] - a.y;
+                const float dxb = lpx[kSlots - 1] - a.x, dyb = lpy[kSlots - 1] - a.y;
+#pragma unroll
+                for (int q = 0; q < kSlots; ++q) {
+                    if (kSlots == 1 || ((ql[q] >> j) & 1ull)) {
+                        const bool xb = kSlots == 4 ? (q & 1) : false;
+                        const bool yb = kSlots == 4 ? (q >> 1) : false;
+                        const float dx = xb ? dxb : dxa;
+                        const float dy = yb ? dyb : dya;
+                        const float pw = entry_power(a, b, dx, dy);
+                        float w = 1.0f;
+                        if (cut) w = chord_weight(s_cut[j], dx, dy, p.ax, p.ay);
+                        composite(pw, b.y, w, b.z, b.w, cb_, k1, T[q], thr[q], C0[q], C1[q], C2[q], last[q],
+                                  walked[q]);
+                    }
                 }
             }
             live = live_quads();
@@ -171,14 +196,13 @@ __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec
         const int px = tx * kTile + (int)lpx[q], py = ty * kTile + (int)lpy[q];
         if (px >= p.W || py >= p.H) continue;
         const int64_t pix = (int64_t)py * p.W + px;
-        const float Tq = fabsf(T[q]);
-        image[pix] = C0[q] + Tq * p.bg[0];
-        image[HW + pix] = C1[q] + Tq * p.bg[1];
-        image[2 * HW + pix] = C2[q] + Tq * p.bg[2];
-        final_T[pix] = Tq;
+        image[pix] = C0[q] + T[q] * p.bg[0];
+        image[HW + pix] = C1[q] + T[q] * p.bg[1];
+        image[2 * HW + pix] = C2[q] + T[q] * p.bg[2];
+        final_T[pix] = T[q];
         n_contrib[pix] = last[q];
-        // a pixel still alive at the end examined the whole list
-        if (kWalked) n_walked[pix] = T[q] > 0.0f ? rg.y - rg.x : walked[q];
+        // a pixel still live at the end examined the whole list
+        if (kWalked) n_walked[pix] = thr[q] < 1.0f ? rg.y - rg.x : walked[q];
     }
 }
 
@@ -194,8 +218,8 @@ __device__ __forceinline__ void blend_block(const Splat* __restrict__ splats, co
     if (!unit_of_block(blockIdx.x, work, p.num_tiles, unit)) return;
     const int tile = (int)(unit >> 3), mode = (int)(unit & 7u);
     if (tile >= p.num_tiles || mode > 4) return;
-    __shared__ float4 s_a[2][kBatch], s_b[2][kBatch], s_c[2][kBatch];
-    __shared__ CutRec s_cut[2][kBatch];
+    __shared__ float4 s_a[kBatch], s_b[kBatch], s_c[kBatch];
+    __shared__ CutRec s_cut[kBatch];
     const uint2 rg = ranges[tile];
     if (mode == 4)
         blend_unit<4, kWalked>(splats, rays, vals, rg, tile, 0, p, s_a, s_b, s_c, s_cut, image, final_T, n_contrib,

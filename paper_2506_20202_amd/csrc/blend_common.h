@@ -74,34 +74,74 @@ __device__ inline float chord_weight(const CutRec& k, float dx, float dy, float 
     return c.w;
 }
 
+// Whether the alpha >= 1/255 region of an entry can reach the pixel centres
+// [qx, qx + 7] x [qy, qy + 7] (tile coordinates).  alpha >= 1/255 needs the
+// conic form q(d) = ca dx^2 + 2 cb dx dy + cc dy^2 at d = pixel - centre to be
+// at most m2 = 2 ln(255 delta) (the clip weight only lowers alpha).  The form
+// is convex, so its minimum over the box is 0 when the centre lies inside and
+// otherwise the smallest of the four edge minima; along the edge dx = X it is
+// cc (dy - dy*)^2 + X^2 det/cc with dy* = -cb X / cc clamped to the edge, a sum
+// of two non-negative terms (no cancellation).  The caller pads m2 so that
+// float rounding can only keep a quadrant, never drop one.
+struct QuadForm {
+    float mx, my;    // centre, tile coordinates
+    float ca, cc;    // conic diagonal
+    float kx, ky;    // -cb / cc, -cb / ca
+    float dx_, dy_;  // det / cc, det / ca
+};
+
+__device__ inline bool quad_reach(const QuadForm& f, float m2, float qx, float qy)
+{
+    const float x0 = qx - f.mx, x1 = (qx + 7.0f) - f.mx;
+    const float y0 = qy - f.my, y1 = (qy + 7.0f) - f.my;
+    const bool inside = (x0 <= 0.0f) && (x1 >= 0.0f) && (y0 <= 0.0f) && (y1 >= 0.0f);
+    auto edge_x = [&](float X) {
+        const float ys = f.kx * X;
+        const float t = __builtin_amdgcn_fmed3f(ys, y0, y1) - ys;
+        return fmaf(f.cc * t, t, f.dx_ * (X * X));
+    };
+    auto edge_y = [&](float Y) {
+        const float xs = f.ky * Y;
+        const float t = __builtin_amdgcn_fmed3f(xs, x0, x1) - xs;
+        return fmaf(f.ca * t, t, f.dy_ * (Y * Y));
+    };
+    const float qmin = fminf(fminf(edge_x(x0), edge_x(x1)), fminf(edge_y(y0), edge_y(y1)));
+    return inside || qmin <= m2;
+}
+
 // Staged form of one list entry.  s_a: centre (tile-relative), pre-scaled
 // conic a and b; s_b: pre-scaled conic c, opacity, red, green; s_c: blue,
-// label | quadrant mask << 8, Gaussian index.
-__device__ inline void stage_entry(const Splat& nx, double ox, double oy, float4& sa, float4& sb, float4& sc,
-                                   uint32_t& qmask, uint32_t id)
+// label | quadrant mask << 8, Gaussian index.  The quadrant mask holds bit q
+// (q = 2 * row + column of the 8x8 quadrant) for every quadrant in `want`
+// that the entry can reach with alpha >= 1/255; an entry is never left out of
+// a quadrant it could reach.
+__device__ inline void stage_entry(const Splat& nx, double ox, double oy, uint32_t want, float4& sa, float4& sb,
+                                   float4& sc, uint32_t& qmask, uint32_t id)
 {
     const float kq = -0.5f * kLog2e;
     const float mx = (float)(nx.mx - ox), my = (float)(nx.my - oy);
     sa = make_float4(mx, my, nx.ca * kq, -nx.cb * kLog2e);
     sb = make_float4(nx.cc * kq, nx.op, nx.r, nx.g);
-    // Quadrants of the tile the entry can reach with alpha >= 1/255:
-    // delta exp(-m/2) >= 1/255 needs Mahalanobis^2 m <= 2 ln(255 delta),
-    // whose ellipse has axis half-widths sqrt(m Vhat_00), sqrt(m Vhat_11).
-    // Padded (1 % + 0.1 px) so float rounding can only widen the box; an entry
-    // is never skipped for a pixel it could reach.
     qmask = 0u;
     const float s255 = 255.0f * nx.op;
     if (s255 > 1.0f) {
-        const float m2 = 2.0f * __logf(s255) * 1.001f + 1e-3f;
-        const float idet = 1.0f / (nx.ca * nx.cc - nx.cb * nx.cb);
-        const float hx = sqrtf(m2 * nx.cc * idet) * 1.01f + 0.1f;
-        const float hy = sqrtf(m2 * nx.ca * idet) * 1.01f + 0.1f;
+        // padded by 2 % + 0.02 against the rounding of the form, det and log
+        const float m2 = fmaf(2.0f * __logf(s255), 1.02f, 0.02f);
+        const float det = fmaf(nx.ca, nx.cc, -nx.cb * nx.cb);
+        const float ica = 1.0f / nx.ca, icc = 1.0f / nx.cc;
+        QuadForm f;
+        f.mx = mx;
+        f.my = my;
+        f.ca = nx.ca;
+        f.cc = nx.cc;
+        f.kx = -nx.cb * icc;
+        f.ky = -nx.cb * ica;
+        f.dx_ = fmaxf(det, 0.0f) * icc;
+        f.dy_ = fmaxf(det, 0.0f) * ica;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float qx = (float)((q & 1) * 8), qy = (float)((q >> 1) * 8);
-            const bool hit = (mx - hx <= qx + 7.0f) && (mx + hx >= qx) && (my - hy <= qy + 7.0f) && (my + hy >= qy);
-            qmask |= hit ? (1u << q) : 0u;
-        }
+        for (int q = 0; q < 4; ++q)
+            if ((want >> q) & 1u)
+                qmask |= quad_reach(f, m2, (float)((q & 1) * 8), (float)((q >> 1) * 8)) ? (1u << q) : 0u;
     }
     sc = make_float4(nx.b, __uint_as_float(nx.label | (qmask << 8)), __uint_as_float(id), 0.0f);
 }

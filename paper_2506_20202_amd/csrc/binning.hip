@@ -129,6 +129,12 @@ __global__ __launch_bounds__(1024) void scan_blocks_kernel(uint32_t* __restrict_
 }
 
 // One (tile, index) pair per covered tile, Gaussians taken in depth order.
+// A workgroup owns 256 consecutive Gaussians of the depth order and the
+// contiguous run of pairs they emit.  The pairs are expanded cooperatively:
+// thread e of each 256-pair step finds the Gaussian that owns pair e by a
+// binary search over the workgroup's inclusive pair offsets in LDS, so the
+// work per thread does not depend on footprint sizes and the stores of a
+// step are consecutive.
 __global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ tt, const uint16_t* __restrict__ rect,
                                                    const uint32_t* __restrict__ order,
                                                    const int64_t* __restrict__ count,
@@ -136,22 +142,35 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ 
                                                    const int32_t* __restrict__ overflow, uint32_t* __restrict__ tkeys,
                                                    uint32_t* __restrict__ tvals)
 {
-    const int64_t k = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    __shared__ uint32_t s_end[kScanBlock];   // inclusive end of each Gaussian's pairs inside the workgroup
+    __shared__ uint32_t s_id[kScanBlock];
+    __shared__ ushort4 s_rc[kScanBlock];
+    const int tid = threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * kScanBlock + tid;
     const bool valid = k < *count;
     const uint32_t id = valid ? order[k] : 0u;
     const uint32_t v = valid ? tt[id] : 0u;
     uint32_t total;
     const uint32_t pre = block_ballot_scan(v, total);
-    if (*overflow) return;
-    if (v == 0) return;
-    uint32_t off = block_off[blockIdx.x] + pre;
-    const ushort4 rc = *reinterpret_cast<const ushort4*>(rect + 4 * (int64_t)id);
-    for (int y = rc.y; y < rc.w; ++y)
-        for (int x = rc.x; x < rc.z; ++x) {
-            tkeys[off] = (uint32_t)(y * tiles_x + x);
-            tvals[off] = id;
-            ++off;
-        }
+    if (*overflow || total == 0u) return;   // uniform over the workgroup
+    s_end[tid] = pre + v;
+    s_id[tid] = id;
+    s_rc[tid] = v ? *reinterpret_cast<const ushort4*>(rect + 4 * (int64_t)id) : make_ushort4(0, 0, 1, 1);
+    __syncthreads();
+    const uint32_t base = block_off[blockIdx.x];
+    for (uint32_t e = (uint32_t)tid; e < total; e += kScanBlock) {
+        // owner = number of Gaussians whose pairs all precede e (s_end is non-decreasing, s_end[255] = total)
+        int own = 0;
+#pragma unroll
+        for (int step = kScanBlock / 2; step > 0; step >>= 1)
+            if (s_end[own + step - 1] <= e) own += step;
+        const uint32_t li = e - (own ? s_end[own - 1] : 0u);
+        const ushort4 rc = s_rc[own];
+        const uint32_t w = (uint32_t)(rc.z - rc.x);
+        const uint32_t row = li / w, col = li - row * w;
+        tkeys[base + e] = (uint32_t)((rc.y + row) * (uint32_t)tiles_x + rc.x + col);
+        tvals[base + e] = s_id[own];
+    }
 }
 
 __global__ __launch_bounds__(256) void ranges_clear_kernel(uint32_t* __restrict__ ranges, int num_tiles)
@@ -175,69 +194,66 @@ __global__ __launch_bounds__(256) void ranges_mark_kernel(const uint64_t* __rest
     }
 }
 
-// Exclusive count of set flags over a 1024-thread block (16 waves) and the total.
-__device__ inline uint32_t block_flag_scan(bool f, uint32_t& total, uint32_t* wave_cnt)
+// Exclusive sum of v over a 1024-thread block (16 waves) and the block total.
+__device__ inline uint32_t block_sum_scan(uint32_t v, uint32_t& total, uint32_t* wave_tot)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t m = __ballot(f);
-    if (lane == 0) wave_cnt[wave] = (uint32_t)__popcll(m);
+    uint32_t incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) wave_tot[wave] = incl;
     __syncthreads();
     uint32_t before = 0, tot = 0;
     for (int w = 0; w < 16; ++w) {
-        const uint32_t c = wave_cnt[w];
+        const uint32_t c = wave_tot[w];
         before += w < wave ? c : 0u;
         tot += c;
     }
     __syncthreads();
     total = tot;
-    return before + lanes_below(m);
+    return before + incl - v;
 }
 
 // Blend schedule: tiles whose list has at least kHeavyList entries (the first
 // kMaxHeavy of them in tile order) become four quadrant units, dispatched
 // first so the longest walks start earliest and run on four waves; every
 // other tile is one unit.  work[4h + q] = quadrant q of split tile h,
-// work[4H + l] = l-th whole tile (tile order), work[4T] = H.  Deterministic
-// (ballot compaction in tile order).
+// work[4H + l] = l-th whole tile (tile order), work[4T] = H.  One workgroup;
+// thread t owns a contiguous run of tiles, so two block scans place every
+// unit (deterministic, tile order).
 __global__ __launch_bounds__(1024) void plan_kernel(const uint2* __restrict__ ranges, int num_tiles,
                                                     uint32_t* __restrict__ work)
 {
-    __shared__ uint32_t wave_cnt[16];
+    __shared__ uint32_t wave_tot[16];
     const int tid = threadIdx.x;
-    uint32_t H = 0;
-    for (int c = 0; c < num_tiles; c += 1024) {
-        const int t = c + tid;
-        bool heavy = false;
-        if (t < num_tiles) {
-            const uint2 r = ranges[t];
-            heavy = r.y - r.x >= kHeavyList;
+    const int per = (num_tiles + 1023) / 1024;
+    const int t0 = tid * per < num_tiles ? tid * per : num_tiles;
+    const int t1 = t0 + per < num_tiles ? t0 + per : num_tiles;
+    auto heavy = [&](int t) {
+        const uint2 r = ranges[t];
+        return r.y - r.x >= kHeavyList;
+    };
+    uint32_t hc = 0;
+    for (int t = t0; t < t1; ++t) hc += heavy(t) ? 1u : 0u;
+    uint32_t htot;
+    const uint32_t hx = block_sum_scan(hc, htot, wave_tot);
+    const uint32_t H = htot < (uint32_t)kMaxHeavy ? htot : (uint32_t)kMaxHeavy;
+    // heavy tiles of rank >= H stay whole
+    const uint32_t nsplit = hx >= H ? 0u : (hx + hc <= H ? hc : H - hx);
+    uint32_t ltot;
+    const uint32_t lx = block_sum_scan((uint32_t)(t1 - t0) - nsplit, ltot, wave_tot);
+    uint32_t h = hx, l = lx;
+    for (int t = t0; t < t1; ++t) {
+        if (heavy(t) && h < H) {
+            for (uint32_t q = 0; q < 4; ++q) work[4 * h + q] = ((uint32_t)t << 3) | q;
+            ++h;
+        } else {
+            work[4 * H + l] = ((uint32_t)t << 3) | 4u;
+            ++l;
         }
-        uint32_t tot;
-        block_flag_scan(heavy, tot, wave_cnt);
-        H += tot;
-    }
-    if (H > (uint32_t)kMaxHeavy) H = kMaxHeavy;
-    uint32_t hbase = 0, lbase = 0;
-    for (int c = 0; c < num_tiles; c += 1024) {
-        const int t = c + tid;
-        bool heavy = false;
-        if (t < num_tiles) {
-            const uint2 r = ranges[t];
-            heavy = r.y - r.x >= kHeavyList;
-        }
-        uint32_t htot;
-        const uint32_t hr = block_flag_scan(heavy, htot, wave_cnt);
-        const bool split = heavy && hbase + hr < H;
-        uint32_t stot;
-        block_flag_scan(split, stot, wave_cnt);
-        const bool whole = t < num_tiles && !split;
-        uint32_t ltot;
-        const uint32_t lr = block_flag_scan(whole, ltot, wave_cnt);
-        if (split)
-            for (uint32_t q = 0; q < 4; ++q) work[4 * (hbase + hr) + q] = ((uint32_t)t << 3) | q;
-        if (whole) work[4 * H + lbase + lr] = ((uint32_t)t << 3) | 4u;
-        hbase += stot;
-        lbase += ltot;
     }
     if (tid == 0) work[4 * num_tiles] = H;
 }

@@ -41,6 +41,9 @@ __device__ inline void sh_eval(int deg, double x, double y, double z, double* Y)
     Y[15] = -0.5900435899266435 * x * (xx - 3.0 * yy);
 }
 
+// kDeg: the SH degree, fixed per launch so that every coefficient load of a
+// Gaussian is issued before the first one is used.
+template <int kDeg>
 __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl,
                                                const ProjPtrs& out, int64_t i)
 {
@@ -110,9 +113,10 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
                     double dir[3] = {mu[0] - cam.e[0], mu[1] - cam.e[1], mu[2] - cam.e[2]};
                     const double dl = 1.0 / sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
                     double Y[16];
-                    sh_eval(g.sh_degree, dir[0] * dl, dir[1] * dl, dir[2] * dl, Y);
-                    const int ncoef = (g.sh_degree + 1) * (g.sh_degree + 1);
+                    sh_eval(kDeg, dir[0] * dl, dir[1] * dl, dir[2] * dl, Y);
+                    constexpr int ncoef = (kDeg + 1) * (kDeg + 1);
                     double rgb[3] = {0.5, 0.5, 0.5};
+#pragma unroll
                     for (int k = 0; k < ncoef; ++k)
                         for (int c = 0; c < 3; ++c) rgb[c] += Y[k] * (double)g.sh[((int64_t)k * 3 + c) * n + i];
 
@@ -158,13 +162,15 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
     out.tiles_touched[i] = touched;
 }
 
+template <int kDeg>
 __global__ __launch_bounds__(256) void preprocess_kernel(GaussPtrs g, CamParams cam, PlaneParams pl, ProjPtrs out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < g.n) preprocess_one(g, cam, pl, out, i);
+    if (i < g.n) preprocess_one<kDeg>(g, cam, pl, out, i);
 }
 
 // Frame-graph variant: camera and plane read from device memory.
+template <int kDeg>
 __global__ __launch_bounds__(256) void preprocess_fp_kernel(GaussPtrs g, const FrameParams* __restrict__ fp,
                                                             ProjPtrs out)
 {
@@ -172,7 +178,7 @@ __global__ __launch_bounds__(256) void preprocess_fp_kernel(GaussPtrs g, const F
     if (i >= g.n) return;
     const CamParams cam = fp->cam;
     const PlaneParams pl = fp->plane;
-    preprocess_one(g, cam, pl, out, i);
+    preprocess_one<kDeg>(g, cam, pl, out, i);
 }
 
 }  // namespace
@@ -181,16 +187,26 @@ hipError_t launch_preprocess(const GaussPtrs& g, const CamParams& cam, const Pla
                              hipStream_t s)
 {
     if (g.n == 0) return hipSuccess;
-    const int64_t blocks = (g.n + 255) / 256;
-    hipLaunchKernelGGL(preprocess_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, pl, out);
+    const dim3 grid((unsigned)((g.n + 255) / 256)), block(256);
+    switch (g.sh_degree) {
+    case 0: hipLaunchKernelGGL(preprocess_kernel<0>, grid, block, 0, s, g, cam, pl, out); break;
+    case 1: hipLaunchKernelGGL(preprocess_kernel<1>, grid, block, 0, s, g, cam, pl, out); break;
+    case 2: hipLaunchKernelGGL(preprocess_kernel<2>, grid, block, 0, s, g, cam, pl, out); break;
+    default: hipLaunchKernelGGL(preprocess_kernel<3>, grid, block, 0, s, g, cam, pl, out); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_preprocess_fp(const GaussPtrs& g, const FrameParams* fp, const ProjPtrs& out, hipStream_t s)
 {
     if (g.n == 0) return hipSuccess;
-    const int64_t blocks = (g.n + 255) / 256;
-    hipLaunchKernelGGL(preprocess_fp_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g, fp, out);
+    const dim3 grid((unsigned)((g.n + 255) / 256)), block(256);
+    switch (g.sh_degree) {
+    case 0: hipLaunchKernelGGL(preprocess_fp_kernel<0>, grid, block, 0, s, g, fp, out); break;
+    case 1: hipLaunchKernelGGL(preprocess_fp_kernel<1>, grid, block, 0, s, g, fp, out); break;
+    case 2: hipLaunchKernelGGL(preprocess_fp_kernel<2>, grid, block, 0, s, g, fp, out); break;
+    default: hipLaunchKernelGGL(preprocess_fp_kernel<3>, grid, block, 0, s, g, fp, out); break;
+    }
     return hipGetLastError();
 }
 

@@ -103,7 +103,7 @@ inline int64_t work_grid(int64_t tiles) { return tiles + 3 * (tiles < kMaxHeavy 
 // ---- bin/sort workspace carve-up -------------------------------------------
 constexpr int kScanBlock = 256;      // Gaussians per scan chunk
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;       // keys per thread per sort tile
+constexpr int kSortItems = 4;        // keys per thread per sort tile
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;

@@ -5,14 +5,15 @@
 // w = 1 for VISIBLE Gaussians; for CUTOFF ones w is the visible fraction of
 // the pixel ray's chord through the 3-sigma ellipsoid (eqs. 4-8, 11).
 //
-// Layout: one 64-lane wave per 16x16 tile, each lane owning the same pixel of
-// the four 8x8 quadrants.  The tile's sorted list is walked in batches of 64:
-// each lane gathers one 48-byte splat record (and, for CUTOFF Gaussians, the
-// 48-byte ray record) into LDS, converting the projected centre to
-// tile-relative FP32 (exact to ~1e-6 px) and folding -log2(e)/2 into the conic
-// so that alpha needs one exp2.  Every lane then reads each staged record as
-// an LDS broadcast and evaluates its four pixels.  The CUTOFF branch is
-// wave-uniform (labels are per Gaussian).
+// Layout: one 256-thread workgroup per 16x16 tile; wave w owns the 8x8
+// quadrant w (one pixel per lane).  The tile's sorted list is walked in
+// batches of 256: each thread gathers one 48-byte splat record (and, for
+// CUTOFF Gaussians, the 48-byte ray record), converts the projected centre to
+// tile-relative FP32 (exact to ~1e-6 px), folds -log2(e)/2 into the conic so
+// that alpha needs one exp2, tests which quadrants the entry can reach, and
+// stages it in LDS.  Each wave then visits, in list order, the staged entries
+// that reach its quadrant, reading each as an LDS broadcast.  The CUTOFF
+// branch is wave-uniform (labels are per Gaussian).
 //
 // The weight is evaluated in whitened space from the pixel offset, not from
 // the world-space quadratic: with delta = gx dx + gy dy, D = d0 + delta,
@@ -56,157 +57,98 @@ __device__ inline void composite(float pw, float op, float w, float cr, float cg
     walked = term ? k1 : walked;
 }
 
-// Pixels of one work unit: a whole 16x16 tile (kSlots = 4, each lane owns the
-// same pixel of the four 8x8 quadrants) or a single quadrant of a tile with a
-// long list (kSlots = 1), so that such tiles are walked by four waves at once.
-//
-// The list is walked in batches of 64 entries.  Each lane gathers one entry,
-// stages it in LDS and tests which of the unit's quadrants the entry can
-// reach; per batch, one ballot per quadrant (and one for CUTOFF entries)
-// turns those tests into wave-uniform bit sets, so the entry loop itself does
-// no per-entry mask reads or lane-mask branches.  Every 16 entries the
-// quadrants that still hold a live pixel are re-taken and the walk ends when
-// none is left.
-template <int kSlots, bool kWalked>
-__device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
-                                  const uint32_t* __restrict__ vals, const uint2 rg, int tile, int quad,
-                                  const RenderParams& p, float4* s_a, float4* s_b, float4* s_c, CutRec* s_cut,
+constexpr int kTileBatch = 256;   // entries staged per batch, one per thread
+
+// One tile: thread t of wave w = t / 64 owns pixel (t % 8, (t / 8) % 8) of the
+// 8x8 quadrant w.  Per batch, every thread stages one entry; after the
+// barrier each wave takes, per 64 staged entries, one ballot of the entries
+// that reach its quadrant and one of the CUTOFF entries, and visits the set
+// bits in order.  A wave re-takes its live pixels every 16 entries and stops
+// visiting once none is left; the workgroup stops when no wave has one.
+template <bool kWalked>
+__device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
+                                  const uint32_t* __restrict__ vals, const uint2 rg, int tile,
+                                  const RenderParams& p, float4* s_a, float4* s_b, float2* s_c, CutRec* s_cut,
                                   float* __restrict__ image, float* __restrict__ final_T,
                                   uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
 {
     const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
-    const int lane = threadIdx.x;
-    const int lx = lane & 7, ly = lane >> 3;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int ox8 = (wave & 1) * 8 + (lane & 7), oy8 = (wave >> 1) * 8 + (lane >> 3);
+    const float lpx = (float)ox8, lpy = (float)oy8;
+    const int px = tx * kTile + ox8, py = ty * kTile + oy8;
+    const bool inside = px < p.W && py < p.H;
 
-    float lpx[kSlots], lpy[kSlots];
-    float T[kSlots], thr[kSlots], C0[kSlots], C1[kSlots], C2[kSlots];
-    uint32_t last[kSlots], walked[kSlots];
-    int qof[kSlots];
-    uint32_t want = 0u;
-#pragma unroll
-    for (int q = 0; q < kSlots; ++q) {
-        const int qq = kSlots == 4 ? q : quad;
-        qof[q] = qq;
-        want |= 1u << qq;
-        lpx[q] = (float)((qq & 1) * 8 + lx);
-        lpy[q] = (float)((qq >> 1) * 8 + ly);
-        const bool inside = (tx * kTile + (qq & 1) * 8 + lx < p.W) && (ty * kTile + (qq >> 1) * 8 + ly < p.H);
-        T[q] = 1.0f;
-        thr[q] = inside ? kAlphaMin : 2.0f;   // pixels outside the image never take part
-        C0[q] = C1[q] = C2[q] = 0.0f;
-        last[q] = walked[q] = 0u;
-    }
+    float T = 1.0f, thr = inside ? kAlphaMin : 2.0f;   // pixels outside the image never take part
+    float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+    uint32_t last = 0u, walked = 0u;
 
     const double ox = (double)(tx * kTile), oy = (double)(ty * kTile);
     const bool plane_on = p.plane_enabled != 0;
+    bool live = __ballot(thr < 1.0f) != 0ull;
 
-    Splat nx;
-    float4 nr0, nr1, nr2;
-    bool have = false;
-    uint32_t cur_id = 0u;
-    auto fetch = [&](uint32_t base) {
-        const uint32_t idx = base + lane;
-        have = idx < rg.y;
-        if (have) {
+    for (uint32_t base = rg.x; base < rg.y; base += kTileBatch) {
+        if (!__syncthreads_or(live ? 1 : 0)) break;   // also: the previous batch has been read
+        const uint32_t idx = base + (uint32_t)tid;
+        float2 sc = make_float2(0.0f, 0.0f);   // label | quadrant mask << 8 = 0: reaches nothing
+        if (idx < rg.y) {
             const uint32_t id = vals[idx];
-            cur_id = id;
-            nx = splats[id];
-            if (nx.label == RARA_LABEL_CUTOFF && plane_on) {
+            const Splat sp = splats[id];
+            float4 sa, sb, c4;
+            uint32_t qm;
+            stage_entry(sp, ox, oy, 0xfu, sa, sb, c4, qm, id);
+            s_a[tid] = sa;
+            s_b[tid] = sb;
+            sc = make_float2(c4.x, c4.y);
+            if (sp.label == RARA_LABEL_CUTOFF && plane_on) {
                 const float4* rr = reinterpret_cast<const float4*>(rays + id);
-                nr0 = rr[0];
-                nr1 = rr[1];
-                nr2 = rr[2];
+                const float4 r0 = rr[0], r1 = rr[1], r2 = rr[2];
+                s_cut[tid].a = r0;
+                s_cut[tid].b = r1;
+                s_cut[tid].c = r2;
             }
         }
-    };
-    // quadrants (bit qof[q]) that still hold a live pixel, wave-uniform
-    auto live_quads = [&]() -> uint32_t {
-        uint32_t m = 0u;
-#pragma unroll
-        for (int q = 0; q < kSlots; ++q) m |= __ballot(thr[q] < 1.0f) != 0ull ? (1u << qof[q]) : 0u;
-        return m;
-    };
-
-    uint32_t live = live_quads();
-    if (rg.x < rg.y && live) fetch(rg.x);
-    for (uint32_t base = rg.x; base < rg.y && live; base += kBatch) {
-        uint32_t my_mask = 0u;
-        bool my_cut = false;
-        __syncthreads();   // the previous batch has been read
-        if (have) {
-            stage_entry(nx, ox, oy, want, s_a[lane], s_b[lane], s_c[lane], my_mask, cur_id);
-            my_cut = nx.label == RARA_LABEL_CUTOFF && plane_on;
-            if (my_cut) {
-                CutRec c;
-                c.a = nr0;
-                c.b = nr1;
-                c.c = nr2;
-                s_cut[lane] = c;
-            }
-        }
+        s_c[tid] = sc;
         __syncthreads();
-        if (base + kBatch < rg.y) fetch(base + kBatch);   // overlaps with the compositing below
-        uint64_t qb[kSlots];
-#pragma unroll
-        for (int q = 0; q < kSlots; ++q) qb[q] = __ballot((my_mask >> qof[q]) & 1u);
-        const uint64_t cutb = __ballot(my_cut);
+        if (!live) continue;
+        const uint32_t cnt = rg.y - base < (uint32_t)kTileBatch ? rg.y - base : (uint32_t)kTileBatch;
         const uint32_t kofs = base - rg.x + 1u;
-        for (int chunk = 0; chunk < kBatch; chunk += 16) {
-            // entries of this chunk that reach a quadrant with live pixels, in list order
-            uint64_t ql[kSlots];
-            uint64_t todo = 0ull;
-#pragma unroll
-            for (int q = 0; q < kSlots; ++q) {
-                ql[q] = ((live >> qof[q]) & 1u) ? qb[q] : 0ull;
-                todo |= ql[q];
-            }
-            todo &= 0xffffull << chunk;
-            while (todo) {
-                const int j = (int)__builtin_ctzll(todo);
-                todo &= todo - 1ull;
-                const float4 a = s_a[j], b = s_b[j];
-                const float cb_ = s_c[j].x;
-                const bool cut = (cutb >> j) & 1ull;
-                const uint32_t k1 = kofs + (uint32_t)j;
-                const float dxa = lpx[0] - a.x, dya = lpy[0] - a.y;
-                const float dxb = lpx[kSlots - 1] - a.x, dyb = lpy[kSlots - 1] - a.y;
-#pragma unroll
-                for (int q = 0; q < kSlots; ++q) {
-                    if (kSlots == 1 || ((ql[q] >> j) & 1ull)) {
-                        const bool xb = kSlots == 4 ? (q & 1) : false;
-                        const bool yb = kSlots == 4 ? (q >> 1) : false;
-                        const float dx = xb ? dxb : dxa;
-                        const float dy = yb ? dyb : dya;
-                        const float pw = entry_power(a, b, dx, dy);
-                        float w = 1.0f;
-                        if (cut) w = chord_weight(s_cut[j], dx, dy, p.ax, p.ay);
-                        composite(pw, b.y, w, b.z, b.w, cb_, k1, T[q], thr[q], C0[q], C1[q], C2[q], last[q],
-                                  walked[q]);
-                    }
+        for (uint32_t sub = 0; sub < cnt && live; sub += 64) {
+            const uint32_t lm = __float_as_uint(s_c[sub + lane].y);
+            const uint64_t qb = __ballot((lm >> (8 + wave)) & 1u);
+            const uint64_t cutb = __ballot(plane_on && (lm & 0xffu) == RARA_LABEL_CUTOFF);
+            for (int chunk = 0; chunk < 64; chunk += 16) {
+                uint64_t todo = qb & (0xffffull << chunk);
+                while (todo) {
+                    const int j = (int)__builtin_ctzll(todo);
+                    todo &= todo - 1ull;
+                    const uint32_t e = sub + (uint32_t)j;
+                    const float4 a = s_a[e], b = s_b[e];
+                    const float cb_ = s_c[e].x;
+                    const float dx = lpx - a.x, dy = lpy - a.y;
+                    const float pw = entry_power(a, b, dx, dy);
+                    float w = 1.0f;
+                    if ((cutb >> j) & 1ull) w = chord_weight(s_cut[e], dx, dy, p.ax, p.ay);
+                    composite(pw, b.y, w, b.z, b.w, cb_, kofs + e, T, thr, C0, C1, C2, last, walked);
                 }
+                live = __ballot(thr < 1.0f) != 0ull;
+                if (!live) break;
             }
-            live = live_quads();
-            if (!live) break;
         }
     }
 
+    if (!inside) return;
     const int64_t HW = (int64_t)p.H * p.W;
-#pragma unroll
-    for (int q = 0; q < kSlots; ++q) {
-        const int px = tx * kTile + (int)lpx[q], py = ty * kTile + (int)lpy[q];
-        if (px >= p.W || py >= p.H) continue;
-        const int64_t pix = (int64_t)py * p.W + px;
-        image[pix] = C0[q] + T[q] * p.bg[0];
-        image[HW + pix] = C1[q] + T[q] * p.bg[1];
-        image[2 * HW + pix] = C2[q] + T[q] * p.bg[2];
-        final_T[pix] = T[q];
-        n_contrib[pix] = last[q];
-        // a pixel still live at the end examined the whole list
-        if (kWalked) n_walked[pix] = thr[q] < 1.0f ? rg.y - rg.x : walked[q];
-    }
+    const int64_t pix = (int64_t)py * p.W + px;
+    image[pix] = C0 + T * p.bg[0];
+    image[HW + pix] = C1 + T * p.bg[1];
+    image[2 * HW + pix] = C2 + T * p.bg[2];
+    final_T[pix] = T;
+    n_contrib[pix] = last;
+    // a pixel still live at the end examined the whole list
+    if (kWalked) n_walked[pix] = thr < 1.0f ? rg.y - rg.x : walked;
 }
 
-// One wave per work unit (see unit_of_block for the schedule).
 template <bool kWalked>
 __device__ __forceinline__ void blend_block(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
                                             const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
@@ -214,28 +156,26 @@ __device__ __forceinline__ void blend_block(const Splat* __restrict__ splats, co
                                             float* __restrict__ image, float* __restrict__ final_T,
                                             uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
 {
-    uint32_t unit;
-    if (!unit_of_block(blockIdx.x, work, p.num_tiles, unit)) return;
-    const int tile = (int)(unit >> 3), mode = (int)(unit & 7u);
-    if (tile >= p.num_tiles || mode > 4) return;
-    __shared__ float4 s_a[kBatch], s_b[kBatch], s_c[kBatch];
-    __shared__ CutRec s_cut[kBatch];
-    const uint2 rg = ranges[tile];
-    if (mode == 4)
-        blend_unit<4, kWalked>(splats, rays, vals, rg, tile, 0, p, s_a, s_b, s_c, s_cut, image, final_T, n_contrib,
-                               n_walked);
-    else
-        blend_unit<1, kWalked>(splats, rays, vals, rg, tile, mode, p, s_a, s_b, s_c, s_cut, image, final_T, n_contrib,
-                               n_walked);
+    uint32_t tile;
+    if (!tile_of_block(blockIdx.x, work, p.num_tiles, tile)) return;
+    if (tile >= (uint32_t)p.num_tiles) return;
+    __shared__ float4 s_a[kTileBatch], s_b[kTileBatch];
+    __shared__ float2 s_c[kTileBatch];
+    __shared__ CutRec s_cut[kTileBatch];
+    blend_tile<kWalked>(splats, rays, vals, ranges[tile], (int)tile, p, s_a, s_b, s_c, s_cut, image, final_T,
+                        n_contrib, n_walked);
 }
 
 template <bool kWalked>
-__global__ __launch_bounds__(64) void blend_kernel(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
-                                                   const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
-                                                   const uint32_t* __restrict__ work,
-                                                   const int32_t* __restrict__ overflow, RenderParams p,
-                                                   float* __restrict__ image, float* __restrict__ final_T,
-                                                   uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
+__global__ __launch_bounds__(kTileBatch) void blend_kernel(const Splat* __restrict__ splats,
+                                                           const RayRec* __restrict__ rays,
+                                                           const uint32_t* __restrict__ vals,
+                                                           const uint2* __restrict__ ranges,
+                                                           const uint32_t* __restrict__ work,
+                                                           const int32_t* __restrict__ overflow, RenderParams p,
+                                                           float* __restrict__ image, float* __restrict__ final_T,
+                                                           uint32_t* __restrict__ n_contrib,
+                                                           uint32_t* __restrict__ n_walked)
 {
     if (*overflow) return;
     blend_block<kWalked>(splats, rays, vals, ranges, work, p, image, final_T, n_contrib, n_walked);
@@ -243,15 +183,16 @@ __global__ __launch_bounds__(64) void blend_kernel(const Splat* __restrict__ spl
 
 // Frame-graph variant: render parameters read from device memory.
 template <bool kWalked>
-__global__ __launch_bounds__(64) void blend_fp_kernel(const Splat* __restrict__ splats,
-                                                      const RayRec* __restrict__ rays,
-                                                      const uint32_t* __restrict__ vals,
-                                                      const uint2* __restrict__ ranges,
-                                                      const uint32_t* __restrict__ work,
-                                                      const int32_t* __restrict__ overflow,
-                                                      const FrameParams* __restrict__ fp, float* __restrict__ image,
-                                                      float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
-                                                      uint32_t* __restrict__ n_walked)
+__global__ __launch_bounds__(kTileBatch) void blend_fp_kernel(const Splat* __restrict__ splats,
+                                                              const RayRec* __restrict__ rays,
+                                                              const uint32_t* __restrict__ vals,
+                                                              const uint2* __restrict__ ranges,
+                                                              const uint32_t* __restrict__ work,
+                                                              const int32_t* __restrict__ overflow,
+                                                              const FrameParams* __restrict__ fp,
+                                                              float* __restrict__ image, float* __restrict__ final_T,
+                                                              uint32_t* __restrict__ n_contrib,
+                                                              uint32_t* __restrict__ n_walked)
 {
     if (*overflow) return;
     const RenderParams p = fp->render;
@@ -263,13 +204,13 @@ __global__ __launch_bounds__(64) void blend_fp_kernel(const Splat* __restrict__ 
 hipError_t launch_blend(const Splat* splat, const RayRec* ray, const rara_binned& bins, const RenderParams& p,
                         float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked, hipStream_t s)
 {
-    const unsigned grid = (unsigned)work_grid(p.num_tiles);
+    const unsigned grid = (unsigned)tiles_grid(p.num_tiles);
     if (n_walked)
-        hipLaunchKernelGGL(blend_kernel<true>, dim3(grid), dim3(64), 0, s, splat, ray, bins.vals,
+        hipLaunchKernelGGL(blend_kernel<true>, dim3(grid), dim3(kTileBatch), 0, s, splat, ray, bins.vals,
                            reinterpret_cast<const uint2*>(bins.ranges), bins.work, bins.overflow, p, image, final_T,
                            n_contrib, n_walked);
     else
-        hipLaunchKernelGGL(blend_kernel<false>, dim3(grid), dim3(64), 0, s, splat, ray, bins.vals,
+        hipLaunchKernelGGL(blend_kernel<false>, dim3(grid), dim3(kTileBatch), 0, s, splat, ray, bins.vals,
                            reinterpret_cast<const uint2*>(bins.ranges), bins.work, bins.overflow, p, image, final_T,
                            n_contrib, n_walked);
     return hipGetLastError();
@@ -279,13 +220,13 @@ hipError_t launch_blend_fp(const Splat* splat, const RayRec* ray, const rara_bin
                            int num_tiles, float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked,
                            hipStream_t s)
 {
-    const unsigned grid = (unsigned)work_grid(num_tiles);
+    const unsigned grid = (unsigned)tiles_grid(num_tiles);
     const uint2* ranges = reinterpret_cast<const uint2*>(bins.ranges);
     if (n_walked)
-        hipLaunchKernelGGL(blend_fp_kernel<true>, dim3(grid), dim3(64), 0, s, splat, ray, bins.vals, ranges, bins.work,
+        hipLaunchKernelGGL(blend_fp_kernel<true>, dim3(grid), dim3(kTileBatch), 0, s, splat, ray, bins.vals, ranges, bins.work,
                            bins.overflow, fp, image, final_T, n_contrib, n_walked);
     else
-        hipLaunchKernelGGL(blend_fp_kernel<false>, dim3(grid), dim3(64), 0, s, splat, ray, bins.vals, ranges,
+        hipLaunchKernelGGL(blend_fp_kernel<false>, dim3(grid), dim3(kTileBatch), 0, s, splat, ray, bins.vals, ranges,
                            bins.work, bins.overflow, fp, image, final_T, n_contrib, n_walked);
     return hipGetLastError();
 }

@@ -174,4 +174,24 @@ __device__ inline bool unit_of_block(uint32_t b, const uint32_t* __restrict__ wo
     return true;
 }
 
+// Tile of forward workgroup b.  The tile order is the one the work list
+// encodes: the H split (long-list) tiles first, then the others, each group
+// in tile order.  Every XCD (b mod 8) takes one contiguous run of each group,
+// so the long lists start first and neighbouring tiles, which share splats,
+// stay on one L2.  tiles_grid(T) workgroups cover both groups.
+__device__ inline bool tile_of_block(uint32_t b, const uint32_t* __restrict__ work, int num_tiles, uint32_t& tile)
+{
+    const uint32_t H = work[4 * num_tiles];
+    const uint32_t hb = (H + 7u) & ~7u;
+    const bool heavy = b < hb;
+    const uint32_t bb = heavy ? b : b - hb;   // hb is a multiple of 8: bb and b share an XCD
+    const uint32_t cnt = heavy ? H : (uint32_t)num_tiles - H;
+    const uint32_t x = bb & 7u, k = bb >> 3;
+    const uint32_t q8 = cnt >> 3, r8 = cnt & 7u;
+    if (k >= q8 + (x < r8 ? 1u : 0u)) return false;
+    const uint32_t i = x * q8 + (x < r8 ? x : r8) + k;
+    tile = (heavy ? work[4 * i] : work[4 * H + i]) >> 3;
+    return true;
+}
+
 }  // namespace rara

@@ -99,6 +99,8 @@ struct FrameParams {
 constexpr uint32_t kHeavyList = 1536;
 constexpr int kMaxHeavy = 2048;
 inline int64_t work_grid(int64_t tiles) { return tiles + 3 * (tiles < kMaxHeavy ? tiles : kMaxHeavy) + 64; }
+// forward blend: one workgroup per tile, both tile groups padded to 8
+inline int64_t tiles_grid(int64_t tiles) { return tiles + 16; }
 
 // ---- bin/sort workspace carve-up -------------------------------------------
 constexpr int kScanBlock = 256;      // Gaussians per scan chunk

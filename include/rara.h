@@ -78,7 +78,30 @@ typedef struct {
 } rara_camera;
 
 /* Clipping plane of eq. (3): n.x + d = 0, the half-space n points into is
- * visible.  enabled = 0 renders without clipping (every label VISIBLE). */
+ * visible.  `enabled` is the clip mode:
+ *   RARA_CLIP_OFF   0  no clipping (every label VISIBLE);
+ *   RARA_CLIP_RARA  1  the paper's method: three-way labels of Sec. 3.2 with
+ *                      r = 3 max(sigma), CUTOFF Gaussians weighted by eq. (11);
+ *   RARA_CLIP_HARD  2  hard clipping, the baseline of Sec. 1 and Table 1: a
+ *                      Gaussian is kept whole when its centre is on the
+ *                      visible side (n.mu + d >= 0) and dropped otherwise;
+ * and, only together with RARA_CLIP_RARA, the flags
+ *   RARA_CLIP_TIGHT        4  r = 3 |S R^T n|, the exact half-width of the
+ *                             3-sigma ellipsoid along the normal (Sec. 3.2
+ *                             notes that 3 max(sigma) over-estimates it);
+ *   RARA_CLIP_STRICT_MISS  8  a pixel ray that misses a CUTOFF Gaussian's
+ *                             ellipsoid gets w = 1 only when its point closest
+ *                             to the centre (whitened metric) is visible, else
+ *                             0, instead of w = 1 (the sub-pixel case of the
+ *                             paper's closing discussion).
+ * Any other value is RARA_ERR_INVALID. */
+enum {
+    RARA_CLIP_OFF = 0,
+    RARA_CLIP_RARA = 1,
+    RARA_CLIP_HARD = 2,
+    RARA_CLIP_TIGHT = 4,
+    RARA_CLIP_STRICT_MISS = 8
+};
 typedef struct {
     float n[3];
     float d;

@@ -45,12 +45,12 @@ def lib():
             from . import build as _b
             _b.build()
         L = ctypes.CDLL(_SO)
-        L.oracle_classify.argtypes = [_I64, _P, _P, _P, _I32, _P, _P, _P]
+        L.oracle_classify.argtypes = [_I64, _P, _P, _P, _P, _I32, _P, _P, _P]
         L.oracle_classify.restype = _I32
         L.oracle_project.argtypes = [_I64, _I32, _P, _P, _P, _P, _P, _I32, _I32, _D, _P, _I32,
                                      _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
         L.oracle_project.restype = None
-        L.oracle_weight.argtypes = [_P, _P, _P, _P, _P, _D, _D, _P]
+        L.oracle_weight.argtypes = [_P, _P, _P, _P, _P, _D, _D, _I32, _P]
         L.oracle_weight.restype = _D
         L.oracle_lists.argtypes = [_I64, _P, _P, _P, _I32, _I32, _P, _P]
         L.oracle_lists.restype = _I64
@@ -82,6 +82,17 @@ def camera_centre(cam) -> np.ndarray:
 
 # ------------------------------------------------------------- primitives ----
 
+# clip modes (the plane's ``enabled`` value): rule in the low two bits
+CLIP_OFF, CLIP_RARA, CLIP_HARD = 0, 1, 2
+CLIP_TIGHT = 4          # RaRa with the exact 3-sigma half-width along the normal
+CLIP_STRICT_MISS = 8    # RaRa with the strict miss policy of oracle_weight
+
+
+def clip_mode(plane) -> int:
+    """Clip mode of a plane: False/True map to off/RaRa, ints pass through."""
+    return int(plane.enabled)
+
+
 def classify(scene, plane):
     """Sec. 3.2 labels (uint8 [n]), signed distances d_ep and radii 3 max(sigma)."""
     n = scene.n
@@ -89,10 +100,10 @@ def classify(scene, plane):
     dep = np.empty(n, np.float64)
     rad = np.empty(n, np.float64)
     pa = plane.as_array()
-    ok = lib().oracle_classify(n, _p(scene.mean), _p(scene.scale), _p(pa), int(bool(plane.enabled)),
+    ok = lib().oracle_classify(n, _p(scene.mean), _p(scene.scale), _p(scene.quat), _p(pa), clip_mode(plane),
                                _p(label), _p(dep), _p(rad))
     if not ok:
-        raise ValueError("plane normal has zero length")
+        raise ValueError("plane normal has zero length, or an invalid clip mode")
     return label, dep, rad
 
 
@@ -147,9 +158,10 @@ def sh_basis(degree: int, direction) -> np.ndarray:
     return Y[: (degree + 1) ** 2]
 
 
-def weight(e, v, mu, quat, scale, plane_n, plane_d, kappa: float = KAPPA):
+def weight(e, v, mu, quat, scale, plane_n, plane_d, kappa: float = KAPPA, strict_miss: bool = False):
     """Eq. (11) decay weight of one ray r(t) = e + t v (v normalised) and one
-    Gaussian; returns (w, info) with info = (disc/4A, t1, t2, t_p)."""
+    Gaussian; returns (w, info) with info = (disc/4A, t1, t2, t_p).
+    strict_miss: a missing ray gets w = [plane value at its closest approach >= 0]."""
     nn = np.asarray(plane_n, np.float64)
     L = float(np.linalg.norm(nn))
     nn = np.ascontiguousarray(nn / L)
@@ -160,7 +172,7 @@ def weight(e, v, mu, quat, scale, plane_n, plane_d, kappa: float = KAPPA):
     mu = np.ascontiguousarray(mu, np.float64)
     mi = np.ascontiguousarray(minv(quat, scale).reshape(-1))
     info = np.zeros(4)
-    w = lib().oracle_weight(_p(e), _p(v), _p(mu), _p(mi), _p(nn), d, float(kappa), _p(info))
+    w = lib().oracle_weight(_p(e), _p(v), _p(mu), _p(mi), _p(nn), d, float(kappa), int(strict_miss), _p(info))
     return w, info
 
 
@@ -186,7 +198,7 @@ def render(scene, cam, plane, bg=(0.0, 0.0, 0.0), kappa: float = KAPPA, trace_vi
     bgv = np.asarray(bg, np.float32)
     lib().oracle_composite(scene.n, _p(label), _p(proj["mean2d"]), _p(proj["conic"]), _p(scene.opacity),
                            _p(proj["rgb"]), _p(scene.mean), _p(proj["minv"]), _p(plane.as_array()),
-                           int(bool(plane.enabled)), _p(cam_array(cam)), W, H, _p(bgv), _p(offsets), _p(ids),
+                           clip_mode(plane), _p(cam_array(cam)), W, H, _p(bgv), _p(offsets), _p(ids),
                            float(kappa), int(trace_visible), int(t0), int(t1), float(tau_sil), _p(image),
                            _p(final_T), _p(n_contrib), _p(n_walked), _p(flags), _p(counters))
     out = dict(label=label, d_ep=dep, radius3=rad, proj=proj, offsets=offsets, ids=ids, image=image,
@@ -203,7 +215,10 @@ def boundary_events(scene, cam, plane, label, dep, rad, tol: float = 1e-6) -> di
     with their tile rectangles."""
     n = scene.n
     lab_b = np.zeros(n, bool)
-    if plane.enabled:
+    mode = clip_mode(plane)
+    if mode & 3 == 2:
+        lab_b = np.abs(dep) <= tol
+    elif mode & 3:
         lab_b = (np.abs(dep - rad) <= tol) | (np.abs(dep + rad) <= tol)
     allp = project(scene, cam, label, project_all=True)
     r3 = 3.0 * np.sqrt(np.maximum(allp["lam_max"], 0.0))

@@ -119,23 +119,45 @@ void oracle_sh_basis(int deg, double x, double y, double z, double* Y) { sh_basi
 /*
  * Sec. 3.2 / Algorithm 1 step 1.  d_ep = n.mu + d, r = 3 max(sigma):
  *   INVISIBLE if d_ep < -r, VISIBLE if d_ep > r, CUTOFF if |d_ep| <= r.
- * With the plane disabled every Gaussian is VISIBLE.
- * mean, scale: [3][n].  Returns 0 on an invalid plane.
+ * mode & 3 selects the rule: 0 no plane (every Gaussian VISIBLE), 1 the
+ * three-way RaRa labels above, 2 hard clipping (the baseline of Sec. 1 and
+ * Table 1: a Gaussian is kept whole, VISIBLE, when its centre is on the
+ * visible side, d_ep >= 0, and dropped, INVISIBLE, otherwise).  mode & 4
+ * (with rule 1) replaces r by the exact half-width of the 3-sigma ellipsoid
+ * along the normal, r = 3 |S R^T n| (the support function of the ellipsoid;
+ * the paper notes 3 max(sigma) over-estimates it).
+ * mean, scale: [3][n], quat: [4][n] (w, x, y, z; only read with mode & 4).
+ * Returns 0 on an invalid plane or mode.
  */
-int oracle_classify(int64_t n, const float* mean, const float* scale, const float* plane, int enabled,
-                    uint8_t* label, double* d_ep, double* radius)
+int oracle_classify(int64_t n, const float* mean, const float* scale, const float* quat, const float* plane,
+                    int mode, uint8_t* label, double* d_ep, double* radius)
 {
+    const int rule = mode & 3;
+    const int tight = (mode & 4) != 0;
     double nn[3], d;
-    if (enabled && !normalise_plane(plane, nn, &d)) return 0;
+    if (rule == 3 || (tight && (rule != 1 || !quat))) return 0;
+    if (rule && !normalise_plane(plane, nn, &d)) return 0;
     for (int64_t i = 0; i < n; i++) {
         double mu[3] = {mean[i], mean[n + i], mean[2 * n + i]};
-        double s = fmax(fmax((double)scale[i], (double)scale[n + i]), (double)scale[2 * n + i]);
-        double r = 3.0 * s;
-        double dist = enabled ? dot3(nn, mu) + d : INFINITY;
+        double sig[3] = {scale[i], scale[n + i], scale[2 * n + i]};
+        double r = 3.0 * fmax(fmax(sig[0], sig[1]), sig[2]);
+        if (tight) {
+            double R[9];
+            quat_to_rot(quat[i], quat[n + i], quat[2 * n + i], quat[3 * n + i], R);
+            /* (S R^T n)_a = sigma_a (column a of R) . n */
+            double q2 = 0.0;
+            for (int a = 0; a < 3; a++) {
+                double c = sig[a] * (R[a] * nn[0] + R[3 + a] * nn[1] + R[6 + a] * nn[2]);
+                q2 += c * c;
+            }
+            r = 3.0 * sqrt(q2);
+        }
+        double dist = rule ? dot3(nn, mu) + d : INFINITY;
         if (d_ep) d_ep[i] = dist;
         if (radius) radius[i] = r;
-        if (!enabled) { label[i] = OR_VISIBLE; continue; }
-        if (dist < -r) label[i] = OR_INVISIBLE;
+        if (rule == 0) label[i] = OR_VISIBLE;
+        else if (rule == 2) label[i] = dist < 0 ? OR_INVISIBLE : OR_VISIBLE;
+        else if (dist < -r) label[i] = OR_INVISIBLE;
         else if (dist > r) label[i] = OR_VISIBLE;
         else label[i] = OR_CUTOFF;
     }
@@ -270,11 +292,17 @@ void oracle_project(int64_t n, int sh_degree, const float* mean, const float* sc
  *   t_p = -(n.e + d) / (n.v)                               (eq. 8)
  *   w = L_vis / (t2 - t1) if two intersections with t >= 0 exist, else 1 (eq. 11)
  * with L_vis the length of {t in [t1, t2] : n.(e + t v) + d >= 0}.
+ * strict_miss: a ray that misses the ellipsoid (no real roots) gets
+ * w = [n.(e + t* v) + d >= 0] instead of 1, t* = -B / 2A the point of the
+ * ray closest to the centre in the whitened metric (the sub-pixel variant of
+ * the paper's closing discussion); tangent rays and rays with a root behind
+ * the camera keep w = 1.
  * info (optional, 4 doubles): disc/(4A) (the squared distance margin
- * kappa^2 - |closest whitened point|^2), t1, t2, t_p.
+ * kappa^2 - |closest whitened point|^2), t1, t2, t_p; for a strict miss,
+ * info[3] is the plane value at the closest approach instead.
  */
 double oracle_weight(const double* e, const double* v, const double* mu, const double* minv, const double* nrm,
-                     double d, double kappa, double* info)
+                     double d, double kappa, int strict_miss, double* info)
 {
     double em[3] = {e[0] - mu[0], e[1] - mu[1], e[2] - mu[2]};
     double et[3], vt[3];
@@ -289,7 +317,15 @@ double oracle_weight(const double* e, const double* v, const double* mu, const d
     double nv = dot3(nrm, v);
     double phi_e = dot3(nrm, e) + d;
     if (info) { info[0] = disc / (4.0 * A); info[1] = info[2] = info[3] = NAN; }
-    if (!(disc > 0)) return 1.0;              /* miss or tangent: keep rasterised alpha */
+    if (!(disc > 0)) {                       /* miss or tangent: keep rasterised alpha */
+        if (strict_miss && disc < 0) {
+            double ts = -B / (2.0 * A);
+            double phis = phi_e + ts * nv;
+            if (info) info[3] = phis;
+            return phis >= 0 ? 1.0 : 0.0;
+        }
+        return 1.0;
+    }
     double sq = sqrt(disc);
     double t1 = (-B - sq) / (2.0 * A);
     double t2 = (-B + sq) / (2.0 * A);
@@ -379,6 +415,8 @@ int64_t oracle_lists(int64_t n, const uint8_t* drawn, const int32_t* rect, const
  *   T (1 - alpha) < 1e-4; C += alpha T c; T *= 1 - alpha.
  * The ray of pixel (i, j) starts at the camera centre with direction
  * R_c^T ((i - cx)/fx, (j - cy)/fy, 1), normalised.
+ * plane_enabled is the clip mode of oracle_classify (0: no plane); with
+ * mode & 8 the weight uses the strict miss policy of oracle_weight.
  * Outputs: image [3][H][W] = C + T bg, final_T, n_contrib (1-based index of
  * the last composited entry), n_walked (entries examined), flags (event bits).
  * counters: [0] entries examined, [1] CUTOFF entries examined, [2] composited,
@@ -398,6 +436,7 @@ void oracle_composite(int64_t n, const uint8_t* label, const double* mean2d, con
     double fx = cam[12], fy = cam[13], cx = cam[14], cy = cam[15];
     camera_centre(Rc, tc, e);
     if (plane_enabled) normalise_plane(plane, nn, &d);
+    const int strict = (plane_enabled & 8) != 0;   /* strict miss policy, see oracle_weight */
     int tiles_x = (W + OR_TILE - 1) / OR_TILE;
     int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0, c7 = 0;
 
@@ -430,9 +469,11 @@ void oracle_composite(int64_t n, const uint8_t* label, const double* mean2d, con
                     if (traced && plane_enabled) {
                         double mu[3] = {mean[g], mean[n + g], mean[2 * n + g]};
                         double info[4];
-                        w = oracle_weight(e, v, mu, minv + 9 * (int64_t)g, nn, d, kappa, info);
+                        w = oracle_weight(e, v, mu, minv + 9 * (int64_t)g, nn, d, kappa, strict, info);
                         if (a0 >= OR_ALPHA_MIN * (1 - 1e-3)) {
                             if (fabs(info[0]) <= tau_sil * kappa * kappa) { fl |= OR_EV_SILHOUETTE; c3++; }
+                            /* strict miss: the weight steps where the closest approach crosses the plane */
+                            if (strict && info[0] < 0 && fabs(info[3]) <= 1e-5) { fl |= OR_EV_SILHOUETTE; c3++; }
                             if (info[1] == info[1] && info[1] < 0 && info[2] > 0) {
                                 c4++;
                                 if (fabs(info[1]) <= 1e-3 * (info[2] - info[1])) fl |= OR_EV_INSIDE;

@@ -12,6 +12,8 @@ LIB_PATH = os.path.join(HERE, "librara.so")
 RARA_OK, RARA_ERR_INVALID, RARA_ERR_CAPACITY, RARA_ERR_HIP, RARA_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
 RARA_WS_BIN_SORT, RARA_WS_BACKWARD = 0, 1
 LABEL_INVISIBLE, LABEL_VISIBLE, LABEL_CUTOFF = 0, 1, 2
+# clip modes (rara_plane.enabled): a rule, plus flags that go with RARA_CLIP_RARA
+RARA_CLIP_OFF, RARA_CLIP_RARA, RARA_CLIP_HARD, RARA_CLIP_TIGHT, RARA_CLIP_STRICT_MISS = 0, 1, 2, 4, 8
 SPLAT_BYTES = 48
 RAY_BYTES = 48
 
@@ -117,7 +119,7 @@ def make_plane(plane) -> Plane:
     p = Plane()
     p.n = (ctypes.c_float * 3)(*[float(v) for v in plane.n])
     p.d = float(plane.d)
-    p.enabled = 1 if plane.enabled else 0
+    p.enabled = int(plane.enabled)   # clip mode: False/True -> off/RaRa, ints pass through
     return p
 
 

@@ -36,7 +36,10 @@ bool make_cam(const rara_camera* c, CamParams* p)
 bool make_plane(const rara_plane* pl, PlaneParams* p)
 {
     if (!pl) return false;
-    p->enabled = pl->enabled ? 1 : 0;
+    const int mode = pl->enabled, rule = mode & 3, flags = mode & ~3;
+    if (rule == 3 || (flags & ~(RARA_CLIP_TIGHT | RARA_CLIP_STRICT_MISS)) || (flags && rule != RARA_CLIP_RARA))
+        return false;
+    p->enabled = mode;
     p->n[0] = p->n[1] = p->n[2] = 0.0;
     p->d = 0.0;
     if (!p->enabled) return true;

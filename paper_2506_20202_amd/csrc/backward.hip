@@ -207,7 +207,7 @@ __device__ inline void blend_back_unit(const Splat* __restrict__ splats, const R
                     Chord ch;
                     float w = 1.0f;
                     if (cut) {
-                        chord_eval(cr, dx, dy, p.ax, p.ay, ch);
+                        chord_eval(cr, dx, dy, p.ax, p.ay, (p.plane_enabled & RARA_CLIP_STRICT_MISS) != 0, ch);
                         w = ch.w;
                     }
                     const float aw = a0 * w;

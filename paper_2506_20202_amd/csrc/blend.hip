@@ -85,6 +85,7 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
 
     const double ox = (double)(tx * kTile), oy = (double)(ty * kTile);
     const bool plane_on = p.plane_enabled != 0;
+    const bool strict = (p.plane_enabled & RARA_CLIP_STRICT_MISS) != 0;
     bool live = __ballot(thr < 1.0f) != 0ull;
 
     for (uint32_t base = rg.x; base < rg.y; base += kTileBatch) {
@@ -128,7 +129,7 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
                     const float dx = lpx - a.x, dy = lpy - a.y;
                     const float pw = entry_power(a, b, dx, dy);
                     float w = 1.0f;
-                    if ((cutb >> j) & 1ull) w = chord_weight(s_cut[e], dx, dy, p.ax, p.ay);
+                    if ((cutb >> j) & 1ull) w = chord_weight(s_cut[e], dx, dy, p.ax, p.ay, strict);
                     composite(pw, b.y, w, b.z, b.w, cb_, kofs + e, T, thr, C0, C1, C2, last, walked);
                 }
                 live = __ballot(thr < 1.0f) != 0ull;

@@ -33,7 +33,9 @@ struct Chord {
     float w;
 };
 
-__device__ inline void chord_eval(const CutRec& k, float dx, float dy, float ax, float ay, Chord& c)
+// strict: a miss (h^2 < 0) gets w = [plane value at the closest approach >= 0]
+// (kind 5) instead of w = 1.
+__device__ inline void chord_eval(const CutRec& k, float dx, float dy, float ax, float ay, bool strict, Chord& c)
 {
     const float gx[3] = {k.a.w, k.b.x, k.b.y};
     const float gy[3] = {k.b.z, k.b.w, k.c.x};
@@ -54,7 +56,18 @@ __device__ inline void chord_eval(const CutRec& k, float dx, float dy, float ax,
     c.h2 = kKappa2 - fmaf(c.Q[0], c.Q[0], fmaf(c.Q[1], c.Q[1], c.Q[2] * c.Q[2]));
     c.hs = 0.0f;
     c.u = c.gg = c.phim = c.inv = 0.0f;
-    if (!(c.h2 > 0.0f)) { c.kind = 0; c.w = 1.0f; return; }   // fewer than two intersections
+    if (!(c.h2 > 0.0f)) {   // fewer than two intersections
+        c.kind = 0;
+        c.w = 1.0f;
+        if (strict && c.h2 < 0.0f) {
+            c.u = fmaf(ax, dx, ay * dy);
+            c.gg = g0 + c.u;
+            c.phim = fmaf(c.sm, c.gg, fmaf(z, c.u, dep));
+            c.kind = 5;
+            c.w = c.phim >= 0.0f ? 1.0f : 0.0f;
+        }
+        return;
+    }
     c.hs = __builtin_amdgcn_sqrtf(c.h2 * c.iDD);               // chord half-length in camera depth
     if ((z + c.sm) - c.hs < 0.0f) { c.kind = 1; c.w = 1.0f; return; }
     c.u = fmaf(ax, dx, ay * dy);
@@ -67,10 +80,10 @@ __device__ inline void chord_eval(const CutRec& k, float dx, float dy, float ax,
     c.w = __builtin_amdgcn_fmed3f(wr, 0.0f, 1.0f);
 }
 
-__device__ inline float chord_weight(const CutRec& k, float dx, float dy, float ax, float ay)
+__device__ inline float chord_weight(const CutRec& k, float dx, float dy, float ax, float ay, bool strict)
 {
     Chord c;
-    chord_eval(k, dx, dy, ax, ay, c);
+    chord_eval(k, dx, dy, ax, ay, strict, c);
     return c.w;
 }
 

@@ -52,13 +52,31 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
     const double mu[3] = {g.mean[i], g.mean[n + i], g.mean[2 * n + i]};
     const double s[3] = {g.scale[i], g.scale[n + i], g.scale[2 * n + i]};
 
-    // Sec. 3.2: d_ep = n.mu + d, r = 3 max(sigma).
+    // Sec. 3.2: d_ep = n.mu + d, r = 3 max(sigma); hard clipping keeps a
+    // Gaussian by its centre's side; the tight variant takes r = 3 |S R^T n|.
     uint8_t label = RARA_LABEL_VISIBLE;
     double dep = 0.0;
     if (pl.enabled) {
-        const double r = 3.0 * fmax(fmax(s[0], s[1]), s[2]);
         dep = pl.n[0] * mu[0] + pl.n[1] * mu[1] + pl.n[2] * mu[2] + pl.d;
-        label = dep < -r ? RARA_LABEL_INVISIBLE : (dep > r ? RARA_LABEL_VISIBLE : RARA_LABEL_CUTOFF);
+        if ((pl.enabled & 3) == RARA_CLIP_HARD) {
+            label = dep < 0.0 ? RARA_LABEL_INVISIBLE : RARA_LABEL_VISIBLE;
+        } else {
+            double r = 3.0 * fmax(fmax(s[0], s[1]), s[2]);
+            if (pl.enabled & RARA_CLIP_TIGHT) {
+                double qw = g.quat[i], qx = g.quat[n + i], qy = g.quat[2 * n + i], qz = g.quat[3 * n + i];
+                const double ql = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+                qw /= ql; qx /= ql; qy /= ql; qz /= ql;
+                // (S R^T n)_a = sigma_a (column a of R) . n
+                const double c0 = s[0] * ((1 - 2 * (qy * qy + qz * qz)) * pl.n[0] + 2 * (qx * qy + qw * qz) * pl.n[1] +
+                                          2 * (qx * qz - qw * qy) * pl.n[2]);
+                const double c1 = s[1] * (2 * (qx * qy - qw * qz) * pl.n[0] + (1 - 2 * (qx * qx + qz * qz)) * pl.n[1] +
+                                          2 * (qy * qz + qw * qx) * pl.n[2]);
+                const double c2 = s[2] * (2 * (qx * qz + qw * qy) * pl.n[0] + 2 * (qy * qz - qw * qx) * pl.n[1] +
+                                          (1 - 2 * (qx * qx + qy * qy)) * pl.n[2]);
+                r = 3.0 * sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+            }
+            label = dep < -r ? RARA_LABEL_INVISIBLE : (dep > r ? RARA_LABEL_VISIBLE : RARA_LABEL_CUTOFF);
+        }
     }
     out.label[i] = label;
     uint32_t touched = 0;

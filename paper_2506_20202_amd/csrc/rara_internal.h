@@ -52,7 +52,7 @@ struct CamParams {
 struct PlaneParams {
     double n[3];
     double d;
-    int enabled;
+    int enabled;   // clip mode (RARA_CLIP_*), 0 when off
 };
 
 struct GaussPtrs {
@@ -76,7 +76,7 @@ struct ProjPtrs {
 
 struct RenderParams {
     int W, H, tiles_x, tiles_y, num_tiles;
-    int plane_enabled;
+    int plane_enabled;   // clip mode (RARA_CLIP_*)
     float ax, ay;
     float bg[3];
 };

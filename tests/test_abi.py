@@ -129,6 +129,31 @@ def test_argument_validation_before_any_launch(B):
                            None, None, None, None) == B.RARA_ERR_INVALID
 
 
+def test_clip_modes_agree_and_invalid_modes_are_rejected(B):
+    """rara_plane.enabled values: the header, the binding and the oracle agree;
+    rule 3 and flags without the RaRa rule are RARA_ERR_INVALID (checked on the
+    host before any launch)."""
+    hdr = open(os.path.join(ROOT, "include", "rara.h")).read()
+    import oracle
+    for name, ov in [("RARA_CLIP_OFF", oracle.CLIP_OFF), ("RARA_CLIP_RARA", oracle.CLIP_RARA),
+                     ("RARA_CLIP_HARD", oracle.CLIP_HARD), ("RARA_CLIP_TIGHT", oracle.CLIP_TIGHT),
+                     ("RARA_CLIP_STRICT_MISS", oracle.CLIP_STRICT_MISS)]:
+        hv = int(re.search(name + r" = (\d+)", hdr).group(1))
+        assert hv == getattr(B, name) == ov
+    lib = B.lib()
+    g = B.Gaussians()
+    g.n = 0
+    cam = _cam(B)
+    out = B.Projected()
+    for mode, ok in [(0, True), (1, True), (2, True), (5, True), (9, True), (13, True),
+                     (3, False), (6, False), (4, False), (8, False), (16, False), (-1, False)]:
+        pl = B.Plane()
+        pl.n[2] = 1.0
+        pl.enabled = mode
+        st = lib.rara_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(pl), ctypes.byref(out), None)
+        assert st == (B.RARA_OK if ok else B.RARA_ERR_INVALID), (mode, st)
+
+
 def test_constants_agree_between_oracle_and_kernels():
     """The oracle and the kernels are written separately; their conventions
     (thresholds, dilation, guard band, tile size, kappa) must agree."""

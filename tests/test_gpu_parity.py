@@ -193,3 +193,26 @@ def test_strand_scene_sampled():
     print(f"strands: P={g['P']} cutoff={(o['label'] == 2).sum()} boundary={len(o['boundary_ids'])} "
           f"mismatched={len(bad)} max_err={err:.2e} flagged={fl:.4f}", flush=True)
     assert err <= TOL
+
+
+CLIP_MODES = [("hard", oracle.CLIP_HARD), ("tight", oracle.CLIP_RARA | oracle.CLIP_TIGHT),
+              ("strict_miss", oracle.CLIP_RARA | oracle.CLIP_STRICT_MISS),
+              ("tight_strict", oracle.CLIP_RARA | oracle.CLIP_TIGHT | oracle.CLIP_STRICT_MISS)]
+
+
+@pytest.mark.parametrize("name,mode", CLIP_MODES)
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_clip_mode_parity(name, mode, seed):
+    """Hard clipping, tight classification and the strict miss policy: labels
+    and lists exact, images within the bar."""
+    pl = scenes.tiny_plane(seed)
+    _full_check(scenes.tiny_scene(seed), scenes.tiny_camera(), scenes.Plane(pl.n, pl.d, enabled=mode))
+
+
+@pytest.mark.parametrize("name,mode", CLIP_MODES)
+def test_clip_mode_parity_large_gaussians(name, mode):
+    sc = scenes.small_scene(1, n=24)
+    rng = np.random.default_rng(71)
+    n = rng.standard_normal(3)
+    pl = scenes.Plane((n / np.linalg.norm(n)).astype(np.float32), float(rng.uniform(-0.1, 0.1)), enabled=mode)
+    _full_check(sc, scenes.small_camera(96), pl)

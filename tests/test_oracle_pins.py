@@ -492,3 +492,129 @@ def test_rigid_motion_leaves_the_image_unchanged():
     # float32 re-rounding of inputs moves alpha by ~1e-6; label flips (<0.5%) are local
     assert np.median(err[ok]) < 1e-4
     assert (err[ok] < 1e-3).mean() > 0.97
+
+
+# ------------------------------------------------------- clip-mode variants ----
+
+def _mode_plane(pl, mode):
+    return scenes.Plane(pl.n, pl.d, enabled=mode)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_hard_clip_equals_plain_render_of_the_kept_gaussians(seed):
+    """Hard clipping (Sec. 1, Table 1 'Hard'): the render equals the unclipped
+    render of the Gaussians whose centre is on the visible side, bit for bit,
+    and away from the plane (|d_ep| > r) its labels are the RaRa labels."""
+    sc = scenes.tiny_scene(seed)
+    cam = scenes.tiny_camera()
+    pl = scenes.tiny_plane(seed)
+    hard = oracle.render(sc, cam, _mode_plane(pl, oracle.CLIP_HARD), bg=(0.1, 0.2, 0.3), events=False)
+    n = pl.n.astype(np.float64) / np.linalg.norm(pl.n)
+    d = float(pl.d) / float(np.linalg.norm(pl.n.astype(np.float64)))
+    side = n @ sc.mean.astype(np.float64) + d
+    keep = np.nonzero(side >= 0)[0]
+    assert 0 < keep.size < sc.n
+    plain = oracle.render(sc.subset(keep), cam, scenes.Plane(pl.n, pl.d, enabled=False), bg=(0.1, 0.2, 0.3),
+                          events=False)
+    np.testing.assert_array_equal(hard["image"], plain["image"])
+    assert (hard["label"] != oracle.CUTOFF).all()
+    rara, _, rad = oracle.classify(sc, pl)
+    far = np.abs(side) > rad
+    np.testing.assert_array_equal(hard["label"][far], rara[far])
+
+
+def test_tight_radius_closed_forms_and_support():
+    """f3: r = 3 |S R^T n| is the half-width of the 3-sigma ellipsoid along n:
+    3 sigma for isotropic Gaussians, 3 sigma_a when n is the a-th principal
+    axis, never above 3 max(sigma), and equal to the largest n.(x - mu) over
+    points sampled on the ellipsoid surface (brute force, scipy rotations)."""
+    rng = np.random.default_rng(11)
+    for _ in range(60):
+        q = rng.standard_normal(4)
+        s = np.exp(rng.normal(-2, 0.8, 3))
+        nrm = _rand_unit(rng)
+        one = scenes.Scene(mean=np.zeros((3, 1), np.float32), scale=s.reshape(3, 1).astype(np.float32),
+                           quat=q.reshape(4, 1).astype(np.float32), opacity=np.ones(1, np.float32),
+                           sh=np.zeros((1, 3, 1), np.float32), sh_degree=0)
+        pl = scenes.Plane(nrm.astype(np.float32), 0.0, enabled=oracle.CLIP_RARA | oracle.CLIP_TIGHT)
+        _, _, r = oracle.classify(one, pl)
+        qf = one.quat[:, 0].astype(np.float64)
+        sf = one.scale[:, 0].astype(np.float64)
+        nf = pl.n.astype(np.float64) / np.linalg.norm(pl.n.astype(np.float64))
+        R = Rotation.from_quat([qf[1], qf[2], qf[3], qf[0]]).as_matrix()
+        u = rng.standard_normal((3, 20000))
+        u /= np.linalg.norm(u, axis=0)
+        pts = R @ (3.0 * sf[:, None] * u)
+        brute = float((nf @ pts).max())
+        assert brute <= r[0] * (1 + 1e-12)
+        assert r[0] - brute <= 2e-3 * r[0]
+        assert r[0] <= 3.0 * sf.max() * (1 + 1e-12)
+    # isotropic and principal-axis closed forms
+    iso = scenes.Scene(mean=np.zeros((3, 1), np.float32), scale=np.full((3, 1), 0.05, np.float32),
+                       quat=np.array([[0.3], [0.5], [-0.2], [0.7]], np.float32), opacity=np.ones(1, np.float32),
+                       sh=np.zeros((1, 3, 1), np.float32), sh_degree=0)
+    _, _, r = oracle.classify(iso, scenes.Plane(np.array([0.2, -0.9, 0.4], np.float32), 0.0,
+                                                enabled=oracle.CLIP_RARA | oracle.CLIP_TIGHT))
+    assert abs(r[0] - 3 * np.float64(np.float32(0.05))) < 1e-12
+    ax = scenes.Scene(mean=np.zeros((3, 1), np.float32), scale=np.array([[0.01], [0.2], [0.03]], np.float32),
+                      quat=np.array([[1.0], [0.0], [0.0], [0.0]], np.float32), opacity=np.ones(1, np.float32),
+                      sh=np.zeros((1, 3, 1), np.float32), sh_degree=0)
+    for a in range(3):
+        e = np.zeros(3, np.float32)
+        e[a] = -1.0
+        _, _, r = oracle.classify(ax, scenes.Plane(e, 0.0, enabled=oracle.CLIP_RARA | oracle.CLIP_TIGHT))
+        assert abs(r[0] - 3 * np.float64(ax.scale[a, 0])) < 1e-15
+
+
+@pytest.mark.parametrize("seed", [1, 4])
+def test_tight_mode_equals_rara_without_the_miss_ring(seed):
+    """f3: the tight labels only turn CUTOFF Gaussians whose 3-sigma ellipsoid
+    lies wholly on one side into VISIBLE (their eq. (11) weight was exactly 1)
+    or INVISIBLE (weight 0 on hits, 1 on misses: the miss ring).  So the tight
+    render equals the RaRa render of the scene without the latter, exactly."""
+    sc = scenes.tiny_scene(seed)
+    cam = scenes.tiny_camera()
+    pl = scenes.tiny_plane(seed)
+    tight = oracle.render(sc, cam, _mode_plane(pl, oracle.CLIP_RARA | oracle.CLIP_TIGHT), events=False)
+    rara_lab = oracle.classify(sc, pl)[0]
+    gone = (rara_lab == oracle.CUTOFF) & (tight["label"] == oracle.INVISIBLE)
+    came = (rara_lab == oracle.CUTOFF) & (tight["label"] == oracle.VISIBLE)
+    assert gone.any() and came.any()
+    assert ((rara_lab != oracle.CUTOFF) <= (tight["label"] == rara_lab)).all()
+    ref = oracle.render(sc.subset(np.nonzero(~gone)[0]), cam, pl, events=False)
+    np.testing.assert_array_equal(tight["image"], ref["image"])
+
+
+def test_strict_miss_weight_uses_the_closest_approach_side():
+    """f2: a ray that misses an isotropic Gaussian gets w = 1 exactly when the
+    point of the ray closest to the centre (Euclidean, for isotropic sigma) is
+    on the visible side, else 0; rays that hit keep the eq. (11) weight."""
+    rng = np.random.default_rng(12)
+    for _ in range(300):
+        sigma = float(np.exp(rng.normal(-2, 0.5)))
+        mu = rng.uniform(-1, 1, 3)
+        v = _rand_unit(rng)
+        u = _perp(rng, v)
+        b = rng.uniform(1.05, 3.0) * 3 * sigma           # lateral offset: a miss
+        e = mu + b * u - v * rng.uniform(1.0, 3.0)
+        closest = e + float(np.dot(mu - e, v)) * v
+        n = _rand_unit(rng)
+        d = -float(np.dot(n, closest)) + rng.choice([-1, 1]) * rng.uniform(0.01, 0.5) * sigma
+        q = rng.standard_normal(4)
+        w_strict, info = oracle.weight(e, v, mu, q, [sigma] * 3, n, d, strict_miss=True)
+        w_plain, _ = oracle.weight(e, v, mu, q, [sigma] * 3, n, d)
+        assert info[0] < 0 and w_plain == 1.0
+        assert w_strict == (1.0 if np.dot(n, closest) + d >= 0 else 0.0)
+        # a hit through the same plane: strict and eq. (11) agree
+        eh = mu + 0.5 * sigma * u - v * 2.0
+        wh, ih = oracle.weight(eh, v, mu, q, [sigma] * 3, n, d, strict_miss=True)
+        wp, _ = oracle.weight(eh, v, mu, q, [sigma] * 3, n, d)
+        assert ih[0] > 0 and wh == wp
+
+
+def test_clip_mode_validation():
+    sc = scenes.tiny_scene(0)
+    pl = scenes.tiny_plane(0)
+    for bad in (3, oracle.CLIP_HARD | oracle.CLIP_TIGHT, oracle.CLIP_TIGHT):
+        with pytest.raises(ValueError):
+            oracle.classify(sc, _mode_plane(pl, bad))

@@ -42,8 +42,7 @@ PEAK_HBM = 8.0e12
 # counters read for a plain device copy of known size.  Reported only while
 # the blend's sources are the ones the counters were taken on.
 COUNTER_FILE = os.path.join(ROOT, "profiles", "blend_counters_general_1080p.txt")
-BLEND_SOURCES = ("paper_2506_20202_amd/csrc/blend.hip", "paper_2506_20202_amd/csrc/blend_common.h",
-                 "paper_2506_20202_amd/csrc/rara_internal.h")
+BLEND_SOURCES = ("paper_2506_20202_amd/csrc/blend.hip", "paper_2506_20202_amd/csrc/blend_common.h")
 
 
 def blend_source_hash():
@@ -375,6 +374,88 @@ def measure(sc, frames, args, reps, label):
     return out
 
 
+def multilayer_workload():
+    """One of the serving scenes (5 nested shells, 1.5M Gaussians, SH2) at
+    1024x1024: 8 cameras on a radius-5 sphere x 4 planes through the scene."""
+    from paper_2506_20202_amd import scenes
+    rng = np.random.default_rng(8)
+    sc = scenes.multilayer_scene(32, per_shell=300_000, sh_degree=2)
+    cams = [scenes.random_camera_on_sphere(rng, 5.0, 1024, 1024) for _ in range(8)]
+    planes = [scenes.random_plane_through(rng, sc) for _ in range(4)]
+    frames = [(c, p) for c in cams for p in planes]
+    desc = {"workload": "multi-layer scene, 5 shells x 300,000 = 1,500,000 Gaussians, SH2, 1024x1024, "
+                        "8 cameras x 4 planes", "gaussians": sc.n, "width": 1024, "height": 1024}
+    return sc, frames, desc
+
+
+def diff_bench(reps):
+    """The differentiable workload: 500k general-scene Gaussians (SH3), 8 views
+    at 800x800, each with its own clip plane, mean L2 loss against targets
+    rendered from a perturbed copy.  One batch = 8 forwards + the backward of
+    the loss; the forwards alone are timed too.  Median of `reps` batches."""
+    import torch
+    from paper_2506_20202_amd import autograd as AG
+    from paper_2506_20202_amd import renderer as R
+    from paper_2506_20202_amd import scenes
+    dev = torch.device("cuda:0")
+    sc = scenes.general_scene(4, n=500_000)
+    cams, planes = scenes.diff_views(scene=sc)
+    tgt = scenes.perturbed(sc)
+    frames = [R.Frame(sc.n, c.width, c.height, 16 * sc.n, dev, walked=False) for c in cams]
+
+    def t(a, g=True):
+        return torch.tensor(np.asarray(a), dtype=torch.float32, device=dev, requires_grad=g)
+
+    def p4(pl, g=False):
+        return torch.tensor([float(pl.n[0]), float(pl.n[1]), float(pl.n[2]), float(pl.d)], requires_grad=g)
+
+    with torch.no_grad():
+        tp = [t(a, False) for a in (tgt.mean, tgt.scale, tgt.quat, tgt.opacity, tgt.sh)]
+        targets = [AG.render(*tp, p4(pl), cam, True, frame=fr) for cam, pl, fr in zip(cams, planes, frames)]
+    params = [t(a) for a in (sc.mean, sc.scale, sc.quat, sc.opacity, sc.sh)]
+
+    def forward():
+        loss = 0.0
+        for cam, pl, fr, tg in zip(cams, planes, frames, targets):
+            img = AG.render(*params, p4(pl, True), cam, True, frame=fr)
+            loss = loss + ((img - tg) ** 2).mean()
+        return loss / len(cams)
+
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1)
+
+    def batch():
+        for p in params:
+            p.grad = None
+        forward().backward()
+
+    def fwd_only():
+        with torch.no_grad():
+            forward()
+
+    batch()
+    fwd_only()
+    b = [timed(batch) for _ in range(reps)]
+    f = [timed(fwd_only) for _ in range(reps)]
+    ok = all(bool(torch.isfinite(p.grad).all()) for p in params)
+    out = {"workload": "500,000 general-scene Gaussians, SH3, 8 views x 800x800, one clip plane per view, "
+                       "L2 loss against a perturbed-scene target", "batch_ms": float(np.median(b)),
+           "forward_ms": float(np.median(f)), "backward_ms": float(np.median(b) - np.median(f)),
+           "reps": reps, "gradients_finite": ok,
+           "note": "each forward checks the pair count on the host (one synchronisation per view)"}
+    del frames, params, targets
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -434,6 +515,13 @@ def main():
         sm = measure(ssc, sframes, args, max(1, args.reps // 2), "strands")
         secondary["strands"] = dict(sdesc, **sm)
         strand_case = (ssc, sframes[1][0], sframes[1][1])
+        msc, mframes, mdesc = multilayer_workload()
+        mm = measure(msc, mframes, args, max(1, args.reps // 2), "multilayer")
+        secondary["multilayer"] = dict(mdesc, **mm)
+        del msc, mframes
+        secondary["differentiable"] = diff_bench(3)
+        print(f"[bench] differentiable batch {secondary['differentiable']['batch_ms']:.2f} ms "
+              f"(forward {secondary['differentiable']['forward_ms']:.2f} ms)", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:

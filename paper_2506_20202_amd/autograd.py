@@ -22,7 +22,7 @@ class RaraRender(torch.autograd.Function):
         pv = [float(v) for v in plane4.detach().cpu().tolist()]
         import numpy as np
         from .scenes import Plane
-        plane = Plane(np.array(pv[:3], np.float32), pv[3], bool(plane_enabled))
+        plane = Plane(np.array(pv[:3], np.float32), pv[3], int(plane_enabled))   # clip mode
         out = R.render_checked(ds, frame, cam, plane, bg)
         ctx.save_for_backward(mean, scale, quat, opacity, sh, plane4)
         ctx.frame, ctx.cam, ctx.plane, ctx.bg, ctx.ds = frame, cam, plane, bg, ds

@@ -67,9 +67,12 @@ template <int kMode>
 __global__ __launch_bounds__(256) void chunk_sum_kernel(const uint32_t* __restrict__ tt,
                                                         const uint32_t* __restrict__ order, int64_t n,
                                                         const int64_t* __restrict__ count,
-                                                        uint32_t* __restrict__ block_sums)
+                                                        uint32_t* __restrict__ block_sums,
+                                                        uint32_t* __restrict__ ranges, int64_t range_words)
 {
     const int64_t k = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    // the first kernel of a frame also clears the tile ranges (grid-stride)
+    for (int64_t w = k; w < range_words; w += (int64_t)gridDim.x * kScanBlock) ranges[w] = 0u;
     const int64_t lim = kMode == 2 ? *count : n;
     uint32_t v = 0u;
     if (k < lim) v = kMode == 0 ? tt[k] : (kMode == 1 ? (tt[k] > 0u ? 1u : 0u) : tt[order[k]]);
@@ -227,12 +230,27 @@ __device__ inline uint32_t block_sum_scan(uint32_t v, uint32_t& total, uint32_t*
 __global__ __launch_bounds__(1024) void plan_kernel(const uint2* __restrict__ ranges, int num_tiles,
                                                     uint32_t* __restrict__ work)
 {
+    constexpr int kRegTiles = 8;   // tiles per thread kept in registers (T <= 8192)
     __shared__ uint32_t wave_tot[16];
     const int tid = threadIdx.x;
     const int per = (num_tiles + 1023) / 1024;
     const int t0 = tid * per < num_tiles ? tid * per : num_tiles;
     const int t1 = t0 + per < num_tiles ? t0 + per : num_tiles;
+    // heavy flags of this thread's run: all loads issued at once when they fit
+    uint32_t hbits = 0u;
+    if (per <= kRegTiles) {
+        uint32_t len[kRegTiles];
+#pragma unroll
+        for (int k = 0; k < kRegTiles; ++k) {
+            const int t = t0 + k;
+            const uint2 r = t < t1 ? ranges[t] : make_uint2(0u, 0u);
+            len[k] = r.y - r.x;
+        }
+#pragma unroll
+        for (int k = 0; k < kRegTiles; ++k) hbits |= (len[k] >= kHeavyList ? 1u : 0u) << k;
+    }
     auto heavy = [&](int t) {
+        if (per <= kRegTiles) return ((hbits >> (t - t0)) & 1u) != 0u;
         const uint2 r = ranges[t];
         return r.y - r.x >= kHeavyList;
     };
@@ -274,7 +292,7 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
     // 1. drawn Gaussians in index order
     if (n > 0)
         hipLaunchKernelGGL(chunk_sum_kernel<1>, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, nullptr, n,
-                           nullptr, ws.block_sums);
+                           nullptr, ws.block_sums, out.ranges, (int64_t)cam.tiles_x * cam.tiles_y * 2);
     hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, ws.block_sums, nb, INT64_MAX, ws.dcount,
                        ws.dover);
     if (n > 0)
@@ -287,7 +305,7 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
     // 3. pair offsets in depth order, pair count, overflow flag, emission
     if (n > 0)
         hipLaunchKernelGGL(chunk_sum_kernel<2>, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, ws.dvals[0],
-                           n, ws.dcount, ws.block_sums);
+                           n, ws.dcount, ws.block_sums, nullptr, (int64_t)0);
     hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, ws.block_sums, nb, cap, out.num_pairs,
                        out.overflow);
     // the last tile pass must read the workspace buffer, never out.keys, which
@@ -307,9 +325,12 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
                        ws.digit_totals, out.keys, out.vals, proj.depth, s);
 }
 
-hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, hipStream_t s)
+hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, bool clear, hipStream_t s)
 {
-    hipLaunchKernelGGL(ranges_clear_kernel, dim3((num_tiles + 255) / 256), dim3(256), 0, s, out.ranges, num_tiles);
+    // with Gaussians the first binning kernel has cleared the ranges already
+    if (clear)
+        hipLaunchKernelGGL(ranges_clear_kernel, dim3((num_tiles + 255) / 256), dim3(256), 0, s, out.ranges,
+                           num_tiles);
     int64_t blocks = (cap + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;

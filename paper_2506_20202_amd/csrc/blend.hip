@@ -83,6 +83,16 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
     float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     uint32_t last = 0u, walked = 0u;
 
+    // Long lists set the tail of the launch: their waves get issue priority over
+    // the short tiles sharing their SIMD (wave priority only; no effect on results).
+    const uint32_t len = rg.y - rg.x;
+    if (len >= 2048u)
+        __builtin_amdgcn_s_setprio(3);
+    else if (len >= 768u)
+        __builtin_amdgcn_s_setprio(2);
+    else if (len >= 256u)
+        __builtin_amdgcn_s_setprio(1);
+
     const double ox = (double)(tx * kTile), oy = (double)(ty * kTile);
     const bool plane_on = p.plane_enabled != 0;
     const bool strict = (p.plane_enabled & RARA_CLIP_STRICT_MISS) != 0;

@@ -134,7 +134,7 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
 hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int passes, const int64_t* count,
                        const int32_t* overflow, int64_t blocks, uint32_t* hist, uint32_t* digit_totals,
                        uint64_t* final_keys, uint32_t* final_vals, const float* depth, hipStream_t s);
-hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, hipStream_t s);
+hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, bool clear, hipStream_t s);
 hipError_t launch_plan(const rara_binned& out, int num_tiles, hipStream_t s);
 // the same kernels reading their per-frame parameters from device memory
 hipError_t launch_preprocess_fp(const GaussPtrs& g, const FrameParams* fp, const ProjPtrs& out, hipStream_t s);

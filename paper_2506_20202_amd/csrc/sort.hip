@@ -125,6 +125,9 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     __shared__ uint32_t wave_gsum[kWaves];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // this tile's digit offsets do not depend on the keys: issue their loads first
+    const uint32_t gtot = digit_totals[tid];
+    const uint32_t tile_off = hist[(int64_t)tid * stride + blockIdx.x];
     for (int k = tid; k < kWaves * kRadix; k += kSortThreads) (&counts[0][0])[k] = 0u;
     __syncthreads();
 
@@ -175,7 +178,6 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     // exclusive scans over the 256 digits (4 waves x 64 lanes): local digit
     // starts from dtot, global digit bases from the pass-wide digit totals
     {
-        const uint32_t gtot = digit_totals[tid];
         uint32_t incl = dtot, gincl = gtot;
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t o = __shfl_up(incl, off, 64);
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         uint32_t before = 0, gbefore = 0;
         for (int w = 0; w < wave; ++w) { before += wave_sum[w]; gbefore += wave_gsum[w]; }
         local_start[tid] = before + incl - dtot;
-        global_start[tid] = gbefore + gincl - gtot + hist[(int64_t)tid * stride + blockIdx.x];
+        global_start[tid] = gbefore + gincl - gtot + tile_off;
     }
     __syncthreads();
 

@@ -83,6 +83,10 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=240)
     ap.add_argument("--serve-load", type=float, default=0.5, help="arrival rate as a fraction of saturation")
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0,
+                    help="HBM for serving slots beyond the resident scenes")
+    ap.add_argument("--serve-slots", type=int, default=64, help="slots kept (buffers and captured graphs)")
+    ap.add_argument("--serve-inflight", type=int, default=8, help="frames running at once")
     ap.add_argument("--profile-steps", type=int, default=0, help="only run this many frames (for profilers)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="with --profile-steps: also run one plain 256 MiB device copy (counter calibration)")
@@ -222,11 +226,11 @@ def serve_bench(args):
             ("C", scenes.multilayer_scene(33, per_shell=400_000, sh_degree=3))]
     sizes = [(512, 512), (1024, 1024), (1920, 1080), (2048, 2048)]
     resident = 0
-    eng = Engine(hbm_budget=0, max_slots=16)
+    eng = Engine(hbm_budget=0, max_slots=args.serve_slots, max_inflight=args.serve_inflight)
     for name, sc in defs:
         eng.add_scene(name, sc)
     resident = eng.ex.resident_bytes()
-    budget = resident + (8 << 30)
+    budget = resident + int(args.serve_budget_gib * (1 << 30))
     eng.sched.budget = budget
 
     def make(nreq):
@@ -256,16 +260,16 @@ def serve_bench(args):
     def run(reqs, clipped):
         eng.sched.latencies.clear()
         eng.sched.completed.clear()
-        eng.start()
-        t_start = time.perf_counter()
+        # every request is submitted up front with its Poisson arrival time; the
+        # scheduler admits it once that time has come (no host thread spins)
+        t_start = time.perf_counter() + 0.05
         t = t_start
         futs = []
         for (name, cam, pl), gap in zip(reqs, gaps):
             t += gap
-            while time.perf_counter() < t:
-                pass
             p = pl if clipped else type(pl)(pl.n, pl.d, False)
             futs.append(eng.submit(name, cam, p, arrival=t))
+        eng.start()
         for f in futs:
             f.result(timeout=300)
         wall = time.perf_counter() - t_start
@@ -282,7 +286,9 @@ def serve_bench(args):
     return {"workload": "3 resident multi-layer scenes (1.0M SH0, 1.5M SH2, 2.0M SH3), resolutions "
                         "512^2/1024^2/1920x1080/2048^2, camera on a radius-5 sphere, random plane",
             "requests": len(stream), "saturation_req_s": sat, "offered_load_req_s": rate,
-            "load_fraction": args.serve_load, "hbm_budget_gib": budget / 2 ** 30, "graphs": True,
+            "load_fraction": args.serve_load, "hbm_budget_gib": budget / 2 ** 30, "max_slots": args.serve_slots,
+            "max_inflight": args.serve_inflight,
+            "graphs": True,
             "clipped": clipped, "plain": plain}
 
 

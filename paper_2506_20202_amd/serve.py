@@ -11,6 +11,10 @@ first-come first-served:
     every slot's buffers) allows it, evicting idle slots of other shapes,
     least recently used first;
   * otherwise the queue waits until a running request completes.
+A request submitted with a future arrival time waits in the queue until that
+time.  At most ``max_inflight`` frames run at once (default: one per slot); slots
+beyond that stay cached with their graphs, so shapes that come back do not
+pay a capture again.
 
 Requests admitted while others run go onto their own slot streams, so their
 kernels overlap on the device.  A frame that overflows its slot's pair
@@ -75,10 +79,14 @@ class Scheduler:
     """Admission, slots, HBM budget, retries and latency bookkeeping."""
 
     def __init__(self, executor, hbm_budget: int, max_slots: int = 8, clock: Callable[[], float] = time.perf_counter,
-                 capacity_of: Optional[Callable[[Tuple[str, int, int]], int]] = None, grow: float = 1.5):
+                 capacity_of: Optional[Callable[[Tuple[str, int, int]], int]] = None, grow: float = 1.5,
+                 max_inflight: Optional[int] = None):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
+        # slots kept (built graphs, cached buffers) versus frames running at once:
+        # once the device is busy, more concurrent frames only lengthen each one
+        self.inflight_cap = int(max_inflight) if max_inflight else self.max_slots
         self.clock = clock
         self.capacity_of = capacity_of or (lambda shape: 1 << 20)
         self.grow = grow
@@ -153,8 +161,12 @@ class Scheduler:
             else:
                 self.failed.append(req)
                 req.future.set_exception(RuntimeError(c.error or "render failed"))
-        while self.queue:
+        inflight = sum(1 for s in self.slots if s.request is not None)
+        now = self.clock()
+        while self.queue and inflight < self.inflight_cap:
             req = self.queue[0]
+            if req.arrival > now:   # submitted ahead of its arrival time
+                break
             slot = self._slot_for(req)
             if slot is None:
                 break
@@ -163,8 +175,8 @@ class Scheduler:
             req.start = self.clock()
             slot.last_used = req.start
             self.ex.launch(slot.handle, req)
+            inflight += 1
             changed = True
-        inflight = sum(1 for s in self.slots if s.request is not None)
         self.max_inflight = max(self.max_inflight, inflight)
         return changed
 
@@ -297,9 +309,10 @@ class Engine:
     """Scheduler + GPU executor + a background loop thread."""
 
     def __init__(self, hbm_budget: int, max_slots: int = 8, device=None, use_graphs: bool = True,
-                 capacity_of: Optional[Callable] = None):
+                 capacity_of: Optional[Callable] = None, max_inflight: Optional[int] = None):
         self.ex = GpuExecutor(device, use_graphs)
-        self.sched = Scheduler(self.ex, hbm_budget, max_slots, capacity_of=capacity_of or self._capacity_guess)
+        self.sched = Scheduler(self.ex, hbm_budget, max_slots, capacity_of=capacity_of or self._capacity_guess,
+                               max_inflight=max_inflight)
         self._lock = threading.Lock()
         self._stop = threading.Event()
         self._thread: Optional[threading.Thread] = None

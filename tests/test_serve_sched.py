@@ -172,3 +172,31 @@ def test_latency_percentiles():
     assert sorted(lat.tolist()) == pytest.approx([1000.0, 2000.0, 3000.0, 4000.0])
     assert st["p50_ms"] == pytest.approx(np.percentile(lat, 50))
     assert st["p99_ms"] == pytest.approx(np.percentile(lat, 99))
+
+
+def test_inflight_cap_keeps_slots_cached():
+    """max_inflight bounds the frames running at once; the extra slots stay
+    cached, so a shape that comes back reuses its slot (no new capture)."""
+    clock = Clock()
+    ex = FakeExecutor(clock, resident=0, dur=lambda r: 1.0)
+    s = Scheduler(ex, hbm_budget=1 << 30, max_slots=8, clock=clock, capacity_of=lambda sh: 100, max_inflight=2)
+    for k in range(12):
+        s.submit(_req("a" if k % 3 == 0 else ("b" if k % 3 == 1 else "c"), 10, 10))
+    _run(s, clock)
+    assert s.max_inflight == 2
+    assert s.stats()["completed"] == 12
+    assert ex.created <= 4 and ex.destroyed == 0
+
+
+def test_requests_wait_for_their_arrival_time():
+    """A request submitted ahead of its arrival time is admitted only once the
+    clock reaches it, and its latency counts from the arrival."""
+    clock = Clock()
+    ex = FakeExecutor(clock, dur=lambda r: 1.0)
+    s = Scheduler(ex, hbm_budget=10_000, max_slots=2, clock=clock, capacity_of=lambda sh: 100)
+    s.submit(_req("a", 10, 10, 0.0))
+    s.submit(_req("a", 10, 10, 3.0))
+    _run(s, clock, dt=0.5)
+    starts = {rid: t for t, rid, _ in ex.launched}
+    assert starts[0] == 0.0 and starts[1] == 3.0
+    assert sorted(np.array(s.latencies).round(6).tolist()) == [1.0, 1.0]

@@ -142,7 +142,13 @@ typedef struct {
  *   overflow  [1] int32          set to 1 when P > pair_capacity, else 0.
  *   work [4 tiles + 1] uint32    blend schedule written by rara_bin_sort: quadrant
  *                                units of tiles with long lists, then whole tiles;
- *                                the last entry is the number of split tiles. */
+ *                                the last entry is the number of split tiles.
+ *   pair_start [n] uint32        for each drawn Gaussian, the position of its first
+ *                                pair in emission order (drawn Gaussians by depth,
+ *                                each one's tiles row by row over its rectangle);
+ *                                not written for Gaussians that are not drawn.  Used
+ *                                by rara_render_backward to give every (tile,
+ *                                Gaussian) pair its own gradient slot. */
 typedef struct {
     uint64_t* keys;
     uint32_t* vals;
@@ -150,6 +156,7 @@ typedef struct {
     int64_t* num_pairs;
     int32_t* overflow;
     uint32_t* work;
+    uint32_t* pair_start;
 } rara_binned;
 
 /* Gradients (caller-allocated; overwritten, not accumulated):
@@ -220,16 +227,21 @@ rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned
  * transmittance rebuilt by division) and the clip weight of eq. (11), then
  * through projection and colour to the raw inputs and the plane.  g, cam,
  * plane, bg, proj, bins, final_T and n_contrib must be those of the forward
- * frame.  Needs `ws_bytes` >= rara_workspace_bytes(RARA_WS_BACKWARD, n, ...)
- * bytes of device workspace.  Every array of *grads is overwritten (Gaussians
- * that were not drawn get zero).  Gradients use float atomics, so repeated
- * runs agree to rounding, not bit for bit.
- * Errors: as rara_render, plus RARA_ERR_INVALID for a short workspace or null
- * gradient arrays. */
+ * frame, and pair_capacity the one rara_bin_sort was given.  Needs `ws_bytes`
+ * >= rara_workspace_bytes(RARA_WS_BACKWARD, n, pair_capacity, W, H) bytes of
+ * device workspace: one 84-byte gradient slot per pair of capacity, written
+ * once by the tile that holds the pair, then summed per Gaussian, so no
+ * per-Gaussian atomics are used and repeated runs give identical gradients
+ * except for the plane (a few per-tile float atomics).  Every array of *grads
+ * is overwritten (Gaussians that were not drawn get zero).
+ * Errors: as rara_render, plus RARA_ERR_INVALID for a short workspace, a
+ * pair_capacity outside [1, 2^30), null gradient arrays or a null
+ * bins->pair_start. */
 rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam, const rara_plane* plane,
                                  const float* bg, const rara_projected* proj, const rara_binned* bins,
-                                 const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
-                                 const rara_grads* grads, void* workspace, size_t ws_bytes, void* stream);
+                                 int64_t pair_capacity, const float* final_T, const uint32_t* n_contrib,
+                                 const float* dL_dimage, const rara_grads* grads, void* workspace, size_t ws_bytes,
+                                 void* stream);
 
 /* Frame graphs (for serving many requests of one shape): the kernels of one
  * frame (rara_preprocess + rara_bin_sort + rara_render) captured once into a

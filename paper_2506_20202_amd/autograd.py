@@ -39,12 +39,13 @@ class RaraRender(torch.autograd.Function):
         gs = B.Grads()
         gs.mean, gs.scale, gs.quat = g["mean"].data_ptr(), g["scale"].data_ptr(), g["quat"].data_ptr()
         gs.opacity, gs.sh, gs.plane = g["opacity"].data_ptr(), g["sh"].data_ptr(), dplane.data_ptr()
-        ws_bytes = B.workspace_bytes(B.RARA_WS_BACKWARD, ds.n, 1, fr.width, fr.height)
+        ws_bytes = B.workspace_bytes(B.RARA_WS_BACKWARD, ds.n, fr.capacity, fr.width, fr.height)
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
         dimg = dimage.contiguous().to(torch.float32)
         stream = int(torch.cuda.current_stream(dev).cuda_stream)
         B.render_backward(ds.struct(), B.make_camera(ctx.cam), B.make_plane(ctx.plane), ctx.bg, fr.proj.struct(),
-                          fr.bins.struct(), fr.out.final_T.data_ptr(), fr.out.n_contrib.data_ptr(), dimg.data_ptr(),
+                          fr.bins.struct(), fr.capacity, fr.out.final_T.data_ptr(), fr.out.n_contrib.data_ptr(),
+                          dimg.data_ptr(),
                           gs, ws.data_ptr(), ws_bytes, stream)
         return (g["mean"], g["scale"], g["quat"], g["opacity"], g["sh"], dplane.to(plane4.device, plane4.dtype),
                 None, None, None, None)

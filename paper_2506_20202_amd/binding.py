@@ -40,7 +40,8 @@ class Projected(ctypes.Structure):
 
 
 class Binned(ctypes.Structure):
-    _fields_ = [("keys", _P), ("vals", _P), ("ranges", _P), ("num_pairs", _P), ("overflow", _P), ("work", _P)]
+    _fields_ = [("keys", _P), ("vals", _P), ("ranges", _P), ("num_pairs", _P), ("overflow", _P), ("work", _P),
+                ("pair_start", _P)]
 
 
 class Grads(ctypes.Structure):
@@ -72,8 +73,8 @@ def lib():
         L.rara_preprocess.argtypes = [PG, PC, PP, PJ, _P]
         L.rara_bin_sort.argtypes = [PJ, ctypes.c_int64, PC, ctypes.c_int64, _P, ctypes.c_size_t, PB, _P]
         L.rara_render.argtypes = [PJ, ctypes.c_int64, PB, PC, PP, ctypes.POINTER(ctypes.c_float), _P, _P, _P, _P, _P]
-        L.rara_render_backward.argtypes = [PG, PC, PP, ctypes.POINTER(ctypes.c_float), PJ, PB, _P, _P, _P, PR, _P,
-                                           ctypes.c_size_t, _P]
+        L.rara_render_backward.argtypes = [PG, PC, PP, ctypes.POINTER(ctypes.c_float), PJ, PB, ctypes.c_int64, _P, _P,
+                                           _P, PR, _P, ctypes.c_size_t, _P]
         L.rara_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                            ctypes.c_int32]
         L.rara_workspace_bytes.restype = ctypes.c_size_t
@@ -146,13 +147,14 @@ def render(proj: Projected, n: int, bins: Binned, cam: Camera, plane: Plane, bg,
                                             _P(n_walked or None), _P(stream)))
 
 
-def render_backward(g: Gaussians, cam: Camera, plane: Plane, bg, proj: Projected, bins: Binned, final_T: int,
-                    n_contrib: int, dL_dimage: int, grads: Grads, workspace: int, ws_bytes: int, stream: int):
+def render_backward(g: Gaussians, cam: Camera, plane: Plane, bg, proj: Projected, bins: Binned, pair_capacity: int,
+                    final_T: int, n_contrib: int, dL_dimage: int, grads: Grads, workspace: int, ws_bytes: int,
+                    stream: int):
     bgc = (ctypes.c_float * 3)(*[float(v) for v in bg])
     _check("rara_render_backward",
            lib().rara_render_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(plane), bgc, ctypes.byref(proj),
-                                      ctypes.byref(bins), _P(final_T), _P(n_contrib), _P(dL_dimage),
-                                      ctypes.byref(grads), _P(workspace), ws_bytes, _P(stream)))
+                                      ctypes.byref(bins), ctypes.c_int64(pair_capacity), _P(final_T), _P(n_contrib),
+                                      _P(dL_dimage), ctypes.byref(grads), _P(workspace), ws_bytes, _P(stream)))
 
 
 def frame_graph_create(g: Gaussians, shape: Camera, proj: Projected, bins: Binned, pair_capacity: int, workspace: int,

@@ -157,7 +157,8 @@ size_t rara_workspace_bytes(int32_t which, int64_t n, int64_t pair_capacity, int
         return bin_workspace_layout(n, pair_capacity, nullptr, nullptr);
     }
     if (which == RARA_WS_BACKWARD) {
-        return backward_workspace_bytes(n, width, height);
+        if (pair_capacity < 1 || pair_capacity >= (int64_t(1) << 30)) return 0;
+        return backward_workspace_bytes(n, pair_capacity, width, height);
     }
     return 0;
 }
@@ -184,7 +185,8 @@ rara_status rara_bin_sort(const rara_projected* proj, int64_t n, const rara_came
     if (!proj || n < 0 || !out || !workspace) return RARA_ERR_INVALID;
     if (pair_capacity < 1 || pair_capacity >= (int64_t(1) << 31)) return RARA_ERR_INVALID;
     if (n > 0 && !proj_ok(proj)) return RARA_ERR_INVALID;
-    if (!out->keys || !out->vals || !out->ranges || !out->num_pairs || !out->overflow || !out->work)
+    if (!out->keys || !out->vals || !out->ranges || !out->num_pairs || !out->overflow || !out->work ||
+        (n > 0 && !out->pair_start))
         return RARA_ERR_INVALID;
     CamParams cp;
     if (!make_cam(cam, &cp)) return RARA_ERR_INVALID;
@@ -219,27 +221,30 @@ rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned
 
 rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam, const rara_plane* plane,
                                  const float* bg, const rara_projected* proj, const rara_binned* bins,
-                                 const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
-                                 const rara_grads* grads, void* workspace, size_t ws_bytes, void* stream)
+                                 int64_t pair_capacity, const float* final_T, const uint32_t* n_contrib,
+                                 const float* dL_dimage, const rara_grads* grads, void* workspace, size_t ws_bytes,
+                                 void* stream)
 {
     if (!g || g->n < 0 || !bg || !proj || !bins || !final_T || !n_contrib || !dL_dimage || !grads || !workspace)
         return RARA_ERR_INVALID;
+    if (pair_capacity < 1 || pair_capacity >= (int64_t(1) << 30)) return RARA_ERR_INVALID;
     if (g->sh_degree < 0 || g->sh_degree > 3) return RARA_ERR_UNSUPPORTED;
-    if (!proj_ok(proj) || !bins->vals || !bins->ranges || !bins->overflow || !bins->work) return RARA_ERR_INVALID;
+    if (!proj_ok(proj) || !bins->vals || !bins->ranges || !bins->overflow || !bins->work || !bins->pair_start)
+        return RARA_ERR_INVALID;
     if (!grads->plane || (g->n > 0 && (!grads->mean || !grads->scale || !grads->quat || !grads->opacity || !grads->sh)))
         return RARA_ERR_INVALID;
     if (g->n > 0 && (!g->mean || !g->scale || !g->quat || !g->opacity || !g->sh)) return RARA_ERR_INVALID;
     CamParams cp;
     PlaneParams pp;
     if (!make_cam(cam, &cp) || !make_plane(plane, &pp)) return RARA_ERR_INVALID;
-    if (ws_bytes < backward_workspace_bytes(g->n, cp.W, cp.H)) return RARA_ERR_INVALID;
+    if (ws_bytes < backward_workspace_bytes(g->n, pair_capacity, cp.W, cp.H)) return RARA_ERR_INVALID;
     const RenderParams rp = make_render_params(cp, pp, bg);
     const double len = pp.enabled ? std::sqrt((double)plane->n[0] * plane->n[0] + (double)plane->n[1] * plane->n[1] +
                                               (double)plane->n[2] * plane->n[2])
                                   : 1.0;
     GaussPtrs gp{g->n, g->sh_degree, g->mean, g->scale, g->quat, g->opacity, g->sh};
-    const hipError_t e = launch_backward(gp, cp, pp, len, proj_ptrs(proj), *bins, rp, final_T, n_contrib, dL_dimage,
-                                         *grads, workspace, static_cast<hipStream_t>(stream));
+    const hipError_t e = launch_backward(gp, cp, pp, len, proj_ptrs(proj), *bins, pair_capacity, rp, final_T,
+                                         n_contrib, dL_dimage, *grads, workspace, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
 }
 

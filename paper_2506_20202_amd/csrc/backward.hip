@@ -9,9 +9,12 @@
 //                   and re-evaluating alpha and the clip weight with the
 //                   forward's own arithmetic, so that the composite / skip
 //                   decisions are the forward's bit for bit.  Per entry the
-//                   per-pixel gradients are summed over the wave and added to
-//                   21 per-Gaussian accumulators with one atomic each.
-//   project_backward per Gaussian, FP64 chain rule from (mean2d, conic,
+//                   per-pixel gradients are summed over each wave, the four
+//                   waves of a tile combine them in LDS, and the 21 sums go to
+//                   the pair's own slot (its position in emission order) with
+//                   plain stores: no per-Gaussian atomics.
+//   project_backward per Gaussian, sum of its (contiguous) pair slots, then
+//                   the FP64 chain rule from (mean2d, conic,
 //                   opacity, colour, ray set-up) to (mean, scale, quaternion,
 //                   opacity, SH) and the plane, through the EWA projection of
 //                   eqs. (9)-(10), the SH colour and eq. (4)'s whitening.
@@ -31,11 +34,27 @@ enum {
 // plane accumulators: dn_hat[3], dd_hat, dax, day
 constexpr int kPlaneAcc = 8;
 
+// Sum over the 64 lanes, returned to every lane, with DPP row operations (no
+// LDS): shifts by 1, 2, 4 and 8 within each 16-lane row leave the row sum in
+// the row's last lane; broadcasting lane 15 into row 1 and row 3, then lane 31
+// into rows 2 and 3, leaves the wave sum in lane 63.  Lanes a DPP move does
+// not write (row edges, masked rows) take 0.
+template <int kCtrl, int kRowMask>
+__device__ inline float dpp_step(float v)
+{
+    const int moved = __builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, kRowMask, 0xf, false);
+    return v + __int_as_float(moved);
+}
+
 __device__ inline float wave_sum(float v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v = dpp_step<0x111, 0xf>(v);   // row_shr:1
+    v = dpp_step<0x112, 0xf>(v);   // row_shr:2
+    v = dpp_step<0x114, 0xf>(v);   // row_shr:4
+    v = dpp_step<0x118, 0xf>(v);   // row_shr:8
+    v = dpp_step<0x142, 0xa>(v);   // row_bcast:15 into rows 1, 3
+    v = dpp_step<0x143, 0xc>(v);   // row_bcast:31 into rows 2, 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 __device__ inline uint32_t wave_max(uint32_t v)
@@ -113,119 +132,137 @@ __device__ inline void chord_backward(const CutRec& k, const Chord& c, float dx,
     g[11] += dg0;
 }
 
-template <int kSlots>
-__device__ inline void blend_back_unit(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
-                                       const uint32_t* __restrict__ vals, const uint2 rg, int tile, int quad,
+constexpr int kBackBatch = 128;   // entries staged per batch (threads 0..127 stage)
+
+// Gradient slot of the pair (tile (tx, ty), Gaussian id): its position in
+// emission order, the Gaussian's first pair plus the tile's index in the
+// Gaussian's rectangle, row by row.
+__device__ inline uint32_t pair_slot(uint32_t first, ushort4 rc, int tx, int ty)
+{
+    return first + (uint32_t)(ty - rc.y) * (uint32_t)(rc.z - rc.x) + (uint32_t)(tx - rc.x);
+}
+
+// One tile, back to front.  Thread t of wave w = t / 64 owns pixel
+// (t % 8, (t / 8) % 8) of the 8x8 quadrant w, as in the forward.  The list is
+// walked from the tile's largest n_contrib down, in batches of kBackBatch
+// staged entries; each wave visits, in descending order, the entries that
+// reach its quadrant.  Per entry the wave sums its pixels' gradients and adds
+// them to the entry's LDS accumulators (the four waves share them); after the
+// batch every staged entry's 21 sums go to its pair slot with plain stores.
+// Entries past the largest n_contrib get zero slots.
+__device__ inline void blend_back_tile(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
+                                       const uint32_t* __restrict__ vals, const uint32_t* __restrict__ pair_start,
+                                       const uint16_t* __restrict__ rect, const uint2 rg, int tile,
                                        const BackParams& bp, const float* __restrict__ final_T,
                                        const uint32_t* __restrict__ n_contrib, const float* __restrict__ dL_dimage,
-                                       float* __restrict__ acc, float* __restrict__ plane_acc,
-                                       float4 (*s_a), float4 (*s_b), float4 (*s_c), CutRec (*s_cut))
+                                       float* __restrict__ slots, float* __restrict__ plane_acc, float4* s_a,
+                                       float4* s_b, float4* s_c, CutRec* s_cut, uint32_t* s_slot,
+                                       float (*s_g)[kAccRows], uint32_t* s_red)
 {
     const RenderParams& p = bp.rp;
-    const int64_t n = bp.n;
     const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
-    const int lane = threadIdx.x;
-    const int lx = lane & 7, ly = lane >> 3;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int ox8 = (wave & 1) * 8 + (lane & 7), oy8 = (wave >> 1) * 8 + (lane >> 3);
+    const float lpx = (float)ox8, lpy = (float)oy8;
+    const int px = tx * kTile + ox8, py = ty * kTile + oy8;
+    const bool inside = px < p.W && py < p.H;
     const int64_t HW = (int64_t)p.H * p.W;
+    const int64_t pix = (int64_t)py * p.W + px;
 
-    float lpx[kSlots], lpy[kSlots], T[kSlots], Tfin[kSlots], dC[kSlots][3], ac[kSlots][3], la[kSlots],
-        lc[kSlots][3], bgdot[kSlots];
-    uint32_t nc[kSlots];
-    int qof[kSlots];
-    uint32_t kmax = 0;
-#pragma unroll
-    for (int q = 0; q < kSlots; ++q) {
-        const int qq = kSlots == 4 ? q : quad;
-        qof[q] = qq;
-        const int ox = (qq & 1) * 8 + lx, oy = (qq >> 1) * 8 + ly;
-        lpx[q] = (float)ox;
-        lpy[q] = (float)oy;
-        const int px = tx * kTile + ox, py = ty * kTile + oy;
-        const bool inside = px < p.W && py < p.H;
-        const int64_t pix = (int64_t)py * p.W + px;
-        T[q] = inside ? final_T[pix] : 0.0f;
-        Tfin[q] = T[q];
-        nc[q] = inside ? n_contrib[pix] : 0u;
-        kmax = nc[q] > kmax ? nc[q] : kmax;
-        bgdot[q] = 0.0f;
-        for (int ch = 0; ch < 3; ++ch) {
-            dC[q][ch] = inside ? dL_dimage[ch * HW + pix] : 0.0f;
-            ac[q][ch] = 0.0f;
-            lc[q][ch] = 0.0f;
-            bgdot[q] += p.bg[ch] * dC[q][ch];
-        }
-        la[q] = 0.0f;
+    float T = inside ? final_T[pix] : 0.0f;
+    const float Tfin = T;
+    const uint32_t nc = inside ? n_contrib[pix] : 0u;
+    float dC[3], ac[3] = {0.0f, 0.0f, 0.0f}, lc[3] = {0.0f, 0.0f, 0.0f}, la = 0.0f, bgdot = 0.0f;
+    for (int ch = 0; ch < 3; ++ch) {
+        dC[ch] = inside ? dL_dimage[ch * HW + pix] : 0.0f;
+        bgdot += p.bg[ch] * dC[ch];
     }
-    kmax = __builtin_amdgcn_readfirstlane(wave_max(kmax));
-    if (kmax > rg.y - rg.x) kmax = rg.y - rg.x;   // n_contrib never exceeds the list length
+    // the tile's largest n_contrib, clamped to the list length
+    const uint32_t wm = wave_max(nc);
+    if (lane == 0) s_red[wave] = wm;
+    __syncthreads();
+    uint32_t kmax = s_red[0];
+    for (int w = 1; w < 4; ++w) kmax = s_red[w] > kmax ? s_red[w] : kmax;
+    if (kmax > rg.y - rg.x) kmax = rg.y - rg.x;
+
     const bool plane_on = p.plane_enabled != 0;
+    const bool strict = (p.plane_enabled & RARA_CLIP_STRICT_MISS) != 0;
     const double ox = (double)(tx * kTile), oy = (double)(ty * kTile);
     float pax = 0.0f, pay = 0.0f;
 
     for (uint32_t hi = rg.x + kmax; hi > rg.x;) {
-        const uint32_t lo = hi - rg.x > (uint32_t)kBatch ? hi - kBatch : rg.x;
+        const uint32_t lo = hi - rg.x > (uint32_t)kBackBatch ? hi - kBackBatch : rg.x;
         const uint32_t cnt = hi - lo;
-        uint32_t my_mask = 0u;
-        __syncthreads();
-        if ((uint32_t)lane < cnt) {
-            const uint32_t id = vals[lo + lane];
-            const Splat sp = splats[id];
-            stage_entry(sp, ox, oy, kSlots == 4 ? 0xfu : (1u << quad), s_a[lane], s_b[lane], s_c[lane], my_mask, id);
-            if (sp.label == RARA_LABEL_CUTOFF && plane_on) {
-                const float4* rr = reinterpret_cast<const float4*>(rays + id);
-                CutRec c;
-                c.a = rr[0];
-                c.b = rr[1];
-                c.c = rr[2];
-                s_cut[lane] = c;
+        __syncthreads();   // the previous batch has been read and written out
+        if (tid < kBackBatch) {
+            for (int r = 0; r < kAccRows; ++r) s_g[tid][r] = 0.0f;
+            float4 sc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // mask 0: reaches nothing
+            if ((uint32_t)tid < cnt) {
+                const uint32_t id = vals[lo + tid];
+                const Splat sp = splats[id];
+                float4 sa, sb;
+                uint32_t qm;
+                stage_entry(sp, ox, oy, 0xfu, sa, sb, sc, qm, id);
+                s_a[tid] = sa;
+                s_b[tid] = sb;
+                if (sp.label == RARA_LABEL_CUTOFF && plane_on) {
+                    const float4* rr = reinterpret_cast<const float4*>(rays + id);
+                    const float4 r0 = rr[0], r1 = rr[1], r2 = rr[2];
+                    s_cut[tid].a = r0;
+                    s_cut[tid].b = r1;
+                    s_cut[tid].c = r2;
+                }
+                const ushort4 rc = *reinterpret_cast<const ushort4*>(rect + 4 * (int64_t)id);
+                s_slot[tid] = pair_slot(pair_start[id], rc, tx, ty);
             }
+            s_c[tid] = sc;
         }
         __syncthreads();
-        uint64_t todo = __ballot(my_mask != 0u);
-        while (todo) {
-            const int j = 63 - (int)__builtin_clzll(todo);
-            todo &= ~(1ull << j);
-            const float4 a = s_a[j], b = s_b[j], c = s_c[j];
-            const uint32_t lm = __builtin_amdgcn_readfirstlane(__float_as_uint(c.y));
-            const uint32_t id = __builtin_amdgcn_readfirstlane(__float_as_uint(c.z));
-            const uint32_t k1 = lo - rg.x + (uint32_t)j + 1u;
-            const bool cut = plane_on && ((lm & 0xffu) == RARA_LABEL_CUTOFF);
-            CutRec cr;
-            if (cut) cr = s_cut[j];
-            float g_mx = 0.f, g_my = 0.f, g_ca = 0.f, g_cb = 0.f, g_cc = 0.f, g_op = 0.f;
-            float g_col[3] = {0.f, 0.f, 0.f};
-            float g_ray[12];
-            for (int r = 0; r < 12; ++r) g_ray[r] = 0.f;
-            bool contributed = false;
-#pragma unroll
-            for (int q = 0; q < kSlots; ++q) {
-                if (((lm >> (8 + qof[q])) & 1u) && k1 <= nc[q]) {
-                    const float dx = lpx[q] - a.x, dy = lpy[q] - a.y;
+        // visit this wave's entries in descending order, 64 at a time
+        for (int sub = (int)((cnt - 1) & ~63u); sub >= 0; sub -= 64) {
+            const uint32_t lm = __float_as_uint(s_c[sub + lane].y);
+            uint64_t todo = __ballot((lm >> (8 + wave)) & 1u);
+            const uint64_t cutb = __ballot(plane_on && (lm & 0xffu) == RARA_LABEL_CUTOFF);
+            while (todo) {
+                const int j = 63 - (int)__builtin_clzll(todo);
+                todo &= ~(1ull << j);
+                const int e = sub + j;
+                const float4 a = s_a[e], b = s_b[e], c = s_c[e];
+                const uint32_t k1 = lo - rg.x + (uint32_t)e + 1u;
+                const bool cut = (cutb >> j) & 1ull;
+                float g_mx = 0.f, g_my = 0.f, g_ca = 0.f, g_cb = 0.f, g_cc = 0.f, g_op = 0.f;
+                float g_col[3] = {0.f, 0.f, 0.f};
+                float g_ray[12];
+                for (int r = 0; r < 12; ++r) g_ray[r] = 0.f;
+                bool contributed = false;
+                if (k1 <= nc) {
+                    const float dx = lpx - a.x, dy = lpy - a.y;
                     const float pw = entry_power(a, b, dx, dy);
                     const float G2 = __builtin_amdgcn_exp2f(pw);
                     const float a0 = b.y * G2;
                     Chord ch;
                     float w = 1.0f;
                     if (cut) {
-                        chord_eval(cr, dx, dy, p.ax, p.ay, (p.plane_enabled & RARA_CLIP_STRICT_MISS) != 0, ch);
+                        chord_eval(s_cut[e], dx, dy, p.ax, p.ay, strict, ch);
                         w = ch.w;
                     }
                     const float aw = a0 * w;
                     const float alpha = fminf(kAlphaMax, aw);
                     if (pw <= 0.0f && alpha >= kAlphaMin) {
                         contributed = true;
-                        T[q] = T[q] / (1.0f - alpha);
+                        const float inv1ma = __builtin_amdgcn_rcpf(1.0f - alpha);   // alpha <= 0.99
+                        T = T * inv1ma;
                         const float col[3] = {b.z, b.w, c.x};
                         float dLda = 0.0f;
                         for (int k = 0; k < 3; ++k) {
-                            ac[q][k] = la[q] * lc[q][k] + (1.0f - la[q]) * ac[q][k];
-                            lc[q][k] = col[k];
-                            dLda += (col[k] - ac[q][k]) * dC[q][k];
-                            g_col[k] += alpha * T[q] * dC[q][k];
+                            ac[k] = la * lc[k] + (1.0f - la) * ac[k];
+                            lc[k] = col[k];
+                            dLda += (col[k] - ac[k]) * dC[k];
+                            g_col[k] += alpha * T * dC[k];
                         }
-                        dLda *= T[q];
-                        la[q] = alpha;
-                        dLda += (-Tfin[q] / (1.0f - alpha)) * bgdot[q];
+                        dLda *= T;
+                        la = alpha;
+                        dLda += (-Tfin * inv1ma) * bgdot;
                         if (aw < kAlphaMax) {
                             const float dLda0 = dLda * w;
                             g_op += dLda0 * G2;
@@ -237,30 +274,42 @@ __device__ inline void blend_back_unit(const Splat* __restrict__ splats, const R
                             float ddx = dpow * (2.0f * a.z * dx + a.w * dy) * (1.0f / kLog2e);
                             float ddy = dpow * (a.w * dx + 2.0f * b.x * dy) * (1.0f / kLog2e);
                             if (cut && ch.kind == 4)
-                                chord_backward(cr, ch, dx, dy, p.ax, p.ay, dLda * a0, g_ray, ddx, ddy, pax, pay);
+                                chord_backward(s_cut[e], ch, dx, dy, p.ax, p.ay, dLda * a0, g_ray, ddx, ddy, pax, pay);
                             g_mx -= ddx;
                             g_my -= ddy;
                         }
                     }
                 }
-            }
-            if (__ballot(contributed) != 0ull) {
-                const float v9[9] = {g_mx, g_my, g_ca, g_cb, g_cc, g_op, g_col[0], g_col[1], g_col[2]};
+                if (__ballot(contributed) != 0ull) {
+                    const float v9[9] = {g_mx, g_my, g_ca, g_cb, g_cc, g_op, g_col[0], g_col[1], g_col[2]};
 #pragma unroll
-                for (int r = 0; r < 9; ++r) {
-                    const float s = wave_sum(v9[r]);
-                    if (lane == 0 && s != 0.0f) atomicAdd(acc + (int64_t)r * n + id, s);
-                }
-                if (cut) {
+                    for (int r = 0; r < 9; ++r) {
+                        const float sum = wave_sum(v9[r]);
+                        if (lane == 0 && sum != 0.0f) atomicAdd(&s_g[e][r], sum);
+                    }
+                    if (cut) {
 #pragma unroll
-                    for (int r = 0; r < 12; ++r) {
-                        const float s = wave_sum(g_ray[r]);
-                        if (lane == 0 && s != 0.0f) atomicAdd(acc + (int64_t)(A_D0 + r) * n + id, s);
+                        for (int r = 0; r < 12; ++r) {
+                            const float sum = wave_sum(g_ray[r]);
+                            if (lane == 0 && sum != 0.0f) atomicAdd(&s_g[e][A_D0 + r], sum);
+                        }
                     }
                 }
             }
         }
+        __syncthreads();
+        if ((uint32_t)tid < cnt) {
+            float* dst = slots + (int64_t)s_slot[tid] * kAccRows;
+            for (int r = 0; r < kAccRows; ++r) dst[r] = s_g[tid][r];
+        }
         hi = lo;
+    }
+    // entries after the last composited one: zero slots
+    for (uint32_t k = rg.x + kmax + (uint32_t)tid; k < rg.y; k += blockDim.x) {
+        const uint32_t id = vals[k];
+        const ushort4 rc = *reinterpret_cast<const ushort4*>(rect + 4 * (int64_t)id);
+        float* dst = slots + (int64_t)pair_slot(pair_start[id], rc, tx, ty) * kAccRows;
+        for (int r = 0; r < kAccRows; ++r) dst[r] = 0.0f;
     }
     const float sx = wave_sum(pax), sy = wave_sum(pay);
     if (lane == 0 && (sx != 0.0f || sy != 0.0f)) {
@@ -269,32 +318,30 @@ __device__ inline void blend_back_unit(const Splat* __restrict__ splats, const R
     }
 }
 
-__global__ __launch_bounds__(64) void blend_backward_kernel(const Splat* __restrict__ splats,
-                                                            const RayRec* __restrict__ rays,
-                                                            const uint32_t* __restrict__ vals,
-                                                            const uint2* __restrict__ ranges,
-                                                            const uint32_t* __restrict__ work,
-                                                            const int32_t* __restrict__ overflow, BackParams bp,
-                                                            const float* __restrict__ final_T,
-                                                            const uint32_t* __restrict__ n_contrib,
-                                                            const float* __restrict__ dL_dimage,
-                                                            float* __restrict__ acc, float* __restrict__ plane_acc)
+__global__ __launch_bounds__(256) void blend_backward_kernel(const Splat* __restrict__ splats,
+                                                             const RayRec* __restrict__ rays,
+                                                             const uint32_t* __restrict__ vals,
+                                                             const uint2* __restrict__ ranges,
+                                                             const uint32_t* __restrict__ work,
+                                                             const uint32_t* __restrict__ pair_start,
+                                                             const uint16_t* __restrict__ rect,
+                                                             const int32_t* __restrict__ overflow, BackParams bp,
+                                                             const float* __restrict__ final_T,
+                                                             const uint32_t* __restrict__ n_contrib,
+                                                             const float* __restrict__ dL_dimage,
+                                                             float* __restrict__ slots, float* __restrict__ plane_acc)
 {
     if (*overflow) return;
-    const int T = bp.rp.num_tiles;
-    uint32_t unit;
-    if (!unit_of_block(blockIdx.x, work, T, unit)) return;
-    const int tile = (int)(unit >> 3), mode = (int)(unit & 7u);
-    if (tile >= T || mode > 4) return;
-    __shared__ float4 s_a[kBatch], s_b[kBatch], s_c[kBatch];
-    __shared__ CutRec s_cut[kBatch];
-    const uint2 rg = ranges[tile];
-    if (mode == 4)
-        blend_back_unit<4>(splats, rays, vals, rg, tile, 0, bp, final_T, n_contrib, dL_dimage, acc, plane_acc, s_a,
-                           s_b, s_c, s_cut);
-    else
-        blend_back_unit<1>(splats, rays, vals, rg, tile, mode, bp, final_T, n_contrib, dL_dimage, acc, plane_acc,
-                           s_a, s_b, s_c, s_cut);
+    uint32_t tile;
+    if (!tile_of_block(blockIdx.x, work, bp.rp.num_tiles, tile)) return;
+    if (tile >= (uint32_t)bp.rp.num_tiles) return;
+    __shared__ float4 s_a[kBackBatch], s_b[kBackBatch], s_c[kBackBatch];
+    __shared__ CutRec s_cut[kBackBatch];
+    __shared__ uint32_t s_slot[kBackBatch];
+    __shared__ float s_g[kBackBatch][kAccRows];
+    __shared__ uint32_t s_red[4];
+    blend_back_tile(splats, rays, vals, pair_start, rect, ranges[tile], (int)tile, bp, final_T, n_contrib, dL_dimage,
+                    slots, plane_acc, s_a, s_b, s_c, s_cut, s_slot, s_g, s_red);
 }
 
 __global__ __launch_bounds__(256) void fill_zero_kernel(float* __restrict__ p, int64_t count)
@@ -382,7 +429,8 @@ struct GradPtrs {
 __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamParams cam, PlaneParams pl,
                                                                const uint8_t* __restrict__ label,
                                                                const uint32_t* __restrict__ tiles_touched,
-                                                               const float* __restrict__ acc, GradPtrs out,
+                                                               const uint32_t* __restrict__ pair_start,
+                                                               const float* __restrict__ slots, GradPtrs out,
                                                                float* __restrict__ plane_acc)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -392,8 +440,22 @@ __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamP
     if (i < n) {
         double dmu[3] = {0.0, 0.0, 0.0}, ds[3] = {0.0, 0.0, 0.0}, dqv[4] = {0.0, 0.0, 0.0, 0.0};
         double gop = 0.0;
-        const bool drawn = tiles_touched[i] > 0;
+        const uint32_t tt = tiles_touched[i];
+        const bool drawn = tt > 0;
         if (drawn) {
+            // this Gaussian's per-pair gradient slots are contiguous: sum them
+            const bool cutg = pl.enabled && label[i] == RARA_LABEL_CUTOFF;
+            double acc[kAccRows];
+            for (int r = 0; r < kAccRows; ++r) acc[r] = 0.0;
+            const float* src = slots + (int64_t)pair_start[i] * kAccRows;
+            for (uint32_t j = 0; j < tt; ++j, src += kAccRows) {
+#pragma unroll
+                for (int r = 0; r < 9; ++r) acc[r] += (double)src[r];
+                if (cutg) {
+#pragma unroll
+                    for (int r = 9; r < kAccRows; ++r) acc[r] += (double)src[r];
+                }
+            }
             const double mu[3] = {g.mean[i], g.mean[n + i], g.mean[2 * n + i]};
             const double s[3] = {g.scale[i], g.scale[n + i], g.scale[2 * n + i]};
             double q4[4] = {g.quat[i], g.quat[n + i], g.quat[2 * n + i], g.quat[3 * n + i]};
@@ -426,9 +488,9 @@ __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamP
             const double v11 = K1[0] * K1[0] + K1[1] * K1[1] + K1[2] * K1[2] + kDilation;
             const double det = v00 * v11 - v01 * v01;
             const double id2 = 1.0 / (det * det);
-            const double gmx = acc[A_MX * n + i], gmy = acc[A_MY * n + i];
-            const double gca = acc[A_CA * n + i], gcb = acc[A_CB * n + i], gcc = acc[A_CC * n + i];
-            gop = acc[A_OP * n + i];
+            const double gmx = acc[A_MX], gmy = acc[A_MY];
+            const double gca = acc[A_CA], gcb = acc[A_CB], gcc = acc[A_CC];
+            gop = acc[A_OP];
             // conic (a, b, c) = (v11, -v01, v00) / det  ->  Vhat
             const double dv00 = (-gca * v11 * v11 + gcb * v01 * v11 - gcc * v01 * v01) * id2;
             const double dv11 = (-gca * v01 * v01 + gcb * v01 * v00 - gcc * v00 * v00) * id2;
@@ -481,7 +543,7 @@ __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamP
             sh_values(g.sh_degree, dir[0], dir[1], dir[2], Y);
             for (int k = 0; k < ncoef; ++k) dY[k] = 0.0;
             for (int ch = 0; ch < 3; ++ch) {
-                const double gcol = acc[(A_R + ch) * n + i];
+                const double gcol = acc[A_R + ch];
                 double raw = 0.5;
                 for (int k = 0; k < ncoef; ++k) raw += Y[k] * (double)g.sh[((int64_t)k * 3 + ch) * n + i];
                 const bool pass = raw >= 0.0;
@@ -497,14 +559,14 @@ __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamP
             for (int a = 0; a < 3; ++a) dmu[a] += (ddir[a] - dir[a] * dd) / dlen;
 
             // whitened ray set-up of CUTOFF Gaussians
-            if (pl.enabled && label[i] == RARA_LABEL_CUTOFF) {
+            if (cutg) {
                 double gd0[3], ggx[3], ggy[3];
                 for (int a = 0; a < 3; ++a) {
-                    gd0[a] = acc[(A_D0 + a) * n + i];
-                    ggx[a] = acc[(A_GX + a) * n + i];
-                    ggy[a] = acc[(A_GY + a) * n + i];
+                    gd0[a] = acc[A_D0 + a];
+                    ggx[a] = acc[A_GX + a];
+                    ggy[a] = acc[A_GY + a];
                 }
-                const double gz = acc[A_Z * n + i], gdep = acc[A_DEP * n + i], gg0 = acc[A_G0 * n + i];
+                const double gz = acc[A_Z], gdep = acc[A_DEP], gg0 = acc[A_G0];
                 const double v0[3] = {dvec[0] * iz, dvec[1] * iz, dvec[2] * iz};
                 double dv0[3] = {pl.n[0] * gg0, pl.n[1] * gg0, pl.n[2] * gg0};
                 for (int a = 0; a < 3; ++a) {
@@ -588,35 +650,36 @@ __global__ void plane_finalize_kernel(CamParams cam, PlaneParams pl, double len,
 
 }  // namespace
 
-size_t backward_workspace_bytes(int64_t n, int32_t width, int32_t height)
+size_t backward_workspace_bytes(int64_t n, int64_t pair_capacity, int32_t width, int32_t height)
 {
+    (void)n;
     (void)width;
     (void)height;
-    const size_t acc = ((size_t)kAccRows * (size_t)(n > 0 ? n : 1) * 4 + 255) & ~size_t(255);
-    return acc + 256;
+    const size_t slot_bytes = ((size_t)kAccRows * (size_t)(pair_capacity > 0 ? pair_capacity : 1) * 4 + 255) &
+                              ~size_t(255);
+    return slot_bytes + 256;
 }
 
 hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl, double plane_len,
-                           const ProjPtrs& proj, const rara_binned& bins, const RenderParams& rp,
-                           const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
-                           const rara_grads& grads, void* workspace, hipStream_t s)
+                           const ProjPtrs& proj, const rara_binned& bins, int64_t pair_capacity,
+                           const RenderParams& rp, const float* final_T, const uint32_t* n_contrib,
+                           const float* dL_dimage, const rara_grads& grads, void* workspace, hipStream_t s)
 {
-    const int64_t n = g.n > 0 ? g.n : 1;
-    float* acc = static_cast<float*>(workspace);
-    const size_t acc_bytes = ((size_t)kAccRows * (size_t)n * 4 + 255) & ~size_t(255);
-    float* plane_acc = reinterpret_cast<float*>(static_cast<char*>(workspace) + acc_bytes);
-    const int64_t count = (int64_t)(acc_bytes / 4) + kPlaneAcc;
-    int64_t blocks = (count + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, acc, count);
+    float* slots = static_cast<float*>(workspace);
+    const size_t slot_bytes = ((size_t)kAccRows * (size_t)(pair_capacity > 0 ? pair_capacity : 1) * 4 + 255) &
+                              ~size_t(255);
+    float* plane_acc = reinterpret_cast<float*>(static_cast<char*>(workspace) + slot_bytes);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(1), dim3(256), 0, s, plane_acc, (int64_t)kPlaneAcc);
     BackParams bp{rp, g.n};
-    hipLaunchKernelGGL(blend_backward_kernel, dim3((unsigned)work_grid(rp.num_tiles)), dim3(64), 0, s, proj.splat,
-                       proj.ray, bins.vals, reinterpret_cast<const uint2*>(bins.ranges), bins.work, bins.overflow, bp,
-                       final_T, n_contrib, dL_dimage, acc, plane_acc);
+    if (g.n > 0)
+        hipLaunchKernelGGL(blend_backward_kernel, dim3((unsigned)tiles_grid(rp.num_tiles)), dim3(256), 0, s,
+                           proj.splat, proj.ray, bins.vals, reinterpret_cast<const uint2*>(bins.ranges), bins.work,
+                           bins.pair_start, proj.rect, bins.overflow, bp, final_T, n_contrib, dL_dimage, slots,
+                           plane_acc);
     if (g.n > 0) {
         GradPtrs gp{grads.mean, grads.scale, grads.quat, grads.opacity, grads.sh};
         hipLaunchKernelGGL(project_backward_kernel, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g, cam, pl,
-                           proj.label, proj.tiles_touched, acc, gp, plane_acc);
+                           proj.label, proj.tiles_touched, bins.pair_start, slots, gp, plane_acc);
     }
     hipLaunchKernelGGL(plane_finalize_kernel, dim3(1), dim3(64), 0, s, cam, pl, plane_len, plane_acc, grads.plane);
     return hipGetLastError();

@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ 
                                                    const int64_t* __restrict__ count,
                                                    const uint32_t* __restrict__ block_off, int tiles_x,
                                                    const int32_t* __restrict__ overflow, uint32_t* __restrict__ tkeys,
-                                                   uint32_t* __restrict__ tvals)
+                                                   uint32_t* __restrict__ tvals, uint32_t* __restrict__ pair_start)
 {
     __shared__ uint32_t s_end[kScanBlock];   // inclusive end of each Gaussian's pairs inside the workgroup
     __shared__ uint32_t s_id[kScanBlock];
@@ -156,11 +156,12 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ 
     uint32_t total;
     const uint32_t pre = block_ballot_scan(v, total);
     if (*overflow || total == 0u) return;   // uniform over the workgroup
+    const uint32_t base = block_off[blockIdx.x];
+    if (v) pair_start[id] = base + pre;     // first pair of this Gaussian, emission order
     s_end[tid] = pre + v;
     s_id[tid] = id;
     s_rc[tid] = v ? *reinterpret_cast<const ushort4*>(rect + 4 * (int64_t)id) : make_ushort4(0, 0, 1, 1);
     __syncthreads();
-    const uint32_t base = block_off[blockIdx.x];
     for (uint32_t e = (uint32_t)tid; e < total; e += kScanBlock) {
         // owner = number of Gaussians whose pairs all precede e (s_end is non-decreasing, s_end[255] = total)
         int own = 0;
@@ -319,7 +320,7 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
     uint32_t* vb = last_reads_a ? alias_v : ws.tvals;
     if (n > 0)
         hipLaunchKernelGGL(emit_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, proj.rect, ws.dvals[0],
-                           ws.dcount, ws.block_sums, cam.tiles_x, out.overflow, ka, va);
+                           ws.dcount, ws.block_sums, cam.tiles_x, out.overflow, ka, va, out.pair_start);
     // 4. tile digits; the last pass writes the 64-bit keys and the values
     return sort_passes(ka, va, kb, vb, tile_passes, out.num_pairs, out.overflow, ws.tile_blocks, ws.hist,
                        ws.digit_totals, out.keys, out.vals, proj.depth, s);

@@ -124,7 +124,7 @@ struct BinWorkspace {
 };
 
 size_t bin_workspace_layout(int64_t n, int64_t cap, BinWorkspace* ws, char* base);
-size_t backward_workspace_bytes(int64_t n, int32_t width, int32_t height);
+size_t backward_workspace_bytes(int64_t n, int64_t pair_capacity, int32_t width, int32_t height);
 
 // ---- launch helpers (each returns the hipGetLastError of its launches) ----
 hipError_t launch_preprocess(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl, const ProjPtrs& out,
@@ -146,7 +146,7 @@ bool make_cam_params(const rara_camera* c, CamParams* p);
 bool make_plane_params(const rara_plane* pl, PlaneParams* p);
 RenderParams make_render_params(const CamParams& cp, const PlaneParams& pp, const float* bg);
 hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl, double plane_len,
-                           const ProjPtrs& proj, const rara_binned& bins, const RenderParams& rp,
+                           const ProjPtrs& proj, const rara_binned& bins, int64_t pair_capacity, const RenderParams& rp,
                            const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
                            const rara_grads& grads, void* workspace, hipStream_t s);
 hipError_t launch_blend(const Splat* splat, const RayRec* ray, const rara_binned& bins, const RenderParams& p,

@@ -88,6 +88,7 @@ class BinBuffers:
         self.num_pairs = torch.zeros(1, dtype=torch.int64, device=device)
         self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
         self.work = torch.empty(4 * tiles + 1, dtype=torch.int32, device=device)
+        self.pair_start = torch.empty(max(int(n), 1), dtype=torch.int32, device=device)
         self.ws_bytes = B.workspace_bytes(B.RARA_WS_BIN_SORT, n, self.capacity, width, height)
         if self.ws_bytes == 0:
             raise ValueError("invalid bin/sort workspace request")
@@ -98,10 +99,11 @@ class BinBuffers:
         b.keys, b.vals, b.ranges = _ptr(self.keys), _ptr(self.vals), _ptr(self.ranges)
         b.num_pairs, b.overflow = _ptr(self.num_pairs), _ptr(self.overflow)
         b.work = _ptr(self.work)
+        b.pair_start = _ptr(self.pair_start)
         return b
 
     def nbytes(self) -> int:
-        return self.capacity * 12 + self.ranges.numel() * 4 + self.ws_bytes
+        return self.capacity * 12 + self.ranges.numel() * 4 + self.pair_start.numel() * 4 + self.ws_bytes
 
 
 class ImageBuffers:

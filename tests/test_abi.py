@@ -123,6 +123,18 @@ def test_argument_validation_before_any_launch(B):
         == B.RARA_ERR_INVALID   # workspace too small
     assert lib.rara_bin_sort(ctypes.byref(out), 0, ctypes.byref(cam), 0, fake, 1 << 30, ctypes.byref(bins), None) \
         == B.RARA_ERR_INVALID   # capacity < 1
+    # backward: pair capacity and pair_start are required
+    grads = B.Grads()
+    grads.mean = grads.scale = grads.quat = grads.opacity = grads.sh = grads.plane = 0x1000
+    bins.pair_start = 0
+    for cap, ps in [(0, 0x1000), (1 << 30, 0x1000), (100, 0)]:
+        bins.pair_start = ps
+        assert lib.rara_render_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(pl), (ctypes.c_float * 3)(),
+                                        ctypes.byref(out), ctypes.byref(bins), cap, fake, fake, fake,
+                                        ctypes.byref(grads), fake, 1 << 40, None) == B.RARA_ERR_INVALID
+    bins.pair_start = 0x1000
+    assert B.workspace_bytes(B.RARA_WS_BACKWARD, 1000, 0, 128, 128) == 0
+    assert B.workspace_bytes(B.RARA_WS_BACKWARD, 1000, 2000, 128, 128) >= 2000 * 21 * 4
     # render: null outputs
     bg = (ctypes.c_float * 3)(0, 0, 0)
     assert lib.rara_render(ctypes.byref(out), 0, ctypes.byref(bins), ctypes.byref(cam), ctypes.byref(pl), bg, None,

@@ -295,7 +295,10 @@ def serve_bench(args):
 def measure(sc, frames, args, reps, label):
     """Frames per second over the frame list with clipping (RaRa), without a
     plane (Original) and with hard clipping (Hard), each the median of `reps`
-    timed sweeps of args.steps frames; per-stage times and work counts."""
+    timed sweeps of args.steps frames, rendered two ways: one frame after the
+    other on one stream ("serial"), and with two frames in flight
+    (renderer.FramePipeline: the blend of frame i beside the preprocess and
+    binning of frame i+1).  Per-stage times and work counts."""
     import torch
     from paper_2506_20202_amd import renderer as R
     dev = torch.device("cuda:0")
@@ -308,23 +311,32 @@ def measure(sc, frames, args, reps, label):
     if args.no_plain:
         del variants["original"], variants["hard"]
     # capacity from one pass over every frame (outside the timed region)
-    fr = R.Frame(sc.n, W, H, 8 * sc.n, dev)
+    fr = R.Frame(sc.n, W, H, 8 * sc.n, dev, walked=False)
     maxP = 0
     for name, fl in variants.items():
         for cam, pl in (fl if name == "rara" else fl[:: max(1, len(fl) // 16)]):
             R.render_checked(ds, fr, cam, pl)
             maxP = max(maxP, int(fr.bins.num_pairs.item()))
     fr.grow(int(maxP * 1.05) + 4096)
+    pipe = R.FramePipeline(ds, W, H, fr.capacity, walked=False)
+    torch.cuda.synchronize()
     print(f"[bench] {label}: max pairs {maxP}, capacity {fr.capacity}", file=sys.stderr, flush=True)
 
-    def run(frame_list, k):
+    def run_serial(frame_list, k):
         for i in range(k):
             cam, pl = frame_list[i % len(frame_list)]
             R.enqueue_frame(ds, fr, cam, pl)
 
+    def run_pipe(frame_list, k):
+        pipe.start(stream)
+        for i in range(k):
+            cam, pl = frame_list[i % len(frame_list)]
+            pipe.submit(cam, pl)
+        pipe.join(stream)
+
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    fps = {}
-    for name, fl in variants.items():
+
+    def timed(run, fl, check):
         run(fl, args.warmup)
         torch.cuda.synchronize()
         vals = []
@@ -335,15 +347,25 @@ def measure(sc, frames, args, reps, label):
             ev1.record(stream)
             torch.cuda.synchronize()
             vals.append(args.steps / (ev0.elapsed_time(ev1) / 1e3))
-            assert int(fr.bins.overflow.item()) == 0
-        fps[name] = {"median": float(np.median(vals)), "reps": vals}
-        print(f"[bench] {label} {name}: {fps[name]['median']:.1f} FPS (median of {reps})", file=sys.stderr, flush=True)
+            assert not check()
+        return {"median": float(np.median(vals)), "reps": vals}
+
+    fps, fps_serial = {}, {}
+    for name, fl in variants.items():
+        fps_serial[name] = timed(run_serial, fl, lambda: int(fr.bins.overflow.item()))
+        fps[name] = timed(run_pipe, fl, pipe.overflowed)
+        print(f"[bench] {label} {name}: {fps[name]['median']:.1f} FPS two in flight, "
+              f"{fps_serial[name]['median']:.1f} serial (medians of {reps})", file=sys.stderr, flush=True)
+    del pipe
 
     # per-stage times (HIP events on the launch stream) and work counts; the
     # render (one blend launch) is timed over kRenderRepeat back-to-back
     # launches on the same binned frame, so its figure is the kernel's own
-    # duration rather than that of an isolated launch
+    # duration rather than that of an isolated launch.  The work counts come
+    # from one more launch into images with the n_walked output, untimed.
     kRenderRepeat = 4
+    frw = R.Frame(sc.n, W, H, 1, dev, walked=True)
+    frw.proj, frw.bins = fr.proj, fr.bins
     stage_ms = {"preprocess": 0.0, "bin_sort": 0.0, "render": 0.0}
     E_tot, Ecut_tot, P_tot, n_live = 0, 0, 0, 0
     nst = len(frames)
@@ -358,11 +380,12 @@ def measure(sc, frames, args, reps, label):
         for _ in range(kRenderRepeat):
             R.enqueue_frame(ds, fr, cam, pl, stages=("render",))
         evs[3].record(stream)
+        R.enqueue_frame(ds, frw, cam, pl, stages=("render",))
         torch.cuda.synchronize()
         stage_ms["preprocess"] += evs[0].elapsed_time(evs[1])
         stage_ms["bin_sort"] += evs[1].elapsed_time(evs[2])
         stage_ms["render"] += evs[2].elapsed_time(evs[3]) / kRenderRepeat
-        E, Ec = count_evals(fr, sc.n)
+        E, Ec = count_evals(frw, sc.n)
         E_tot += E
         Ecut_tot += Ec
         P_tot += int(fr.bins.num_pairs.item())
@@ -371,11 +394,12 @@ def measure(sc, frames, args, reps, label):
         stage_ms[k] /= nst
     render_s = stage_ms["render"] / 1e3
     flops = (E_tot * FLOPS_EVAL + Ecut_tot * FLOPS_CUT) / nst
-    out = {"fps": fps, "stage_ms": stage_ms, "pairs_per_frame": P_tot / nst, "live_gaussians_per_frame": n_live / nst,
+    out = {"fps": fps, "fps_serial": fps_serial, "stage_ms": stage_ms, "pairs_per_frame": P_tot / nst,
+           "live_gaussians_per_frame": n_live / nst,
            "evals_per_frame": E_tot / nst, "cutoff_evals_per_frame": Ecut_tot / nst,
            "geval_per_s": E_tot / nst / render_s / 1e9, "flops_per_launch": flops,
            "blend_tflops": flops / render_s / 1e12, "pair_capacity": fr.capacity}
-    del fr, ds
+    del fr, frw, ds
     torch.cuda.empty_cache()
     return out
 
@@ -550,10 +574,12 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": dict(desc, parallelism="single GPU", pair_capacity=main_m["pair_capacity"],
-                       timing=f"median of {args.reps} sweeps of {args.steps} frames"),
+                       timing=f"median of {args.reps} sweeps of {args.steps} frames, two frames in flight"),
         "plain_fps": plain, "hard_fps": hard, "clipped_over_plain_frame_time": (plain / fps) if plain else None,
         "table1_protocol": {"original_fps": plain, "hard_fps": hard, "rara_fps": fps},
         "fps_reps": main_m["fps"]["rara"]["reps"],
+        "serial": {k: v["median"] for k, v in main_m["fps_serial"].items()},
+        "serial_ms_per_frame": 1e3 / main_m["fps_serial"]["rara"]["median"],
         "stage_ms": main_m["stage_ms"], "pairs_per_frame": main_m["pairs_per_frame"],
         "live_gaussians_per_frame": main_m["live_gaussians_per_frame"], "geval_per_s": main_m["geval_per_s"],
         "roofline": roofline, "cpu_baseline": cpu, "serving": serving, "secondary": secondary or None,

@@ -26,6 +26,19 @@ __device__ inline uint32_t lanes_below(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Sort tile of workgroup b.  Workgroups go to the 8 XCDs round robin (b mod 8)
+// and every XCD takes one contiguous run of the live tiles, so neighbouring
+// tiles -- whose histogram entries share cache lines and whose digit runs are
+// written next to each other -- are merged in one L2.  The grid is a multiple
+// of 8; -1 for a workgroup without a tile.
+__device__ inline int64_t sort_tile_of_block(int64_t b, int64_t tiles)
+{
+    const int64_t per = (tiles + 7) / 8;
+    const int64_t j = b >> 3;
+    const int64_t t = (b & 7) * per + j;
+    return (j < per && t < tiles) ? t : -1;
+}
+
 // Lanes of the wave whose (valid) digit equals this lane's digit.
 __device__ inline uint64_t match_digit(uint32_t digit, bool valid)
 {
@@ -46,8 +59,9 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
 {
     if (overflow && *overflow) return;
     const int64_t P = *num_items;
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    if (base >= P) return;
+    const int64_t tile = sort_tile_of_block(blockIdx.x, (P + kSortTile - 1) / kSortTile);
+    if (tile < 0) return;
+    const int64_t base = tile * kSortTile;
     __shared__ uint32_t counts[kWaves][kRadix];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int k = threadIdx.x; k < kWaves * kRadix; k += kSortThreads) (&counts[0][0])[k] = 0u;
@@ -64,7 +78,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
     for (int d = threadIdx.x; d < kRadix; d += kSortThreads) {
         uint32_t t = 0;
         for (int w = 0; w < kWaves; ++w) t += counts[w][d];
-        hist[(int64_t)d * stride + blockIdx.x] = t;
+        hist[(int64_t)d * stride + tile] = t;
     }
 }
 
@@ -113,8 +127,9 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 {
     if (overflow && *overflow) return;
     const int64_t P = *num_items;
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    if (base >= P) return;
+    const int64_t tile = sort_tile_of_block(blockIdx.x, (P + kSortTile - 1) / kSortTile);
+    if (tile < 0) return;
+    const int64_t base = tile * kSortTile;
 
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
@@ -127,7 +142,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // this tile's digit offsets do not depend on the keys: issue their loads first
     const uint32_t gtot = digit_totals[tid];
-    const uint32_t tile_off = hist[(int64_t)tid * stride + blockIdx.x];
+    const uint32_t tile_off = hist[(int64_t)tid * stride + tile];
     for (int k = tid; k < kWaves * kRadix; k += kSortThreads) (&counts[0][0])[k] = 0u;
     __syncthreads();
 
@@ -229,6 +244,7 @@ hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, i
 {
     // pass p reads (ka, va) when p is even and (kb, vb) when odd; with final_keys
     // the last pass writes (final_keys, final_vals) instead of the other buffer
+    const unsigned grid = (unsigned)((blocks + 7) / 8 * 8);   // see sort_tile_of_block
     for (int p = 0; p < passes; ++p) {
         const bool even = (p & 1) == 0;
         const uint32_t* kin = even ? ka : kb;
@@ -236,15 +252,15 @@ hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, i
         uint32_t* kout = even ? kb : ka;
         uint32_t* vout = even ? vb : va;
         const int shift = p * kRadixBits;
-        hipLaunchKernelGGL(radix_upsweep_kernel, dim3((unsigned)blocks), dim3(kSortThreads), 0, s, kin, count, overflow,
+        hipLaunchKernelGGL(radix_upsweep_kernel, dim3(grid), dim3(kSortThreads), 0, s, kin, count, overflow,
                            shift, hist, blocks);
         hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadix), dim3(256), 0, s, hist, blocks, count, overflow,
                            digit_totals);
         if (final_keys && p == passes - 1)
-            hipLaunchKernelGGL(radix_scatter_kernel<true>, dim3((unsigned)blocks), dim3(kSortThreads), 0, s, kin, vin,
+            hipLaunchKernelGGL(radix_scatter_kernel<true>, dim3(grid), dim3(kSortThreads), 0, s, kin, vin,
                                kout, final_vals, count, overflow, shift, hist, blocks, digit_totals, final_keys, depth);
         else
-            hipLaunchKernelGGL(radix_scatter_kernel<false>, dim3((unsigned)blocks), dim3(kSortThreads), 0, s, kin, vin,
+            hipLaunchKernelGGL(radix_scatter_kernel<false>, dim3(grid), dim3(kSortThreads), 0, s, kin, vin,
                                kout, vout, count, overflow, shift, hist, blocks, digit_totals, nullptr, nullptr);
     }
     return hipGetLastError();

@@ -166,6 +166,75 @@ def render_checked(scene: DeviceScene, frame: Frame, cam, plane, bg=(0.0, 0.0, 0
     return frame.out
 
 
+class FramePipeline:
+    """Renders a sequence of frames of one shape with ``depth`` frames in
+    flight over two streams: preprocess and binning of frame i+1 run on one
+    stream while the blend of frame i runs on the other, so the latency-bound
+    sort kernels fill the CUs the blend leaves idle.  Frame i uses buffer set
+    i mod depth, whose preprocess waits for the blend that last read the set.
+    Both streams keep the default priority."""
+
+    def __init__(self, scene: DeviceScene, width: int, height: int, capacity: int, depth: int = 2,
+                 walked: bool = True):
+        dev = scene.mean.device
+        self.scene = scene
+        self.frames = [Frame(scene.n, width, height, capacity, dev, walked) for _ in range(depth)]
+        self.bin_stream = torch.cuda.Stream(dev)
+        self.blend_stream = torch.cuda.Stream(dev)
+        self.binned = [torch.cuda.Event() for _ in range(depth)]
+        self.blended = [torch.cuda.Event() for _ in range(depth)]
+        self.count = 0
+        self.start()
+
+    def start(self, stream=None):
+        """Order the pipeline after the work already on ``stream``."""
+        if stream is None:
+            stream = torch.cuda.current_stream(self.scene.mean.device)
+        self.bin_stream.wait_stream(stream)
+        self.blend_stream.wait_stream(stream)
+
+    def submit(self, cam, plane, bg=(0.0, 0.0, 0.0), consume=None) -> Frame:
+        """Enqueue one frame and return its Frame.  Its outputs are valid once
+        the blend stream has passed the frame (``join``) and until the same
+        set is reused ``depth`` submissions later.  ``consume(frame)``, if
+        given, is called with the blend stream as torch's current stream,
+        after the render: work it enqueues (a copy of the image, a loss) runs
+        before the set can be reused, without waiting for later frames."""
+        k = self.count % len(self.frames)
+        fr = self.frames[k]
+        if self.count >= len(self.frames):
+            self.bin_stream.wait_event(self.blended[k])
+        enqueue_frame(self.scene, fr, cam, plane, bg, stream=self.bin_stream, stages=("pre", "bin"))
+        self.binned[k].record(self.bin_stream)
+        self.blend_stream.wait_event(self.binned[k])
+        enqueue_frame(self.scene, fr, cam, plane, bg, stream=self.blend_stream, stages=("render",))
+        if consume is not None:
+            with torch.cuda.stream(self.blend_stream):
+                consume(fr)
+        self.blended[k].record(self.blend_stream)
+        self.count += 1
+        return fr
+
+    def join(self, stream=None):
+        """Order ``stream`` after every submitted frame."""
+        if stream is None:
+            stream = torch.cuda.current_stream(self.scene.mean.device)
+        stream.wait_stream(self.bin_stream)
+        stream.wait_stream(self.blend_stream)
+
+    def grow(self, capacity: int):
+        torch.cuda.synchronize(self.scene.mean.device)
+        for fr in self.frames:
+            fr.grow(capacity)
+
+    @property
+    def capacity(self) -> int:
+        return self.frames[0].capacity
+
+    def overflowed(self) -> bool:
+        return any(int(fr.bins.overflow.item()) for fr in self.frames)
+
+
 def splat_fields(proj: ProjectedBuffers) -> dict:
     """Decode the 48-byte splat records (host copy) for inspection and tests."""
     import numpy as np

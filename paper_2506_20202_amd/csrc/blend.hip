@@ -32,18 +32,22 @@ namespace rara {
 namespace {
 
 // One pixel's front-to-back update with one list entry, straight-line and
-// without lane masks.  alpha = min(0.99, a0 w), a0 = delta 2^pw; entries with
-// pw > 0 or alpha below the pixel's threshold `thr` are skipped (thr = 1/255
-// while the pixel is live; a finished pixel has thr = 2, above any alpha, so
-// it is left unchanged).  An entry that would take T below 1e-4 finishes the
+// without lane masks.  alpha = min(0.99, a0 w), a0 = delta 2^pw (0 for
+// pw > 0); entries with alpha below the pixel's threshold `thr` are skipped
+// (thr = 1/255 while the pixel is live; a finished pixel has thr = 2, above
+// any alpha, so it is left unchanged).  An entry that would take T below 1e-4 finishes the
 // pixel without being composited: T keeps its value, the final transmittance.
 // A live pixel always has T >= 1e-4, so a skipped entry (alpha = 0, new
 // T = T) can never finish it.
-__device__ inline void composite(float pw, float op, float w, float cr, float cg, float cb, uint32_t k1, float& T,
-                                 float& thr, float& C0, float& C1, float& C2, uint32_t& last, uint32_t& walked)
+__device__ inline float entry_a0(float pw, float op)
 {
-    const float e = __builtin_amdgcn_exp2f(pw > 0.0f ? -INFINITY : pw);
-    float alpha = fminf(kAlphaMax, (op * e) * w);
+    return op * __builtin_amdgcn_exp2f(pw > 0.0f ? -INFINITY : pw);
+}
+
+__device__ inline void composite(float a0, float w, float cr, float cg, float cb, uint32_t k1, float& T, float& thr,
+                                 float& C0, float& C1, float& C2, uint32_t& last, uint32_t& walked)
+{
+    float alpha = fminf(kAlphaMax, a0 * w);
     alpha = alpha >= thr ? alpha : 0.0f;
     const float tT = fmaf(-alpha, T, T);
     const bool term = tT < kTMin;
@@ -137,10 +141,15 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
                     const float4 a = s_a[e], b = s_b[e];
                     const float cb_ = s_c[e].x;
                     const float dx = lpx - a.x, dy = lpy - a.y;
-                    const float pw = entry_power(a, b, dx, dy);
+                    const float a0 = entry_a0(entry_power(a, b, dx, dy), b.y);
                     float w = 1.0f;
-                    if ((cutb >> j) & 1ull) w = chord_weight(s_cut[e], dx, dy, p.ax, p.ay, strict);
-                    composite(pw, b.y, w, b.z, b.w, cb_, kofs + e, T, thr, C0, C1, C2, last, walked);
+                    if ((cutb >> j) & 1ull) {
+                        // alpha <= a0 (w <= 1): when no pixel can reach its threshold the
+                        // entry changes nothing and its weight is not needed
+                        if (__ballot(a0 >= thr) == 0ull) continue;
+                        w = chord_weight_flat(s_cut[e], dx, dy, p.ax, p.ay, strict);
+                    }
+                    composite(a0, w, b.z, b.w, cb_, kofs + e, T, thr, C0, C1, C2, last, walked);
                 }
                 live = __ballot(thr < 1.0f) != 0ull;
                 if (!live) break;

@@ -87,6 +87,45 @@ __device__ inline float chord_weight(const CutRec& k, float dx, float dy, float 
     return c.w;
 }
 
+// chord_eval's weight without branches, for the forward: every case's value
+// is formed with chord_eval's own operations on the same inputs, and the case
+// is then selected, so the result is chord_eval's w bit for bit.  A wave whose
+// pixels fall in different cases (rays crossing the silhouette, the near-root
+// boundary) takes one straight path instead of each case in turn.
+__device__ inline float chord_weight_flat(const CutRec& k, float dx, float dy, float ax, float ay, bool strict)
+{
+    const float gx[3] = {k.a.w, k.b.x, k.b.y};
+    const float gy[3] = {k.b.z, k.b.w, k.c.x};
+    const float d0[3] = {k.a.x, k.a.y, k.a.z};
+    const float z = k.c.y, dep = k.c.z, g0 = k.c.w;
+    float D[3], P[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float e = fmaf(gx[i], dx, gy[i] * dy);
+        D[i] = d0[i] + e;
+        P[i] = z * e;
+    }
+    const float DD = fmaf(D[0], D[0], fmaf(D[1], D[1], D[2] * D[2]));
+    const float PD = fmaf(P[0], D[0], fmaf(P[1], D[1], P[2] * D[2]));
+    const float iDD = __builtin_amdgcn_rcpf(DD);
+    const float sm = -PD * iDD;
+    float Q[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Q[i] = fmaf(sm, D[i], P[i]);
+    const float h2 = kKappa2 - fmaf(Q[0], Q[0], fmaf(Q[1], Q[1], Q[2] * Q[2]));
+    const float u = fmaf(ax, dx, ay * dy);
+    const float gg = g0 + u;
+    const float phim = fmaf(sm, gg, fmaf(z, u, dep));
+    const float step = phim >= 0.0f ? 1.0f : 0.0f;                  // cases 2 and 5
+    const float hs = __builtin_amdgcn_sqrtf(h2 * iDD);              // NaN for a miss: not selected
+    const float inv = __builtin_amdgcn_rcpf((2.0f * fabsf(gg)) * hs);
+    float w = __builtin_amdgcn_fmed3f(fmaf(phim, inv, 0.5f), 0.0f, 1.0f);   // cases 3, 4
+    w = gg == 0.0f ? step : w;                                      // case 2
+    w = (z + sm) - hs < 0.0f ? 1.0f : w;                            // case 1
+    const float miss = (strict && h2 < 0.0f) ? step : 1.0f;         // cases 5 and 0
+    return h2 > 0.0f ? w : miss;
+}
+
 // Whether the alpha >= 1/255 region of an entry can reach the pixel centres
 // [qx, qx + 7] x [qy, qy + 7] (tile coordinates).  alpha >= 1/255 needs the
 // conic form q(d) = ca dx^2 + 2 cb dx dy + cc dy^2 at d = pixel - centre to be

@@ -171,20 +171,27 @@ _hip_runtime = None
 
 
 def new_stream(device) -> "torch.cuda.ExternalStream":
-    """A HIP stream of its own on ``device`` (non-blocking, default priority),
-    outside torch's stream pool; release it with ``destroy_stream``.  A frame
-    pipeline on the first streams torch's pool hands out ran 9 % slower than
-    on fresh streams."""
+    """A HIP stream with a hardware queue of its own on ``device`` (default
+    priority); release it with ``destroy_stream``.  It is created with a CU
+    mask that enables every CU, which gives the stream a dedicated queue: plain
+    streams share the process's four queues in an order set by the streams
+    created and destroyed before them, and a frame pipeline on three of them
+    ran at 2500-3600 frames/s depending on that history (3570-3600 on
+    dedicated queues)."""
     global _hip_runtime
     if _hip_runtime is None:
         _hip_runtime = ctypes.CDLL("libamdhip64.so")
-        _hip_runtime.hipStreamCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+        _hip_runtime.hipExtStreamCreateWithCUMask.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32,
+                                                              ctypes.POINTER(ctypes.c_uint32)]
         _hip_runtime.hipStreamDestroy.argtypes = [ctypes.c_void_p]
+    ncu = torch.cuda.get_device_properties(device).multi_processor_count
+    words = (ncu + 31) // 32
+    mask = (ctypes.c_uint32 * words)(*([0xFFFFFFFF] * words))
     h = ctypes.c_void_p()
     with torch.cuda.device(device):
-        status = _hip_runtime.hipStreamCreateWithFlags(ctypes.byref(h), 1)   # hipStreamNonBlocking
+        status = _hip_runtime.hipExtStreamCreateWithCUMask(ctypes.byref(h), words, mask)
     if status != 0:
-        raise RuntimeError(f"hipStreamCreateWithFlags failed ({status})")
+        raise RuntimeError(f"hipExtStreamCreateWithCUMask failed ({status})")
     return torch.cuda.ExternalStream(h.value, device=device)
 
 
@@ -199,11 +206,10 @@ class FramePipeline:
     set i mod streams, so frames on different streams overlap (one frame's
     latency-bound sort kernels and the tail of another's blend fill the CUs a
     single frame leaves idle) while each stream keeps its frames in order and
-    reuses its set only after its previous frame.  The streams are HIP streams
-    of their own at the default priority.  A process has four hardware queues
-    (HIP's default) and torch's null stream holds one: three streams keep one
-    queue each (on the 1080p sweep: 3 streams 3630 frames/s, 2 streams 3210,
-    4 streams 3050, one frame at a time 2270)."""
+    reuses its set only after its previous frame.  Each stream has a hardware
+    queue of its own (``new_stream``) and the default priority.  On the 1080p
+    sweep: 3 streams 3570-3600 frames/s, 2 streams 3210, 4 streams 2760,
+    6 streams 3060, one frame at a time 2260."""
 
     def __init__(self, scene: DeviceScene, width: int, height: int, capacity: int, streams: int = 3,
                  walked: bool = True):

@@ -91,6 +91,7 @@ def parse():
                     help="HBM for serving slots beyond the resident scenes")
     ap.add_argument("--serve-slots", type=int, default=64, help="slots kept (buffers and captured graphs)")
     ap.add_argument("--serve-inflight", type=int, default=8, help="frames running at once")
+    ap.add_argument("--serve-lanes", type=int, default=3, help="streams (hardware queues) the frames run on")
     ap.add_argument("--profile-steps", type=int, default=0, help="only run this many frames (for profilers)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="with --profile-steps: also run one plain 256 MiB device copy (counter calibration)")
@@ -230,7 +231,7 @@ def serve_bench(args):
             ("C", scenes.multilayer_scene(33, per_shell=400_000, sh_degree=3))]
     sizes = [(512, 512), (1024, 1024), (1920, 1080), (2048, 2048)]
     resident = 0
-    eng = Engine(hbm_budget=0, max_slots=args.serve_slots, max_inflight=args.serve_inflight)
+    eng = Engine(hbm_budget=0, max_slots=args.serve_slots, max_inflight=args.serve_inflight, lanes=args.serve_lanes)
     for name, sc in defs:
         eng.add_scene(name, sc)
     resident = eng.ex.resident_bytes()
@@ -291,7 +292,7 @@ def serve_bench(args):
                         "512^2/1024^2/1920x1080/2048^2, camera on a radius-5 sphere, random plane",
             "requests": len(stream), "saturation_req_s": sat, "offered_load_req_s": rate,
             "load_fraction": args.serve_load, "hbm_budget_gib": budget / 2 ** 30, "max_slots": args.serve_slots,
-            "max_inflight": args.serve_inflight,
+            "max_inflight": args.serve_inflight, "lanes": args.serve_lanes,
             "graphs": True,
             "clipped": clipped, "plain": plain}
 

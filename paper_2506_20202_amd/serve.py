@@ -222,15 +222,22 @@ class Scheduler:
 
 class GpuExecutor:
     """Slots on the GPU: per slot a Frame (device buffers), a captured
-    FrameGraph, its own stream, a completion event and pinned words for the
-    overflow flag and the pair count."""
+    FrameGraph, a completion event and pinned words for the overflow flag and
+    the pair count.  Frames run on ``lanes`` streams with hardware queues of
+    their own (renderer.new_stream); each launch takes the lane with the fewest
+    frames still running, so requests admitted together overlap on the device.
+    A slot is launched again only after its previous frame completed, so a
+    slot needs no ordering between the lanes it runs on."""
 
-    def __init__(self, device=None, use_graphs: bool = True):
+    def __init__(self, device=None, use_graphs: bool = True, lanes: int = 3):
         import torch
+        from . import renderer as R
         self.torch = torch
         self.device = torch.device(device or "cuda:0")
         self.scenes: Dict[str, Any] = {}
         self.use_graphs = use_graphs
+        self.lanes = [R.new_stream(self.device) for _ in range(max(1, lanes))]
+        self.lane_busy = [0] * len(self.lanes)
 
     def add_scene(self, name: str, scene):
         from . import renderer as R
@@ -254,11 +261,12 @@ class GpuExecutor:
         name, W, H = shape
         scene = self.scenes[name]
         fr = R.Frame(scene.n, W, H, capacity, self.device, walked=False)
-        st = self.torch.cuda.Stream(self.device)
         # the buffers were allocated (and the scene uploaded) on the current
-        # stream: order the slot stream after that work
-        st.wait_stream(self.torch.cuda.current_stream(self.device))
-        h = dict(frame=fr, stream=st, scene=scene, graph=None, event=None, status=None, result=None, req=None)
+        # stream: the slot's first launch waits for that work
+        ready = self.torch.cuda.Event()
+        ready.record(self.torch.cuda.current_stream(self.device))
+        h = dict(frame=fr, ready=ready, lane=None, scene=scene, graph=None, event=None, status=None, result=None,
+                 req=None)
         h["status"] = self.torch.zeros(2, dtype=self.torch.int64, pin_memory=True)
         if self.use_graphs:
             from .scenes import pinhole
@@ -268,17 +276,31 @@ class GpuExecutor:
 
     def destroy_slot(self, h):
         # the frame buffers return to the allocator of the stream they were
-        # allocated on: nothing may still run on the slot stream
-        if h.get("stream") is not None:
-            h["stream"].synchronize()
+        # allocated on: nothing may still use them
+        if h.get("event") is not None:
+            h["event"].synchronize()
+        if h.get("lane") is not None:
+            self.lanes[h["lane"]].synchronize()
         if h.get("graph") is not None:
             h["graph"].close()
         h.clear()
 
+    def close(self):
+        from . import renderer as R
+        lanes, self.lanes = self.lanes, []
+        for st in lanes:
+            R.destroy_stream(st)
+
     def launch(self, h, req: Request):
         from . import renderer as R
         torch = self.torch
-        st = h["stream"]
+        lane = min(range(len(self.lanes)), key=lambda i: self.lane_busy[i])
+        self.lane_busy[lane] += 1
+        h["lane"] = lane
+        st = self.lanes[lane]
+        if h.get("ready") is not None:
+            st.wait_event(h["ready"])
+            h["ready"] = None
         fr = h["frame"]
         with torch.cuda.stream(st):
             if h["graph"] is not None:
@@ -299,6 +321,7 @@ class GpuExecutor:
         if ev is None or not ev.query():
             return None
         h["event"] = None
+        self.lane_busy[h["lane"]] -= 1
         over, pairs = (int(v) for v in h["status"].tolist())
         res = h["result"]
         h["result"] = None
@@ -309,8 +332,8 @@ class Engine:
     """Scheduler + GPU executor + a background loop thread."""
 
     def __init__(self, hbm_budget: int, max_slots: int = 8, device=None, use_graphs: bool = True,
-                 capacity_of: Optional[Callable] = None, max_inflight: Optional[int] = None):
-        self.ex = GpuExecutor(device, use_graphs)
+                 capacity_of: Optional[Callable] = None, max_inflight: Optional[int] = None, lanes: int = 3):
+        self.ex = GpuExecutor(device, use_graphs, lanes)
         self.sched = Scheduler(self.ex, hbm_budget, max_slots, capacity_of=capacity_of or self._capacity_guess,
                                max_inflight=max_inflight)
         self._lock = threading.Lock()
@@ -367,6 +390,7 @@ class Engine:
         self.stop()
         with self._lock:
             self.sched.close()
+            self.ex.close()
 
     def stats(self):
         with self._lock:

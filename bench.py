@@ -316,7 +316,7 @@ def measure(sc, frames, args, reps, label):
     if args.no_plain:
         del variants["original"], variants["hard"]
     # capacity from one pass over every frame (outside the timed region)
-    fr = R.Frame(sc.n, W, H, 8 * sc.n, dev, walked=False)
+    fr = R.Frame(sc.n, W, H, 8 * sc.n, dev, walked=False, pair_start=False)
     maxP = 0
     for name, fl in variants.items():
         for cam, pl in (fl if name == "rara" else fl[:: max(1, len(fl) // 16)]):
@@ -512,7 +512,7 @@ def main():
         ds = R.DeviceScene.from_scene(sc, dev)
         W, H = frames[0][0].width, frames[0][0].height
         pick = [frames[i % len(frames)] for i in range(args.warmup + args.profile_steps)]
-        fr = R.Frame(sc.n, W, H, 8 * sc.n, dev, walked=False)
+        fr = R.Frame(sc.n, W, H, 8 * sc.n, dev, walked=False, pair_start=False)
         maxP = 0
         for cam, pl in frames:
             R.render_checked(ds, fr, cam, pl)

@@ -143,12 +143,14 @@ typedef struct {
  *   work [4 tiles + 1] uint32    blend schedule written by rara_bin_sort: quadrant
  *                                units of tiles with long lists, then whole tiles;
  *                                the last entry is the number of split tiles.
- *   pair_start [n] uint32        for each drawn Gaussian, the position of its first
- *                                pair in emission order (drawn Gaussians by depth,
- *                                each one's tiles row by row over its rectangle);
- *                                not written for Gaussians that are not drawn.  Used
- *                                by rara_render_backward to give every (tile,
- *                                Gaussian) pair its own gradient slot. */
+ *   pair_start [n] uint32        optional (NULL: not written): for each drawn
+ *                                Gaussian, the position of its first pair in emission
+ *                                order (drawn Gaussians by depth, each one's tiles
+ *                                row by row over its rectangle); not written for
+ *                                Gaussians that are not drawn.  Required by
+ *                                rara_render_backward, which gives every (tile,
+ *                                Gaussian) pair its own gradient slot; a frame that
+ *                                is only rendered can leave it NULL. */
 typedef struct {
     uint64_t* keys;
     uint32_t* vals;

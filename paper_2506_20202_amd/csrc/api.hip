@@ -113,7 +113,6 @@ size_t rara::bin_workspace_layout(int64_t n, int64_t cap, BinWorkspace* ws, char
     w.block_sums = reinterpret_cast<uint32_t*>(base + off);
     off += align((size_t)scan_blocks * 4);
     w.dcount = reinterpret_cast<int64_t*>(base + off);
-    w.dover = reinterpret_cast<int32_t*>(base + off + 8);
     off += 256;
     for (int b = 0; b < 2; ++b) {
         w.dkeys[b] = reinterpret_cast<uint32_t*>(base + off);
@@ -185,8 +184,7 @@ rara_status rara_bin_sort(const rara_projected* proj, int64_t n, const rara_came
     if (!proj || n < 0 || !out || !workspace) return RARA_ERR_INVALID;
     if (pair_capacity < 1 || pair_capacity >= (int64_t(1) << 31)) return RARA_ERR_INVALID;
     if (n > 0 && !proj_ok(proj)) return RARA_ERR_INVALID;
-    if (!out->keys || !out->vals || !out->ranges || !out->num_pairs || !out->overflow || !out->work ||
-        (n > 0 && !out->pair_start))
+    if (!out->keys || !out->vals || !out->ranges || !out->num_pairs || !out->overflow || !out->work)
         return RARA_ERR_INVALID;
     CamParams cp;
     if (!make_cam(cam, &cp)) return RARA_ERR_INVALID;

@@ -4,8 +4,9 @@
 // ties by Gaussian index, with a stable LSD radix sort.  LSD handles the low
 // (depth) digits first, and all pairs of one Gaussian share its depth, so the
 // depth passes run on the drawn Gaussians before expansion:
-//   1. compact the drawn Gaussians (index order) with their depth bits;
-//   2. four 8-bit LSD passes on the depth bits (stable: ties stay in index order);
+//   1-2. four 8-bit LSD passes on the depth bits of the drawn Gaussians (stable:
+//      ties stay in index order); the first pass reads all Gaussians in index
+//      order and keeps the drawn ones, so no separate compaction runs;
 //   3. exclusive scan of tiles_touched in that order and emission of one
 //      (tile, index) pair per covered tile -- the pairs are now in depth order;
 //   4. ceil(log2(tiles) / 8) stable LSD passes on the tile digits, the last one
@@ -14,7 +15,7 @@
 // This is the same permutation as sorting the expanded pairs by all their key
 // bits, with the four depth passes over ~P / 5 items instead of P.
 //
-// The scan is reduce-then-scan over 256-Gaussian chunks.  Inside a chunk the
+// The pair-offset scan is reduce-then-scan over 256-Gaussian chunks.  Inside a chunk the
 // prefix is a wavefront-ballot scan: bit b of every lane's count is gathered
 // with one 64-lane ballot, and mbcnt (popcount of the ballot below the lane)
 // times 2^b is added to the lane's prefix; the loop stops at the highest bit
@@ -61,40 +62,17 @@ __device__ inline uint32_t block_ballot_scan(uint32_t v, uint32_t& total)
     return before + p;
 }
 
-// Per-256-chunk sums.  kMode 0: tiles_touched[i]; 1: [tiles_touched[i] > 0];
-// 2: tiles_touched[order[k]] for k < *count (depth order).
-template <int kMode>
+// Per-256-chunk sums of tiles_touched[order[k]] over the depth order, k < *count.
 __global__ __launch_bounds__(256) void chunk_sum_kernel(const uint32_t* __restrict__ tt,
-                                                        const uint32_t* __restrict__ order, int64_t n,
+                                                        const uint32_t* __restrict__ order,
                                                         const int64_t* __restrict__ count,
-                                                        uint32_t* __restrict__ block_sums,
-                                                        uint32_t* __restrict__ ranges, int64_t range_words)
+                                                        uint32_t* __restrict__ block_sums)
 {
     const int64_t k = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
-    // the first kernel of a frame also clears the tile ranges (grid-stride)
-    for (int64_t w = k; w < range_words; w += (int64_t)gridDim.x * kScanBlock) ranges[w] = 0u;
-    const int64_t lim = kMode == 2 ? *count : n;
-    uint32_t v = 0u;
-    if (k < lim) v = kMode == 0 ? tt[k] : (kMode == 1 ? (tt[k] > 0u ? 1u : 0u) : tt[order[k]]);
+    const uint32_t v = k < *count ? tt[order[k]] : 0u;
     uint32_t total;
     block_ballot_scan(v, total);
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
-}
-
-// Drawn Gaussians in index order with their depth bits (positive floats order
-// like their bit patterns).
-__global__ __launch_bounds__(256) void compact_kernel(const uint32_t* __restrict__ tt, const float* __restrict__ depth,
-                                                      int64_t n, const uint32_t* __restrict__ block_off,
-                                                      uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals)
-{
-    const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
-    const bool drawn = i < n && tt[i] > 0u;
-    uint32_t total;
-    const uint32_t pre = block_ballot_scan(drawn ? 1u : 0u, total);
-    if (!drawn) return;
-    const uint32_t off = block_off[blockIdx.x] + pre;
-    dkeys[off] = __float_as_uint(depth[i]);
-    dvals[off] = (uint32_t)i;
 }
 
 // Single-workgroup exclusive scan of the chunk sums; writes the pair count and
@@ -157,7 +135,7 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ 
     const uint32_t pre = block_ballot_scan(v, total);
     if (*overflow || total == 0u) return;   // uniform over the workgroup
     const uint32_t base = block_off[blockIdx.x];
-    if (v) pair_start[id] = base + pre;     // first pair of this Gaussian, emission order
+    if (pair_start && v) pair_start[id] = base + pre;   // first pair of this Gaussian, emission order
     s_end[tid] = pre + v;
     s_id[tid] = id;
     s_rc[tid] = v ? *reinterpret_cast<const ushort4*>(rect + 4 * (int64_t)id) : make_ushort4(0, 0, 1, 1);
@@ -290,23 +268,20 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
                       const rara_binned& out, int tile_passes, hipStream_t s)
 {
     const int64_t nb = n > 0 ? ws.scan_blocks : 0;   // no chunks: every count is 0
-    // 1. drawn Gaussians in index order
-    if (n > 0)
-        hipLaunchKernelGGL(chunk_sum_kernel<1>, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, nullptr, n,
-                           nullptr, ws.block_sums, out.ranges, (int64_t)cam.tiles_x * cam.tiles_y * 2);
-    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, ws.block_sums, nb, INT64_MAX, ws.dcount,
-                       ws.dover);
-    if (n > 0)
-        hipLaunchKernelGGL(compact_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, proj.depth, n,
-                           ws.block_sums, ws.dkeys[0], ws.dvals[0]);
-    // 2. depth order (four passes: the result is back in buffer 0)
-    hipError_t e = sort_passes(ws.dkeys[0], ws.dvals[0], ws.dkeys[1], ws.dvals[1], 4, ws.dcount, nullptr,
-                               ws.depth_blocks, ws.hist, ws.digit_totals, nullptr, nullptr, nullptr, s);
-    if (e != hipSuccess) return e;
+    // 1-2. depth order of the drawn Gaussians: the first of the four passes
+    // takes them straight from the preprocess output (and counts them); the
+    // result is back in buffer 0
+    if (n > 0) {
+        const SortFirstPass first{proj.depth, proj.tiles_touched, n, ws.dcount, out.ranges,
+                                  (int64_t)cam.tiles_x * cam.tiles_y * 2};
+        hipError_t e = sort_passes(ws.dkeys[0], ws.dvals[0], ws.dkeys[1], ws.dvals[1], 4, ws.dcount, nullptr,
+                                   ws.depth_blocks, ws.hist, ws.digit_totals, nullptr, nullptr, nullptr, &first, s);
+        if (e != hipSuccess) return e;
+    }
     // 3. pair offsets in depth order, pair count, overflow flag, emission
     if (n > 0)
-        hipLaunchKernelGGL(chunk_sum_kernel<2>, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, ws.dvals[0],
-                           n, ws.dcount, ws.block_sums, nullptr, (int64_t)0);
+        hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, ws.dvals[0],
+                           ws.dcount, ws.block_sums);
     hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, ws.block_sums, nb, cap, out.num_pairs,
                        out.overflow);
     // the last tile pass must read the workspace buffer, never out.keys, which
@@ -323,7 +298,7 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
                            ws.dcount, ws.block_sums, cam.tiles_x, out.overflow, ka, va, out.pair_start);
     // 4. tile digits; the last pass writes the 64-bit keys and the values
     return sort_passes(ka, va, kb, vb, tile_passes, out.num_pairs, out.overflow, ws.tile_blocks, ws.hist,
-                       ws.digit_totals, out.keys, out.vals, proj.depth, s);
+                       ws.digit_totals, out.keys, out.vals, proj.depth, nullptr, s);
 }
 
 hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, bool clear, hipStream_t s)

@@ -113,7 +113,6 @@ constexpr int kRadix = 1 << kRadixBits;
 struct BinWorkspace {
     uint32_t* block_sums;    // [scan_blocks]
     int64_t* dcount;         // drawn-Gaussian count
-    int32_t* dover;          // unused overflow slot of that count
     uint32_t* dkeys[2];      // depth keys, ping-pong [n]
     uint32_t* dvals[2];      // Gaussian indices, ping-pong [n]
     uint32_t* tkeys;         // tile keys [cap]
@@ -131,9 +130,22 @@ hipError_t launch_preprocess(const GaussPtrs& g, const CamParams& cam, const Pla
                              hipStream_t s);
 hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int64_t cap, const BinWorkspace& ws,
                       const rara_binned& out, int tile_passes, hipStream_t s);
+// First pass of the depth sort: its items are the n Gaussians in index order,
+// taken when drawn (tiles_touched > 0) with the bits of their depth as keys;
+// it writes the number of drawn Gaussians to count_out and clears the tile
+// ranges [range_words].
+struct SortFirstPass {
+    const float* depth;
+    const uint32_t* tt;
+    int64_t n;
+    int64_t* count_out;
+    uint32_t* ranges;
+    int64_t range_words;
+};
 hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int passes, const int64_t* count,
                        const int32_t* overflow, int64_t blocks, uint32_t* hist, uint32_t* digit_totals,
-                       uint64_t* final_keys, uint32_t* final_vals, const float* depth, hipStream_t s);
+                       uint64_t* final_keys, uint32_t* final_vals, const float* depth, const SortFirstPass* first,
+                       hipStream_t s);
 hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, bool clear, hipStream_t s);
 hipError_t launch_plan(const rara_binned& out, int num_tiles, hipStream_t s);
 // the same kernels reading their per-frame parameters from device memory

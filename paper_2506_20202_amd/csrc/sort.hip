@@ -52,13 +52,21 @@ __device__ inline uint64_t match_digit(uint32_t digit, bool valid)
     return peers;
 }
 
-__global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint32_t* __restrict__ keys,
-                                                                     const int64_t* __restrict__ num_items,
-                                                                     const int32_t* __restrict__ overflow, int shift,
-                                                                     uint32_t* __restrict__ hist, int64_t stride)
+// kFilter (first depth pass): item i is Gaussian i, taken when it is drawn
+// (tiles_touched > 0), its key the bits of its positive depth; the kernel also
+// clears the tile ranges of the frame.
+template <bool kFilter>
+__global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
+    const uint32_t* __restrict__ keys, const int64_t* __restrict__ num_items, const int32_t* __restrict__ overflow,
+    int shift, uint32_t* __restrict__ hist, int64_t stride, const float* __restrict__ depth,
+    const uint32_t* __restrict__ tt, int64_t n_items, uint32_t* __restrict__ ranges, int64_t range_words)
 {
+    if (kFilter)
+        for (int64_t w = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; w < range_words;
+             w += (int64_t)gridDim.x * kSortThreads)
+            ranges[w] = 0u;
     if (overflow && *overflow) return;
-    const int64_t P = *num_items;
+    const int64_t P = kFilter ? n_items : *num_items;
     const int64_t tile = sort_tile_of_block(blockIdx.x, (P + kSortTile - 1) / kSortTile);
     if (tile < 0) return;
     const int64_t base = tile * kSortTile;
@@ -69,8 +77,9 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
     const int64_t wbase = base + (int64_t)wave * kWaveKeys;
     for (int r = 0; r < kWaveKeys / 64; ++r) {
         const int64_t idx = wbase + r * 64 + lane;
-        const bool valid = idx < P;
-        const uint32_t d = valid ? (keys[idx] >> shift) & (kRadix - 1) : 0u;
+        const bool valid = idx < P && (!kFilter || tt[idx] > 0u);
+        const uint32_t key = valid ? (kFilter ? __float_as_uint(depth[idx]) : keys[idx]) : 0u;
+        const uint32_t d = (key >> shift) & (kRadix - 1);
         const uint64_t peers = match_digit(d, valid);
         if (valid && lanes_below(peers) == 0) counts[wave][d] += (uint32_t)__popcll(peers);
     }
@@ -83,14 +92,14 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
 }
 
 // One workgroup per digit: exclusive scan of hist[d][0..tiles) in place and the
-// digit's total.
+// digit's total.  The item count is *num_items, or n_items without it.
 __global__ __launch_bounds__(256) void radix_scan_kernel(uint32_t* __restrict__ hist, int64_t stride,
-                                                         const int64_t* __restrict__ num_items,
+                                                         const int64_t* __restrict__ num_items, int64_t n_items,
                                                          const int32_t* __restrict__ overflow,
                                                          uint32_t* __restrict__ digit_totals)
 {
     if (overflow && *overflow) return;
-    const int64_t P = *num_items;
+    const int64_t P = num_items ? *num_items : n_items;
     const int64_t tiles = (P + kSortTile - 1) / kSortTile;
     uint32_t* row = hist + (int64_t)blockIdx.x * stride;
     __shared__ uint32_t part[256];
@@ -117,16 +126,19 @@ __global__ __launch_bounds__(256) void radix_scan_kernel(uint32_t* __restrict__ 
 }
 
 // kFinal: keys_out is ignored and the 64-bit (key << 32 | depth bits of the
-// value's Gaussian) key is written to final_keys instead.
-template <bool kFinal>
+// value's Gaussian) key is written to final_keys instead.  kFilter: the input
+// of radix_upsweep_kernel<true>; the pass also writes the number of drawn
+// Gaussians to count_out.
+template <bool kFinal, bool kFilter>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const int64_t* __restrict__ num_items, const int32_t* __restrict__ overflow,
     int shift, const uint32_t* __restrict__ hist, int64_t stride, const uint32_t* __restrict__ digit_totals,
-    uint64_t* __restrict__ final_keys, const float* __restrict__ depth)
+    uint64_t* __restrict__ final_keys, const float* __restrict__ depth, const uint32_t* __restrict__ tt,
+    int64_t n_items, int64_t* __restrict__ count_out)
 {
     if (overflow && *overflow) return;
-    const int64_t P = *num_items;
+    const int64_t P = kFilter ? n_items : *num_items;
     const int64_t tile = sort_tile_of_block(blockIdx.x, (P + kSortTile - 1) / kSortTile);
     if (tile < 0) return;
     const int64_t base = tile * kSortTile;
@@ -138,6 +150,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     __shared__ uint32_t global_start[kRadix];     // global position of that run
     __shared__ uint32_t wave_sum[kWaves];
     __shared__ uint32_t wave_gsum[kWaves];
+    __shared__ uint32_t s_count;                  // keys of this tile
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // this tile's digit offsets do not depend on the keys: issue their loads first
@@ -154,14 +167,14 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t idx = wbase + r * 64 + lane;
-        const bool valid = idx < P;
-        key[r] = valid ? keys_in[idx] : 0u;
-        val[r] = valid ? vals_in[idx] : 0u;
+        const bool valid = idx < P && (!kFilter || tt[idx] > 0u);
+        key[r] = valid ? (kFilter ? __float_as_uint(depth[idx]) : keys_in[idx]) : 0u;
+        val[r] = valid ? (kFilter ? (uint32_t)idx : vals_in[idx]) : 0u;
+        packed[r] = valid ? 0u : 0xffffffffu;
     }
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
-        const int64_t idx = wbase + r * 64 + lane;
-        const bool valid = idx < P;
+        const bool valid = packed[r] == 0u;
         const uint32_t d = (key[r] >> shift) & (kRadix - 1);
         const uint64_t peers = match_digit(d, valid);
         uint32_t rank = 0;
@@ -205,6 +218,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         for (int w = 0; w < wave; ++w) { before += wave_sum[w]; gbefore += wave_gsum[w]; }
         local_start[tid] = before + incl - dtot;
         global_start[tid] = gbefore + gincl - gtot + tile_off;
+        if (tid == kRadix - 1) {
+            s_count = before + incl;
+            if (kFilter && tile == 0) *count_out = (int64_t)(gbefore + gincl);   // all drawn Gaussians
+        }
     }
     __syncthreads();
 
@@ -221,8 +238,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     __syncthreads();
 
     // 4. write each digit run contiguously
-    const int64_t cnt64 = P - base < kSortTile ? P - base : kSortTile;
-    const int cnt = (int)cnt64;
+    const int cnt = (int)s_count;
     for (int k = tid; k < cnt; k += kSortThreads) {
         const uint32_t kk = s_keys[k];
         const uint32_t d = (kk >> shift) & (kRadix - 1);
@@ -240,10 +256,13 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 
 hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int passes, const int64_t* count,
                        const int32_t* overflow, int64_t blocks, uint32_t* hist, uint32_t* digit_totals,
-                       uint64_t* final_keys, uint32_t* final_vals, const float* depth, hipStream_t s)
+                       uint64_t* final_keys, uint32_t* final_vals, const float* depth, const SortFirstPass* first,
+                       hipStream_t s)
 {
     // pass p reads (ka, va) when p is even and (kb, vb) when odd; with final_keys
-    // the last pass writes (final_keys, final_vals) instead of the other buffer
+    // the last pass writes (final_keys, final_vals) instead of the other buffer;
+    // with `first`, pass 0 reads the drawn Gaussians instead of (ka, va) and
+    // writes their number to first->count_out (the `count` of later passes)
     const unsigned grid = (unsigned)((blocks + 7) / 8 * 8);   // see sort_tile_of_block
     for (int p = 0; p < passes; ++p) {
         const bool even = (p & 1) == 0;
@@ -252,16 +271,30 @@ hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, i
         uint32_t* kout = even ? kb : ka;
         uint32_t* vout = even ? vb : va;
         const int shift = p * kRadixBits;
-        hipLaunchKernelGGL(radix_upsweep_kernel, dim3(grid), dim3(kSortThreads), 0, s, kin, count, overflow,
-                           shift, hist, blocks);
-        hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadix), dim3(256), 0, s, hist, blocks, count, overflow,
-                           digit_totals);
+        const bool filter = first && p == 0;
+        if (filter) {
+            hipLaunchKernelGGL(radix_upsweep_kernel<true>, dim3(grid), dim3(kSortThreads), 0, s, nullptr, nullptr,
+                               overflow, shift, hist, blocks, first->depth, first->tt, first->n, first->ranges,
+                               first->range_words);
+            hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadix), dim3(256), 0, s, hist, blocks, nullptr, first->n,
+                               overflow, digit_totals);
+            hipLaunchKernelGGL((radix_scatter_kernel<false, true>), dim3(grid), dim3(kSortThreads), 0, s, nullptr,
+                               nullptr, kout, vout, nullptr, overflow, shift, hist, blocks, digit_totals, nullptr,
+                               first->depth, first->tt, first->n, first->count_out);
+            continue;
+        }
+        hipLaunchKernelGGL(radix_upsweep_kernel<false>, dim3(grid), dim3(kSortThreads), 0, s, kin, count, overflow,
+                           shift, hist, blocks, nullptr, nullptr, (int64_t)0, nullptr, (int64_t)0);
+        hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadix), dim3(256), 0, s, hist, blocks, count, (int64_t)0,
+                           overflow, digit_totals);
         if (final_keys && p == passes - 1)
-            hipLaunchKernelGGL(radix_scatter_kernel<true>, dim3(grid), dim3(kSortThreads), 0, s, kin, vin,
-                               kout, final_vals, count, overflow, shift, hist, blocks, digit_totals, final_keys, depth);
+            hipLaunchKernelGGL((radix_scatter_kernel<true, false>), dim3(grid), dim3(kSortThreads), 0, s, kin, vin,
+                               kout, final_vals, count, overflow, shift, hist, blocks, digit_totals, final_keys, depth,
+                               nullptr, (int64_t)0, nullptr);
         else
-            hipLaunchKernelGGL(radix_scatter_kernel<false>, dim3(grid), dim3(kSortThreads), 0, s, kin, vin,
-                               kout, vout, count, overflow, shift, hist, blocks, digit_totals, nullptr, nullptr);
+            hipLaunchKernelGGL((radix_scatter_kernel<false, false>), dim3(grid), dim3(kSortThreads), 0, s, kin, vin,
+                               kout, vout, count, overflow, shift, hist, blocks, digit_totals, nullptr, nullptr,
+                               nullptr, (int64_t)0, nullptr);
     }
     return hipGetLastError();
 }

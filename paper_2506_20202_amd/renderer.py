@@ -78,9 +78,10 @@ class ProjectedBuffers:
 
 
 class BinBuffers:
-    """rara_binned plus the bin/sort workspace for a pair capacity."""
+    """rara_binned plus the bin/sort workspace for a pair capacity.
+    ``pair_start`` (needed only by the backward) is allocated on request."""
 
-    def __init__(self, n: int, width: int, height: int, capacity: int, device="cuda"):
+    def __init__(self, n: int, width: int, height: int, capacity: int, device="cuda", pair_start: bool = True):
         self.capacity = int(capacity)
         tiles = ((width + 15) // 16) * ((height + 15) // 16)
         self.keys = torch.empty(self.capacity, dtype=torch.int64, device=device)
@@ -89,7 +90,7 @@ class BinBuffers:
         self.num_pairs = torch.zeros(1, dtype=torch.int64, device=device)
         self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
         self.work = torch.empty(4 * tiles + 1, dtype=torch.int32, device=device)
-        self.pair_start = torch.empty(max(int(n), 1), dtype=torch.int32, device=device)
+        self.pair_start = torch.empty(max(int(n), 1), dtype=torch.int32, device=device) if pair_start else None
         self.ws_bytes = B.workspace_bytes(B.RARA_WS_BIN_SORT, n, self.capacity, width, height)
         if self.ws_bytes == 0:
             raise ValueError("invalid bin/sort workspace request")
@@ -104,7 +105,8 @@ class BinBuffers:
         return b
 
     def nbytes(self) -> int:
-        return self.capacity * 12 + self.ranges.numel() * 4 + self.pair_start.numel() * 4 + self.ws_bytes
+        ps = self.pair_start.numel() * 4 if self.pair_start is not None else 0
+        return self.capacity * 12 + self.ranges.numel() * 4 + ps + self.ws_bytes
 
 
 class ImageBuffers:
@@ -116,13 +118,16 @@ class ImageBuffers:
 
 
 class Frame:
-    """All device buffers of one frame shape (n Gaussians, W x H, capacity)."""
+    """All device buffers of one frame shape (n Gaussians, W x H, capacity).
+    ``pair_start`` keeps the per-Gaussian pair offsets the backward needs;
+    a frame that is only rendered can go without them."""
 
-    def __init__(self, n: int, width: int, height: int, capacity: int, device="cuda", walked: bool = True):
+    def __init__(self, n: int, width: int, height: int, capacity: int, device="cuda", walked: bool = True,
+                 pair_start: bool = True):
         self.n, self.width, self.height = int(n), int(width), int(height)
         self.device = device
         self.proj = ProjectedBuffers(n, device)
-        self.bins = BinBuffers(n, width, height, capacity, device)
+        self.bins = BinBuffers(n, width, height, capacity, device, pair_start)
         self.out = ImageBuffers(width, height, device, walked)
 
     @property
@@ -130,7 +135,8 @@ class Frame:
         return self.bins.capacity
 
     def grow(self, capacity: int):
-        self.bins = BinBuffers(self.n, self.width, self.height, capacity, self.device)
+        self.bins = BinBuffers(self.n, self.width, self.height, capacity, self.device,
+                               self.bins.pair_start is not None)
 
 
 def enqueue_frame(scene: DeviceScene, frame: Frame, cam, plane, bg=(0.0, 0.0, 0.0), stream=None,
@@ -217,7 +223,7 @@ class FramePipeline:
         if streams < 1:
             raise ValueError("streams must be at least 1")
         self.scene = scene
-        self.frames = [Frame(scene.n, width, height, capacity, dev, walked) for _ in range(streams)]
+        self.frames = [Frame(scene.n, width, height, capacity, dev, walked, pair_start=False) for _ in range(streams)]
         self.streams = [new_stream(dev) for _ in range(streams)]
         self.count = 0
         self.start()

@@ -216,3 +216,23 @@ def test_clip_mode_parity_large_gaussians(name, mode):
     n = rng.standard_normal(3)
     pl = scenes.Plane((n / np.linalg.norm(n)).astype(np.float32), float(rng.uniform(-0.1, 0.1)), enabled=mode)
     _full_check(sc, scenes.small_camera(96), pl)
+
+
+def test_bin_sort_without_pair_start_matches():
+    """pair_start is optional in rara_binned: a frame binned without it renders
+    and sorts exactly as one with it."""
+    import torch
+    from paper_2506_20202_amd import renderer as R
+    sc = scenes.tiny_scene(4)
+    cam, pl = scenes.tiny_camera(), scenes.tiny_plane(4)
+    dev = torch.device("cuda:0")
+    ds = R.DeviceScene.from_scene(sc, dev)
+    outs = []
+    for ps in (True, False):
+        fr = R.Frame(sc.n, cam.width, cam.height, 1 << 18, dev, walked=True, pair_start=ps)
+        R.render_checked(ds, fr, cam, pl)
+        P = int(fr.bins.num_pairs.item())
+        outs.append((fr.out.image.clone(), fr.bins.keys[:P].clone(), fr.bins.vals[:P].clone(),
+                     fr.out.n_contrib.clone(), fr.out.n_walked.clone()))
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)

@@ -7,13 +7,14 @@
 //
 // Layout: one 256-thread workgroup per 16x16 tile; wave w owns the 8x8
 // quadrant w (one pixel per lane).  The tile's sorted list is walked in
-// batches of 256: each thread gathers one 48-byte splat record (and, for
-// CUTOFF Gaussians, the 48-byte ray record), converts the projected centre to
-// tile-relative FP32 (exact to ~1e-6 px), folds -log2(e)/2 into the conic so
-// that alpha needs one exp2, tests which quadrants the entry can reach, and
-// stages it in LDS.  Each wave then visits, in list order, the staged entries
-// that reach its quadrant, reading each as an LDS broadcast.  The CUTOFF
-// branch is wave-uniform (labels are per Gaussian).
+// batches of 224: each of the first 224 threads gathers one 48-byte splat
+// record (and, for CUTOFF Gaussians, the 48-byte ray record), converts the
+// projected centre to tile-relative FP32 (exact to ~1e-6 px), folds
+// -log2(e)/2 into the conic so that alpha needs one exp2, tests which
+// quadrants the entry can reach, and stages it in LDS.  Each wave then
+// visits, in list order, the staged entries that reach its quadrant, reading
+// each as an LDS broadcast.  The CUTOFF branch is wave-uniform (labels are per
+// Gaussian).
 //
 // The weight is evaluated in whitened space from the pixel offset, not from
 // the world-space quadratic: with delta = gx dx + gy dy, D = d0 + delta,
@@ -61,7 +62,11 @@ __device__ inline void composite(float a0, float w, float cr, float cg, float cb
     walked = term ? k1 : walked;
 }
 
-constexpr int kTileBatch = 256;   // entries staged per batch, one per thread
+constexpr int kBlendThreads = 256;   // one workgroup per tile: four waves, one per 8x8 quadrant
+// entries staged per batch, one per thread of the first 224: with 64 VGPRs
+// and under 20 KB of LDS a CU holds 8 workgroups (8 waves per SIMD)
+constexpr int kTileBatch = 224;
+constexpr int kBatchSlots = 256;     // s_c rows: four 64-entry ballots, the tail zero
 
 // One tile: thread t of wave w = t / 64 owns pixel (t % 8, (t / 8) % 8) of the
 // 8x8 quadrant w.  Per batch, every thread stages one entry; after the
@@ -106,7 +111,7 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
         if (!__syncthreads_or(live ? 1 : 0)) break;   // also: the previous batch has been read
         const uint32_t idx = base + (uint32_t)tid;
         float2 sc = make_float2(0.0f, 0.0f);   // label | quadrant mask << 8 = 0: reaches nothing
-        if (idx < rg.y) {
+        if (tid < kTileBatch && idx < rg.y) {
             const uint32_t id = vals[idx];
             const Splat sp = splats[id];
             float4 sa, sb, c4;
@@ -180,22 +185,18 @@ __device__ __forceinline__ void blend_block(const Splat* __restrict__ splats, co
     if (!tile_of_block(blockIdx.x, work, p.num_tiles, tile)) return;
     if (tile >= (uint32_t)p.num_tiles) return;
     __shared__ float4 s_a[kTileBatch], s_b[kTileBatch];
-    __shared__ float2 s_c[kTileBatch];
+    __shared__ float2 s_c[kBatchSlots];
     __shared__ CutRec s_cut[kTileBatch];
     blend_tile<kWalked>(splats, rays, vals, ranges[tile], (int)tile, p, s_a, s_b, s_c, s_cut, image, final_T,
                         n_contrib, n_walked);
 }
 
 template <bool kWalked>
-__global__ __launch_bounds__(kTileBatch) void blend_kernel(const Splat* __restrict__ splats,
-                                                           const RayRec* __restrict__ rays,
-                                                           const uint32_t* __restrict__ vals,
-                                                           const uint2* __restrict__ ranges,
-                                                           const uint32_t* __restrict__ work,
-                                                           const int32_t* __restrict__ overflow, RenderParams p,
-                                                           float* __restrict__ image, float* __restrict__ final_T,
-                                                           uint32_t* __restrict__ n_contrib,
-                                                           uint32_t* __restrict__ n_walked)
+__global__ __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(8)))
+void blend_kernel(const Splat* __restrict__ splats, const RayRec* __restrict__ rays, const uint32_t* __restrict__ vals,
+                  const uint2* __restrict__ ranges, const uint32_t* __restrict__ work,
+                  const int32_t* __restrict__ overflow, RenderParams p, float* __restrict__ image,
+                  float* __restrict__ final_T, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
 {
     if (*overflow) return;
     blend_block<kWalked>(splats, rays, vals, ranges, work, p, image, final_T, n_contrib, n_walked);
@@ -203,16 +204,12 @@ __global__ __launch_bounds__(kTileBatch) void blend_kernel(const Splat* __restri
 
 // Frame-graph variant: render parameters read from device memory.
 template <bool kWalked>
-__global__ __launch_bounds__(kTileBatch) void blend_fp_kernel(const Splat* __restrict__ splats,
-                                                              const RayRec* __restrict__ rays,
-                                                              const uint32_t* __restrict__ vals,
-                                                              const uint2* __restrict__ ranges,
-                                                              const uint32_t* __restrict__ work,
-                                                              const int32_t* __restrict__ overflow,
-                                                              const FrameParams* __restrict__ fp,
-                                                              float* __restrict__ image, float* __restrict__ final_T,
-                                                              uint32_t* __restrict__ n_contrib,
-                                                              uint32_t* __restrict__ n_walked)
+__global__ __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(8)))
+void blend_fp_kernel(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
+                     const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
+                     const uint32_t* __restrict__ work, const int32_t* __restrict__ overflow,
+                     const FrameParams* __restrict__ fp, float* __restrict__ image, float* __restrict__ final_T,
+                     uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
 {
     if (*overflow) return;
     const RenderParams p = fp->render;
@@ -226,11 +223,11 @@ hipError_t launch_blend(const Splat* splat, const RayRec* ray, const rara_binned
 {
     const unsigned grid = (unsigned)tiles_grid(p.num_tiles);
     if (n_walked)
-        hipLaunchKernelGGL(blend_kernel<true>, dim3(grid), dim3(kTileBatch), 0, s, splat, ray, bins.vals,
+        hipLaunchKernelGGL(blend_kernel<true>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals,
                            reinterpret_cast<const uint2*>(bins.ranges), bins.work, bins.overflow, p, image, final_T,
                            n_contrib, n_walked);
     else
-        hipLaunchKernelGGL(blend_kernel<false>, dim3(grid), dim3(kTileBatch), 0, s, splat, ray, bins.vals,
+        hipLaunchKernelGGL(blend_kernel<false>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals,
                            reinterpret_cast<const uint2*>(bins.ranges), bins.work, bins.overflow, p, image, final_T,
                            n_contrib, n_walked);
     return hipGetLastError();
@@ -243,10 +240,10 @@ hipError_t launch_blend_fp(const Splat* splat, const RayRec* ray, const rara_bin
     const unsigned grid = (unsigned)tiles_grid(num_tiles);
     const uint2* ranges = reinterpret_cast<const uint2*>(bins.ranges);
     if (n_walked)
-        hipLaunchKernelGGL(blend_fp_kernel<true>, dim3(grid), dim3(kTileBatch), 0, s, splat, ray, bins.vals, ranges, bins.work,
+        hipLaunchKernelGGL(blend_fp_kernel<true>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals, ranges, bins.work,
                            bins.overflow, fp, image, final_T, n_contrib, n_walked);
     else
-        hipLaunchKernelGGL(blend_fp_kernel<false>, dim3(grid), dim3(kTileBatch), 0, s, splat, ray, bins.vals, ranges,
+        hipLaunchKernelGGL(blend_fp_kernel<false>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals, ranges,
                            bins.work, bins.overflow, fp, image, final_T, n_contrib, n_walked);
     return hipGetLastError();
 }

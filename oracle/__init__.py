@@ -45,16 +45,18 @@ def lib():
             from . import build as _b
             _b.build()
         L = ctypes.CDLL(_SO)
-        L.oracle_classify.argtypes = [_I64, _P, _P, _P, _P, _I32, _P, _P, _P]
+        L.oracle_classify.argtypes = [_I64, _P, _P, _P, _P, _I32, _I32, _P, _P, _P]
         L.oracle_classify.restype = _I32
         L.oracle_project.argtypes = [_I64, _I32, _P, _P, _P, _P, _P, _I32, _I32, _D, _P, _I32,
                                      _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
         L.oracle_project.restype = None
         L.oracle_weight.argtypes = [_P, _P, _P, _P, _P, _D, _D, _I32, _P]
         L.oracle_weight.restype = _D
+        L.oracle_weight_region.argtypes = [_P, _P, _P, _P, _P, _P, _I32, _D, _I32, _P]
+        L.oracle_weight_region.restype = _D
         L.oracle_lists.argtypes = [_I64, _P, _P, _P, _I32, _I32, _P, _P]
         L.oracle_lists.restype = _I64
-        L.oracle_composite.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _I32, _P, _I32, _I32, _P,
+        L.oracle_composite.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _I32, _I32, _P, _I32, _I32, _P,
                                        _P, _P, _D, _I32, _I64, _I64, _D, _P, _P, _P, _P, _P, _P]
         L.oracle_composite.restype = None
         L.oracle_minv.argtypes = [_P, _P, _P]
@@ -93,17 +95,27 @@ def clip_mode(plane) -> int:
     return int(plane.enabled)
 
 
+def planes_of(plane) -> np.ndarray:
+    """[count][4] float32 (n, d) rows of a plane or a region of planes."""
+    pa = plane.planes_array() if hasattr(plane, "planes_array") else plane.as_array()[None, :]
+    return np.ascontiguousarray(pa, np.float32)
+
+
 def classify(scene, plane):
-    """Sec. 3.2 labels (uint8 [n]), signed distances d_ep and radii 3 max(sigma)."""
+    """Sec. 3.2 labels (uint8 [n]), signed distances d_ep and radii 3 max(sigma);
+    for a region of several planes d_ep and the radii are [count][n]."""
     n = scene.n
+    pa = planes_of(plane)
+    count = pa.shape[0]
     label = np.empty(n, np.uint8)
-    dep = np.empty(n, np.float64)
-    rad = np.empty(n, np.float64)
-    pa = plane.as_array()
-    ok = lib().oracle_classify(n, _p(scene.mean), _p(scene.scale), _p(scene.quat), _p(pa), clip_mode(plane),
-                               _p(label), _p(dep), _p(rad))
+    dep = np.empty((count, n), np.float64)
+    rad = np.empty((count, n), np.float64)
+    ok = lib().oracle_classify(n, _p(scene.mean), _p(scene.scale), _p(scene.quat), _p(pa), count,
+                               clip_mode(plane), _p(label), _p(dep), _p(rad))
     if not ok:
-        raise ValueError("plane normal has zero length, or an invalid clip mode")
+        raise ValueError("plane normal has zero length, or an invalid clip mode or plane count")
+    if count == 1:
+        return label, dep[0], rad[0]
     return label, dep, rad
 
 
@@ -176,6 +188,24 @@ def weight(e, v, mu, quat, scale, plane_n, plane_d, kappa: float = KAPPA, strict
     return w, info
 
 
+def weight_region(e, v, mu, quat, scale, planes, kappa: float = KAPPA, strict_miss: bool = False):
+    """Eq. (11) weight for the intersection of the half-spaces of ``planes``
+    ([count][4] rows (n, d)) and one ray; returns (w, info)."""
+    pa = np.asarray(planes, np.float64).reshape(-1, 4)
+    L = np.linalg.norm(pa[:, :3], axis=1)
+    nn = np.ascontiguousarray(pa[:, :3] / L[:, None])
+    dd = np.ascontiguousarray(pa[:, 3] / L)
+    v = np.asarray(v, np.float64)
+    v = np.ascontiguousarray(v / np.linalg.norm(v))
+    e = np.ascontiguousarray(e, np.float64)
+    mu = np.ascontiguousarray(mu, np.float64)
+    mi = np.ascontiguousarray(minv(quat, scale).reshape(-1))
+    info = np.zeros(4)
+    w = lib().oracle_weight_region(_p(e), _p(v), _p(mu), _p(mi), _p(nn), _p(dd), pa.shape[0], float(kappa),
+                                   int(strict_miss), _p(info))
+    return w, info
+
+
 # ------------------------------------------------------------ full render ----
 
 def render(scene, cam, plane, bg=(0.0, 0.0, 0.0), kappa: float = KAPPA, trace_visible: bool = False,
@@ -196,8 +226,9 @@ def render(scene, cam, plane, bg=(0.0, 0.0, 0.0), kappa: float = KAPPA, trace_vi
     flags = np.zeros(H * W, np.uint32)
     counters = np.zeros(8, np.int64)
     bgv = np.asarray(bg, np.float32)
+    pa = planes_of(plane)
     lib().oracle_composite(scene.n, _p(label), _p(proj["mean2d"]), _p(proj["conic"]), _p(scene.opacity),
-                           _p(proj["rgb"]), _p(scene.mean), _p(proj["minv"]), _p(plane.as_array()),
+                           _p(proj["rgb"]), _p(scene.mean), _p(proj["minv"]), _p(pa), pa.shape[0],
                            clip_mode(plane), _p(cam_array(cam)), W, H, _p(bgv), _p(offsets), _p(ids),
                            float(kappa), int(trace_visible), int(t0), int(t1), float(tau_sil), _p(image),
                            _p(final_T), _p(n_contrib), _p(n_walked), _p(flags), _p(counters))
@@ -216,10 +247,11 @@ def boundary_events(scene, cam, plane, label, dep, rad, tol: float = 1e-6) -> di
     n = scene.n
     lab_b = np.zeros(n, bool)
     mode = clip_mode(plane)
+    dep2, rad2 = np.atleast_2d(dep), np.atleast_2d(rad)   # [count][n]
     if mode & 3 == 2:
-        lab_b = np.abs(dep) <= tol
+        lab_b = (np.abs(dep2) <= tol).any(0)
     elif mode & 3:
-        lab_b = (np.abs(dep - rad) <= tol) | (np.abs(dep + rad) <= tol)
+        lab_b = ((np.abs(dep2 - rad2) <= tol) | (np.abs(dep2 + rad2) <= tol)).any(0)
     allp = project(scene, cam, label, project_all=True)
     r3 = 3.0 * np.sqrt(np.maximum(allp["lam_max"], 0.0))
 

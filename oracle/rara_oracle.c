@@ -20,6 +20,9 @@
  *   oracle_weight    - Sec. 3.3 eqs. (4)-(8): ray into unit-sphere space,
  *                      quadratic, roots, ray-plane parameter; Sec. 3.4 eq. (11)
  *                      visible-length decay weight (step 2 of Algorithm 1).
+ *   oracle_weight_region - the same weight for a clip region that is the
+ *                      intersection of several half-spaces (a box is six): the
+ *                      extension to other clipping primitives of Sec. 6.
  *   oracle_lists     - depth-sorted per-tile lists (Sec. 3.1, "sorted by depth").
  *   oracle_composite - Sec. 3.1 eq. (2) front-to-back compositing with the
  *                      opacity of eq. (12) and the 0.99 clamp of step 3 of
@@ -35,6 +38,12 @@
  *     side n.x + d >= 0 (the eq. (11) definition; Algorithm 1's branch order
  *     is garbled and is not followed literally);
  *   - the plane is normalised: (n, d) / |n|;
+ *   - a region of several planes (Sec. 6 names other clipping primitives as
+ *     the extension; Sec. 2 cites box clipping of multi-layer fields): every
+ *     plane is normalised, a Gaussian is INVISIBLE when it is beyond r of any
+ *     plane's visible side, VISIBLE when it is beyond r inside every plane,
+ *     CUTOFF otherwise; hard clipping keeps it when its centre is inside every
+ *     half-space; L_vis is the part of the chord inside every half-space;
  *   - alpha is the unnormalised delta * exp(-1/2 dx^T V^-1 dx) (the usual
  *     splatting convention), skip when alpha < 1/255, stop before a Gaussian
  *     that would take transmittance below 1e-4, dilation 0.3 px^2,
@@ -52,6 +61,7 @@
 #define OR_T_MIN 1e-4
 #define OR_DILATION 0.3
 #define OR_GUARD 1.3
+#define OR_MAX_PLANES 8
 
 enum { OR_INVISIBLE = 0, OR_VISIBLE = 1, OR_CUTOFF = 2 };
 
@@ -127,38 +137,50 @@ void oracle_sh_basis(int deg, double x, double y, double z, double* Y) { sh_basi
  * along the normal, r = 3 |S R^T n| (the support function of the ellipsoid;
  * the paper notes 3 max(sigma) over-estimates it).
  * mean, scale: [3][n], quat: [4][n] (w, x, y, z; only read with mode & 4).
- * Returns 0 on an invalid plane or mode.
+ * planes: [count][4] rows (n, d); with count > 1 the visible region is the
+ * intersection of the half-spaces: INVISIBLE when d_ep < -r for some plane,
+ * VISIBLE when d_ep > r for every plane, CUTOFF otherwise (hard clipping:
+ * VISIBLE when d_ep >= 0 for every plane).  d_ep, radius: [count][n].
+ * Returns 0 on an invalid plane, count or mode.
  */
-int oracle_classify(int64_t n, const float* mean, const float* scale, const float* quat, const float* plane,
-                    int mode, uint8_t* label, double* d_ep, double* radius)
+int oracle_classify(int64_t n, const float* mean, const float* scale, const float* quat, const float* planes,
+                    int count, int mode, uint8_t* label, double* d_ep, double* radius)
 {
     const int rule = mode & 3;
     const int tight = (mode & 4) != 0;
-    double nn[3], d;
+    double nn[OR_MAX_PLANES][3], d[OR_MAX_PLANES];
     if (rule == 3 || (tight && (rule != 1 || !quat))) return 0;
-    if (rule && !normalise_plane(plane, nn, &d)) return 0;
+    if (count < 1 || count > OR_MAX_PLANES) return 0;
+    for (int k = 0; k < count; k++)
+        if (rule && !normalise_plane(planes + 4 * k, nn[k], &d[k])) return 0;
     for (int64_t i = 0; i < n; i++) {
         double mu[3] = {mean[i], mean[n + i], mean[2 * n + i]};
         double sig[3] = {scale[i], scale[n + i], scale[2 * n + i]};
-        double r = 3.0 * fmax(fmax(sig[0], sig[1]), sig[2]);
-        if (tight) {
-            double R[9];
-            quat_to_rot(quat[i], quat[n + i], quat[2 * n + i], quat[3 * n + i], R);
-            /* (S R^T n)_a = sigma_a (column a of R) . n */
-            double q2 = 0.0;
-            for (int a = 0; a < 3; a++) {
-                double c = sig[a] * (R[a] * nn[0] + R[3 + a] * nn[1] + R[6 + a] * nn[2]);
-                q2 += c * c;
+        double R[9];
+        if (tight) quat_to_rot(quat[i], quat[n + i], quat[2 * n + i], quat[3 * n + i], R);
+        int any_out = 0, all_in = 1, any_behind = 0;
+        for (int k = 0; k < count; k++) {
+            double r = 3.0 * fmax(fmax(sig[0], sig[1]), sig[2]);
+            if (tight) {
+                /* (S R^T n)_a = sigma_a (column a of R) . n */
+                double q2 = 0.0;
+                for (int a = 0; a < 3; a++) {
+                    double c = sig[a] * (R[a] * nn[k][0] + R[3 + a] * nn[k][1] + R[6 + a] * nn[k][2]);
+                    q2 += c * c;
+                }
+                r = 3.0 * sqrt(q2);
             }
-            r = 3.0 * sqrt(q2);
+            double dist = rule ? dot3(nn[k], mu) + d[k] : INFINITY;
+            if (d_ep) d_ep[(int64_t)k * n + i] = dist;
+            if (radius) radius[(int64_t)k * n + i] = r;
+            if (dist < -r) any_out = 1;
+            if (!(dist > r)) all_in = 0;
+            if (dist < 0) any_behind = 1;
         }
-        double dist = rule ? dot3(nn, mu) + d : INFINITY;
-        if (d_ep) d_ep[i] = dist;
-        if (radius) radius[i] = r;
         if (rule == 0) label[i] = OR_VISIBLE;
-        else if (rule == 2) label[i] = dist < 0 ? OR_INVISIBLE : OR_VISIBLE;
-        else if (dist < -r) label[i] = OR_INVISIBLE;
-        else if (dist > r) label[i] = OR_VISIBLE;
+        else if (rule == 2) label[i] = any_behind ? OR_INVISIBLE : OR_VISIBLE;
+        else if (any_out) label[i] = OR_INVISIBLE;
+        else if (all_in) label[i] = OR_VISIBLE;
         else label[i] = OR_CUTOFF;
     }
     return 1;
@@ -348,6 +370,74 @@ double oracle_weight(const double* e, const double* v, const double* mu, const d
 }
 
 /*
+ * Eq. (11) for a clip region that is the intersection of `count` half-spaces
+ * n_k.x + d_k >= 0 (each normalised): the extension to other clipping
+ * primitives named in Sec. 6, here convex ones built from planes (a box is
+ * six).  w = L_vis / (t2 - t1) as in oracle_weight, with L_vis the length of
+ * the part of the chord [t1, t2] inside every half-space.  A line meets a
+ * convex region in one interval: each plane with n.v > 0 bounds it from below
+ * at its crossing t_p, each with n.v < 0 from above, and a plane parallel to
+ * the ray keeps all of it or none.  Misses, tangent rays and rays with a root
+ * behind the camera keep w = 1; strict_miss gives a miss w = [the closest
+ * approach lies inside every half-space].  nrm [count][3], dd [count].
+ * info as oracle_weight, except that for a strict miss info[3] is the plane
+ * value of smallest magnitude at the closest approach.
+ */
+double oracle_weight_region(const double* e, const double* v, const double* mu, const double* minv,
+                            const double* nrm, const double* dd, int count, double kappa, int strict_miss,
+                            double* info)
+{
+    double em[3] = {e[0] - mu[0], e[1] - mu[1], e[2] - mu[2]};
+    double et[3], vt[3];
+    for (int a = 0; a < 3; a++) {
+        et[a] = minv[3 * a] * em[0] + minv[3 * a + 1] * em[1] + minv[3 * a + 2] * em[2];
+        vt[a] = minv[3 * a] * v[0] + minv[3 * a + 1] * v[1] + minv[3 * a + 2] * v[2];
+    }
+    double A = dot3(vt, vt);
+    double B = 2.0 * dot3(et, vt);
+    double C = dot3(et, et) - kappa * kappa;
+    double disc = B * B - 4.0 * A * C;
+    if (info) { info[0] = disc / (4.0 * A); info[1] = info[2] = info[3] = NAN; }
+    if (!(disc > 0)) {
+        if (strict_miss && disc < 0) {
+            double ts = -B / (2.0 * A);
+            double closest = INFINITY;
+            int inside = 1;
+            for (int k = 0; k < count; k++) {
+                const double* nk = nrm + 3 * k;
+                double phis = dot3(nk, e) + dd[k] + ts * dot3(nk, v);
+                if (phis < 0) inside = 0;
+                if (fabs(phis) < fabs(closest)) closest = phis;
+            }
+            if (info) info[3] = closest;
+            return inside ? 1.0 : 0.0;
+        }
+        return 1.0;
+    }
+    double sq = sqrt(disc);
+    double t1 = (-B - sq) / (2.0 * A);
+    double t2 = (-B + sq) / (2.0 * A);
+    if (info) { info[1] = t1; info[2] = t2; }
+    if (t1 < 0) return 1.0;
+    double lo = t1, hi = t2;
+    for (int k = 0; k < count; k++) {
+        const double* nk = nrm + 3 * k;
+        double nv = dot3(nk, v);
+        double phi_e = dot3(nk, e) + dd[k];
+        if (k == 0 && info) info[3] = nv != 0 ? -phi_e / nv : NAN;
+        if (nv == 0) {
+            if (phi_e < 0) hi = lo;           /* parallel and outside: nothing visible */
+        } else if (nv > 0) {
+            lo = fmax(lo, -phi_e / nv);       /* visible for t >= t_p */
+        } else {
+            hi = fmin(hi, -phi_e / nv);       /* visible for t <= t_p */
+        }
+    }
+    double lvis = hi > lo ? hi - lo : 0.0;
+    return lvis / (t2 - t1);
+}
+
+/*
  * Per-tile lists: ids of drawn Gaussians whose tile rectangle contains the
  * tile, ordered by (float32 depth, index).  offsets has tiles+1 entries.
  */
@@ -417,6 +507,7 @@ int64_t oracle_lists(int64_t n, const uint8_t* drawn, const int32_t* rect, const
  * R_c^T ((i - cx)/fx, (j - cy)/fy, 1), normalised.
  * plane_enabled is the clip mode of oracle_classify (0: no plane); with
  * mode & 8 the weight uses the strict miss policy of oracle_weight.
+ * planes: [count][4]; with count > 1 the weight is oracle_weight_region.
  * Outputs: image [3][H][W] = C + T bg, final_T, n_contrib (1-based index of
  * the last composited entry), n_walked (entries examined), flags (event bits).
  * counters: [0] entries examined, [1] CUTOFF entries examined, [2] composited,
@@ -425,17 +516,20 @@ int64_t oracle_lists(int64_t n, const uint8_t* drawn, const int32_t* rect, const
  */
 void oracle_composite(int64_t n, const uint8_t* label, const double* mean2d, const double* conic,
                       const float* opacity, const double* rgb, const float* mean, const double* minv,
-                      const float* plane, int plane_enabled, const float* cam, int W, int H, const float* bg,
-                      const int64_t* offsets, const int32_t* ids, double kappa, int trace_visible,
+                      const float* planes, int count, int plane_enabled, const float* cam, int W, int H,
+                      const float* bg, const int64_t* offsets, const int32_t* ids, double kappa, int trace_visible,
                       int64_t tile_begin, int64_t tile_end, double tau_sil, double* image, double* final_T,
                       int32_t* n_contrib, int32_t* n_walked, uint32_t* flags, int64_t* counters)
 {
-    double Rc[9], tc[3], e[3], nn[3] = {0, 0, 0}, d = 0;
+    double Rc[9], tc[3], e[3], nn[OR_MAX_PLANES * 3] = {0}, dd[OR_MAX_PLANES] = {0};
     for (int k = 0; k < 9; k++) Rc[k] = cam[k];
     for (int k = 0; k < 3; k++) tc[k] = cam[9 + k];
     double fx = cam[12], fy = cam[13], cx = cam[14], cy = cam[15];
     camera_centre(Rc, tc, e);
-    if (plane_enabled) normalise_plane(plane, nn, &d);
+    if (count < 1) count = 1;
+    if (count > OR_MAX_PLANES) count = OR_MAX_PLANES;
+    if (plane_enabled)
+        for (int k = 0; k < count; k++) normalise_plane(planes + 4 * k, nn + 3 * k, &dd[k]);
     const int strict = (plane_enabled & 8) != 0;   /* strict miss policy, see oracle_weight */
     int tiles_x = (W + OR_TILE - 1) / OR_TILE;
     int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0, c7 = 0;
@@ -469,7 +563,9 @@ void oracle_composite(int64_t n, const uint8_t* label, const double* mean2d, con
                     if (traced && plane_enabled) {
                         double mu[3] = {mean[g], mean[n + g], mean[2 * n + g]};
                         double info[4];
-                        w = oracle_weight(e, v, mu, minv + 9 * (int64_t)g, nn, d, kappa, strict, info);
+                        w = count == 1 ? oracle_weight(e, v, mu, minv + 9 * (int64_t)g, nn, dd[0], kappa, strict, info)
+                                       : oracle_weight_region(e, v, mu, minv + 9 * (int64_t)g, nn, dd, count, kappa,
+                                                              strict, info);
                         if (a0 >= OR_ALPHA_MIN * (1 - 1e-3)) {
                             if (fabs(info[0]) <= tau_sil * kappa * kappa) { fl |= OR_EV_SILHOUETTE; c3++; }
                             /* strict miss: the weight steps where the closest approach crosses the plane */

@@ -90,16 +90,52 @@ class Camera:
         return (self.width + 15) // 16, (self.height + 15) // 16
 
 
+MAX_PLANES = 8
+
+
 @dataclasses.dataclass
 class Plane:
-    """Clipping plane n.x + d = 0; the half-space n points into is visible."""
+    """Clipping plane n.x + d = 0; the half-space n points into is visible.
+    ``extra`` holds further planes (n, d): the visible region is then the
+    intersection of all the half-spaces (a box is six of them)."""
 
     n: np.ndarray
     d: float
     enabled: bool = True
+    extra: tuple = ()
 
     def as_array(self) -> np.ndarray:
         return np.array([self.n[0], self.n[1], self.n[2], self.d], dtype=np.float32)
+
+    @property
+    def count(self) -> int:
+        return 1 + len(self.extra)
+
+    def planes_array(self) -> np.ndarray:
+        """[count][4] float32 rows (n.x, n.y, n.z, d), this plane first."""
+        rows = [self.as_array()] + [np.array([n[0], n[1], n[2], d], dtype=np.float32) for n, d in self.extra]
+        return np.ascontiguousarray(np.stack(rows))
+
+
+def box_region(lo, hi, enabled=True) -> Plane:
+    """The axis-aligned box lo <= x <= hi as six half-spaces."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    rows = []
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = 1.0
+        rows.append((_f32(e), float(np.float32(-lo[a]))))
+        rows.append((_f32(-e), float(np.float32(hi[a]))))
+    return Plane(rows[0][0], rows[0][1], enabled, tuple(rows[1:]))
+
+
+def region(planes, enabled=True) -> Plane:
+    """Intersection of the half-spaces of the given planes [(n, d), ...]."""
+    rows = [(_f32(n), float(np.float32(d))) for n, d in planes]
+    if not 1 <= len(rows) <= MAX_PLANES:
+        raise ValueError(f"a region has 1 to {MAX_PLANES} planes")
+    return Plane(rows[0][0], rows[0][1], enabled, tuple(rows[1:]))
 
 
 def _f32(a) -> np.ndarray:

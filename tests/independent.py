@@ -127,17 +127,20 @@ def render(scene, cam, plane, bg=(0.0, 0.0, 0.0), trace_visible=False):
     e = -wc[:, :3].T @ wc[:, 3]
     n = scene.n
     mean = scene.mean.astype(np.float64)
-    nn = np.asarray(plane.n, np.float64)
-    Ln = np.linalg.norm(nn)
+    # one plane, or several whose half-spaces intersect (a region)
+    rows = [np.array([*np.asarray(plane.n, np.float64), float(plane.d)])]
+    rows += [np.array([*np.asarray(n_, np.float64), float(d_)]) for n_, d_ in getattr(plane, "extra", ())]
+    planes = np.stack(rows)
+    Lk = np.linalg.norm(planes[:, :3], axis=1)
     recs = []
     for i in range(n):
         mu = mean[:, i]
         s = scene.scale[:, i].astype(np.float64)
         q = scene.quat[:, i].astype(np.float64)
         if plane.enabled:
-            dep = float(np.dot(nn / Ln, mu)) + float(plane.d) / Ln
+            dep = planes[:, :3] @ mu / Lk + planes[:, 3] / Lk
             r = 3.0 * s.max()
-            lab = 0 if dep < -r else (1 if dep > r else 2)
+            lab = 0 if (dep < -r).any() else (1 if (dep > r).all() else 2)
         else:
             lab = 1
         if lab == 0:
@@ -174,7 +177,10 @@ def render(scene, cam, plane, bg=(0.0, 0.0, 0.0), trace_visible=False):
                 a0 = r["op"] * math.exp(p)
                 w = 1.0
                 if plane.enabled and (r["lab"] == 2 or (trace_visible and r["lab"] == 1)):
-                    w, _ = chord_weight(e, v, r["mu"], r["Vinv"], plane.n, plane.d)
+                    if len(planes) == 1:
+                        w, _ = chord_weight(e, v, r["mu"], r["Vinv"], plane.n, plane.d)
+                    else:
+                        w, _, _ = chord_weight_region(e, v, r["mu"], r["Vinv"], planes, samples=4000)
                 a = min(0.99, a0 * w)
                 if a < 1.0 / 255.0:
                     continue
@@ -185,3 +191,66 @@ def render(scene, cam, plane, bg=(0.0, 0.0, 0.0), trace_visible=False):
                 T = tT
             img[:, py, px] = C + T * np.asarray(bg)
     return img
+
+
+def chord_weight_region(e, v, mu, Vinv, planes, samples: int = 20000):
+    """Visible fraction of the 3-sigma chord inside every half-space of
+    ``planes`` ([count][4] rows (n, d)) by marching and bisection: returns
+    (w, hit, spacing) with spacing the marching step over the chord length
+    (an interval narrower than that may be missed)."""
+    e = np.asarray(e, np.float64)
+    v = np.asarray(v, np.float64)
+    mu = np.asarray(mu, np.float64)
+    vv = v / np.linalg.norm(v)
+    rb = 3.0 / math.sqrt(np.linalg.eigvalsh(Vinv).min())
+    tc = float(np.dot(mu - e, vv))
+    lo, hi = max(0.0, tc - rb * 1.01), tc + rb * 1.01
+    if hi <= 0:
+        return 1.0, False, 0.0
+
+    def inside(t):
+        x = e[None, :] + np.atleast_1d(t)[:, None] * vv[None, :] - mu[None, :]
+        return np.einsum("ni,ij,nj->n", x, Vinv, x) <= KAPPA2
+
+    ts = np.linspace(lo, hi, samples)
+    ins = inside(ts)
+    if not ins.any():
+        return 1.0, False, 0.0
+    if ins[0] and lo == 0.0:
+        return 1.0, True, 0.0
+    i0, i1 = int(np.argmax(ins)), samples - 1 - int(np.argmax(ins[::-1]))
+
+    def bisect(a, b, pred, a_val):
+        for _ in range(90):
+            m = 0.5 * (a + b)
+            if pred(m) == a_val:
+                a = m
+            else:
+                b = m
+        return 0.5 * (a + b)
+
+    ins1 = lambda t: bool(inside(t)[0])
+    t1 = bisect(ts[i0 - 1], ts[i0], ins1, False) if i0 > 0 else ts[0]
+    t2 = bisect(ts[i1], ts[i1 + 1], ins1, True) if i1 < samples - 1 else ts[-1]
+    pa = np.asarray(planes, np.float64).reshape(-1, 4)
+    L = np.linalg.norm(pa[:, :3], axis=1)
+    nn, dd = pa[:, :3] / L[:, None], pa[:, 3] / L
+
+    def vis(t):
+        t = np.atleast_1d(t)
+        x = e[None, :] + t[:, None] * vv[None, :]
+        return np.all(x @ nn.T + dd[None, :] >= 0, axis=1)
+
+    tt = np.linspace(t1, t2, samples)
+    vs = vis(tt)
+    spacing = 1.0 / (samples - 1)
+    if not vs.any():
+        return 0.0, True, spacing
+    j0, j1 = int(np.argmax(vs)), samples - 1 - int(np.argmax(vs[::-1]))
+    vis1 = lambda t: bool(vis(t)[0])
+    a = bisect(tt[j0 - 1], tt[j0], vis1, False) if j0 > 0 else t1
+    b = bisect(tt[j1], tt[j1 + 1], vis1, True) if j1 < samples - 1 else t2
+    return (b - a) / (t2 - t1), True, spacing
+
+
+render_region = render   # render takes a plane or a region (a Plane with extra planes)

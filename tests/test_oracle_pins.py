@@ -618,3 +618,174 @@ def test_clip_mode_validation():
     for bad in (3, oracle.CLIP_HARD | oracle.CLIP_TIGHT, oracle.CLIP_TIGHT):
         with pytest.raises(ValueError):
             oracle.classify(sc, _mode_plane(pl, bad))
+
+
+# ---- clip regions: intersections of several half-spaces (Sec. 6 extension) ----
+
+def _rand_case(rng):
+    s = np.exp(rng.normal(-2, 0.6, 3))
+    q = rng.standard_normal(4)
+    mu = rng.uniform(-1, 1, 3)
+    e = mu + _rand_unit(rng) * rng.uniform(1.0, 4.0)
+    v = mu + rng.normal(0, 1.5, 3) * s - e
+    return s, q, mu, e, v
+
+
+def _plane_near(rng, mu, s, lo=-3.0, hi=3.0):
+    n = _rand_unit(rng)
+    return np.array([*n, -float(np.dot(n, mu)) + rng.uniform(lo, hi) * s.max()])
+
+
+def test_region_of_one_plane_is_the_plane_weight():
+    """A region of one half-space gives eq. (11)'s weight of that plane, the
+    single-plane oracle pinned above, to rounding."""
+    rng = np.random.default_rng(71)
+    for _ in range(300):
+        s, q, mu, e, v = _rand_case(rng)
+        pl = _plane_near(rng, mu, s)
+        w1, i1 = oracle.weight(e, v, mu, q, s, pl[:3], pl[3])
+        w2, i2 = oracle.weight_region(e, v, mu, q, s, pl[None, :])
+        assert abs(w1 - w2) <= 1e-12, (w1, w2)
+
+
+def test_region_weight_matches_brute_force_marching():
+    """Regions of 2-6 random planes through the Gaussian: the oracle's weight
+    equals the part of the chord inside every half-space measured by marching
+    and bisection."""
+    rng = np.random.default_rng(72)
+    checked = zero = part = 0
+    for _ in range(250):
+        s, q, mu, e, v = _rand_case(rng)
+        # mostly keeping the centre inside, so that regions with a partly visible chord are common
+        planes = np.stack([_plane_near(rng, mu, s, -1.5, 3.0) for _ in range(int(rng.integers(2, 7)))])
+        w, info = oracle.weight_region(e, v, mu, q, s, planes)
+        if abs(info[0]) < 1e-6:
+            continue
+        Vinv = np.linalg.inv(independent.cov3(q, s))
+        w_bf, hit, spacing = independent.chord_weight_region(e, v, mu, Vinv, planes)
+        assert hit == (info[0] > 0)
+        if w_bf == 0.0 and w <= 2 * spacing:
+            pass   # a visible piece narrower than the marching step
+        else:
+            assert abs(w - w_bf) < 1e-7, (w, w_bf, info)
+        checked += 1
+        zero += w == 0.0
+        part += 0.0 < w < 1.0
+    assert checked > 200 and zero > 10 and part > 30
+
+
+def test_region_redundant_and_disjoint_planes():
+    """A plane repeated, or joined by planes far outside the Gaussian, gives
+    that plane's weight; two half-spaces with a gap between them leave no
+    visible chord (w = 0 for every hit)."""
+    rng = np.random.default_rng(73)
+    for _ in range(100):
+        s, q, mu, e, v = _rand_case(rng)
+        pl = _plane_near(rng, mu, s)
+        w1, info = oracle.weight(e, v, mu, q, s, pl[:3], pl[3])
+        if not info[0] > 0:
+            continue
+        far = []
+        for _ in range(3):
+            n = _rand_unit(rng)
+            far.append([*n, -float(np.dot(n, mu)) + 50.0])
+        for planes in (np.stack([pl, pl]), np.stack([pl] + far)):
+            w2, _ = oracle.weight_region(e, v, mu, q, s, planes)
+            assert abs(w1 - w2) <= 1e-12
+        n = _rand_unit(rng)
+        gap = np.stack([[*n, -float(np.dot(n, mu)) - 10.0], [*(-n), float(np.dot(n, mu)) - 10.0]])
+        w3, info3 = oracle.weight_region(e, v, mu, q, s, gap)
+        if info3[0] > 0 and info3[1] >= 0:
+            assert w3 == 0.0
+
+
+def test_region_strict_miss_uses_every_plane():
+    """Strict miss policy in a region: a missing ray gets w = 1 exactly when
+    its closest approach to the centre (whitened metric) is inside every
+    half-space."""
+    rng = np.random.default_rng(74)
+    seen = {0.0: 0, 1.0: 0}
+    for _ in range(400):
+        s, q, mu, e, _ = _rand_case(rng)
+        v = mu + _rand_unit(rng) * 5.0 * s.max() - e     # aims beside the ellipsoid
+        planes = np.stack([_plane_near(rng, mu, s) for _ in range(3)])
+        w, info = oracle.weight_region(e, v, mu, q, s, planes, strict_miss=True)
+        if not info[0] < -1e-9:
+            continue
+        Minv = oracle.minv(q, s)
+        vv = v / np.linalg.norm(v)
+        et, vt = Minv @ (e - mu), Minv @ vv
+        ts = -np.dot(et, vt) / np.dot(vt, vt)
+        x = e + ts * vv
+        pa = planes / np.linalg.norm(planes[:, :3], axis=1)[:, None]
+        vals = pa[:, :3] @ x + pa[:, 3]
+        if np.abs(vals).min() < 1e-9:
+            continue
+        assert w == (1.0 if (vals >= 0).all() else 0.0)
+        seen[w] += 1
+    assert seen[0.0] > 20 and seen[1.0] > 5
+
+
+def test_region_labels_follow_the_inequalities():
+    """Labels for a box of six half-spaces, from per-plane distances computed
+    here: INVISIBLE beyond r outside any face, VISIBLE beyond r inside every
+    face, CUTOFF otherwise; hard clipping keeps exactly the centres inside."""
+    sc = scenes.tiny_scene(5)
+    box = scenes.box_region((-0.75, -0.8, -0.7), (0.8, 0.7, 0.75))
+    label, dep, rad = oracle.classify(sc, box)
+    pa = box.planes_array().astype(np.float64)
+    nn = pa[:, :3] / np.linalg.norm(pa[:, :3], axis=1)[:, None]
+    dist = nn @ sc.mean.astype(np.float64) + (pa[:, 3] / np.linalg.norm(pa[:, :3], axis=1))[:, None]
+    r = 3.0 * sc.scale.astype(np.float64).max(0)
+    want = np.where((dist < -r).any(0), 0, np.where((dist > r).all(0), 1, 2))
+    np.testing.assert_array_equal(label, want)
+    np.testing.assert_allclose(dep, dist, atol=1e-12)
+    assert (label == 0).sum() > 50 and (label == 1).sum() > 50 and (label == 2).sum() > 50
+    hard, _, _ = oracle.classify(sc, scenes.Plane(box.n, box.d, 2, box.extra))
+    np.testing.assert_array_equal(hard, (dist >= 0).all(0).astype(np.uint8))
+
+
+def test_box_around_the_scene_is_the_plain_render():
+    """A box that holds every Gaussian's 3-sigma ball leaves the frame
+    unclipped: the image equals the render without a plane exactly."""
+    sc = scenes.tiny_scene(6)
+    cam = scenes.tiny_camera()
+    m = sc.mean.astype(np.float64)
+    pad = 3.0 * float(sc.scale.max()) + 0.05
+    box = scenes.box_region(m.min(1) - pad, m.max(1) + pad)
+    a = oracle.render(sc, cam, box, events=False)
+    b = oracle.render(sc, cam, scenes.Plane(box.n, box.d, False), events=False)
+    assert (a["label"] == 1).all()
+    np.testing.assert_array_equal(a["image"], b["image"])
+
+
+def test_plane_plus_far_planes_renders_as_the_plane():
+    """A region of one plane and five planes far outside the scene renders
+    the single-plane frame exactly (labels, image, n_contrib)."""
+    sc = scenes.tiny_scene(7)
+    cam = scenes.tiny_camera()
+    pl = scenes.tiny_plane(7)
+    rng = np.random.default_rng(75)
+    far = [(scenes._f32(n), 40.0) for n in (_rand_unit(rng) for _ in range(5))]
+    reg = scenes.Plane(pl.n, pl.d, True, tuple(far))
+    a = oracle.render(sc, cam, reg, events=False)
+    b = oracle.render(sc, cam, pl, events=False)
+    np.testing.assert_array_equal(a["label"], b["label"])
+    np.testing.assert_array_equal(a["image"], b["image"])
+    np.testing.assert_array_equal(a["n_contrib"], b["n_contrib"])
+    assert (a["label"] == 2).sum() > 20
+
+
+def test_box_render_matches_independent_marcher():
+    """End to end on a box: the oracle frame of a few large Gaussians equals a
+    brute-force render whose weights come from the region marcher, except
+    on pixels the oracle flags as discontinuity events."""
+    sc = scenes.small_scene(3)
+    cam = scenes.small_camera()
+    box = scenes.box_region((-0.25, -0.2, -0.3), (0.2, 0.3, 0.25))
+    o = oracle.render(sc, cam, box)
+    img = independent.render_region(sc, cam, box)
+    ok = o["flags"] == 0
+    assert ok.mean() > 0.9 and (o["label"] == 2).sum() >= 3
+    err = np.abs(o["image"] - img).max(0)[ok]
+    assert err.max() < 1e-5, err.max()

@@ -12,6 +12,7 @@ the dominant kernel and the FP64 oracle timed on a bounded sample on the host.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -172,10 +173,11 @@ def oracle_frame(sc, cam, plane, budget_s):
         image = np.zeros((3, H, W)); fT = np.ones(H * W); nc = np.zeros(H * W, np.int32)
         nw = np.zeros(H * W, np.int32); fl = np.zeros(H * W, np.uint32); cnt = np.zeros(8, np.int64)
         bg = np.zeros(3, np.float32)
+        pa = oracle.planes_of(plane)
         s = time.perf_counter()
         L.oracle_composite(sc.n, oracle._p(lab), oracle._p(proj["mean2d"]), oracle._p(proj["conic"]),
                            oracle._p(sc.opacity), oracle._p(proj["rgb"]), oracle._p(sc.mean), oracle._p(proj["minv"]),
-                           oracle._p(plane.as_array()), oracle.clip_mode(plane), oracle._p(oracle.cam_array(cam)), W,
+                           oracle._p(pa), pa.shape[0], oracle.clip_mode(plane), oracle._p(oracle.cam_array(cam)), W,
                            H, oracle._p(bg), oracle._p(offs), oracle._p(ids), 3.0, 0, int(t0_), int(t1_), 1e-3,
                            oracle._p(image), oracle._p(fT), oracle._p(nc), oracle._p(nw), oracle._p(fl),
                            oracle._p(cnt))
@@ -311,8 +313,8 @@ def measure(sc, frames, args, reps, label):
     W, H = frames[0][0].width, frames[0][0].height
     stream = torch.cuda.current_stream(dev)
     variants = {"rara": frames,
-                "original": [(cam, type(pl)(pl.n, pl.d, 0)) for cam, pl in frames],
-                "hard": [(cam, type(pl)(pl.n, pl.d, 2)) for cam, pl in frames]}
+                "original": [(cam, dataclasses.replace(pl, enabled=0)) for cam, pl in frames],
+                "hard": [(cam, dataclasses.replace(pl, enabled=2)) for cam, pl in frames]}
     if args.no_plain:
         del variants["original"], variants["hard"]
     # capacity from one pass over every frame (outside the timed region)
@@ -421,6 +423,26 @@ def multilayer_workload():
     frames = [(c, p) for c in cams for p in planes]
     desc = {"workload": "multi-layer scene, 5 shells x 300,000 = 1,500,000 Gaussians, SH2, 1024x1024, "
                         "8 cameras x 4 planes", "gaussians": sc.n, "width": 1024, "height": 1024}
+    return sc, frames, desc
+
+
+def box_workload():
+    """Box clipping of a layered field, the case the paper cites for clip
+    regions: the 1.5M-Gaussian multi-layer scene at 1024x1024, 8 cameras on a
+    radius-5 sphere x 8 axis-aligned boxes (six half-spaces each) around a
+    point near the centre, from one holding every shell to one inside the
+    innermost."""
+    from paper_2506_20202_amd import scenes
+    rng = np.random.default_rng(9)
+    sc = scenes.multilayer_scene(32, per_shell=300_000, sh_degree=2)
+    cams = [scenes.random_camera_on_sphere(rng, 5.0, 1024, 1024) for _ in range(8)]
+    c = rng.uniform(-0.2, 0.2, 3)
+    boxes = [scenes.box_region(c - h * np.array([1.0, 0.8, 0.9]), c + h * np.array([0.9, 1.0, 0.8]))
+             for h in np.linspace(2.3, 0.5, 8)]
+    frames = [(cam, b) for cam in cams for b in boxes]
+    desc = {"workload": "box clipping: multi-layer scene, 1,500,000 Gaussians, SH2, 1024x1024, 8 cameras x 8 "
+                        "boxes (half-sizes 2.3 to 0.5 around a point near the centre)",
+            "gaussians": sc.n, "width": 1024, "height": 1024}
     return sc, frames, desc
 
 
@@ -555,6 +577,10 @@ def main():
         mm = measure(msc, mframes, args, max(1, args.reps // 2), "multilayer")
         secondary["multilayer"] = dict(mdesc, **mm)
         del msc, mframes
+        bsc, bframes, bdesc = box_workload()
+        bm = measure(bsc, bframes, args, max(1, args.reps // 2), "box")
+        secondary["box"] = dict(bdesc, **bm)
+        del bsc, bframes
         secondary["differentiable"] = diff_bench(3)
         print(f"[bench] differentiable batch {secondary['differentiable']['batch_ms']:.2f} ms "
               f"(forward {secondary['differentiable']['forward_ms']:.2f} ms)", file=sys.stderr, flush=True)

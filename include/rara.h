@@ -94,7 +94,21 @@ typedef struct {
  *                             to the centre (whitened metric) is visible, else
  *                             0, instead of w = 1 (the sub-pixel case of the
  *                             paper's closing discussion).
- * Any other value is RARA_ERR_INVALID. */
+ * Any other value is RARA_ERR_INVALID.
+ *
+ * Clip regions (the extension to other clipping primitives that Sec. 6
+ * names; Sec. 2 cites box clipping of multi-layer fields): with count >= 2
+ * the visible region is the intersection of the half-spaces of (n, d) and
+ * extra[0 .. count-2], each (n.x, n.y, n.z, d); an axis-aligned box is six.
+ * Every mode applies with the plane read as the region: a Gaussian is
+ * INVISIBLE when it is beyond r outside any plane, VISIBLE when it is beyond
+ * r inside every plane, CUTOFF otherwise; hard clipping keeps it when its
+ * centre is inside every half-space; eq. (11)'s L_vis is the part of the
+ * chord inside every half-space; a strict miss needs the closest approach
+ * inside every half-space.  count 0 or 1 is the single plane (n, d).
+ * Regions need rara_projected.ray_ext; rara_render_backward and frame graphs
+ * take a single plane only (RARA_ERR_UNSUPPORTED otherwise).  A count above
+ * RARA_MAX_PLANES is RARA_ERR_INVALID. */
 enum {
     RARA_CLIP_OFF = 0,
     RARA_CLIP_RARA = 1,
@@ -102,10 +116,13 @@ enum {
     RARA_CLIP_TIGHT = 4,
     RARA_CLIP_STRICT_MISS = 8
 };
+#define RARA_MAX_PLANES 8
 typedef struct {
     float n[3];
     float d;
     int32_t enabled;
+    int32_t count;
+    float extra[RARA_MAX_PLANES - 1][4];
 } rara_plane;
 
 /* Per-Gaussian results of rara_preprocess (caller-allocated, n entries each).
@@ -122,6 +139,10 @@ typedef struct {
  *   depth [n] float            camera depth of drawn Gaussians.
  *   rect  [n][4] uint16        tile rectangle tx0, ty0, tx1, ty1 (half-open).
  *   tiles_touched [n] uint32   (tx1-tx0)(ty1-ty0) if drawn, else 0.
+ *   ray_ext [n][RARA_MAX_PLANES-1][2] float   optional (NULL with a single
+ *                              plane; required by a clip region): for drawn
+ *                              CUTOFF Gaussians, the ray terms of the region's
+ *                              further planes (private layout, like ray).
  * A Gaussian is drawn when it is not INVISIBLE, its depth exceeds near_z and
  * its footprint ceil(3 sqrt(lambda_max)) px box meets the image. */
 typedef struct {
@@ -131,6 +152,7 @@ typedef struct {
     float* depth;
     uint16_t* rect;
     uint32_t* tiles_touched;
+    float* ray_ext;
 } rara_projected;
 
 /* Binned, depth-sorted (tile, Gaussian) pairs (caller-allocated).

@@ -31,12 +31,18 @@ class Camera(ctypes.Structure):
                 ("height", ctypes.c_int32), ("near_z", ctypes.c_float)]
 
 
+MAX_PLANES = 8
+RAY_EXT_FLOATS = 2 * (MAX_PLANES - 1)   # per Gaussian, rara_projected.ray_ext
+
+
 class Plane(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_float * 3), ("d", ctypes.c_float), ("enabled", ctypes.c_int32)]
+    _fields_ = [("n", ctypes.c_float * 3), ("d", ctypes.c_float), ("enabled", ctypes.c_int32),
+                ("count", ctypes.c_int32), ("extra", (ctypes.c_float * 4) * (MAX_PLANES - 1))]
 
 
 class Projected(ctypes.Structure):
-    _fields_ = [("label", _P), ("splat", _P), ("ray", _P), ("depth", _P), ("rect", _P), ("tiles_touched", _P)]
+    _fields_ = [("label", _P), ("splat", _P), ("ray", _P), ("depth", _P), ("rect", _P), ("tiles_touched", _P),
+                ("ray_ext", _P)]
 
 
 class Binned(ctypes.Structure):
@@ -117,10 +123,17 @@ def make_camera(cam) -> Camera:
 
 
 def make_plane(plane) -> Plane:
+    """rara_plane of a plane, or of a region (a plane with ``extra`` planes)."""
     p = Plane()
     p.n = (ctypes.c_float * 3)(*[float(v) for v in plane.n])
     p.d = float(plane.d)
     p.enabled = int(plane.enabled)   # clip mode: False/True -> off/RaRa, ints pass through
+    extra = list(getattr(plane, "extra", ()))
+    if len(extra) > MAX_PLANES - 1:
+        raise ValueError(f"a clip region has at most {MAX_PLANES} planes")
+    p.count = 1 + len(extra)
+    for k, (n, d) in enumerate(extra):
+        p.extra[k] = (ctypes.c_float * 4)(float(n[0]), float(n[1]), float(n[2]), float(d))
     return p
 
 

@@ -33,23 +33,35 @@ bool make_cam(const rara_camera* c, CamParams* p)
     return true;
 }
 
+// (n, d) / |n| of one plane; false for a zero or non-finite normal or offset
+bool normalise(const float* n, float d, double* out_n, double* out_d)
+{
+    const double n0 = n[0], n1 = n[1], n2 = n[2];
+    const double len = std::sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    if (!(len > 0.0) || !std::isfinite(len) || !std::isfinite((double)d)) return false;
+    out_n[0] = n0 / len;
+    out_n[1] = n1 / len;
+    out_n[2] = n2 / len;
+    *out_d = (double)d / len;
+    return true;
+}
+
 bool make_plane(const rara_plane* pl, PlaneParams* p)
 {
     if (!pl) return false;
     const int mode = pl->enabled, rule = mode & 3, flags = mode & ~3;
     if (rule == 3 || (flags & ~(RARA_CLIP_TIGHT | RARA_CLIP_STRICT_MISS)) || (flags && rule != RARA_CLIP_RARA))
         return false;
+    if (pl->count < 0 || pl->count > kMaxPlanes) return false;
     p->enabled = mode;
+    p->count = pl->count > 1 ? pl->count : 1;
     p->n[0] = p->n[1] = p->n[2] = 0.0;
     p->d = 0.0;
+    for (int k = 0; k < kMaxPlanes - 1; ++k) p->xn[k][0] = p->xn[k][1] = p->xn[k][2] = p->xd[k] = 0.0;
     if (!p->enabled) return true;
-    const double n0 = pl->n[0], n1 = pl->n[1], n2 = pl->n[2];
-    const double len = std::sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-    if (!(len > 0.0) || !std::isfinite(len) || !std::isfinite((double)pl->d)) return false;
-    p->n[0] = n0 / len;
-    p->n[1] = n1 / len;
-    p->n[2] = n2 / len;
-    p->d = (double)pl->d / len;
+    if (!normalise(pl->n, pl->d, p->n, &p->d)) return false;
+    for (int k = 1; k < p->count; ++k)
+        if (!normalise(pl->extra[k - 1], pl->extra[k - 1][3], p->xn[k - 1], &p->xd[k - 1])) return false;
     return true;
 }
 
@@ -67,7 +79,8 @@ bool proj_ok(const rara_projected* p)
 
 ProjPtrs proj_ptrs(const rara_projected* p)
 {
-    return ProjPtrs{p->label, static_cast<Splat*>(p->splat), static_cast<RayRec*>(p->ray), p->depth, p->rect,
+    return ProjPtrs{p->label, static_cast<Splat*>(p->splat), static_cast<RayRec*>(p->ray),
+                    reinterpret_cast<float2*>(p->ray_ext), p->depth, p->rect,
                     p->tiles_touched};
 }
 
@@ -90,6 +103,14 @@ RenderParams rara::make_render_params(const CamParams& cp, const PlaneParams& pp
     const double rn1 = cp.R[3] * pp.n[0] + cp.R[4] * pp.n[1] + cp.R[5] * pp.n[2];
     rp.ax = (float)(rn0 / cp.fx);
     rp.ay = (float)(rn1 / cp.fy);
+    rp.plane_count = pp.count;
+    for (int k = 0; k < kMaxPlanes - 1; ++k) {
+        const double* xn = pp.xn[k];
+        const double x0 = cp.R[0] * xn[0] + cp.R[1] * xn[1] + cp.R[2] * xn[2];
+        const double x1 = cp.R[3] * xn[0] + cp.R[4] * xn[1] + cp.R[5] * xn[2];
+        rp.xax[k] = (float)(x0 / cp.fx);
+        rp.xay[k] = (float)(x1 / cp.fy);
+    }
     rp.bg[0] = bg[0];
     rp.bg[1] = bg[1];
     rp.bg[2] = bg[2];
@@ -173,6 +194,7 @@ rara_status rara_preprocess(const rara_gaussians* g, const rara_camera* cam, con
     if (cp.tiles_x > 65535 || cp.tiles_y > 65535) return RARA_ERR_UNSUPPORTED;
     if (g->n == 0) return RARA_OK;
     if (!g->mean || !g->scale || !g->quat || !g->opacity || !g->sh || !proj_ok(out)) return RARA_ERR_INVALID;
+    if (pp.enabled && pp.count > 1 && !out->ray_ext) return RARA_ERR_INVALID;   // a region's further planes
     GaussPtrs gp{g->n, g->sh_degree, g->mean, g->scale, g->quat, g->opacity, g->sh};
     const hipError_t e = launch_preprocess(gp, cp, pp, proj_ptrs(out), static_cast<hipStream_t>(stream));
     return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
@@ -211,9 +233,11 @@ rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned
     CamParams cp;
     PlaneParams pp;
     if (!make_cam(cam, &cp) || !make_plane(plane, &pp)) return RARA_ERR_INVALID;
+    if (pp.enabled && pp.count > 1 && !proj->ray_ext) return RARA_ERR_INVALID;
     const RenderParams rp = make_render_params(cp, pp, bg);
     const hipError_t e = launch_blend(static_cast<const Splat*>(proj->splat), static_cast<const RayRec*>(proj->ray),
-                                      *bins, rp, image, final_T, n_contrib, n_walked, static_cast<hipStream_t>(stream));
+                                      reinterpret_cast<const float2*>(proj->ray_ext), *bins, rp, image, final_T,
+                                      n_contrib, n_walked, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
 }
 
@@ -235,6 +259,7 @@ rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam
     CamParams cp;
     PlaneParams pp;
     if (!make_cam(cam, &cp) || !make_plane(plane, &pp)) return RARA_ERR_INVALID;
+    if (pp.enabled && pp.count > 1) return RARA_ERR_UNSUPPORTED;   // gradients of one plane only
     if (ws_bytes < backward_workspace_bytes(g->n, pair_capacity, cp.W, cp.H)) return RARA_ERR_INVALID;
     const RenderParams rp = make_render_params(cp, pp, bg);
     const double len = pp.enabled ? std::sqrt((double)plane->n[0] * plane->n[0] + (double)plane->n[1] * plane->n[1] +

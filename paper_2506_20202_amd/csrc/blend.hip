@@ -74,10 +74,14 @@ constexpr int kBatchSlots = 256;     // s_c rows: four 64-entry ballots, the tai
 // that reach its quadrant and one of the CUTOFF entries, and visits the set
 // bits in order.  A wave re-takes its live pixels every 16 entries and stops
 // visiting once none is left; the workgroup stops when no wave has one.
-template <bool kWalked>
+// kRegion: the clip region of p.plane_count half-spaces (chord_weight_region),
+// with each CUTOFF entry's further-plane terms staged in s_ext and the
+// per-frame rates of those planes in s_rate.
+template <bool kWalked, bool kRegion>
 __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
-                                  const uint32_t* __restrict__ vals, const uint2 rg, int tile,
-                                  const RenderParams& p, float4* s_a, float4* s_b, float2* s_c, CutRec* s_cut,
+                                  const float2* __restrict__ ray_ext, const uint32_t* __restrict__ vals,
+                                  const uint2 rg, int tile, const RenderParams& p, float4* s_a, float4* s_b,
+                                  float2* s_c, CutRec* s_cut, float2* s_ext, float2* s_rate,
                                   float* __restrict__ image, float* __restrict__ final_T,
                                   uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
 {
@@ -126,6 +130,9 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
                 s_cut[tid].a = r0;
                 s_cut[tid].b = r1;
                 s_cut[tid].c = r2;
+                if (kRegion)
+                    for (int k = 0; k < p.plane_count - 1; ++k)
+                        s_ext[tid * (kMaxPlanes - 1) + k] = ray_ext[(int64_t)id * (kMaxPlanes - 1) + k];
             }
         }
         s_c[tid] = sc;
@@ -152,7 +159,9 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
                         // alpha <= a0 (w <= 1): when no pixel can reach its threshold the
                         // entry changes nothing and its weight is not needed
                         if (__ballot(a0 >= thr) == 0ull) continue;
-                        w = chord_weight_flat(s_cut[e], dx, dy, p.ax, p.ay, strict);
+                        w = kRegion ? chord_weight_region(s_cut[e], s_ext + e * (kMaxPlanes - 1), p.plane_count,
+                                                          dx, dy, p.ax, p.ay, s_rate, strict)
+                                    : chord_weight_flat(s_cut[e], dx, dy, p.ax, p.ay, strict);
                     }
                     composite(a0, w, b.z, b.w, cb_, kofs + e, T, thr, C0, C1, C2, last, walked);
                 }
@@ -174,12 +183,13 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
     if (kWalked) n_walked[pix] = thr < 1.0f ? rg.y - rg.x : walked;
 }
 
-template <bool kWalked>
+template <bool kWalked, bool kRegion>
 __device__ __forceinline__ void blend_block(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
-                                            const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
-                                            const uint32_t* __restrict__ work, const RenderParams& p,
-                                            float* __restrict__ image, float* __restrict__ final_T,
-                                            uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
+                                            const float2* __restrict__ ray_ext, const uint32_t* __restrict__ vals,
+                                            const uint2* __restrict__ ranges, const uint32_t* __restrict__ work,
+                                            const RenderParams& p, float* __restrict__ image,
+                                            float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
+                                            uint32_t* __restrict__ n_walked)
 {
     uint32_t tile;
     if (!tile_of_block(blockIdx.x, work, p.num_tiles, tile)) return;
@@ -187,8 +197,14 @@ __device__ __forceinline__ void blend_block(const Splat* __restrict__ splats, co
     __shared__ float4 s_a[kTileBatch], s_b[kTileBatch];
     __shared__ float2 s_c[kBatchSlots];
     __shared__ CutRec s_cut[kTileBatch];
-    blend_tile<kWalked>(splats, rays, vals, ranges[tile], (int)tile, p, s_a, s_b, s_c, s_cut, image, final_T,
-                        n_contrib, n_walked);
+    __shared__ float2 s_ext[kRegion ? kTileBatch * (kMaxPlanes - 1) : 1];
+    __shared__ float2 s_rate[kMaxPlanes - 1];
+    if (kRegion) {
+        // the further planes' per-frame rates; the first batch's barrier orders them before any visit
+        if (threadIdx.x < kMaxPlanes - 1) s_rate[threadIdx.x] = make_float2(p.xax[threadIdx.x], p.xay[threadIdx.x]);
+    }
+    blend_tile<kWalked, kRegion>(splats, rays, ray_ext, vals, ranges[tile], (int)tile, p, s_a, s_b, s_c, s_cut, s_ext,
+                                 s_rate, image, final_T, n_contrib, n_walked);
 }
 
 template <bool kWalked>
@@ -199,7 +215,22 @@ void blend_kernel(const Splat* __restrict__ splats, const RayRec* __restrict__ r
                   float* __restrict__ final_T, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
 {
     if (*overflow) return;
-    blend_block<kWalked>(splats, rays, vals, ranges, work, p, image, final_T, n_contrib, n_walked);
+    blend_block<kWalked, false>(splats, rays, nullptr, vals, ranges, work, p, image, final_T, n_contrib, n_walked);
+}
+
+// Clip-region variant (p.plane_count > 1): more LDS per workgroup for the
+// further planes' terms, fewer workgroups per CU.
+template <bool kWalked>
+__global__ __launch_bounds__(kBlendThreads)
+void blend_region_kernel(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
+                         const float2* __restrict__ ray_ext, const uint32_t* __restrict__ vals,
+                         const uint2* __restrict__ ranges, const uint32_t* __restrict__ work,
+                         const int32_t* __restrict__ overflow, RenderParams p, float* __restrict__ image,
+                         float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
+                         uint32_t* __restrict__ n_walked)
+{
+    if (*overflow) return;
+    blend_block<kWalked, true>(splats, rays, ray_ext, vals, ranges, work, p, image, final_T, n_contrib, n_walked);
 }
 
 // Frame-graph variant: render parameters read from device memory.
@@ -213,23 +244,31 @@ void blend_fp_kernel(const Splat* __restrict__ splats, const RayRec* __restrict_
 {
     if (*overflow) return;
     const RenderParams p = fp->render;
-    blend_block<kWalked>(splats, rays, vals, ranges, work, p, image, final_T, n_contrib, n_walked);
+    blend_block<kWalked, false>(splats, rays, nullptr, vals, ranges, work, p, image, final_T, n_contrib, n_walked);
 }
 
 }  // namespace
 
-hipError_t launch_blend(const Splat* splat, const RayRec* ray, const rara_binned& bins, const RenderParams& p,
-                        float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked, hipStream_t s)
+hipError_t launch_blend(const Splat* splat, const RayRec* ray, const float2* ray_ext, const rara_binned& bins,
+                        const RenderParams& p, float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked,
+                        hipStream_t s)
 {
     const unsigned grid = (unsigned)tiles_grid(p.num_tiles);
-    if (n_walked)
-        hipLaunchKernelGGL(blend_kernel<true>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals,
-                           reinterpret_cast<const uint2*>(bins.ranges), bins.work, bins.overflow, p, image, final_T,
-                           n_contrib, n_walked);
-    else
-        hipLaunchKernelGGL(blend_kernel<false>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals,
-                           reinterpret_cast<const uint2*>(bins.ranges), bins.work, bins.overflow, p, image, final_T,
-                           n_contrib, n_walked);
+    const uint2* ranges = reinterpret_cast<const uint2*>(bins.ranges);
+    if (p.plane_enabled && p.plane_count > 1) {
+        if (n_walked)
+            hipLaunchKernelGGL(blend_region_kernel<true>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, ray_ext,
+                               bins.vals, ranges, bins.work, bins.overflow, p, image, final_T, n_contrib, n_walked);
+        else
+            hipLaunchKernelGGL(blend_region_kernel<false>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, ray_ext,
+                               bins.vals, ranges, bins.work, bins.overflow, p, image, final_T, n_contrib, n_walked);
+    } else if (n_walked) {
+        hipLaunchKernelGGL(blend_kernel<true>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals, ranges,
+                           bins.work, bins.overflow, p, image, final_T, n_contrib, n_walked);
+    } else {
+        hipLaunchKernelGGL(blend_kernel<false>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals, ranges,
+                           bins.work, bins.overflow, p, image, final_T, n_contrib, n_walked);
+    }
     return hipGetLastError();
 }
 
@@ -240,8 +279,8 @@ hipError_t launch_blend_fp(const Splat* splat, const RayRec* ray, const rara_bin
     const unsigned grid = (unsigned)tiles_grid(num_tiles);
     const uint2* ranges = reinterpret_cast<const uint2*>(bins.ranges);
     if (n_walked)
-        hipLaunchKernelGGL(blend_fp_kernel<true>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals, ranges, bins.work,
-                           bins.overflow, fp, image, final_T, n_contrib, n_walked);
+        hipLaunchKernelGGL(blend_fp_kernel<true>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals, ranges,
+                           bins.work, bins.overflow, fp, image, final_T, n_contrib, n_walked);
     else
         hipLaunchKernelGGL(blend_fp_kernel<false>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals, ranges,
                            bins.work, bins.overflow, fp, image, final_T, n_contrib, n_walked);

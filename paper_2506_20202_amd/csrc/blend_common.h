@@ -126,6 +126,61 @@ __device__ inline float chord_weight_flat(const CutRec& k, float dx, float dy, f
     return h2 > 0.0f ? w : miss;
 }
 
+// Clip weight for a region, the intersection of `count` half-spaces: plane 0
+// from the ray record, planes 1.. from ext[k - 1] = (d_ep, g0) and the
+// per-frame rates[k - 1] = (ax, ay).  The chord geometry is chord_eval's.  Along the
+// chord, s in [-h, h] from its midpoint (camera depth), plane k has the value
+// phi_k + g_k s; the chord is visible where every one is >= 0, an interval
+// [lo, hi]: planes with g_k > 0 raise lo to -phi_k / g_k, planes with g_k < 0
+// lower hi to it, a plane with g_k = 0 keeps all or nothing.  The weight is
+// (hi - lo) / 2h clamped to [0, 1] (for one plane this is eq. (11)'s
+// 1/2 + phi / (2 |g| h)).  A miss keeps w = 1, or with the strict policy
+// w = [the closest approach is inside every half-space]; a near root behind
+// the camera keeps w = 1.
+__device__ inline float chord_weight_region(const CutRec& k, const float2* __restrict__ ext, int count, float dx,
+                                            float dy, float ax, float ay, const float2* __restrict__ rates,
+                                            bool strict)
+{
+    const float gx[3] = {k.a.w, k.b.x, k.b.y};
+    const float gy[3] = {k.b.z, k.b.w, k.c.x};
+    const float d0[3] = {k.a.x, k.a.y, k.a.z};
+    const float z = k.c.y;
+    float D[3], P[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float e = fmaf(gx[i], dx, gy[i] * dy);
+        D[i] = d0[i] + e;
+        P[i] = z * e;
+    }
+    const float DD = fmaf(D[0], D[0], fmaf(D[1], D[1], D[2] * D[2]));
+    const float PD = fmaf(P[0], D[0], fmaf(P[1], D[1], P[2] * D[2]));
+    const float iDD = __builtin_amdgcn_rcpf(DD);
+    const float sm = -PD * iDD;
+    float Q[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Q[i] = fmaf(sm, D[i], P[i]);
+    const float h2 = kKappa2 - fmaf(Q[0], Q[0], fmaf(Q[1], Q[1], Q[2] * Q[2]));
+    const float hs = __builtin_amdgcn_sqrtf(h2 * iDD);   // NaN for a miss: not selected
+    float lo = -hs, hi = hs;
+    bool empty = false, all_in = true;
+    for (int p = 0; p < count; ++p) {
+        const float2 pe = p == 0 ? make_float2(k.c.z, k.c.w) : ext[p - 1];
+        const float pax = p == 0 ? ax : rates[p - 1].x, pay = p == 0 ? ay : rates[p - 1].y;
+        const float u = fmaf(pax, dx, pay * dy);
+        const float gg = pe.y + u;
+        const float phim = fmaf(sm, gg, fmaf(z, u, pe.x));
+        all_in = all_in && phim >= 0.0f;
+        const float c = -phim * __builtin_amdgcn_rcpf(gg);
+        lo = gg > 0.0f ? fmaxf(lo, c) : lo;
+        hi = gg < 0.0f ? fminf(hi, c) : hi;
+        empty = empty || (gg == 0.0f && phim < 0.0f);
+    }
+    float w = empty ? 0.0f : __builtin_amdgcn_fmed3f((hi - lo) * __builtin_amdgcn_rcpf(2.0f * hs), 0.0f, 1.0f);
+    w = (z + sm) - hs < 0.0f ? 1.0f : w;
+    const float miss = (strict && h2 < 0.0f) ? (all_in ? 1.0f : 0.0f) : 1.0f;
+    return h2 > 0.0f ? w : miss;
+}
+
 // Whether the alpha >= 1/255 region of an entry can reach the pixel centres
 // [qx, qx + 7] x [qy, qy + 7] (tile coordinates).  alpha >= 1/255 needs the
 // conic form q(d) = ca dx^2 + 2 cb dx dy + cc dy^2 at d = pixel - centre to be

@@ -80,8 +80,8 @@ rara_status rara_frame_graph_create(const rara_gaussians* g, const rara_camera* 
     }
 
     const GaussPtrs gp{g->n, g->sh_degree, g->mean, g->scale, g->quat, g->opacity, g->sh};
-    const ProjPtrs pp{proj->label, static_cast<Splat*>(proj->splat), static_cast<RayRec*>(proj->ray), proj->depth,
-                      proj->rect, proj->tiles_touched};
+    const ProjPtrs pp{proj->label, static_cast<Splat*>(proj->splat), static_cast<RayRec*>(proj->ray), nullptr,
+                      proj->depth, proj->rect, proj->tiles_touched};
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
         destroy(fg);
@@ -124,6 +124,7 @@ rara_status rara_frame_graph_launch(rara_frame_graph* fg, const rara_camera* cam
     FrameParams fp;
     if (!make_cam_params(cam, &fp.cam) || !make_plane_params(plane, &fp.plane)) return RARA_ERR_INVALID;
     if (fp.cam.W != fg->W || fp.cam.H != fg->H) return RARA_ERR_INVALID;
+    if (fp.plane.enabled && fp.plane.count > 1) return RARA_ERR_UNSUPPORTED;   // the graph holds the one-plane blend
     fp.render = make_render_params(fp.cam, fp.plane, bg);
     hipStream_t s = static_cast<hipStream_t>(stream);
     // the staging block may be rewritten once the previous copy out of it ran

@@ -54,28 +54,49 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
 
     // Sec. 3.2: d_ep = n.mu + d, r = 3 max(sigma); hard clipping keeps a
     // Gaussian by its centre's side; the tight variant takes r = 3 |S R^T n|.
+    // A region (count > 1 half-spaces): INVISIBLE beyond r outside any plane,
+    // VISIBLE beyond r inside every plane; hard clipping keeps a centre
+    // inside every half-space.
     uint8_t label = RARA_LABEL_VISIBLE;
     double dep = 0.0;
     if (pl.enabled) {
         dep = pl.n[0] * mu[0] + pl.n[1] * mu[1] + pl.n[2] * mu[2] + pl.d;
         if ((pl.enabled & 3) == RARA_CLIP_HARD) {
-            label = dep < 0.0 ? RARA_LABEL_INVISIBLE : RARA_LABEL_VISIBLE;
+            bool behind = dep < 0.0;
+            for (int k = 1; k < pl.count; ++k) {
+                const double* xn = pl.xn[k - 1];
+                behind = behind || xn[0] * mu[0] + xn[1] * mu[1] + xn[2] * mu[2] + pl.xd[k - 1] < 0.0;
+            }
+            label = behind ? RARA_LABEL_INVISIBLE : RARA_LABEL_VISIBLE;
         } else {
-            double r = 3.0 * fmax(fmax(s[0], s[1]), s[2]);
-            if (pl.enabled & RARA_CLIP_TIGHT) {
-                double qw = g.quat[i], qx = g.quat[n + i], qy = g.quat[2 * n + i], qz = g.quat[3 * n + i];
+            const bool tight = (pl.enabled & RARA_CLIP_TIGHT) != 0;
+            double qw = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
+            if (tight) {
+                qw = g.quat[i]; qx = g.quat[n + i]; qy = g.quat[2 * n + i]; qz = g.quat[3 * n + i];
                 const double ql = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
                 qw /= ql; qx /= ql; qy /= ql; qz /= ql;
-                // (S R^T n)_a = sigma_a (column a of R) . n
-                const double c0 = s[0] * ((1 - 2 * (qy * qy + qz * qz)) * pl.n[0] + 2 * (qx * qy + qw * qz) * pl.n[1] +
-                                          2 * (qx * qz - qw * qy) * pl.n[2]);
-                const double c1 = s[1] * (2 * (qx * qy - qw * qz) * pl.n[0] + (1 - 2 * (qx * qx + qz * qz)) * pl.n[1] +
-                                          2 * (qy * qz + qw * qx) * pl.n[2]);
-                const double c2 = s[2] * (2 * (qx * qz + qw * qy) * pl.n[0] + 2 * (qy * qz - qw * qx) * pl.n[1] +
-                                          (1 - 2 * (qx * qx + qy * qy)) * pl.n[2]);
-                r = 3.0 * sqrt(c0 * c0 + c1 * c1 + c2 * c2);
             }
-            label = dep < -r ? RARA_LABEL_INVISIBLE : (dep > r ? RARA_LABEL_VISIBLE : RARA_LABEL_CUTOFF);
+            auto radius = [&](const double* nn) {
+                if (!tight) return 3.0 * fmax(fmax(s[0], s[1]), s[2]);
+                // (S R^T n)_a = sigma_a (column a of R) . n
+                const double c0 = s[0] * ((1 - 2 * (qy * qy + qz * qz)) * nn[0] + 2 * (qx * qy + qw * qz) * nn[1] +
+                                          2 * (qx * qz - qw * qy) * nn[2]);
+                const double c1 = s[1] * (2 * (qx * qy - qw * qz) * nn[0] + (1 - 2 * (qx * qx + qz * qz)) * nn[1] +
+                                          2 * (qy * qz + qw * qx) * nn[2]);
+                const double c2 = s[2] * (2 * (qx * qz + qw * qy) * nn[0] + 2 * (qy * qz - qw * qx) * nn[1] +
+                                          (1 - 2 * (qx * qx + qy * qy)) * nn[2]);
+                return 3.0 * sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+            };
+            const double r = radius(pl.n);
+            bool outside = dep < -r, inside = dep > r;
+            for (int k = 1; k < pl.count; ++k) {
+                const double* xn = pl.xn[k - 1];
+                const double dk = xn[0] * mu[0] + xn[1] * mu[1] + xn[2] * mu[2] + pl.xd[k - 1];
+                const double rk = radius(xn);
+                outside = outside || dk < -rk;
+                inside = inside && dk > rk;
+            }
+            label = outside ? RARA_LABEL_INVISIBLE : (inside ? RARA_LABEL_VISIBLE : RARA_LABEL_CUTOFF);
         }
     }
     out.label[i] = label;
@@ -172,6 +193,13 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
                         rr.dep = (float)dep;
                         rr.g0 = (float)(pl.n[0] * v0[0] + pl.n[1] * v0[1] + pl.n[2] * v0[2]);
                         out.ray[i] = rr;
+                        // a region's further planes: (d_ep, g0) of each
+                        for (int k = 1; k < pl.count; ++k) {
+                            const double* xn = pl.xn[k - 1];
+                            const double dk = xn[0] * mu[0] + xn[1] * mu[1] + xn[2] * mu[2] + pl.xd[k - 1];
+                            out.ray_ext[i * (kMaxPlanes - 1) + (k - 1)] =
+                                make_float2((float)dk, (float)(xn[0] * v0[0] + xn[1] * v0[1] + xn[2] * v0[2]));
+                        }
                     }
                 }
             }

@@ -49,10 +49,17 @@ struct CamParams {
     int W, H, tiles_x, tiles_y;
 };
 
+constexpr int kMaxPlanes = RARA_MAX_PLANES;
+
+// Clip plane, or region: plane 0 is (n, d); with count > 1 the further
+// planes are xn / xd (all normalised).
 struct PlaneParams {
     double n[3];
     double d;
     int enabled;   // clip mode (RARA_CLIP_*), 0 when off
+    int count;     // half-spaces in the region, 1 for a single plane
+    double xn[kMaxPlanes - 1][3];
+    double xd[kMaxPlanes - 1];
 };
 
 struct GaussPtrs {
@@ -69,6 +76,7 @@ struct ProjPtrs {
     uint8_t* label;
     Splat* splat;
     RayRec* ray;
+    float2* ray_ext;   // [n][kMaxPlanes - 1] (dep, g0) of planes 1.. for a region, else unused
     float* depth;
     uint16_t* rect;
     uint32_t* tiles_touched;
@@ -79,6 +87,8 @@ struct RenderParams {
     int plane_enabled;   // clip mode (RARA_CLIP_*)
     float ax, ay;
     float bg[3];
+    int plane_count;                          // 1, or the half-spaces of a region
+    float xax[kMaxPlanes - 1], xay[kMaxPlanes - 1];   // (ax, ay) of planes 1 .. count-1
 };
 
 // Everything a frame reads that depends on the camera pose, the clip plane or
@@ -161,7 +171,8 @@ hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const Plane
                            const ProjPtrs& proj, const rara_binned& bins, int64_t pair_capacity, const RenderParams& rp,
                            const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
                            const rara_grads& grads, void* workspace, hipStream_t s);
-hipError_t launch_blend(const Splat* splat, const RayRec* ray, const rara_binned& bins, const RenderParams& p,
-                        float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked, hipStream_t s);
+hipError_t launch_blend(const Splat* splat, const RayRec* ray, const float2* ray_ext, const rara_binned& bins,
+                        const RenderParams& p, float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked,
+                        hipStream_t s);
 
 }  // namespace rara

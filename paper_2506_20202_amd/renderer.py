@@ -66,15 +66,24 @@ class ProjectedBuffers:
         self.depth = torch.empty(m, dtype=torch.float32, device=device)
         self.rect = torch.empty(m * 4, dtype=torch.int16, device=device)
         self.tiles_touched = torch.empty(m, dtype=torch.int32, device=device)
+        self.ray_ext = None   # a clip region's further-plane terms, allocated on first use
+        self.device = device
+
+    def ensure_ray_ext(self):
+        if self.ray_ext is None:
+            m = max(self.n, 1)
+            self.ray_ext = torch.empty(m * B.RAY_EXT_FLOATS, dtype=torch.float32, device=self.device)
 
     def struct(self) -> B.Projected:
         p = B.Projected()
         p.label, p.splat, p.ray = _ptr(self.label), _ptr(self.splat), _ptr(self.ray)
         p.depth, p.rect, p.tiles_touched = _ptr(self.depth), _ptr(self.rect), _ptr(self.tiles_touched)
+        p.ray_ext = _ptr(self.ray_ext)
         return p
 
     def nbytes(self) -> int:
-        return self.n * (1 + B.SPLAT_BYTES + B.RAY_BYTES + 4 + 8 + 4)
+        ext = self.ray_ext.numel() * 4 if self.ray_ext is not None else 0
+        return self.n * (1 + B.SPLAT_BYTES + B.RAY_BYTES + 4 + 8 + 4) + ext
 
 
 class BinBuffers:
@@ -148,6 +157,8 @@ def enqueue_frame(scene: DeviceScene, frame: Frame, cam, plane, bg=(0.0, 0.0, 0.
     sp = int(stream.cuda_stream)
     c = B.make_camera(cam)
     p = B.make_plane(plane)
+    if p.count > 1:
+        frame.proj.ensure_ray_ext()   # a clip region: further-plane terms per CUTOFF Gaussian
     pj = frame.proj.struct()
     bn = frame.bins.struct()
     if "pre" in stages:

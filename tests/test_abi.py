@@ -166,6 +166,61 @@ def test_clip_modes_agree_and_invalid_modes_are_rejected(B):
         assert st == (B.RARA_OK if ok else B.RARA_ERR_INVALID), (mode, st)
 
 
+def test_clip_regions_are_validated_on_the_host(B):
+    """rara_plane.count: a region of 2..RARA_MAX_PLANES half-spaces; a count
+    above the maximum, a zero normal among the extra planes, or a region
+    without rara_projected.ray_ext is RARA_ERR_INVALID; the backward and frame
+    graphs take one plane (RARA_ERR_UNSUPPORTED).  All checked before any
+    launch."""
+    import oracle
+    from paper_2506_20202_amd import scenes
+    hdr = open(os.path.join(ROOT, "include", "rara.h")).read()
+    assert int(re.search(r"#define RARA_MAX_PLANES (\d+)", hdr).group(1)) == B.MAX_PLANES == scenes.MAX_PLANES
+    orc = open(os.path.join(ROOT, "oracle", "rara_oracle.c")).read()
+    assert int(re.search(r"#define OR_MAX_PLANES (\d+)", orc).group(1)) == B.MAX_PLANES
+    lib = B.lib()
+    g = B.Gaussians()
+    g.n, g.sh_degree = 0, 0
+    cam = _cam(B)
+    out = B.Projected()
+    box = B.make_plane(scenes.box_region((-1, -1, -1), (1, 1, 1)))
+    assert box.count == 6
+    # n = 0 returns before launching: a valid region is accepted
+    assert lib.rara_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(box), ctypes.byref(out), None) \
+        == B.RARA_OK
+    for bad in (B.MAX_PLANES + 1, -1):
+        pl = B.make_plane(scenes.box_region((-1, -1, -1), (1, 1, 1)))
+        pl.count = bad
+        assert lib.rara_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(pl), ctypes.byref(out),
+                                   None) == B.RARA_ERR_INVALID
+    zero = B.make_plane(scenes.box_region((-1, -1, -1), (1, 1, 1)))
+    zero.extra[2] = (ctypes.c_float * 4)(0.0, 0.0, 0.0, 1.0)
+    assert lib.rara_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(zero), ctypes.byref(out), None) \
+        == B.RARA_ERR_INVALID
+    # a region needs ray_ext once there are Gaussians
+    g.n = 10
+    fake = ctypes.c_void_p(0x1000)
+    full = B.Projected()
+    full.label = full.splat = full.ray = full.depth = full.rect = full.tiles_touched = 0x1000
+    g.mean = g.scale = g.quat = g.opacity = g.sh = 0x1000
+    assert lib.rara_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(box), ctypes.byref(full), None) \
+        == B.RARA_ERR_INVALID
+    bins = B.Binned()
+    bins.keys = bins.vals = bins.ranges = bins.num_pairs = bins.overflow = bins.work = bins.pair_start = 0x1000
+    img = (ctypes.c_float * 3)()
+    assert lib.rara_render(ctypes.byref(full), 10, ctypes.byref(bins), ctypes.byref(cam), ctypes.byref(box), img,
+                           fake, fake, fake, None, None) == B.RARA_ERR_INVALID
+    grads = B.Grads()
+    grads.mean = grads.scale = grads.quat = grads.opacity = grads.sh = grads.plane = 0x1000
+    full.ray_ext = 0x1000
+    assert lib.rara_render_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(box), img, ctypes.byref(full),
+                                    ctypes.byref(bins), 100, fake, fake, fake, ctypes.byref(grads), fake, 1 << 40,
+                                    None) == B.RARA_ERR_UNSUPPORTED
+    # the oracle reads the same region
+    np.testing.assert_array_equal(oracle.planes_of(scenes.box_region((-1, -1, -1), (1, 1, 1)))[1:],
+                                  np.array([list(r) for r in box.extra[:5]], np.float32))
+
+
 def test_constants_agree_between_oracle_and_kernels():
     """The oracle and the kernels are written separately; their conventions
     (thresholds, dilation, guard band, tile size, kappa) must agree."""

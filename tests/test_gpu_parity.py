@@ -236,3 +236,48 @@ def test_bin_sort_without_pair_start_matches():
                      fr.out.n_contrib.clone(), fr.out.n_walked.clone()))
     for a, b in zip(*outs):
         assert torch.equal(a, b)
+
+
+# ---- clip regions (several half-spaces; a box is six) ----
+
+def _tiny_box(seed):
+    rng = np.random.default_rng(300 + seed)
+    lo = rng.uniform(-0.8, -0.2, 3)
+    hi = rng.uniform(0.2, 0.8, 3)
+    return scenes.box_region(lo, hi)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_box_region_parity(seed):
+    """A box of six half-spaces: labels and lists exact, images within the bar
+    (the region blend kernel against the region oracle)."""
+    box = _tiny_box(seed)
+    g, o = _full_check(scenes.tiny_scene(seed), scenes.tiny_camera(), box)
+    assert (o["label"] == 2).sum() > 20 and (o["label"] == 0).sum() > 20
+
+
+@pytest.mark.parametrize("name,mode", CLIP_MODES)
+def test_box_region_clip_modes(name, mode):
+    box = _tiny_box(7)
+    _full_check(scenes.tiny_scene(7), scenes.tiny_camera(), scenes.Plane(box.n, box.d, mode, box.extra))
+
+
+@pytest.mark.parametrize("count", [2, 3, 8])
+def test_random_region_parity(count):
+    """Regions of random planes through the scene, up to the maximum count."""
+    rng = np.random.default_rng(400 + count)
+    sc = scenes.tiny_scene(10 + count)
+    planes = []
+    for _ in range(count):
+        n = rng.standard_normal(3)
+        n /= np.linalg.norm(n)
+        planes.append((n, float(rng.uniform(0.2, 0.7))))   # the origin is inside every half-space
+    _full_check(sc, scenes.tiny_camera(), scenes.region(planes))
+
+
+def test_box_region_large_gaussians():
+    """Large Gaussians cut by box faces and edges (most of them CUTOFF)."""
+    sc = scenes.small_scene(2, n=24)
+    box = scenes.box_region((-0.15, -0.2, -0.1), (0.2, 0.1, 0.15))
+    g, o = _full_check(sc, scenes.small_camera(96), box)
+    assert (o["label"] == 2).sum() >= 8

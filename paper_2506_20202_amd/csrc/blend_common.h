@@ -281,23 +281,30 @@ __device__ inline bool unit_of_block(uint32_t b, const uint32_t* __restrict__ wo
     return true;
 }
 
-// Tile of forward workgroup b.  The tile order is the one the work list
-// encodes: the H split (long-list) tiles first, then the others, each group
-// in tile order.  Every XCD (b mod 8) takes one contiguous run of each group,
-// so the long lists start first and neighbouring tiles, which share splats,
-// stay on one L2.  tiles_grid(T) workgroups cover both groups.
+// Tile of blend workgroup b.  The work list holds the H split (long-list)
+// tiles first, then the others, each group in tile order.  Workgroups go to
+// the 8 XCDs round robin (b mod 8), each XCD with its own L2.  The long lists
+// start first, every XCD taking one contiguous run of them.  The other tiles
+// are dealt to the XCDs in chunks of kDealChunk consecutive tiles (a piece of
+// a tile row, whose tiles share splats in one L2), chunk c to XCD c mod 8, so
+// that the dense parts of the image spread over every XCD.  tiles_grid(T)
+// workgroups cover both groups.
 __device__ inline bool tile_of_block(uint32_t b, const uint32_t* __restrict__ work, int num_tiles, uint32_t& tile)
 {
     const uint32_t H = work[4 * num_tiles];
     const uint32_t hb = (H + 7u) & ~7u;
-    const bool heavy = b < hb;
-    const uint32_t bb = heavy ? b : b - hb;   // hb is a multiple of 8: bb and b share an XCD
-    const uint32_t cnt = heavy ? H : (uint32_t)num_tiles - H;
+    if (b < hb) {
+        const uint32_t x = b & 7u, k = b >> 3;
+        const uint32_t q8 = H >> 3, r8 = H & 7u;
+        if (k >= q8 + (x < r8 ? 1u : 0u)) return false;
+        tile = work[4 * (x * q8 + (x < r8 ? x : r8) + k)] >> 3;
+        return true;
+    }
+    const uint32_t bb = b - hb;   // hb is a multiple of 8: bb and b share an XCD
     const uint32_t x = bb & 7u, k = bb >> 3;
-    const uint32_t q8 = cnt >> 3, r8 = cnt & 7u;
-    if (k >= q8 + (x < r8 ? 1u : 0u)) return false;
-    const uint32_t i = x * q8 + (x < r8 ? x : r8) + k;
-    tile = (heavy ? work[4 * i] : work[4 * H + i]) >> 3;
+    const uint32_t i = (x + 8u * (k / kDealChunk)) * kDealChunk + k % kDealChunk;
+    if (i >= (uint32_t)num_tiles - H) return false;
+    tile = work[4 * H + i] >> 3;
     return true;
 }
 

@@ -110,7 +110,10 @@ constexpr uint32_t kHeavyList = 1536;
 constexpr int kMaxHeavy = 2048;
 inline int64_t work_grid(int64_t tiles) { return tiles + 3 * (tiles < kMaxHeavy ? tiles : kMaxHeavy) + 64; }
 // forward blend: one workgroup per tile, both tile groups padded to 8
-inline int64_t tiles_grid(int64_t tiles) { return tiles + 16; }
+// (the non-split tiles are dealt to the XCDs in chunks of kDealChunk: the
+// fullest XCD holds up to 2 kDealChunk more than an even share)
+constexpr uint32_t kDealChunk = 16;
+inline int64_t tiles_grid(int64_t tiles) { return tiles + 16 + 16 * (int64_t)kDealChunk; }
 
 // ---- bin/sort workspace carve-up -------------------------------------------
 constexpr int kScanBlock = 256;      // Gaussians per scan chunk

@@ -162,9 +162,9 @@ typedef struct {
  *   ranges [tiles][2] uint32     [start, end) of each tile's pairs.
  *   num_pairs [1] int64          total pairs P of the frame (written even on overflow).
  *   overflow  [1] int32          set to 1 when P > pair_capacity, else 0.
- *   work [4 tiles + 1] uint32    blend schedule written by rara_bin_sort: quadrant
- *                                units of tiles with long lists, then whole tiles;
- *                                the last entry is the number of split tiles.
+ *   work [tiles + 1] uint32      blend schedule written by rara_bin_sort: the
+ *                                tiles with long lists, then the others; the last
+ *                                entry is the number of long-list tiles.
  *   pair_start [n] uint32        optional (NULL: not written): for each drawn
  *                                Gaussian, the position of its first pair in emission
  *                                order (drawn Gaussians by depth, each one's tiles

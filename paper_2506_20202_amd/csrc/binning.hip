@@ -199,13 +199,11 @@ __device__ inline uint32_t block_sum_scan(uint32_t v, uint32_t& total, uint32_t*
     return before + incl - v;
 }
 
-// Blend schedule: tiles whose list has at least kHeavyList entries (the first
-// kMaxHeavy of them in tile order) become four quadrant units, dispatched
-// first so the longest walks start earliest and run on four waves; every
-// other tile is one unit.  work[4h + q] = quadrant q of split tile h,
-// work[4H + l] = l-th whole tile (tile order), work[4T] = H.  One workgroup;
-// thread t owns a contiguous run of tiles, so two block scans place every
-// unit (deterministic, tile order).
+// Blend schedule: the tiles whose list has at least kHeavyList entries come
+// first, so that the longest walks start earliest, then the others, each
+// group in tile order: work[h] = h-th long-list tile, work[H + l] = l-th other
+// tile, work[T] = H.  One workgroup; thread t owns a contiguous run of tiles,
+// so one block scan places every tile (deterministic).
 __global__ __launch_bounds__(1024) void plan_kernel(const uint2* __restrict__ ranges, int num_tiles,
                                                     uint32_t* __restrict__ work)
 {
@@ -215,7 +213,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(const uint2* __restrict__ ra
     const int per = (num_tiles + 1023) / 1024;
     const int t0 = tid * per < num_tiles ? tid * per : num_tiles;
     const int t1 = t0 + per < num_tiles ? t0 + per : num_tiles;
-    // heavy flags of this thread's run: all loads issued at once when they fit
+    // long-list flags of this thread's run: all loads issued at once when they fit
     uint32_t hbits = 0u;
     if (per <= kRegTiles) {
         uint32_t len[kRegTiles];
@@ -235,24 +233,16 @@ __global__ __launch_bounds__(1024) void plan_kernel(const uint2* __restrict__ ra
     };
     uint32_t hc = 0;
     for (int t = t0; t < t1; ++t) hc += heavy(t) ? 1u : 0u;
-    uint32_t htot;
-    const uint32_t hx = block_sum_scan(hc, htot, wave_tot);
-    const uint32_t H = htot < (uint32_t)kMaxHeavy ? htot : (uint32_t)kMaxHeavy;
-    // heavy tiles of rank >= H stay whole
-    const uint32_t nsplit = hx >= H ? 0u : (hx + hc <= H ? hc : H - hx);
-    uint32_t ltot;
-    const uint32_t lx = block_sum_scan((uint32_t)(t1 - t0) - nsplit, ltot, wave_tot);
-    uint32_t h = hx, l = lx;
+    uint32_t H;
+    const uint32_t hx = block_sum_scan(hc, H, wave_tot);
+    uint32_t h = hx, l = (uint32_t)t0 - hx;   // other tiles before t0
     for (int t = t0; t < t1; ++t) {
-        if (heavy(t) && h < H) {
-            for (uint32_t q = 0; q < 4; ++q) work[4 * h + q] = ((uint32_t)t << 3) | q;
-            ++h;
-        } else {
-            work[4 * H + l] = ((uint32_t)t << 3) | 4u;
-            ++l;
-        }
+        if (heavy(t))
+            work[h++] = (uint32_t)t;
+        else
+            work[H + l++] = (uint32_t)t;
     }
-    if (tid == 0) work[4 * num_tiles] = H;
+    if (tid == 0) work[num_tiles] = H;
 }
 
 }  // namespace

@@ -253,36 +253,9 @@ __device__ inline void stage_entry(const Splat& nx, double ox, double oy, uint32
     sc = make_float4(nx.b, __uint_as_float(nx.label | (qmask << 8)), __uint_as_float(id), 0.0f);
 }
 
-// Work unit of workgroup b.  Workgroups are dispatched round-robin to the 8
-// XCDs (b mod 8), each with its own L2: the four quadrant units of a split
-// tile are given to one XCD (blocks b, b+8, b+16, b+24), and the whole-tile
-// units are dealt out so that every XCD takes one contiguous run of tiles (a
-// band of the image), keeping the tiles that share splats on one L2.
-// work[4T] holds the number H of split tiles; split tile h has its quadrant
-// units at work[4h..4h+3], whole tiles follow from work[4H] in tile order.
-__device__ inline bool unit_of_block(uint32_t b, const uint32_t* __restrict__ work, int num_tiles, uint32_t& unit)
-{
-    const uint32_t H = work[4 * num_tiles];
-    const uint32_t hb = 4u * ((H + 7u) & ~7u);
-    if (b < hb) {
-        const uint32_t x = b & 7u, r = b >> 3, h = (r >> 2) * 8u + x, q = r & 3u;
-        if (h >= H) return false;
-        unit = work[4 * h + q];
-        return true;
-    }
-    const uint32_t bb = b - hb;   // hb is a multiple of 32: bb and b share an XCD
-    const uint32_t nl = (uint32_t)num_tiles - H;
-    const uint32_t x = bb & 7u, k = bb >> 3;
-    const uint32_t q8 = nl >> 3, r8 = nl & 7u;
-    const uint32_t cnt = q8 + (x < r8 ? 1u : 0u);
-    if (k >= cnt) return false;
-    const uint32_t start = x * q8 + (x < r8 ? x : r8);
-    unit = work[4 * H + start + k];
-    return true;
-}
-
-// Tile of blend workgroup b.  The work list holds the H split (long-list)
-// tiles first, then the others, each group in tile order.  Workgroups go to
+// Tile of blend workgroup b.  The work list holds the H long-list tiles
+// (kHeavyList entries or more) first, then the others, each group in tile
+// order, and H in its last entry.  Workgroups go to
 // the 8 XCDs round robin (b mod 8), each XCD with its own L2.  The long lists
 // start first, every XCD taking one contiguous run of them.  The other tiles
 // are dealt to the XCDs in chunks of kDealChunk consecutive tiles (a piece of
@@ -291,20 +264,20 @@ __device__ inline bool unit_of_block(uint32_t b, const uint32_t* __restrict__ wo
 // workgroups cover both groups.
 __device__ inline bool tile_of_block(uint32_t b, const uint32_t* __restrict__ work, int num_tiles, uint32_t& tile)
 {
-    const uint32_t H = work[4 * num_tiles];
+    const uint32_t H = work[num_tiles];
     const uint32_t hb = (H + 7u) & ~7u;
     if (b < hb) {
         const uint32_t x = b & 7u, k = b >> 3;
         const uint32_t q8 = H >> 3, r8 = H & 7u;
         if (k >= q8 + (x < r8 ? 1u : 0u)) return false;
-        tile = work[4 * (x * q8 + (x < r8 ? x : r8) + k)] >> 3;
+        tile = work[x * q8 + (x < r8 ? x : r8) + k];
         return true;
     }
     const uint32_t bb = b - hb;   // hb is a multiple of 8: bb and b share an XCD
     const uint32_t x = bb & 7u, k = bb >> 3;
     const uint32_t i = (x + 8u * (k / kDealChunk)) * kDealChunk + k % kDealChunk;
     if (i >= (uint32_t)num_tiles - H) return false;
-    tile = work[4 * H + i] >> 3;
+    tile = work[H + i];
     return true;
 }
 

@@ -102,13 +102,9 @@ struct FrameParams {
 };
 
 // ---- blend work list --------------------------------------------------------
-// Tiles whose list holds at least kHeavyList entries are blended as four
-// quadrant units (one wave each) and scheduled first; at most kMaxHeavy tiles
-// per frame are split.  work[] has 4 * tiles + 1 entries; the blend grid adds
-// room for the XCD-aligned padding of the schedule.
+// Tiles whose list holds at least kHeavyList entries are blended first
+// (work[] has tiles + 1 entries, see plan_kernel).
 constexpr uint32_t kHeavyList = 1536;
-constexpr int kMaxHeavy = 2048;
-inline int64_t work_grid(int64_t tiles) { return tiles + 3 * (tiles < kMaxHeavy ? tiles : kMaxHeavy) + 64; }
 // forward blend: one workgroup per tile, both tile groups padded to 8
 // (the non-split tiles are dealt to the XCDs in chunks of kDealChunk: the
 // fullest XCD holds up to 2 kDealChunk more than an even share)

@@ -98,7 +98,7 @@ class BinBuffers:
         self.ranges = torch.empty(tiles * 2, dtype=torch.int32, device=device)
         self.num_pairs = torch.zeros(1, dtype=torch.int64, device=device)
         self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
-        self.work = torch.empty(4 * tiles + 1, dtype=torch.int32, device=device)
+        self.work = torch.empty(tiles + 1, dtype=torch.int32, device=device)
         self.pair_start = torch.empty(max(int(n), 1), dtype=torch.int32, device=device) if pair_start else None
         self.ws_bytes = B.workspace_bytes(B.RARA_WS_BIN_SORT, n, self.capacity, width, height)
         if self.ws_bytes == 0:

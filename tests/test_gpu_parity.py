@@ -7,6 +7,8 @@ discontinuity event (alpha at the 1/255 skip, transmittance at the 1e-4 stop,
 a ray grazing the traced ellipsoid, a Gaussian within 1e-6 of a label or
 footprint boundary).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -281,3 +283,76 @@ def test_box_region_large_gaussians():
     box = scenes.box_region((-0.15, -0.2, -0.1), (0.2, 0.1, 0.15))
     g, o = _full_check(sc, scenes.small_camera(96), box)
     assert (o["label"] == 2).sum() >= 8
+
+
+# Long lists: thousands of overlapping Gaussians over a few tiles, most of them
+# CUTOFF, so tiles hold 2000-7600 entries (the blend dispatches tiles of 1536
+# entries or more first, each XCD taking a run of them).  With that many
+# entries per pixel, many pixels carry an oracle event (an alpha
+# within 0.1 % of 1/255 or a grazing ray); the rest are checked to the usual bar.
+DENSE_NORMAL = (np.array([0.3, 0.2, -0.93]) / np.linalg.norm([0.3, 0.2, -0.93])).astype(np.float32)
+
+
+def _dense_scene(seed, n, opacity_scale, logscale_mean):
+    sc = scenes.small_scene(seed, n=n, spread=0.35, logscale_mean=logscale_mean)
+    return dataclasses.replace(sc, opacity=(sc.opacity * opacity_scale).astype(np.float32))
+
+
+def _dense_check(sc, cam, pl, tiles=None, min_long=1):
+    g = H.gpu_frame(sc, cam, pl, capacity=max(1 << 20, 400 * sc.n))
+    o = oracle.render(sc, cam, pl, tiles=tiles)
+    bad, rects = H.check_projection(g, o)
+    skip = H.tiles_of(rects, cam.tiles[0])
+    t0, t1 = tiles if tiles is not None else (0, cam.tiles[0] * cam.tiles[1])
+    H.check_lists(g, o, tiles=range(t0, t1), skip=skip)
+    lens = g["ranges"][:, 1] - g["ranges"][:, 0]
+    region = _tile_pixel_mask(cam, t0, t1)
+    excl = oracle.tile_mask(cam, rects)
+    err, flagged, _ = H.image_error(g["image"], o, exclude=excl, region=region)
+    ok = (o["flags"] == 0) & ~excl & region
+    print(f"n={sc.n} {cam.width}x{cam.height} P={g['P']} long={(lens >= 1536).sum()} max_len={lens.max()} "
+          f"max_err={err:.2e} flagged={flagged:.4f} checked={ok.sum()} mismatched={len(bad)}", flush=True)
+    assert (lens >= 1536).sum() >= min_long
+    assert ok.sum() >= 0.25 * region.sum()
+    assert err <= TOL
+    np.testing.assert_array_equal(g["n_contrib"][ok], o["n_contrib"][ok])
+    np.testing.assert_array_equal(g["n_walked"][ok], o["n_walked"][ok])
+    np.testing.assert_allclose(g["final_T"][ok], o["final_T"][ok], rtol=1e-3, atol=1e-6)
+    return g, o
+
+
+@pytest.mark.parametrize("seed,opacity_scale,size", [(0, 1.0, 72), (1, 0.03, 72), (2, 0.05, 100)])
+def test_long_list_parity(seed, opacity_scale, size):
+    """Opaque (pixels terminate early) and faint (every list walked to its
+    end); at 72 px the right quadrants of the last tile column lie outside
+    the image."""
+    n, ls = (4000, -2.3) if size < 100 else (6000, -2.5)
+    _dense_check(_dense_scene(seed, n, opacity_scale, ls), scenes.small_camera(size),
+                 scenes.Plane(DENSE_NORMAL, 0.02), min_long=8)
+
+
+@pytest.mark.parametrize("name,mode", CLIP_MODES)
+def test_long_list_clip_modes(name, mode):
+    _dense_check(_dense_scene(1, 4000, 0.03, -2.3), scenes.small_camera(72),
+                 scenes.Plane(DENSE_NORMAL, 0.02, enabled=mode), min_long=4)
+
+
+def test_many_long_list_tiles():
+    """576 tiles of 2500-7600 entries each, every tile in the long-list group;
+    a band near the top and the bottom row are checked."""
+    sc = _dense_scene(3, 12000, 0.04, -2.6)
+    cam = scenes.pinhole((0.3, -0.4, -3.0), (0.0, 0.0, 0.0), 384, 384, 12.0)
+    pl = scenes.Plane(DENSE_NORMAL, 0.05)
+    tx = cam.tiles[0]
+    for band in [(5 * tx, 6 * tx), (23 * tx, 24 * tx)]:
+        g, _ = _dense_check(sc, cam, pl, tiles=band, min_long=576)
+
+
+def test_long_list_forward_is_deterministic():
+    sc = _dense_scene(2, 6000, 0.05, -2.5)
+    cam = scenes.small_camera(100)
+    pl = scenes.Plane(DENSE_NORMAL, 0.02)
+    a = H.gpu_frame(sc, cam, pl, capacity=1 << 22)
+    b = H.gpu_frame(sc, cam, pl, capacity=1 << 22)
+    for k in ("image", "final_T", "n_contrib", "n_walked"):
+        np.testing.assert_array_equal(a[k], b[k])

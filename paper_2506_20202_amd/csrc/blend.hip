@@ -32,34 +32,35 @@ namespace rara {
 
 namespace {
 
-// One pixel's front-to-back update with one list entry, straight-line and
-// without lane masks.  alpha = min(0.99, a0 w), a0 = delta 2^pw (0 for
-// pw > 0); entries with alpha below the pixel's threshold `thr` are skipped
-// (thr = 1/255 while the pixel is live; a finished pixel has thr = 2, above
-// any alpha, so it is left unchanged).  An entry that would take T below 1e-4 finishes the
-// pixel without being composited: T keeps its value, the final transmittance.
-// A live pixel always has T >= 1e-4, so a skipped entry (alpha = 0, new
-// T = T) can never finish it.
+// One pixel's front-to-back update with one list entry of opacity
+// alpha = min(0.99, a0 w), a0 = delta 2^pw (0 for pw > 0), straight-line and
+// without lane masks.  The entry is taken when alpha reaches the pixel's
+// threshold `thr` (1/255 while the pixel is live; a finished pixel has thr = 2,
+// above any alpha, so it is left unchanged).  A taken entry that would bring T
+// below 1e-4 finishes the pixel without being composited: T keeps its value,
+// the final transmittance.  Otherwise a taken entry is composited (its weight
+// alpha T > 0, so it is the pixel's last contributor so far); an entry not
+// taken changes nothing.
 __device__ inline float entry_a0(float pw, float op)
 {
     return op * __builtin_amdgcn_exp2f(pw > 0.0f ? -INFINITY : pw);
 }
 
-__device__ inline void composite(float a0, float w, float cr, float cg, float cb, uint32_t k1, float& T, float& thr,
+__device__ inline void composite(float alpha, float cr, float cg, float cb, uint32_t k1, float& T, float& thr,
                                  float& C0, float& C1, float& C2, uint32_t& last, uint32_t& walked)
 {
-    float alpha = fminf(kAlphaMax, a0 * w);
-    alpha = alpha >= thr ? alpha : 0.0f;
-    const float tT = fmaf(-alpha, T, T);
-    const bool term = tT < kTMin;
-    const float wt = term ? 0.0f : alpha * T;
+    const float tT = fmaf(-alpha, T, T);   // finite: alpha in [0, 0.99], T in [1e-4, 1]
+    const bool take = alpha >= thr;
+    const bool ok = take && tT >= kTMin;
+    const bool fin = take && !ok;
+    const float wt = ok ? alpha * T : 0.0f;
     C0 = fmaf(wt, cr, C0);
     C1 = fmaf(wt, cg, C1);
     C2 = fmaf(wt, cb, C2);
-    T = term ? T : tT;
-    thr = term ? 2.0f : thr;
-    last = wt > 0.0f ? k1 : last;
-    walked = term ? k1 : walked;
+    T = ok ? tT : T;
+    thr = fin ? 2.0f : thr;
+    last = ok ? k1 : last;
+    walked = fin ? k1 : walked;
 }
 
 constexpr int kBlendThreads = 256;   // one workgroup per tile: four waves, one per 8x8 quadrant
@@ -146,24 +147,40 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
             const uint64_t cutb = __ballot(plane_on && (lm & 0xffu) == RARA_LABEL_CUTOFF);
             for (int chunk = 0; chunk < 64; chunk += 16) {
                 uint64_t todo = qb & (0xffffull << chunk);
-                while (todo) {
-                    const int j = (int)__builtin_ctzll(todo);
-                    todo &= todo - 1ull;
-                    const uint32_t e = sub + (uint32_t)j;
-                    const float4 a = s_a[e], b = s_b[e];
-                    const float cb_ = s_c[e].x;
-                    const float dx = lpx - a.x, dy = lpy - a.y;
-                    const float a0 = entry_a0(entry_power(a, b, dx, dy), b.y);
-                    float w = 1.0f;
-                    if ((cutb >> j) & 1ull) {
-                        // alpha <= a0 (w <= 1): when no pixel can reach its threshold the
-                        // entry changes nothing and its weight is not needed
-                        if (__ballot(a0 >= thr) == 0ull) continue;
-                        w = kRegion ? chord_weight_region(s_cut[e], s_ext + e * (kMaxPlanes - 1), p.plane_count,
-                                                          dx, dy, p.ax, p.ay, s_rate, strict)
-                                    : chord_weight_flat(s_cut[e], dx, dy, p.ax, p.ay, strict);
+                if ((todo & cutb) == 0ull) {
+                    // no CUTOFF entry in this chunk: w = 1 throughout
+                    while (todo) {
+                        const int j = (int)__builtin_ctzll(todo);
+                        todo &= todo - 1ull;
+                        const uint32_t e = sub + (uint32_t)j;
+                        const float4 a = s_a[e], b = s_b[e];
+                        const float cb_ = s_c[e].x;
+                        const float dx = lpx - a.x, dy = lpy - a.y;
+                        const float a0 = entry_a0(entry_power(a, b, dx, dy), b.y);
+                        composite(fminf(kAlphaMax, a0), b.z, b.w, cb_, kofs + e, T, thr, C0, C1, C2, last, walked);
                     }
-                    composite(a0, w, b.z, b.w, cb_, kofs + e, T, thr, C0, C1, C2, last, walked);
+                } else {
+                    while (todo) {
+                        const int j = (int)__builtin_ctzll(todo);
+                        todo &= todo - 1ull;
+                        const uint32_t e = sub + (uint32_t)j;
+                        const float4 a = s_a[e], b = s_b[e];
+                        const float cb_ = s_c[e].x;
+                        const float dx = lpx - a.x, dy = lpy - a.y;
+                        const float a0 = entry_a0(entry_power(a, b, dx, dy), b.y);
+                        float alpha = fminf(kAlphaMax, a0);   // w = 1
+                        if ((cutb >> j) & 1ull) {
+                            // alpha <= a0 (w <= 1): when no pixel can reach its threshold the
+                            // entry changes nothing and its weight is not needed
+                            if (__ballot(a0 >= thr) == 0ull) continue;
+                            const float w = kRegion ? chord_weight_region(s_cut[e], s_ext + e * (kMaxPlanes - 1),
+                                                                          p.plane_count, dx, dy, p.ax, p.ay, s_rate,
+                                                                          strict)
+                                                    : chord_weight_flat(s_cut[e], dx, dy, p.ax, p.ay, strict);
+                            alpha = fminf(kAlphaMax, a0 * w);
+                        }
+                        composite(alpha, b.z, b.w, cb_, kofs + e, T, thr, C0, C1, C2, last, walked);
+                    }
                 }
                 live = __ballot(thr < 1.0f) != 0ull;
                 if (!live) break;

@@ -218,7 +218,7 @@ rara_status rara_bin_sort(const rara_projected* proj, int64_t n, const rara_came
     if (tile_passes < 1) tile_passes = 1;   // the last pass also writes the 64-bit keys
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = launch_bin(proj_ptrs(proj), n, cp, pair_capacity, ws, *out, tile_passes, s);
-    if (e == hipSuccess) e = launch_ranges(*out, pair_capacity, num_tiles, n == 0, s);
+    if (e == hipSuccess && n == 0) e = launch_ranges_clear(*out, num_tiles, s);   // else set by launch_bin
     if (e == hipSuccess) e = launch_plan(*out, num_tiles, s);
     return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
 }

@@ -15,11 +15,14 @@
 // This is the same permutation as sorting the expanded pairs by all their key
 // bits, with the four depth passes over ~P / 5 items instead of P.
 //
-// The pair-offset scan is reduce-then-scan over 256-Gaussian chunks.  Inside a chunk the
-// prefix is a wavefront-ballot scan: bit b of every lane's count is gathered
-// with one 64-lane ballot, and mbcnt (popcount of the ballot below the lane)
-// times 2^b is added to the lane's prefix; the loop stops at the highest bit
-// any lane still holds.  Four wave totals are combined through LDS.
+// The pair offsets are a reduce-then-scan over 256-Gaussian chunks of the
+// depth order: a sum of the tile counts per chunk, and each emit workgroup
+// adds the sums before its chunk to get its first pair (a few KB of reads
+// that stay in L2, instead of a kernel that scans the sums).  Inside a chunk the prefix is a wavefront-ballot scan: bit b
+// of every lane's count is gathered with one 64-lane ballot, and mbcnt
+// (popcount of the ballot below the lane) times 2^b is added to the lane's
+// prefix; the loop stops at the highest bit any lane still holds.  Four wave
+// totals are combined through LDS.
 #include "rara_internal.h"
 
 namespace rara {
@@ -62,79 +65,71 @@ __device__ inline uint32_t block_ballot_scan(uint32_t v, uint32_t& total)
     return before + p;
 }
 
-// Per-256-chunk sums of tiles_touched[order[k]] over the depth order, k < *count.
+// Per-chunk sums of tiles_touched[order[k]] over the depth order (k < *count),
+// chunk b = the 256 Gaussians from b * 256.
 __global__ __launch_bounds__(256) void chunk_sum_kernel(const uint32_t* __restrict__ tt,
                                                         const uint32_t* __restrict__ order,
                                                         const int64_t* __restrict__ count,
-                                                        uint32_t* __restrict__ block_sums)
+                                                        uint32_t* __restrict__ chunk_sums)
 {
     const int64_t k = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
     const uint32_t v = k < *count ? tt[order[k]] : 0u;
     uint32_t total;
     block_ballot_scan(v, total);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+    if (threadIdx.x == 0) chunk_sums[blockIdx.x] = total;
 }
 
-// Single-workgroup exclusive scan of the chunk sums; writes the pair count and
-// the overflow flag.
-__global__ __launch_bounds__(1024) void scan_blocks_kernel(uint32_t* __restrict__ sums, int64_t nb, int64_t cap,
-                                                           int64_t* __restrict__ num_pairs,
-                                                           int32_t* __restrict__ overflow)
+// A frame without Gaussians: no pairs, no overflow.
+__global__ void no_pairs_kernel(int64_t* __restrict__ num_pairs, int32_t* __restrict__ overflow)
 {
-    __shared__ uint64_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t per = (nb + 1023) / 1024;
-    const int64_t lo = t * per, hi = lo + per < nb ? lo + per : nb;
-    uint64_t acc = 0;
-    for (int64_t k = lo; k < hi; ++k) acc += sums[k];
-    part[t] = acc;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over the 1024 partial sums
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint64_t add = t >= off ? part[t - off] : 0ull;
-        __syncthreads();
-        part[t] += add;
-        __syncthreads();
-    }
-    uint64_t run = t > 0 ? part[t - 1] : 0ull;
-    for (int64_t k = lo; k < hi; ++k) {
-        const uint32_t v = sums[k];
-        sums[k] = (uint32_t)run;
-        run += v;
-    }
-    if (t == 1023) {
-        const uint64_t P = part[1023];
-        *num_pairs = (int64_t)P;
-        *overflow = P > (uint64_t)cap ? 1 : 0;
-    }
+    *num_pairs = 0;
+    *overflow = 0;
 }
 
 // One (tile, index) pair per covered tile, Gaussians taken in depth order.
-// A workgroup owns 256 consecutive Gaussians of the depth order and the
-// contiguous run of pairs they emit.  The pairs are expanded cooperatively:
-// thread e of each 256-pair step finds the Gaussian that owns pair e by a
-// binary search over the workgroup's inclusive pair offsets in LDS, so the
-// work per thread does not depend on footprint sizes and the stores of a
-// step are consecutive.
+// A workgroup owns 256 consecutive Gaussians of the depth order (chunk b) and
+// the contiguous run of pairs they emit, from the sum of the chunk sums before
+// it; the last workgroup also writes the pair count and the overflow flag.  A
+// workgroup whose pairs do not all fit the capacity writes none (the frame
+// then overflows).  The pairs are expanded cooperatively: thread e of each
+// 256-pair step finds the Gaussian that owns pair e by a binary search over
+// the workgroup's inclusive pair offsets in LDS, so the work per thread does
+// not depend on footprint sizes and the stores of a step are consecutive.
 __global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ tt, const uint16_t* __restrict__ rect,
                                                    const uint32_t* __restrict__ order,
                                                    const int64_t* __restrict__ count,
-                                                   const uint32_t* __restrict__ block_off, int tiles_x,
-                                                   const int32_t* __restrict__ overflow, uint32_t* __restrict__ tkeys,
+                                                   const uint32_t* __restrict__ chunk_sums, int64_t cap, int tiles_x, int64_t* __restrict__ num_pairs,
+                                                   int32_t* __restrict__ overflow, uint32_t* __restrict__ tkeys,
                                                    uint32_t* __restrict__ tvals, uint32_t* __restrict__ pair_start)
 {
     __shared__ uint32_t s_end[kScanBlock];   // inclusive end of each Gaussian's pairs inside the workgroup
     __shared__ uint32_t s_id[kScanBlock];
     __shared__ ushort4 s_rc[kScanBlock];
-    const int tid = threadIdx.x;
-    const int64_t k = (int64_t)blockIdx.x * kScanBlock + tid;
+    __shared__ uint64_t s_part[kScanBlock / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t b = blockIdx.x;
+    // pairs before this chunk
+    uint64_t before = 0;
+    {
+        for (int64_t c = tid; c < b; c += kScanBlock) before += chunk_sums[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) before += __shfl_xor(before, off, 64);
+    }
+    const int64_t k = b * kScanBlock + tid;
     const bool valid = k < *count;
     const uint32_t id = valid ? order[k] : 0u;
     const uint32_t v = valid ? tt[id] : 0u;
+    if (lane == 0) s_part[wave] = before;
     uint32_t total;
-    const uint32_t pre = block_ballot_scan(v, total);
-    if (*overflow || total == 0u) return;   // uniform over the workgroup
-    const uint32_t base = block_off[blockIdx.x];
+    const uint32_t pre = block_ballot_scan(v, total);   // its barrier orders s_part
+    const uint64_t base64 = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+    if (b == (int64_t)gridDim.x - 1 && tid == 0) {
+        const uint64_t P = base64 + total;
+        *num_pairs = (int64_t)P;
+        *overflow = P > (uint64_t)cap ? 1 : 0;
+    }
+    if (total == 0u || base64 + total > (uint64_t)cap) return;   // uniform over the workgroup
+    const uint32_t base = (uint32_t)base64;
     if (pair_start && v) pair_start[id] = base + pre;   // first pair of this Gaussian, emission order
     s_end[tid] = pre + v;
     s_id[tid] = id;
@@ -159,21 +154,6 @@ __global__ __launch_bounds__(256) void ranges_clear_kernel(uint32_t* __restrict_
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < num_tiles) reinterpret_cast<uint2*>(ranges)[t] = make_uint2(0u, 0u);
-}
-
-__global__ __launch_bounds__(256) void ranges_mark_kernel(const uint64_t* __restrict__ keys,
-                                                          const int64_t* __restrict__ num_pairs,
-                                                          const int32_t* __restrict__ overflow,
-                                                          uint32_t* __restrict__ ranges, uint32_t num_tiles)
-{
-    if (*overflow) return;
-    const int64_t P = *num_pairs;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t tile = (uint32_t)(keys[i] >> 32);
-        if (tile >= num_tiles) continue;
-        if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != tile) ranges[2 * tile] = (uint32_t)i;
-        if (i == P - 1 || (uint32_t)(keys[i + 1] >> 32) != tile) ranges[2 * tile + 1] = (uint32_t)(i + 1);
-    }
 }
 
 // Exclusive sum of v over a 1024-thread block (16 waves) and the block total.
@@ -203,8 +183,19 @@ __device__ inline uint32_t block_sum_scan(uint32_t v, uint32_t& total, uint32_t*
 // first, so that the longest walks start earliest, then the others, each
 // group in tile order: work[h] = h-th long-list tile, work[H + l] = l-th other
 // tile, work[T] = H.  One workgroup; thread t owns a contiguous run of tiles,
-// so one block scan places every tile (deterministic).
-__global__ __launch_bounds__(1024) void plan_kernel(const uint2* __restrict__ ranges, int num_tiles,
+// so one block scan places every tile (deterministic).  Tiles without pairs
+// (end 0) get the empty range (0, 0).
+__device__ inline uint2 final_range(uint2* ranges, int t)
+{
+    uint2 r = ranges[t];
+    if (r.y == 0u && r.x != 0u) {
+        r = make_uint2(0u, 0u);
+        ranges[t] = r;
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(1024) void plan_kernel(uint2* __restrict__ ranges, int num_tiles,
                                                     uint32_t* __restrict__ work)
 {
     constexpr int kRegTiles = 8;   // tiles per thread kept in registers (T <= 8192)
@@ -216,21 +207,26 @@ __global__ __launch_bounds__(1024) void plan_kernel(const uint2* __restrict__ ra
     // long-list flags of this thread's run: all loads issued at once when they fit
     uint32_t hbits = 0u;
     if (per <= kRegTiles) {
-        uint32_t len[kRegTiles];
+        uint2 r[kRegTiles];
+#pragma unroll
+        for (int k = 0; k < kRegTiles; ++k) r[k] = t0 + k < t1 ? ranges[t0 + k] : make_uint2(0u, 0u);
 #pragma unroll
         for (int k = 0; k < kRegTiles; ++k) {
-            const int t = t0 + k;
-            const uint2 r = t < t1 ? ranges[t] : make_uint2(0u, 0u);
-            len[k] = r.y - r.x;
+            if (r[k].y == 0u && r[k].x != 0u) {   // no pair: the empty range (0, 0)
+                r[k] = make_uint2(0u, 0u);
+                ranges[t0 + k] = r[k];
+            }
+            hbits |= (r[k].y - r[k].x >= kHeavyList ? 1u : 0u) << k;
         }
-#pragma unroll
-        for (int k = 0; k < kRegTiles; ++k) hbits |= (len[k] >= kHeavyList ? 1u : 0u) << k;
     }
     auto heavy = [&](int t) {
         if (per <= kRegTiles) return ((hbits >> (t - t0)) & 1u) != 0u;
         const uint2 r = ranges[t];
         return r.y - r.x >= kHeavyList;
     };
+    if (per > kRegTiles) {
+        for (int t = t0; t < t1; ++t) final_range(ranges, t);
+    }
     uint32_t hc = 0;
     for (int t = t0; t < t1; ++t) hc += heavy(t) ? 1u : 0u;
     uint32_t H;
@@ -249,7 +245,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(const uint2* __restrict__ ra
 
 hipError_t launch_plan(const rara_binned& out, int num_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, reinterpret_cast<const uint2*>(out.ranges), num_tiles,
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, reinterpret_cast<uint2*>(out.ranges), num_tiles,
                        out.work);
     return hipGetLastError();
 }
@@ -257,23 +253,23 @@ hipError_t launch_plan(const rara_binned& out, int num_tiles, hipStream_t s)
 hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int64_t cap, const BinWorkspace& ws,
                       const rara_binned& out, int tile_passes, hipStream_t s)
 {
-    const int64_t nb = n > 0 ? ws.scan_blocks : 0;   // no chunks: every count is 0
+    const int64_t nb = ws.scan_blocks;
+    const uint32_t num_tiles = (uint32_t)(cam.tiles_x * cam.tiles_y);
     // 1-2. depth order of the drawn Gaussians: the first of the four passes
     // takes them straight from the preprocess output (and counts them); the
     // result is back in buffer 0
     if (n > 0) {
         const SortFirstPass first{proj.depth, proj.tiles_touched, n, ws.dcount, out.ranges,
-                                  (int64_t)cam.tiles_x * cam.tiles_y * 2};
+                                  (int64_t)num_tiles * 2};
         hipError_t e = sort_passes(ws.dkeys[0], ws.dvals[0], ws.dkeys[1], ws.dvals[1], 4, ws.dcount, nullptr,
-                                   ws.depth_blocks, ws.hist, ws.digit_totals, nullptr, nullptr, nullptr, &first, s);
+                                   ws.depth_blocks, ws.hist, ws.digit_totals, nullptr, nullptr, nullptr, &first,
+                                   nullptr, s);
         if (e != hipSuccess) return e;
-    }
-    // 3. pair offsets in depth order, pair count, overflow flag, emission
-    if (n > 0)
         hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, ws.dvals[0],
                            ws.dcount, ws.block_sums);
-    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, ws.block_sums, nb, cap, out.num_pairs,
-                       out.overflow);
+    } else {
+        hipLaunchKernelGGL(no_pairs_kernel, dim3(1), dim3(1), 0, s, out.num_pairs, out.overflow);
+    }
     // the last tile pass must read the workspace buffer, never out.keys, which
     // it writes; the other buffer lives in out.keys (cap x (u32, u32) fits)
     uint32_t* alias_k = reinterpret_cast<uint32_t*>(out.keys);
@@ -283,25 +279,21 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
     uint32_t* va = last_reads_a ? ws.tvals : alias_v;
     uint32_t* kb = last_reads_a ? alias_k : ws.tkeys;
     uint32_t* vb = last_reads_a ? alias_v : ws.tvals;
+    // 3. pair offsets in depth order, pair count, overflow flag, emission
     if (n > 0)
         hipLaunchKernelGGL(emit_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, proj.rect, ws.dvals[0],
-                           ws.dcount, ws.block_sums, cam.tiles_x, out.overflow, ka, va, out.pair_start);
-    // 4. tile digits; the last pass writes the 64-bit keys and the values
+                           ws.dcount, ws.block_sums, cap, cam.tiles_x, out.num_pairs, out.overflow, ka, va,
+                           out.pair_start);
+    // 4. tile digits; the last pass writes the 64-bit keys and the values, and
+    // the tile ranges (tiles without pairs keep (0xffffffff, 0) for plan_kernel)
+    const SortLastPass last{n > 0 ? out.ranges : nullptr, num_tiles};
     return sort_passes(ka, va, kb, vb, tile_passes, out.num_pairs, out.overflow, ws.tile_blocks, ws.hist,
-                       ws.digit_totals, out.keys, out.vals, proj.depth, nullptr, s);
+                       ws.digit_totals, out.keys, out.vals, proj.depth, nullptr, &last, s);
 }
 
-hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, bool clear, hipStream_t s)
+hipError_t launch_ranges_clear(const rara_binned& out, int num_tiles, hipStream_t s)
 {
-    // with Gaussians the first binning kernel has cleared the ranges already
-    if (clear)
-        hipLaunchKernelGGL(ranges_clear_kernel, dim3((num_tiles + 255) / 256), dim3(256), 0, s, out.ranges,
-                           num_tiles);
-    int64_t blocks = (cap + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(ranges_mark_kernel, dim3((unsigned)blocks), dim3(256), 0, s, out.keys, out.num_pairs,
-                       out.overflow, out.ranges, (uint32_t)num_tiles);
+    hipLaunchKernelGGL(ranges_clear_kernel, dim3((num_tiles + 255) / 256), dim3(256), 0, s, out.ranges, num_tiles);
     return hipGetLastError();
 }
 

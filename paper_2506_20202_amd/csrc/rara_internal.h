@@ -120,7 +120,7 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
 struct BinWorkspace {
-    uint32_t* block_sums;    // [scan_blocks]
+    uint32_t* block_sums;    // [scan_blocks]: tile counts per kScanBlock Gaussians of the depth order
     int64_t* dcount;         // drawn-Gaussian count
     uint32_t* dkeys[2];      // depth keys, ping-pong [n]
     uint32_t* dvals[2];      // Gaussian indices, ping-pong [n]
@@ -141,8 +141,8 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
                       const rara_binned& out, int tile_passes, hipStream_t s);
 // First pass of the depth sort: its items are the n Gaussians in index order,
 // taken when drawn (tiles_touched > 0) with the bits of their depth as keys;
-// it writes the number of drawn Gaussians to count_out and clears the tile
-// ranges [range_words].
+// it writes the number of drawn Gaussians to count_out and sets the tile
+// ranges [range_words] to (0xffffffff, 0) (no pair yet).
 struct SortFirstPass {
     const float* depth;
     const uint32_t* tt;
@@ -151,11 +151,18 @@ struct SortFirstPass {
     uint32_t* ranges;
     int64_t range_words;
 };
+// Extra output of the last pass: for every key below num_tiles, the first
+// output position (atomic min into ranges[2 key]) and one past the last
+// (atomic max into ranges[2 key + 1]).
+struct SortLastPass {
+    uint32_t* ranges;
+    uint32_t num_tiles;
+};
 hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int passes, const int64_t* count,
                        const int32_t* overflow, int64_t blocks, uint32_t* hist, uint32_t* digit_totals,
                        uint64_t* final_keys, uint32_t* final_vals, const float* depth, const SortFirstPass* first,
-                       hipStream_t s);
-hipError_t launch_ranges(const rara_binned& out, int64_t cap, int num_tiles, bool clear, hipStream_t s);
+                       const SortLastPass* last, hipStream_t s);
+hipError_t launch_ranges_clear(const rara_binned& out, int num_tiles, hipStream_t s);
 hipError_t launch_plan(const rara_binned& out, int num_tiles, hipStream_t s);
 // the same kernels reading their per-frame parameters from device memory
 hipError_t launch_preprocess_fp(const GaussPtrs& g, const FrameParams* fp, const ProjPtrs& out, hipStream_t s);

@@ -54,7 +54,7 @@ __device__ inline uint64_t match_digit(uint32_t digit, bool valid)
 
 // kFilter (first depth pass): item i is Gaussian i, taken when it is drawn
 // (tiles_touched > 0), its key the bits of its positive depth; the kernel also
-// clears the tile ranges of the frame.
+// resets the tile ranges of the frame (start 0xffffffff, end 0: no pair yet).
 template <bool kFilter>
 __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
     const uint32_t* __restrict__ keys, const int64_t* __restrict__ num_items, const int32_t* __restrict__ overflow,
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
     if (kFilter)
         for (int64_t w = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; w < range_words;
              w += (int64_t)gridDim.x * kSortThreads)
-            ranges[w] = 0u;
+            ranges[w] = (w & 1) ? 0u : 0xffffffffu;
     if (overflow && *overflow) return;
     const int64_t P = kFilter ? n_items : *num_items;
     const int64_t tile = sort_tile_of_block(blockIdx.x, (P + kSortTile - 1) / kSortTile);
@@ -128,14 +128,15 @@ __global__ __launch_bounds__(256) void radix_scan_kernel(uint32_t* __restrict__ 
 // kFinal: keys_out is ignored and the 64-bit (key << 32 | depth bits of the
 // value's Gaussian) key is written to final_keys instead.  kFilter: the input
 // of radix_upsweep_kernel<true>; the pass also writes the number of drawn
-// Gaussians to count_out.
+// Gaussians to count_out.  last.ranges (optional): the tile ranges of
+// SortLastPass.
 template <bool kFinal, bool kFilter>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const int64_t* __restrict__ num_items, const int32_t* __restrict__ overflow,
     int shift, const uint32_t* __restrict__ hist, int64_t stride, const uint32_t* __restrict__ digit_totals,
     uint64_t* __restrict__ final_keys, const float* __restrict__ depth, const uint32_t* __restrict__ tt,
-    int64_t n_items, int64_t* __restrict__ count_out)
+    int64_t n_items, int64_t* __restrict__ count_out, SortLastPass last)
 {
     if (overflow && *overflow) return;
     const int64_t P = kFilter ? n_items : *num_items;
@@ -249,6 +250,13 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         else
             keys_out[g] = kk;
         vals_out[g] = v;
+        // equal keys are consecutive in s_keys and in the output: the first and
+        // last of each group here bound the key's range (every workgroup's
+        // groups of one key together form one interval)
+        if (last.ranges && kk < last.num_tiles) {
+            if (k == 0 || s_keys[k - 1] != kk) atomicMin(&last.ranges[2 * kk], g);
+            if (k == cnt - 1 || s_keys[k + 1] != kk) atomicMax(&last.ranges[2 * kk + 1], g + 1u);
+        }
     }
 }
 
@@ -257,8 +265,9 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int passes, const int64_t* count,
                        const int32_t* overflow, int64_t blocks, uint32_t* hist, uint32_t* digit_totals,
                        uint64_t* final_keys, uint32_t* final_vals, const float* depth, const SortFirstPass* first,
-                       hipStream_t s)
+                       const SortLastPass* last, hipStream_t s)
 {
+    const SortLastPass none{nullptr, 0u};
     // pass p reads (ka, va) when p is even and (kb, vb) when odd; with final_keys
     // the last pass writes (final_keys, final_vals) instead of the other buffer;
     // with `first`, pass 0 reads the drawn Gaussians instead of (ka, va) and
@@ -272,6 +281,7 @@ hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, i
         uint32_t* vout = even ? vb : va;
         const int shift = p * kRadixBits;
         const bool filter = first && p == 0;
+        const SortLastPass lp = (last && p == passes - 1) ? *last : none;
         if (filter) {
             hipLaunchKernelGGL(radix_upsweep_kernel<true>, dim3(grid), dim3(kSortThreads), 0, s, nullptr, nullptr,
                                overflow, shift, hist, blocks, first->depth, first->tt, first->n, first->ranges,
@@ -280,7 +290,7 @@ hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, i
                                overflow, digit_totals);
             hipLaunchKernelGGL((radix_scatter_kernel<false, true>), dim3(grid), dim3(kSortThreads), 0, s, nullptr,
                                nullptr, kout, vout, nullptr, overflow, shift, hist, blocks, digit_totals, nullptr,
-                               first->depth, first->tt, first->n, first->count_out);
+                               first->depth, first->tt, first->n, first->count_out, lp);
             continue;
         }
         hipLaunchKernelGGL(radix_upsweep_kernel<false>, dim3(grid), dim3(kSortThreads), 0, s, kin, count, overflow,
@@ -290,11 +300,11 @@ hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, i
         if (final_keys && p == passes - 1)
             hipLaunchKernelGGL((radix_scatter_kernel<true, false>), dim3(grid), dim3(kSortThreads), 0, s, kin, vin,
                                kout, final_vals, count, overflow, shift, hist, blocks, digit_totals, final_keys, depth,
-                               nullptr, (int64_t)0, nullptr);
+                               nullptr, (int64_t)0, nullptr, lp);
         else
             hipLaunchKernelGGL((radix_scatter_kernel<false, false>), dim3(grid), dim3(kSortThreads), 0, s, kin, vin,
                                kout, vout, count, overflow, shift, hist, blocks, digit_totals, nullptr, nullptr,
-                               nullptr, (int64_t)0, nullptr);
+                               nullptr, (int64_t)0, nullptr, lp);
     }
     return hipGetLastError();
 }

@@ -85,8 +85,22 @@ def tiles_of(rects, tiles_x):
     return out
 
 
+def check_ranges(g):
+    """Every tile's [start, end) equals the run of its pairs in the sorted
+    keys, (0, 0) for a tile without pairs."""
+    rng = g["ranges"].astype(np.int64)
+    tile = (g["keys"] >> np.uint64(32)).astype(np.int64)
+    assert np.all(np.diff(tile) >= 0), "keys not sorted by tile"
+    counts = np.bincount(tile, minlength=len(rng))[: len(rng)]
+    starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    exp = np.where((counts > 0)[:, None], np.stack([starts, starts + counts], 1), 0)
+    bad = np.nonzero(np.any(rng != exp, axis=1))[0]
+    assert len(bad) == 0, f"{len(bad)} tile ranges wrong, first {bad[:5]}: {rng[bad[:3]].tolist()} vs {exp[bad[:3]].tolist()}"
+
+
 def check_lists(g, o, tiles=None, skip=()):
     """Per-tile lists identical to the oracle's (ids and order)."""
+    check_ranges(g)
     offs, ids = o["offsets"], o["ids"]
     T = len(offs) - 1
     tiles = range(T) if tiles is None else tiles

@@ -98,6 +98,7 @@ def test_plane_behind_scene_gives_background():
     back = scenes.plane_sweep(sc, scenes.tiny_plane(0).n, count=2)[-1]
     g = H.gpu_frame(sc, cam, back, bg=(0.25, 0.5, 0.75))
     assert (g["label"] == 0).all() and g["P"] == 0
+    assert not g["ranges"].any()
     np.testing.assert_array_equal(g["image"], np.broadcast_to(np.array([0.25, 0.5, 0.75], np.float32)[:, None, None],
                                                               g["image"].shape).astype(np.float64))
 
@@ -116,6 +117,7 @@ def test_empty_scene():
     sc = scenes.tiny_scene(0).subset(np.arange(0))
     g = H.gpu_frame(sc, scenes.tiny_camera(), scenes.tiny_plane(0), bg=(0.1, 0.1, 0.1))
     assert g["P"] == 0
+    assert not g["ranges"].any()
     np.testing.assert_allclose(g["image"], 0.1, atol=1e-7)
 
 
@@ -148,8 +150,10 @@ def test_capacity_overflow_reported_and_frame_untouched():
     assert int(fr.bins.overflow.item()) == 1
     assert int(fr.bins.num_pairs.item()) == P
     assert (fr.out.image == -7.0).all()
+    assert not fr.bins.ranges.any()   # no tile gets a list from an overflowing frame
     out = R.render_checked(ds, fr, cam, pl)
     assert int(fr.bins.overflow.item()) == 0 and fr.capacity >= P
+    H.check_lists(H.collect(fr, out, sc.n), o)
 
 
 def test_general_scene_1080p_sampled():

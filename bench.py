@@ -318,7 +318,7 @@ def measure(sc, frames, args, reps, label):
     if args.no_plain:
         del variants["original"], variants["hard"]
     # capacity from one pass over every frame (outside the timed region)
-    fr = R.Frame(sc.n, W, H, 8 * sc.n, dev, walked=False, pair_start=False)
+    fr = R.Frame(sc.n, W, H, 8 * sc.n, dev, walked=False, pair_start=False, sorted_keys=False)
     maxP = 0
     for name, fl in variants.items():
         for cam, pl in (fl if name == "rara" else fl[:: max(1, len(fl) // 16)]):
@@ -459,7 +459,7 @@ def diff_bench(reps):
     sc = scenes.general_scene(4, n=500_000)
     cams, planes = scenes.diff_views(scene=sc)
     tgt = scenes.perturbed(sc)
-    frames = [R.Frame(sc.n, c.width, c.height, 16 * sc.n, dev, walked=False) for c in cams]
+    frames = [R.Frame(sc.n, c.width, c.height, 16 * sc.n, dev, walked=False, sorted_keys=False) for c in cams]
 
     def t(a, g=True):
         return torch.tensor(np.asarray(a), dtype=torch.float32, device=dev, requires_grad=g)
@@ -534,7 +534,7 @@ def main():
         ds = R.DeviceScene.from_scene(sc, dev)
         W, H = frames[0][0].width, frames[0][0].height
         pick = [frames[i % len(frames)] for i in range(args.warmup + args.profile_steps)]
-        fr = R.Frame(sc.n, W, H, 8 * sc.n, dev, walked=False, pair_start=False)
+        fr = R.Frame(sc.n, W, H, 8 * sc.n, dev, walked=False, pair_start=False, sorted_keys=False)
         maxP = 0
         for cam, pl in frames:
             R.render_checked(ds, fr, cam, pl)

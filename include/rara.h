@@ -172,7 +172,13 @@ typedef struct {
  *                                Gaussians that are not drawn.  Required by
  *                                rara_render_backward, which gives every (tile,
  *                                Gaussian) pair its own gradient slot; a frame that
- *                                is only rendered can leave it NULL. */
+ *                                is only rendered can leave it NULL.
+ *   keys_scratch                 0: keys holds the sorted keys above.  Nonzero: keys
+ *                                only serves as scratch memory of the sort and its
+ *                                contents are unspecified afterwards; rara_render and
+ *                                rara_render_backward do not read it, and the last
+ *                                sort pass then skips a per-pair gather of the depth.
+ *                                A zero-initialised struct keeps the sorted keys. */
 typedef struct {
     uint64_t* keys;
     uint32_t* vals;
@@ -181,6 +187,7 @@ typedef struct {
     int32_t* overflow;
     uint32_t* work;
     uint32_t* pair_start;
+    int32_t keys_scratch;
 } rara_binned;
 
 /* Gradients (caller-allocated; overwritten, not accumulated):

@@ -56,5 +56,6 @@ def render(mean, scale, quat, opacity, sh, plane4, cam, plane_enabled=True, bg=(
     """Differentiable RaRa-clipped image [3][H][W] of one camera."""
     if frame is None:
         n = int(mean.shape[1])
-        frame = R.Frame(n, cam.width, cam.height, capacity or max(1 << 16, 16 * n), mean.device, walked=False)
+        frame = R.Frame(n, cam.width, cam.height, capacity or max(1 << 16, 16 * n), mean.device, walked=False,
+                        sorted_keys=False)
     return RaraRender.apply(mean, scale, quat, opacity, sh, plane4, cam, plane_enabled, tuple(bg), frame)

@@ -47,7 +47,7 @@ class Projected(ctypes.Structure):
 
 class Binned(ctypes.Structure):
     _fields_ = [("keys", _P), ("vals", _P), ("ranges", _P), ("num_pairs", _P), ("overflow", _P), ("work", _P),
-                ("pair_start", _P)]
+                ("pair_start", _P), ("keys_scratch", ctypes.c_int32)]
 
 
 class Grads(ctypes.Structure):

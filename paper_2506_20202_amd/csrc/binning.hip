@@ -288,7 +288,8 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
     // the tile ranges (tiles without pairs keep (0xffffffff, 0) for plan_kernel)
     const SortLastPass last{n > 0 ? out.ranges : nullptr, num_tiles};
     return sort_passes(ka, va, kb, vb, tile_passes, out.num_pairs, out.overflow, ws.tile_blocks, ws.hist,
-                       ws.digit_totals, out.keys, out.vals, proj.depth, nullptr, &last, s);
+                       ws.digit_totals, out.keys_scratch ? nullptr : out.keys, out.vals, proj.depth, nullptr, &last,
+                       s);
 }
 
 hipError_t launch_ranges_clear(const rara_binned& out, int num_tiles, hipStream_t s)

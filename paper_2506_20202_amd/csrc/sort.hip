@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void radix_scan_kernel(uint32_t* __restrict__ 
 }
 
 // kFinal: keys_out is ignored and the 64-bit (key << 32 | depth bits of the
-// value's Gaussian) key is written to final_keys instead.  kFilter: the input
+// value's Gaussian) key is written to final_keys instead (when not null).  kFilter: the input
 // of radix_upsweep_kernel<true>; the pass also writes the number of drawn
 // Gaussians to count_out.  last.ranges (optional): the tile ranges of
 // SortLastPass.
@@ -245,10 +245,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         const uint32_t d = (kk >> shift) & (kRadix - 1);
         const uint32_t g = global_start[d] + ((uint32_t)k - local_start[d]);
         const uint32_t v = s_vals[k];
-        if (kFinal)
-            final_keys[g] = ((uint64_t)kk << 32) | (uint64_t)__float_as_uint(depth[v]);
-        else
+        if (!kFinal)
             keys_out[g] = kk;
+        else if (final_keys)
+            final_keys[g] = ((uint64_t)kk << 32) | (uint64_t)__float_as_uint(depth[v]);
         vals_out[g] = v;
         // equal keys are consecutive in s_keys and in the output: the first and
         // last of each group here bound the key's range (every workgroup's
@@ -268,8 +268,9 @@ hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, i
                        const SortLastPass* last, hipStream_t s)
 {
     const SortLastPass none{nullptr, 0u};
-    // pass p reads (ka, va) when p is even and (kb, vb) when odd; with final_keys
-    // the last pass writes (final_keys, final_vals) instead of the other buffer;
+    // pass p reads (ka, va) when p is even and (kb, vb) when odd; with final_vals
+    // the last pass writes (final_keys, final_vals) instead of the other buffer
+    // (final_keys may be null: no keys written);
     // with `first`, pass 0 reads the drawn Gaussians instead of (ka, va) and
     // writes their number to first->count_out (the `count` of later passes)
     const unsigned grid = (unsigned)((blocks + 7) / 8 * 8);   // see sort_tile_of_block
@@ -297,7 +298,7 @@ hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, i
                            shift, hist, blocks, nullptr, nullptr, (int64_t)0, nullptr, (int64_t)0);
         hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadix), dim3(256), 0, s, hist, blocks, count, (int64_t)0,
                            overflow, digit_totals);
-        if (final_keys && p == passes - 1)
+        if (final_vals && p == passes - 1)
             hipLaunchKernelGGL((radix_scatter_kernel<true, false>), dim3(grid), dim3(kSortThreads), 0, s, kin, vin,
                                kout, final_vals, count, overflow, shift, hist, blocks, digit_totals, final_keys, depth,
                                nullptr, (int64_t)0, nullptr, lp);

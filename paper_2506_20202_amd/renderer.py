@@ -88,10 +88,15 @@ class ProjectedBuffers:
 
 class BinBuffers:
     """rara_binned plus the bin/sort workspace for a pair capacity.
-    ``pair_start`` (needed only by the backward) is allocated on request."""
+    ``pair_start`` (needed only by the backward) is allocated on request;
+    ``sorted_keys=False`` leaves ``keys`` as sort scratch (the frame's tile
+    lists, ranges and image are the same; only the 64-bit keys are not
+    written)."""
 
-    def __init__(self, n: int, width: int, height: int, capacity: int, device="cuda", pair_start: bool = True):
+    def __init__(self, n: int, width: int, height: int, capacity: int, device="cuda", pair_start: bool = True,
+                 sorted_keys: bool = True):
         self.capacity = int(capacity)
+        self.sorted_keys = bool(sorted_keys)
         tiles = ((width + 15) // 16) * ((height + 15) // 16)
         self.keys = torch.empty(self.capacity, dtype=torch.int64, device=device)
         self.vals = torch.empty(self.capacity, dtype=torch.int32, device=device)
@@ -111,6 +116,7 @@ class BinBuffers:
         b.num_pairs, b.overflow = _ptr(self.num_pairs), _ptr(self.overflow)
         b.work = _ptr(self.work)
         b.pair_start = _ptr(self.pair_start)
+        b.keys_scratch = 0 if self.sorted_keys else 1
         return b
 
     def nbytes(self) -> int:
@@ -128,15 +134,16 @@ class ImageBuffers:
 
 class Frame:
     """All device buffers of one frame shape (n Gaussians, W x H, capacity).
-    ``pair_start`` keeps the per-Gaussian pair offsets the backward needs;
-    a frame that is only rendered can go without them."""
+    ``pair_start`` keeps the per-Gaussian pair offsets the backward needs and
+    ``sorted_keys`` the 64-bit sorted keys; a frame that is only rendered can
+    go without both."""
 
     def __init__(self, n: int, width: int, height: int, capacity: int, device="cuda", walked: bool = True,
-                 pair_start: bool = True):
+                 pair_start: bool = True, sorted_keys: bool = True):
         self.n, self.width, self.height = int(n), int(width), int(height)
         self.device = device
         self.proj = ProjectedBuffers(n, device)
-        self.bins = BinBuffers(n, width, height, capacity, device, pair_start)
+        self.bins = BinBuffers(n, width, height, capacity, device, pair_start, sorted_keys)
         self.out = ImageBuffers(width, height, device, walked)
 
     @property
@@ -145,7 +152,7 @@ class Frame:
 
     def grow(self, capacity: int):
         self.bins = BinBuffers(self.n, self.width, self.height, capacity, self.device,
-                               self.bins.pair_start is not None)
+                               self.bins.pair_start is not None, self.bins.sorted_keys)
 
 
 def enqueue_frame(scene: DeviceScene, frame: Frame, cam, plane, bg=(0.0, 0.0, 0.0), stream=None,
@@ -234,7 +241,8 @@ class FramePipeline:
         if streams < 1:
             raise ValueError("streams must be at least 1")
         self.scene = scene
-        self.frames = [Frame(scene.n, width, height, capacity, dev, walked, pair_start=False) for _ in range(streams)]
+        self.frames = [Frame(scene.n, width, height, capacity, dev, walked, pair_start=False, sorted_keys=False)
+                       for _ in range(streams)]
         self.streams = [new_stream(dev) for _ in range(streams)]
         self.count = 0
         self.start()

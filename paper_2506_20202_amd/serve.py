@@ -260,7 +260,7 @@ class GpuExecutor:
         from . import renderer as R
         name, W, H = shape
         scene = self.scenes[name]
-        fr = R.Frame(scene.n, W, H, capacity, self.device, walked=False, pair_start=False)
+        fr = R.Frame(scene.n, W, H, capacity, self.device, walked=False, pair_start=False, sorted_keys=False)
         # the buffers were allocated (and the scene uploaded) on the current
         # stream: the slot's first launch waits for that work
         ready = self.torch.cuda.Event()

@@ -51,6 +51,30 @@ def test_header_compiles_as_c(tmp_path):
                     str(tmp_path / "t")], check=True)
 
 
+def test_struct_layouts_match_header(B, tmp_path):
+    """Every ctypes struct of the binding has the C header's size and field
+    offsets (the binding marshals by layout)."""
+    pairs = [("rara_gaussians", B.Gaussians), ("rara_camera", B.Camera), ("rara_plane", B.Plane),
+             ("rara_projected", B.Projected), ("rara_binned", B.Binned), ("rara_grads", B.Grads)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rara.h"', 'int main(void){']
+    for cname, py in pairs:
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append('return 0; }')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                               check=True).stdout.splitlines())
+    for cname, py in pairs:
+        assert int(got[f"{cname} sizeof"]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname} {f}"]) == getattr(py, f).offset, (cname, f)
+
+
 def test_status_strings_and_version(B):
     assert B.status_string(B.RARA_OK) == "ok"
     assert "invalid" in B.status_string(B.RARA_ERR_INVALID)

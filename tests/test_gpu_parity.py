@@ -360,3 +360,28 @@ def test_long_list_forward_is_deterministic():
     b = H.gpu_frame(sc, cam, pl, capacity=1 << 22)
     for k in ("image", "final_T", "n_contrib", "n_walked"):
         np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_scratch_keys_frame_matches_sorted_keys_frame():
+    """keys_scratch = 1 (the sorted 64-bit keys not written): the same lists,
+    ranges, schedule and image as a frame that writes them."""
+    import torch
+    from paper_2506_20202_amd import renderer as R
+    sc = _dense_scene(2, 6000, 0.05, -2.5)
+    cam = scenes.small_camera(100)
+    pl = scenes.Plane(DENSE_NORMAL, 0.02)
+    dev = torch.device("cuda:0")
+    ds = R.DeviceScene.from_scene(sc, dev)
+    outs = []
+    for sorted_keys in (True, False):
+        fr = R.Frame(sc.n, cam.width, cam.height, 1 << 22, dev, sorted_keys=sorted_keys)
+        fr.bins.keys.fill_(-1)
+        out = R.render_checked(ds, fr, cam, pl)
+        outs.append((fr, H.collect(fr, out, sc.n)))
+    (fa, a), (fb, b) = outs
+    H.check_ranges(a)
+    P = a["P"]
+    assert P == b["P"] and P > 0
+    for k in ("vals", "ranges", "image", "final_T", "n_contrib", "n_walked"):
+        np.testing.assert_array_equal(a[k], b[k])
+    np.testing.assert_array_equal(fa.bins.work.cpu().numpy(), fb.bins.work.cpu().numpy())

@@ -18,11 +18,12 @@
 // The pair offsets are a reduce-then-scan over 256-Gaussian chunks of the
 // depth order: a sum of the tile counts per chunk, and each emit workgroup
 // adds the sums before its chunk to get its first pair (a few KB of reads
-// that stay in L2, instead of a kernel that scans the sums).  Inside a chunk the prefix is a wavefront-ballot scan: bit b
-// of every lane's count is gathered with one 64-lane ballot, and mbcnt
-// (popcount of the ballot below the lane) times 2^b is added to the lane's
-// prefix; the loop stops at the highest bit any lane still holds.  Four wave
-// totals are combined through LDS.
+// that stay in L2, instead of a kernel that scans the sums).  Inside a chunk
+// the prefix is a wavefront-ballot scan: bit b of every lane's count is
+// gathered with one 64-lane ballot, and mbcnt (popcount of the ballot below
+// the lane) times 2^b is added to the lane's prefix; the loop stops at the
+// highest bit any lane still holds.  Four wave totals are combined through
+// LDS.
 #include "rara_internal.h"
 
 namespace rara {
@@ -98,7 +99,8 @@ __global__ void no_pairs_kernel(int64_t* __restrict__ num_pairs, int32_t* __rest
 __global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ tt, const uint16_t* __restrict__ rect,
                                                    const uint32_t* __restrict__ order,
                                                    const int64_t* __restrict__ count,
-                                                   const uint32_t* __restrict__ chunk_sums, int64_t cap, int tiles_x, int64_t* __restrict__ num_pairs,
+                                                   const uint32_t* __restrict__ chunk_sums, int64_t cap,
+                                                   int tiles_x, int64_t* __restrict__ num_pairs,
                                                    int32_t* __restrict__ overflow, uint32_t* __restrict__ tkeys,
                                                    uint32_t* __restrict__ tvals, uint32_t* __restrict__ pair_start)
 {

@@ -75,13 +75,29 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
     for (int k = threadIdx.x; k < kWaves * kRadix; k += kSortThreads) (&counts[0][0])[k] = 0u;
     __syncthreads();
     const int64_t wbase = base + (int64_t)wave * kWaveKeys;
-    for (int r = 0; r < kWaveKeys / 64; ++r) {
+    // every load of the wave first (the filter's depth and tile-count loads
+    // together), then the ballot counts
+    uint32_t key[kSortItems];
+    bool valid[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
         const int64_t idx = wbase + r * 64 + lane;
-        const bool valid = idx < P && (!kFilter || tt[idx] > 0u);
-        const uint32_t key = valid ? (kFilter ? __float_as_uint(depth[idx]) : keys[idx]) : 0u;
-        const uint32_t d = (key >> shift) & (kRadix - 1);
-        const uint64_t peers = match_digit(d, valid);
-        if (valid && lanes_below(peers) == 0) counts[wave][d] += (uint32_t)__popcll(peers);
+        const bool in = idx < P;
+        if (kFilter) {
+            const uint32_t t = in ? tt[idx] : 0u;
+            const uint32_t k = in ? __float_as_uint(depth[idx]) : 0u;
+            valid[r] = t > 0u;
+            key[r] = k;
+        } else {
+            valid[r] = in;
+            key[r] = in ? keys[idx] : 0u;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint32_t d = (key[r] >> shift) & (kRadix - 1);
+        const uint64_t peers = match_digit(d, valid[r]);
+        if (valid[r] && lanes_below(peers) == 0) counts[wave][d] += (uint32_t)__popcll(peers);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < kRadix; d += kSortThreads) {
@@ -168,9 +184,18 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t idx = wbase + r * 64 + lane;
-        const bool valid = idx < P && (!kFilter || tt[idx] > 0u);
-        key[r] = valid ? (kFilter ? __float_as_uint(depth[idx]) : keys_in[idx]) : 0u;
-        val[r] = valid ? (kFilter ? (uint32_t)idx : vals_in[idx]) : 0u;
+        const bool in = idx < P;
+        bool valid;
+        if (kFilter) {
+            const uint32_t t = in ? tt[idx] : 0u;
+            key[r] = in ? __float_as_uint(depth[idx]) : 0u;
+            val[r] = (uint32_t)idx;
+            valid = t > 0u;
+        } else {
+            key[r] = in ? keys_in[idx] : 0u;
+            val[r] = in ? vals_in[idx] : 0u;
+            valid = in;
+        }
         packed[r] = valid ? 0u : 0xffffffffu;
     }
 #pragma unroll

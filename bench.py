@@ -237,6 +237,7 @@ def serve_bench(args):
     for name, sc in defs:
         eng.add_scene(name, sc)
     resident = eng.ex.resident_bytes()
+    graphs = eng.ex.use_graphs
     budget = resident + int(args.serve_budget_gib * (1 << 30))
     eng.sched.budget = budget
 
@@ -295,7 +296,7 @@ def serve_bench(args):
             "requests": len(stream), "saturation_req_s": sat, "offered_load_req_s": rate,
             "load_fraction": args.serve_load, "hbm_budget_gib": budget / 2 ** 30, "max_slots": args.serve_slots,
             "max_inflight": args.serve_inflight, "lanes": args.serve_lanes,
-            "graphs": True,
+            "graphs": graphs,
             "clipped": clipped, "plain": plain}
 
 

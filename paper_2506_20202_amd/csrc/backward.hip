@@ -13,8 +13,9 @@
 //                   waves of a tile combine them in LDS, and the 21 sums go to
 //                   the pair's own slot (its position in emission order) with
 //                   plain stores: no per-Gaussian atomics.
-//   project_backward per Gaussian, sum of its (contiguous) pair slots, then
-//                   the FP64 chain rule from (mean2d, conic,
+//   slot_sum        per Gaussian, the FP64 sum of its (contiguous) pair slots
+//                   (a light kernel, so that many waves hide the loads);
+//   project_backward per Gaussian, the FP64 chain rule from (mean2d, conic,
 //                   opacity, colour, ray set-up) to (mean, scale, quaternion,
 //                   opacity, SH) and the plane, through the EWA projection of
 //                   eqs. (9)-(10), the SH colour and eq. (4)'s whitening.
@@ -177,7 +178,7 @@ __device__ inline void blend_back_tile(const Splat* __restrict__ splats, const R
         dC[ch] = inside ? dL_dimage[ch * HW + pix] : 0.0f;
         bgdot += p.bg[ch] * dC[ch];
     }
-    // the tile's largest n_contrib, clamped to the list length
+    // the wave's and the tile's largest n_contrib (the tile's clamped to the list length)
     const uint32_t wm = wave_max(nc);
     if (lane == 0) s_red[wave] = wm;
     __syncthreads();
@@ -222,6 +223,12 @@ __device__ inline void blend_back_tile(const Splat* __restrict__ splats, const R
         for (int sub = (int)((cnt - 1) & ~63u); sub >= 0; sub -= 64) {
             const uint32_t lm = __float_as_uint(s_c[sub + lane].y);
             uint64_t todo = __ballot((lm >> (8 + wave)) & 1u);
+            // entries past the wave's largest n_contrib change none of its pixels
+            const uint32_t kb = lo - rg.x + (uint32_t)sub;   // entry sub + j has k1 = kb + j + 1
+            if (wm <= kb)
+                todo = 0ull;
+            else if (wm - kb < 64u)
+                todo &= (1ull << (wm - kb)) - 1ull;
             const uint64_t cutb = __ballot(plane_on && (lm & 0xffu) == RARA_LABEL_CUTOFF);
             while (todo) {
                 const int j = 63 - (int)__builtin_clzll(todo);
@@ -281,19 +288,22 @@ __device__ inline void blend_back_tile(const Splat* __restrict__ splats, const R
                     }
                 }
                 if (__ballot(contributed) != 0ull) {
+                    // the wave sums, row r in lane r, added with one LDS instruction
                     const float v9[9] = {g_mx, g_my, g_ca, g_cb, g_cc, g_op, g_col[0], g_col[1], g_col[2]};
+                    float mine = 0.0f;
 #pragma unroll
                     for (int r = 0; r < 9; ++r) {
                         const float sum = wave_sum(v9[r]);
-                        if (lane == 0 && sum != 0.0f) atomicAdd(&s_g[e][r], sum);
+                        mine = lane == r ? sum : mine;
                     }
                     if (cut) {
 #pragma unroll
                         for (int r = 0; r < 12; ++r) {
                             const float sum = wave_sum(g_ray[r]);
-                            if (lane == 0 && sum != 0.0f) atomicAdd(&s_g[e][A_D0 + r], sum);
+                            mine = lane == A_D0 + r ? sum : mine;
                         }
                     }
+                    if (lane < (cut ? kAccRows : A_D0) && mine != 0.0f) atomicAdd(&s_g[e][lane], mine);
                 }
             }
         }
@@ -318,18 +328,12 @@ __device__ inline void blend_back_tile(const Splat* __restrict__ splats, const R
     }
 }
 
-__global__ __launch_bounds__(256) void blend_backward_kernel(const Splat* __restrict__ splats,
-                                                             const RayRec* __restrict__ rays,
-                                                             const uint32_t* __restrict__ vals,
-                                                             const uint2* __restrict__ ranges,
-                                                             const uint32_t* __restrict__ work,
-                                                             const uint32_t* __restrict__ pair_start,
-                                                             const uint16_t* __restrict__ rect,
-                                                             const int32_t* __restrict__ overflow, BackParams bp,
-                                                             const float* __restrict__ final_T,
-                                                             const uint32_t* __restrict__ n_contrib,
-                                                             const float* __restrict__ dL_dimage,
-                                                             float* __restrict__ slots, float* __restrict__ plane_acc)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void blend_backward_kernel(
+    const Splat* __restrict__ splats, const RayRec* __restrict__ rays, const uint32_t* __restrict__ vals,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ work, const uint32_t* __restrict__ pair_start,
+    const uint16_t* __restrict__ rect, const int32_t* __restrict__ overflow, BackParams bp,
+    const float* __restrict__ final_T, const uint32_t* __restrict__ n_contrib, const float* __restrict__ dL_dimage,
+    float* __restrict__ slots, float* __restrict__ plane_acc)
 {
     if (*overflow) return;
     uint32_t tile;
@@ -426,11 +430,43 @@ struct GradPtrs {
     float *mean, *scale, *quat, *opacity, *sh;
 };
 
+// Sum of each drawn Gaussian's pair slots (contiguous in emission order) in
+// FP64: rows 0..8 always, the ray set-up rows 9.. for a CUTOFF Gaussian with
+// the plane on; sums[r][i].  Rows a Gaussian does not use are not written.
+__global__ __launch_bounds__(256) void slot_sum_kernel(int64_t n, int32_t plane_enabled,
+                                                       const uint8_t* __restrict__ label,
+                                                       const uint32_t* __restrict__ tiles_touched,
+                                                       const uint32_t* __restrict__ pair_start,
+                                                       const float* __restrict__ slots, double* __restrict__ sums)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t tt = tiles_touched[i];
+    if (tt == 0u) return;
+    const bool cutg = plane_enabled && label[i] == RARA_LABEL_CUTOFF;
+    double acc[kAccRows];
+    for (int r = 0; r < kAccRows; ++r) acc[r] = 0.0;
+    const float* src = slots + (int64_t)pair_start[i] * kAccRows;
+    for (uint32_t j = 0; j < tt; ++j, src += kAccRows) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) acc[r] += (double)src[r];
+        if (cutg) {
+#pragma unroll
+            for (int r = 9; r < kAccRows; ++r) acc[r] += (double)src[r];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 9; ++r) sums[r * n + i] = acc[r];
+    if (cutg) {
+#pragma unroll
+        for (int r = 9; r < kAccRows; ++r) sums[r * n + i] = acc[r];
+    }
+}
+
 __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamParams cam, PlaneParams pl,
                                                                const uint8_t* __restrict__ label,
                                                                const uint32_t* __restrict__ tiles_touched,
-                                                               const uint32_t* __restrict__ pair_start,
-                                                               const float* __restrict__ slots, GradPtrs out,
+                                                               const double* __restrict__ sums, GradPtrs out,
                                                                float* __restrict__ plane_acc)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -443,19 +479,13 @@ __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamP
         const uint32_t tt = tiles_touched[i];
         const bool drawn = tt > 0;
         if (drawn) {
-            // this Gaussian's per-pair gradient slots are contiguous: sum them
+            // the sums of this Gaussian's pair slots (slot_sum_kernel)
             const bool cutg = pl.enabled && label[i] == RARA_LABEL_CUTOFF;
             double acc[kAccRows];
-            for (int r = 0; r < kAccRows; ++r) acc[r] = 0.0;
-            const float* src = slots + (int64_t)pair_start[i] * kAccRows;
-            for (uint32_t j = 0; j < tt; ++j, src += kAccRows) {
 #pragma unroll
-                for (int r = 0; r < 9; ++r) acc[r] += (double)src[r];
-                if (cutg) {
+            for (int r = 0; r < 9; ++r) acc[r] = sums[r * n + i];
 #pragma unroll
-                    for (int r = 9; r < kAccRows; ++r) acc[r] += (double)src[r];
-                }
-            }
+            for (int r = 9; r < kAccRows; ++r) acc[r] = cutg ? sums[r * n + i] : 0.0;
             const double mu[3] = {g.mean[i], g.mean[n + i], g.mean[2 * n + i]};
             const double s[3] = {g.scale[i], g.scale[n + i], g.scale[2 * n + i]};
             double q4[4] = {g.quat[i], g.quat[n + i], g.quat[2 * n + i], g.quat[3 * n + i]};
@@ -650,14 +680,15 @@ __global__ void plane_finalize_kernel(CamParams cam, PlaneParams pl, double len,
 
 }  // namespace
 
+// workspace: pair slots [pair_capacity][kAccRows] float, the plane
+// accumulators (256 B), per-Gaussian slot sums [kAccRows][n] double
 size_t backward_workspace_bytes(int64_t n, int64_t pair_capacity, int32_t width, int32_t height)
 {
-    (void)n;
     (void)width;
     (void)height;
     const size_t slot_bytes = ((size_t)kAccRows * (size_t)(pair_capacity > 0 ? pair_capacity : 1) * 4 + 255) &
                               ~size_t(255);
-    return slot_bytes + 256;
+    return slot_bytes + 256 + (size_t)kAccRows * (size_t)(n > 0 ? n : 1) * 8;
 }
 
 hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl, double plane_len,
@@ -669,6 +700,7 @@ hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const Plane
     const size_t slot_bytes = ((size_t)kAccRows * (size_t)(pair_capacity > 0 ? pair_capacity : 1) * 4 + 255) &
                               ~size_t(255);
     float* plane_acc = reinterpret_cast<float*>(static_cast<char*>(workspace) + slot_bytes);
+    double* sums = reinterpret_cast<double*>(static_cast<char*>(workspace) + slot_bytes + 256);
     hipLaunchKernelGGL(fill_zero_kernel, dim3(1), dim3(256), 0, s, plane_acc, (int64_t)kPlaneAcc);
     BackParams bp{rp, g.n};
     if (g.n > 0)
@@ -677,9 +709,12 @@ hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const Plane
                            bins.pair_start, proj.rect, bins.overflow, bp, final_T, n_contrib, dL_dimage, slots,
                            plane_acc);
     if (g.n > 0) {
+        const dim3 grid((unsigned)((g.n + 255) / 256));
+        hipLaunchKernelGGL(slot_sum_kernel, grid, dim3(256), 0, s, g.n, pl.enabled, proj.label, proj.tiles_touched,
+                           bins.pair_start, slots, sums);
         GradPtrs gp{grads.mean, grads.scale, grads.quat, grads.opacity, grads.sh};
-        hipLaunchKernelGGL(project_backward_kernel, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g, cam, pl,
-                           proj.label, proj.tiles_touched, bins.pair_start, slots, gp, plane_acc);
+        hipLaunchKernelGGL(project_backward_kernel, grid, dim3(256), 0, s, g, cam, pl, proj.label, proj.tiles_touched,
+                           sums, gp, plane_acc);
     }
     hipLaunchKernelGGL(plane_finalize_kernel, dim3(1), dim3(64), 0, s, cam, pl, plane_len, plane_acc, grads.plane);
     return hipGetLastError();

@@ -385,3 +385,30 @@ def test_scratch_keys_frame_matches_sorted_keys_frame():
     for k in ("vals", "ranges", "image", "final_T", "n_contrib", "n_walked"):
         np.testing.assert_array_equal(a[k], b[k])
     np.testing.assert_array_equal(fa.bins.work.cpu().numpy(), fb.bins.work.cpu().numpy())
+
+
+@pytest.mark.parametrize("mode", [0, oracle.CLIP_RARA, oracle.CLIP_RARA | oracle.CLIP_TIGHT])
+def test_degenerate_gaussians(mode):
+    """Gaussians behind the camera, at the camera centre, on both sides of the
+    near plane, with a zero quaternion, a zero scale or a 1e-6 scale, one
+    centred on the clip plane: labels, culling, lists and image as the oracle
+    decides, with the rest of the scene unchanged."""
+    sc = scenes.tiny_scene(3, n=200)
+    cam = scenes.tiny_camera()
+    pl0 = scenes.tiny_plane(3)
+    mean, quat, scale = sc.mean.copy(), sc.quat.copy(), sc.scale.copy()
+    eye = np.array([0.0, 0.0, -3.0], np.float32)
+    mean[:, 0] = [0.0, 0.0, -4.0]          # behind the camera
+    mean[:, 1] = eye                       # at the camera centre
+    mean[:, 2] = [0.0, 0.0, -2.81]         # just inside the near plane (z = 0.19)
+    mean[:, 3] = [0.05, 0.0, -2.79]        # just beyond it (z = 0.21)
+    quat[:, 4] = 0.0                       # zero quaternion
+    scale[:, 5] = 0.0                      # zero scale
+    scale[:, 6] = 1e-6
+    n = np.asarray(pl0.n, np.float64)
+    mean[:, 7] = (-pl0.d * n).astype(np.float32)   # centred on the plane
+    sc2 = scenes.Scene(mean, scale, quat, sc.opacity, sc.sh, sc.sh_degree)
+    g, o = _full_check(sc2, cam, scenes.Plane(pl0.n, pl0.d, enabled=mode))
+    np.testing.assert_array_equal(g["label"][:8], o["label"][:8])
+    np.testing.assert_array_equal(g["tiles_touched"][:8], o["proj"]["tiles_touched"][:8])
+    assert np.isfinite(g["image"]).all()

@@ -433,6 +433,18 @@ struct GradPtrs {
 // Sum of each drawn Gaussian's pair slots (contiguous in emission order) in
 // FP64: rows 0..8 always, the ray set-up rows 9.. for a CUTOFF Gaussian with
 // the plane on; sums[r][i].  Rows a Gaussian does not use are not written.
+// A Gaussian with up to kSerialSlots slots is summed by its own thread, in
+// slot order; a larger one by the whole wave (lane l takes slots l, l + 64,
+// ..., then a wave sum), so that no wave waits on one long serial loop.
+constexpr uint32_t kSerialSlots = 32;
+
+__device__ inline double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 __global__ __launch_bounds__(256) void slot_sum_kernel(int64_t n, int32_t plane_enabled,
                                                        const uint8_t* __restrict__ label,
                                                        const uint32_t* __restrict__ tiles_touched,
@@ -440,26 +452,62 @@ __global__ __launch_bounds__(256) void slot_sum_kernel(int64_t n, int32_t plane_
                                                        const float* __restrict__ slots, double* __restrict__ sums)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t tt = tiles_touched[i];
-    if (tt == 0u) return;
-    const bool cutg = plane_enabled && label[i] == RARA_LABEL_CUTOFF;
-    double acc[kAccRows];
-    for (int r = 0; r < kAccRows; ++r) acc[r] = 0.0;
-    const float* src = slots + (int64_t)pair_start[i] * kAccRows;
-    for (uint32_t j = 0; j < tt; ++j, src += kAccRows) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t tt = i < n ? tiles_touched[i] : 0u;
+    const bool cutg = tt > 0u && plane_enabled && label[i] == RARA_LABEL_CUTOFF;
+    const uint32_t first = tt > 0u ? pair_start[i] : 0u;
+    if (tt > 0u && tt <= kSerialSlots) {
+        double acc[kAccRows];
+        for (int r = 0; r < kAccRows; ++r) acc[r] = 0.0;
+        const float* src = slots + (int64_t)first * kAccRows;
+        for (uint32_t j = 0; j < tt; ++j, src += kAccRows) {
 #pragma unroll
-        for (int r = 0; r < 9; ++r) acc[r] += (double)src[r];
+            for (int r = 0; r < 9; ++r) acc[r] += (double)src[r];
+            if (cutg) {
+#pragma unroll
+                for (int r = 9; r < kAccRows; ++r) acc[r] += (double)src[r];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 9; ++r) sums[r * n + i] = acc[r];
         if (cutg) {
 #pragma unroll
-            for (int r = 9; r < kAccRows; ++r) acc[r] += (double)src[r];
+            for (int r = 9; r < kAccRows; ++r) sums[r * n + i] = acc[r];
         }
     }
+    // the wave's large Gaussians, one after the other
+    uint64_t big = __ballot(tt > kSerialSlots);
+    while (big) {
+        const int src_lane = (int)__builtin_ctzll(big);
+        big &= big - 1ull;
+        const uint32_t bt = __builtin_amdgcn_readlane(tt, src_lane);
+        const uint32_t bfirst = __builtin_amdgcn_readlane(first, src_lane);
+        const bool bcut = __builtin_amdgcn_readlane(cutg ? 1 : 0, src_lane) != 0;
+        const int64_t bi = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63) + src_lane;
+        double acc[kAccRows];
 #pragma unroll
-    for (int r = 0; r < 9; ++r) sums[r * n + i] = acc[r];
-    if (cutg) {
+        for (int r = 0; r < kAccRows; ++r) acc[r] = 0.0;
+        for (uint32_t j = (uint32_t)lane; j < bt; j += 64) {
+            const float* src = slots + ((int64_t)bfirst + j) * kAccRows;
 #pragma unroll
-        for (int r = 9; r < kAccRows; ++r) sums[r * n + i] = acc[r];
+            for (int r = 0; r < 9; ++r) acc[r] += (double)src[r];
+            if (bcut) {
+#pragma unroll
+                for (int r = 9; r < kAccRows; ++r) acc[r] += (double)src[r];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            const double t = wave_sum_f64(acc[r]);
+            if (lane == 0) sums[r * n + bi] = t;
+        }
+        if (bcut) {
+#pragma unroll
+            for (int r = 9; r < kAccRows; ++r) {
+                const double t = wave_sum_f64(acc[r]);
+                if (lane == 0) sums[r * n + bi] = t;
+            }
+        }
     }
 }
 

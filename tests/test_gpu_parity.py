@@ -412,3 +412,39 @@ def test_degenerate_gaussians(mode):
     np.testing.assert_array_equal(g["label"][:8], o["label"][:8])
     np.testing.assert_array_equal(g["tiles_touched"][:8], o["proj"]["tiles_touched"][:8])
     assert np.isfinite(g["image"]).all()
+
+
+def test_pipelined_general_1080p_equals_alone():
+    """The configuration the bench times -- the 1M-Gaussian general scene at
+    1920x1080 through the three-stream frame pipeline, render-only frames
+    (scratch keys, no pair starts) -- renders each frame bit-identically to a
+    single frame with sorted keys.  The first pick is the frame that
+    test_general_scene_1080p_sampled checks against the oracle."""
+    import torch
+    from paper_2506_20202_amd import renderer as R
+    dev = torch.device("cuda:0")
+    sc = scenes.general_scene(1)
+    cams = scenes.general_views()
+    planes = scenes.plane_sweep(sc, scenes.general_plane_normal(1))
+    picks = [(cams[0], planes[8]), (cams[3], planes[2]), (cams[7], planes[12]), (cams[11], planes[5]),
+             (cams[0], planes[8]), (cams[15], planes[0]), (cams[5], scenes.Plane(planes[8].n, planes[8].d, 0))]
+    ds = R.DeviceScene.from_scene(sc, dev)
+    W, H = cams[0].width, cams[0].height
+    fr = R.Frame(sc.n, W, H, 12_000_000, dev)
+    refs, maxp = [], 0
+    for cam, pl in picks:
+        out = R.render_checked(ds, fr, cam, pl)
+        torch.cuda.synchronize()
+        refs.append(out.image.clone())
+        maxp = max(maxp, int(fr.bins.num_pairs.item()))
+    del fr
+    pipe = R.FramePipeline(ds, W, H, int(maxp * 1.05) + 4096, streams=3, walked=False)
+    got = []
+    for cam, pl in picks:
+        pipe.submit(cam, pl, consume=lambda f: got.append(f.out.image.clone()))
+    pipe.join()
+    torch.cuda.synchronize()
+    assert not pipe.overflowed()
+    pipe.close()
+    for k, (a, b) in enumerate(zip(got, refs)):
+        assert torch.equal(a, b), f"frame {k} differs"

@@ -68,6 +68,11 @@ constexpr int kBlendThreads = 256;   // one workgroup per tile: four waves, one 
 // and under 20 KB of LDS a CU holds 8 workgroups (8 waves per SIMD)
 constexpr int kTileBatch = 224;
 constexpr int kBatchSlots = 256;     // s_c rows: four 64-entry ballots, the tail zero
+// the clip-region variant stages the further planes' terms too (56 B per
+// entry): 128-entry batches keep it under 20 KB of LDS
+constexpr int kRegionBatch = 128;
+template <bool kRegion> constexpr int batch_of() { return kRegion ? kRegionBatch : kTileBatch; }
+template <bool kRegion> constexpr int slots_of() { return kRegion ? kRegionBatch : kBatchSlots; }
 
 // One tile: thread t of wave w = t / 64 owns pixel (t % 8, (t / 8) % 8) of the
 // 8x8 quadrant w.  Per batch, every thread stages one entry; after the
@@ -112,11 +117,12 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
     const bool strict = (p.plane_enabled & RARA_CLIP_STRICT_MISS) != 0;
     bool live = __ballot(thr < 1.0f) != 0ull;
 
-    for (uint32_t base = rg.x; base < rg.y; base += kTileBatch) {
+    constexpr int kB = batch_of<kRegion>();
+    for (uint32_t base = rg.x; base < rg.y; base += kB) {
         if (!__syncthreads_or(live ? 1 : 0)) break;   // also: the previous batch has been read
         const uint32_t idx = base + (uint32_t)tid;
         float2 sc = make_float2(0.0f, 0.0f);   // label | quadrant mask << 8 = 0: reaches nothing
-        if (tid < kTileBatch && idx < rg.y) {
+        if (tid < kB && idx < rg.y) {
             const uint32_t id = vals[idx];
             const Splat sp = splats[id];
             float4 sa, sb, c4;
@@ -136,10 +142,10 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
                         s_ext[tid * (kMaxPlanes - 1) + k] = ray_ext[(int64_t)id * (kMaxPlanes - 1) + k];
             }
         }
-        s_c[tid] = sc;
+        if (tid < slots_of<kRegion>()) s_c[tid] = sc;
         __syncthreads();
         if (!live) continue;
-        const uint32_t cnt = rg.y - base < (uint32_t)kTileBatch ? rg.y - base : (uint32_t)kTileBatch;
+        const uint32_t cnt = rg.y - base < (uint32_t)kB ? rg.y - base : (uint32_t)kB;
         const uint32_t kofs = base - rg.x + 1u;
         for (uint32_t sub = 0; sub < cnt && live; sub += 64) {
             const uint32_t lm = __float_as_uint(s_c[sub + lane].y);
@@ -211,10 +217,11 @@ __device__ __forceinline__ void blend_block(const Splat* __restrict__ splats, co
     uint32_t tile;
     if (!tile_of_block(blockIdx.x, work, p.num_tiles, tile)) return;
     if (tile >= (uint32_t)p.num_tiles) return;
-    __shared__ float4 s_a[kTileBatch], s_b[kTileBatch];
-    __shared__ float2 s_c[kBatchSlots];
-    __shared__ CutRec s_cut[kTileBatch];
-    __shared__ float2 s_ext[kRegion ? kTileBatch * (kMaxPlanes - 1) : 1];
+    constexpr int kB = batch_of<kRegion>();
+    __shared__ float4 s_a[kB], s_b[kB];
+    __shared__ float2 s_c[slots_of<kRegion>()];
+    __shared__ CutRec s_cut[kB];
+    __shared__ float2 s_ext[kRegion ? kB * (kMaxPlanes - 1) : 1];
     __shared__ float2 s_rate[kMaxPlanes - 1];
     if (kRegion) {
         // the further planes' per-frame rates; the first batch's barrier orders them before any visit
@@ -235,10 +242,10 @@ void blend_kernel(const Splat* __restrict__ splats, const RayRec* __restrict__ r
     blend_block<kWalked, false>(splats, rays, nullptr, vals, ranges, work, p, image, final_T, n_contrib, n_walked);
 }
 
-// Clip-region variant (p.plane_count > 1): more LDS per workgroup for the
-// further planes' terms, fewer workgroups per CU.
+// Clip-region variant (p.plane_count > 1): the further planes' terms staged
+// too, in 128-entry batches, still 8 workgroups per CU.
 template <bool kWalked>
-__global__ __launch_bounds__(kBlendThreads)
+__global__ __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(8)))
 void blend_region_kernel(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
                          const float2* __restrict__ ray_ext, const uint32_t* __restrict__ vals,
                          const uint2* __restrict__ ranges, const uint32_t* __restrict__ work,

@@ -34,7 +34,7 @@ METRIC = "RaRa-clipped FPS @1080p/1M Gaussians; served p50/p99 latency vs plain"
 FLOPS_EVAL = 24
 FLOPS_CUT = 56
 PEAK_FP32 = 157.3e12          # MI355X FP32 vector, packed FMA
-PEAK_FP32_UNPACKED = 78.6e12  # without packed FP32 (this build does not emit it)
+PEAK_FP32_UNPACKED = 78.6e12  # without packed FP32 (the kernels are compiled without it)
 PEAK_HBM = 8.0e12
 
 # frames in flight in the timed sweep (renderer.FramePipeline): one stream and
@@ -518,7 +518,7 @@ def diff_bench(reps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+        print(f"bench.py measures one GPU only: there is no multi-GPU path (asked for --gpus {args.gpus}); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -108,7 +108,16 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
 }
 
 // One workgroup per digit: exclusive scan of hist[d][0..tiles) in place and the
-// digit's total.  The item count is *num_items, or n_items without it.
+// digit's total.  The item count is *num_items, or n_items without it.  The
+// row is scanned in chunks of 4096 counts: coalesced loads (16 per thread, all
+// in flight) into LDS, a serial scan of 16 consecutive counts per thread (the
+// LDS rows are padded to 17 words, so the 64 lanes hit distinct banks), a
+// block scan of the thread totals, and coalesced stores.
+constexpr int kScanPer = 16;
+constexpr int kScanChunk = 256 * kScanPer;
+
+__device__ inline int scan_slot(int i) { return i + (i >> 4); }
+
 __global__ __launch_bounds__(256) void radix_scan_kernel(uint32_t* __restrict__ hist, int64_t stride,
                                                          const int64_t* __restrict__ num_items, int64_t n_items,
                                                          const int32_t* __restrict__ overflow,
@@ -118,27 +127,55 @@ __global__ __launch_bounds__(256) void radix_scan_kernel(uint32_t* __restrict__ 
     const int64_t P = num_items ? *num_items : n_items;
     const int64_t tiles = (P + kSortTile - 1) / kSortTile;
     uint32_t* row = hist + (int64_t)blockIdx.x * stride;
-    __shared__ uint32_t part[256];
-    const int t = threadIdx.x;
-    const int64_t per = (tiles + 255) / 256;
-    const int64_t lo = t * per, hi = lo + per < tiles ? lo + per : tiles;
-    uint32_t acc = 0;
-    for (int64_t k = lo; k < hi; ++k) acc += row[k];
-    part[t] = acc;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const uint32_t add = t >= off ? part[t - off] : 0u;
+    __shared__ uint32_t buf[kScanChunk + kScanChunk / kScanPer];
+    __shared__ uint32_t wave_tot[4];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t carry = 0;
+    for (int64_t c0 = 0; c0 < tiles; c0 += kScanChunk) {
+        const int m = (int)(tiles - c0 < kScanChunk ? tiles - c0 : kScanChunk);
+        uint32_t v[kScanPer];
+#pragma unroll
+        for (int j = 0; j < kScanPer; ++j) {
+            const int i = j * 256 + t;
+            v[j] = i < m ? row[c0 + i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kScanPer; ++j) buf[scan_slot(j * 256 + t)] = v[j];
         __syncthreads();
-        part[t] += add;
+        uint32_t acc = 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            v[k] = acc;
+            acc += buf[t * (kScanPer + 1) + k];
+        }
+        // inclusive scan of the thread totals within the wave, then across waves
+        uint32_t inc = acc;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t up = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += up;
+        }
+        if (lane == 63) wave_tot[wave] = inc;
         __syncthreads();
+        uint32_t before = carry, chunk = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            before += w < wave ? wave_tot[w] : 0u;
+            chunk += wave_tot[w];
+        }
+        const uint32_t excl = before + inc - acc;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) buf[t * (kScanPer + 1) + k] = excl + v[k];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kScanPer; ++j) {
+            const int i = j * 256 + t;
+            if (i < m) row[c0 + i] = buf[scan_slot(i)];
+        }
+        carry += chunk;
+        __syncthreads();   // buf and wave_tot are rewritten by the next chunk
     }
-    uint32_t run = t > 0 ? part[t - 1] : 0u;
-    for (int64_t k = lo; k < hi; ++k) {
-        const uint32_t v = row[k];
-        row[k] = run;
-        run += v;
-    }
-    if (t == 255) digit_totals[blockIdx.x] = part[255];
+    if (t == 0) digit_totals[blockIdx.x] = carry;
 }
 
 // kFinal: keys_out is ignored and the 64-bit (key << 32 | depth bits of the

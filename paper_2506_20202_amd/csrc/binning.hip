@@ -73,8 +73,13 @@ __global__ __launch_bounds__(256) void chunk_sum_kernel(const uint32_t* __restri
                                                         const int64_t* __restrict__ count,
                                                         uint32_t* __restrict__ chunk_sums)
 {
+    const int64_t drawn = *count;
+    if ((int64_t)blockIdx.x * kScanBlock >= drawn) {   // past the drawn Gaussians: uniform
+        if (threadIdx.x == 0) chunk_sums[blockIdx.x] = 0u;
+        return;
+    }
     const int64_t k = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
-    const uint32_t v = k < *count ? tt[order[k]] : 0u;
+    const uint32_t v = k < drawn ? tt[order[k]] : 0u;
     uint32_t total;
     block_ballot_scan(v, total);
     if (threadIdx.x == 0) chunk_sums[blockIdx.x] = total;
@@ -110,22 +115,34 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ 
     __shared__ uint64_t s_part[kScanBlock / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t b = blockIdx.x;
-    // pairs before this chunk
+    const bool last_block = b == (int64_t)gridDim.x - 1;
+    const int64_t drawn = *count;
+    // a chunk past the drawn Gaussians emits nothing; the last workgroup still
+    // sums every chunk for the pair count
+    if (b * kScanBlock >= drawn && !last_block) return;
+    // pairs before this chunk: 8 loads per thread in flight per step
     uint64_t before = 0;
-    {
-        for (int64_t c = tid; c < b; c += kScanBlock) before += chunk_sums[c];
+    for (int64_t c0 = 0; c0 < b; c0 += 8 * kScanBlock) {
+        uint32_t x[8];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) before += __shfl_xor(before, off, 64);
+        for (int u = 0; u < 8; ++u) {
+            const int64_t c = c0 + u * kScanBlock + tid;
+            x[u] = c < b ? chunk_sums[c] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) before += x[u];
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) before += __shfl_xor(before, off, 64);
     const int64_t k = b * kScanBlock + tid;
-    const bool valid = k < *count;
+    const bool valid = k < drawn;
     const uint32_t id = valid ? order[k] : 0u;
     const uint32_t v = valid ? tt[id] : 0u;
     if (lane == 0) s_part[wave] = before;
     uint32_t total;
     const uint32_t pre = block_ballot_scan(v, total);   // its barrier orders s_part
     const uint64_t base64 = s_part[0] + s_part[1] + s_part[2] + s_part[3];
-    if (b == (int64_t)gridDim.x - 1 && tid == 0) {
+    if (last_block && tid == 0) {
         const uint64_t P = base64 + total;
         *num_pairs = (int64_t)P;
         *overflow = P > (uint64_t)cap ? 1 : 0;

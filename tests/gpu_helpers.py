@@ -8,6 +8,7 @@ import torch
 from paper_2506_20202_amd import renderer as R
 
 TILE = 16
+HEAVY_LIST = 1536   # lists of at least this many entries are scheduled first
 
 
 def gpu_frame(scene, cam, plane, bg=(0.0, 0.0, 0.0), capacity=None, dscene=None):
@@ -31,6 +32,7 @@ def collect(fr, out, n):
         keys=fr.bins.keys[:P].cpu().numpy().view(np.uint64),
         vals=fr.bins.vals[:P].cpu().numpy().view(np.uint32),
         ranges=fr.bins.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2),
+        work=fr.bins.work.cpu().numpy().view(np.uint32),
         image=out.image.cpu().numpy().astype(np.float64),
         final_T=out.final_T.cpu().numpy(),
         n_contrib=out.n_contrib.cpu().numpy(),
@@ -96,6 +98,17 @@ def check_ranges(g):
     exp = np.where((counts > 0)[:, None], np.stack([starts, starts + counts], 1), 0)
     bad = np.nonzero(np.any(rng != exp, axis=1))[0]
     assert len(bad) == 0, f"{len(bad)} tile ranges wrong, first {bad[:5]}: {rng[bad[:3]].tolist()} vs {exp[bad[:3]].tolist()}"
+    check_schedule(g["work"], counts)
+
+
+def check_schedule(work, counts):
+    """The blend schedule: the tiles with long lists in tile order, then the
+    others in tile order, then their number."""
+    T = len(counts)
+    heavy = np.nonzero(counts >= HEAVY_LIST)[0]
+    light = np.nonzero(counts < HEAVY_LIST)[0]
+    assert int(work[T]) == len(heavy), (int(work[T]), len(heavy))
+    np.testing.assert_array_equal(work[:T].astype(np.int64), np.concatenate([heavy, light]))
 
 
 def check_lists(g, o, tiles=None, skip=()):

@@ -99,6 +99,7 @@ def test_plane_behind_scene_gives_background():
     g = H.gpu_frame(sc, cam, back, bg=(0.25, 0.5, 0.75))
     assert (g["label"] == 0).all() and g["P"] == 0
     assert not g["ranges"].any()
+    H.check_schedule(g["work"], np.zeros(len(g["ranges"]), np.int64))
     np.testing.assert_array_equal(g["image"], np.broadcast_to(np.array([0.25, 0.5, 0.75], np.float32)[:, None, None],
                                                               g["image"].shape).astype(np.float64))
 
@@ -118,6 +119,7 @@ def test_empty_scene():
     g = H.gpu_frame(sc, scenes.tiny_camera(), scenes.tiny_plane(0), bg=(0.1, 0.1, 0.1))
     assert g["P"] == 0
     assert not g["ranges"].any()
+    H.check_schedule(g["work"], np.zeros(len(g["ranges"]), np.int64))
     np.testing.assert_allclose(g["image"], 0.1, atol=1e-7)
 
 
@@ -151,6 +153,7 @@ def test_capacity_overflow_reported_and_frame_untouched():
     assert int(fr.bins.num_pairs.item()) == P
     assert (fr.out.image == -7.0).all()
     assert not fr.bins.ranges.any()   # no tile gets a list from an overflowing frame
+    H.check_schedule(fr.bins.work.cpu().numpy().view(np.uint32), np.zeros(fr.bins.ranges.numel() // 2, np.int64))
     out = R.render_checked(ds, fr, cam, pl)
     assert int(fr.bins.overflow.item()) == 0 and fr.capacity >= P
     H.check_lists(H.collect(fr, out, sc.n), o)

@@ -127,10 +127,10 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ 
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int64_t c = c0 + u * kScanBlock + tid;
-            x[u] = c < b ? chunk_sums[c] : 0u;
+            x[u] = chunk_sums[c < b ? c : b - 1];   // unconditional (b >= 1 here): no load waits for another
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) before += x[u];
+        for (int u = 0; u < 8; ++u) before += c0 + u * kScanBlock + tid < b ? x[u] : 0u;
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) before += __shfl_xor(before, off, 64);
@@ -175,87 +175,100 @@ __global__ __launch_bounds__(256) void ranges_clear_kernel(uint32_t* __restrict_
     if (t < num_tiles) reinterpret_cast<uint2*>(ranges)[t] = make_uint2(0u, 0u);
 }
 
-// Exclusive sum of v over a 1024-thread block (16 waves) and the block total.
-__device__ inline uint32_t block_sum_scan(uint32_t v, uint32_t& total, uint32_t* wave_tot)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t incl = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t o = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += o;
-    }
-    if (lane == 63) wave_tot[wave] = incl;
-    __syncthreads();
-    uint32_t before = 0, tot = 0;
-    for (int w = 0; w < 16; ++w) {
-        const uint32_t c = wave_tot[w];
-        before += w < wave ? c : 0u;
-        tot += c;
-    }
-    __syncthreads();
-    total = tot;
-    return before + incl - v;
-}
-
 // Blend schedule: the tiles whose list has at least kHeavyList entries come
 // first, so that the longest walks start earliest, then the others, each
 // group in tile order: work[h] = h-th long-list tile, work[H + l] = l-th other
-// tile, work[T] = H.  One workgroup; thread t owns a contiguous run of tiles,
-// so one block scan places every tile (deterministic).  Tiles without pairs
-// (end 0) get the empty range (0, 0).
-__device__ inline uint2 final_range(uint2* ranges, int t)
-{
-    uint2 r = ranges[t];
-    if (r.y == 0u && r.x != 0u) {
-        r = make_uint2(0u, 0u);
-        ranges[t] = r;
-    }
-    return r;
-}
+// tile, work[T] = H.  Tiles without pairs (end 0) get the empty range (0, 0).
+//
+// One 1024-thread workgroup, so all of it runs on one CU: the accesses are
+// kept coalesced (thread t takes tiles t, t + 1024, ... of each 8192-tile
+// block) and the long-list flags are counted with wave ballots.  A tile's
+// long-list rank is the long-list count of the blocks before it, of the rounds
+// of 1024 tiles before it in its block, of the waves before it in its round,
+// and of the lanes before it in its wave.  A first sweep counts H (the ranges
+// of the first block stay in registers), the second writes the ranges and
+// the schedule.
+__device__ inline bool plan_heavy(uint2 r) { return r.y != 0u && r.y - r.x >= kHeavyList; }
 
 __global__ __launch_bounds__(1024) void plan_kernel(uint2* __restrict__ ranges, int num_tiles,
                                                     uint32_t* __restrict__ work)
 {
-    constexpr int kRegTiles = 8;   // tiles per thread kept in registers (T <= 8192)
-    __shared__ uint32_t wave_tot[16];
-    const int tid = threadIdx.x;
-    const int per = (num_tiles + 1023) / 1024;
-    const int t0 = tid * per < num_tiles ? tid * per : num_tiles;
-    const int t1 = t0 + per < num_tiles ? t0 + per : num_tiles;
-    // long-list flags of this thread's run: all loads issued at once when they fit
-    uint32_t hbits = 0u;
-    if (per <= kRegTiles) {
-        uint2 r[kRegTiles];
+    constexpr int kRounds = 8, kBlock = kRounds * 1024;
+    __shared__ uint32_t s_cnt[kRounds * 16];   // long-list count per (round, wave), then its exclusive prefix
+    __shared__ uint32_t s_tot[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    auto load_block = [&](int b0, uint2* r) {
 #pragma unroll
-        for (int k = 0; k < kRegTiles; ++k) r[k] = t0 + k < t1 ? ranges[t0 + k] : make_uint2(0u, 0u);
-#pragma unroll
-        for (int k = 0; k < kRegTiles; ++k) {
-            if (r[k].y == 0u && r[k].x != 0u) {   // no pair: the empty range (0, 0)
-                r[k] = make_uint2(0u, 0u);
-                ranges[t0 + k] = r[k];
-            }
-            hbits |= (r[k].y - r[k].x >= kHeavyList ? 1u : 0u) << k;
+        for (int j = 0; j < kRounds; ++j) {
+            const int t = b0 + j * 1024 + tid;
+            r[j] = ranges[t < num_tiles ? t : num_tiles - 1];
+            if (t >= num_tiles) r[j] = make_uint2(0u, 0u);
         }
-    }
-    auto heavy = [&](int t) {
-        if (per <= kRegTiles) return ((hbits >> (t - t0)) & 1u) != 0u;
-        const uint2 r = ranges[t];
-        return r.y - r.x >= kHeavyList;
     };
-    if (per > kRegTiles) {
-        for (int t = t0; t < t1; ++t) final_range(ranges, t);
-    }
+    // sweep 1: H
+    uint2 r0[kRounds];
+    load_block(0, r0);
     uint32_t hc = 0;
-    for (int t = t0; t < t1; ++t) hc += heavy(t) ? 1u : 0u;
-    uint32_t H;
-    const uint32_t hx = block_sum_scan(hc, H, wave_tot);
-    uint32_t h = hx, l = (uint32_t)t0 - hx;   // other tiles before t0
-    for (int t = t0; t < t1; ++t) {
-        if (heavy(t))
-            work[h++] = (uint32_t)t;
-        else
-            work[H + l++] = (uint32_t)t;
+#pragma unroll
+    for (int j = 0; j < kRounds; ++j) hc += plan_heavy(r0[j]) ? 1u : 0u;
+    for (int b0 = kBlock; b0 < num_tiles; b0 += kBlock) {
+        uint2 r[kRounds];
+        load_block(b0, r);
+#pragma unroll
+        for (int j = 0; j < kRounds; ++j) hc += plan_heavy(r[j]) ? 1u : 0u;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) hc += __shfl_xor(hc, off, 64);
+    if (lane == 0) s_tot[wave] = hc;
+    __syncthreads();
+    uint32_t H = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) H += s_tot[w];
+    // sweep 2: ranges and positions, block by block
+    uint32_t carry = 0;   // long-list tiles in the blocks before
+    for (int b0 = 0; b0 < num_tiles; b0 += kBlock) {
+        uint2 r[kRounds];
+        if (b0 == 0) {
+#pragma unroll
+            for (int j = 0; j < kRounds; ++j) r[j] = r0[j];
+        } else {
+            load_block(b0, r);
+        }
+        uint64_t m[kRounds];
+#pragma unroll
+        for (int j = 0; j < kRounds; ++j) {
+            m[j] = __ballot(plan_heavy(r[j]));
+            if (lane == 0) s_cnt[j * 16 + wave] = (uint32_t)__popcll(m[j]);
+        }
+        __syncthreads();
+        if (wave == 0) {   // exclusive prefix of the 128 counts in (round, wave) order, two per lane
+            const uint32_t c0 = s_cnt[2 * lane], c1 = s_cnt[2 * lane + 1];
+            uint32_t incl = c0 + c1;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t o = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += o;
+            }
+            const uint32_t ex = incl - c0 - c1;
+            s_cnt[2 * lane] = ex;
+            s_cnt[2 * lane + 1] = ex + c0;
+            if (lane == 63) s_tot[0] = incl;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kRounds; ++j) {
+            const int t = b0 + j * 1024 + tid;
+            if (t < num_tiles) {
+                const bool heavy = ((m[j] >> lane) & 1ull) != 0ull;
+                const uint32_t hb = carry + s_cnt[j * 16 + wave] +
+                                    __builtin_amdgcn_mbcnt_hi((uint32_t)(m[j] >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m[j], 0u));
+                ranges[t] = r[j].y == 0u ? make_uint2(0u, 0u) : r[j];
+                work[heavy ? hb : H + (uint32_t)t - hb] = (uint32_t)t;
+            }
+        }
+        carry += s_tot[0];
+        __syncthreads();   // s_cnt and s_tot are rewritten by the next block
     }
     if (tid == 0) work[num_tiles] = H;
 }

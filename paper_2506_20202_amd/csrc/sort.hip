@@ -84,10 +84,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
         const int64_t idx = wbase + r * 64 + lane;
         const bool in = idx < P;
         if (kFilter) {
-            const uint32_t t = in ? tt[idx] : 0u;
-            const uint32_t k = in ? __float_as_uint(depth[idx]) : 0u;
-            valid[r] = t > 0u;
-            key[r] = k;
+            // unconditional loads (a clamped index; P >= 1 here), so that none waits for another
+            const int64_t ic = in ? idx : P - 1;
+            const uint32_t t = tt[ic];
+            const uint32_t k = __float_as_uint(depth[ic]);
+            valid[r] = in && t > 0u;
+            key[r] = in ? k : 0u;
         } else {
             valid[r] = in;
             key[r] = in ? keys[idx] : 0u;
@@ -224,10 +226,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         const bool in = idx < P;
         bool valid;
         if (kFilter) {
-            const uint32_t t = in ? tt[idx] : 0u;
-            key[r] = in ? __float_as_uint(depth[idx]) : 0u;
+            const int64_t ic = in ? idx : P - 1;   // unconditional loads, as in the upsweep
+            const uint32_t t = tt[ic];
+            const uint32_t k = __float_as_uint(depth[ic]);
+            key[r] = in ? k : 0u;
             val[r] = (uint32_t)idx;
-            valid = t > 0u;
+            valid = in && t > 0u;
         } else {
             key[r] = in ? keys_in[idx] : 0u;
             val[r] = in ? vals_in[idx] : 0u;

@@ -222,9 +222,9 @@ __global__ __launch_bounds__(256) void preprocess_fp_kernel(GaussPtrs g, const F
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n) return;
-    const CamParams cam = fp->cam;
-    const PlaneParams pl = fp->plane;
-    preprocess_one<kDeg>(g, cam, pl, out, i);
+    // read through the pointer: a private copy of the plane arrays, indexed
+    // by the plane number, would live in scratch memory
+    preprocess_one<kDeg>(g, fp->cam, fp->plane, out, i);
 }
 
 }  // namespace

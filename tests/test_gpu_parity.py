@@ -451,3 +451,20 @@ def test_pipelined_general_1080p_equals_alone():
     pipe.close()
     for k, (a, b) in enumerate(zip(got, refs)):
         assert torch.equal(a, b), f"frame {k} differs"
+
+
+def test_schedule_over_many_tiles():
+    """A frame of 147 x 147 = 21609 tiles: the plan kernel takes three blocks of
+    8192 tiles, and long lists fall in more than one of them.  Ranges and the
+    schedule are checked against the sorted keys (no oracle render)."""
+    sc = scenes.small_scene(5, n=40_000, spread=0.8, logscale_mean=-3.0)
+    cam = scenes.tiny_camera(2352, 2352)
+    off = scenes.Plane(scenes.tiny_plane(5).n, 0.0, False)
+    g = H.gpu_frame(sc, cam, off, capacity=1 << 24)
+    assert g["overflow"] == 0
+    H.check_ranges(g)   # also the schedule
+    lens = g["ranges"][:, 1] - g["ranges"][:, 0]
+    long_tiles = np.nonzero(lens >= H.HEAVY_LIST)[0]
+    print(f"P={g['P']} tiles={len(lens)} long={len(long_tiles)}", flush=True)
+    assert len(lens) == 147 * 147
+    assert len(np.unique(long_tiles // 8192)) >= 2

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
     __syncthreads();
     const int64_t wbase = base + (int64_t)wave * kWaveKeys;
     // every load of the wave first (the filter's depth and tile-count loads
-    // together), then the ballot counts
+    // together), then the counts
     uint32_t key[kSortItems];
     bool valid[kSortItems];
 #pragma unroll
@@ -95,12 +95,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
             key[r] = in ? keys[idx] : 0u;
         }
     }
+    // a histogram needs no ranks: one LDS atomic per key into the wave's own row
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint32_t d = (key[r] >> shift) & (kRadix - 1);
-        const uint64_t peers = match_digit(d, valid[r]);
-        if (valid[r] && lanes_below(peers) == 0) counts[wave][d] += (uint32_t)__popcll(peers);
-    }
+    for (int r = 0; r < kSortItems; ++r)
+        if (valid[r]) atomicAdd(&counts[wave][(key[r] >> shift) & (kRadix - 1)], 1u);
     __syncthreads();
     for (int d = threadIdx.x; d < kRadix; d += kSortThreads) {
         uint32_t t = 0;

@@ -47,7 +47,9 @@ PIPE_STREAMS = 3
 # counters read for a plain device copy of known size.  Reported only while
 # the blend's sources are the ones the counters were taken on.
 COUNTER_FILE = os.path.join(ROOT, "profiles", "blend_counters_general_1080p.txt")
-BLEND_SOURCES = ("paper_2506_20202_amd/csrc/blend.hip", "paper_2506_20202_amd/csrc/blend_common.h")
+# the blend's sources, and the header holding its schedule and batch constants
+BLEND_SOURCES = ("paper_2506_20202_amd/csrc/blend.hip", "paper_2506_20202_amd/csrc/blend_common.h",
+                 "paper_2506_20202_amd/csrc/rara_internal.h")
 
 
 def blend_source_hash():

@@ -104,7 +104,7 @@ struct FrameParams {
 // ---- blend work list --------------------------------------------------------
 // Tiles whose list holds at least kHeavyList entries are blended first
 // (work[] has tiles + 1 entries, see plan_kernel).
-constexpr uint32_t kHeavyList = 1536;
+constexpr uint32_t kHeavyList = 1024;
 // forward blend: one workgroup per tile, both tile groups padded to 8
 // (the non-split tiles are dealt to the XCDs in chunks of kDealChunk: the
 // fullest XCD holds up to 2 kDealChunk more than an even share)

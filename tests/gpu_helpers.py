@@ -8,7 +8,7 @@ import torch
 from paper_2506_20202_amd import renderer as R
 
 TILE = 16
-HEAVY_LIST = 1536   # lists of at least this many entries are scheduled first
+HEAVY_LIST = 1024   # lists of at least this many entries are scheduled first
 
 
 def gpu_frame(scene, cam, plane, bg=(0.0, 0.0, 0.0), capacity=None, dscene=None):

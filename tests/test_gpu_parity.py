@@ -293,7 +293,7 @@ def test_box_region_large_gaussians():
 
 
 # Long lists: thousands of overlapping Gaussians over a few tiles, most of them
-# CUTOFF, so tiles hold 2000-7600 entries (the blend dispatches tiles of 1536
+# CUTOFF, so tiles hold 2000-7600 entries (the blend dispatches tiles of 1024
 # entries or more first, each XCD taking a run of them).  With that many
 # entries per pixel, many pixels carry an oracle event (an alpha
 # within 0.1 % of 1/255 or a grazing ray); the rest are checked to the usual bar.
@@ -317,9 +317,9 @@ def _dense_check(sc, cam, pl, tiles=None, min_long=1):
     excl = oracle.tile_mask(cam, rects)
     err, flagged, _ = H.image_error(g["image"], o, exclude=excl, region=region)
     ok = (o["flags"] == 0) & ~excl & region
-    print(f"n={sc.n} {cam.width}x{cam.height} P={g['P']} long={(lens >= 1536).sum()} max_len={lens.max()} "
+    print(f"n={sc.n} {cam.width}x{cam.height} P={g['P']} long={(lens >= H.HEAVY_LIST).sum()} max_len={lens.max()} "
           f"max_err={err:.2e} flagged={flagged:.4f} checked={ok.sum()} mismatched={len(bad)}", flush=True)
-    assert (lens >= 1536).sum() >= min_long
+    assert (lens >= H.HEAVY_LIST).sum() >= min_long
     assert ok.sum() >= 0.25 * region.sum()
     assert err <= TOL
     np.testing.assert_array_equal(g["n_contrib"][ok], o["n_contrib"][ok])

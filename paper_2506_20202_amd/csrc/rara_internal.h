@@ -114,7 +114,7 @@ inline int64_t tiles_grid(int64_t tiles) { return tiles + 16 + 16 * (int64_t)kDe
 // ---- bin/sort workspace carve-up -------------------------------------------
 constexpr int kScanBlock = 256;      // Gaussians per scan chunk
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 4;        // keys per thread per sort tile
+constexpr int kSortItems = 8;        // keys per thread per sort tile
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;

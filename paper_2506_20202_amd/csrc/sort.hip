@@ -4,7 +4,7 @@
 // The last tile pass writes the 64-bit (tile << 32 | float32 depth bits) keys.
 //
 // Each pass is reduce-then-scan, with no inter-workgroup waiting:
-//   upsweep  - per 1024-key tile, a 256-bin digit histogram;
+//   upsweep  - per 2048-key tile, a 256-bin digit histogram;
 //   scan     - one workgroup per digit scans that digit's counts over tiles;
 //   scatter  - each tile ranks its keys stably in LDS (per-wave ballot match
 //              on the 8 digit bits, wave-private running counters), stages

@@ -79,7 +79,7 @@ def blend_traffic():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=256)
+    ap.add_argument("--steps", type=int, default=160)
     ap.add_argument("--reps", type=int, default=5, help="timed sweeps per variant; the median is reported")
     ap.add_argument("--no-secondary", action="store_true", help="skip the strand workload")
     ap.add_argument("--warmup", type=int, default=16)
@@ -88,6 +88,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the copy and FMA-loop peak measurements")
     ap.add_argument("--serve-requests", type=int, default=240)
     ap.add_argument("--serve-load", type=float, default=0.5, help="arrival rate as a fraction of saturation")
     ap.add_argument("--serve-budget-gib", type=float, default=32.0,
@@ -102,23 +103,39 @@ def parse():
 
 
 def workload(name):
+    """Scene, frame grid (grid[view][offset] = (camera, plane)) and description."""
     from paper_2506_20202_amd import scenes
     if name == "general":
         sc = scenes.general_scene(1)
         cams = scenes.general_views()
         planes = scenes.plane_sweep(sc, scenes.general_plane_normal(1), count=16)
-        frames = [(cams[v], planes[o]) for o in range(16) for v in range(16)]
+        grid = [[(cams[v], planes[o]) for o in range(16)] for v in range(16)]
         desc = {"workload": "general scene, 1,000,000 Gaussians (64 clusters), SH3, 1920x1080, "
                             "16 orbit views x 16 plane offsets", "gaussians": sc.n, "width": 1920, "height": 1080,
                 "views": 16, "plane_offsets": 16}
     else:
         sc = scenes.strand_scene(2)
         cams = scenes.strand_views()
-        frames = [(cams[v], p) for v in range(8) for p in scenes.strand_planes(v)]
+        grid = [[(cams[v], p) for p in scenes.strand_planes(v)] for v in range(8)]
         desc = {"workload": "strand scene, 100,000 strands x 32 = 3,200,000 Gaussians, SH1, 1024x1024, "
                             "8 views x 4 oblique planes", "gaussians": sc.n, "width": 1024, "height": 1024,
                 "views": 8, "plane_offsets": 4}
-    return sc, frames, desc
+    return sc, grid, desc
+
+
+def clip_order(clipping):
+    """Order of the timed frames.  ``clipping[v]`` lists the plane offsets that
+    clip in view v (Sec. 4.2's protocol sweeps a plane through the scene; a
+    frame clips when the plane leaves some Gaussians CUTOFF and some
+    INVISIBLE).  Frame i takes view v = i mod V and, with m = i div V, the
+    offset clipping[v][(m + v) mod K_v]: every prefix strides views and
+    offsets alike, and V * max(K_v) frames visit every clipping (view,
+    offset) pair (each exactly once when all K_v are equal)."""
+    V = len(clipping)
+    if V == 0 or any(len(c) == 0 for c in clipping):
+        raise ValueError("every view needs at least one clipping offset")
+    K = max(len(c) for c in clipping)
+    return [(i % V, clipping[i % V][(i // V + i % V) % len(clipping[i % V])]) for i in range(V * K)]
 
 
 def count_evals(fr, n):
@@ -143,6 +160,28 @@ def count_evals(fr, n):
     start = ranges[tile, 0]
     Ecut = int((csum[start + walked] - csum[start]).sum().item())
     return E, Ecut
+
+
+def preprocess_bytes(n, sh_degree, live, drawn, cut_drawn):
+    """Algorithmic HBM bytes of one preprocess launch: mean and scale (24 B),
+    the label (1 B) and tiles_touched (4 B) of every Gaussian; the quaternion
+    (16 B) of every Gaussian that is not INVISIBLE; opacity (4 B), SH
+    coefficients (12 (D+1)^2 B) and the splat record, depth and rectangle
+    (60 B) of every drawn one; the 48 B ray record of a drawn CUTOFF one."""
+    return 29 * n + 16 * live + (4 + 12 * (sh_degree + 1) ** 2 + 60) * drawn + 48 * cut_drawn
+
+
+def bin_sort_bytes(n, drawn, pairs, tiles):
+    """Algorithmic HBM bytes of rara_bin_sort as this sort runs it, each pass
+    reading and writing its keys and values once: the first depth pass reads
+    depth and tile count of every Gaussian and writes 8 B per drawn one, three
+    more depth passes move 16 B per drawn Gaussian, the emit reads 16 B per
+    drawn Gaussian and writes 8 B per pair, the tile passes move 16 B per pair
+    except the last, which writes only the values (12 B per pair), and the
+    ranges and schedule take 12 B per tile."""
+    tile_passes = max(1, (max(1, int(tiles - 1).bit_length()) + 7) // 8)
+    return (8 * n + 8 * drawn + 48 * drawn + 16 * drawn + 8 * pairs + 16 * pairs * (tile_passes - 1) + 12 * pairs
+            + 12 * tiles)
 
 
 def _omp_threads(k=None):
@@ -302,35 +341,115 @@ def serve_bench(args):
             "clipped": clipped, "plain": plain}
 
 
-def measure(sc, frames, args, reps, label):
-    """Frames per second over the frame list with clipping (RaRa), without a
-    plane (Original) and with hard clipping (Hard), each the median of `reps`
-    timed sweeps of args.steps frames, rendered two ways: one frame after the
-    other on one stream ("serial"), and with PIPE_STREAMS frames in flight
+def measured_peaks(reps: int = 5):
+    """Attainable peaks on this GPU (libpeak.so): a streaming copy of 1 GiB
+    (larger than the 256 MB Infinity Cache) and 8192 workgroups of
+    independent unpacked FP32 FMA chains, each the best of ``reps`` runs timed
+    with HIP events on the launch stream."""
+    import torch
+    from paper_2506_20202_amd import binding as B
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    sp = int(stream.cuda_stream)
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    out = torch.zeros(8192 * 256, dtype=torch.float32, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def best(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        return min(ts)
+
+    t_copy = best(lambda: B.peak_copy(dst.data_ptr(), src.data_ptr(), nbytes, 256 * 32, sp))
+    flops = [0.0]
+
+    def fma():
+        flops[0] = B.peak_fma(out.data_ptr(), 8192, 4096, sp)
+    t_fma = best(fma)
+    res = {"hbm_copy_gbs": 2 * nbytes / t_copy / 1e9, "hbm_copy_bytes": 2 * nbytes,
+           "fp32_fma_tflops": flops[0] / t_fma / 1e12,
+           "copy_frac_of_spec": 2 * nbytes / t_copy / PEAK_HBM,
+           "fma_frac_of_unpacked_spec": flops[0] / t_fma / PEAK_FP32_UNPACKED,
+           "note": "copy: 1 GiB read + 1 GiB written; FMA: unpacked v_fma_f32, 16 independent chains per lane"}
+    del src, dst, out
+    torch.cuda.empty_cache()
+    print(f"[bench] measured peaks: copy {res['hbm_copy_gbs']:.0f} GB/s, FMA {res['fp32_fma_tflops']:.1f} TFLOP/s",
+          file=sys.stderr, flush=True)
+    return res
+
+
+def scan_grid(ds, fr, grid):
+    """Preprocess + bin_sort of every frame of the grid (no blend; the pair
+    capacity of ``fr`` grows as needed): the largest pair count, the label
+    counts of each (view, offset) from the device's labels, and the timed
+    order over the frames that clip (``clip_order``)."""
+    import torch
+    from paper_2506_20202_amd import renderer as R
+    n = ds.n
+    maxP, labels = 0, {}
+    for v, row in enumerate(grid):
+        for o, (cam, pl) in enumerate(row):
+            R.enqueue_frame(ds, fr, cam, pl, stages=("pre", "bin"))
+            torch.cuda.synchronize()
+            P = int(fr.bins.num_pairs.item())
+            if int(fr.bins.overflow.item()):
+                fr.grow(max(int(P * 1.25) + 1024, fr.capacity * 2))
+                R.enqueue_frame(ds, fr, cam, pl, stages=("pre", "bin"))
+                torch.cuda.synchronize()
+                assert not int(fr.bins.overflow.item())
+            maxP = max(maxP, P)
+            cnt = torch.bincount(fr.proj.label[:n].to(torch.int64), minlength=3).cpu().tolist()
+            labels[(v, o)] = {"visible": cnt[1], "cutoff": cnt[2], "invisible": cnt[0]}
+    clipping = [[o for o in range(len(row)) if labels[(v, o)]["cutoff"] > 0 and labels[(v, o)]["invisible"] > 0]
+                for v, row in enumerate(grid)]
+    return maxP, labels, clip_order(clipping)
+
+
+def measure(sc, grid, args, reps, label):
+    """Frames per second with clipping (RaRa), without a plane (Original) and
+    with hard clipping (Hard), over the frames of ``grid`` that clip, in the
+    order of ``clip_order``: each the median of ``reps`` timed sweeps of
+    args.steps frames, rendered two ways: one frame after the other on one
+    stream ("serial"), and with PIPE_STREAMS frames in flight
     (renderer.FramePipeline: consecutive frames on their own streams overlap).
-    Per-stage times and work counts."""
+    The whole grid, non-clipping frames included, is timed too.  Per-stage
+    times and work counts over exactly the timed frames."""
     import torch
     from paper_2506_20202_amd import renderer as R
     dev = torch.device("cuda:0")
     ds = R.DeviceScene.from_scene(sc, dev)
-    W, H = frames[0][0].width, frames[0][0].height
+    V, O = len(grid), len(grid[0])
+    W, H = grid[0][0][0].width, grid[0][0][0].height
     stream = torch.cuda.current_stream(dev)
+    # capacity and labels from one pass over every frame (outside the timed region)
+    fr = R.Frame(sc.n, W, H, 8 * sc.n, dev, walked=False, pair_start=False, sorted_keys=False)
+    maxP, labels, order = scan_grid(ds, fr, grid)
+    frames = [grid[v][o] for v, o in order]
+    sweep = [grid[v][o] for o in range(O) for v in range(V)]
     variants = {"rara": frames,
                 "original": [(cam, dataclasses.replace(pl, enabled=0)) for cam, pl in frames],
                 "hard": [(cam, dataclasses.replace(pl, enabled=2)) for cam, pl in frames]}
     if args.no_plain:
         del variants["original"], variants["hard"]
-    # capacity from one pass over every frame (outside the timed region)
-    fr = R.Frame(sc.n, W, H, 8 * sc.n, dev, walked=False, pair_start=False, sorted_keys=False)
-    maxP = 0
     for name, fl in variants.items():
-        for cam, pl in (fl if name == "rara" else fl[:: max(1, len(fl) // 16)]):
-            R.render_checked(ds, fr, cam, pl)
-            maxP = max(maxP, int(fr.bins.num_pairs.item()))
+        if name != "rara":
+            for cam, pl in fl[:: max(1, len(fl) // 16)]:
+                R.render_checked(ds, fr, cam, pl)
+                maxP = max(maxP, int(fr.bins.num_pairs.item()))
     fr.grow(int(maxP * 1.05) + 4096)
     pipe = R.FramePipeline(ds, W, H, fr.capacity, streams=PIPE_STREAMS, walked=False)
     torch.cuda.synchronize()
-    print(f"[bench] {label}: max pairs {maxP}, capacity {fr.capacity}", file=sys.stderr, flush=True)
+    print(f"[bench] {label}: max pairs {maxP}, capacity {fr.capacity}, {len(order)} clipping frames "
+          f"of {V * O}", file=sys.stderr, flush=True)
 
     def run_serial(frame_list, k):
         for i in range(k):
@@ -346,40 +465,46 @@ def measure(sc, frames, args, reps, label):
 
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
-    def timed(run, fl, check):
+    def timed(run, fl, check, steps):
         run(fl, args.warmup)
         torch.cuda.synchronize()
         vals = []
         for _ in range(reps):
             torch.cuda.synchronize()
             ev0.record(stream)
-            run(fl, args.steps)
+            run(fl, steps)
             ev1.record(stream)
             torch.cuda.synchronize()
-            vals.append(args.steps / (ev0.elapsed_time(ev1) / 1e3))
+            vals.append(steps / (ev0.elapsed_time(ev1) / 1e3))
             assert not check()
         return {"median": float(np.median(vals)), "reps": vals}
 
     fps, fps_serial = {}, {}
     for name, fl in variants.items():
-        fps_serial[name] = timed(run_serial, fl, lambda: int(fr.bins.overflow.item()))
-        fps[name] = timed(run_pipe, fl, pipe.overflowed)
+        fps_serial[name] = timed(run_serial, fl, lambda: int(fr.bins.overflow.item()), args.steps)
+        fps[name] = timed(run_pipe, fl, pipe.overflowed, args.steps)
         print(f"[bench] {label} {name}: {fps[name]['median']:.1f} FPS pipelined, "
               f"{fps_serial[name]['median']:.1f} serial (medians of {reps})", file=sys.stderr, flush=True)
+    # the whole grid in sweep order, frames that clip nothing included
+    full_sweep = {"pipelined": timed(run_pipe, sweep, pipe.overflowed, len(sweep))["median"],
+                  "serial": timed(run_serial, sweep, lambda: int(fr.bins.overflow.item()), len(sweep))["median"],
+                  "frames": len(sweep)}
     pipe.close()
     del pipe
 
-    # per-stage times (HIP events on the launch stream) and work counts; the
-    # render (one blend launch) is timed over kRenderRepeat back-to-back
-    # launches on the same binned frame, so its figure is the kernel's own
-    # duration rather than that of an isolated launch.  The work counts come
-    # from one more launch into images with the n_walked output, untimed.
+    # per-stage times (HIP events on the launch stream) and work counts over
+    # the timed frames; the render (one blend launch) is timed over
+    # kRenderRepeat back-to-back launches on the same binned frame, so its
+    # figure is the kernel's own duration rather than that of an isolated
+    # launch.  The work counts come from one more launch into images with the
+    # n_walked output, untimed.
     kRenderRepeat = 4
     frw = R.Frame(sc.n, W, H, 1, dev, walked=True)
     frw.proj, frw.bins = fr.proj, fr.bins
     stage_ms = {"preprocess": 0.0, "bin_sort": 0.0, "render": 0.0}
-    E_tot, Ecut_tot, P_tot, n_live = 0, 0, 0, 0
-    nst = len(frames)
+    E_tot, Ecut_tot, P_tot, n_live, n_drawn, n_cut_drawn = 0, 0, 0, 0, 0, 0
+    bytes_pre, bytes_bin = 0, 0
+    nst = args.steps
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     for i in range(nst):
         cam, pl = frames[i % len(frames)]
@@ -400,16 +525,31 @@ def measure(sc, frames, args, reps, label):
         E_tot += E
         Ecut_tot += Ec
         P_tot += int(fr.bins.num_pairs.item())
-        n_live += int((fr.proj.label != 0).sum().item())
+        lab = fr.proj.label[: sc.n]
+        drawn = fr.proj.tiles_touched[: sc.n] != 0
+        n_live += int((lab != 0).sum().item())
+        n_drawn += int(drawn.sum().item())
+        n_cut_drawn += int((drawn & (lab == 2)).sum().item())
+        live_i, drawn_i = int((lab != 0).sum().item()), int(drawn.sum().item())
+        bytes_pre += preprocess_bytes(sc.n, sc.sh_degree, live_i, drawn_i, int((drawn & (lab == 2)).sum().item()))
+        bytes_bin += bin_sort_bytes(sc.n, drawn_i, int(fr.bins.num_pairs.item()), ((W + 15) // 16) * ((H + 15) // 16))
     for k in stage_ms:
         stage_ms[k] /= nst
     render_s = stage_ms["render"] / 1e3
     flops = (E_tot * FLOPS_EVAL + Ecut_tot * FLOPS_CUT) / nst
-    out = {"fps": fps, "fps_serial": fps_serial, "stage_ms": stage_ms, "pairs_per_frame": P_tot / nst,
-           "live_gaussians_per_frame": n_live / nst,
+    timed_pairs = sorted(set(order[i % len(order)] for i in range(nst)))
+    out = {"fps": fps, "fps_serial": fps_serial, "full_sweep": full_sweep, "stage_ms": stage_ms,
+           "pairs_per_frame": P_tot / nst, "live_gaussians_per_frame": n_live / nst,
+           "drawn_gaussians_per_frame": n_drawn / nst, "cutoff_drawn_per_frame": n_cut_drawn / nst,
            "evals_per_frame": E_tot / nst, "cutoff_evals_per_frame": Ecut_tot / nst,
            "geval_per_s": E_tot / nst / render_s / 1e9, "flops_per_launch": flops,
-           "blend_tflops": flops / render_s / 1e12, "pair_capacity": fr.capacity}
+           "blend_tflops": flops / render_s / 1e12, "pair_capacity": fr.capacity,
+           "preprocess_bytes_per_launch": bytes_pre / nst, "bin_sort_bytes_per_frame": bytes_bin / nst,
+           "timed_frames": [[v, o, labels[(v, o)]["cutoff"], labels[(v, o)]["invisible"]] for v, o in timed_pairs],
+           "timed_order_head": [list(order[i % len(order)]) for i in range(min(nst, 32))],
+           "clipping_frames": len(order), "grid_frames": V * O,
+           "labels_by_offset_view0": [[labels[(0, o)]["visible"], labels[(0, o)]["cutoff"],
+                                       labels[(0, o)]["invisible"]] for o in range(O)]}
     del fr, frw, ds
     torch.cuda.empty_cache()
     return out
@@ -423,10 +563,10 @@ def multilayer_workload():
     sc = scenes.multilayer_scene(32, per_shell=300_000, sh_degree=2)
     cams = [scenes.random_camera_on_sphere(rng, 5.0, 1024, 1024) for _ in range(8)]
     planes = [scenes.random_plane_through(rng, sc) for _ in range(4)]
-    frames = [(c, p) for c in cams for p in planes]
+    grid = [[(c, p) for p in planes] for c in cams]
     desc = {"workload": "multi-layer scene, 5 shells x 300,000 = 1,500,000 Gaussians, SH2, 1024x1024, "
                         "8 cameras x 4 planes", "gaussians": sc.n, "width": 1024, "height": 1024}
-    return sc, frames, desc
+    return sc, grid, desc
 
 
 def box_workload():
@@ -442,11 +582,11 @@ def box_workload():
     c = rng.uniform(-0.2, 0.2, 3)
     boxes = [scenes.box_region(c - h * np.array([1.0, 0.8, 0.9]), c + h * np.array([0.9, 1.0, 0.8]))
              for h in np.linspace(2.3, 0.5, 8)]
-    frames = [(cam, b) for cam in cams for b in boxes]
+    grid = [[(cam, b) for b in boxes] for cam in cams]
     desc = {"workload": "box clipping: multi-layer scene, 1,500,000 Gaussians, SH2, 1024x1024, 8 cameras x 8 "
                         "boxes (half-sizes 2.3 to 0.5 around a point near the centre)",
             "gaussians": sc.n, "width": 1024, "height": 1024}
-    return sc, frames, desc
+    return sc, grid, desc
 
 
 def diff_bench(reps):
@@ -528,24 +668,22 @@ def main():
 
     dev = torch.device("cuda:0")
     t_setup = time.perf_counter()
-    sc, frames, desc = workload(args.workload)
+    sc, grid, desc = workload(args.workload)
     print(f"[bench] scene n={sc.n} ready in {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
 
     if args.profile_steps:
-        # profiler runs: the capacity pass over every frame of the sweep (as in
-        # the timed run), then the frames asked for, in sweep order
+        # profiler runs: preprocess + bin_sort over every frame of the grid
+        # (capacity and labels, no blend), then warmup + profile_steps frames
+        # in the timed order over the frames that clip, as in the timed run
         ds = R.DeviceScene.from_scene(sc, dev)
-        W, H = frames[0][0].width, frames[0][0].height
-        pick = [frames[i % len(frames)] for i in range(args.warmup + args.profile_steps)]
+        W, H = grid[0][0][0].width, grid[0][0][0].height
         fr = R.Frame(sc.n, W, H, 8 * sc.n, dev, walked=False, pair_start=False, sorted_keys=False)
-        maxP = 0
-        for cam, pl in frames:
-            R.render_checked(ds, fr, cam, pl)
-            maxP = max(maxP, int(fr.bins.num_pairs.item()))
+        maxP, _, order = scan_grid(ds, fr, grid)
         fr.grow(int(maxP * 1.05) + 4096)
         torch.cuda.synchronize()
-        for cam, pl in pick:
-            R.enqueue_frame(ds, fr, cam, pl)
+        for i in range(args.warmup + args.profile_steps):
+            v, o = order[i % len(order)]
+            R.enqueue_frame(ds, fr, *grid[v][o])
         torch.cuda.synchronize()
         assert int(fr.bins.overflow.item()) == 0
         if args.calibrate_copy:
@@ -555,27 +693,47 @@ def main():
             dst.copy_(src)
             torch.cuda.synchronize()
         print(json.dumps({"profile_steps": args.profile_steps, "warmup": args.warmup, "pair_capacity": fr.capacity,
+                          "frames": [list(order[i % len(order)]) for i in range(args.warmup + args.profile_steps)],
                           "copy_bytes": (256 << 20) if args.calibrate_copy else 0}))
         return
 
-    main_m = measure(sc, frames, args, args.reps, args.workload)
+    main_m = measure(sc, grid, args, args.reps, args.workload)
     fps = main_m["fps"]["rara"]["median"]
     ms_per_step = 1e3 / fps
+    st = main_m["stage_ms"]
+    pre_gbs = main_m["preprocess_bytes_per_launch"] / (st["preprocess"] / 1e3) / 1e9
+    bin_gbs = main_m["bin_sort_bytes_per_frame"] / (st["bin_sort"] / 1e3) / 1e9
     roofline = {"bound": "alu", "kernel": "blend_kernel (rara_render)", "achieved": main_m["blend_tflops"],
                 "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": main_m["blend_tflops"] * 1e12 / PEAK_FP32,
                 "traffic": blend_traffic(), "flops_per_launch": main_m["flops_per_launch"],
                 "evals_per_launch": main_m["evals_per_frame"],
                 "cutoff_evals_per_launch": main_m["cutoff_evals_per_frame"],
-                "avg_launch_ms": main_m["stage_ms"]["render"],
-                "frac_of_unpacked_fp32": main_m["blend_tflops"] * 1e12 / PEAK_FP32_UNPACKED}
+                "avg_launch_ms": st["render"],
+                "frac_of_unpacked_fp32": main_m["blend_tflops"] * 1e12 / PEAK_FP32_UNPACKED,
+                "window": "the timed frames (every frame clips)",
+                "stages": {
+                    "preprocess": {"bound": "hbm", "unit": "GB/s", "achieved": pre_gbs, "peak": PEAK_HBM / 1e9,
+                                   "frac": pre_gbs * 1e9 / PEAK_HBM,
+                                   "bytes_per_launch": main_m["preprocess_bytes_per_launch"],
+                                   "avg_launch_ms": st["preprocess"]},
+                    "bin_sort": {"bound": "hbm", "unit": "GB/s", "achieved": bin_gbs, "peak": PEAK_HBM / 1e9,
+                                 "frac": bin_gbs * 1e9 / PEAK_HBM,
+                                 "bytes_per_frame": main_m["bin_sort_bytes_per_frame"],
+                                 "avg_frame_ms": st["bin_sort"], "note": "all kernels of rara_bin_sort, from the "
+                                 "first launch's start to the last one's end"}}}
+    peaks = measured_peaks() if not args.no_peaks else None
+    if peaks:
+        roofline["frac_of_measured_fp32"] = main_m["blend_tflops"] / peaks["fp32_fma_tflops"]
+        roofline["stages"]["preprocess"]["frac_of_measured_copy"] = pre_gbs / peaks["hbm_copy_gbs"]
+        roofline["stages"]["bin_sort"]["frac_of_measured_copy"] = bin_gbs / peaks["hbm_copy_gbs"]
 
     secondary = {}
     strand_case = None
     if args.workload == "general" and not args.no_secondary:
-        ssc, sframes, sdesc = workload("strands")
-        sm = measure(ssc, sframes, args, max(1, args.reps // 2), "strands")
+        ssc, sgrid, sdesc = workload("strands")
+        sm = measure(ssc, sgrid, args, max(1, args.reps // 2), "strands")
         secondary["strands"] = dict(sdesc, **sm)
-        strand_case = (ssc, sframes[1][0], sframes[1][1])
+        strand_case = (ssc, *sgrid[0][1])
         msc, mframes, mdesc = multilayer_workload()
         mm = measure(msc, mframes, args, max(1, args.reps // 2), "multilayer")
         secondary["multilayer"] = dict(mdesc, **mm)
@@ -590,8 +748,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        gcase = (sc, frames[8 * 16][0], frames[8 * 16][1]) if args.workload == "general" else \
-            (sc, frames[1][0], frames[1][1])
+        gcase = (sc, *grid[0][8]) if args.workload == "general" else (sc, *grid[0][1])
         cpu = cpu_baseline(gcase, strand_case, args.cpu_seconds)
         print(f"[bench] oracle: {cpu['value']:.4f} frames/s on {cpu['cores']} threads, "
               f"{cpu['single_core']['value']:.4f} on 1", file=sys.stderr, flush=True)
@@ -610,15 +767,26 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": dict(desc, parallelism="single GPU", pair_capacity=main_m["pair_capacity"],
                        timing=f"median of {args.reps} sweeps of {args.steps} frames, {PIPE_STREAMS} in flight "
-                              "(frame i on stream i mod 3)"),
+                              "(frame i on stream i mod 3); the frames are the (view, offset) pairs whose plane "
+                              "leaves Gaussians both CUTOFF and INVISIBLE, frame i taking view i mod V and "
+                              "the ((i div V + i mod V) mod K)-th such offset",
+                       clipping_frames=main_m["clipping_frames"], grid_frames=main_m["grid_frames"],
+                       timed_frames_view_offset_cutoff_invisible=main_m["timed_frames"],
+                       timed_order_head=main_m["timed_order_head"],
+                       labels_by_offset_view0_visible_cutoff_invisible=main_m["labels_by_offset_view0"]),
         "plain_fps": plain, "hard_fps": hard, "clipped_over_plain_frame_time": (plain / fps) if plain else None,
-        "table1_protocol": {"original_fps": plain, "hard_fps": hard, "rara_fps": fps},
+        "rara_over_hard_frame_time": (hard / fps) if hard else None,
+        "table1_protocol": {"original_fps": plain, "hard_fps": hard, "rara_fps": fps,
+                            "frames": "the timed clipping frames"},
+        "full_sweep": main_m["full_sweep"],
         "fps_reps": main_m["fps"]["rara"]["reps"],
         "serial": {k: v["median"] for k, v in main_m["fps_serial"].items()},
         "serial_ms_per_frame": 1e3 / main_m["fps_serial"]["rara"]["median"],
         "stage_ms": main_m["stage_ms"], "pairs_per_frame": main_m["pairs_per_frame"],
-        "live_gaussians_per_frame": main_m["live_gaussians_per_frame"], "geval_per_s": main_m["geval_per_s"],
-        "roofline": roofline, "cpu_baseline": cpu, "serving": serving, "secondary": secondary or None,
+        "live_gaussians_per_frame": main_m["live_gaussians_per_frame"],
+        "drawn_gaussians_per_frame": main_m["drawn_gaussians_per_frame"], "geval_per_s": main_m["geval_per_s"],
+        "roofline": roofline, "measured_peaks": peaks, "cpu_baseline": cpu, "serving": serving,
+        "secondary": secondary or None,
     }
     print(json.dumps(out))
 

@@ -227,9 +227,13 @@ rara_status rara_preprocess(const rara_gaussians* g, const rara_camera* cam, con
  * bits, and per-tile ranges.  Needs `ws_bytes` >= rara_workspace_bytes(
  * RARA_WS_BIN_SORT, n, pair_capacity, W, H) bytes of device workspace.
  * Overflow: if the frame has more than pair_capacity pairs, *num_pairs holds
- * the required count, *overflow is 1, no pair is written and rara_render
- * leaves its outputs untouched; the caller checks after synchronising and
- * retries with a larger capacity.
+ * the required count and *overflow is 1.  The sorted pairs, ranges and
+ * schedule are then not produced, and the contents of keys, vals, ranges,
+ * work, pair_start and the workspace are unspecified (pairs that fit may
+ * have been written).  rara_render leaves its outputs untouched and
+ * rara_render_backward writes zero gradients for such a frame (both check the
+ * flag on the device); the caller checks after synchronising and retries
+ * with a larger capacity.
  * Errors: RARA_ERR_INVALID for null pointers, n < 0, pair_capacity outside
  * [1, 2^31), or a workspace that is too small. */
 rara_status rara_bin_sort(const rara_projected* proj, int64_t n, const rara_camera* cam, int64_t pair_capacity,
@@ -265,6 +269,8 @@ rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned
  * per-Gaussian atomics are used and repeated runs give identical gradients
  * except for the plane (a few per-tile float atomics).  Every array of *grads
  * is overwritten (Gaussians that were not drawn get zero).
+ * A frame whose overflow flag is set gets zero for every gradient, the
+ * plane's included (checked on the device; no pair slot is read).
  * Errors: as rara_render, plus RARA_ERR_INVALID for a short workspace, a
  * pair_capacity outside [1, 2^30), null gradient arrays or a null
  * bins->pair_start. */
@@ -285,9 +291,9 @@ rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam
  * image size (a launch with another size is rejected); its pose only serves
  * the capture.  n_walked may be NULL.  The handle owns a HIP graph, a
  * FrameParams-sized device block, pinned staging memory and two events.
- * Launches of one handle must go to one stream (each replay overwrites the
- * same outputs); a launch waits on the host only until the previous launch's
- * parameter copy has run.  rara_frame_graph_destroy waits for the last replay
+ * Each replay overwrites the same outputs; a launch on another stream first
+ * waits (on the device) for the previous replay of the handle to finish, and
+ * on the host only until the previous launch's parameter copy has run.  rara_frame_graph_destroy waits for the last replay
  * to finish before it frees anything.  Errors: RARA_ERR_INVALID for bad or
  * mismatched arguments (n must be > 0), RARA_ERR_UNSUPPORTED for an SH degree
  * above 3 or more than 65535 tile columns or rows, RARA_ERR_HIP if an

@@ -189,3 +189,41 @@ def frame_graph_launch(handle: int, cam: Camera, plane: Plane, bg, stream: int):
 def frame_graph_destroy(handle: int):
     if handle:
         lib().rara_frame_graph_destroy(_P(handle))
+
+
+# ---- attainable-peak probes (include/rara_peak.h, libpeak.so) ---------------
+
+PEAK_LIB_PATH = os.path.join(HERE, "libpeak.so")
+PEAK_EXPORTS = ["rara_peak_copy", "rara_peak_fma", "rara_peak_fma_flops"]
+_peak = None
+
+
+def peak_lib():
+    global _peak
+    if _peak is None:
+        if not os.path.exists(PEAK_LIB_PATH):
+            raise RuntimeError(f"libpeak.so is not built ({PEAK_LIB_PATH}); run __graft_entry__.build()")
+        L = ctypes.CDLL(PEAK_LIB_PATH)
+        L.rara_peak_copy.argtypes = [_P, _P, ctypes.c_size_t, ctypes.c_int, _P]
+        L.rara_peak_copy.restype = ctypes.c_int
+        L.rara_peak_fma.argtypes = [_P, ctypes.c_int, ctypes.c_int, _P]
+        L.rara_peak_fma.restype = ctypes.c_int
+        L.rara_peak_fma_flops.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.rara_peak_fma_flops.restype = ctypes.c_double
+        _peak = L
+    return _peak
+
+
+def peak_copy(dst: int, src: int, nbytes: int, blocks: int, stream: int):
+    st = peak_lib().rara_peak_copy(_P(dst), _P(src), nbytes, blocks, _P(stream))
+    if st != 0:
+        raise RuntimeError(f"rara_peak_copy failed ({st})")
+
+
+def peak_fma(out: int, blocks: int, iters: int, stream: int) -> float:
+    """Enqueue the FMA loop; returns its flop count."""
+    L = peak_lib()
+    st = L.rara_peak_fma(_P(out), blocks, iters, _P(stream))
+    if st != 0:
+        raise RuntimeError(f"rara_peak_fma failed ({st})")
+    return float(L.rara_peak_fma_flops(blocks, iters))

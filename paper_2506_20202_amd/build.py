@@ -1,6 +1,8 @@
-"""Build the gfx950 HIP library librara.so in-tree (hipcc cross-compiles
-without a GPU).  Every HIP source is compiled with packed-FP32 instructions
-disabled."""
+"""Build the gfx950 HIP libraries in-tree (hipcc cross-compiles without a
+GPU): librara.so, the renderer (csrc/*.hip), and libpeak.so, the
+attainable-peak probes the benchmark states its roofline fractions against
+(measure/peak.hip).  Every HIP source is compiled with packed-FP32
+instructions disabled."""
 import glob
 import os
 import subprocess
@@ -9,6 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librara.so")
+PEAK_LIB = os.path.join(HERE, "libpeak.so")
 ARCH = os.environ.get("RARA_OFFLOAD_ARCH", "gfx950")
 
 
@@ -17,6 +20,12 @@ def sources():
 
 
 def build(verbose: bool = False, jobs: int = 8) -> str:
+    _build_lib(sources(), LIB, verbose, jobs)
+    _build_lib([os.path.join(HERE, "measure", "peak.hip")], PEAK_LIB, verbose, jobs)
+    return LIB
+
+
+def _build_lib(srcs, lib, verbose, jobs):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
@@ -24,7 +33,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
               "-I", os.path.join(HERE, "csrc"), "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
     procs, objs = [], []
-    for src in sources():
+    for src in srcs:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         cmd = common + ["-c", src, "-o", obj]
         if verbose:
@@ -35,13 +44,12 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
             _wait(procs.pop(0), verbose)
     for p in procs:
         _wait(p, verbose)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
 
 
 def _wait(item, verbose):

@@ -449,8 +449,12 @@ __global__ __launch_bounds__(256) void slot_sum_kernel(int64_t n, int32_t plane_
                                                        const uint8_t* __restrict__ label,
                                                        const uint32_t* __restrict__ tiles_touched,
                                                        const uint32_t* __restrict__ pair_start,
+                                                       const int32_t* __restrict__ overflow,
                                                        const float* __restrict__ slots, double* __restrict__ sums)
 {
+    // an overflowed frame has no complete pair slots (nor pair starts): the
+    // chain rule writes zero gradients without reading the sums
+    if (*overflow) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const uint32_t tt = i < n ? tiles_touched[i] : 0u;
@@ -514,18 +518,20 @@ __global__ __launch_bounds__(256) void slot_sum_kernel(int64_t n, int32_t plane_
 __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamParams cam, PlaneParams pl,
                                                                const uint8_t* __restrict__ label,
                                                                const uint32_t* __restrict__ tiles_touched,
+                                                               const int32_t* __restrict__ overflow,
                                                                const double* __restrict__ sums, GradPtrs out,
                                                                float* __restrict__ plane_acc)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = g.n;
+    const bool overflowed = *overflow != 0;   // no sums: every gradient is zero
     const int ncoef = (g.sh_degree + 1) * (g.sh_degree + 1);
     double pn[4] = {0.0, 0.0, 0.0, 0.0};   // d n_hat, d d_hat contributed by this Gaussian
     if (i < n) {
         double dmu[3] = {0.0, 0.0, 0.0}, ds[3] = {0.0, 0.0, 0.0}, dqv[4] = {0.0, 0.0, 0.0, 0.0};
         double gop = 0.0;
         const uint32_t tt = tiles_touched[i];
-        const bool drawn = tt > 0;
+        const bool drawn = tt > 0 && !overflowed;
         if (drawn) {
             // the sums of this Gaussian's pair slots (slot_sum_kernel)
             const bool cutg = pl.enabled && label[i] == RARA_LABEL_CUTOFF;
@@ -710,10 +716,10 @@ __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamP
 // raw plane gradient: n_hat = n / |n|, d_hat = d / |n|; the pixel-rate terms
 // (ax, ay) = (R_c n_hat)_{x,y} / f_{x,y}.
 __global__ void plane_finalize_kernel(CamParams cam, PlaneParams pl, double len, const float* __restrict__ plane_acc,
-                                      float* __restrict__ out)
+                                      const int32_t* __restrict__ overflow, float* __restrict__ out)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (!pl.enabled) {
+    if (!pl.enabled || *overflow) {
         out[0] = out[1] = out[2] = out[3] = 0.0f;
         return;
     }
@@ -759,12 +765,13 @@ hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const Plane
     if (g.n > 0) {
         const dim3 grid((unsigned)((g.n + 255) / 256));
         hipLaunchKernelGGL(slot_sum_kernel, grid, dim3(256), 0, s, g.n, pl.enabled, proj.label, proj.tiles_touched,
-                           bins.pair_start, slots, sums);
+                           bins.pair_start, bins.overflow, slots, sums);
         GradPtrs gp{grads.mean, grads.scale, grads.quat, grads.opacity, grads.sh};
         hipLaunchKernelGGL(project_backward_kernel, grid, dim3(256), 0, s, g, cam, pl, proj.label, proj.tiles_touched,
-                           sums, gp, plane_acc);
+                           bins.overflow, sums, gp, plane_acc);
     }
-    hipLaunchKernelGGL(plane_finalize_kernel, dim3(1), dim3(64), 0, s, cam, pl, plane_len, plane_acc, grads.plane);
+    hipLaunchKernelGGL(plane_finalize_kernel, dim3(1), dim3(64), 0, s, cam, pl, plane_len, plane_acc, bins.overflow,
+                       grads.plane);
     return hipGetLastError();
 }
 

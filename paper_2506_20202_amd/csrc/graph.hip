@@ -127,8 +127,11 @@ rara_status rara_frame_graph_launch(rara_frame_graph* fg, const rara_camera* cam
     if (fp.plane.enabled && fp.plane.count > 1) return RARA_ERR_UNSUPPORTED;   // the graph holds the one-plane blend
     fp.render = make_render_params(fp.cam, fp.plane, bg);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // the staging block may be rewritten once the previous copy out of it ran
+    // the staging block may be rewritten once the previous copy out of it ran;
+    // the device block and the frame's buffers once the previous replay ended
+    // (a launch on another stream must not overtake it)
     if (fg->launched && hipEventSynchronize(fg->staged) != hipSuccess) return RARA_ERR_HIP;
+    if (fg->launched && hipStreamWaitEvent(s, fg->done, 0) != hipSuccess) return RARA_ERR_HIP;
     std::memcpy(fg->host_params, &fp, sizeof(FrameParams));
     if (hipMemcpyAsync(fg->dev_params, fg->host_params, sizeof(FrameParams), hipMemcpyHostToDevice, s) != hipSuccess)
         return RARA_ERR_HIP;

@@ -476,3 +476,71 @@ def grad_plane(seed: int = 4) -> Plane:
     rng = np.random.default_rng(70_000 + seed)
     n = _unit_vectors(rng, 1)[0]
     return Plane(_f32(n), float(np.float32(rng.uniform(-0.1, 0.1))), True)
+
+
+def concat(*parts: Scene) -> Scene:
+    """One scene holding the Gaussians of ``parts`` in order (same SH degree)."""
+    deg = parts[0].sh_degree
+    assert all(p.sh_degree == deg for p in parts)
+    return Scene(*(np.ascontiguousarray(np.concatenate([getattr(p, f) for p in parts], axis=-1))
+                   for f in ("mean", "scale", "quat", "opacity", "sh")), deg)
+
+
+def wide_gaussians(seed: int = 0, n: int = 6, sh_degree: int = 3, sigma=(0.4, 0.6),
+                   opacity: float = 0.3) -> Scene:
+    """A few large anisotropic Gaussians near the origin (per-axis sigma
+    U[sigma], means N(0, 0.15^2)): at a grad_camera of 128 px or more their
+    footprints span most of the image, over 32 tiles each."""
+    rng = np.random.default_rng(80_000 + seed)
+    mean = rng.normal(0.0, 0.15, (3, n))
+    scale = rng.uniform(sigma[0], sigma[1], (3, n))
+    quat = _unit_quats(rng, n)
+    op = np.full(n, opacity)
+    sh = rng.normal(0.0, 0.3, ((sh_degree + 1) ** 2, 3, n))
+    return Scene(_f32(mean), _f32(scale), _f32(quat), _f32(op), _f32(sh), sh_degree)
+
+
+def faint_list_scene(seed: int = 0, n: int = 1500, opacity: float = 0.0058, sh_degree: int = 3,
+                     spread: float = 0.1, sigma=(0.8, 1.2)) -> Scene:
+    """``n`` large, faint Gaussians in a small cluster (means U[-spread,
+    spread]^3, per-axis sigma U[sigma], opacity ``opacity``).  Seen by
+    ``faint_camera`` every pixel is within a fraction of a sigma of every
+    centre, so alpha stays within about 25 % of ``opacity``: each tile list
+    holds all n Gaussians, every entry is composited, and no pixel terminates
+    (the product of (1 - alpha) over the list stays above 1e-4)."""
+    rng = np.random.default_rng(90_000 + seed)
+    mean = rng.uniform(-spread, spread, (3, n))
+    scale = rng.uniform(sigma[0], sigma[1], (3, n))
+    quat = _unit_quats(rng, n)
+    op = np.full(n, opacity)
+    sh = rng.normal(0.0, 0.3, ((sh_degree + 1) ** 2, 3, n))
+    return Scene(_f32(mean), _f32(scale), _f32(quat), _f32(op), _f32(sh), sh_degree)
+
+
+def faint_camera(size: int = 32) -> Camera:
+    """A narrow (9 degree) view of the faint cluster from distance about 6.3."""
+    return pinhole((1.5, 1.2, -6.0), (0.0, 0.0, 0.0), size, size, 9.0)
+
+
+def inside_gaussian(cam: Camera, depth: float = 0.5, sigma=(0.3, 0.3, 0.3), opacity: float = 0.4,
+                    sh_degree: int = 3, seed: int = 0) -> Scene:
+    """One Gaussian centred ``depth`` in front of the camera on its optical
+    axis: with 3 sigma > depth the camera lies inside its 3-sigma ellipsoid
+    (the case where the near root of the ray-ellipsoid quadratic is behind the
+    camera)."""
+    rng = np.random.default_rng(95_000 + seed)
+    wc = np.asarray(cam.world_to_cam, np.float64).reshape(3, 4)
+    eye = -wc[:, :3].T @ wc[:, 3]
+    fwd = wc[2, :3]
+    mean = (eye + depth * fwd)[:, None]
+    scale = np.asarray(sigma, np.float64)[:, None]
+    quat = _unit_quats(rng, 1)
+    sh = rng.normal(0.0, 0.3, ((sh_degree + 1) ** 2, 3, 1))
+    return Scene(_f32(mean), _f32(scale), _f32(quat), _f32(np.array([opacity])), _f32(sh), sh_degree)
+
+
+def plane_through(point, normal, enabled=True) -> Plane:
+    """Plane with unit normal ``normal`` through ``point``."""
+    n = np.asarray(normal, np.float64)
+    n = n / np.linalg.norm(n)
+    return Plane(_f32(n), float(np.float32(-float(n @ np.asarray(point, np.float64)))), enabled)

@@ -254,3 +254,37 @@ def chord_weight_region(e, v, mu, Vinv, planes, samples: int = 20000):
 
 
 render_region = render   # render takes a plane or a region (a Plane with extra planes)
+
+
+def closest_approach(e, v, mu, Vinv, iters: int = 200):
+    """Point of the line e + t v closest to mu in the metric of Vinv (the
+    whitened distance of Sec. 3.3), found by golden-section search on the
+    convex function f(t) = (e + t v - mu)^T Vinv (e + t v - mu) after
+    bracketing its minimum; no closed form.  Returns (point, f at it)."""
+    e, v, mu = (np.asarray(a, np.float64) for a in (e, v, mu))
+
+    def f(t):
+        r = e + t * v - mu
+        return float(r @ Vinv @ r)
+
+    step = max(1.0, float(np.linalg.norm(mu - e))) / max(float(np.linalg.norm(v)), 1e-300)
+    lo, hi = -step, step
+    while f(lo) < f(lo + 0.5 * step) or f(hi) < f(hi - 0.5 * step):
+        lo, hi, step = lo - 2 * step, hi + 2 * step, 2 * step
+    g = (math.sqrt(5.0) - 1.0) / 2.0
+    a, b = lo, hi
+    c, d = b - g * (b - a), a + g * (b - a)
+    fc, fd = f(c), f(d)
+    for _ in range(iters):
+        if fc < fd:
+            b, d, fd = d, c, fc
+            c = b - g * (b - a)
+            fc = f(c)
+        else:
+            a, c, fc = c, d, fd
+            d = a + g * (b - a)
+            fd = f(d)
+        if b - a <= 1e-13 * max(1.0, abs(a)):
+            break
+    t = 0.5 * (a + b)
+    return e + t * v, f(t)

@@ -43,6 +43,26 @@ def test_library_exports_every_declared_symbol(B):
     assert set(B.EXPORTS) <= set(declared_functions())
 
 
+def test_peak_library_exports_its_header(B):
+    """libpeak.so (include/rara_peak.h), the attainable-peak probes the
+    benchmark measures its roofline fractions against, loads and exports every
+    function its header declares; bad arguments are refused without a launch."""
+    hdr = open(os.path.join(ROOT, "include", "rara_peak.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    declared = sorted(set(re.findall(r"\b(rara_peak_[a-z_]+)\s*\(", hdr)))
+    assert declared == sorted(B.PEAK_EXPORTS)
+    L = B.peak_lib()
+    nm = subprocess.run(["nm", "-D", "--defined-only", B.PEAK_LIB_PATH], capture_output=True, text=True,
+                        check=True).stdout
+    exported = set(re.findall(r"\s[TW]\s+(\S+)", nm))
+    for f in declared:
+        assert f in exported and hasattr(L, f)
+    assert L.rara_peak_copy(None, None, 16, 1, None) == 1
+    assert L.rara_peak_copy(ctypes.c_void_p(16), ctypes.c_void_p(16), 15, 1, None) == 1
+    assert L.rara_peak_fma(None, 1, 1, None) == 1
+    assert L.rara_peak_fma_flops(2, 3) == 2.0 * 16 * 256 * 2 * 3
+
+
 def test_header_compiles_as_c(tmp_path):
     src = tmp_path / "t.c"
     src.write_text('#include "rara.h"\nint main(void){ rara_camera c; rara_plane p; (void)c; (void)p; '

@@ -26,3 +26,35 @@ def test_gpu_count_above_one_is_refused(capsys, monkeypatch):
         bench.main()
     assert e.value.code == 2
     assert "one GPU" in capsys.readouterr().err
+
+
+def test_clip_order_strides_views_and_offsets():
+    """The timed frames: any prefix strides views and offsets, and one full
+    pass visits every clipping (view, offset) pair exactly once."""
+    clip = [list(range(3, 13))] * 16
+    order = bench.clip_order(clip)
+    assert len(order) == 160 and len(set(order)) == 160
+    assert all(o in range(3, 13) for _, o in order)
+    head = order[:20]
+    assert [v for v, _ in head] == list(range(16)) + [0, 1, 2, 3]
+    assert len({o for _, o in head}) == 10          # every clipping offset within the first 20 frames
+    # unequal offset lists per view: every pair still appears
+    clip2 = [[0, 1], [2], [1, 2, 3]]
+    order2 = bench.clip_order(clip2)
+    assert {(v, o) for v in range(3) for o in clip2[v]} == set(order2)
+    import pytest
+    with pytest.raises(ValueError):
+        bench.clip_order([[1], []])
+
+
+def test_stage_byte_models():
+    """Per-stage algorithmic bytes: the preprocess of a scene where nothing is
+    live moves 29 B per Gaussian; one drawn SH3 Gaussian adds 16 + 4 + 192 +
+    60 B; the sort's tile passes follow the tile count (2 passes for the
+    8160 tiles of 1080p, 1 for 64)."""
+    assert bench.preprocess_bytes(1000, 3, 0, 0, 0) == 29000
+    assert bench.preprocess_bytes(1, 3, 1, 1, 0) - 29 == 16 + 4 + 192 + 60
+    assert bench.preprocess_bytes(1, 3, 1, 1, 1) - bench.preprocess_bytes(1, 3, 1, 1, 0) == 48
+    one = bench.bin_sort_bytes(0, 0, 1, 64) - bench.bin_sort_bytes(0, 0, 0, 64)
+    two = bench.bin_sort_bytes(0, 0, 1, 8160) - bench.bin_sort_bytes(0, 0, 0, 8160)
+    assert one == 8 + 12 and two == 8 + 16 + 12

@@ -75,6 +75,127 @@ def test_plain_gradients_match_oracle():
     assert np.all(g["plane"] == 0)
 
 
+def _check_case(sc, cam, pl, seed, min_unflagged=0.5, bg=(0.0, 0.0, 0.0)):
+    o = oracle.render(sc, cam, pl, bg=bg)
+    ok = o["flags"] == 0
+    assert ok.mean() >= min_unflagged, ok.mean()
+    rng = np.random.default_rng(seed)
+    wimg = rng.normal(size=(3, cam.height, cam.width)) * ok[None]
+    g, img = _grads_gpu(sc, cam, pl, wimg, bg)
+    r, rimg = _grads_ref(sc, cam, pl, wimg, bg)
+    assert np.abs(img.detach().cpu().numpy() - rimg.detach().numpy()).max(0)[ok].max() < 1e-3
+    groups = ["mean", "scale", "quat", "opacity", "sh"] + (["plane"] if pl.enabled else [])
+    _compare(g, r, groups)
+    return o, g
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_wide_gaussian_gradients_match_oracle(seed):
+    """Gaussians spanning more than 32 tiles, whose pair slots the backward
+    sums with a whole wave instead of one thread, at 128x128 (64 tiles), most
+    of them CUTOFF, among 150 general-scene Gaussians."""
+    cam = scenes.grad_camera(128)
+    sc = scenes.concat(scenes.grad_scene(10 + seed, n=150), scenes.wide_gaussians(seed))
+    pl = scenes.grad_plane(10 + seed)
+    o, _ = _check_case(sc, cam, pl, 100 + seed)
+    tt = o["proj"]["tiles_touched"]
+    print(f"wide seed {seed}: Gaussians over 32 tiles: {(tt > 32).sum()}, largest {tt.max()}", flush=True)
+    assert (tt > 32).sum() >= 5
+    assert (o["label"][tt > 32] == oracle.CUTOFF).sum() >= 5
+
+
+@pytest.mark.parametrize("clipped", [False, True])
+def test_long_faint_list_gradients_match_oracle(clipped):
+    """Tile lists of 1500 faint entries (alpha about 0.005), every one of them
+    composited: the backward rebuilds the transmittance by division over the
+    whole list.  Clipped: a plane that leaves partial weights on the CUTOFF
+    entries (the final transmittance rises from 1.7e-4 to 4.5e-4)."""
+    cam = scenes.faint_camera()
+    sc = scenes.faint_list_scene(0)
+    nrm = np.array([0.2, 0.3, 1.0])
+    pl = scenes.Plane((nrm / np.linalg.norm(nrm)).astype(np.float32), 1.8, enabled=clipped)
+    o, _ = _check_case(sc, cam, pl, 7 + int(clipped))
+    ok = o["flags"] == 0
+    lens = np.diff(o["offsets"])
+    print(f"faint list clipped={clipped}: list lengths {lens.min()}-{lens.max()}, n_contrib on checked pixels "
+          f"{o['n_contrib'][ok].min()}-{o['n_contrib'][ok].max()}, T min {o['final_T'].min():.2e}", flush=True)
+    assert lens.min() >= 1500
+    assert o["n_contrib"][ok].min() >= 1500
+
+
+@pytest.mark.parametrize("normal", [(0.3, -0.5, 0.8), (1.0, 0.2, 0.1)])
+def test_camera_inside_gradients_match_oracle(normal):
+    """A CUTOFF Gaussian holding the camera inside its 3-sigma ellipsoid (the
+    near root behind the camera, w = 1 on every pixel ray: eq. (11)'s
+    "otherwise" case) in front of 150 general-scene Gaussians."""
+    cam = scenes.grad_camera(64)
+    ins = scenes.inside_gaussian(cam)
+    sc = scenes.concat(scenes.grad_scene(21, n=150), ins)
+    pl = scenes.plane_through(ins.mean[:, 0], normal)
+    o, _ = _check_case(sc, cam, pl, 31)
+    assert o["label"][-1] == oracle.CUTOFF
+    assert o["counters"][4] >= cam.width * cam.height * 0.99
+
+
+def test_backward_of_an_overflowed_frame_is_zero():
+    """rara_render_backward on a frame whose pair capacity overflowed writes
+    zero to every gradient (the pair slots and pair starts of such a frame
+    are incomplete and are not read)."""
+    from paper_2506_20202_amd import binding as B
+    from paper_2506_20202_amd import renderer as R
+    dev = torch.device("cuda:0")
+    sc, cam, pl = scenes.grad_scene(4), scenes.grad_camera(), scenes.grad_plane(4)
+    o = oracle.render(sc, cam, pl, events=False)
+    P = len(o["ids"])
+    ds = R.DeviceScene.from_scene(sc, dev)
+    fr = R.Frame(sc.n, cam.width, cam.height, P // 2, dev, walked=False)
+    fr.out.final_T.fill_(0.5)
+    fr.out.n_contrib.fill_(3)
+    R.enqueue_frame(ds, fr, cam, pl)
+    torch.cuda.synchronize()
+    assert int(fr.bins.overflow.item()) == 1
+    g = {k: torch.full_like(getattr(ds, k), float("nan")) for k in ("mean", "scale", "quat", "opacity", "sh")}
+    dplane = torch.full((4,), float("nan"), dtype=torch.float32, device=dev)
+    gs = B.Grads()
+    gs.mean, gs.scale, gs.quat = g["mean"].data_ptr(), g["scale"].data_ptr(), g["quat"].data_ptr()
+    gs.opacity, gs.sh, gs.plane = g["opacity"].data_ptr(), g["sh"].data_ptr(), dplane.data_ptr()
+    ws_bytes = B.workspace_bytes(B.RARA_WS_BACKWARD, sc.n, fr.capacity, cam.width, cam.height)
+    ws = torch.full((ws_bytes,), 0xAB, dtype=torch.uint8, device=dev)
+    dimg = torch.ones((3, cam.height, cam.width), dtype=torch.float32, device=dev)
+    stream = int(torch.cuda.current_stream(dev).cuda_stream)
+    B.render_backward(ds.struct(), B.make_camera(cam), B.make_plane(pl), (0.0, 0.0, 0.0), fr.proj.struct(),
+                      fr.bins.struct(), fr.capacity, fr.out.final_T.data_ptr(), fr.out.n_contrib.data_ptr(),
+                      dimg.data_ptr(), gs, ws.data_ptr(), ws_bytes, stream)
+    torch.cuda.synchronize()
+    for k, v in g.items():
+        assert bool((v == 0).all()), k
+    assert bool((dplane == 0).all())
+
+
+def test_pair_starts_stay_within_the_pairs():
+    """For a frame that fits, every drawn Gaussian's pair slots
+    [pair_start, pair_start + tiles_touched) lie inside [0, num_pairs): the
+    bound the backward's slot reads rely on."""
+    from paper_2506_20202_amd import renderer as R
+    dev = torch.device("cuda:0")
+    for sc, cam, pl in ((scenes.grad_scene(4), scenes.grad_camera(), scenes.grad_plane(4)),
+                        (scenes.tiny_scene(1), scenes.tiny_camera(), scenes.tiny_plane(1))):
+        ds = R.DeviceScene.from_scene(sc, dev)
+        fr = R.Frame(sc.n, cam.width, cam.height, 1 << 16, dev, walked=False)
+        R.render_checked(ds, fr, cam, pl)
+        P = int(fr.bins.num_pairs.item())
+        tt = fr.proj.tiles_touched[: sc.n].cpu().numpy().view(np.uint32).astype(np.int64)
+        ps = fr.bins.pair_start[: sc.n].cpu().numpy().view(np.uint32).astype(np.int64)
+        drawn = tt > 0
+        assert drawn.any()
+        assert (ps[drawn] + tt[drawn] <= P).all()
+        # the slots of the drawn Gaussians tile [0, P) exactly
+        cover = np.zeros(P, np.int64)
+        for a, b in zip(ps[drawn], tt[drawn]):
+            cover[a:a + b] += 1
+        assert (cover == 1).all()
+
+
 def test_differentiable_batch_full_size():
     """The 500k-Gaussian, 8 views x 800x800 differentiable workload: L2 loss
     against a perturbed-scene target; gradients finite, zero for Gaussians no

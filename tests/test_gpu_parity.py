@@ -159,46 +159,44 @@ def test_capacity_overflow_reported_and_frame_untouched():
     H.check_lists(H.collect(fr, out, sc.n), o)
 
 
-def test_general_scene_1080p_sampled():
-    """The 1M-Gaussian general scene at 1920x1080, mid-sweep plane: every
-    label, rectangle and tile list checked; the image checked on two bands of
-    tiles the oracle composites."""
+@pytest.mark.parametrize("view,offset", [(0, 8), (5, 6), (11, 10)])
+def test_general_scene_1080p_full_frame(view, offset):
+    """The 1M-Gaussian general scene at 1920x1080 with planes that clip
+    (offsets 6-10 of the 16-offset sweep): every label, rectangle and tile list
+    checked, and the whole image (every tile the oracle composites)."""
     sc = scenes.general_scene(1)
-    cam = scenes.general_views()[0]
-    pl = scenes.plane_sweep(sc, scenes.general_plane_normal(1))[8]
-    tx = cam.tiles[0]
-    bands = [(30 * tx, 32 * tx), (50 * tx + 20, 50 * tx + 80)]
+    cam = scenes.general_views()[view]
+    pl = scenes.plane_sweep(sc, scenes.general_plane_normal(1))[offset]
     g = H.gpu_frame(sc, cam, pl, capacity=12_000_000)
-    o = oracle.render(sc, cam, pl, tiles=bands[0], events=True)
+    o = oracle.render(sc, cam, pl, events=True)
     bad, rects = H.check_projection(g, o)
     skip = H.tiles_of(rects, cam.tiles[0])
     H.check_lists(g, o, skip=skip)
     excl = oracle.tile_mask(cam, rects)
-    print(f"general: P={g['P']} boundary={len(o['boundary_ids'])} mismatched={len(bad)} "
-          f"cutoff={(o['label'] == 2).sum()}", flush=True)
-    for t0, t1 in bands:
-        ob = oracle.render(sc, cam, pl, tiles=(t0, t1), events=False)
-        m = _tile_pixel_mask(cam, t0, t1)
-        err, fl, _ = H.image_error(g["image"], ob, exclude=excl, region=m)
-        print(f"band {t0}-{t1}: max_err={err:.2e} flagged={fl:.4f}", flush=True)
-        assert err <= TOL
+    err, fl, _ = H.image_error(g["image"], o, exclude=excl)
+    print(f"general v{view} o{offset}: P={g['P']} boundary={len(o['boundary_ids'])} mismatched={len(bad)} "
+          f"cutoff={(o['label'] == 2).sum()} invisible={(o['label'] == 0).sum()} max_err={err:.2e} "
+          f"flagged={fl:.4f}", flush=True)
+    assert (o["label"] == 2).sum() > 0 and (o["label"] == 0).sum() > 0   # the plane clips
+    assert err <= TOL
+    assert fl < 0.05
+    ok = (o["flags"] == 0) & ~excl
+    np.testing.assert_array_equal(g["n_contrib"][ok], o["n_contrib"][ok])
 
 
-def test_strand_scene_sampled():
+def test_strand_scene_full_frame():
     """3.2M strand Gaussians (40:1:1) at 1024x1024 with an oblique plane:
-    labels and lists exact, image on a band of tiles through the cut."""
+    labels and lists exact, the whole image within the bar."""
     sc = scenes.strand_scene(2)
     cam = scenes.strand_views()[0]
     pl = scenes.strand_planes(0)[1]
     g = H.gpu_frame(sc, cam, pl, capacity=40_000_000)
     tx = cam.tiles[0]
-    band = (28 * tx, 30 * tx)
-    o = oracle.render(sc, cam, pl, tiles=band, events=True)
+    o = oracle.render(sc, cam, pl, events=True)
     bad, rects = H.check_projection(g, o)
     skip = H.tiles_of(rects, tx)
-    H.check_lists(g, o, tiles=range(band[0], band[1]), skip=skip)
-    m = _tile_pixel_mask(cam, *band)
-    err, fl, _ = H.image_error(g["image"], o, exclude=oracle.tile_mask(cam, rects), region=m)
+    H.check_lists(g, o, skip=skip)
+    err, fl, _ = H.image_error(g["image"], o, exclude=oracle.tile_mask(cam, rects))
     print(f"strands: P={g['P']} cutoff={(o['label'] == 2).sum()} boundary={len(o['boundary_ids'])} "
           f"mismatched={len(bad)} max_err={err:.2e} flagged={fl:.4f}", flush=True)
     assert err <= TOL
@@ -225,6 +223,27 @@ def test_clip_mode_parity_large_gaussians(name, mode):
     n = rng.standard_normal(3)
     pl = scenes.Plane((n / np.linalg.norm(n)).astype(np.float32), float(rng.uniform(-0.1, 0.1)), enabled=mode)
     _full_check(sc, scenes.small_camera(96), pl)
+
+
+@pytest.mark.parametrize("mode", [oracle.CLIP_RARA, oracle.CLIP_RARA | oracle.CLIP_TIGHT,
+                                  oracle.CLIP_RARA | oracle.CLIP_STRICT_MISS])
+@pytest.mark.parametrize("normal", [(0.3, -0.5, 0.8), (1.0, 0.2, 0.1)])
+def test_camera_inside_cutoff_gaussian(mode, normal):
+    """Eq. (11)'s "otherwise" case with the near root behind the camera: a
+    CUTOFF Gaussian (sigma 0.3) centred 0.5 in front of the camera, cut by a
+    plane through its centre, holds the camera inside its 3-sigma ellipsoid,
+    so every pixel ray meets it once at t >= 0 and keeps w = 1.  Labels,
+    lists and image as the oracle, whose camera-inside counter covers every
+    pixel."""
+    cam = scenes.grad_camera(128)
+    ins = scenes.inside_gaussian(cam)
+    sc = scenes.concat(scenes.grad_scene(20, n=150), ins)
+    base = scenes.plane_through(ins.mean[:, 0], normal)
+    pl = scenes.Plane(base.n, base.d, mode)
+    g, o = _full_check(sc, cam, pl)
+    assert o["label"][-1] == oracle.CUTOFF and g["label"][-1] == oracle.CUTOFF
+    assert g["tiles_touched"][-1] == 64
+    assert o["counters"][4] >= cam.width * cam.height * 0.99
 
 
 def test_bin_sort_without_pair_start_matches():

@@ -612,6 +612,46 @@ def test_strict_miss_weight_uses_the_closest_approach_side():
         assert ih[0] > 0 and wh == wp
 
 
+def test_strict_miss_weight_follows_the_whitened_closest_point_anisotropic():
+    """f2 for anisotropic Gaussians: a missing ray gets w = 1 exactly when the
+    point of the ray closest to the centre in the Gaussian's own metric (the
+    whitened space of Sec. 3.3) is on the visible side.  That point is found
+    independently: a golden-section search of the Mahalanobis distance along
+    the ray, with the covariance from scipy's rotation (no closed form, no
+    oracle routine).  Half of the planes pass between this point and the
+    Euclidean closest point, so taking the Euclidean point (or a transposed
+    whitening) would flip the weight there."""
+    rng = np.random.default_rng(13)
+    checked = discriminating = 0
+    for it in range(400):
+        s = np.exp(rng.normal(-2.0, 0.8, 3))              # axis ratios up to ~20:1
+        q = rng.standard_normal(4)
+        mu = rng.uniform(-1, 1, 3)
+        Vinv = np.linalg.inv(independent.cov3(q, s))
+        e = mu + _rand_unit(rng) * rng.uniform(1.0, 4.0)
+        v = mu + _rand_unit(rng) * rng.uniform(1.1, 4.0) * 3.0 * s.max() - e   # passes beside the ellipsoid
+        v = v / np.linalg.norm(v)
+        xw, fmin = independent.closest_approach(e, v, mu, Vinv)
+        if fmin <= 9.0 * (1.0 + 1e-6):
+            continue                                       # a hit or a graze: not the strict-miss case
+        xe = e + float(np.dot(mu - e, v)) * v              # Euclidean closest point
+        if it % 2 == 0 and np.linalg.norm(xw - xe) > 1e-3 * s.max():
+            n = (xw - xe) / np.linalg.norm(xw - xe)        # plane between the two points
+            d = -float(np.dot(n, 0.5 * (xw + xe)))
+        else:
+            n = _rand_unit(rng)
+            d = -float(np.dot(n, xw)) + rng.uniform(-0.5, 0.5) * s.min()
+        side = float(np.dot(n, xw)) + d
+        if abs(side) <= 1e-7 * max(1.0, float(np.linalg.norm(xw))):
+            continue
+        w, info = oracle.weight(e, v, mu, q, s, n, d, strict_miss=True)
+        assert info[0] < 0
+        assert w == (1.0 if side >= 0 else 0.0), (w, side, it)
+        checked += 1
+        discriminating += (side >= 0) != (float(np.dot(n, xe)) + d >= 0)
+    assert checked > 250 and discriminating > 80, (checked, discriminating)
+
+
 def test_clip_mode_validation():
     sc = scenes.tiny_scene(0)
     pl = scenes.tiny_plane(0)

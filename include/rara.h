@@ -46,7 +46,9 @@ typedef enum {
     RARA_ERR_INVALID = 1,     /* bad argument (null pointer, size, plane, workspace too small) */
     RARA_ERR_CAPACITY = 2,    /* reserved for callers: device overflow flag was found set   */
     RARA_ERR_HIP = 3,         /* a HIP runtime call or kernel launch failed                 */
-    RARA_ERR_UNSUPPORTED = 4  /* e.g. sh_degree > 3, image larger than 65535 tiles a side   */
+    RARA_ERR_UNSUPPORTED = 4, /* e.g. sh_degree > 3, image larger than 65535 tiles a side   */
+    RARA_ERR_SCRATCH = 5      /* rara_bin_sort_static: the frame needs more workspace than
+                                 RARA_STATIC_WS_BYTES                                       */
 } rara_status;
 
 /* Labels of Sec. 3.2 (written by rara_preprocess, one byte per Gaussian). */
@@ -279,6 +281,27 @@ rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam
                                  int64_t pair_capacity, const float* final_T, const uint32_t* n_contrib,
                                  const float* dL_dimage, const rara_grads* grads, void* workspace, size_t ws_bytes,
                                  void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rara_bin_sort
+ * with its workspace taken from a static device array of the library instead
+ * of a caller buffer.  Same arguments (minus the workspace), same outputs and
+ * overflow contract, same kernels: the results are bit-identical to
+ * rara_bin_sort's.  The call allocates nothing; on its first call on a device
+ * it looks up that device's copy of the array (each GPU holds its own copy of
+ * RARA_STATIC_WS_BYTES = 64 MiB from the library's load until the process
+ * ends).  Every call on a GPU shares that GPU's array: calls of one process
+ * that overlap on one GPU (on several streams or from several threads) race
+ * and must be serialised by the caller.  No part of the array needs to start
+ * at zero (every byte a call reads, the call has written first), so the
+ * previous call's contents do no harm.
+ * Errors: those of rara_bin_sort, and RARA_ERR_SCRATCH (before anything is
+ * enqueued) when rara_workspace_bytes(RARA_WS_BIN_SORT, n, pair_capacity, W, H)
+ * exceeds RARA_STATIC_WS_BYTES (it does not for 1M Gaussians and 5.6M pairs
+ * of capacity); RARA_ERR_HIP when the array's address cannot be found. */
+#define RARA_STATIC_WS_BYTES ((size_t)64 << 20)
+rara_status rara_bin_sort_static(const rara_projected* proj, int64_t n, const rara_camera* cam,
+                                 int64_t pair_capacity, const rara_binned* out, void* stream);
 
 /* Frame graphs (for serving many requests of one shape): the kernels of one
  * frame (rara_preprocess + rara_bin_sort + rara_render) captured once into a

@@ -9,7 +9,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librara.so")
 
-RARA_OK, RARA_ERR_INVALID, RARA_ERR_CAPACITY, RARA_ERR_HIP, RARA_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
+RARA_OK, RARA_ERR_INVALID, RARA_ERR_CAPACITY, RARA_ERR_HIP, RARA_ERR_UNSUPPORTED, RARA_ERR_SCRATCH = 0, 1, 2, 3, 4, 5
+STATIC_WS_BYTES = 64 << 20   # RARA_STATIC_WS_BYTES: workspace of rara_bin_sort_static
 RARA_WS_BIN_SORT, RARA_WS_BACKWARD = 0, 1
 LABEL_INVISIBLE, LABEL_VISIBLE, LABEL_CUTOFF = 0, 1, 2
 # clip modes (rara_plane.enabled): a rule, plus flags that go with RARA_CLIP_RARA
@@ -56,7 +57,7 @@ class Grads(ctypes.Structure):
 
 EXPORTS = ["rara_preprocess", "rara_bin_sort", "rara_render", "rara_render_backward", "rara_workspace_bytes",
            "rara_status_string", "rara_version", "rara_frame_graph_create", "rara_frame_graph_launch",
-           "rara_frame_graph_destroy"]
+           "rara_frame_graph_destroy", "rara_bin_sort_static"]
 
 _lib = None
 
@@ -78,6 +79,7 @@ def lib():
         PJ, PB, PR = ctypes.POINTER(Projected), ctypes.POINTER(Binned), ctypes.POINTER(Grads)
         L.rara_preprocess.argtypes = [PG, PC, PP, PJ, _P]
         L.rara_bin_sort.argtypes = [PJ, ctypes.c_int64, PC, ctypes.c_int64, _P, ctypes.c_size_t, PB, _P]
+        L.rara_bin_sort_static.argtypes = [PJ, ctypes.c_int64, PC, ctypes.c_int64, PB, _P]
         L.rara_render.argtypes = [PJ, ctypes.c_int64, PB, PC, PP, ctypes.POINTER(ctypes.c_float), _P, _P, _P, _P, _P]
         L.rara_render_backward.argtypes = [PG, PC, PP, ctypes.POINTER(ctypes.c_float), PJ, PB, ctypes.c_int64, _P, _P,
                                            _P, PR, _P, ctypes.c_size_t, _P]
@@ -93,7 +95,7 @@ def lib():
         L.rara_frame_graph_destroy.argtypes = [_P]
         L.rara_frame_graph_destroy.restype = None
         for f in ("rara_preprocess", "rara_bin_sort", "rara_render", "rara_render_backward", "rara_frame_graph_create",
-                  "rara_frame_graph_launch"):
+                  "rara_frame_graph_launch", "rara_bin_sort_static"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -150,6 +152,12 @@ def bin_sort(proj: Projected, n: int, cam: Camera, pair_capacity: int, workspace
              out: Binned, stream: int):
     _check("rara_bin_sort", lib().rara_bin_sort(ctypes.byref(proj), n, ctypes.byref(cam), pair_capacity,
                                                 _P(workspace), ws_bytes, ctypes.byref(out), _P(stream)))
+
+
+def bin_sort_static(proj: Projected, n: int, cam: Camera, pair_capacity: int, out: Binned, stream: int):
+    """rara_bin_sort with the library's static workspace (no caller buffer)."""
+    _check("rara_bin_sort_static", lib().rara_bin_sort_static(ctypes.byref(proj), n, ctypes.byref(cam),
+                                                              pair_capacity, ctypes.byref(out), _P(stream)))
 
 
 def render(proj: Projected, n: int, bins: Binned, cam: Camera, plane: Plane, bg, image: int, final_T: int,

@@ -3,10 +3,17 @@
 // kernel launches.  Nothing here allocates or synchronises.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "rara_internal.h"
 
 using namespace rara;
+
+// Workspace of rara_bin_sort_static: one copy per GPU, held from the library's
+// load until the process ends.  Host code never uses this name as an address
+// (it is a host-side stand-in there): the device address of each GPU's copy
+// comes from hipGetSymbolAddress, below.
+static __device__ __align__(256) unsigned char scratch[RARA_STATIC_WS_BYTES];
 
 namespace {
 
@@ -82,6 +89,54 @@ ProjPtrs proj_ptrs(const rara_projected* p)
     return ProjPtrs{p->label, static_cast<Splat*>(p->splat), static_cast<RayRec*>(p->ray),
                     reinterpret_cast<float2*>(p->ray_ext), p->depth, p->rect,
                     p->tiles_touched};
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices];   // device address of `scratch` on each device, once looked up
+
+// Device address of the current device's copy of `scratch`, looked up on the
+// first call on that device (with it current); nullptr on failure.
+void* static_workspace()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// Argument checks of rara_bin_sort (everything but the workspace); on success
+// fills the camera parameters.
+rara_status check_bin_args(const rara_projected* proj, int64_t n, const rara_camera* cam, int64_t pair_capacity,
+                           const rara_binned* out, CamParams* cp)
+{
+    if (!proj || n < 0 || !out) return RARA_ERR_INVALID;
+    if (pair_capacity < 1 || pair_capacity >= (int64_t(1) << 31)) return RARA_ERR_INVALID;
+    if (n > 0 && !proj_ok(proj)) return RARA_ERR_INVALID;
+    if (!out->keys || !out->vals || !out->ranges || !out->num_pairs || !out->overflow || !out->work)
+        return RARA_ERR_INVALID;
+    if (!make_cam(cam, cp)) return RARA_ERR_INVALID;
+    return RARA_OK;
+}
+
+// The launches of rara_bin_sort on a checked frame and a large enough workspace.
+rara_status bin_sort_launch(const rara_projected* proj, int64_t n, const CamParams& cp, int64_t pair_capacity,
+                            void* workspace, const rara_binned* out, hipStream_t s)
+{
+    BinWorkspace ws;
+    bin_workspace_layout(n, pair_capacity, &ws, static_cast<char*>(workspace));
+    const int num_tiles = cp.tiles_x * cp.tiles_y;
+    int tile_passes = (ceil_log2(num_tiles) + kRadixBits - 1) / kRadixBits;
+    if (tile_passes < 1) tile_passes = 1;   // the last pass also writes the 64-bit keys
+    hipError_t e = launch_bin(proj_ptrs(proj), n, cp, pair_capacity, ws, *out, tile_passes, s);
+    if (e == hipSuccess && n == 0) e = launch_ranges_clear(*out, num_tiles, s);   // else set by launch_bin
+    if (e == hipSuccess) e = launch_plan(*out, num_tiles, s);
+    return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
 }
 
 }  // namespace
@@ -163,6 +218,7 @@ const char* rara_status_string(rara_status s)
     case RARA_ERR_CAPACITY: return "pair capacity exceeded";
     case RARA_ERR_HIP: return "HIP runtime error";
     case RARA_ERR_UNSUPPORTED: return "unsupported configuration";
+    case RARA_ERR_SCRATCH: return "frame needs more than the static workspace (RARA_STATIC_WS_BYTES)";
     }
     return "unknown status";
 }
@@ -203,24 +259,23 @@ rara_status rara_preprocess(const rara_gaussians* g, const rara_camera* cam, con
 rara_status rara_bin_sort(const rara_projected* proj, int64_t n, const rara_camera* cam, int64_t pair_capacity,
                           void* workspace, size_t ws_bytes, const rara_binned* out, void* stream)
 {
-    if (!proj || n < 0 || !out || !workspace) return RARA_ERR_INVALID;
-    if (pair_capacity < 1 || pair_capacity >= (int64_t(1) << 31)) return RARA_ERR_INVALID;
-    if (n > 0 && !proj_ok(proj)) return RARA_ERR_INVALID;
-    if (!out->keys || !out->vals || !out->ranges || !out->num_pairs || !out->overflow || !out->work)
-        return RARA_ERR_INVALID;
     CamParams cp;
-    if (!make_cam(cam, &cp)) return RARA_ERR_INVALID;
-    BinWorkspace ws;
-    const size_t need = bin_workspace_layout(n, pair_capacity, &ws, static_cast<char*>(workspace));
-    if (ws_bytes < need) return RARA_ERR_INVALID;
-    const int num_tiles = cp.tiles_x * cp.tiles_y;
-    int tile_passes = (ceil_log2(num_tiles) + kRadixBits - 1) / kRadixBits;
-    if (tile_passes < 1) tile_passes = 1;   // the last pass also writes the 64-bit keys
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = launch_bin(proj_ptrs(proj), n, cp, pair_capacity, ws, *out, tile_passes, s);
-    if (e == hipSuccess && n == 0) e = launch_ranges_clear(*out, num_tiles, s);   // else set by launch_bin
-    if (e == hipSuccess) e = launch_plan(*out, num_tiles, s);
-    return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
+    const rara_status st = check_bin_args(proj, n, cam, pair_capacity, out, &cp);
+    if (st != RARA_OK) return st;
+    if (!workspace || ws_bytes < bin_workspace_layout(n, pair_capacity, nullptr, nullptr)) return RARA_ERR_INVALID;
+    return bin_sort_launch(proj, n, cp, pair_capacity, workspace, out, static_cast<hipStream_t>(stream));
+}
+
+rara_status rara_bin_sort_static(const rara_projected* proj, int64_t n, const rara_camera* cam,
+                                 int64_t pair_capacity, const rara_binned* out, void* stream)
+{
+    CamParams cp;
+    const rara_status st = check_bin_args(proj, n, cam, pair_capacity, out, &cp);
+    if (st != RARA_OK) return st;
+    if (bin_workspace_layout(n, pair_capacity, nullptr, nullptr) > RARA_STATIC_WS_BYTES) return RARA_ERR_SCRATCH;
+    void* ws = static_workspace();
+    if (!ws) return RARA_ERR_HIP;
+    return bin_sort_launch(proj, n, cp, pair_capacity, ws, out, static_cast<hipStream_t>(stream));
 }
 
 rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned* bins, const rara_camera* cam,

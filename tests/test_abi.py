@@ -185,6 +185,34 @@ def test_argument_validation_before_any_launch(B):
                            None, None, None, None) == B.RARA_ERR_INVALID
 
 
+def test_static_bin_sort_rejects_frames_beyond_its_workspace(B):
+    """rara_bin_sort_static (the entry point for callers that cannot allocate)
+    checks its arguments like rara_bin_sort and refuses a frame whose
+    workspace exceeds RARA_STATIC_WS_BYTES with RARA_ERR_SCRATCH, both before
+    anything reaches the GPU; the headline frame (1M Gaussians, 5.6M pairs of
+    capacity at 1080p) fits."""
+    lib = B.lib()
+    hdr = open(HEADER).read()
+    assert re.search(r"#define RARA_STATIC_WS_BYTES \(\(size_t\)64 << 20\)", hdr)
+    assert B.STATIC_WS_BYTES == 64 << 20
+    assert "RARA_ERR_SCRATCH = 5" in hdr and B.RARA_ERR_SCRATCH == 5
+    assert "static workspace" in B.status_string(B.RARA_ERR_SCRATCH)
+    cam = _cam(B)
+    proj = B.Projected()
+    proj.label = proj.splat = proj.ray = proj.depth = proj.rect = proj.tiles_touched = 0x1000
+    bins = B.Binned()
+    assert lib.rara_bin_sort_static(ctypes.byref(proj), 10, ctypes.byref(cam), 100, ctypes.byref(bins), None) \
+        == B.RARA_ERR_INVALID   # null outputs
+    bins.keys = bins.vals = bins.ranges = bins.num_pairs = bins.overflow = bins.work = 0x1000
+    assert lib.rara_bin_sort_static(ctypes.byref(proj), 10, ctypes.byref(cam), 0, ctypes.byref(bins), None) \
+        == B.RARA_ERR_INVALID   # capacity < 1
+    n, cap = 1_000_000, 10_000_000
+    assert B.workspace_bytes(B.RARA_WS_BIN_SORT, n, cap, 1920, 1080) > B.STATIC_WS_BYTES
+    assert lib.rara_bin_sort_static(ctypes.byref(proj), n, ctypes.byref(cam), cap, ctypes.byref(bins), None) \
+        == B.RARA_ERR_SCRATCH
+    assert B.workspace_bytes(B.RARA_WS_BIN_SORT, 1_000_000, 5_629_420, 1920, 1080) <= B.STATIC_WS_BYTES
+
+
 def test_clip_modes_agree_and_invalid_modes_are_rejected(B):
     """rara_plane.enabled values: the header, the binding and the oracle agree;
     rule 3 and flags without the RaRa rule are RARA_ERR_INVALID (checked on the

@@ -493,12 +493,12 @@ def measure(sc, grid, args, reps, label):
     del pipe
 
     # per-stage times (HIP events on the launch stream) and work counts over
-    # the timed frames; the render (one blend launch) is timed over
-    # kRenderRepeat back-to-back launches on the same binned frame, so its
-    # figure is the kernel's own duration rather than that of an isolated
-    # launch.  The work counts come from one more launch into images with the
-    # n_walked output, untimed.
-    kRenderRepeat = 4
+    # the timed frames; each stage is timed over kRepeat back-to-back runs on
+    # the same inputs (each run rewrites the same outputs), so its figure is
+    # the kernels' own duration rather than that of an isolated launch.  The
+    # work counts come from one more render into images with the n_walked
+    # output, untimed.
+    kRepeat = 4
     frw = R.Frame(sc.n, W, H, 1, dev, walked=True)
     frw.proj, frw.bins = fr.proj, fr.bins
     stage_ms = {"preprocess": 0.0, "bin_sort": 0.0, "render": 0.0}
@@ -509,18 +509,20 @@ def measure(sc, grid, args, reps, label):
     for i in range(nst):
         cam, pl = frames[i % len(frames)]
         evs[0].record(stream)
-        R.enqueue_frame(ds, fr, cam, pl, stages=("pre",))
+        for _ in range(kRepeat):
+            R.enqueue_frame(ds, fr, cam, pl, stages=("pre",))
         evs[1].record(stream)
-        R.enqueue_frame(ds, fr, cam, pl, stages=("bin",))
+        for _ in range(kRepeat):
+            R.enqueue_frame(ds, fr, cam, pl, stages=("bin",))
         evs[2].record(stream)
-        for _ in range(kRenderRepeat):
+        for _ in range(kRepeat):
             R.enqueue_frame(ds, fr, cam, pl, stages=("render",))
         evs[3].record(stream)
         R.enqueue_frame(ds, frw, cam, pl, stages=("render",))
         torch.cuda.synchronize()
-        stage_ms["preprocess"] += evs[0].elapsed_time(evs[1])
-        stage_ms["bin_sort"] += evs[1].elapsed_time(evs[2])
-        stage_ms["render"] += evs[2].elapsed_time(evs[3]) / kRenderRepeat
+        stage_ms["preprocess"] += evs[0].elapsed_time(evs[1]) / kRepeat
+        stage_ms["bin_sort"] += evs[1].elapsed_time(evs[2]) / kRepeat
+        stage_ms["render"] += evs[2].elapsed_time(evs[3]) / kRepeat
         E, Ec = count_evals(frw, sc.n)
         E_tot += E
         Ecut_tot += Ec

@@ -10,11 +10,23 @@
 
 namespace {
 
-__global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
-                                                   int64_t n4)
+// Each thread moves kCopyUnroll 16-byte words per step, their loads all issued
+// before the stores, so that many loads per wave are in flight.
+constexpr int kCopyUnroll = 4;
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void copy_kernel(const v4f* __restrict__ src, v4f* __restrict__ dst, int64_t n4)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) dst[i] = src[i];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (kCopyUnroll - 1) * stride < n4; i += kCopyUnroll * stride) {
+        v4f v[kCopyUnroll];
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+    }
+    for (; i < n4; i += stride) dst[i] = src[i];
 }
 
 constexpr int kChains = 16;   // independent FMA chains per lane (hide the FMA latency)
@@ -43,7 +55,7 @@ int rara_peak_copy(void* dst, const void* src, size_t bytes, int blocks, void* s
 {
     if (!dst || !src || bytes % 16 != 0 || blocks < 1) return 1;
     hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, static_cast<hipStream_t>(stream),
-                       static_cast<const float4*>(src), static_cast<float4*>(dst), (int64_t)(bytes / 16));
+                       static_cast<const v4f*>(src), static_cast<v4f*>(dst), (int64_t)(bytes / 16));
     return hipGetLastError() == hipSuccess ? 0 : 3;
 }
 

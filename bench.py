@@ -83,7 +83,8 @@ def parse():
     ap.add_argument("--reps", type=int, default=5, help="timed sweeps per variant; the median is reported")
     ap.add_argument("--no-secondary", action="store_true", help="skip the strand workload")
     ap.add_argument("--warmup", type=int, default=16)
-    ap.add_argument("--workload", default="general", choices=["general", "strands"])
+    ap.add_argument("--workload", default="general", choices=["general", "strands", "multilayer", "box", "diff"],
+                    help="headline workload (general); the others for profiler runs and secondary measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-plain", action="store_true")
@@ -113,6 +114,10 @@ def workload(name):
         desc = {"workload": "general scene, 1,000,000 Gaussians (64 clusters), SH3, 1920x1080, "
                             "16 orbit views x 16 plane offsets", "gaussians": sc.n, "width": 1920, "height": 1080,
                 "views": 16, "plane_offsets": 16}
+    elif name == "multilayer":
+        return multilayer_workload()
+    elif name == "box":
+        return box_workload()
     else:
         sc = scenes.strand_scene(2)
         cams = scenes.strand_views()
@@ -139,27 +144,16 @@ def clip_order(clipping):
 
 
 def count_evals(fr, n):
-    """Gaussian-pixel evaluations the method performs in the frame just
-    rendered: per pixel, the list entries examined before termination, and
-    how many of those are CUTOFF Gaussians (measurement only)."""
+    """Work of the frame just rendered (measurement only): Gaussian-pixel
+    evaluations by the method's definition (per pixel, the list entries up to
+    termination, n_walked), the evaluations the blend kernel actually
+    performed for live pixels (n_eval plane 0: entries its conservative
+    quadrant / strip test lets reach the pixel), and the clip weights among
+    those (n_eval plane 1)."""
     import torch
-    P = int(fr.bins.num_pairs.item())
-    W, H = fr.width, fr.height
-    walked = fr.out.n_walked.to(torch.int64)
-    E = int(walked.sum().item())
-    if P == 0:
-        return E, 0
-    vals = fr.bins.vals[:P].to(torch.int64)
-    cut = (fr.proj.label[vals] == 2).to(torch.int64)
-    csum = torch.zeros(P + 1, dtype=torch.int64, device=cut.device)
-    csum[1:] = torch.cumsum(cut, 0)
-    tx = (W + 15) // 16
-    ranges = fr.bins.ranges.view(-1, 2).to(torch.int64)
-    ys, xs = torch.meshgrid(torch.arange(H, device=cut.device), torch.arange(W, device=cut.device), indexing="ij")
-    tile = (ys // 16) * tx + (xs // 16)
-    start = ranges[tile, 0]
-    Ecut = int((csum[start + walked] - csum[start]).sum().item())
-    return E, Ecut
+    walked = int(fr.out.n_walked.to(torch.int64).sum().item())
+    ev = fr.out.n_eval.to(torch.int64).sum(dim=(1, 2)).cpu().tolist()
+    return walked, int(ev[0]), int(ev[1])
 
 
 def preprocess_bytes(n, sh_degree, live, drawn, cut_drawn):
@@ -387,6 +381,39 @@ def measured_peaks(reps: int = 5):
     return res
 
 
+def profile_run(args, sc, grid, dev):
+    """Profiler runs (rocprofv3): preprocess + bin_sort over every frame of the
+    grid (capacity and labels, no blend; the initial capacity of 8 pairs per
+    Gaussian holds every frame of the workloads here, so each of those kernels
+    runs once per grid frame), then warmup + profile_steps whole frames in the
+    timed order over the frames that clip, as in the timed run: each kernel's
+    last warmup + profile_steps dispatches are those frames."""
+    import torch
+    from paper_2506_20202_amd import renderer as R
+    ds = R.DeviceScene.from_scene(sc, dev)
+    W, H = grid[0][0][0].width, grid[0][0][0].height
+    fr = R.Frame(sc.n, W, H, 8 * sc.n, dev, walked=False, pair_start=False, sorted_keys=False)
+    cap0 = fr.capacity
+    maxP, _, order = scan_grid(ds, fr, grid)
+    fr.grow(int(maxP * 1.05) + 4096)
+    torch.cuda.synchronize()
+    for i in range(args.warmup + args.profile_steps):
+        v, o = order[i % len(order)]
+        R.enqueue_frame(ds, fr, *grid[v][o])
+    torch.cuda.synchronize()
+    assert int(fr.bins.overflow.item()) == 0
+    if args.calibrate_copy:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+    print(json.dumps({"profile_steps": args.profile_steps, "warmup": args.warmup, "pair_capacity": fr.capacity,
+                      "scan_capacity": cap0, "scan_grew": maxP > cap0, "grid_frames": len(grid) * len(grid[0]),
+                      "frames": [list(order[i % len(order)]) for i in range(args.warmup + args.profile_steps)],
+                      "copy_bytes": (256 << 20) if args.calibrate_copy else 0}))
+
+
 def scan_grid(ds, fr, grid):
     """Preprocess + bin_sort of every frame of the grid (no blend; the pair
     capacity of ``fr`` grows as needed): the largest pair count, the label
@@ -502,7 +529,7 @@ def measure(sc, grid, args, reps, label):
     frw = R.Frame(sc.n, W, H, 1, dev, walked=True)
     frw.proj, frw.bins = fr.proj, fr.bins
     stage_ms = {"preprocess": 0.0, "bin_sort": 0.0, "render": 0.0}
-    E_tot, Ecut_tot, P_tot, n_live, n_drawn, n_cut_drawn = 0, 0, 0, 0, 0, 0
+    E_tot, Ev_tot, Ecut_tot, P_tot, n_live, n_drawn, n_cut_drawn = 0, 0, 0, 0, 0, 0, 0
     bytes_pre, bytes_bin = 0, 0
     nst = args.steps
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
@@ -523,8 +550,9 @@ def measure(sc, grid, args, reps, label):
         stage_ms["preprocess"] += evs[0].elapsed_time(evs[1]) / kRepeat
         stage_ms["bin_sort"] += evs[1].elapsed_time(evs[2]) / kRepeat
         stage_ms["render"] += evs[2].elapsed_time(evs[3]) / kRepeat
-        E, Ec = count_evals(frw, sc.n)
+        E, Ev, Ec = count_evals(frw, sc.n)
         E_tot += E
+        Ev_tot += Ev
         Ecut_tot += Ec
         P_tot += int(fr.bins.num_pairs.item())
         lab = fr.proj.label[: sc.n]
@@ -538,12 +566,13 @@ def measure(sc, grid, args, reps, label):
     for k in stage_ms:
         stage_ms[k] /= nst
     render_s = stage_ms["render"] / 1e3
-    flops = (E_tot * FLOPS_EVAL + Ecut_tot * FLOPS_CUT) / nst
+    flops = (Ev_tot * FLOPS_EVAL + Ecut_tot * FLOPS_CUT) / nst
     timed_pairs = sorted(set(order[i % len(order)] for i in range(nst)))
     out = {"fps": fps, "fps_serial": fps_serial, "full_sweep": full_sweep, "stage_ms": stage_ms,
            "pairs_per_frame": P_tot / nst, "live_gaussians_per_frame": n_live / nst,
            "drawn_gaussians_per_frame": n_drawn / nst, "cutoff_drawn_per_frame": n_cut_drawn / nst,
-           "evals_per_frame": E_tot / nst, "cutoff_evals_per_frame": Ecut_tot / nst,
+           "evals_per_frame": E_tot / nst, "evaluated_per_frame": Ev_tot / nst,
+           "cutoff_weights_per_frame": Ecut_tot / nst,
            "geval_per_s": E_tot / nst / render_s / 1e9, "flops_per_launch": flops,
            "blend_tflops": flops / render_s / 1e12, "pair_capacity": fr.capacity,
            "preprocess_bytes_per_launch": bytes_pre / nst, "bin_sort_bytes_per_frame": bytes_bin / nst,
@@ -670,33 +699,16 @@ def main():
 
     dev = torch.device("cuda:0")
     t_setup = time.perf_counter()
+    if args.workload == "diff":
+        if not args.profile_steps:
+            sys.exit("--workload diff is a profiler run: give --profile-steps")
+        print(json.dumps(diff_bench(args.profile_steps)))
+        return
     sc, grid, desc = workload(args.workload)
     print(f"[bench] scene n={sc.n} ready in {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
 
     if args.profile_steps:
-        # profiler runs: preprocess + bin_sort over every frame of the grid
-        # (capacity and labels, no blend), then warmup + profile_steps frames
-        # in the timed order over the frames that clip, as in the timed run
-        ds = R.DeviceScene.from_scene(sc, dev)
-        W, H = grid[0][0][0].width, grid[0][0][0].height
-        fr = R.Frame(sc.n, W, H, 8 * sc.n, dev, walked=False, pair_start=False, sorted_keys=False)
-        maxP, _, order = scan_grid(ds, fr, grid)
-        fr.grow(int(maxP * 1.05) + 4096)
-        torch.cuda.synchronize()
-        for i in range(args.warmup + args.profile_steps):
-            v, o = order[i % len(order)]
-            R.enqueue_frame(ds, fr, *grid[v][o])
-        torch.cuda.synchronize()
-        assert int(fr.bins.overflow.item()) == 0
-        if args.calibrate_copy:
-            src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
-            dst = torch.empty_like(src)
-            torch.cuda.synchronize()
-            dst.copy_(src)
-            torch.cuda.synchronize()
-        print(json.dumps({"profile_steps": args.profile_steps, "warmup": args.warmup, "pair_capacity": fr.capacity,
-                          "frames": [list(order[i % len(order)]) for i in range(args.warmup + args.profile_steps)],
-                          "copy_bytes": (256 << 20) if args.calibrate_copy else 0}))
+        profile_run(args, sc, grid, dev)
         return
 
     main_m = measure(sc, grid, args, args.reps, args.workload)
@@ -708,8 +720,11 @@ def main():
     roofline = {"bound": "alu", "kernel": "blend_kernel (rara_render)", "achieved": main_m["blend_tflops"],
                 "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": main_m["blend_tflops"] * 1e12 / PEAK_FP32,
                 "traffic": blend_traffic(), "flops_per_launch": main_m["flops_per_launch"],
-                "evals_per_launch": main_m["evals_per_frame"],
-                "cutoff_evals_per_launch": main_m["cutoff_evals_per_frame"],
+                "evaluated_per_launch": main_m["evaluated_per_frame"],
+                "cutoff_weights_per_launch": main_m["cutoff_weights_per_frame"],
+                "walked_evals_per_launch": main_m["evals_per_frame"],
+                "flops_model": f"{FLOPS_EVAL} per evaluation the kernel performs for a live pixel + {FLOPS_CUT} per "
+                               "clip weight it evaluates (FMA = 2, exp/rcp/sqrt = 1)",
                 "avg_launch_ms": st["render"],
                 "frac_of_unpacked_fp32": main_m["blend_tflops"] * 1e12 / PEAK_FP32_UNPACKED,
                 "window": "the timed frames (every frame clips)",

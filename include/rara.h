@@ -251,13 +251,18 @@ rara_status rara_bin_sort(const rara_projected* proj, int64_t n, const rara_came
  * Outputs (device, caller-allocated): image [3][H][W] float = C + T bg,
  * final_T [H][W] float, n_contrib [H][W] uint32 (1-based index in the tile
  * list of the last composited Gaussian, used by the backward), and optional
- * n_walked [H][W] uint32 (entries examined; may be NULL).  bg is a host
- * array of 3 floats.
+ * n_walked [H][W] uint32 (entries examined; may be NULL), and optional
+ * n_eval [2][H][W] uint32 (may be NULL), a measure of the work done rather
+ * than part of the method: plane 0 counts the entries whose alpha the launch
+ * evaluated for the pixel while the pixel was live (the entries a
+ * conservative test lets reach the pixel's 8x8 quadrant, or in a long list
+ * its 8x2 strip, with alpha >= 1/255), plane 1 how many of those needed the
+ * clip weight of a CUTOFF Gaussian.  bg is a host array of 3 floats.
  * Errors: RARA_ERR_INVALID for null pointers or a camera that differs in size
  * from the one binned (not detectable: the caller must pass the same camera). */
 rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned* bins, const rara_camera* cam,
                         const rara_plane* plane, const float* bg, float* image, float* final_T,
-                        uint32_t* n_contrib, uint32_t* n_walked, void* stream);
+                        uint32_t* n_contrib, uint32_t* n_walked, uint32_t* n_eval, void* stream);
 
 /* Gradient of a scalar loss L given dL/dimage [3][H][W] (device), through the
  * blend (re-walking each tile list from n_contrib back to front, with the

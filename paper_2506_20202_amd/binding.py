@@ -80,7 +80,8 @@ def lib():
         L.rara_preprocess.argtypes = [PG, PC, PP, PJ, _P]
         L.rara_bin_sort.argtypes = [PJ, ctypes.c_int64, PC, ctypes.c_int64, _P, ctypes.c_size_t, PB, _P]
         L.rara_bin_sort_static.argtypes = [PJ, ctypes.c_int64, PC, ctypes.c_int64, PB, _P]
-        L.rara_render.argtypes = [PJ, ctypes.c_int64, PB, PC, PP, ctypes.POINTER(ctypes.c_float), _P, _P, _P, _P, _P]
+        L.rara_render.argtypes = [PJ, ctypes.c_int64, PB, PC, PP, ctypes.POINTER(ctypes.c_float), _P, _P, _P, _P, _P,
+                                  _P]
         L.rara_render_backward.argtypes = [PG, PC, PP, ctypes.POINTER(ctypes.c_float), PJ, PB, ctypes.c_int64, _P, _P,
                                            _P, PR, _P, ctypes.c_size_t, _P]
         L.rara_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
@@ -161,11 +162,11 @@ def bin_sort_static(proj: Projected, n: int, cam: Camera, pair_capacity: int, ou
 
 
 def render(proj: Projected, n: int, bins: Binned, cam: Camera, plane: Plane, bg, image: int, final_T: int,
-           n_contrib: int, n_walked: int, stream: int):
+           n_contrib: int, n_walked: int, stream: int, n_eval: int = 0):
     bgc = (ctypes.c_float * 3)(*[float(v) for v in bg])
     _check("rara_render", lib().rara_render(ctypes.byref(proj), n, ctypes.byref(bins), ctypes.byref(cam),
                                             ctypes.byref(plane), bgc, _P(image), _P(final_T), _P(n_contrib),
-                                            _P(n_walked or None), _P(stream)))
+                                            _P(n_walked or None), _P(n_eval or None), _P(stream)))
 
 
 def render_backward(g: Gaussians, cam: Camera, plane: Plane, bg, proj: Projected, bins: Binned, pair_capacity: int,

@@ -280,7 +280,7 @@ rara_status rara_bin_sort_static(const rara_projected* proj, int64_t n, const ra
 
 rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned* bins, const rara_camera* cam,
                         const rara_plane* plane, const float* bg, float* image, float* final_T, uint32_t* n_contrib,
-                        uint32_t* n_walked, void* stream)
+                        uint32_t* n_walked, uint32_t* n_eval, void* stream)
 {
     if (!proj || n < 0 || !bins || !bg || !image || !final_T || !n_contrib) return RARA_ERR_INVALID;
     if (!proj->splat || !proj->ray || !bins->vals || !bins->ranges || !bins->overflow || !bins->work)
@@ -292,7 +292,7 @@ rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned
     const RenderParams rp = make_render_params(cp, pp, bg);
     const hipError_t e = launch_blend(static_cast<const Splat*>(proj->splat), static_cast<const RayRec*>(proj->ray),
                                       reinterpret_cast<const float2*>(proj->ray_ext), *bins, rp, image, final_T,
-                                      n_contrib, n_walked, static_cast<hipStream_t>(stream));
+                                      n_contrib, n_walked, n_eval, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
 }
 

@@ -89,7 +89,8 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
                                   const uint2 rg, int tile, const RenderParams& p, float4* s_a, float4* s_b,
                                   float2* s_c, CutRec* s_cut, float2* s_ext, float2* s_rate,
                                   float* __restrict__ image, float* __restrict__ final_T,
-                                  uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
+                                  uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked,
+                                  uint32_t* __restrict__ n_eval)
 {
     const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -101,6 +102,7 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
     float T = 1.0f, thr = inside ? kAlphaMin : 2.0f;   // pixels outside the image never take part
     float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     uint32_t last = 0u, walked = 0u;
+    uint32_t ev = 0u, evc = 0u;   // evaluations while live, and clip weights among them (kWalked only)
 
     // Long lists set the tail of the launch: their waves get issue priority over
     // the short tiles sharing their SIMD (wave priority only; no effect on results).
@@ -163,6 +165,7 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
                         const float cb_ = s_c[e].x;
                         const float dx = lpx - a.x, dy = lpy - a.y;
                         const float a0 = entry_a0(entry_power(a, b, dx, dy), b.y);
+                        if (kWalked) ev += thr < 1.0f ? 1u : 0u;
                         composite(fminf(kAlphaMax, a0), b.z, b.w, cb_, kofs + e, T, thr, C0, C1, C2, last, walked);
                     }
                 } else {
@@ -175,6 +178,7 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
                         const float dx = lpx - a.x, dy = lpy - a.y;
                         const float a0 = entry_a0(entry_power(a, b, dx, dy), b.y);
                         float alpha = fminf(kAlphaMax, a0);   // w = 1
+                        if (kWalked) ev += thr < 1.0f ? 1u : 0u;
                         if ((cutb >> j) & 1ull) {
                             // alpha <= a0 (w <= 1): when no pixel can reach its threshold the
                             // entry changes nothing and its weight is not needed
@@ -184,6 +188,7 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
                                                                           strict)
                                                     : chord_weight_flat(s_cut[e], dx, dy, p.ax, p.ay, strict);
                             alpha = fminf(kAlphaMax, a0 * w);
+                            if (kWalked) evc += thr < 1.0f ? 1u : 0u;
                         }
                         composite(alpha, b.z, b.w, cb_, kofs + e, T, thr, C0, C1, C2, last, walked);
                     }
@@ -203,7 +208,235 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
     final_T[pix] = T;
     n_contrib[pix] = last;
     // a pixel still live at the end examined the whole list
-    if (kWalked) n_walked[pix] = thr < 1.0f ? rg.y - rg.x : walked;
+    if (kWalked && n_walked) n_walked[pix] = thr < 1.0f ? rg.y - rg.x : walked;
+    if (kWalked && n_eval) {
+        n_eval[pix] = ev;
+        n_eval[HW + pix] = evc;
+    }
+}
+
+// ---- long lists: quadrant units ---------------------------------------------
+//
+// A tile whose list holds kHeavyList entries or more runs as four
+// workgroups, one per 8x8 quadrant, so that its work spreads over four CUs.
+// Wave w of a unit owns strip w of the quadrant (rows 2w, 2w + 1: 16 pixels)
+// with four lanes per pixel: lane 4 p + j evaluates, for pixel p, the j-th of
+// the next four entries of the list that reach the strip.  The four alphas of
+// a pixel are then composited in list order with a prefix product over its
+// lanes: with f_j = 1 - alpha_j for a taken entry (alpha_j at or above the
+// pixel's threshold) and 1 otherwise, entry j sees T_j = T prod_{i<j} f_i;
+// it is composited (weight alpha_j T_j) when T_j f_j stays at or above 1e-4,
+// and the first taken entry that would go below finishes the pixel with
+// T = T_j (T_j f_j only decreases along the four entries, so no later entry
+// is composited).  Each lane keeps its own colour sums, last contributor
+// and finishing index; the four are combined when the unit ends.
+
+// quad_perm selectors (lane i of each group of four reads lane sel[i])
+constexpr int kQpPrev = 0x90;      // [0, 0, 1, 2]
+constexpr int kQpPrev2 = 0x40;     // [0, 0, 0, 1]
+constexpr int kQpSwap1 = 0xB1;     // [1, 0, 3, 2]
+constexpr int kQpSwap2 = 0x4E;     // [2, 3, 0, 1]
+constexpr int kQpLast = 0xFF;      // [3, 3, 3, 3]
+
+template <int kSel>
+__device__ inline float qperm(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), kSel, 0xf, 0xf, false));
+}
+
+template <int kSel>
+__device__ inline uint32_t qperm_u(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kSel, 0xf, 0xf, false);
+}
+
+__device__ inline float quad_sum(float v)
+{
+    v += qperm<kQpSwap1>(v);
+    return v + qperm<kQpSwap2>(v);
+}
+
+__device__ inline uint32_t quad_sum_u(uint32_t v)
+{
+    v += qperm_u<kQpSwap1>(v);
+    return v + qperm_u<kQpSwap2>(v);
+}
+
+__device__ inline uint32_t quad_max(uint32_t v)
+{
+    const uint32_t a = qperm_u<kQpSwap1>(v);
+    v = a > v ? a : v;
+    const uint32_t b = qperm_u<kQpSwap2>(v);
+    return b > v ? b : v;
+}
+
+// One step of four entries for one pixel (see above); j = lane & 3.  The
+// common case, where no pixel of the wave finishes in the step, takes a short
+// path: every taken entry is composited and T becomes T prod f.
+__device__ inline void composite4(float alpha, float cr, float cg, float cb, uint32_t k1, int j, float& T, float& thr,
+                                  float& C0, float& C1, float& C2, uint32_t& last, uint32_t& walked)
+{
+    const bool take = alpha >= thr;
+    const float f = take ? 1.0f - alpha : 1.0f;
+    // inclusive prefix product of f over the pixel's lanes (every lane takes
+    // part in each DPP move; the lane's own factor is selected afterwards)
+    float q = f;
+    const float t1 = qperm<kQpPrev>(q);
+    q = j >= 1 ? q * t1 : q;
+    const float t2 = qperm<kQpPrev2>(q);
+    q = j >= 2 ? q * t2 : q;
+    const float qp = qperm<kQpPrev>(q);
+    const float ex = j >= 1 ? qp : 1.0f;
+    const float Tj = T * ex;
+    const float tT = T * q;
+    const float t3 = qperm<kQpLast>(tT);
+    if (__ballot(take && tT < kTMin) == 0ull) {
+        const float wt = take ? alpha * Tj : 0.0f;
+        C0 = fmaf(wt, cr, C0);
+        C1 = fmaf(wt, cg, C1);
+        C2 = fmaf(wt, cb, C2);
+        last = take ? k1 : last;
+        T = t3;
+        return;
+    }
+    const bool ok = take && tT >= kTMin;
+    const bool fin = take && !ok;
+    const float wt = ok ? alpha * Tj : 0.0f;
+    C0 = fmaf(wt, cr, C0);
+    C1 = fmaf(wt, cg, C1);
+    C2 = fmaf(wt, cb, C2);
+    last = ok ? k1 : last;
+    // several lanes may be taken below 1e-4; the first of them finishes the
+    // pixel, and it has the largest T_j among them (each taken entry lowers
+    // T_j of the next by its factor f < 1).  v >= 0, so its bits order like
+    // unsigned integers: an integer max.
+    uint32_t v = fin ? __float_as_uint(Tj) : 0u;
+    v = quad_max(v);
+    walked = (fin && __float_as_uint(Tj) == v) ? k1 : walked;
+    const bool done = v != 0u;
+    T = done ? __uint_as_float(v) : t3;
+    thr = done ? 2.0f : thr;
+}
+
+constexpr int kUnitBatch = 224;   // entries staged per batch, as the tile path (under 20 KB of LDS)
+
+template <bool kWalked>
+__device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
+                                  const uint32_t* __restrict__ vals, const uint2 rg, int tile, int quad,
+                                  const RenderParams& p, float4* s_a, float4* s_b, float2* s_c, CutRec* s_cut,
+                                  uint8_t* s_list,
+                                  float* __restrict__ image, float* __restrict__ final_T,
+                                  uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked,
+                                  uint32_t* __restrict__ n_eval)
+{
+    const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int j = lane & 3, pp = lane >> 2;
+    const int ox8 = (quad & 1) * 8 + (pp & 7), oy8 = (quad >> 1) * 8 + 2 * wave + (pp >> 3);
+    const float lpx = (float)ox8, lpy = (float)oy8;
+    const int px = tx * kTile + ox8, py = ty * kTile + oy8;
+    const bool inside = px < p.W && py < p.H;
+
+    float T = 1.0f, thr = inside ? kAlphaMin : 2.0f;
+    float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+    uint32_t last = 0u, walked = 0u, ev = 0u, evc = 0u;
+    // the long lists set the tail of the launch: issue priority over the short tiles
+    __builtin_amdgcn_s_setprio(3);
+
+    const double ox = (double)(tx * kTile), oy = (double)(ty * kTile);
+    const bool plane_on = p.plane_enabled != 0;
+    const bool strict = (p.plane_enabled & RARA_CLIP_STRICT_MISS) != 0;
+    bool live = __ballot(thr < 1.0f) != 0ull;
+
+    for (uint32_t base = rg.x; base < rg.y; base += kUnitBatch) {
+        if (!__syncthreads_or(live ? 1 : 0)) break;   // also: the previous batch has been read
+        const uint32_t idx = base + (uint32_t)tid;
+        float2 sc = make_float2(0.0f, 0.0f);   // reaches no strip
+        if (tid < kUnitBatch && idx < rg.y) {
+            const uint32_t id = vals[idx];
+            const Splat sp = splats[id];
+            float4 sa, sb;
+            uint32_t sm;
+            stage_entry_strips(sp, ox, oy, quad, sa, sb, sc, sm);
+            s_a[tid] = sa;
+            s_b[tid] = sb;
+            if (sp.label == RARA_LABEL_CUTOFF && plane_on && sm) {
+                const float4* rr = reinterpret_cast<const float4*>(rays + id);
+                s_cut[tid].a = rr[0];
+                s_cut[tid].b = rr[1];
+                s_cut[tid].c = rr[2];
+            }
+        }
+        if (tid < kBatchSlots) s_c[tid] = sc;
+        __syncthreads();
+        if (!live) continue;
+        const uint32_t cnt = rg.y - base < (uint32_t)kUnitBatch ? rg.y - base : (uint32_t)kUnitBatch;
+        const uint32_t kofs = base - rg.x + 1u;
+        for (uint32_t sub = 0; sub < cnt && live; sub += 64) {
+            const uint32_t lm = __float_as_uint(s_c[sub + lane].y);
+            const bool mine = (lm >> (8 + wave)) & 1u;
+            const uint64_t todo = __ballot(mine);
+            // the window's entries that reach the strip, in list order, listed
+            // in this wave's row of s_list (a wave's own LDS writes and reads
+            // are ordered)
+            const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(todo >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)todo, 0u));
+            if (mine) s_list[wave * 64 + pos] = (uint8_t)lane;
+            const uint32_t nsel = (uint32_t)__builtin_popcountll(todo);
+            int steps = 0;
+            for (uint32_t k = 0; k < nsel; k += 4) {
+                // lane j of each pixel takes the (k + j)-th of them
+                const bool valid = k + (uint32_t)j < nsel;
+                const uint32_t e = s_list[wave * 64 + (valid ? k + (uint32_t)j : k)];
+                const uint32_t E = sub + e;
+                const float4 a = s_a[E], b = s_b[E];
+                const float2 c2 = s_c[E];
+                const float cb_ = c2.x;
+                const float dx = lpx - a.x, dy = lpy - a.y;
+                const float a0 = entry_a0(entry_power(a, b, dx, dy), b.y);
+                float alpha = fminf(kAlphaMax, a0);   // w = 1
+                const bool cut = plane_on && (__float_as_uint(c2.y) & 0xffu) == RARA_LABEL_CUTOFF;
+                // alpha <= a0 (w <= 1): the weights are needed only when some live
+                // pixel's CUTOFF entry can reach its threshold
+                if (__ballot(valid && cut && a0 >= thr) != 0ull) {
+                    const float w = chord_weight_flat(s_cut[E], dx, dy, p.ax, p.ay, strict);
+                    alpha = cut ? fminf(kAlphaMax, a0 * w) : alpha;
+                    if (kWalked) evc += (valid && cut && thr < 1.0f) ? 1u : 0u;
+                }
+                if (kWalked) ev += (valid && thr < 1.0f) ? 1u : 0u;
+                composite4(valid ? alpha : 0.0f, b.z, b.w, cb_, kofs + E, j, T, thr, C0, C1, C2, last, walked);
+                if (++steps == 4) {
+                    steps = 0;
+                    live = __ballot(thr < 1.0f) != 0ull;
+                    if (!live) break;
+                }
+            }
+            live = __ballot(thr < 1.0f) != 0ull;
+        }
+    }
+
+    C0 = quad_sum(C0);
+    C1 = quad_sum(C1);
+    C2 = quad_sum(C2);
+    last = quad_max(last);
+    walked = quad_max(walked);
+    if (kWalked) {
+        ev = quad_sum_u(ev);
+        evc = quad_sum_u(evc);
+    }
+    if (!inside || j != 0) return;
+    const int64_t HW = (int64_t)p.H * p.W;
+    const int64_t pix = (int64_t)py * p.W + px;
+    image[pix] = C0 + T * p.bg[0];
+    image[HW + pix] = C1 + T * p.bg[1];
+    image[2 * HW + pix] = C2 + T * p.bg[2];
+    final_T[pix] = T;
+    n_contrib[pix] = last;
+    if (kWalked && n_walked) n_walked[pix] = thr < 1.0f ? rg.y - rg.x : walked;
+    if (kWalked && n_eval) {
+        n_eval[pix] = ev;
+        n_eval[HW + pix] = evc;
+    }
 }
 
 template <bool kWalked, bool kRegion>
@@ -212,10 +445,15 @@ __device__ __forceinline__ void blend_block(const Splat* __restrict__ splats, co
                                             const uint2* __restrict__ ranges, const uint32_t* __restrict__ work,
                                             const RenderParams& p, float* __restrict__ image,
                                             float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
-                                            uint32_t* __restrict__ n_walked)
+                                            uint32_t* __restrict__ n_walked, uint32_t* __restrict__ n_eval)
 {
     uint32_t tile;
-    if (!tile_of_block(blockIdx.x, work, p.num_tiles, tile)) return;
+    int quad = -1;
+    // clip regions: one workgroup per tile (tile_of_block); a single plane:
+    // long lists as quadrant units (unit_of_block)
+    if (kRegion ? !tile_of_block(blockIdx.x, work, p.num_tiles, tile)
+                : !unit_of_block(blockIdx.x, work, p.num_tiles, tile, quad))
+        return;
     if (tile >= (uint32_t)p.num_tiles) return;
     constexpr int kB = batch_of<kRegion>();
     __shared__ float4 s_a[kB], s_b[kB];
@@ -223,12 +461,19 @@ __device__ __forceinline__ void blend_block(const Splat* __restrict__ splats, co
     __shared__ CutRec s_cut[kB];
     __shared__ float2 s_ext[kRegion ? kB * (kMaxPlanes - 1) : 1];
     __shared__ float2 s_rate[kMaxPlanes - 1];
+    __shared__ uint8_t s_list[kRegion ? 1 : 4 * 64];
+    if (!kRegion && quad >= 0) {
+        static_assert(kUnitBatch <= kTileBatch, "the units reuse the tile path's LDS");
+        blend_unit<kWalked>(splats, rays, vals, ranges[tile], (int)tile, quad, p, s_a, s_b, s_c, s_cut, s_list,
+                            image, final_T, n_contrib, n_walked, n_eval);
+        return;
+    }
     if (kRegion) {
         // the further planes' per-frame rates; the first batch's barrier orders them before any visit
         if (threadIdx.x < kMaxPlanes - 1) s_rate[threadIdx.x] = make_float2(p.xax[threadIdx.x], p.xay[threadIdx.x]);
     }
     blend_tile<kWalked, kRegion>(splats, rays, ray_ext, vals, ranges[tile], (int)tile, p, s_a, s_b, s_c, s_cut, s_ext,
-                                 s_rate, image, final_T, n_contrib, n_walked);
+                                 s_rate, image, final_T, n_contrib, n_walked, n_eval);
 }
 
 template <bool kWalked>
@@ -236,10 +481,12 @@ __global__ __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(8
 void blend_kernel(const Splat* __restrict__ splats, const RayRec* __restrict__ rays, const uint32_t* __restrict__ vals,
                   const uint2* __restrict__ ranges, const uint32_t* __restrict__ work,
                   const int32_t* __restrict__ overflow, RenderParams p, float* __restrict__ image,
-                  float* __restrict__ final_T, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked)
+                  float* __restrict__ final_T, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked,
+                  uint32_t* __restrict__ n_eval)
 {
     if (*overflow) return;
-    blend_block<kWalked, false>(splats, rays, nullptr, vals, ranges, work, p, image, final_T, n_contrib, n_walked);
+    blend_block<kWalked, false>(splats, rays, nullptr, vals, ranges, work, p, image, final_T, n_contrib, n_walked,
+                                n_eval);
 }
 
 // Clip-region variant (p.plane_count > 1): the further planes' terms staged
@@ -251,10 +498,11 @@ void blend_region_kernel(const Splat* __restrict__ splats, const RayRec* __restr
                          const uint2* __restrict__ ranges, const uint32_t* __restrict__ work,
                          const int32_t* __restrict__ overflow, RenderParams p, float* __restrict__ image,
                          float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
-                         uint32_t* __restrict__ n_walked)
+                         uint32_t* __restrict__ n_walked, uint32_t* __restrict__ n_eval)
 {
     if (*overflow) return;
-    blend_block<kWalked, true>(splats, rays, ray_ext, vals, ranges, work, p, image, final_T, n_contrib, n_walked);
+    blend_block<kWalked, true>(splats, rays, ray_ext, vals, ranges, work, p, image, final_T, n_contrib, n_walked,
+                               n_eval);
 }
 
 // Frame-graph variant: render parameters read from device memory.
@@ -268,31 +516,37 @@ void blend_fp_kernel(const Splat* __restrict__ splats, const RayRec* __restrict_
 {
     if (*overflow) return;
     const RenderParams p = fp->render;
-    blend_block<kWalked, false>(splats, rays, nullptr, vals, ranges, work, p, image, final_T, n_contrib, n_walked);
+    blend_block<kWalked, false>(splats, rays, nullptr, vals, ranges, work, p, image, final_T, n_contrib, n_walked,
+                                nullptr);
 }
 
 }  // namespace
 
 hipError_t launch_blend(const Splat* splat, const RayRec* ray, const float2* ray_ext, const rara_binned& bins,
                         const RenderParams& p, float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked,
-                        hipStream_t s)
+                        uint32_t* n_eval, hipStream_t s)
 {
-    const unsigned grid = (unsigned)tiles_grid(p.num_tiles);
     const uint2* ranges = reinterpret_cast<const uint2*>(bins.ranges);
+    const bool count = n_walked || n_eval;
     if (p.plane_enabled && p.plane_count > 1) {
-        if (n_walked)
+        const unsigned grid = (unsigned)tiles_grid(p.num_tiles);
+        if (count)
             hipLaunchKernelGGL(blend_region_kernel<true>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, ray_ext,
-                               bins.vals, ranges, bins.work, bins.overflow, p, image, final_T, n_contrib, n_walked);
+                               bins.vals, ranges, bins.work, bins.overflow, p, image, final_T, n_contrib, n_walked,
+                               n_eval);
         else
             hipLaunchKernelGGL(blend_region_kernel<false>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, ray_ext,
-                               bins.vals, ranges, bins.work, bins.overflow, p, image, final_T, n_contrib, n_walked);
-    } else if (n_walked) {
-        hipLaunchKernelGGL(blend_kernel<true>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals, ranges,
-                           bins.work, bins.overflow, p, image, final_T, n_contrib, n_walked);
-    } else {
-        hipLaunchKernelGGL(blend_kernel<false>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals, ranges,
-                           bins.work, bins.overflow, p, image, final_T, n_contrib, n_walked);
+                               bins.vals, ranges, bins.work, bins.overflow, p, image, final_T, n_contrib, n_walked,
+                               n_eval);
+        return hipGetLastError();
     }
+    const unsigned grid = (unsigned)blend_grid(p.num_tiles);
+    if (count)
+        hipLaunchKernelGGL(blend_kernel<true>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals, ranges,
+                           bins.work, bins.overflow, p, image, final_T, n_contrib, n_walked, n_eval);
+    else
+        hipLaunchKernelGGL(blend_kernel<false>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals, ranges,
+                           bins.work, bins.overflow, p, image, final_T, n_contrib, n_walked, n_eval);
     return hipGetLastError();
 }
 
@@ -300,7 +554,7 @@ hipError_t launch_blend_fp(const Splat* splat, const RayRec* ray, const rara_bin
                            int num_tiles, float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked,
                            hipStream_t s)
 {
-    const unsigned grid = (unsigned)tiles_grid(num_tiles);
+    const unsigned grid = (unsigned)blend_grid(num_tiles);
     const uint2* ranges = reinterpret_cast<const uint2*>(bins.ranges);
     if (n_walked)
         hipLaunchKernelGGL(blend_fp_kernel<true>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, bins.vals, ranges,

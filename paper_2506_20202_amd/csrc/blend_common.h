@@ -197,10 +197,12 @@ struct QuadForm {
     float dx_, dy_;  // det / cc, det / ca
 };
 
-__device__ inline bool quad_reach(const QuadForm& f, float m2, float qx, float qy)
+// Box of pixel centres [bx, bx + w] x [by, by + h] (tile coordinates); an 8x8
+// quadrant is w = h = 7.
+__device__ inline bool box_reach(const QuadForm& f, float m2, float bx, float by, float w, float h)
 {
-    const float x0 = qx - f.mx, x1 = (qx + 7.0f) - f.mx;
-    const float y0 = qy - f.my, y1 = (qy + 7.0f) - f.my;
+    const float x0 = bx - f.mx, x1 = (bx + w) - f.mx;
+    const float y0 = by - f.my, y1 = (by + h) - f.my;
     const bool inside = (x0 <= 0.0f) && (x1 >= 0.0f) && (y0 <= 0.0f) && (y1 >= 0.0f);
     auto edge_x = [&](float X) {
         const float ys = f.kx * X;
@@ -214,6 +216,32 @@ __device__ inline bool quad_reach(const QuadForm& f, float m2, float qx, float q
     };
     const float qmin = fminf(fminf(edge_x(x0), edge_x(x1)), fminf(edge_y(y0), edge_y(y1)));
     return inside || qmin <= m2;
+}
+
+__device__ inline bool quad_reach(const QuadForm& f, float m2, float qx, float qy)
+{
+    return box_reach(f, m2, qx, qy, 7.0f, 7.0f);
+}
+
+// The reach test's form of a splat (centre relative to the tile) and its
+// padded threshold m2; false when the opacity alone is below 1/255.
+__device__ inline bool reach_form(const Splat& nx, float mx, float my, QuadForm& f, float& m2)
+{
+    const float s255 = 255.0f * nx.op;
+    if (!(s255 > 1.0f)) return false;
+    // padded by 2 % + 0.02 against the rounding of the form, det and log
+    m2 = fmaf(2.0f * __logf(s255), 1.02f, 0.02f);
+    const float det = fmaf(nx.ca, nx.cc, -nx.cb * nx.cb);
+    const float ica = 1.0f / nx.ca, icc = 1.0f / nx.cc;
+    f.mx = mx;
+    f.my = my;
+    f.ca = nx.ca;
+    f.cc = nx.cc;
+    f.kx = -nx.cb * icc;
+    f.ky = -nx.cb * ica;
+    f.dx_ = fmaxf(det, 0.0f) * icc;
+    f.dy_ = fmaxf(det, 0.0f) * ica;
+    return true;
 }
 
 // Staged form of one list entry.  s_a: centre (tile-relative), pre-scaled
@@ -230,27 +258,37 @@ __device__ inline void stage_entry(const Splat& nx, double ox, double oy, uint32
     sa = make_float4(mx, my, nx.ca * kq, -nx.cb * kLog2e);
     sb = make_float4(nx.cc * kq, nx.op, nx.r, nx.g);
     qmask = 0u;
-    const float s255 = 255.0f * nx.op;
-    if (s255 > 1.0f) {
-        // padded by 2 % + 0.02 against the rounding of the form, det and log
-        const float m2 = fmaf(2.0f * __logf(s255), 1.02f, 0.02f);
-        const float det = fmaf(nx.ca, nx.cc, -nx.cb * nx.cb);
-        const float ica = 1.0f / nx.ca, icc = 1.0f / nx.cc;
-        QuadForm f;
-        f.mx = mx;
-        f.my = my;
-        f.ca = nx.ca;
-        f.cc = nx.cc;
-        f.kx = -nx.cb * icc;
-        f.ky = -nx.cb * ica;
-        f.dx_ = fmaxf(det, 0.0f) * icc;
-        f.dy_ = fmaxf(det, 0.0f) * ica;
+    QuadForm f;
+    float m2;
+    if (reach_form(nx, mx, my, f, m2)) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if ((want >> q) & 1u)
                 qmask |= quad_reach(f, m2, (float)((q & 1) * 8), (float)((q >> 1) * 8)) ? (1u << q) : 0u;
     }
     sc = make_float4(nx.b, __uint_as_float(nx.label | (qmask << 8)), __uint_as_float(id), 0.0f);
+}
+
+// The same staging for a long-list quadrant unit: bit w of the mask is set
+// when the entry can reach strip w of quadrant `quad` (the pixel centres of
+// quadrant rows 2w and 2w + 1, tile columns qx .. qx + 7).
+__device__ inline void stage_entry_strips(const Splat& nx, double ox, double oy, int quad, float4& sa, float4& sb,
+                                          float2& sc, uint32_t& smask)
+{
+    const float kq = -0.5f * kLog2e;
+    const float mx = (float)(nx.mx - ox), my = (float)(nx.my - oy);
+    sa = make_float4(mx, my, nx.ca * kq, -nx.cb * kLog2e);
+    sb = make_float4(nx.cc * kq, nx.op, nx.r, nx.g);
+    smask = 0u;
+    QuadForm f;
+    float m2;
+    if (reach_form(nx, mx, my, f, m2)) {
+        const float qx = (float)((quad & 1) * 8), qy = (float)((quad >> 1) * 8);
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+            smask |= box_reach(f, m2, qx, qy + 2.0f * (float)w, 7.0f, 1.0f) ? (1u << w) : 0u;
+    }
+    sc = make_float2(nx.b, __uint_as_float(nx.label | (smask << 8)));
 }
 
 // Tile of blend workgroup b.  The work list holds the H long-list tiles
@@ -262,9 +300,9 @@ __device__ inline void stage_entry(const Splat& nx, double ox, double oy, uint32
 // a tile row, whose tiles share splats in one L2), chunk c to XCD c mod 8, so
 // that the dense parts of the image spread over every XCD.  tiles_grid(T)
 // workgroups cover both groups.
-__device__ inline bool tile_of_block(uint32_t b, const uint32_t* __restrict__ work, int num_tiles, uint32_t& tile)
+__device__ inline bool tile_of_block_in(uint32_t b, const uint32_t* __restrict__ work, uint32_t H, uint32_t num,
+                                        uint32_t& tile)
 {
-    const uint32_t H = work[num_tiles];
     const uint32_t hb = (H + 7u) & ~7u;
     if (b < hb) {
         const uint32_t x = b & 7u, k = b >> 3;
@@ -276,9 +314,40 @@ __device__ inline bool tile_of_block(uint32_t b, const uint32_t* __restrict__ wo
     const uint32_t bb = b - hb;   // hb is a multiple of 8: bb and b share an XCD
     const uint32_t x = bb & 7u, k = bb >> 3;
     const uint32_t i = (x + 8u * (k / kDealChunk)) * kDealChunk + k % kDealChunk;
-    if (i >= (uint32_t)num_tiles - H) return false;
+    if (i >= num - H) return false;
     tile = work[H + i];
     return true;
+}
+
+__device__ inline bool tile_of_block(uint32_t b, const uint32_t* __restrict__ work, int num_tiles, uint32_t& tile)
+{
+    return tile_of_block_in(b, work, work[num_tiles], (uint32_t)num_tiles, tile);
+}
+
+// Work unit of forward blend workgroup b: the first U = min(H, kMaxUnitTiles)
+// long-list tiles are blended as four quadrant units each, units 4i .. 4i + 3
+// of the i-th of them on an XCD on that XCD (b mod 8), one after the other,
+// so that the four units of a tile share one L2; the other tiles follow as in
+// tile_of_block (the remaining long tiles first), one workgroup each.  quad
+// is -1 for a whole tile.  blend_grid(T) workgroups cover every case.
+__device__ inline bool unit_of_block(uint32_t b, const uint32_t* __restrict__ work, int num_tiles, uint32_t& tile,
+                                     int& quad)
+{
+    const uint32_t H = work[num_tiles];
+    const uint32_t U = H < kMaxUnitTiles ? H : kMaxUnitTiles;
+    const uint32_t ub = (U + 7u) & ~7u;
+    if (b < 4u * ub) {
+        const uint32_t x = b & 7u, k = b >> 3;
+        const uint32_t i = k >> 2;
+        const uint32_t q8 = U >> 3, r8 = U & 7u;
+        if (i >= q8 + (x < r8 ? 1u : 0u)) return false;
+        tile = work[x * q8 + (x < r8 ? x : r8) + i];
+        quad = (int)(k & 3u);
+        return true;
+    }
+    quad = -1;
+    // a multiple of 8 below b: the two share an XCD
+    return tile_of_block_in(b - 4u * ub, work + U, H - U, (uint32_t)num_tiles - U, tile);
 }
 
 }  // namespace rara

@@ -110,6 +110,15 @@ constexpr uint32_t kHeavyList = 1024;
 // fullest XCD holds up to 2 kDealChunk more than an even share)
 constexpr uint32_t kDealChunk = 16;
 inline int64_t tiles_grid(int64_t tiles) { return tiles + 16 + 16 * (int64_t)kDealChunk; }
+// forward blend: the first kMaxUnitTiles long-list tiles run as four quadrant
+// units each (the grid's padding, workgroups that find no work and exit, stays
+// a few thousand at most)
+constexpr uint32_t kMaxUnitTiles = 1024;
+inline int64_t blend_grid(int64_t tiles)
+{
+    const int64_t u = tiles < (int64_t)kMaxUnitTiles ? tiles : (int64_t)kMaxUnitTiles;
+    return 4 * (u + 8) + tiles_grid(tiles);
+}
 
 // ---- bin/sort workspace carve-up -------------------------------------------
 constexpr int kScanBlock = 256;      // Gaussians per scan chunk
@@ -179,6 +188,6 @@ hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const Plane
                            const rara_grads& grads, void* workspace, hipStream_t s);
 hipError_t launch_blend(const Splat* splat, const RayRec* ray, const float2* ray_ext, const rara_binned& bins,
                         const RenderParams& p, float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked,
-                        hipStream_t s);
+                        uint32_t* n_eval, hipStream_t s);
 
 }  // namespace rara

@@ -125,11 +125,15 @@ class BinBuffers:
 
 
 class ImageBuffers:
+    """image, final_T, n_contrib; with ``walked`` also n_walked and n_eval
+    (work counts: [2][H][W], evaluations and clip weights per pixel)."""
+
     def __init__(self, width: int, height: int, device="cuda", walked: bool = True):
         self.image = torch.empty((3, height, width), dtype=torch.float32, device=device)
         self.final_T = torch.empty((height, width), dtype=torch.float32, device=device)
         self.n_contrib = torch.empty((height, width), dtype=torch.int32, device=device)
         self.n_walked = torch.empty((height, width), dtype=torch.int32, device=device) if walked else None
+        self.n_eval = torch.empty((2, height, width), dtype=torch.int32, device=device) if walked else None
 
 
 class Frame:
@@ -174,7 +178,8 @@ def enqueue_frame(scene: DeviceScene, frame: Frame, cam, plane, bg=(0.0, 0.0, 0.
         B.bin_sort(pj, scene.n, c, frame.capacity, _ptr(frame.bins.workspace), frame.bins.ws_bytes, bn, sp)
     if "render" in stages:
         o = frame.out
-        B.render(pj, scene.n, bn, c, p, bg, _ptr(o.image), _ptr(o.final_T), _ptr(o.n_contrib), _ptr(o.n_walked), sp)
+        B.render(pj, scene.n, bn, c, p, bg, _ptr(o.image), _ptr(o.final_T), _ptr(o.n_contrib), _ptr(o.n_walked), sp,
+                 _ptr(o.n_eval))
 
 
 def render_checked(scene: DeviceScene, frame: Frame, cam, plane, bg=(0.0, 0.0, 0.0), slack: float = 1.25):

@@ -37,6 +37,7 @@ def collect(fr, out, n):
         final_T=out.final_T.cpu().numpy(),
         n_contrib=out.n_contrib.cpu().numpy(),
         n_walked=out.n_walked.cpu().numpy() if out.n_walked is not None else None,
+        n_eval=out.n_eval.cpu().numpy() if out.n_eval is not None else None,
     )
     res.update({"splat_" + k: v for k, v in R.splat_fields(fr.proj).items()})
     return res

@@ -182,7 +182,7 @@ def test_argument_validation_before_any_launch(B):
     # render: null outputs
     bg = (ctypes.c_float * 3)(0, 0, 0)
     assert lib.rara_render(ctypes.byref(out), 0, ctypes.byref(bins), ctypes.byref(cam), ctypes.byref(pl), bg, None,
-                           None, None, None, None) == B.RARA_ERR_INVALID
+                           None, None, None, None, None) == B.RARA_ERR_INVALID
 
 
 def test_static_bin_sort_rejects_frames_beyond_its_workspace(B):
@@ -281,7 +281,7 @@ def test_clip_regions_are_validated_on_the_host(B):
     bins.keys = bins.vals = bins.ranges = bins.num_pairs = bins.overflow = bins.work = bins.pair_start = 0x1000
     img = (ctypes.c_float * 3)()
     assert lib.rara_render(ctypes.byref(full), 10, ctypes.byref(bins), ctypes.byref(cam), ctypes.byref(box), img,
-                           fake, fake, fake, None, None) == B.RARA_ERR_INVALID
+                           fake, fake, fake, None, None, None) == B.RARA_ERR_INVALID
     grads = B.Grads()
     grads.mean = grads.scale = grads.quat = grads.opacity = grads.sh = grads.plane = 0x1000
     full.ray_ext = 0x1000

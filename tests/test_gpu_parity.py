@@ -48,6 +48,10 @@ def _full_check(sc, cam, pl, bg=(0.0, 0.0, 0.0)):
     np.testing.assert_array_equal(g["n_contrib"][ok], o["n_contrib"][ok])
     np.testing.assert_array_equal(g["n_walked"][ok], o["n_walked"][ok])
     np.testing.assert_allclose(g["final_T"][ok], o["final_T"][ok], rtol=1e-3, atol=1e-6)
+    # work counts: evaluations for live pixels (a long-list step of four entries
+    # may evaluate up to three past the pixel's last), clip weights among them
+    ev = g["n_eval"].astype(np.int64)
+    assert (ev[0] <= g["n_walked"].astype(np.int64) + 3).all() and (ev[1] <= ev[0]).all()
     return g, o
 
 
@@ -361,6 +365,18 @@ def test_long_list_parity(seed, opacity_scale, size):
 def test_long_list_clip_modes(name, mode):
     _dense_check(_dense_scene(1, 4000, 0.03, -2.3), scenes.small_camera(72),
                  scenes.Plane(DENSE_NORMAL, 0.02, enabled=mode), min_long=4)
+
+
+@pytest.mark.parametrize("seed,size", [(1, 72), (2, 100)])
+def test_long_list_plain(seed, size):
+    """Long lists without a plane: lists of 4096 entries or more still run
+    as quadrant units (four lanes per pixel), shorter ones as whole tiles."""
+    n, ls = (4000, -2.3) if size < 100 else (6000, -2.5)
+    g, _ = _dense_check(_dense_scene(seed, n, 0.03, ls), scenes.small_camera(size),
+                        scenes.Plane(DENSE_NORMAL, 0.02, enabled=False), min_long=4)
+    lens = g["ranges"][:, 1] - g["ranges"][:, 0]
+    print(f"lists of 4096 or more: {(lens >= 4096).sum()}, of 1024-4095: {((lens >= 1024) & (lens < 4096)).sum()}",
+          flush=True)
 
 
 def test_many_long_list_tiles():

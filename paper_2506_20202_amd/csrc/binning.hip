@@ -176,26 +176,31 @@ __global__ __launch_bounds__(256) void ranges_clear_kernel(uint32_t* __restrict_
 }
 
 // Blend schedule: the tiles whose list has at least kHeavyList entries come
-// first, so that the longest walks start earliest, then the others, each
-// group in tile order: work[h] = h-th long-list tile, work[H + l] = l-th other
-// tile, work[T] = H.  Tiles without pairs (end 0) get the empty range (0, 0).
+// first, so that the longest walks start earliest, and among them those with
+// at least kUnitList entries (the forward blend gives the first
+// kMaxUnitTiles of the group four workgroups each); then the other tiles;
+// each class in tile order.  work[h] = h-th long-list tile, work[H + l] = l-th
+// other tile, work[T] = H.  Tiles without pairs (end 0) get the empty range
+// (0, 0).
 //
 // One 1024-thread workgroup, so all of it runs on one CU: the accesses are
 // kept coalesced (thread t takes tiles t, t + 1024, ... of each 8192-tile
-// block) and the long-list flags are counted with wave ballots.  A tile's
-// long-list rank is the long-list count of the blocks before it, of the rounds
-// of 1024 tiles before it in its block, of the waves before it in its round,
-// and of the lanes before it in its wave.  A first sweep counts H (the ranges
-// of the first block stay in registers), the second writes the ranges and
-// the schedule.
+// block) and the class flags are counted with wave ballots.  A tile's rank in
+// its class is the class count of the blocks before it, of the rounds of 1024
+// tiles before it in its block, of the waves before it in its round, and of
+// the lanes before it in its wave.  A first sweep counts the classes (the
+// ranges of the first block stay in registers), the second writes the ranges
+// and the schedule.
 __device__ inline bool plan_heavy(uint2 r) { return r.y != 0u && r.y - r.x >= kHeavyList; }
+__device__ inline bool plan_unit(uint2 r) { return r.y != 0u && r.y - r.x >= kUnitList; }
 
 __global__ __launch_bounds__(1024) void plan_kernel(uint2* __restrict__ ranges, int num_tiles,
                                                     uint32_t* __restrict__ work)
 {
     constexpr int kRounds = 8, kBlock = kRounds * 1024;
-    __shared__ uint32_t s_cnt[kRounds * 16];   // long-list count per (round, wave), then its exclusive prefix
-    __shared__ uint32_t s_tot[16];
+    // per (round, wave): the count of each class (very long, long), then its exclusive prefix
+    __shared__ uint32_t s_cnt[2][kRounds * 16];
+    __shared__ uint32_t s_tot[2][16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     auto load_block = [&](int b0, uint2* r) {
 #pragma unroll
@@ -205,27 +210,43 @@ __global__ __launch_bounds__(1024) void plan_kernel(uint2* __restrict__ ranges, 
             if (t >= num_tiles) r[j] = make_uint2(0u, 0u);
         }
     };
-    // sweep 1: H
+    // sweep 1: the class sizes V (very long) and H (all long)
     uint2 r0[kRounds];
     load_block(0, r0);
-    uint32_t hc = 0;
+    uint32_t hc = 0, vc = 0;
 #pragma unroll
-    for (int j = 0; j < kRounds; ++j) hc += plan_heavy(r0[j]) ? 1u : 0u;
+    for (int j = 0; j < kRounds; ++j) {
+        hc += plan_heavy(r0[j]) ? 1u : 0u;
+        vc += plan_unit(r0[j]) ? 1u : 0u;
+    }
     for (int b0 = kBlock; b0 < num_tiles; b0 += kBlock) {
         uint2 r[kRounds];
         load_block(b0, r);
 #pragma unroll
-        for (int j = 0; j < kRounds; ++j) hc += plan_heavy(r[j]) ? 1u : 0u;
+        for (int j = 0; j < kRounds; ++j) {
+            hc += plan_heavy(r[j]) ? 1u : 0u;
+            vc += plan_unit(r[j]) ? 1u : 0u;
+        }
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) hc += __shfl_xor(hc, off, 64);
-    if (lane == 0) s_tot[wave] = hc;
+    for (int off = 32; off > 0; off >>= 1) {
+        hc += __shfl_xor(hc, off, 64);
+        vc += __shfl_xor(vc, off, 64);
+    }
+    if (lane == 0) {
+        s_tot[0][wave] = vc;
+        s_tot[1][wave] = hc;
+    }
     __syncthreads();
-    uint32_t H = 0;
+    uint32_t V = 0, H = 0;
 #pragma unroll
-    for (int w = 0; w < 16; ++w) H += s_tot[w];
+    for (int w = 0; w < 16; ++w) {
+        V += s_tot[0][w];
+        H += s_tot[1][w];
+    }
+    __syncthreads();   // s_tot is rewritten below
     // sweep 2: ranges and positions, block by block
-    uint32_t carry = 0;   // long-list tiles in the blocks before
+    uint32_t carry[2] = {0u, 0u};   // tiles of each class in the blocks before
     for (int b0 = 0; b0 < num_tiles; b0 += kBlock) {
         uint2 r[kRounds];
         if (b0 == 0) {
@@ -234,15 +255,20 @@ __global__ __launch_bounds__(1024) void plan_kernel(uint2* __restrict__ ranges, 
         } else {
             load_block(b0, r);
         }
-        uint64_t m[kRounds];
+        uint64_t mv[kRounds], ml[kRounds];
 #pragma unroll
         for (int j = 0; j < kRounds; ++j) {
-            m[j] = __ballot(plan_heavy(r[j]));
-            if (lane == 0) s_cnt[j * 16 + wave] = (uint32_t)__popcll(m[j]);
+            mv[j] = __ballot(plan_unit(r[j]));
+            ml[j] = __ballot(plan_heavy(r[j]) && !plan_unit(r[j]));
+            if (lane == 0) {
+                s_cnt[0][j * 16 + wave] = (uint32_t)__popcll(mv[j]);
+                s_cnt[1][j * 16 + wave] = (uint32_t)__popcll(ml[j]);
+            }
         }
         __syncthreads();
-        if (wave == 0) {   // exclusive prefix of the 128 counts in (round, wave) order, two per lane
-            const uint32_t c0 = s_cnt[2 * lane], c1 = s_cnt[2 * lane + 1];
+        if (wave < 2) {   // exclusive prefix of each class's 128 counts in (round, wave) order, two per lane
+            uint32_t* c = s_cnt[wave];
+            const uint32_t c0 = c[2 * lane], c1 = c[2 * lane + 1];
             uint32_t incl = c0 + c1;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
@@ -250,24 +276,29 @@ __global__ __launch_bounds__(1024) void plan_kernel(uint2* __restrict__ ranges, 
                 if (lane >= off) incl += o;
             }
             const uint32_t ex = incl - c0 - c1;
-            s_cnt[2 * lane] = ex;
-            s_cnt[2 * lane + 1] = ex + c0;
-            if (lane == 63) s_tot[0] = incl;
+            c[2 * lane] = ex;
+            c[2 * lane + 1] = ex + c0;
+            if (lane == 63) s_tot[wave][0] = incl;
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kRounds; ++j) {
             const int t = b0 + j * 1024 + tid;
             if (t < num_tiles) {
-                const bool heavy = ((m[j] >> lane) & 1ull) != 0ull;
-                const uint32_t hb = carry + s_cnt[j * 16 + wave] +
-                                    __builtin_amdgcn_mbcnt_hi((uint32_t)(m[j] >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m[j], 0u));
+                const bool very = ((mv[j] >> lane) & 1ull) != 0ull;
+                const bool lng = ((ml[j] >> lane) & 1ull) != 0ull;
+                const uint32_t vb = carry[0] + s_cnt[0][j * 16 + wave] +
+                                    __builtin_amdgcn_mbcnt_hi((uint32_t)(mv[j] >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mv[j], 0u));
+                const uint32_t lb = carry[1] + s_cnt[1][j * 16 + wave] +
+                                    __builtin_amdgcn_mbcnt_hi((uint32_t)(ml[j] >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)ml[j], 0u));
                 ranges[t] = r[j].y == 0u ? make_uint2(0u, 0u) : r[j];
-                work[heavy ? hb : H + (uint32_t)t - hb] = (uint32_t)t;
+                work[very ? vb : lng ? V + lb : H + (uint32_t)t - vb - lb] = (uint32_t)t;
             }
         }
-        carry += s_tot[0];
+        carry[0] += s_tot[0][0];
+        carry[1] += s_tot[1][0];
         __syncthreads();   // s_cnt and s_tot are rewritten by the next block
     }
     if (tid == 0) work[num_tiles] = H;

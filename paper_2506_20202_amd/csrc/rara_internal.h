@@ -112,8 +112,10 @@ constexpr uint32_t kDealChunk = 16;
 inline int64_t tiles_grid(int64_t tiles) { return tiles + 16 + 16 * (int64_t)kDealChunk; }
 // forward blend: the first kMaxUnitTiles long-list tiles run as four quadrant
 // units each (the grid's padding, workgroups that find no work and exit, stays
-// a few thousand at most)
-constexpr uint32_t kMaxUnitTiles = 1024;
+// a few thousand at most); the schedule puts the lists of kUnitList entries
+// or more first
+constexpr uint32_t kMaxUnitTiles = 512;
+constexpr uint32_t kUnitList = 2048;
 inline int64_t blend_grid(int64_t tiles)
 {
     const int64_t u = tiles < (int64_t)kMaxUnitTiles ? tiles : (int64_t)kMaxUnitTiles;

@@ -9,6 +9,7 @@ from paper_2506_20202_amd import renderer as R
 
 TILE = 16
 HEAVY_LIST = 1024   # lists of at least this many entries are scheduled first
+UNIT_LIST = 2048    # and among them, first, those of at least this many
 
 
 def gpu_frame(scene, cam, plane, bg=(0.0, 0.0, 0.0), capacity=None, dscene=None):
@@ -103,13 +104,15 @@ def check_ranges(g):
 
 
 def check_schedule(work, counts):
-    """The blend schedule: the tiles with long lists in tile order, then the
-    others in tile order, then their number."""
+    """The blend schedule: the tiles with long lists, those of UNIT_LIST
+    entries or more first, each class in tile order, then the others in tile
+    order, then the number of long-list tiles."""
     T = len(counts)
-    heavy = np.nonzero(counts >= HEAVY_LIST)[0]
+    very = np.nonzero(counts >= UNIT_LIST)[0]
+    heavy = np.nonzero((counts >= HEAVY_LIST) & (counts < UNIT_LIST))[0]
     light = np.nonzero(counts < HEAVY_LIST)[0]
-    assert int(work[T]) == len(heavy), (int(work[T]), len(heavy))
-    np.testing.assert_array_equal(work[:T].astype(np.int64), np.concatenate([heavy, light]))
+    assert int(work[T]) == len(very) + len(heavy), (int(work[T]), len(very), len(heavy))
+    np.testing.assert_array_equal(work[:T].astype(np.int64), np.concatenate([very, heavy, light]))
 
 
 def check_lists(g, o, tiles=None, skip=()):

@@ -317,6 +317,15 @@ def test_constants_agree_between_oracle_and_kernels():
     assert oracle.KAPPA ** 2 == 9.0
 
 
+def test_schedule_constants_agree_with_the_gpu_tests():
+    """The GPU tests check the blend schedule with their own copies of the
+    long-list thresholds; they must be the kernels' values."""
+    internal = open(os.path.join(ROOT, "paper_2506_20202_amd", "csrc", "rara_internal.h")).read()
+    from tests import gpu_helpers as H
+    assert int(re.search(r"constexpr uint32_t kHeavyList = (\d+);", internal).group(1)) == H.HEAVY_LIST
+    assert int(re.search(r"constexpr uint32_t kUnitList = (\d+);", internal).group(1)) == H.UNIT_LIST
+
+
 def test_sh_constants_agree_with_closed_forms():
     """The kernel's SH normalisations (decimal literals) equal the closed forms
     the oracle evaluates."""

@@ -90,8 +90,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-peaks", action="store_true", help="skip the copy and FMA-loop peak measurements")
-    ap.add_argument("--serve-requests", type=int, default=240)
-    ap.add_argument("--serve-load", type=float, default=0.5, help="arrival rate as a fraction of saturation")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per load point")
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9],
+                    help="arrival rates as fractions of the saturation rate")
     ap.add_argument("--serve-budget-gib", type=float, default=32.0,
                     help="HBM for serving slots beyond the resident scenes")
     ap.add_argument("--serve-slots", type=int, default=64, help="slots kept (buffers and captured graphs)")
@@ -257,9 +258,10 @@ def serve_bench(args):
     """Serving mix over multi-layer scenes: 3 resident scenes (5 shells of
     200k/300k/400k Gaussians, SH 0/2/3), requests with a random scene, a
     resolution from {512^2, 1024^2, 1920x1080, 2048^2}, a camera on a sphere of
-    radius 5 and a random plane; Poisson arrivals at a fraction of the
-    measured saturation rate; the same stream with clipping off for plain."""
-    import torch
+    radius 5 and a random plane.  Saturation is measured from a burst; then
+    Poisson arrivals at 0.25, 0.5, 0.75 and 0.9 of it, each the same request
+    stream clipped and with clipping off (plain); then a run whose HBM budget
+    leaves 1 GiB beyond the resident scenes, which forces queuing."""
     from paper_2506_20202_amd import scenes
     from paper_2506_20202_amd.serve import Engine
     rng = np.random.default_rng(3)
@@ -267,7 +269,6 @@ def serve_bench(args):
             ("B", scenes.multilayer_scene(32, per_shell=300_000, sh_degree=2)),
             ("C", scenes.multilayer_scene(33, per_shell=400_000, sh_degree=3))]
     sizes = [(512, 512), (1024, 1024), (1920, 1080), (2048, 2048)]
-    resident = 0
     eng = Engine(hbm_budget=0, max_slots=args.serve_slots, max_inflight=args.serve_inflight, lanes=args.serve_lanes)
     for name, sc in defs:
         eng.add_scene(name, sc)
@@ -284,25 +285,25 @@ def serve_bench(args):
             out.append((name, scenes.random_camera_on_sphere(rng, 5.0, W, H), scenes.random_plane_through(rng, sc)))
         return out
 
-    # warm-up: every shape class once (slots and graphs built)
+    # warm-up: every shape class once (slots built)
     for name, _ in defs:
         for W, H in sizes:
             eng.submit(name, scenes.random_camera_on_sphere(rng, 5.0, W, H), scenes.random_plane_through(rng, defs[0][1]))
     eng.run_until_idle()
     # saturation: a burst of requests all queued at once
-    burst = make(96)
+    burst = make(128)
     t0 = time.perf_counter()
     for r in burst:
         eng.submit(*r)
     eng.run_until_idle()
     sat = len(burst) / (time.perf_counter() - t0)
-    rate = args.serve_load * sat
-    stream = make(args.serve_requests)
-    gaps = rng.exponential(1.0 / rate, len(stream))
 
-    def run(reqs, clipped):
+    def run(reqs, gaps, clipped):
         eng.sched.latencies.clear()
         eng.sched.completed.clear()
+        eng.ex.batches.clear()
+        eng.sched.max_inflight = 0
+        ev0 = eng.sched.evictions
         # every request is submitted up front with its Poisson arrival time; the
         # scheduler admits it once that time has come (no host thread spins)
         t_start = time.perf_counter() + 0.05
@@ -314,25 +315,47 @@ def serve_bench(args):
             futs.append(eng.submit(name, cam, p, arrival=t))
         eng.start()
         for f in futs:
-            f.result(timeout=300)
+            f.result(timeout=600)
         wall = time.perf_counter() - t_start
         eng.stop()
         st = eng.stats()
         mpix = sum(c.width * c.height for _, c, _ in reqs) / 1e6
         return {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
                 "throughput_req_s": len(reqs) / wall, "throughput_mpix_s": mpix / wall,
-                "max_inflight": st["max_inflight"], "retries": st["retries"], "evictions": st["evictions"]}
+                "max_inflight": st["max_inflight"], "retries": st["retries"],
+                "evictions": eng.sched.evictions - ev0, "mean_batch": st.get("mean_batch"),
+                "max_batch": st.get("max_batch")}
 
-    clipped = run(stream, True)
-    plain = run(stream, False)
+    loads = []
+    for frac in args.serve_loads:
+        rate = frac * sat
+        reqs = make(args.serve_requests)
+        gaps = rng.exponential(1.0 / rate, len(reqs))
+        clipped = run(reqs, gaps, True)
+        plain = run(reqs, gaps, False)
+        loads.append({"load_fraction": frac, "offered_req_s": rate, "requests": len(reqs), "clipped": clipped,
+                      "plain": plain})
+        print(f"[bench] serving at {frac:.2f} x saturation ({rate:.0f} req/s): clipped p50 {clipped['p50_ms']:.2f} "
+              f"p99 {clipped['p99_ms']:.2f} ms, plain p50 {plain['p50_ms']:.2f} p99 {plain['p99_ms']:.2f} ms",
+              file=sys.stderr, flush=True)
+    # a tight HBM budget: resident scenes plus 1 GiB of slots, so requests queue for memory
+    for sl in list(eng.sched.slots):
+        if sl.request is None:
+            eng.sched._drop(sl)
+    eng.sched.budget = resident + (1 << 30)
+    reqs = make(max(200, args.serve_requests // 4))
+    rate = 0.5 * sat
+    gaps = rng.exponential(1.0 / rate, len(reqs))
+    tight = dict(run(reqs, gaps, True), hbm_budget_gib=eng.sched.budget / 2 ** 30, offered_req_s=rate,
+                 requests=len(reqs), load_fraction=0.5)
+    print(f"[bench] serving with 1 GiB of slots: p50 {tight['p50_ms']:.2f} p99 {tight['p99_ms']:.2f} ms, "
+          f"{tight['evictions']} evictions", file=sys.stderr, flush=True)
     eng.close()
     return {"workload": "3 resident multi-layer scenes (1.0M SH0, 1.5M SH2, 2.0M SH3), resolutions "
                         "512^2/1024^2/1920x1080/2048^2, camera on a radius-5 sphere, random plane",
-            "requests": len(stream), "saturation_req_s": sat, "offered_load_req_s": rate,
-            "load_fraction": args.serve_load, "hbm_budget_gib": budget / 2 ** 30, "max_slots": args.serve_slots,
-            "max_inflight": args.serve_inflight, "lanes": args.serve_lanes,
-            "graphs": graphs,
-            "clipped": clipped, "plain": plain}
+            "saturation_req_s": sat, "hbm_budget_gib": budget / 2 ** 30, "max_slots": args.serve_slots,
+            "max_inflight": args.serve_inflight, "lanes": args.serve_lanes, "graphs": graphs,
+            "batched_blends": eng.ex.batch, "loads": loads, "tight_budget": tight}
 
 
 def measured_peaks(reps: int = 5):
@@ -773,8 +796,7 @@ def main():
     serving = None
     if not args.no_serve:
         serving = serve_bench(args)
-        print(f"[bench] serving: clipped p50 {serving['clipped']['p50_ms']:.2f} ms p99 {serving['clipped']['p99_ms']:.2f} ms"
-              f" at {serving['offered_load_req_s']:.0f} req/s", file=sys.stderr, flush=True)
+        print(f"[bench] serving: saturation {serving['saturation_req_s']:.0f} req/s", file=sys.stderr, flush=True)
 
     plain = main_m["fps"].get("original", {}).get("median")
     hard = main_m["fps"].get("hard", {}).get("median")

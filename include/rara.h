@@ -264,6 +264,32 @@ rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned
                         const rara_plane* plane, const float* bg, float* image, float* final_T,
                         uint32_t* n_contrib, uint32_t* n_walked, uint32_t* n_eval, void* stream);
 
+/* Several frames' blends in one launch, for serving many requests at once:
+ * item i is the rara_render of its own frame (its own projected Gaussians,
+ * binned pairs, camera, plane, background and outputs, any image size), and
+ * the launch's workgroups are split among the items, so that small frames
+ * share the GPU instead of running as separate small launches.  Each item's
+ * outputs are bit-identical to rara_render's with the same arguments (n_walked
+ * and n_eval are not produced).  An item whose overflow flag is set is left
+ * untouched, as by rara_render.  The items are read on the host during the
+ * call; their frames must already be binned on `stream` (or ordered before it).
+ * Errors: RARA_ERR_INVALID for count outside [1, RARA_MAX_BATCH] or an item
+ * rara_render would reject; RARA_ERR_UNSUPPORTED for a clip region (more than
+ * one plane) in any item. */
+#define RARA_MAX_BATCH 16
+typedef struct {
+    const rara_projected* proj;
+    int64_t n;
+    const rara_binned* bins;
+    const rara_camera* cam;
+    const rara_plane* plane;
+    const float* bg;           /* host array of 3 floats */
+    float* image;              /* [3][H][W] */
+    float* final_T;            /* [H][W] */
+    uint32_t* n_contrib;       /* [H][W] */
+} rara_render_item;
+rara_status rara_render_batch(const rara_render_item* items, int32_t count, void* stream);
+
 /* Gradient of a scalar loss L given dL/dimage [3][H][W] (device), through the
  * blend (re-walking each tile list from n_contrib back to front, with the
  * transmittance rebuilt by division) and the clip weight of eq. (11), then

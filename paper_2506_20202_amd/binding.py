@@ -51,13 +51,22 @@ class Binned(ctypes.Structure):
                 ("pair_start", _P), ("keys_scratch", ctypes.c_int32)]
 
 
+MAX_BATCH = 16   # RARA_MAX_BATCH
+
+
+class RenderItem(ctypes.Structure):
+    _fields_ = [("proj", ctypes.POINTER(Projected)), ("n", ctypes.c_int64), ("bins", ctypes.POINTER(Binned)),
+                ("cam", ctypes.POINTER(Camera)), ("plane", ctypes.POINTER(Plane)),
+                ("bg", ctypes.POINTER(ctypes.c_float)), ("image", _P), ("final_T", _P), ("n_contrib", _P)]
+
+
 class Grads(ctypes.Structure):
     _fields_ = [("mean", _P), ("scale", _P), ("quat", _P), ("opacity", _P), ("sh", _P), ("plane", _P)]
 
 
 EXPORTS = ["rara_preprocess", "rara_bin_sort", "rara_render", "rara_render_backward", "rara_workspace_bytes",
            "rara_status_string", "rara_version", "rara_frame_graph_create", "rara_frame_graph_launch",
-           "rara_frame_graph_destroy", "rara_bin_sort_static"]
+           "rara_frame_graph_destroy", "rara_bin_sort_static", "rara_render_batch"]
 
 _lib = None
 
@@ -80,6 +89,7 @@ def lib():
         L.rara_preprocess.argtypes = [PG, PC, PP, PJ, _P]
         L.rara_bin_sort.argtypes = [PJ, ctypes.c_int64, PC, ctypes.c_int64, _P, ctypes.c_size_t, PB, _P]
         L.rara_bin_sort_static.argtypes = [PJ, ctypes.c_int64, PC, ctypes.c_int64, PB, _P]
+        L.rara_render_batch.argtypes = [ctypes.POINTER(RenderItem), ctypes.c_int32, _P]
         L.rara_render.argtypes = [PJ, ctypes.c_int64, PB, PC, PP, ctypes.POINTER(ctypes.c_float), _P, _P, _P, _P, _P,
                                   _P]
         L.rara_render_backward.argtypes = [PG, PC, PP, ctypes.POINTER(ctypes.c_float), PJ, PB, ctypes.c_int64, _P, _P,
@@ -96,7 +106,7 @@ def lib():
         L.rara_frame_graph_destroy.argtypes = [_P]
         L.rara_frame_graph_destroy.restype = None
         for f in ("rara_preprocess", "rara_bin_sort", "rara_render", "rara_render_backward", "rara_frame_graph_create",
-                  "rara_frame_graph_launch", "rara_bin_sort_static"):
+                  "rara_frame_graph_launch", "rara_bin_sort_static", "rara_render_batch"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -167,6 +177,23 @@ def render(proj: Projected, n: int, bins: Binned, cam: Camera, plane: Plane, bg,
     _check("rara_render", lib().rara_render(ctypes.byref(proj), n, ctypes.byref(bins), ctypes.byref(cam),
                                             ctypes.byref(plane), bgc, _P(image), _P(final_T), _P(n_contrib),
                                             _P(n_walked or None), _P(n_eval or None), _P(stream)))
+
+
+def render_batch(items, stream: int):
+    """rara_render_batch over a list of (proj, n, bins, cam, plane, bg, image,
+    final_T, n_contrib) with ctypes structs and device pointers; the structs
+    are kept alive for the call."""
+    if not 1 <= len(items) <= MAX_BATCH:
+        raise ValueError(f"a batch holds 1 to {MAX_BATCH} frames")
+    arr = (RenderItem * len(items))()
+    keep = []
+    for k, (proj, n, bins, cam, plane, bg, image, final_T, n_contrib) in enumerate(items):
+        bgc = (ctypes.c_float * 3)(*[float(v) for v in bg])
+        keep += [proj, bins, cam, plane, bgc]
+        arr[k].proj, arr[k].n, arr[k].bins = ctypes.pointer(proj), int(n), ctypes.pointer(bins)
+        arr[k].cam, arr[k].plane, arr[k].bg = ctypes.pointer(cam), ctypes.pointer(plane), bgc
+        arr[k].image, arr[k].final_T, arr[k].n_contrib = image, final_T, n_contrib
+    _check("rara_render_batch", lib().rara_render_batch(arr, len(items), _P(stream)))
 
 
 def render_backward(g: Gaussians, cam: Camera, plane: Plane, bg, proj: Projected, bins: Binned, pair_capacity: int,

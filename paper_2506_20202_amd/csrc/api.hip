@@ -296,6 +296,39 @@ rara_status rara_render(const rara_projected* proj, int64_t n, const rara_binned
     return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
 }
 
+rara_status rara_render_batch(const rara_render_item* items, int32_t count, void* stream)
+{
+    if (!items || count < 1 || count > RARA_MAX_BATCH) return RARA_ERR_INVALID;
+    BatchArgs a;
+    a.count = count;
+    for (int i = 0; i < count; ++i) {
+        const rara_render_item& it = items[i];
+        const rara_projected* proj = it.proj;
+        const rara_binned* bins = it.bins;
+        if (!proj || it.n < 0 || !bins || !it.bg || !it.image || !it.final_T || !it.n_contrib) return RARA_ERR_INVALID;
+        if (!proj->splat || !proj->ray || !bins->vals || !bins->ranges || !bins->overflow || !bins->work)
+            return RARA_ERR_INVALID;
+        CamParams cp;
+        PlaneParams pp;
+        if (!make_cam(it.cam, &cp) || !make_plane(it.plane, &pp)) return RARA_ERR_INVALID;
+        if (pp.enabled && pp.count > 1) return RARA_ERR_UNSUPPORTED;
+        BatchItem& b = a.items[i];
+        b.splat = static_cast<const Splat*>(proj->splat);
+        b.ray = static_cast<const RayRec*>(proj->ray);
+        b.vals = bins->vals;
+        b.ranges = reinterpret_cast<const uint2*>(bins->ranges);
+        b.work = bins->work;
+        b.overflow = bins->overflow;
+        b.image = it.image;
+        b.final_T = it.final_T;
+        b.n_contrib = it.n_contrib;
+        b.p = make_render_params(cp, pp, it.bg);
+        b.first_block = 0;
+    }
+    const hipError_t e = launch_blend_batch(a, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
+}
+
 rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam, const rara_plane* plane,
                                  const float* bg, const rara_projected* proj, const rara_binned* bins,
                                  int64_t pair_capacity, const float* final_T, const uint32_t* n_contrib,

@@ -445,14 +445,15 @@ __device__ __forceinline__ void blend_block(const Splat* __restrict__ splats, co
                                             const uint2* __restrict__ ranges, const uint32_t* __restrict__ work,
                                             const RenderParams& p, float* __restrict__ image,
                                             float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
-                                            uint32_t* __restrict__ n_walked, uint32_t* __restrict__ n_eval)
+                                            uint32_t* __restrict__ n_walked, uint32_t* __restrict__ n_eval,
+                                            uint32_t block)
 {
     uint32_t tile;
     int quad = -1;
     // clip regions: one workgroup per tile (tile_of_block); a single plane:
     // long lists as quadrant units (unit_of_block)
-    if (kRegion ? !tile_of_block(blockIdx.x, work, p.num_tiles, tile)
-                : !unit_of_block(blockIdx.x, work, p.num_tiles, tile, quad))
+    if (kRegion ? !tile_of_block(block, work, p.num_tiles, tile)
+                : !unit_of_block(block, work, p.num_tiles, tile, quad))
         return;
     if (tile >= (uint32_t)p.num_tiles) return;
     constexpr int kB = batch_of<kRegion>();
@@ -486,7 +487,7 @@ void blend_kernel(const Splat* __restrict__ splats, const RayRec* __restrict__ r
 {
     if (*overflow) return;
     blend_block<kWalked, false>(splats, rays, nullptr, vals, ranges, work, p, image, final_T, n_contrib, n_walked,
-                                n_eval);
+                                n_eval, blockIdx.x);
 }
 
 // Clip-region variant (p.plane_count > 1): the further planes' terms staged
@@ -502,7 +503,7 @@ void blend_region_kernel(const Splat* __restrict__ splats, const RayRec* __restr
 {
     if (*overflow) return;
     blend_block<kWalked, true>(splats, rays, ray_ext, vals, ranges, work, p, image, final_T, n_contrib, n_walked,
-                               n_eval);
+                               n_eval, blockIdx.x);
 }
 
 // Frame-graph variant: render parameters read from device memory.
@@ -517,10 +518,36 @@ void blend_fp_kernel(const Splat* __restrict__ splats, const RayRec* __restrict_
     if (*overflow) return;
     const RenderParams p = fp->render;
     blend_block<kWalked, false>(splats, rays, nullptr, vals, ranges, work, p, image, final_T, n_contrib, n_walked,
-                                nullptr);
+                                nullptr, blockIdx.x);
+}
+
+// Several frames in one launch (rara_render_batch): item i owns the
+// workgroups [first_block_i, first_block_{i+1}), each a multiple of 8 so that
+// a workgroup's XCD (b mod 8) is the same in the item's own numbering.
+__global__ __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(8)))
+void blend_batch_kernel(BatchArgs a)
+{
+    const uint32_t b = blockIdx.x;
+    int i = 0;
+    while (i + 1 < a.count && b >= a.items[i + 1].first_block) ++i;
+    const BatchItem& it = a.items[i];
+    if (*it.overflow) return;
+    blend_block<false, false>(it.splat, it.ray, nullptr, it.vals, it.ranges, it.work, it.p, it.image, it.final_T,
+                              it.n_contrib, nullptr, nullptr, b - it.first_block);
 }
 
 }  // namespace
+
+hipError_t launch_blend_batch(BatchArgs& a, hipStream_t s)
+{
+    uint32_t next = 0;
+    for (int i = 0; i < a.count; ++i) {
+        a.items[i].first_block = next;
+        next += (uint32_t)((blend_grid(a.items[i].p.num_tiles) + 7) / 8 * 8);
+    }
+    hipLaunchKernelGGL(blend_batch_kernel, dim3(next), dim3(kBlendThreads), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_blend(const Splat* splat, const RayRec* ray, const float2* ray_ext, const rara_binned& bins,
                         const RenderParams& p, float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked,

@@ -188,6 +188,26 @@ hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const Plane
                            const ProjPtrs& proj, const rara_binned& bins, int64_t pair_capacity, const RenderParams& rp,
                            const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
                            const rara_grads& grads, void* workspace, hipStream_t s);
+// one frame of a batched blend launch (rara_render_batch), passed by value
+struct BatchItem {
+    const Splat* splat;
+    const RayRec* ray;
+    const uint32_t* vals;
+    const uint2* ranges;
+    const uint32_t* work;
+    const int32_t* overflow;
+    float* image;
+    float* final_T;
+    uint32_t* n_contrib;
+    RenderParams p;
+    uint32_t first_block;   // set by launch_blend_batch
+};
+struct BatchArgs {
+    int count;
+    BatchItem items[RARA_MAX_BATCH];
+};
+static_assert(sizeof(BatchArgs) <= 4096, "batched blend arguments must fit the kernel argument limit");
+hipError_t launch_blend_batch(BatchArgs& a, hipStream_t s);
 hipError_t launch_blend(const Splat* splat, const RayRec* ray, const float2* ray_ext, const rara_binned& bins,
                         const RenderParams& p, float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked,
                         uint32_t* n_eval, hipStream_t s);

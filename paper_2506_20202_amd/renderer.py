@@ -182,6 +182,20 @@ def enqueue_frame(scene: DeviceScene, frame: Frame, cam, plane, bg=(0.0, 0.0, 0.
                  _ptr(o.n_eval))
 
 
+def enqueue_render_batch(jobs, stream=None):
+    """One rara_render_batch launch over frames already binned on ``stream``
+    (or ordered before it): ``jobs`` is a list of (scene, frame, cam, plane,
+    bg).  No synchronisation."""
+    if stream is None:
+        stream = torch.cuda.current_stream(jobs[0][0].mean.device)
+    items = []
+    for scene, frame, cam, plane, bg in jobs:
+        o = frame.out
+        items.append((frame.proj.struct(), scene.n, frame.bins.struct(), B.make_camera(cam), B.make_plane(plane), bg,
+                      _ptr(o.image), _ptr(o.final_T), _ptr(o.n_contrib)))
+    B.render_batch(items, int(stream.cuda_stream))
+
+
 def render_checked(scene: DeviceScene, frame: Frame, cam, plane, bg=(0.0, 0.0, 0.0), slack: float = 1.25):
     """Render one frame, growing the pair capacity (and re-rendering) when the
     device reports overflow.  Synchronises once."""

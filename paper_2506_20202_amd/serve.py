@@ -20,7 +20,10 @@ beyond that stay cached with their buffers (and graphs), so shapes that come
 back do not pay an allocation (or a capture) again.
 
 Requests admitted while others run go onto their own slot streams, so their
-kernels overlap on the device.  A frame that overflows its slot's pair
+kernels overlap on the device.  By default the frames admitted in one
+scheduling step are blended together: each runs its preprocess and binning on
+a lane, then one rara_render_batch launch blends all of them (up to 16), so
+the tiles of several requests share one launch instead of many small ones.  A frame that overflows its slot's pair
 capacity is re-run on a slot built with a larger capacity.  Latency is taken
 from the arrival time to the moment the loop sees the completion event.
 
@@ -181,6 +184,9 @@ class Scheduler:
             inflight += 1
             changed = True
         self.max_inflight = max(self.max_inflight, inflight)
+        flush = getattr(self.ex, "flush", None)
+        if flush is not None:
+            flush()   # an executor that batches: the frames admitted in this step
         return changed
 
     def _drop(self, s: Slot):
@@ -217,6 +223,9 @@ class Scheduler:
         lat = np.asarray(self.latencies) * 1e3
         out = dict(completed=len(self.completed), failed=len(self.failed), retries=self.retries,
                    evictions=self.evictions, max_inflight=self.max_inflight, slots=len(self.slots))
+        batches = getattr(self.ex, "batches", None)
+        if batches:
+            out.update(batched_launches=len(batches), mean_batch=float(np.mean(batches)), max_batch=int(max(batches)))
         if lat.size:
             out.update(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                        mean_ms=float(lat.mean()), max_ms=float(lat.max()))
@@ -232,13 +241,18 @@ class GpuExecutor:
     A slot is launched again only after its previous frame completed, so a
     slot needs no ordering between the lanes it runs on."""
 
-    def __init__(self, device=None, use_graphs: bool = False, lanes: int = 3):
+    def __init__(self, device=None, use_graphs: bool = False, lanes: int = 3, batch: bool = True):
         import torch
         from . import renderer as R
         self.torch = torch
         self.device = torch.device(device or "cuda:0")
         self.scenes: Dict[str, Any] = {}
         self.use_graphs = use_graphs
+        # batched blends: a launch runs preprocess + binning of its frame, and
+        # flush() blends every frame launched since in one rara_render_batch
+        self.batch = batch and not use_graphs
+        self.pending: List[dict] = []
+        self.batches: List[int] = []   # frames per batched blend launch
         self.lanes = [R.new_stream(self.device) for _ in range(max(1, lanes))]
         self.lane_busy = [0] * len(self.lanes)
 
@@ -305,6 +319,15 @@ class GpuExecutor:
             st.wait_event(h["ready"])
             h["ready"] = None
         fr = h["frame"]
+        if self.batch:
+            with torch.cuda.stream(st):
+                R.enqueue_frame(h["scene"], fr, req.cam, req.plane, req.bg, stream=st, stages=("pre", "bin"))
+                binned = torch.cuda.Event()
+                binned.record(st)
+            h["binned"] = binned
+            h["req"] = req
+            self.pending.append(h)
+            return
         with torch.cuda.stream(st):
             if h["graph"] is not None:
                 h["graph"].launch(req.cam, req.plane, req.bg, st)
@@ -318,6 +341,37 @@ class GpuExecutor:
             h["result"].record_stream(st)
         h["event"] = ev
         h["req"] = req
+
+    def flush(self):
+        """Blend the frames launched since the last flush, up to RARA_MAX_BATCH
+        per launch, on the least busy lane after their binning; each frame's
+        image is copied out and its status words read back, then one event
+        marks the batch complete."""
+        if not self.pending:
+            return
+        from . import binding as B
+        from . import renderer as R
+        torch = self.torch
+        pend, self.pending = self.pending, []
+        st = self.lanes[min(range(len(self.lanes)), key=lambda i: self.lane_busy[i])]
+        for k in range(0, len(pend), B.MAX_BATCH):
+            group = pend[k:k + B.MAX_BATCH]
+            with torch.cuda.stream(st):
+                for h in group:
+                    st.wait_event(h["binned"])
+                R.enqueue_render_batch([(h["scene"], h["frame"], h["req"].cam, h["req"].plane, h["req"].bg)
+                                        for h in group], st)
+                for h in group:
+                    fr = h["frame"]
+                    h["result"] = fr.out.image.clone()
+                    words = torch.stack([fr.bins.overflow.to(torch.int64)[0], fr.bins.num_pairs[0]])
+                    h["status"].copy_(words, non_blocking=True)
+                    h["result"].record_stream(st)
+                ev = torch.cuda.Event()
+                ev.record(st)
+            for h in group:
+                h["event"] = ev
+            self.batches.append(len(group))
 
     def poll(self, h) -> Optional[Completion]:
         ev = h.get("event")
@@ -335,8 +389,9 @@ class Engine:
     """Scheduler + GPU executor + a background loop thread."""
 
     def __init__(self, hbm_budget: int, max_slots: int = 8, device=None, use_graphs: bool = False,
-                 capacity_of: Optional[Callable] = None, max_inflight: Optional[int] = None, lanes: int = 3):
-        self.ex = GpuExecutor(device, use_graphs, lanes)
+                 capacity_of: Optional[Callable] = None, max_inflight: Optional[int] = None, lanes: int = 3,
+                 batch: bool = True):
+        self.ex = GpuExecutor(device, use_graphs, lanes, batch)
         self.sched = Scheduler(self.ex, hbm_budget, max_slots, capacity_of=capacity_of or self._capacity_guess,
                                max_inflight=max_inflight)
         self._lock = threading.Lock()

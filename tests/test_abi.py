@@ -75,7 +75,8 @@ def test_struct_layouts_match_header(B, tmp_path):
     """Every ctypes struct of the binding has the C header's size and field
     offsets (the binding marshals by layout)."""
     pairs = [("rara_gaussians", B.Gaussians), ("rara_camera", B.Camera), ("rara_plane", B.Plane),
-             ("rara_projected", B.Projected), ("rara_binned", B.Binned), ("rara_grads", B.Grads)]
+             ("rara_projected", B.Projected), ("rara_binned", B.Binned), ("rara_grads", B.Grads),
+             ("rara_render_item", B.RenderItem)]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rara.h"', 'int main(void){']
     for cname, py in pairs:
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
@@ -211,6 +212,34 @@ def test_static_bin_sort_rejects_frames_beyond_its_workspace(B):
     assert lib.rara_bin_sort_static(ctypes.byref(proj), n, ctypes.byref(cam), cap, ctypes.byref(bins), None) \
         == B.RARA_ERR_SCRATCH
     assert B.workspace_bytes(B.RARA_WS_BIN_SORT, 1_000_000, 5_629_420, 1920, 1080) <= B.STATIC_WS_BYTES
+
+
+def test_render_batch_validation(B):
+    """rara_render_batch checks its items on the host: a count outside
+    [1, RARA_MAX_BATCH], an item rara_render would reject, and a clip region
+    (not supported in a batch) are refused before any launch."""
+    lib = B.lib()
+    assert "#define RARA_MAX_BATCH 16" in open(HEADER).read() and B.MAX_BATCH == 16
+    assert lib.rara_render_batch(None, 1, None) == B.RARA_ERR_INVALID
+    items = (B.RenderItem * 17)()
+    assert lib.rara_render_batch(items, 0, None) == B.RARA_ERR_INVALID
+    assert lib.rara_render_batch(items, 17, None) == B.RARA_ERR_INVALID
+    assert lib.rara_render_batch(items, 1, None) == B.RARA_ERR_INVALID   # null pointers
+    proj, bins = B.Projected(), B.Binned()
+    proj.label = proj.splat = proj.ray = proj.depth = proj.rect = proj.tiles_touched = 0x1000
+    bins.keys = bins.vals = bins.ranges = bins.num_pairs = bins.overflow = bins.work = 0x1000
+    cam = _cam(B)
+    box = B.make_plane(__import__("paper_2506_20202_amd.scenes", fromlist=["x"]).box_region((-1, -1, -1), (1, 1, 1)))
+    bg = (ctypes.c_float * 3)()
+    it = items[0]
+    it.proj, it.n, it.bins = ctypes.pointer(proj), 10, ctypes.pointer(bins)
+    it.cam, it.plane, it.bg = ctypes.pointer(cam), ctypes.pointer(box), bg
+    it.image = it.final_T = it.n_contrib = 0x1000
+    assert lib.rara_render_batch(items, 1, None) == B.RARA_ERR_UNSUPPORTED
+    bad = _cam(B)
+    bad.width = 0
+    it.cam = ctypes.pointer(bad)
+    assert lib.rara_render_batch(items, 1, None) == B.RARA_ERR_INVALID
 
 
 def test_clip_modes_agree_and_invalid_modes_are_rejected(B):

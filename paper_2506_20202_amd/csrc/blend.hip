@@ -133,7 +133,7 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
             s_a[tid] = sa;
             s_b[tid] = sb;
             sc = make_float2(c4.x, c4.y);
-            if (sp.label == RARA_LABEL_CUTOFF && plane_on) {
+            if ((sp.label & 0xffu) == RARA_LABEL_CUTOFF && plane_on) {
                 const float4* rr = reinterpret_cast<const float4*>(rays + id);
                 const float4 r0 = rr[0], r1 = rr[1], r2 = rr[2];
                 s_cut[tid].a = r0;
@@ -183,10 +183,31 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
                             // alpha <= a0 (w <= 1): when no pixel can reach its threshold the
                             // entry changes nothing and its weight is not needed
                             if (__ballot(a0 >= thr) == 0ull) continue;
-                            const float w = kRegion ? chord_weight_region(s_cut[e], s_ext + e * (kMaxPlanes - 1),
-                                                                          p.plane_count, dx, dy, p.ax, p.ay, s_rate,
-                                                                          strict)
-                                                    : chord_weight_flat(s_cut[e], dx, dy, p.ax, p.ay, strict);
+                            float w;
+                            if (kRegion) {
+                                // the planes the Gaussian straddles (set by the preprocess); the
+                                // others hold its whole ellipsoid on their visible side
+                                const uint32_t cuts = (__float_as_uint(s_c[e].y) >> 16) & 0xffu;
+                                if (!strict && __popc(cuts) == 1) {
+                                    // one plane: eq. (11) with that plane's terms
+                                    const int kp = __ffs(cuts) - 1;
+                                    CutRec rec = s_cut[e];
+                                    float pax = p.ax, pay = p.ay;
+                                    if (kp > 0) {
+                                        const float2 x = s_ext[e * (kMaxPlanes - 1) + kp - 1];
+                                        rec.c.z = x.x;
+                                        rec.c.w = x.y;
+                                        pax = s_rate[kp - 1].x;
+                                        pay = s_rate[kp - 1].y;
+                                    }
+                                    w = chord_weight_flat(rec, dx, dy, pax, pay, false);
+                                } else {
+                                    w = chord_weight_region(s_cut[e], s_ext + e * (kMaxPlanes - 1), p.plane_count, dx,
+                                                            dy, p.ax, p.ay, s_rate, strict, strict ? 0xffu : cuts);
+                                }
+                            } else {
+                                w = chord_weight_flat(s_cut[e], dx, dy, p.ax, p.ay, strict);
+                            }
                             alpha = fminf(kAlphaMax, a0 * w);
                             if (kWalked) evc += thr < 1.0f ? 1u : 0u;
                         }
@@ -360,7 +381,7 @@ __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec
             stage_entry_strips(sp, ox, oy, quad, sa, sb, sc, sm);
             s_a[tid] = sa;
             s_b[tid] = sb;
-            if (sp.label == RARA_LABEL_CUTOFF && plane_on && sm) {
+            if ((sp.label & 0xffu) == RARA_LABEL_CUTOFF && plane_on && sm) {
                 const float4* rr = reinterpret_cast<const float4*>(rays + id);
                 s_cut[tid].a = rr[0];
                 s_cut[tid].b = rr[1];

@@ -136,10 +136,12 @@ __device__ inline float chord_weight_flat(const CutRec& k, float dx, float dy, f
 // (hi - lo) / 2h clamped to [0, 1] (for one plane this is eq. (11)'s
 // 1/2 + phi / (2 |g| h)).  A miss keeps w = 1, or with the strict policy
 // w = [the closest approach is inside every half-space]; a near root behind
-// the camera keeps w = 1.
+// the camera keeps w = 1.  `mask` may leave out planes that hold the whole
+// 3-sigma ellipsoid on their visible side: they bound no chord (not for the
+// strict policy, whose closest approach of a miss lies outside the ellipsoid).
 __device__ inline float chord_weight_region(const CutRec& k, const float2* __restrict__ ext, int count, float dx,
                                             float dy, float ax, float ay, const float2* __restrict__ rates,
-                                            bool strict)
+                                            bool strict, uint32_t mask = 0xffu)
 {
     const float gx[3] = {k.a.w, k.b.x, k.b.y};
     const float gy[3] = {k.b.z, k.b.w, k.c.x};
@@ -164,6 +166,7 @@ __device__ inline float chord_weight_region(const CutRec& k, const float2* __res
     float lo = -hs, hi = hs;
     bool empty = false, all_in = true;
     for (int p = 0; p < count; ++p) {
+        if (!((mask >> p) & 1u)) continue;   // a plane the caller knows keeps the whole chord visible
         const float2 pe = p == 0 ? make_float2(k.c.z, k.c.w) : ext[p - 1];
         const float pax = p == 0 ? ax : rates[p - 1].x, pay = p == 0 ? ay : rates[p - 1].y;
         const float u = fmaf(pax, dx, pay * dy);

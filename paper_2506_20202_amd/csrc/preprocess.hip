@@ -59,6 +59,9 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
     // inside every half-space.
     uint8_t label = RARA_LABEL_VISIBLE;
     double dep = 0.0;
+    // the planes whose 3-sigma bound the Gaussian straddles (|d| <= r); the
+    // others hold its whole ellipsoid on their visible side (for a CUTOFF one)
+    uint32_t cuts = 0u;
     if (pl.enabled) {
         dep = pl.n[0] * mu[0] + pl.n[1] * mu[1] + pl.n[2] * mu[2] + pl.d;
         if ((pl.enabled & 3) == RARA_CLIP_HARD) {
@@ -89,12 +92,14 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
             };
             const double r = radius(pl.n);
             bool outside = dep < -r, inside = dep > r;
+            cuts = fabs(dep) <= r ? 1u : 0u;
             for (int k = 1; k < pl.count; ++k) {
                 const double* xn = pl.xn[k - 1];
                 const double dk = xn[0] * mu[0] + xn[1] * mu[1] + xn[2] * mu[2] + pl.xd[k - 1];
                 const double rk = radius(xn);
                 outside = outside || dk < -rk;
                 inside = inside && dk > rk;
+                cuts |= fabs(dk) <= rk ? (1u << k) : 0u;
             }
             label = outside ? RARA_LABEL_INVISIBLE : (inside ? RARA_LABEL_VISIBLE : RARA_LABEL_CUTOFF);
         }
@@ -170,7 +175,9 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
                     sp.r = (float)fmax(0.0, rgb[0]);
                     sp.g = (float)fmax(0.0, rgb[1]);
                     sp.b = (float)fmax(0.0, rgb[2]);
-                    sp.label = label;
+                    // bits 16.. of the record's label word: the planes a CUTOFF
+                    // Gaussian straddles (the blend of a region needs only those)
+                    sp.label = label | (label == RARA_LABEL_CUTOFF ? cuts << 16 : 0u);
                     out.splat[i] = sp;
                     out.depth[i] = (float)tz;
                     ushort4 rc = make_ushort4((unsigned short)tx0, (unsigned short)ty0, (unsigned short)tx1,

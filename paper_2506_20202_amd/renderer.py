@@ -327,8 +327,9 @@ def splat_fields(proj: ProjectedBuffers) -> dict:
     raw = proj.splat.detach().cpu().numpy().view(np.uint8).reshape(-1, B.SPLAT_BYTES)[: proj.n]
     mean2d = raw[:, 0:16].copy().view(np.float64).reshape(-1, 2)
     f = raw[:, 16:48].copy().view(np.float32).reshape(-1, 8)
-    lab = raw[:, 44:48].copy().view(np.uint32).reshape(-1)
-    return dict(mean2d=mean2d, conic=f[:, 0:3].copy(), opacity=f[:, 3].copy(), rgb=f[:, 4:7].copy(), label=lab)
+    word = raw[:, 44:48].copy().view(np.uint32).reshape(-1)
+    return dict(mean2d=mean2d, conic=f[:, 0:3].copy(), opacity=f[:, 3].copy(), rgb=f[:, 4:7].copy(),
+                label=word & 0xFF, cuts=word >> 16)
 
 
 class FrameGraph:

@@ -286,6 +286,25 @@ def test_box_region_parity(seed):
     box = _tiny_box(seed)
     g, o = _full_check(scenes.tiny_scene(seed), scenes.tiny_camera(), box)
     assert (o["label"] == 2).sum() > 20 and (o["label"] == 0).sum() > 20
+    _check_straddled_planes(g, o)
+
+
+def _check_straddled_planes(g, o):
+    """The preprocess marks, for each drawn CUTOFF Gaussian of a region, the
+    planes it straddles (|d_k| <= r_k); the oracle's per-plane distances and
+    radii decide the same, off the 1e-6 boundary."""
+    cut = (o["label"] == 2) & (g["tiles_touched"] > 0)
+    dep, rad = np.atleast_2d(o["d_ep"]), np.atleast_2d(o["radius3"])
+    want = np.zeros(len(cut), np.int64)
+    near = np.zeros(len(cut), bool)
+    for k in range(dep.shape[0]):
+        want |= (np.abs(dep[k]) <= rad[k]).astype(np.int64) << k
+        near |= np.abs(np.abs(dep[k]) - rad[k]) <= 1e-6
+    got = g["splat_cuts"].astype(np.int64)
+    ok = cut & ~near
+    assert ok.sum() > 10
+    np.testing.assert_array_equal(got[ok], want[ok])
+    print(f"straddled planes per CUTOFF Gaussian: {np.bincount([bin(v).count('1') for v in got[ok]])}", flush=True)
 
 
 @pytest.mark.parametrize("name,mode", CLIP_MODES)
@@ -304,7 +323,8 @@ def test_random_region_parity(count):
         n = rng.standard_normal(3)
         n /= np.linalg.norm(n)
         planes.append((n, float(rng.uniform(0.2, 0.7))))   # the origin is inside every half-space
-    _full_check(sc, scenes.tiny_camera(), scenes.region(planes))
+    g, o = _full_check(sc, scenes.tiny_camera(), scenes.region(planes))
+    _check_straddled_planes(g, o)
 
 
 def test_box_region_large_gaussians():
@@ -313,6 +333,7 @@ def test_box_region_large_gaussians():
     box = scenes.box_region((-0.15, -0.2, -0.1), (0.2, 0.1, 0.15))
     g, o = _full_check(sc, scenes.small_camera(96), box)
     assert (o["label"] == 2).sum() >= 8
+    _check_straddled_planes(g, o)
 
 
 # Long lists: thousands of overlapping Gaussians over a few tiles, most of them

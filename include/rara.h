@@ -135,8 +135,9 @@ typedef struct {
  *        float  opacity        delta
  *        float  rgb[3]         colour, clamped at 0
  *        uint32 label          the label in the low byte; for a CUTOFF Gaussian,
- *                              bit 16 + k is set when it straddles plane k
- *                              (|n_k.mu + d_k| <= r_k) of the plane or region
+ *                              bit 16 + k is set when plane k of the plane or
+ *                              region does not hold its whole 3-sigma ellipsoid
+ *                              on the visible side: n_k.mu + d_k <= 3 |S R^T n_k|
  *   ray  [n] 48-byte records   written for drawn CUTOFF Gaussians only: the
  *        whitened-space ray set-up of eq. (4) (12 floats; layout private to the
  *        library, consumed by rara_render / rara_render_backward).

@@ -203,10 +203,10 @@ __device__ inline void blend_back_tile(const Splat* __restrict__ splats, const R
                 const Splat sp = splats[id];
                 float4 sa, sb;
                 uint32_t qm;
-                stage_entry(sp, ox, oy, 0xfu, sa, sb, sc, qm, id);
+                stage_entry(sp, ox, oy, 0xfu, strict, sa, sb, sc, qm, id);
                 s_a[tid] = sa;
                 s_b[tid] = sb;
-                if ((sp.label & 0xffu) == RARA_LABEL_CUTOFF && plane_on) {
+                if ((__float_as_uint(sc.y) & 0xffu) == RARA_LABEL_CUTOFF && plane_on) {
                     const float4* rr = reinterpret_cast<const float4*>(rays + id);
                     const float4 r0 = rr[0], r1 = rr[1], r2 = rr[2];
                     s_cut[tid].a = r0;

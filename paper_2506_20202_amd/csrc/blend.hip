@@ -129,11 +129,11 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
             const Splat sp = splats[id];
             float4 sa, sb, c4;
             uint32_t qm;
-            stage_entry(sp, ox, oy, 0xfu, sa, sb, c4, qm, id);
+            stage_entry(sp, ox, oy, 0xfu, strict, sa, sb, c4, qm, id);
             s_a[tid] = sa;
             s_b[tid] = sb;
             sc = make_float2(c4.x, c4.y);
-            if ((sp.label & 0xffu) == RARA_LABEL_CUTOFF && plane_on) {
+            if ((__float_as_uint(c4.y) & 0xffu) == RARA_LABEL_CUTOFF && plane_on) {
                 const float4* rr = reinterpret_cast<const float4*>(rays + id);
                 const float4 r0 = rr[0], r1 = rr[1], r2 = rr[2];
                 s_cut[tid].a = r0;
@@ -185,8 +185,8 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
                             if (__ballot(a0 >= thr) == 0ull) continue;
                             float w;
                             if (kRegion) {
-                                // the planes the Gaussian straddles (set by the preprocess); the
-                                // others hold its whole ellipsoid on their visible side
+                                // the planes that do not hold the whole ellipsoid on their visible
+                                // side (set by the preprocess); the others leave every chord whole
                                 const uint32_t cuts = (__float_as_uint(s_c[e].y) >> 16) & 0xffu;
                                 if (!strict && __popc(cuts) == 1) {
                                     // one plane: eq. (11) with that plane's terms
@@ -378,10 +378,10 @@ __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec
             const Splat sp = splats[id];
             float4 sa, sb;
             uint32_t sm;
-            stage_entry_strips(sp, ox, oy, quad, sa, sb, sc, sm);
+            stage_entry_strips(sp, ox, oy, quad, strict, sa, sb, sc, sm);
             s_a[tid] = sa;
             s_b[tid] = sb;
-            if ((sp.label & 0xffu) == RARA_LABEL_CUTOFF && plane_on && sm) {
+            if ((__float_as_uint(sc.y) & 0xffu) == RARA_LABEL_CUTOFF && plane_on && sm) {
                 const float4* rr = reinterpret_cast<const float4*>(rays + id);
                 s_cut[tid].a = rr[0];
                 s_cut[tid].b = rr[1];

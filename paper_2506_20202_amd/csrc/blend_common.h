@@ -247,14 +247,29 @@ __device__ inline bool reach_form(const Splat& nx, float mx, float my, QuadForm&
     return true;
 }
 
+// Label word of a list entry as staged for the blend: the label in the low
+// byte, the plane mask (bits 16..23 of the splat's word: the planes whose
+// visible side does not hold the whole 3-sigma ellipsoid) kept.  With an empty
+// mask every chord lies inside every half-space, and a miss or a near root
+// behind the camera keeps 1 as well, so w = 1 on every pixel ray (eq. 11): such
+// a CUTOFF Gaussian is staged as VISIBLE and its weight is not evaluated.  Not
+// under the strict miss policy, where a miss depends on the closest approach.
+__device__ inline uint32_t staged_word(uint32_t word, bool strict)
+{
+    const uint32_t lab = word & 0xffu;
+    const uint32_t cuts = word & 0x00ff0000u;
+    const bool all_in = lab == RARA_LABEL_CUTOFF && !strict && cuts == 0u;
+    return (all_in ? (uint32_t)RARA_LABEL_VISIBLE : lab) | cuts;
+}
+
 // Staged form of one list entry.  s_a: centre (tile-relative), pre-scaled
 // conic a and b; s_b: pre-scaled conic c, opacity, red, green; s_c: blue,
 // label | quadrant mask << 8, Gaussian index.  The quadrant mask holds bit q
 // (q = 2 * row + column of the 8x8 quadrant) for every quadrant in `want`
 // that the entry can reach with alpha >= 1/255; an entry is never left out of
 // a quadrant it could reach.
-__device__ inline void stage_entry(const Splat& nx, double ox, double oy, uint32_t want, float4& sa, float4& sb,
-                                   float4& sc, uint32_t& qmask, uint32_t id)
+__device__ inline void stage_entry(const Splat& nx, double ox, double oy, uint32_t want, bool strict, float4& sa,
+                                   float4& sb, float4& sc, uint32_t& qmask, uint32_t id)
 {
     const float kq = -0.5f * kLog2e;
     const float mx = (float)(nx.mx - ox), my = (float)(nx.my - oy);
@@ -269,14 +284,15 @@ __device__ inline void stage_entry(const Splat& nx, double ox, double oy, uint32
             if ((want >> q) & 1u)
                 qmask |= quad_reach(f, m2, (float)((q & 1) * 8), (float)((q >> 1) * 8)) ? (1u << q) : 0u;
     }
-    sc = make_float4(nx.b, __uint_as_float(nx.label | (qmask << 8)), __uint_as_float(id), 0.0f);
+    sc = make_float4(nx.b, __uint_as_float(staged_word(nx.label, strict) | (qmask << 8)), __uint_as_float(id),
+                     0.0f);
 }
 
 // The same staging for a long-list quadrant unit: bit w of the mask is set
 // when the entry can reach strip w of quadrant `quad` (the pixel centres of
 // quadrant rows 2w and 2w + 1, tile columns qx .. qx + 7).
-__device__ inline void stage_entry_strips(const Splat& nx, double ox, double oy, int quad, float4& sa, float4& sb,
-                                          float2& sc, uint32_t& smask)
+__device__ inline void stage_entry_strips(const Splat& nx, double ox, double oy, int quad, bool strict, float4& sa,
+                                          float4& sb, float2& sc, uint32_t& smask)
 {
     const float kq = -0.5f * kLog2e;
     const float mx = (float)(nx.mx - ox), my = (float)(nx.my - oy);
@@ -291,7 +307,7 @@ __device__ inline void stage_entry_strips(const Splat& nx, double ox, double oy,
         for (int w = 0; w < 4; ++w)
             smask |= box_reach(f, m2, qx, qy + 2.0f * (float)w, 7.0f, 1.0f) ? (1u << w) : 0u;
     }
-    sc = make_float2(nx.b, __uint_as_float(nx.label | (smask << 8)));
+    sc = make_float2(nx.b, __uint_as_float(staged_word(nx.label, strict) | (smask << 8)));
 }
 
 // Tile of blend workgroup b.  The work list holds the H long-list tiles

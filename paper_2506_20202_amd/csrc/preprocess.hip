@@ -59,8 +59,8 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
     // inside every half-space.
     uint8_t label = RARA_LABEL_VISIBLE;
     double dep = 0.0;
-    // the planes whose 3-sigma bound the Gaussian straddles (|d| <= r); the
-    // others hold its whole ellipsoid on their visible side (for a CUTOFF one)
+    // for a CUTOFF Gaussian: the planes whose visible side does not hold its
+    // whole 3-sigma ellipsoid (d_k <= the ellipsoid's half-width along n_k)
     uint32_t cuts = 0u;
     if (pl.enabled) {
         dep = pl.n[0] * mu[0] + pl.n[1] * mu[1] + pl.n[2] * mu[2] + pl.d;
@@ -73,14 +73,11 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
             label = behind ? RARA_LABEL_INVISIBLE : RARA_LABEL_VISIBLE;
         } else {
             const bool tight = (pl.enabled & RARA_CLIP_TIGHT) != 0;
-            double qw = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
-            if (tight) {
-                qw = g.quat[i]; qx = g.quat[n + i]; qy = g.quat[2 * n + i]; qz = g.quat[3 * n + i];
-                const double ql = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-                qw /= ql; qx /= ql; qy /= ql; qz /= ql;
-            }
-            auto radius = [&](const double* nn) {
-                if (!tight) return 3.0 * fmax(fmax(s[0], s[1]), s[2]);
+            double qw = g.quat[i], qx = g.quat[n + i], qy = g.quat[2 * n + i], qz = g.quat[3 * n + i];
+            const double ql = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+            qw /= ql; qx /= ql; qy /= ql; qz /= ql;
+            // 3 |S R^T n|: the half-width of the 3-sigma ellipsoid along n
+            auto support = [&](const double* nn) {
                 // (S R^T n)_a = sigma_a (column a of R) . n
                 const double c0 = s[0] * ((1 - 2 * (qy * qy + qz * qz)) * nn[0] + 2 * (qx * qy + qw * qz) * nn[1] +
                                           2 * (qx * qz - qw * qy) * nn[2]);
@@ -90,16 +87,22 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
                                           (1 - 2 * (qx * qx + qy * qy)) * nn[2]);
                 return 3.0 * sqrt(c0 * c0 + c1 * c1 + c2 * c2);
             };
-            const double r = radius(pl.n);
+            const double rmax = 3.0 * fmax(fmax(s[0], s[1]), s[2]);
+            const double st0 = support(pl.n);
+            const double r = tight ? st0 : rmax;
             bool outside = dep < -r, inside = dep > r;
-            cuts = fabs(dep) <= r ? 1u : 0u;
+            // the planes that cut into, or hold outside, the 3-sigma ellipsoid
+            // itself (the label takes the 3 max(sigma) ball unless the tight
+            // flag is set)
+            cuts = dep <= st0 ? 1u : 0u;
             for (int k = 1; k < pl.count; ++k) {
                 const double* xn = pl.xn[k - 1];
                 const double dk = xn[0] * mu[0] + xn[1] * mu[1] + xn[2] * mu[2] + pl.xd[k - 1];
-                const double rk = radius(xn);
+                const double sk = support(xn);
+                const double rk = tight ? sk : rmax;
                 outside = outside || dk < -rk;
                 inside = inside && dk > rk;
-                cuts |= fabs(dk) <= rk ? (1u << k) : 0u;
+                cuts |= dk <= sk ? (1u << k) : 0u;
             }
             label = outside ? RARA_LABEL_INVISIBLE : (inside ? RARA_LABEL_VISIBLE : RARA_LABEL_CUTOFF);
         }
@@ -175,8 +178,8 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
                     sp.r = (float)fmax(0.0, rgb[0]);
                     sp.g = (float)fmax(0.0, rgb[1]);
                     sp.b = (float)fmax(0.0, rgb[2]);
-                    // bits 16.. of the record's label word: the planes a CUTOFF
-                    // Gaussian straddles (the blend of a region needs only those)
+                    // bits 16.. of the record's label word: the planes that do
+                    // not hold a CUTOFF Gaussian's ellipsoid inside (see staged_word)
                     sp.label = label | (label == RARA_LABEL_CUTOFF ? cuts << 16 : 0u);
                     out.splat[i] = sp;
                     out.depth[i] = (float)tz;

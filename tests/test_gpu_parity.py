@@ -8,6 +8,7 @@ a ray grazing the traced ellipsoid, a Gaussian within 1e-6 of a label or
 footprint boundary).
 """
 import dataclasses
+import math
 
 import numpy as np
 import pytest
@@ -15,6 +16,7 @@ import pytest
 import oracle
 from paper_2506_20202_amd import scenes
 from tests import gpu_helpers as H
+from tests import independent
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +59,9 @@ def _full_check(sc, cam, pl, bg=(0.0, 0.0, 0.0)):
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
 def test_tiny_scene_parity(seed):
-    _full_check(scenes.tiny_scene(seed), scenes.tiny_camera(), scenes.tiny_plane(seed))
+    sc, pl = scenes.tiny_scene(seed), scenes.tiny_plane(seed)
+    g, o = _full_check(sc, scenes.tiny_camera(), pl)
+    _check_plane_mask(g, o, sc, pl)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
@@ -67,7 +71,9 @@ def test_small_large_gaussians_parity(seed):
     cam = scenes.small_camera(96)
     rng = np.random.default_rng(70 + seed)
     n = rng.standard_normal(3)
-    _full_check(sc, cam, scenes.Plane((n / np.linalg.norm(n)).astype(np.float32), float(rng.uniform(-0.1, 0.1))))
+    pl = scenes.Plane((n / np.linalg.norm(n)).astype(np.float32), float(rng.uniform(-0.1, 0.1)))
+    g, o = _full_check(sc, cam, pl)
+    _check_plane_mask(g, o, sc, pl)
 
 
 def test_ragged_image_and_background():
@@ -286,25 +292,34 @@ def test_box_region_parity(seed):
     box = _tiny_box(seed)
     g, o = _full_check(scenes.tiny_scene(seed), scenes.tiny_camera(), box)
     assert (o["label"] == 2).sum() > 20 and (o["label"] == 0).sum() > 20
-    _check_straddled_planes(g, o)
+    _check_plane_mask(g, o, scenes.tiny_scene(seed), box)
 
 
-def _check_straddled_planes(g, o):
-    """The preprocess marks, for each drawn CUTOFF Gaussian of a region, the
-    planes it straddles (|d_k| <= r_k); the oracle's per-plane distances and
-    radii decide the same, off the 1e-6 boundary."""
-    cut = (o["label"] == 2) & (g["tiles_touched"] > 0)
-    dep, rad = np.atleast_2d(o["d_ep"]), np.atleast_2d(o["radius3"])
+def _check_plane_mask(g, o, sc, pl):
+    """The preprocess marks, for each drawn CUTOFF Gaussian, the planes whose
+    visible side does not hold its whole 3-sigma ellipsoid: d_k <= 3 sqrt(n_k^T
+    Sigma n_k), the ellipsoid's half-width along n_k.  The oracle's per-plane
+    distances and a covariance built here decide the same, off a 1e-6 boundary.
+    A CUTOFF Gaussian with no plane marked is blended as VISIBLE (every chord
+    lies inside every half-space)."""
+    cut = np.flatnonzero((o["label"] == 2) & (g["tiles_touched"] > 0))
+    dep = np.atleast_2d(o["d_ep"])
+    normals = [np.asarray(pl.n, np.float64)] + [np.asarray(n, np.float64) for n, _ in pl.extra]
     want = np.zeros(len(cut), np.int64)
     near = np.zeros(len(cut), bool)
-    for k in range(dep.shape[0]):
-        want |= (np.abs(dep[k]) <= rad[k]).astype(np.int64) << k
-        near |= np.abs(np.abs(dep[k]) - rad[k]) <= 1e-6
-    got = g["splat_cuts"].astype(np.int64)
-    ok = cut & ~near
+    for j, i in enumerate(cut):
+        cov = independent.cov3(sc.quat[:, i], sc.scale[:, i])
+        for k, nk in enumerate(normals):
+            nk = nk / np.linalg.norm(nk)
+            sup = 3.0 * math.sqrt(nk @ cov @ nk)
+            want[j] |= int(dep[k, i] <= sup) << k
+            near[j] |= abs(dep[k, i] - sup) <= 1e-6
+    got = g["splat_cuts"][cut].astype(np.int64)
+    ok = ~near
     assert ok.sum() > 10
     np.testing.assert_array_equal(got[ok], want[ok])
-    print(f"straddled planes per CUTOFF Gaussian: {np.bincount([bin(v).count('1') for v in got[ok]])}", flush=True)
+    planes = np.bincount([bin(v).count("1") for v in got[ok]])
+    print(f"marked planes per CUTOFF Gaussian: {planes}", flush=True)
 
 
 @pytest.mark.parametrize("name,mode", CLIP_MODES)
@@ -323,8 +338,9 @@ def test_random_region_parity(count):
         n = rng.standard_normal(3)
         n /= np.linalg.norm(n)
         planes.append((n, float(rng.uniform(0.2, 0.7))))   # the origin is inside every half-space
-    g, o = _full_check(sc, scenes.tiny_camera(), scenes.region(planes))
-    _check_straddled_planes(g, o)
+    pl = scenes.region(planes)
+    g, o = _full_check(sc, scenes.tiny_camera(), pl)
+    _check_plane_mask(g, o, sc, pl)
 
 
 def test_box_region_large_gaussians():
@@ -333,7 +349,7 @@ def test_box_region_large_gaussians():
     box = scenes.box_region((-0.15, -0.2, -0.1), (0.2, 0.1, 0.15))
     g, o = _full_check(sc, scenes.small_camera(96), box)
     assert (o["label"] == 2).sum() >= 8
-    _check_straddled_planes(g, o)
+    _check_plane_mask(g, o, sc, box)
 
 
 # Long lists: thousands of overlapping Gaussians over a few tiles, most of them

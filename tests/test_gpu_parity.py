@@ -352,6 +352,41 @@ def test_box_region_large_gaussians():
     _check_plane_mask(g, o, sc, box)
 
 
+# One 16x16 tile holding the whole list: lists of about 1000, 3000 and 9600
+# entries (the depth passes of the sort then run over several 2048-key sort
+# tiles whose digit runs all land in one tile's range).  Copies of one
+# Gaussian's shape at one point near the origin make runs of 6 and 40 equal
+# depths, which must keep index order.
+def _one_tile_scene(n, runs, seed=5):
+    sc = scenes.small_scene(seed, n=n, spread=0.3, logscale_mean=-2.5)
+    mean, scale, quat = sc.mean.copy(), sc.scale.copy(), sc.quat.copy()
+    for k, (start, length) in enumerate(runs):
+        mean[:, start: start + length] = np.array([[0.01 - 0.03 * k], [0.02], [0.03 + 0.02 * k]], np.float32)
+        for a in (scale, quat):
+            a[:, start + 1: start + length] = a[:, start:start + 1]
+    return dataclasses.replace(sc, mean=mean, scale=scale, quat=quat, opacity=(sc.opacity * 0.02).astype(np.float32))
+
+
+@pytest.mark.parametrize("n", [1000, 3000, 10000])
+@pytest.mark.parametrize("runs", [((100, 6),), ((100, 6), (300, 40))], ids=["run6", "run6_run40"])
+def test_one_tile_long_lists_and_equal_depths(n, runs):
+    sc = _one_tile_scene(n, runs)
+    cam, pl = scenes.small_camera(16), scenes.tiny_plane(0)
+    lab, _, _ = oracle.classify(sc, pl)
+    proj = oracle.project(sc, cam, lab)
+    offs, ids = oracle.tile_lists(proj, cam)
+    g = H.gpu_frame(sc, cam, pl, capacity=2 * n)
+    d = proj["depth32"][ids]
+    runs_found = np.diff(np.flatnonzero(np.diff(np.concatenate([[np.nan], d, [np.nan]])) != 0))
+    print(f"n={n} list={len(ids)} longest equal-depth run={runs_found.max()}", flush=True)
+    assert runs_found.max() == max(length for _, length in runs)
+    assert g["P"] == len(ids)
+    H.check_lists(g, {"offsets": offs, "ids": ids})
+    # the sorted keys carry each entry's float32 depth bits
+    np.testing.assert_array_equal((g["keys"] & np.uint64(0xFFFFFFFF)).astype(np.uint32),
+                                  d.astype(np.float32).view(np.uint32))
+
+
 # Long lists: thousands of overlapping Gaussians over a few tiles, most of them
 # CUTOFF, so tiles hold 2000-7600 entries (the blend dispatches tiles of 1024
 # entries or more first, each XCD taking a run of them).  With that many

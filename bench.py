@@ -46,7 +46,7 @@ PIPE_STREAMS = 3
 # bytes per launch from FETCH_SIZE and WRITE_SIZE, scaled by what the same
 # counters read for a plain device copy of known size.  Reported only while
 # the blend's sources are the ones the counters were taken on.
-COUNTER_FILE = os.path.join(ROOT, "profiles", "blend_counters_general_1080p.txt")
+COUNTER_FILE = os.path.join(ROOT, "profiles", "hbm_general_1080p.md")
 # the blend's sources, and the header holding its schedule and batch constants
 BLEND_SOURCES = ("paper_2506_20202_amd/csrc/blend.hip", "paper_2506_20202_amd/csrc/blend_common.h",
                  "paper_2506_20202_amd/csrc/rara_internal.h")
@@ -100,7 +100,8 @@ def parse():
     ap.add_argument("--serve-lanes", type=int, default=3, help="streams (hardware queues) the frames run on")
     ap.add_argument("--profile-steps", type=int, default=0, help="only run this many frames (for profilers)")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="with --profile-steps: also run one plain 256 MiB device copy (counter calibration)")
+                    help="with --profile-steps: also run one plain 256 MiB device copy at the end (counter "
+                         "calibration)")
     return ap.parse_args()
 
 
@@ -426,15 +427,23 @@ def profile_run(args, sc, grid, dev):
     torch.cuda.synchronize()
     assert int(fr.bins.overflow.item()) == 0
     if args.calibrate_copy:
-        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
+        calibration_copy(dev)
     print(json.dumps({"profile_steps": args.profile_steps, "warmup": args.warmup, "pair_capacity": fr.capacity,
                       "scan_capacity": cap0, "scan_grew": maxP > cap0, "grid_frames": len(grid) * len(grid[0]),
                       "frames": [list(order[i % len(order)]) for i in range(args.warmup + args.profile_steps)],
                       "copy_bytes": (256 << 20) if args.calibrate_copy else 0}))
+
+
+def calibration_copy(dev):
+    """One plain 256 MiB device-to-device copy, whose FETCH_SIZE and
+    WRITE_SIZE readings scale the other kernels' (rocprofv3 --pmc runs)."""
+    import torch
+    src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def scan_grid(ds, fr, grid):
@@ -643,6 +652,68 @@ def box_workload():
     return sc, grid, desc
 
 
+def backward_bytes(n, D, drawn, cut, pairs, pixels):
+    """Algorithmic HBM bytes of one rara_render_backward: per pixel final_T,
+    n_contrib and dL/dimage (20 B); per pair its list entry (4 B) and its
+    84-byte gradient slot written once and read once; per drawn Gaussian its
+    splat record (48 B, and the 48-byte ray record of a CUTOFF one) and its
+    84-byte slot sum written and read; per Gaussian the raw parameters read
+    and their gradients written (44 + 12 (D+1)^2 B each way)."""
+    per_g = 44 + 12 * (D + 1) ** 2
+    return 20 * pixels + pairs * (4 + 2 * 84) + drawn * (48 + 2 * 84) + 48 * cut + 2 * per_g * n
+
+
+def backward_roofline(sc, cam, plane, fr, params, target, p4, reps):
+    """One view's rara_render_backward through the C ABI, timed with HIP
+    events on the stream it runs on (median of ``reps``), against its
+    algorithmic bytes (backward_bytes)."""
+    import torch
+    from paper_2506_20202_amd import autograd as AG
+    from paper_2506_20202_amd import binding as B
+    dev = params[0].device
+    with torch.no_grad():
+        img = AG.render(*params, p4(plane), cam, True, frame=fr)
+        dimg = (2.0 * (img - target) / img.numel()).contiguous()
+    g = [torch.empty_like(p) for p in params]
+    dplane = torch.empty(4, dtype=torch.float32, device=dev)
+    gs = B.Grads()
+    gs.mean, gs.scale, gs.quat, gs.opacity, gs.sh = (x.data_ptr() for x in g)
+    gs.plane = dplane.data_ptr()
+    ws_bytes = B.workspace_bytes(B.RARA_WS_BACKWARD, sc.n, fr.capacity, fr.width, fr.height)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    from paper_2506_20202_amd import renderer as R
+    ds = R.DeviceScene(*(p.detach() for p in params), sc.sh_degree)
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pl = rara_plane_of(plane)
+    ms = []
+    for _ in range(reps + 1):
+        e0.record(stream)
+        B.render_backward(ds.struct(), B.make_camera(cam), B.make_plane(pl), (0.0, 0.0, 0.0), fr.proj.struct(),
+                          fr.bins.struct(), fr.capacity, fr.out.final_T.data_ptr(), fr.out.n_contrib.data_ptr(),
+                          dimg.data_ptr(), gs, ws.data_ptr(), ws_bytes, int(stream.cuda_stream))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    ms = float(np.median(ms[1:]))
+    lab = fr.proj.label[: sc.n]
+    drawn = fr.proj.tiles_touched[: sc.n] != 0
+    nd, ncut = int(drawn.sum().item()), int((drawn & (lab == 2)).sum().item())
+    P = int(fr.bins.num_pairs.item())
+    by = backward_bytes(sc.n, sc.sh_degree, nd, ncut, P, cam.width * cam.height)
+    gbs = by / (ms / 1e3) / 1e9
+    return {"kernel": "rara_render_backward of one view (blend_backward, slot_sum, project_backward, "
+                      "plane_finalize)", "bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+            "frac": gbs / 8000.0, "bytes_per_launch": by, "avg_launch_ms": ms, "pairs": P, "drawn": nd,
+            "note": "the blend_backward walk dominates and is latency-bound, far from this bound"}
+
+
+def rara_plane_of(plane):
+    """The plane as the forward's autograd path builds it (clip mode 1)."""
+    from paper_2506_20202_amd.scenes import Plane
+    return Plane(np.asarray(plane.n, np.float32), float(plane.d), 1)
+
+
 def diff_bench(reps):
     """The differentiable workload: 500k general-scene Gaussians (SH3), 8 views
     at 800x800, each with its own clip plane, mean L2 loss against targets
@@ -701,10 +772,11 @@ def diff_bench(reps):
     b = [timed(batch) for _ in range(reps)]
     f = [timed(fwd_only) for _ in range(reps)]
     ok = all(bool(torch.isfinite(p.grad).all()) for p in params)
+    roof = backward_roofline(sc, cams[0], planes[0], frames[0], params, targets[0], p4, reps)
     out = {"workload": "500,000 general-scene Gaussians, SH3, 8 views x 800x800, one clip plane per view, "
                        "L2 loss against a perturbed-scene target", "batch_ms": float(np.median(b)),
            "forward_ms": float(np.median(f)), "backward_ms": float(np.median(b) - np.median(f)),
-           "reps": reps, "gradients_finite": ok,
+           "reps": reps, "gradients_finite": ok, "roofline": roof,
            "note": "each forward checks the pair count on the host (one synchronisation per view)"}
     del frames, params, targets
     torch.cuda.empty_cache()
@@ -726,6 +798,8 @@ def main():
         if not args.profile_steps:
             sys.exit("--workload diff is a profiler run: give --profile-steps")
         print(json.dumps(diff_bench(args.profile_steps)))
+        if args.calibrate_copy:
+            calibration_copy(dev)
         return
     sc, grid, desc = workload(args.workload)
     print(f"[bench] scene n={sc.n} ready in {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)

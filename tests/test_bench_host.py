@@ -58,3 +58,17 @@ def test_stage_byte_models():
     one = bench.bin_sort_bytes(0, 0, 1, 64) - bench.bin_sort_bytes(0, 0, 0, 64)
     two = bench.bin_sort_bytes(0, 0, 1, 8160) - bench.bin_sort_bytes(0, 0, 0, 8160)
     assert one == 8 + 12 and two == 8 + 16 + 12
+
+
+def test_backward_byte_model():
+    """Backward bytes: 172 B per pair (entry + slot written and read), 216 B
+    per drawn Gaussian (+48 for a CUTOFF one's ray record), 20 B per pixel,
+    and parameters read plus gradients written (236 B each way at SH degree
+    3)."""
+    base = bench.backward_bytes(0, 3, 0, 0, 0, 0)
+    assert base == 0
+    assert bench.backward_bytes(0, 3, 0, 0, 1, 0) == 172
+    assert bench.backward_bytes(0, 3, 1, 1, 0, 0) == 216 + 48
+    assert bench.backward_bytes(0, 3, 0, 0, 0, 10) == 200
+    assert bench.backward_bytes(1, 3, 0, 0, 0, 0) == 2 * 236
+    assert bench.backward_bytes(1, 0, 0, 0, 0, 0) == 2 * 56

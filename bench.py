@@ -171,12 +171,14 @@ def bin_sort_bytes(n, drawn, pairs, tiles):
     """Algorithmic HBM bytes of rara_bin_sort as this sort runs it, each pass
     reading and writing its keys and values once: the first depth pass reads
     depth and tile count of every Gaussian and writes 8 B per drawn one, three
-    more depth passes move 16 B per drawn Gaussian, the emit reads 16 B per
-    drawn Gaussian and writes 8 B per pair, the tile passes move 16 B per pair
-    except the last, which writes only the values (12 B per pair), and the
-    ranges and schedule take 12 B per tile."""
+    more depth passes move 16 B per drawn Gaussian, the chunk sums read each
+    drawn Gaussian's index and rectangle and write the rectangle in depth order
+    (20 B), the emit reads index and rectangle (12 B per drawn Gaussian) and
+    writes 8 B per pair, the tile passes move 16 B per pair except the last,
+    which writes only the values (12 B per pair), and the ranges and schedule
+    take 12 B per tile."""
     tile_passes = max(1, (max(1, int(tiles - 1).bit_length()) + 7) // 8)
-    return (8 * n + 8 * drawn + 48 * drawn + 16 * drawn + 8 * pairs + 16 * pairs * (tile_passes - 1) + 12 * pairs
+    return (8 * n + 8 * drawn + 48 * drawn + 32 * drawn + 8 * pairs + 16 * pairs * (tile_passes - 1) + 12 * pairs
             + 12 * tiles)
 
 

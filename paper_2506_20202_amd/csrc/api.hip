@@ -196,6 +196,7 @@ size_t rara::bin_workspace_layout(int64_t n, int64_t cap, BinWorkspace* ws, char
         w.dvals[b] = reinterpret_cast<uint32_t*>(base + off);
         off += align((size_t)nn * 4);
     }
+    w.drect = reinterpret_cast<ushort4*>(w.dkeys[1]);   // 8 B per Gaussian over dkeys[1] and dvals[1]
     w.tkeys = reinterpret_cast<uint32_t*>(base + off);
     off += align((size_t)cap * 4);
     w.tvals = reinterpret_cast<uint32_t*>(base + off);

@@ -66,12 +66,16 @@ __device__ inline uint32_t block_ballot_scan(uint32_t v, uint32_t& total)
     return before + p;
 }
 
-// Per-chunk sums of tiles_touched[order[k]] over the depth order (k < *count),
-// chunk b = the 256 Gaussians from b * 256.
-__global__ __launch_bounds__(256) void chunk_sum_kernel(const uint32_t* __restrict__ tt,
+// Per-chunk sums of the tile counts over the depth order (k < *count), chunk
+// b = the 256 Gaussians from b * 256; also gathers each drawn Gaussian's tile
+// rectangle into depth order (drect[k] = rect[order[k]]), so that the emit
+// reads rectangles in sequence instead of gathering them again.  The count is
+// the rectangle's area (tiles_touched of a drawn Gaussian).
+__global__ __launch_bounds__(256) void chunk_sum_kernel(const uint16_t* __restrict__ rect,
                                                         const uint32_t* __restrict__ order,
                                                         const int64_t* __restrict__ count,
-                                                        uint32_t* __restrict__ chunk_sums)
+                                                        uint32_t* __restrict__ chunk_sums,
+                                                        ushort4* __restrict__ drect)
 {
     const int64_t drawn = *count;
     if ((int64_t)blockIdx.x * kScanBlock >= drawn) {   // past the drawn Gaussians: uniform
@@ -79,7 +83,12 @@ __global__ __launch_bounds__(256) void chunk_sum_kernel(const uint32_t* __restri
         return;
     }
     const int64_t k = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
-    const uint32_t v = k < drawn ? tt[order[k]] : 0u;
+    uint32_t v = 0u;
+    if (k < drawn) {
+        const ushort4 rc = *reinterpret_cast<const ushort4*>(rect + 4 * (int64_t)order[k]);
+        drect[k] = rc;
+        v = (uint32_t)(rc.z - rc.x) * (uint32_t)(rc.w - rc.y);
+    }
     uint32_t total;
     block_ballot_scan(v, total);
     if (threadIdx.x == 0) chunk_sums[blockIdx.x] = total;
@@ -101,7 +110,7 @@ __global__ void no_pairs_kernel(int64_t* __restrict__ num_pairs, int32_t* __rest
 // 256-pair step finds the Gaussian that owns pair e by a binary search over
 // the workgroup's inclusive pair offsets in LDS, so the work per thread does
 // not depend on footprint sizes and the stores of a step are consecutive.
-__global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ tt, const uint16_t* __restrict__ rect,
+__global__ __launch_bounds__(256) void emit_kernel(const ushort4* __restrict__ drect,
                                                    const uint32_t* __restrict__ order,
                                                    const int64_t* __restrict__ count,
                                                    const uint32_t* __restrict__ chunk_sums, int64_t cap,
@@ -137,7 +146,8 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ 
     const int64_t k = b * kScanBlock + tid;
     const bool valid = k < drawn;
     const uint32_t id = valid ? order[k] : 0u;
-    const uint32_t v = valid ? tt[id] : 0u;
+    const ushort4 rk = valid ? drect[k] : make_ushort4(0, 0, 1, 1);
+    const uint32_t v = valid ? (uint32_t)(rk.z - rk.x) * (uint32_t)(rk.w - rk.y) : 0u;
     if (lane == 0) s_part[wave] = before;
     uint32_t total;
     const uint32_t pre = block_ballot_scan(v, total);   // its barrier orders s_part
@@ -152,7 +162,7 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint32_t* __restrict__ 
     if (pair_start && v) pair_start[id] = base + pre;   // first pair of this Gaussian, emission order
     s_end[tid] = pre + v;
     s_id[tid] = id;
-    s_rc[tid] = v ? *reinterpret_cast<const ushort4*>(rect + 4 * (int64_t)id) : make_ushort4(0, 0, 1, 1);
+    s_rc[tid] = v ? rk : make_ushort4(0, 0, 1, 1);
     __syncthreads();
     for (uint32_t e = (uint32_t)tid; e < total; e += kScanBlock) {
         // owner = number of Gaussians whose pairs all precede e (s_end is non-decreasing, s_end[255] = total)
@@ -328,8 +338,8 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
                                    ws.depth_blocks, ws.hist, ws.digit_totals, nullptr, nullptr, nullptr, &first,
                                    nullptr, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, ws.dvals[0],
-                           ws.dcount, ws.block_sums);
+        hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.rect, ws.dvals[0],
+                           ws.dcount, ws.block_sums, ws.drect);
     } else {
         hipLaunchKernelGGL(no_pairs_kernel, dim3(1), dim3(1), 0, s, out.num_pairs, out.overflow);
     }
@@ -344,7 +354,7 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
     uint32_t* vb = last_reads_a ? alias_v : ws.tvals;
     // 3. pair offsets in depth order, pair count, overflow flag, emission
     if (n > 0)
-        hipLaunchKernelGGL(emit_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.tiles_touched, proj.rect, ws.dvals[0],
+        hipLaunchKernelGGL(emit_kernel, dim3((unsigned)nb), dim3(256), 0, s, ws.drect, ws.dvals[0],
                            ws.dcount, ws.block_sums, cap, cam.tiles_x, out.num_pairs, out.overflow, ka, va,
                            out.pair_start);
     // 4. tile digits; the last pass writes the 64-bit keys and the values, and

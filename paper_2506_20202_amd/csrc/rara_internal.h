@@ -135,6 +135,8 @@ struct BinWorkspace {
     int64_t* dcount;         // drawn-Gaussian count
     uint32_t* dkeys[2];      // depth keys, ping-pong [n]
     uint32_t* dvals[2];      // Gaussian indices, ping-pong [n]
+    ushort4* drect;          // [n] tile rectangles in depth order, over dkeys[1] and dvals[1] (free
+                             // once the depth sort has ended in buffer 0)
     uint32_t* tkeys;         // tile keys [cap]
     uint32_t* tvals;         // Gaussian indices [cap]
     uint32_t* hist;          // [kRadix][max(depth_blocks, tile_blocks)]

@@ -186,12 +186,14 @@ __global__ __launch_bounds__(256) void ranges_clear_kernel(uint32_t* __restrict_
 }
 
 // Blend schedule: the tiles whose list has at least kHeavyList entries come
-// first, so that the longest walks start earliest, and among them those with
-// at least kUnitList entries (the forward blend gives the first
-// kMaxUnitTiles of the group four workgroups each); then the other tiles;
-// each class in tile order.  work[h] = h-th long-list tile, work[H + l] = l-th
-// other tile, work[T] = H.  Tiles without pairs (end 0) get the empty range
-// (0, 0).
+// first, so that the longest walks start earliest, and among them the up to
+// kMaxUnitTiles longest (the forward blend gives the first kMaxUnitTiles of
+// the group four workgroups each): those of at least L* entries, L* the
+// smallest of kHeavyList + kUnitBucket k (k = 0 .. 255) that at most
+// kMaxUnitTiles lists reach, from a histogram of the long lists' lengths; then
+// the other tiles; each class in tile order.  work[h] = h-th long-list tile,
+// work[H + l] = l-th other tile, work[T] = H.  Tiles without pairs (end 0) get
+// the empty range (0, 0).
 //
 // One 1024-thread workgroup, so all of it runs on one CU: the accesses are
 // kept coalesced (thread t takes tiles t, t + 1024, ... of each 8192-tile
@@ -201,8 +203,10 @@ __global__ __launch_bounds__(256) void ranges_clear_kernel(uint32_t* __restrict_
 // the lanes before it in its wave.  A first sweep counts the classes (the
 // ranges of the first block stay in registers), the second writes the ranges
 // and the schedule.
-__device__ inline bool plan_heavy(uint2 r) { return r.y != 0u && r.y - r.x >= kHeavyList; }
-__device__ inline bool plan_unit(uint2 r) { return r.y != 0u && r.y - r.x >= kUnitList; }
+__device__ inline uint32_t plan_len(uint2 r) { return r.y != 0u ? r.y - r.x : 0u; }
+__device__ inline bool plan_heavy(uint2 r) { return plan_len(r) >= kHeavyList; }
+// histogram bucket of a long list's length
+__device__ inline uint32_t plan_bucket(uint32_t len) { return min(255u, (len - kHeavyList) / kUnitBucket); }
 
 __global__ __launch_bounds__(1024) void plan_kernel(uint2* __restrict__ ranges, int num_tiles,
                                                     uint32_t* __restrict__ work)
@@ -211,6 +215,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(uint2* __restrict__ ranges, 
     // per (round, wave): the count of each class (very long, long), then its exclusive prefix
     __shared__ uint32_t s_cnt[2][kRounds * 16];
     __shared__ uint32_t s_tot[2][16];
+    __shared__ uint32_t s_hist[256];   // long lists per length bucket
+    __shared__ uint32_t s_unit[2];     // L*, V
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     auto load_block = [&](int b0, uint2* r) {
 #pragma unroll
@@ -220,41 +226,75 @@ __global__ __launch_bounds__(1024) void plan_kernel(uint2* __restrict__ ranges, 
             if (t >= num_tiles) r[j] = make_uint2(0u, 0u);
         }
     };
-    // sweep 1: the class sizes V (very long) and H (all long)
+    if (tid < 256) s_hist[tid] = 0u;
+    __syncthreads();
+    // sweep 1: H (all long) and the histogram of the long lists' lengths
     uint2 r0[kRounds];
     load_block(0, r0);
-    uint32_t hc = 0, vc = 0;
+    uint32_t hc = 0;
 #pragma unroll
-    for (int j = 0; j < kRounds; ++j) {
-        hc += plan_heavy(r0[j]) ? 1u : 0u;
-        vc += plan_unit(r0[j]) ? 1u : 0u;
-    }
+    for (int j = 0; j < kRounds; ++j)
+        if (plan_heavy(r0[j])) {
+            ++hc;
+            atomicAdd(&s_hist[plan_bucket(plan_len(r0[j]))], 1u);
+        }
     for (int b0 = kBlock; b0 < num_tiles; b0 += kBlock) {
         uint2 r[kRounds];
         load_block(b0, r);
 #pragma unroll
-        for (int j = 0; j < kRounds; ++j) {
-            hc += plan_heavy(r[j]) ? 1u : 0u;
-            vc += plan_unit(r[j]) ? 1u : 0u;
+        for (int j = 0; j < kRounds; ++j)
+            if (plan_heavy(r[j])) {
+                ++hc;
+                atomicAdd(&s_hist[plan_bucket(plan_len(r[j]))], 1u);
+            }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) hc += __shfl_xor(hc, off, 64);
+    if (lane == 0) s_tot[1][wave] = hc;
+    __syncthreads();
+    if (wave == 0) {
+        // S(k) = long lists in buckets k.. (non-increasing in k); k* = the smallest k with
+        // S(k) <= kMaxUnitTiles (256 when none), L* = kHeavyList + kUnitBucket k*, V = S(k*).
+        // Lane l holds buckets 4l .. 4l + 3.
+        uint32_t h[4], sum = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            h[i] = s_hist[4 * lane + i];
+            sum += h[i];
+        }
+        uint32_t suf = sum;   // inclusive suffix over lanes
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_down(suf, off, 64);
+            if (lane + off < 64) suf += o;
+        }
+        uint32_t S[4];
+        S[3] = suf - sum + h[3];
+        S[2] = S[3] + h[2];
+        S[1] = S[2] + h[1];
+        S[0] = S[1] + h[0];
+        int kl = 4;   // this lane's smallest qualifying bucket, 4 when none
+#pragma unroll
+        for (int i = 3; i >= 0; --i)
+            if (S[i] <= kMaxUnitTiles) kl = i;
+        const uint64_t q = __ballot(kl < 4);
+        if (q == 0ull) {
+            if (lane == 0) {
+                s_unit[0] = 0xffffffffu;
+                s_unit[1] = 0u;
+            }
+        } else if (lane == (int)__builtin_ctzll(q)) {
+            s_unit[0] = kHeavyList + kUnitBucket * (uint32_t)(4 * lane + kl);
+            s_unit[1] = S[kl];
         }
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        hc += __shfl_xor(hc, off, 64);
-        vc += __shfl_xor(vc, off, 64);
-    }
-    if (lane == 0) {
-        s_tot[0][wave] = vc;
-        s_tot[1][wave] = hc;
-    }
     __syncthreads();
-    uint32_t V = 0, H = 0;
+    const uint32_t Lstar = s_unit[0], V = s_unit[1];
+    uint32_t H = 0;
 #pragma unroll
-    for (int w = 0; w < 16; ++w) {
-        V += s_tot[0][w];
-        H += s_tot[1][w];
-    }
+    for (int w = 0; w < 16; ++w) H += s_tot[1][w];
     __syncthreads();   // s_tot is rewritten below
+    auto plan_unit = [&](uint2 r) { return plan_len(r) >= Lstar; };
     // sweep 2: ranges and positions, block by block
     uint32_t carry[2] = {0u, 0u};   // tiles of each class in the blocks before
     for (int b0 = 0; b0 < num_tiles; b0 += kBlock) {

@@ -112,10 +112,11 @@ constexpr uint32_t kDealChunk = 16;
 inline int64_t tiles_grid(int64_t tiles) { return tiles + 16 + 16 * (int64_t)kDealChunk; }
 // forward blend: the first kMaxUnitTiles long-list tiles run as four quadrant
 // units each (the grid's padding, workgroups that find no work and exit, stays
-// a few thousand at most); the schedule puts the lists of kUnitList entries
-// or more first
+// a few thousand at most); the schedule puts the up to kMaxUnitTiles longest
+// lists first, found from a histogram of the long lists' lengths in buckets of
+// kUnitBucket entries
 constexpr uint32_t kMaxUnitTiles = 512;
-constexpr uint32_t kUnitList = 2048;
+constexpr uint32_t kUnitBucket = 128;
 inline int64_t blend_grid(int64_t tiles)
 {
     const int64_t u = tiles < (int64_t)kMaxUnitTiles ? tiles : (int64_t)kMaxUnitTiles;

@@ -8,8 +8,21 @@ import torch
 from paper_2506_20202_amd import renderer as R
 
 TILE = 16
-HEAVY_LIST = 1024   # lists of at least this many entries are scheduled first
-UNIT_LIST = 2048    # and among them, first, those of at least this many
+HEAVY_LIST = 1024      # lists of at least this many entries are scheduled first
+MAX_UNIT_TILES = 512   # and among them, first, the up to this many longest
+UNIT_BUCKET = 128      # (by a histogram of their lengths in buckets of this many entries)
+
+
+def unit_threshold(counts):
+    """L*: the smallest HEAVY_LIST + UNIT_BUCKET k (k = 0 .. 255) that at most
+    MAX_UNIT_TILES long lists reach (the last bucket holding every longer
+    list); infinite when even the last bucket holds more."""
+    lng = np.asarray(counts, np.int64)
+    lng = lng[lng >= HEAVY_LIST]
+    hist = np.bincount(np.minimum(255, (lng - HEAVY_LIST) // UNIT_BUCKET), minlength=256)
+    suffix = np.cumsum(hist[::-1])[::-1]
+    ok = np.nonzero(suffix <= MAX_UNIT_TILES)[0]
+    return HEAVY_LIST + UNIT_BUCKET * int(ok[0]) if len(ok) else np.inf
 
 
 def gpu_frame(scene, cam, plane, bg=(0.0, 0.0, 0.0), capacity=None, dscene=None):
@@ -104,13 +117,15 @@ def check_ranges(g):
 
 
 def check_schedule(work, counts):
-    """The blend schedule: the tiles with long lists, those of UNIT_LIST
-    entries or more first, each class in tile order, then the others in tile
-    order, then the number of long-list tiles."""
+    """The blend schedule: the tiles with long lists, those of at least
+    unit_threshold(counts) entries first, each class in tile order, then the
+    others in tile order, then the number of long-list tiles."""
     T = len(counts)
-    very = np.nonzero(counts >= UNIT_LIST)[0]
-    heavy = np.nonzero((counts >= HEAVY_LIST) & (counts < UNIT_LIST))[0]
+    L = unit_threshold(counts)
+    very = np.nonzero(counts >= L)[0]
+    heavy = np.nonzero((counts >= HEAVY_LIST) & (counts < L))[0]
     light = np.nonzero(counts < HEAVY_LIST)[0]
+    assert len(very) <= MAX_UNIT_TILES
     assert int(work[T]) == len(very) + len(heavy), (int(work[T]), len(very), len(heavy))
     np.testing.assert_array_equal(work[:T].astype(np.int64), np.concatenate([very, heavy, light]))
 

@@ -352,7 +352,22 @@ def test_schedule_constants_agree_with_the_gpu_tests():
     internal = open(os.path.join(ROOT, "paper_2506_20202_amd", "csrc", "rara_internal.h")).read()
     from tests import gpu_helpers as H
     assert int(re.search(r"constexpr uint32_t kHeavyList = (\d+);", internal).group(1)) == H.HEAVY_LIST
-    assert int(re.search(r"constexpr uint32_t kUnitList = (\d+);", internal).group(1)) == H.UNIT_LIST
+    assert int(re.search(r"constexpr uint32_t kMaxUnitTiles = (\d+);", internal).group(1)) == H.MAX_UNIT_TILES
+    assert int(re.search(r"constexpr uint32_t kUnitBucket = (\d+);", internal).group(1)) == H.UNIT_BUCKET
+
+
+def test_unit_threshold_takes_the_longest_lists():
+    """The schedule's unit class is the up to 512 longest long lists, to a
+    bucket of 128 entries: all long lists when there are at most 512; else a
+    threshold that at most 512 reach and the next bucket down would exceed."""
+    import numpy as np
+    from tests import gpu_helpers as H
+    assert H.unit_threshold(np.array([5, 1500, 3000])) == H.HEAVY_LIST
+    rng = np.random.default_rng(0)
+    counts = rng.integers(0, 9000, 8160)
+    L = H.unit_threshold(counts)
+    assert (counts >= L).sum() <= 512 < (counts >= L - H.UNIT_BUCKET).sum()
+    assert H.unit_threshold(np.full(600, 40000)) == np.inf   # the last bucket alone holds more than 512
 
 
 def test_sh_constants_agree_with_closed_forms():

@@ -344,17 +344,24 @@ __device__ inline bool tile_of_block(uint32_t b, const uint32_t* __restrict__ wo
 }
 
 // Work unit of forward blend workgroup b: the first U = min(H, kMaxUnitTiles)
-// long-list tiles are blended as four quadrant units each, units 4i .. 4i + 3
-// of the i-th of them on an XCD on that XCD (b mod 8), one after the other,
-// so that the four units of a tile share one L2; the other tiles follow as in
-// tile_of_block (the remaining long tiles first), one workgroup each.  quad
-// is -1 for a whole tile.  blend_grid(T) workgroups cover every case.
+// long-list tiles (the longest, which lead the schedule) are blended as four
+// quadrant units each, the other H - U long-list tiles as whole tiles, and
+// those whole tiles are dispatched first: they are the longest jobs of the
+// launch (a unit does a quarter of a longer list's pixels four entries at a
+// time).  Then the units, units 4i .. 4i + 3 of the i-th tile of an XCD on
+// that XCD (b mod 8), one after the other, so that the four units of a tile
+// share one L2; then the short tiles as in tile_of_block.  quad is -1 for a
+// whole tile.  blend_grid(T) workgroups cover every case.
 __device__ inline bool unit_of_block(uint32_t b, const uint32_t* __restrict__ work, int num_tiles, uint32_t& tile,
                                      int& quad)
 {
     const uint32_t H = work[num_tiles];
     const uint32_t U = H < kMaxUnitTiles ? H : kMaxUnitTiles;
     const uint32_t ub = (U + 7u) & ~7u;
+    const uint32_t hb = (H - U + 7u) & ~7u;   // the whole long-list tiles, dealt as in tile_of_block_in
+    quad = -1;
+    if (b < hb) return tile_of_block_in(b, work + U, H - U, H - U, tile);
+    b -= hb;   // hb is a multiple of 8: b keeps its XCD
     if (b < 4u * ub) {
         const uint32_t x = b & 7u, k = b >> 3;
         const uint32_t i = k >> 2;
@@ -364,9 +371,7 @@ __device__ inline bool unit_of_block(uint32_t b, const uint32_t* __restrict__ wo
         quad = (int)(k & 3u);
         return true;
     }
-    quad = -1;
-    // a multiple of 8 below b: the two share an XCD
-    return tile_of_block_in(b - 4u * ub, work + U, H - U, (uint32_t)num_tiles - U, tile);
+    return tile_of_block_in(b - 4u * ub, work + H, 0u, (uint32_t)num_tiles - H, tile);
 }
 
 }  // namespace rara

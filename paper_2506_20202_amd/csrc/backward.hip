@@ -58,6 +58,80 @@ __device__ inline float wave_sum(float v)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Wave sums of M values at once by halving: a level at lane distance D pairs
+// value i with value i + P (P = ceil(M / 2)) and swaps them with the partner
+// lane l ^ D, so that lanes with bit D clear go on with the sums of the first
+// half and lanes with bit D set with those of the second.  After the levels
+// D = 32, 16, ..., 1 every lane holds one 64-lane sum (or padding) and
+// halve_index names which.  Distances 32 and 16 use v_permlane32_swap and
+// v_permlane16_swap, which exchange both halves in one instruction; 8, 2 and 1
+// use DPP row_ror:8 and quad_perm; 4 uses row_half_mirror (j -> 7 - j) and then
+// quad_perm [3,2,1,0] (j -> j ^ 3).  About 2.5 instructions per value instead
+// of the eight of a wave_sum and its lane select.
+template <int D>
+__device__ inline float lane_xor(float v)
+{
+    const int i = __float_as_int(v);
+    if constexpr (D == 8) {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, i, 0x128, 0xf, 0xf, false));
+    } else if constexpr (D == 4) {
+        const int m = __builtin_amdgcn_update_dpp(0, i, 0x141, 0xf, 0xf, false);
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, m, 0x1b, 0xf, 0xf, false));
+    } else if constexpr (D == 2) {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, i, 0x4e, 0xf, 0xf, false));
+    } else {
+        static_assert(D == 1, "lane distance");
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, i, 0xb1, 0xf, 0xf, false));
+    }
+}
+
+// a[l] + a[l ^ D] in lanes with bit D clear, b[l ^ D] + b[l] in the others
+template <int D>
+__device__ inline float halve_pair(float a, float b, bool hi)
+{
+    if constexpr (D == 32 || D == 16) {
+        const auto r = D == 32 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false)
+                               : __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    } else {
+        return (hi ? b : a) + lane_xor<D>(hi ? a : b);
+    }
+}
+
+template <int M, int D>
+__device__ inline float halve_sum(const float (&v)[M], int lane)
+{
+    static_assert(M >= 1 && M <= 2 * D, "values per lane");
+    constexpr int P = (M + 1) / 2;
+    const bool hi = (lane & D) != 0;
+    float h[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        // a value with no second-half partner is summed in both halves; the
+        // upper copy is padding
+        h[i] = halve_pair<D>(v[i], i + P < M ? v[i + P] : v[i], hi);
+    if constexpr (D == 1)
+        return h[0];
+    else
+        return halve_sum<P, D / 2>(h, lane);
+}
+
+// which of M values halve_sum leaves in this lane, -1 for padding
+__device__ inline int halve_index(int m, int lane)
+{
+    int ms[7];
+    ms[0] = m;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) ms[j + 1] = (ms[j] + 1) / 2;
+    int idx = 0;
+#pragma unroll
+    for (int j = 5; j >= 0; --j) {   // level j has lane distance 32 >> j
+        idx += ((lane >> (5 - j)) & 1) ? ms[j + 1] : 0;
+        if (idx >= ms[j]) return -1;
+    }
+    return idx;
+}
+
 __device__ inline uint32_t wave_max(uint32_t v)
 {
 #pragma unroll
@@ -163,6 +237,7 @@ __device__ inline void blend_back_tile(const Splat* __restrict__ splats, const R
     const RenderParams& p = bp.rp;
     const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int row_all = halve_index(kAccRows, lane), row_base = halve_index(A_D0, lane);
     const int ox8 = (wave & 1) * 8 + (lane & 7), oy8 = (wave >> 1) * 8 + (lane >> 3);
     const float lpx = (float)ox8, lpy = (float)oy8;
     const int px = tx * kTile + ox8, py = ty * kTile + oy8;
@@ -288,22 +363,21 @@ __device__ inline void blend_back_tile(const Splat* __restrict__ splats, const R
                     }
                 }
                 if (__ballot(contributed) != 0ull) {
-                    // the wave sums, row r in lane r, added with one LDS instruction
-                    const float v9[9] = {g_mx, g_my, g_ca, g_cb, g_cc, g_op, g_col[0], g_col[1], g_col[2]};
-                    float mine = 0.0f;
-#pragma unroll
-                    for (int r = 0; r < 9; ++r) {
-                        const float sum = wave_sum(v9[r]);
-                        mine = lane == r ? sum : mine;
-                    }
+                    // the wave sums, one row per lane, added with one LDS instruction
+                    float sum;
+                    int row;
                     if (cut) {
-#pragma unroll
-                        for (int r = 0; r < 12; ++r) {
-                            const float sum = wave_sum(g_ray[r]);
-                            mine = lane == A_D0 + r ? sum : mine;
-                        }
+                        const float v[kAccRows] = {g_mx, g_my, g_ca, g_cb, g_cc, g_op, g_col[0], g_col[1], g_col[2],
+                                                   g_ray[0], g_ray[1], g_ray[2], g_ray[3], g_ray[4], g_ray[5],
+                                                   g_ray[6], g_ray[7], g_ray[8], g_ray[9], g_ray[10], g_ray[11]};
+                        sum = halve_sum<kAccRows, 32>(v, lane);
+                        row = row_all;
+                    } else {
+                        const float v[A_D0] = {g_mx, g_my, g_ca, g_cb, g_cc, g_op, g_col[0], g_col[1], g_col[2]};
+                        sum = halve_sum<A_D0, 32>(v, lane);
+                        row = row_base;
                     }
-                    if (lane < (cut ? kAccRows : A_D0) && mine != 0.0f) atomicAdd(&s_g[e][lane], mine);
+                    if (row >= 0 && sum != 0.0f) atomicAdd(&s_g[e][row], sum);
                 }
             }
         }

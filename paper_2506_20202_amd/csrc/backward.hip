@@ -589,6 +589,7 @@ __global__ __launch_bounds__(256) void slot_sum_kernel(int64_t n, int32_t plane_
     }
 }
 
+template <int DEG>
 __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamParams cam, PlaneParams pl,
                                                                const uint8_t* __restrict__ label,
                                                                const uint32_t* __restrict__ tiles_touched,
@@ -599,7 +600,7 @@ __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamP
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = g.n;
     const bool overflowed = *overflow != 0;   // no sums: every gradient is zero
-    const int ncoef = (g.sh_degree + 1) * (g.sh_degree + 1);
+    constexpr int ncoef = (DEG + 1) * (DEG + 1);
     double pn[4] = {0.0, 0.0, 0.0, 0.0};   // d n_hat, d d_hat contributed by this Gaussian
     if (i < n) {
         double dmu[3] = {0.0, 0.0, 0.0}, ds[3] = {0.0, 0.0, 0.0}, dqv[4] = {0.0, 0.0, 0.0, 0.0};
@@ -618,7 +619,8 @@ __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamP
             const double s[3] = {g.scale[i], g.scale[n + i], g.scale[2 * n + i]};
             double q4[4] = {g.quat[i], g.quat[n + i], g.quat[2 * n + i], g.quat[3 * n + i]};
             const double qlen = sqrt(q4[0] * q4[0] + q4[1] * q4[1] + q4[2] * q4[2] + q4[3] * q4[3]);
-            const double qw = q4[0] / qlen, qx = q4[1] / qlen, qy = q4[2] / qlen, qz = q4[3] / qlen;
+            const double iqlen = 1.0 / qlen;
+            const double qw = q4[0] * iqlen, qx = q4[1] * iqlen, qy = q4[2] * iqlen, qz = q4[3] * iqlen;
             const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
                                  2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
                                  2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
@@ -696,25 +698,35 @@ __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamP
             // colour
             const double dvec[3] = {mu[0] - cam.e[0], mu[1] - cam.e[1], mu[2] - cam.e[2]};
             const double dlen = sqrt(dvec[0] * dvec[0] + dvec[1] * dvec[1] + dvec[2] * dvec[2]);
-            const double dir[3] = {dvec[0] / dlen, dvec[1] / dlen, dvec[2] / dlen};
+            const double idlen = 1.0 / dlen;
+            const double dir[3] = {dvec[0] * idlen, dvec[1] * idlen, dvec[2] * idlen};
+            // every coefficient is loaded before the first is used
+            float shc[ncoef][3];
+#pragma unroll
+            for (int k = 0; k < ncoef; ++k)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) shc[k][ch] = g.sh[((int64_t)k * 3 + ch) * n + i];
             double Y[16], dY[16];
-            sh_values(g.sh_degree, dir[0], dir[1], dir[2], Y);
+            sh_values(DEG, dir[0], dir[1], dir[2], Y);
+#pragma unroll
             for (int k = 0; k < ncoef; ++k) dY[k] = 0.0;
+#pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
                 const double gcol = acc[A_R + ch];
                 double raw = 0.5;
-                for (int k = 0; k < ncoef; ++k) raw += Y[k] * (double)g.sh[((int64_t)k * 3 + ch) * n + i];
+#pragma unroll
+                for (int k = 0; k < ncoef; ++k) raw += Y[k] * (double)shc[k][ch];
                 const bool pass = raw >= 0.0;
+#pragma unroll
                 for (int k = 0; k < ncoef; ++k) {
-                    const int64_t o = ((int64_t)k * 3 + ch) * n + i;
-                    out.sh[o] = pass ? (float)(gcol * Y[k]) : 0.0f;
-                    if (pass) dY[k] += gcol * (double)g.sh[o];
+                    out.sh[((int64_t)k * 3 + ch) * n + i] = pass ? (float)(gcol * Y[k]) : 0.0f;
+                    dY[k] += pass ? gcol * (double)shc[k][ch] : 0.0;
                 }
             }
             double ddir[3];
-            sh_backward(g.sh_degree, dir[0], dir[1], dir[2], dY, ddir);
+            sh_backward(DEG, dir[0], dir[1], dir[2], dY, ddir);
             const double dd = ddir[0] * dir[0] + ddir[1] * dir[1] + ddir[2] * dir[2];
-            for (int a = 0; a < 3; ++a) dmu[a] += (ddir[a] - dir[a] * dd) / dlen;
+            for (int a = 0; a < 3; ++a) dmu[a] += (ddir[a] - dir[a] * dd) * idlen;
 
             // whitened ray set-up of CUTOFF Gaussians
             if (cutg) {
@@ -726,13 +738,14 @@ __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamP
                 }
                 const double gz = acc[A_Z], gdep = acc[A_DEP], gg0 = acc[A_G0];
                 const double v0[3] = {dvec[0] * iz, dvec[1] * iz, dvec[2] * iz};
+                const double ifx = 1.0 / cam.fx, ify = 1.0 / cam.fy;
                 double dv0[3] = {pl.n[0] * gg0, pl.n[1] * gg0, pl.n[2] * gg0};
                 for (int a = 0; a < 3; ++a) {
                     const double ia = 1.0 / s[a];
                     double dsa = 0.0;
                     for (int b2 = 0; b2 < 3; ++b2) {
                         const double mab = R[3 * b2 + a] * ia;   // M^-1[a][b] = R[b][a] / s[a]
-                        const double dM = gd0[a] * v0[b2] + ggx[a] * Rc[b2] / cam.fx + ggy[a] * Rc[3 + b2] / cam.fy;
+                        const double dM = gd0[a] * v0[b2] + ggx[a] * Rc[b2] * ifx + ggy[a] * Rc[3 + b2] * ify;
                         dv0[b2] += mab * gd0[a];
                         dR[3 * b2 + a] += dM * ia;
                         dsa -= dM * mab * ia;
@@ -761,7 +774,7 @@ __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamP
                     2 * x * dR[6] + 2 * y * dR[7];
             const double qn[4] = {qw, qx, qy, qz};
             const double dot = dq[0] * qn[0] + dq[1] * qn[1] + dq[2] * qn[2] + dq[3] * qn[3];
-            for (int k = 0; k < 4; ++k) dqv[k] = (dq[k] - qn[k] * dot) / qlen;
+            for (int k = 0; k < 4; ++k) dqv[k] = (dq[k] - qn[k] * dot) * iqlen;
         } else {
             for (int k = 0; k < ncoef; ++k)
                 for (int ch = 0; ch < 3; ++ch) out.sh[((int64_t)k * 3 + ch) * n + i] = 0.0f;
@@ -841,8 +854,24 @@ hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const Plane
         hipLaunchKernelGGL(slot_sum_kernel, grid, dim3(256), 0, s, g.n, pl.enabled, proj.label, proj.tiles_touched,
                            bins.pair_start, bins.overflow, slots, sums);
         GradPtrs gp{grads.mean, grads.scale, grads.quat, grads.opacity, grads.sh};
-        hipLaunchKernelGGL(project_backward_kernel, grid, dim3(256), 0, s, g, cam, pl, proj.label, proj.tiles_touched,
-                           bins.overflow, sums, gp, plane_acc);
+        switch (g.sh_degree) {
+        case 0:
+            hipLaunchKernelGGL(project_backward_kernel<0>, grid, dim3(256), 0, s, g, cam, pl, proj.label,
+                               proj.tiles_touched, bins.overflow, sums, gp, plane_acc);
+            break;
+        case 1:
+            hipLaunchKernelGGL(project_backward_kernel<1>, grid, dim3(256), 0, s, g, cam, pl, proj.label,
+                               proj.tiles_touched, bins.overflow, sums, gp, plane_acc);
+            break;
+        case 2:
+            hipLaunchKernelGGL(project_backward_kernel<2>, grid, dim3(256), 0, s, g, cam, pl, proj.label,
+                               proj.tiles_touched, bins.overflow, sums, gp, plane_acc);
+            break;
+        default:
+            hipLaunchKernelGGL(project_backward_kernel<3>, grid, dim3(256), 0, s, g, cam, pl, proj.label,
+                               proj.tiles_touched, bins.overflow, sums, gp, plane_acc);
+            break;
+        }
     }
     hipLaunchKernelGGL(plane_finalize_kernel, dim3(1), dim3(64), 0, s, cam, pl, plane_len, plane_acc, bins.overflow,
                        grads.plane);

@@ -76,6 +76,12 @@ def blend_traffic():
     return float(fields["hbm_bytes_per_launch"])
 
 
+# rara_gaussians.sh_layout of the resident scenes: Gaussian-major [n][(D+1)^2][3]
+# (a frame reads only the drawn Gaussians' coefficients) or coefficient-major
+# [(D+1)^2][3][n]
+SH_LAYOUTS = {"gaussian": 1, "coefficient": 0}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +104,8 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=64, help="slots kept (buffers and captured graphs)")
     ap.add_argument("--serve-inflight", type=int, default=8, help="frames running at once")
     ap.add_argument("--serve-lanes", type=int, default=3, help="streams (hardware queues) the frames run on")
+    ap.add_argument("--sh-layout", default="coefficient", choices=sorted(SH_LAYOUTS),
+                    help="layout of the resident scenes' SH coefficients (converted once at upload)")
     ap.add_argument("--profile-steps", type=int, default=0, help="only run this many frames (for profilers)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="with --profile-steps: also run one plain 256 MiB device copy at the end (counter "
@@ -416,7 +424,7 @@ def profile_run(args, sc, grid, dev):
     last warmup + profile_steps dispatches are those frames."""
     import torch
     from paper_2506_20202_amd import renderer as R
-    ds = R.DeviceScene.from_scene(sc, dev)
+    ds = R.DeviceScene.from_scene(sc, dev, sh_layout=SH_LAYOUTS[args.sh_layout])
     W, H = grid[0][0][0].width, grid[0][0][0].height
     fr = R.Frame(sc.n, W, H, 8 * sc.n, dev, walked=False, pair_start=False, sorted_keys=False)
     cap0 = fr.capacity
@@ -487,7 +495,7 @@ def measure(sc, grid, args, reps, label):
     import torch
     from paper_2506_20202_amd import renderer as R
     dev = torch.device("cuda:0")
-    ds = R.DeviceScene.from_scene(sc, dev)
+    ds = R.DeviceScene.from_scene(sc, dev, sh_layout=SH_LAYOUTS[args.sh_layout])
     V, O = len(grid), len(grid[0])
     W, H = grid[0][0][0].width, grid[0][0][0].height
     stream = torch.cuda.current_stream(dev)
@@ -881,6 +889,8 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": dict(desc, parallelism="single GPU", pair_capacity=main_m["pair_capacity"],
+                       sh_layout=("Gaussian-major [n][(D+1)^2][3], converted once when the scene is uploaded"
+                                  if args.sh_layout == "gaussian" else "coefficient-major [(D+1)^2][3][n]"),
                        timing=f"median of {args.reps} sweeps of {args.steps} frames, {PIPE_STREAMS} in flight "
                               "(frame i on stream i mod 3); the frames are the (view, offset) pairs whose plane "
                               "leaves Gaussians both CUTOFF and INVISIBLE, frame i taking view i mod V and "

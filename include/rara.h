@@ -54,14 +54,26 @@ typedef enum {
 /* Labels of Sec. 3.2 (written by rara_preprocess, one byte per Gaussian). */
 enum { RARA_LABEL_INVISIBLE = 0, RARA_LABEL_VISIBLE = 1, RARA_LABEL_CUTOFF = 2 };
 
+/* Layouts of the SH coefficients (rara_gaussians.sh_layout). */
+enum {
+    RARA_SH_COEFF_MAJOR = 0,    /* sh [(sh_degree+1)^2][3][n]                        */
+    RARA_SH_GAUSSIAN_MAJOR = 1  /* sh [n][(sh_degree+1)^2][3]: one Gaussian's
+                                   coefficients contiguous, so that a frame reads
+                                   only the drawn Gaussians' cache lines (align
+                                   the array to 16 bytes for vector loads)       */
+};
+
 /* Gaussians (Sec. 3.1: centre mu, covariance R S^2 R^T, opacity density
  * delta, colour c as real spherical harmonics of degree sh_degree <= 3).
  * Structure-of-arrays float32, n columns each:
  *   mean [3][n], scale [3][n], quat [4][n] (w, x, y, z), opacity [n],
- *   sh [(sh_degree+1)^2][3][n] (coefficient-major, then RGB channel). */
+ *   sh in the layout sh_layout names (coefficient-major, then RGB channel,
+ *   when 0, the value of a zero-initialised struct).  Any other sh_layout is
+ *   RARA_ERR_INVALID. */
 typedef struct {
     int64_t n;
     int32_t sh_degree;
+    int32_t sh_layout;
     const float* mean;
     const float* scale;
     const float* quat;
@@ -196,9 +208,10 @@ typedef struct {
 } rara_binned;
 
 /* Gradients (caller-allocated; overwritten, not accumulated):
- *   mean [3][n], scale [3][n], quat [4][n], opacity [n], sh [(D+1)^2][3][n]
- *   with respect to the raw rara_gaussians inputs, and plane [4] with
- *   respect to the raw (n, d) of rara_plane. */
+ *   mean [3][n], scale [3][n], quat [4][n], opacity [n], and sh in the
+ *   layout of the inputs' sh (sh_layout), with respect to the raw
+ *   rara_gaussians inputs, and plane [4] with respect to the raw (n, d) of
+ *   rara_plane. */
 typedef struct {
     float* mean;
     float* scale;

@@ -21,9 +21,14 @@ RAY_BYTES = 48
 _P = ctypes.c_void_p
 
 
+# rara_gaussians.sh_layout
+SH_COEFF_MAJOR = 0      # sh [(D+1)^2][3][n]
+SH_GAUSSIAN_MAJOR = 1   # sh [n][(D+1)^2][3]
+
+
 class Gaussians(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("mean", _P), ("scale", _P), ("quat", _P),
-                ("opacity", _P), ("sh", _P)]
+    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("sh_layout", ctypes.c_int32), ("mean", _P),
+                ("scale", _P), ("quat", _P), ("opacity", _P), ("sh", _P)]
 
 
 class Camera(ctypes.Structure):

@@ -245,6 +245,7 @@ rara_status rara_preprocess(const rara_gaussians* g, const rara_camera* cam, con
 {
     if (!g || g->n < 0 || !out) return RARA_ERR_INVALID;
     if (g->sh_degree < 0 || g->sh_degree > 3) return RARA_ERR_UNSUPPORTED;
+    if (!sh_layout_ok(g->sh_layout)) return RARA_ERR_INVALID;
     CamParams cp;
     PlaneParams pp;
     if (!make_cam(cam, &cp) || !make_plane(plane, &pp)) return RARA_ERR_INVALID;
@@ -252,7 +253,7 @@ rara_status rara_preprocess(const rara_gaussians* g, const rara_camera* cam, con
     if (g->n == 0) return RARA_OK;
     if (!g->mean || !g->scale || !g->quat || !g->opacity || !g->sh || !proj_ok(out)) return RARA_ERR_INVALID;
     if (pp.enabled && pp.count > 1 && !out->ray_ext) return RARA_ERR_INVALID;   // a region's further planes
-    GaussPtrs gp{g->n, g->sh_degree, g->mean, g->scale, g->quat, g->opacity, g->sh};
+    GaussPtrs gp{g->n, g->sh_degree, g->sh_layout, g->mean, g->scale, g->quat, g->opacity, g->sh};
     const hipError_t e = launch_preprocess(gp, cp, pp, proj_ptrs(out), static_cast<hipStream_t>(stream));
     return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;
 }
@@ -340,6 +341,7 @@ rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam
         return RARA_ERR_INVALID;
     if (pair_capacity < 1 || pair_capacity >= (int64_t(1) << 30)) return RARA_ERR_INVALID;
     if (g->sh_degree < 0 || g->sh_degree > 3) return RARA_ERR_UNSUPPORTED;
+    if (!sh_layout_ok(g->sh_layout)) return RARA_ERR_INVALID;
     if (!proj_ok(proj) || !bins->vals || !bins->ranges || !bins->overflow || !bins->work || !bins->pair_start)
         return RARA_ERR_INVALID;
     if (!grads->plane || (g->n > 0 && (!grads->mean || !grads->scale || !grads->quat || !grads->opacity || !grads->sh)))
@@ -354,7 +356,7 @@ rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam
     const double len = pp.enabled ? std::sqrt((double)plane->n[0] * plane->n[0] + (double)plane->n[1] * plane->n[1] +
                                               (double)plane->n[2] * plane->n[2])
                                   : 1.0;
-    GaussPtrs gp{g->n, g->sh_degree, g->mean, g->scale, g->quat, g->opacity, g->sh};
+    GaussPtrs gp{g->n, g->sh_degree, g->sh_layout, g->mean, g->scale, g->quat, g->opacity, g->sh};
     const hipError_t e = launch_backward(gp, cp, pp, len, proj_ptrs(proj), *bins, pair_capacity, rp, final_T,
                                          n_contrib, dL_dimage, *grads, workspace, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? RARA_OK : RARA_ERR_HIP;

@@ -589,7 +589,7 @@ __global__ __launch_bounds__(256) void slot_sum_kernel(int64_t n, int32_t plane_
     }
 }
 
-template <int DEG>
+template <int DEG, int kShMode>
 __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamParams cam, PlaneParams pl,
                                                                const uint8_t* __restrict__ label,
                                                                const uint32_t* __restrict__ tiles_touched,
@@ -701,26 +701,60 @@ __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamP
             const double idlen = 1.0 / dlen;
             const double dir[3] = {dvec[0] * idlen, dvec[1] * idlen, dvec[2] * idlen};
             // every coefficient is loaded before the first is used
-            float shc[ncoef][3];
+            float shc[3 * ncoef];
+            if constexpr (kShMode == kShCoeffMajor) {
 #pragma unroll
-            for (int k = 0; k < ncoef; ++k)
+                for (int k = 0; k < ncoef; ++k)
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) shc[k][ch] = g.sh[((int64_t)k * 3 + ch) * n + i];
+                    for (int ch = 0; ch < 3; ++ch) shc[3 * k + ch] = g.sh[((int64_t)k * 3 + ch) * n + i];
+            } else {
+                load_sh<ncoef, kShMode>(g, i, shc);
+            }
             double Y[16], dY[16];
             sh_values(DEG, dir[0], dir[1], dir[2], Y);
+            if constexpr (kShMode == kShCoeffMajor) {
 #pragma unroll
-            for (int k = 0; k < ncoef; ++k) dY[k] = 0.0;
+                for (int k = 0; k < ncoef; ++k) dY[k] = 0.0;
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const double gcol = acc[A_R + ch];
-                double raw = 0.5;
+                for (int ch = 0; ch < 3; ++ch) {
+                    const double gcol = acc[A_R + ch];
+                    double raw = 0.5;
 #pragma unroll
-                for (int k = 0; k < ncoef; ++k) raw += Y[k] * (double)shc[k][ch];
-                const bool pass = raw >= 0.0;
+                    for (int k = 0; k < ncoef; ++k) raw += Y[k] * (double)shc[3 * k + ch];
+                    const bool pass = raw >= 0.0;   // the clamp max(0, raw colour)
 #pragma unroll
-                for (int k = 0; k < ncoef; ++k) {
-                    out.sh[((int64_t)k * 3 + ch) * n + i] = pass ? (float)(gcol * Y[k]) : 0.0f;
-                    dY[k] += pass ? gcol * (double)shc[k][ch] : 0.0;
+                    for (int k = 0; k < ncoef; ++k) {
+                        out.sh[((int64_t)k * 3 + ch) * n + i] = pass ? (float)(gcol * Y[k]) : 0.0f;
+                        dY[k] += pass ? gcol * (double)shc[3 * k + ch] : 0.0;
+                    }
+                }
+            } else {
+                // the same sums in the same order, each row entry (or group of
+                // four) stored as soon as it is complete
+                bool pass[3];
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    double raw = 0.5;
+#pragma unroll
+                    for (int k = 0; k < ncoef; ++k) raw += Y[k] * (double)shc[3 * k + ch];
+                    pass[ch] = raw >= 0.0;
+                }
+                float q4v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                float* row = out.sh + i * (3 * ncoef);
+#pragma unroll
+                for (int j = 0; j < 3 * ncoef; ++j) {
+                    const int k = j / 3, ch = j % 3;
+                    if (ch == 0) dY[k] = 0.0;
+                    const double gcol = acc[A_R + ch];
+                    const float gv = pass[ch] ? (float)(gcol * Y[k]) : 0.0f;
+                    dY[k] += pass[ch] ? gcol * (double)shc[j] : 0.0;
+                    if constexpr (kShMode == kShRow) {
+                        row[j] = gv;
+                    } else {
+                        q4v[j & 3] = gv;
+                        if ((j & 3) == 3)
+                            reinterpret_cast<float4*>(row)[j >> 2] = make_float4(q4v[0], q4v[1], q4v[2], q4v[3]);
+                    }
                 }
             }
             double ddir[3];
@@ -776,8 +810,19 @@ __global__ __launch_bounds__(256) void project_backward_kernel(GaussPtrs g, CamP
             const double dot = dq[0] * qn[0] + dq[1] * qn[1] + dq[2] * qn[2] + dq[3] * qn[3];
             for (int k = 0; k < 4; ++k) dqv[k] = (dq[k] - qn[k] * dot) * iqlen;
         } else {
-            for (int k = 0; k < ncoef; ++k)
-                for (int ch = 0; ch < 3; ++ch) out.sh[((int64_t)k * 3 + ch) * n + i] = 0.0f;
+            // (loops, not unrolled: unrolled, their addresses are computed once
+            // for both branches and held in registers across the drawn one)
+            if constexpr (kShMode == kShCoeffMajor) {
+#pragma unroll 1
+                for (int j = 0; j < 3 * ncoef; ++j) out.sh[(int64_t)j * n + i] = 0.0f;
+            } else if constexpr (kShMode == kShRow) {
+#pragma unroll 1
+                for (int j = 0; j < 3 * ncoef; ++j) out.sh[i * (3 * ncoef) + j] = 0.0f;
+            } else {
+#pragma unroll 1
+                for (int j = 0; j < 3 * ncoef / 4; ++j)
+                    reinterpret_cast<float4*>(out.sh + i * (3 * ncoef))[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
         }
         for (int a = 0; a < 3; ++a) {
             out.mean[a * n + i] = (float)dmu[a];
@@ -854,24 +899,25 @@ hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const Plane
         hipLaunchKernelGGL(slot_sum_kernel, grid, dim3(256), 0, s, g.n, pl.enabled, proj.label, proj.tiles_touched,
                            bins.pair_start, bins.overflow, slots, sums);
         GradPtrs gp{grads.mean, grads.scale, grads.quat, grads.opacity, grads.sh};
+        const int mode = sh_mode(g.sh_layout, g.sh_degree, g.sh, grads.sh);
+#define RARA_PB(D, M)                                                                                        \
+    hipLaunchKernelGGL((project_backward_kernel<D, M>), grid, dim3(256), 0, s, g, cam, pl, proj.label,        \
+                       proj.tiles_touched, bins.overflow, sums, gp, plane_acc)
         switch (g.sh_degree) {
-        case 0:
-            hipLaunchKernelGGL(project_backward_kernel<0>, grid, dim3(256), 0, s, g, cam, pl, proj.label,
-                               proj.tiles_touched, bins.overflow, sums, gp, plane_acc);
-            break;
+        case 0: if (mode == kShCoeffMajor) RARA_PB(0, kShCoeffMajor); else RARA_PB(0, kShRow); break;
         case 1:
-            hipLaunchKernelGGL(project_backward_kernel<1>, grid, dim3(256), 0, s, g, cam, pl, proj.label,
-                               proj.tiles_touched, bins.overflow, sums, gp, plane_acc);
+            if (mode == kShCoeffMajor) RARA_PB(1, kShCoeffMajor);
+            else if (mode == kShRow) RARA_PB(1, kShRow);
+            else RARA_PB(1, kShRow16);
             break;
-        case 2:
-            hipLaunchKernelGGL(project_backward_kernel<2>, grid, dim3(256), 0, s, g, cam, pl, proj.label,
-                               proj.tiles_touched, bins.overflow, sums, gp, plane_acc);
-            break;
+        case 2: if (mode == kShCoeffMajor) RARA_PB(2, kShCoeffMajor); else RARA_PB(2, kShRow); break;
         default:
-            hipLaunchKernelGGL(project_backward_kernel<3>, grid, dim3(256), 0, s, g, cam, pl, proj.label,
-                               proj.tiles_touched, bins.overflow, sums, gp, plane_acc);
+            if (mode == kShCoeffMajor) RARA_PB(3, kShCoeffMajor);
+            else if (mode == kShRow) RARA_PB(3, kShRow);
+            else RARA_PB(3, kShRow16);
             break;
         }
+#undef RARA_PB
     }
     hipLaunchKernelGGL(plane_finalize_kernel, dim3(1), dim3(64), 0, s, cam, pl, plane_len, plane_acc, bins.overflow,
                        grads.plane);

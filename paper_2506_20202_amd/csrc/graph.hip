@@ -61,6 +61,7 @@ rara_status rara_frame_graph_create(const rara_gaussians* g, const rara_camera* 
     *out = nullptr;
     if (!g || !shape || !proj || !bins || !image || !final_T || !n_contrib || g->n <= 0) return RARA_ERR_INVALID;
     if (g->sh_degree < 0 || g->sh_degree > 3) return RARA_ERR_UNSUPPORTED;
+    if (!sh_layout_ok(g->sh_layout)) return RARA_ERR_INVALID;
     if (!g->mean || !g->scale || !g->quat || !g->opacity || !g->sh || !proj_complete(proj)) return RARA_ERR_INVALID;
     if (!bins->vals || !bins->ranges || !bins->overflow || !bins->work) return RARA_ERR_INVALID;
     CamParams cp;
@@ -79,7 +80,7 @@ rara_status rara_frame_graph_create(const rara_gaussians* g, const rara_camera* 
         return RARA_ERR_HIP;
     }
 
-    const GaussPtrs gp{g->n, g->sh_degree, g->mean, g->scale, g->quat, g->opacity, g->sh};
+    const GaussPtrs gp{g->n, g->sh_degree, g->sh_layout, g->mean, g->scale, g->quat, g->opacity, g->sh};
     const ProjPtrs pp{proj->label, static_cast<Splat*>(proj->splat), static_cast<RayRec*>(proj->ray), nullptr,
                       proj->depth, proj->rect, proj->tiles_touched};
     hipStream_t s = nullptr;

@@ -43,14 +43,18 @@ __device__ inline void sh_eval(int deg, double x, double y, double z, double* Y)
 
 // kDeg: the SH degree, fixed per launch so that every coefficient load of a
 // Gaussian is issued before the first one is used.
-template <int kDeg>
+template <int kDeg, int kShMode>
 __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl,
                                                const ProjPtrs& out, int64_t i)
 {
     const int64_t n = g.n;
 
+    // every per-Gaussian input but the SH is loaded here, once: the output
+    // stores come last, so no load waits behind a store that may alias it
     const double mu[3] = {g.mean[i], g.mean[n + i], g.mean[2 * n + i]};
     const double s[3] = {g.scale[i], g.scale[n + i], g.scale[2 * n + i]};
+    const float qf[4] = {g.quat[i], g.quat[n + i], g.quat[2 * n + i], g.quat[3 * n + i]};
+    const float opf = g.opacity[i];
 
     // Sec. 3.2: d_ep = n.mu + d, r = 3 max(sigma); hard clipping keeps a
     // Gaussian by its centre's side; the tight variant takes r = 3 |S R^T n|.
@@ -73,7 +77,7 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
             label = behind ? RARA_LABEL_INVISIBLE : RARA_LABEL_VISIBLE;
         } else {
             const bool tight = (pl.enabled & RARA_CLIP_TIGHT) != 0;
-            double qw = g.quat[i], qx = g.quat[n + i], qy = g.quat[2 * n + i], qz = g.quat[3 * n + i];
+            double qw = qf[0], qx = qf[1], qy = qf[2], qz = qf[3];
             const double ql = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
             qw /= ql; qx /= ql; qy /= ql; qz /= ql;
             // 3 |S R^T n|: the half-width of the 3-sigma ellipsoid along n
@@ -107,7 +111,6 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
             label = outside ? RARA_LABEL_INVISIBLE : (inside ? RARA_LABEL_VISIBLE : RARA_LABEL_CUTOFF);
         }
     }
-    out.label[i] = label;
     uint32_t touched = 0;
 
     if (label != RARA_LABEL_INVISIBLE) {
@@ -115,8 +118,13 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
         if (tz > cam.near_z) {
             const double tx = cam.R[0] * mu[0] + cam.R[1] * mu[1] + cam.R[2] * mu[2] + cam.t[0];
             const double ty = cam.R[3] * mu[0] + cam.R[4] * mu[1] + cam.R[5] * mu[2] + cam.t[1];
+            // the SH loads are issued here, so that they are in flight during
+            // the projection (a Gaussian culled by its footprint wastes them)
+            constexpr int ncoef = (kDeg + 1) * (kDeg + 1);
+            float shv[3 * ncoef];
+            load_sh<ncoef, kShMode>(g, i, shv);
             // rotation of the normalised quaternion (w, x, y, z)
-            double qw = g.quat[i], qx = g.quat[n + i], qy = g.quat[2 * n + i], qz = g.quat[3 * n + i];
+            double qw = qf[0], qx = qf[1], qy = qf[2], qz = qf[3];
             const double qs = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
             qw *= qs; qx *= qs; qy *= qs; qz *= qs;
             const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
@@ -161,11 +169,10 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
                     const double dl = 1.0 / sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
                     double Y[16];
                     sh_eval(kDeg, dir[0] * dl, dir[1] * dl, dir[2] * dl, Y);
-                    constexpr int ncoef = (kDeg + 1) * (kDeg + 1);
                     double rgb[3] = {0.5, 0.5, 0.5};
 #pragma unroll
                     for (int k = 0; k < ncoef; ++k)
-                        for (int c = 0; c < 3; ++c) rgb[c] += Y[k] * (double)g.sh[((int64_t)k * 3 + c) * n + i];
+                        for (int c = 0; c < 3; ++c) rgb[c] += Y[k] * (double)shv[3 * k + c];
 
                     const double idet = 1.0 / det;
                     Splat sp;
@@ -174,7 +181,7 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
                     sp.ca = (float)(c11 * idet);
                     sp.cb = (float)(-c01 * idet);
                     sp.cc = (float)(c00 * idet);
-                    sp.op = g.opacity[i];
+                    sp.op = opf;
                     sp.r = (float)fmax(0.0, rgb[0]);
                     sp.g = (float)fmax(0.0, rgb[1]);
                     sp.b = (float)fmax(0.0, rgb[2]);
@@ -215,18 +222,19 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
             }
         }
     }
+    out.label[i] = label;
     out.tiles_touched[i] = touched;
 }
 
-template <int kDeg>
+template <int kDeg, int kShMode>
 __global__ __launch_bounds__(256) void preprocess_kernel(GaussPtrs g, CamParams cam, PlaneParams pl, ProjPtrs out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < g.n) preprocess_one<kDeg>(g, cam, pl, out, i);
+    if (i < g.n) preprocess_one<kDeg, kShMode>(g, cam, pl, out, i);
 }
 
 // Frame-graph variant: camera and plane read from device memory.
-template <int kDeg>
+template <int kDeg, int kShMode>
 __global__ __launch_bounds__(256) void preprocess_fp_kernel(GaussPtrs g, const FrameParams* __restrict__ fp,
                                                             ProjPtrs out)
 {
@@ -234,8 +242,47 @@ __global__ __launch_bounds__(256) void preprocess_fp_kernel(GaussPtrs g, const F
     if (i >= g.n) return;
     // read through the pointer: a private copy of the plane arrays, indexed
     // by the plane number, would live in scratch memory
-    preprocess_one<kDeg>(g, fp->cam, fp->plane, out, i);
+    preprocess_one<kDeg, kShMode>(g, fp->cam, fp->plane, out, i);
 }
+
+// Launches kernel<degree, SH mode> for the degree and SH mode of g (rows of
+// degrees 0 and 2 are not a multiple of four floats: no 16-byte variant).
+template <template <int, int> class L, typename... A>
+void launch_by_sh(const GaussPtrs& g, A... args)
+{
+    const int mode = sh_mode(g.sh_layout, g.sh_degree, g.sh);
+    switch (g.sh_degree) {
+    case 0: mode == kShCoeffMajor ? L<0, kShCoeffMajor>::go(g, args...) : L<0, kShRow>::go(g, args...); break;
+    case 1:
+        mode == kShCoeffMajor ? L<1, kShCoeffMajor>::go(g, args...)
+                              : (mode == kShRow ? L<1, kShRow>::go(g, args...) : L<1, kShRow16>::go(g, args...));
+        break;
+    case 2: mode == kShCoeffMajor ? L<2, kShCoeffMajor>::go(g, args...) : L<2, kShRow>::go(g, args...); break;
+    default:
+        mode == kShCoeffMajor ? L<3, kShCoeffMajor>::go(g, args...)
+                              : (mode == kShRow ? L<3, kShRow>::go(g, args...) : L<3, kShRow16>::go(g, args...));
+        break;
+    }
+}
+
+template <int kDeg, int kShMode>
+struct LaunchPre {
+    static void go(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl, const ProjPtrs& out,
+                   hipStream_t s)
+    {
+        hipLaunchKernelGGL((preprocess_kernel<kDeg, kShMode>), dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s,
+                           g, cam, pl, out);
+    }
+};
+
+template <int kDeg, int kShMode>
+struct LaunchPreFp {
+    static void go(const GaussPtrs& g, const FrameParams* fp, const ProjPtrs& out, hipStream_t s)
+    {
+        hipLaunchKernelGGL((preprocess_fp_kernel<kDeg, kShMode>), dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0,
+                           s, g, fp, out);
+    }
+};
 
 }  // namespace
 
@@ -243,26 +290,14 @@ hipError_t launch_preprocess(const GaussPtrs& g, const CamParams& cam, const Pla
                              hipStream_t s)
 {
     if (g.n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((g.n + 255) / 256)), block(256);
-    switch (g.sh_degree) {
-    case 0: hipLaunchKernelGGL(preprocess_kernel<0>, grid, block, 0, s, g, cam, pl, out); break;
-    case 1: hipLaunchKernelGGL(preprocess_kernel<1>, grid, block, 0, s, g, cam, pl, out); break;
-    case 2: hipLaunchKernelGGL(preprocess_kernel<2>, grid, block, 0, s, g, cam, pl, out); break;
-    default: hipLaunchKernelGGL(preprocess_kernel<3>, grid, block, 0, s, g, cam, pl, out); break;
-    }
+    launch_by_sh<LaunchPre>(g, cam, pl, out, s);
     return hipGetLastError();
 }
 
 hipError_t launch_preprocess_fp(const GaussPtrs& g, const FrameParams* fp, const ProjPtrs& out, hipStream_t s)
 {
     if (g.n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((g.n + 255) / 256)), block(256);
-    switch (g.sh_degree) {
-    case 0: hipLaunchKernelGGL(preprocess_fp_kernel<0>, grid, block, 0, s, g, fp, out); break;
-    case 1: hipLaunchKernelGGL(preprocess_fp_kernel<1>, grid, block, 0, s, g, fp, out); break;
-    case 2: hipLaunchKernelGGL(preprocess_fp_kernel<2>, grid, block, 0, s, g, fp, out); break;
-    default: hipLaunchKernelGGL(preprocess_fp_kernel<3>, grid, block, 0, s, g, fp, out); break;
-    }
+    launch_by_sh<LaunchPreFp>(g, fp, out, s);
     return hipGetLastError();
 }
 

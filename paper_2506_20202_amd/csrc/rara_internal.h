@@ -65,12 +65,55 @@ struct PlaneParams {
 struct GaussPtrs {
     int64_t n;
     int sh_degree;
+    int sh_layout;   // RARA_SH_COEFF_MAJOR or RARA_SH_GAUSSIAN_MAJOR
     const float* mean;
     const float* scale;
     const float* quat;
     const float* opacity;
     const float* sh;
 };
+
+// How a kernel addresses the SH coefficients, fixed per launch on the host:
+// the coefficient-major layout; Gaussian-major rows read a float at a time;
+// Gaussian-major rows of a multiple of four floats in 16-byte aligned arrays,
+// read and written with 16-byte accesses.  A compile-time choice, so that the
+// compiler never merges the layouts' loads into one set of selected addresses.
+enum { kShCoeffMajor = 0, kShRow = 1, kShRow16 = 2 };
+
+inline int sh_mode(int sh_layout, int sh_degree, const void* a, const void* b = nullptr)
+{
+    if (sh_layout != RARA_SH_GAUSSIAN_MAJOR) return kShCoeffMajor;
+    const int row = 3 * (sh_degree + 1) * (sh_degree + 1);
+    const bool aligned = (reinterpret_cast<uintptr_t>(a) & 15u) == 0u && (reinterpret_cast<uintptr_t>(b) & 15u) == 0u;
+    return row % 4 == 0 && aligned ? kShRow16 : kShRow;
+}
+
+// The 3 (D+1)^2 SH coefficients of Gaussian i as v[3k + c] (coefficient k,
+// channel c).
+template <int kCoef, int kMode>
+__device__ inline void load_sh(const GaussPtrs& g, int64_t i, float (&v)[3 * kCoef])
+{
+    constexpr int kN = 3 * kCoef;
+    if constexpr (kMode == kShRow16) {
+        static_assert(kN % 4 == 0, "16-byte rows");
+        const float4* s4 = reinterpret_cast<const float4*>(g.sh + i * kN);
+#pragma unroll
+        for (int j = 0; j < kN / 4; ++j) {
+            const float4 q = s4[j];
+            v[4 * j] = q.x;
+            v[4 * j + 1] = q.y;
+            v[4 * j + 2] = q.z;
+            v[4 * j + 3] = q.w;
+        }
+    } else if constexpr (kMode == kShRow) {
+        const float* src = g.sh + i * kN;
+#pragma unroll
+        for (int j = 0; j < kN; ++j) v[j] = src[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < kN; ++j) v[j] = g.sh[(int64_t)j * g.n + i];
+    }
+}
 
 struct ProjPtrs {
     uint8_t* label;
@@ -184,6 +227,7 @@ hipError_t launch_blend_fp(const Splat* splat, const RayRec* ray, const rara_bin
                            int num_tiles, float* image, float* final_T, uint32_t* n_contrib, uint32_t* n_walked,
                            hipStream_t s);
 // host-side parameter blocks shared by the ABI entry points and frame graphs
+inline bool sh_layout_ok(int32_t v) { return v == RARA_SH_COEFF_MAJOR || v == RARA_SH_GAUSSIAN_MAJOR; }
 bool make_cam_params(const rara_camera* c, CamParams* p);
 bool make_plane_params(const rara_plane* pl, PlaneParams* p);
 RenderParams make_render_params(const CamParams& cp, const PlaneParams& pp, const float* bg);

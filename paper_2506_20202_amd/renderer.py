@@ -23,7 +23,10 @@ def _ptr(t: Optional[torch.Tensor]) -> int:
 
 @dataclasses.dataclass
 class DeviceScene:
-    """A scene resident in HBM, structure-of-arrays float32 (rara_gaussians)."""
+    """A scene resident in HBM, structure-of-arrays float32 (rara_gaussians).
+    ``sh`` is [(D+1)^2][3][n] (``SH_COEFF_MAJOR``) or [n][(D+1)^2][3]
+    (``SH_GAUSSIAN_MAJOR``: a frame then reads only the drawn Gaussians'
+    coefficients); gradients of ``sh`` come back in the same layout."""
 
     mean: torch.Tensor
     scale: torch.Tensor
@@ -31,21 +34,30 @@ class DeviceScene:
     opacity: torch.Tensor
     sh: torch.Tensor
     sh_degree: int
+    sh_layout: int = B.SH_COEFF_MAJOR
 
     @property
     def n(self) -> int:
         return int(self.mean.shape[1])
 
     @staticmethod
-    def from_scene(scene, device="cuda") -> "DeviceScene":
+    def from_scene(scene, device="cuda", sh_layout: int = B.SH_COEFF_MAJOR) -> "DeviceScene":
+        """Uploads a host scene (SH coefficient-major), converting the SH to
+        ``sh_layout`` once on the way."""
         t = lambda a: torch.from_numpy(a).to(device=device, dtype=torch.float32).contiguous()
-        return DeviceScene(t(scene.mean), t(scene.scale), t(scene.quat), t(scene.opacity), t(scene.sh),
-                           int(scene.sh_degree))
+        sh = t(scene.sh)
+        if sh_layout == B.SH_GAUSSIAN_MAJOR:
+            sh = sh.permute(2, 0, 1).contiguous()
+        elif sh_layout != B.SH_COEFF_MAJOR:
+            raise ValueError(f"unknown SH layout {sh_layout}")
+        return DeviceScene(t(scene.mean), t(scene.scale), t(scene.quat), t(scene.opacity), sh,
+                           int(scene.sh_degree), int(sh_layout))
 
     def struct(self) -> B.Gaussians:
         g = B.Gaussians()
         g.n = self.n
         g.sh_degree = self.sh_degree
+        g.sh_layout = self.sh_layout
         g.mean, g.scale, g.quat = _ptr(self.mean), _ptr(self.scale), _ptr(self.quat)
         g.opacity, g.sh = _ptr(self.opacity), _ptr(self.sh)
         return g

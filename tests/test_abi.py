@@ -136,6 +136,16 @@ def test_argument_validation_before_any_launch(B):
     assert lib.rara_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(pl), ctypes.byref(out), None) \
         == B.RARA_ERR_UNSUPPORTED
     g.sh_degree = 0
+    # an SH layout other than the two the header names
+    hdr = open(os.path.join(ROOT, "include", "rara.h")).read()
+    assert int(re.search(r"RARA_SH_COEFF_MAJOR = (\d+)", hdr).group(1)) == B.SH_COEFF_MAJOR
+    assert int(re.search(r"RARA_SH_GAUSSIAN_MAJOR = (\d+)", hdr).group(1)) == B.SH_GAUSSIAN_MAJOR
+    g0 = B.Gaussians()
+    for layout, want in [(B.SH_COEFF_MAJOR, B.RARA_OK), (B.SH_GAUSSIAN_MAJOR, B.RARA_OK), (2, B.RARA_ERR_INVALID),
+                         (-1, B.RARA_ERR_INVALID)]:
+        g0.sh_layout = layout   # n = 0: validated, then nothing to launch
+        assert lib.rara_preprocess(ctypes.byref(g0), ctypes.byref(cam), ctypes.byref(pl), ctypes.byref(out),
+                                   None) == want, layout
     # zero plane normal with clipping enabled
     pl0 = B.Plane()
     pl0.enabled = 1

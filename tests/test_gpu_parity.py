@@ -575,3 +575,45 @@ def test_schedule_over_many_tiles():
     print(f"P={g['P']} tiles={len(lens)} long={len(long_tiles)}", flush=True)
     assert len(lens) == 147 * 147
     assert len(np.unique(long_tiles // 8192)) >= 2
+
+
+def _scene_with_sh_layout(sc, dev, layout, aligned=True):
+    """sc on the device with its SH in `layout`; aligned=False puts a
+    Gaussian-major array 4 bytes past a 16-byte boundary (the kernels then
+    read it a float at a time)."""
+    import torch
+    from paper_2506_20202_amd import binding as B
+    from paper_2506_20202_amd import renderer as R
+    ds = R.DeviceScene.from_scene(sc, dev, sh_layout=layout)
+    if layout == B.SH_GAUSSIAN_MAJOR and not aligned:
+        buf = torch.zeros(ds.sh.numel() + 1, dtype=torch.float32, device=dev)
+        buf[1:] = ds.sh.reshape(-1)
+        ds.sh = buf[1:].view(ds.sh.shape)
+        assert ds.sh.data_ptr() % 16 != 0
+    return ds
+
+
+@pytest.mark.parametrize("deg", [0, 1, 2, 3])
+def test_sh_layouts_give_identical_frames(deg):
+    """The coefficient-major and the Gaussian-major SH layouts (16-byte aligned
+    or not) give bit-identical projected splats and frames; the frame also
+    matches the oracle."""
+    import torch
+    from paper_2506_20202_amd import binding as B
+    dev = torch.device("cuda:0")
+    sc, cam, pl = scenes.grad_scene(7, n=400, sh_degree=deg), scenes.grad_camera(96), scenes.grad_plane(7)
+    print(f"deg={deg} n={sc.n}", flush=True)
+    ref = H.gpu_frame(sc, cam, pl, dscene=_scene_with_sh_layout(sc, dev, B.SH_COEFF_MAJOR))
+    for aligned in (True, False):
+        g = H.gpu_frame(sc, cam, pl, dscene=_scene_with_sh_layout(sc, dev, B.SH_GAUSSIAN_MAJOR, aligned))
+        for k in ("label", "tiles_touched", "vals", "ranges", "image", "final_T", "n_contrib"):
+            np.testing.assert_array_equal(g[k], ref[k], err_msg=f"{k} aligned={aligned}")
+        # the per-Gaussian records are written for drawn Gaussians only
+        drawn = ref["tiles_touched"] > 0
+        assert drawn.any()
+        for k in ["rect", "depth"] + [k for k in ref if k.startswith("splat_")]:
+            np.testing.assert_array_equal(g[k][drawn], ref[k][drawn], err_msg=f"{k} aligned={aligned}")
+    o = oracle.render(sc, cam, pl)
+    H.check_projection(ref, o)
+    err, flagged, _ = H.image_error(ref["image"], o)
+    assert err <= TOL and flagged < 0.05

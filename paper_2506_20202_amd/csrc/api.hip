@@ -177,7 +177,7 @@ size_t rara::bin_workspace_layout(int64_t n, int64_t cap, BinWorkspace* ws, char
     auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
     const int64_t nn = n > 0 ? n : 1;
     int64_t scan_blocks = (nn + kScanBlock - 1) / kScanBlock;
-    const int64_t depth_blocks = (nn + kSortTile - 1) / kSortTile;
+    const int64_t depth_blocks = (nn + kDepthSortTile - 1) / kDepthSortTile;
     int64_t tile_blocks = (cap + kSortTile - 1) / kSortTile;
     if (tile_blocks < 1) tile_blocks = 1;
     const int64_t hist_cols = depth_blocks > tile_blocks ? depth_blocks : tile_blocks;

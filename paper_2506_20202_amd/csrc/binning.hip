@@ -374,9 +374,9 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
     if (n > 0) {
         const SortFirstPass first{proj.depth, proj.tiles_touched, n, ws.dcount, out.ranges,
                                   (int64_t)num_tiles * 2};
-        hipError_t e = sort_passes(ws.dkeys[0], ws.dvals[0], ws.dkeys[1], ws.dvals[1], 4, ws.dcount, nullptr,
-                                   ws.depth_blocks, ws.hist, ws.digit_totals, nullptr, nullptr, nullptr, &first,
-                                   nullptr, s);
+        hipError_t e = sort_passes(ws.dkeys[0], ws.dvals[0], ws.dkeys[1], ws.dvals[1], 4, kDepthSortItems, ws.dcount,
+                                   nullptr, ws.depth_blocks, ws.hist, ws.digit_totals, nullptr, nullptr, nullptr,
+                                   &first, nullptr, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.rect, ws.dvals[0],
                            ws.dcount, ws.block_sums, ws.drect);
@@ -400,7 +400,7 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
     // 4. tile digits; the last pass writes the 64-bit keys and the values, and
     // the tile ranges (tiles without pairs keep (0xffffffff, 0) for plan_kernel)
     const SortLastPass last{n > 0 ? out.ranges : nullptr, num_tiles};
-    return sort_passes(ka, va, kb, vb, tile_passes, out.num_pairs, out.overflow, ws.tile_blocks, ws.hist,
+    return sort_passes(ka, va, kb, vb, tile_passes, kSortItems, out.num_pairs, out.overflow, ws.tile_blocks, ws.hist,
                        ws.digit_totals, out.keys_scratch ? nullptr : out.keys, out.vals, proj.depth, nullptr, &last,
                        s);
 }

@@ -169,8 +169,12 @@ inline int64_t blend_grid(int64_t tiles)
 // ---- bin/sort workspace carve-up -------------------------------------------
 constexpr int kScanBlock = 256;      // Gaussians per scan chunk
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 8;        // keys per thread per sort tile
+constexpr int kSortItems = 8;        // keys per thread per sort tile of the pair passes
 constexpr int kSortTile = kSortThreads * kSortItems;
+// the depth passes sort the drawn Gaussians (about half a million at 1080p):
+// 1024-key tiles give several workgroups per CU instead of one
+constexpr int kDepthSortItems = 4;
+constexpr int kDepthSortTile = kSortThreads * kDepthSortItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
@@ -215,10 +219,11 @@ struct SortLastPass {
     uint32_t* ranges;
     uint32_t num_tiles;
 };
-hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int passes, const int64_t* count,
-                       const int32_t* overflow, int64_t blocks, uint32_t* hist, uint32_t* digit_totals,
-                       uint64_t* final_keys, uint32_t* final_vals, const float* depth, const SortFirstPass* first,
-                       const SortLastPass* last, hipStream_t s);
+// items: keys per thread per sort tile, kDepthSortItems or kSortItems
+hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int passes, int items,
+                       const int64_t* count, const int32_t* overflow, int64_t blocks, uint32_t* hist,
+                       uint32_t* digit_totals, uint64_t* final_keys, uint32_t* final_vals, const float* depth,
+                       const SortFirstPass* first, const SortLastPass* last, hipStream_t s);
 hipError_t launch_ranges_clear(const rara_binned& out, int num_tiles, hipStream_t s);
 hipError_t launch_plan(const rara_binned& out, int num_tiles, hipStream_t s);
 // the same kernels reading their per-frame parameters from device memory

@@ -19,7 +19,8 @@ namespace rara {
 namespace {
 
 constexpr int kWaves = kSortThreads / 64;
-constexpr int kWaveKeys = kSortTile / kWaves;   // consecutive keys owned by one wave
+// kItems keys per thread: a sort tile holds kSortThreads * kItems keys and
+// each wave owns 64 * kItems consecutive ones
 
 __device__ inline uint32_t lanes_below(uint64_t m)
 {
@@ -55,7 +56,7 @@ __device__ inline uint64_t match_digit(uint32_t digit, bool valid)
 // kFilter (first depth pass): item i is Gaussian i, taken when it is drawn
 // (tiles_touched > 0), its key the bits of its positive depth; the kernel also
 // resets the tile ranges of the frame (start 0xffffffff, end 0: no pair yet).
-template <bool kFilter>
+template <bool kFilter, int kItems>
 __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
     const uint32_t* __restrict__ keys, const int64_t* __restrict__ num_items, const int32_t* __restrict__ overflow,
     int shift, uint32_t* __restrict__ hist, int64_t stride, const float* __restrict__ depth,
@@ -66,21 +67,22 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
              w += (int64_t)gridDim.x * kSortThreads)
             ranges[w] = (w & 1) ? 0u : 0xffffffffu;
     if (overflow && *overflow) return;
+    constexpr int kTileKeys = kSortThreads * kItems;
     const int64_t P = kFilter ? n_items : *num_items;
-    const int64_t tile = sort_tile_of_block(blockIdx.x, (P + kSortTile - 1) / kSortTile);
+    const int64_t tile = sort_tile_of_block(blockIdx.x, (P + kTileKeys - 1) / kTileKeys);
     if (tile < 0) return;
-    const int64_t base = tile * kSortTile;
+    const int64_t base = tile * kTileKeys;
     __shared__ uint32_t counts[kWaves][kRadix];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int k = threadIdx.x; k < kWaves * kRadix; k += kSortThreads) (&counts[0][0])[k] = 0u;
     __syncthreads();
-    const int64_t wbase = base + (int64_t)wave * kWaveKeys;
+    const int64_t wbase = base + (int64_t)wave * 64 * kItems;
     // every load of the wave first (the filter's depth and tile-count loads
     // together), then the counts
-    uint32_t key[kSortItems];
-    bool valid[kSortItems];
+    uint32_t key[kItems];
+    bool valid[kItems];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < kItems; ++r) {
         const int64_t idx = wbase + r * 64 + lane;
         const bool in = idx < P;
         if (kFilter) {
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
     }
     // a histogram needs no ranks: one LDS atomic per key into the wave's own row
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r)
+    for (int r = 0; r < kItems; ++r)
         if (valid[r]) atomicAdd(&counts[wave][(key[r] >> shift) & (kRadix - 1)], 1u);
     __syncthreads();
     for (int d = threadIdx.x; d < kRadix; d += kSortThreads) {
@@ -121,11 +123,11 @@ __device__ inline int scan_slot(int i) { return i + (i >> 4); }
 __global__ __launch_bounds__(256) void radix_scan_kernel(uint32_t* __restrict__ hist, int64_t stride,
                                                          const int64_t* __restrict__ num_items, int64_t n_items,
                                                          const int32_t* __restrict__ overflow,
-                                                         uint32_t* __restrict__ digit_totals)
+                                                         uint32_t* __restrict__ digit_totals, int tile_keys)
 {
     if (overflow && *overflow) return;
     const int64_t P = num_items ? *num_items : n_items;
-    const int64_t tiles = (P + kSortTile - 1) / kSortTile;
+    const int64_t tiles = (P + tile_keys - 1) / tile_keys;
     uint32_t* row = hist + (int64_t)blockIdx.x * stride;
     __shared__ uint32_t buf[kScanChunk + kScanChunk / kScanPer];
     __shared__ uint32_t wave_tot[4];
@@ -183,7 +185,7 @@ __global__ __launch_bounds__(256) void radix_scan_kernel(uint32_t* __restrict__ 
 // of radix_upsweep_kernel<true>; the pass also writes the number of drawn
 // Gaussians to count_out.  last.ranges (optional): the tile ranges of
 // SortLastPass.
-template <bool kFinal, bool kFilter>
+template <bool kFinal, bool kFilter, int kItems>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const int64_t* __restrict__ num_items, const int32_t* __restrict__ overflow,
@@ -192,13 +194,14 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     int64_t n_items, int64_t* __restrict__ count_out, SortLastPass last)
 {
     if (overflow && *overflow) return;
+    constexpr int kTileKeys = kSortThreads * kItems;
     const int64_t P = kFilter ? n_items : *num_items;
-    const int64_t tile = sort_tile_of_block(blockIdx.x, (P + kSortTile - 1) / kSortTile);
+    const int64_t tile = sort_tile_of_block(blockIdx.x, (P + kTileKeys - 1) / kTileKeys);
     if (tile < 0) return;
-    const int64_t base = tile * kSortTile;
+    const int64_t base = tile * kTileKeys;
 
-    __shared__ uint32_t s_keys[kSortTile];
-    __shared__ uint32_t s_vals[kSortTile];
+    __shared__ uint32_t s_keys[kTileKeys];
+    __shared__ uint32_t s_vals[kTileKeys];
     __shared__ uint32_t counts[kWaves][kRadix];   // running per-wave digit counts, then per-wave starts
     __shared__ uint32_t local_start[kRadix];      // start of each digit run inside the tile
     __shared__ uint32_t global_start[kRadix];     // global position of that run
@@ -214,12 +217,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     __syncthreads();
 
     // 1. stable rank of every key within (wave, digit)
-    const int64_t wbase = base + (int64_t)wave * kWaveKeys;
-    uint32_t key[kSortItems];
-    uint32_t val[kSortItems];
-    uint32_t packed[kSortItems];   // digit | rank-within-wave-digit << 8 ; 0xffffffff = invalid
+    const int64_t wbase = base + (int64_t)wave * 64 * kItems;
+    uint32_t key[kItems];
+    uint32_t val[kItems];
+    uint32_t packed[kItems];   // digit | rank-within-wave-digit << 8 ; 0xffffffff = invalid
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < kItems; ++r) {
         const int64_t idx = wbase + r * 64 + lane;
         const bool in = idx < P;
         bool valid;
@@ -238,7 +241,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         packed[r] = valid ? 0u : 0xffffffffu;
     }
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < kItems; ++r) {
         const bool valid = packed[r] == 0u;
         const uint32_t d = (key[r] >> shift) & (kRadix - 1);
         const uint64_t peers = match_digit(d, valid);
@@ -292,7 +295,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 
     // 3. stage keys and values in LDS in digit order
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < kItems; ++r) {
         if (packed[r] != 0xffffffffu) {
             const uint32_t d = packed[r] & 0xffu;
             const uint32_t pos = local_start[d] + counts[wave][d] + (packed[r] >> 8);
@@ -326,11 +329,15 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 
 }  // namespace
 
-hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int passes, const int64_t* count,
-                       const int32_t* overflow, int64_t blocks, uint32_t* hist, uint32_t* digit_totals,
-                       uint64_t* final_keys, uint32_t* final_vals, const float* depth, const SortFirstPass* first,
-                       const SortLastPass* last, hipStream_t s)
+namespace {
+
+template <int kItems>
+hipError_t sort_passes_t(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int passes, const int64_t* count,
+                         const int32_t* overflow, int64_t blocks, uint32_t* hist, uint32_t* digit_totals,
+                         uint64_t* final_keys, uint32_t* final_vals, const float* depth, const SortFirstPass* first,
+                         const SortLastPass* last, hipStream_t s)
 {
+    constexpr int kTileKeys = kSortThreads * kItems;
     const SortLastPass none{nullptr, 0u};
     // pass p reads (ka, va) when p is even and (kb, vb) when odd; with final_vals
     // the last pass writes (final_keys, final_vals) instead of the other buffer
@@ -347,31 +354,45 @@ hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, i
         const int shift = p * kRadixBits;
         const bool filter = first && p == 0;
         const SortLastPass lp = (last && p == passes - 1) ? *last : none;
+        const dim3 g(grid), t(kSortThreads);
         if (filter) {
-            hipLaunchKernelGGL(radix_upsweep_kernel<true>, dim3(grid), dim3(kSortThreads), 0, s, nullptr, nullptr,
-                               overflow, shift, hist, blocks, first->depth, first->tt, first->n, first->ranges,
-                               first->range_words);
+            hipLaunchKernelGGL((radix_upsweep_kernel<true, kItems>), g, t, 0, s, nullptr, nullptr, overflow, shift,
+                               hist, blocks, first->depth, first->tt, first->n, first->ranges, first->range_words);
             hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadix), dim3(256), 0, s, hist, blocks, nullptr, first->n,
-                               overflow, digit_totals);
-            hipLaunchKernelGGL((radix_scatter_kernel<false, true>), dim3(grid), dim3(kSortThreads), 0, s, nullptr,
-                               nullptr, kout, vout, nullptr, overflow, shift, hist, blocks, digit_totals, nullptr,
-                               first->depth, first->tt, first->n, first->count_out, lp);
+                               overflow, digit_totals, kTileKeys);
+            hipLaunchKernelGGL((radix_scatter_kernel<false, true, kItems>), g, t, 0, s, nullptr, nullptr, kout, vout,
+                               nullptr, overflow, shift, hist, blocks, digit_totals, nullptr, first->depth, first->tt,
+                               first->n, first->count_out, lp);
             continue;
         }
-        hipLaunchKernelGGL(radix_upsweep_kernel<false>, dim3(grid), dim3(kSortThreads), 0, s, kin, count, overflow,
-                           shift, hist, blocks, nullptr, nullptr, (int64_t)0, nullptr, (int64_t)0);
+        hipLaunchKernelGGL((radix_upsweep_kernel<false, kItems>), g, t, 0, s, kin, count, overflow, shift, hist,
+                           blocks, nullptr, nullptr, (int64_t)0, nullptr, (int64_t)0);
         hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadix), dim3(256), 0, s, hist, blocks, count, (int64_t)0,
-                           overflow, digit_totals);
+                           overflow, digit_totals, kTileKeys);
         if (final_vals && p == passes - 1)
-            hipLaunchKernelGGL((radix_scatter_kernel<true, false>), dim3(grid), dim3(kSortThreads), 0, s, kin, vin,
-                               kout, final_vals, count, overflow, shift, hist, blocks, digit_totals, final_keys, depth,
-                               nullptr, (int64_t)0, nullptr, lp);
+            hipLaunchKernelGGL((radix_scatter_kernel<true, false, kItems>), g, t, 0, s, kin, vin, kout, final_vals,
+                               count, overflow, shift, hist, blocks, digit_totals, final_keys, depth, nullptr,
+                               (int64_t)0, nullptr, lp);
         else
-            hipLaunchKernelGGL((radix_scatter_kernel<false, false>), dim3(grid), dim3(kSortThreads), 0, s, kin, vin,
-                               kout, vout, count, overflow, shift, hist, blocks, digit_totals, nullptr, nullptr,
-                               nullptr, (int64_t)0, nullptr, lp);
+            hipLaunchKernelGGL((radix_scatter_kernel<false, false, kItems>), g, t, 0, s, kin, vin, kout, vout, count,
+                               overflow, shift, hist, blocks, digit_totals, nullptr, nullptr, nullptr, (int64_t)0,
+                               nullptr, lp);
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t sort_passes(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int passes, int items,
+                       const int64_t* count, const int32_t* overflow, int64_t blocks, uint32_t* hist,
+                       uint32_t* digit_totals, uint64_t* final_keys, uint32_t* final_vals, const float* depth,
+                       const SortFirstPass* first, const SortLastPass* last, hipStream_t s)
+{
+    if (items == kDepthSortItems)
+        return sort_passes_t<kDepthSortItems>(ka, va, kb, vb, passes, count, overflow, blocks, hist, digit_totals,
+                                              final_keys, final_vals, depth, first, last, s);
+    return sort_passes_t<kSortItems>(ka, va, kb, vb, passes, count, overflow, blocks, hist, digit_totals, final_keys,
+                                     final_vals, depth, first, last, s);
 }
 
 }  // namespace rara

@@ -16,14 +16,18 @@ from . import renderer as R
 
 class RaraRender(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, mean, scale, quat, opacity, sh, plane4, cam, plane_enabled, bg, frame):
+    def forward(ctx, mean, scale, quat, opacity, sh, plane4, cam, plane_enabled, bg, frame, check):
         sh_degree = int(round(sh.shape[0] ** 0.5)) - 1
         ds = R.DeviceScene(mean.detach(), scale.detach(), quat.detach(), opacity.detach(), sh.detach(), sh_degree)
         pv = [float(v) for v in plane4.detach().cpu().tolist()]
         import numpy as np
         from .scenes import Plane
         plane = Plane(np.array(pv[:3], np.float32), pv[3], int(plane_enabled))   # clip mode
-        out = R.render_checked(ds, frame, cam, plane, bg)
+        if check:
+            out = R.render_checked(ds, frame, cam, plane, bg)
+        else:
+            R.enqueue_frame(ds, frame, cam, plane, bg)
+            out = frame.out
         ctx.save_for_backward(mean, scale, quat, opacity, sh, plane4)
         ctx.frame, ctx.cam, ctx.plane, ctx.bg, ctx.ds = frame, cam, plane, bg, ds
         return out.image.clone()
@@ -48,14 +52,27 @@ class RaraRender(torch.autograd.Function):
                           dimg.data_ptr(),
                           gs, ws.data_ptr(), ws_bytes, stream)
         return (g["mean"], g["scale"], g["quat"], g["opacity"], g["sh"], dplane.to(plane4.device, plane4.dtype),
-                None, None, None, None)
+                None, None, None, None, None)
 
 
 def render(mean, scale, quat, opacity, sh, plane4, cam, plane_enabled=True, bg=(0.0, 0.0, 0.0), frame=None,
-           capacity=None):
-    """Differentiable RaRa-clipped image [3][H][W] of one camera."""
+           capacity=None, check=True):
+    """Differentiable RaRa-clipped image [3][H][W] of one camera.
+
+    check=True synchronises once to read the frame's overflow flag and grows
+    the pair capacity and re-renders when it is set.  check=False only
+    enqueues the frame: the caller reads ``frame.bins.overflow`` later (for
+    example once for all the views of a batch, see ``overflowed``) and
+    discards the result when it is set."""
     if frame is None:
         n = int(mean.shape[1])
         frame = R.Frame(n, cam.width, cam.height, capacity or max(1 << 16, 16 * n), mean.device, walked=False,
                         sorted_keys=False)
-    return RaraRender.apply(mean, scale, quat, opacity, sh, plane4, cam, plane_enabled, tuple(bg), frame)
+    return RaraRender.apply(mean, scale, quat, opacity, sh, plane4, cam, plane_enabled, tuple(bg), frame, bool(check))
+
+
+def overflowed(frames) -> bool:
+    """Whether any of the frames' pair capacity overflowed (one
+    synchronisation for all of them)."""
+    flags = torch.stack([f.bins.overflow.reshape(()) for f in frames])
+    return bool(flags.any().item())

@@ -298,3 +298,37 @@ def test_sh_layouts_give_identical_gradients(deg):
             bound = 1e-5 * float(np.abs(want[k]).max())
             diff = float(np.abs(got[k].astype(np.float64) - want[k]).max())
             assert diff <= bound, (k, aligned, diff, bound)
+
+
+def test_deferred_overflow_check_gives_the_same_gradients():
+    """render(check=False) only enqueues the frame: images and gradients equal
+    those of the checked render (to the backward's float-atomic rounding), and
+    overflowed() reads the flags of several frames at once, true for a frame
+    whose pair capacity is too small."""
+    from paper_2506_20202_amd import autograd as AG
+    from paper_2506_20202_amd import renderer as R
+    dev = torch.device("cuda:0")
+    sc, cam, pl = scenes.grad_scene(6), scenes.grad_camera(), scenes.grad_plane(6)
+    p4 = torch.tensor([float(pl.n[0]), float(pl.n[1]), float(pl.n[2]), float(pl.d)])
+
+    def run(check):
+        ps = [torch.tensor(np.asarray(a), dtype=torch.float32, device=dev, requires_grad=True)
+              for a in (sc.mean, sc.scale, sc.quat, sc.opacity, sc.sh)]
+        fr = R.Frame(sc.n, cam.width, cam.height, 1 << 16, dev, walked=False, sorted_keys=False)
+        img = AG.render(*ps, p4, cam, True, frame=fr, check=check)
+        (img ** 2).mean().backward()
+        assert not AG.overflowed([fr])
+        return img.detach().cpu().numpy(), [p.grad.cpu().numpy() for p in ps]
+
+    img0, g0 = run(True)
+    img1, g1 = run(False)
+    np.testing.assert_array_equal(img1, img0)
+    for a, b in zip(g1, g0):
+        assert np.abs(a.astype(np.float64) - b).max() <= 1e-5 * np.abs(b).max()
+    o = oracle.render(sc, cam, pl, events=False)
+    small = R.Frame(sc.n, cam.width, cam.height, max(1, len(o["ids"]) // 2), dev, walked=False, sorted_keys=False)
+    ok = R.Frame(sc.n, cam.width, cam.height, 1 << 16, dev, walked=False, sorted_keys=False)
+    ds = R.DeviceScene.from_scene(sc, dev)
+    R.enqueue_frame(ds, ok, cam, pl)
+    R.enqueue_frame(ds, small, cam, pl)
+    assert AG.overflowed([ok, small]) and not AG.overflowed([ok])

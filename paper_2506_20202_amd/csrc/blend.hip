@@ -341,15 +341,19 @@ __device__ inline void composite4(float alpha, float cr, float cg, float cb, uin
 
 constexpr int kUnitBatch = 224;   // entries staged per batch, as the tile path (under 20 KB of LDS)
 
-template <bool kWalked>
+// kRegion: a clip region, as in blend_tile (the further planes' terms of each
+// CUTOFF entry staged in s_ext, the weight from the entry's plane mask), in
+// batches of kRegionBatch entries.
+template <bool kWalked, bool kRegion>
 __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
-                                  const uint32_t* __restrict__ vals, const uint2 rg, int tile, int quad,
-                                  const RenderParams& p, float4* s_a, float4* s_b, float2* s_c, CutRec* s_cut,
-                                  uint8_t* s_list,
+                                  const float2* __restrict__ ray_ext, const uint32_t* __restrict__ vals,
+                                  const uint2 rg, int tile, int quad, const RenderParams& p, float4* s_a, float4* s_b,
+                                  float2* s_c, CutRec* s_cut, float2* s_ext, const float2* s_rate, uint8_t* s_list,
                                   float* __restrict__ image, float* __restrict__ final_T,
                                   uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_walked,
                                   uint32_t* __restrict__ n_eval)
 {
+    constexpr int kUB = kRegion ? kRegionBatch : kUnitBatch;
     const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int j = lane & 3, pp = lane >> 2;
@@ -369,11 +373,11 @@ __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec
     const bool strict = (p.plane_enabled & RARA_CLIP_STRICT_MISS) != 0;
     bool live = __ballot(thr < 1.0f) != 0ull;
 
-    for (uint32_t base = rg.x; base < rg.y; base += kUnitBatch) {
+    for (uint32_t base = rg.x; base < rg.y; base += kUB) {
         if (!__syncthreads_or(live ? 1 : 0)) break;   // also: the previous batch has been read
         const uint32_t idx = base + (uint32_t)tid;
         float2 sc = make_float2(0.0f, 0.0f);   // reaches no strip
-        if (tid < kUnitBatch && idx < rg.y) {
+        if (tid < kUB && idx < rg.y) {
             const uint32_t id = vals[idx];
             const Splat sp = splats[id];
             float4 sa, sb;
@@ -386,12 +390,15 @@ __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec
                 s_cut[tid].a = rr[0];
                 s_cut[tid].b = rr[1];
                 s_cut[tid].c = rr[2];
+                if (kRegion)
+                    for (int k = 0; k < p.plane_count - 1; ++k)
+                        s_ext[tid * (kMaxPlanes - 1) + k] = ray_ext[(int64_t)id * (kMaxPlanes - 1) + k];
             }
         }
-        if (tid < kBatchSlots) s_c[tid] = sc;
+        if (tid < slots_of<kRegion>()) s_c[tid] = sc;
         __syncthreads();
         if (!live) continue;
-        const uint32_t cnt = rg.y - base < (uint32_t)kUnitBatch ? rg.y - base : (uint32_t)kUnitBatch;
+        const uint32_t cnt = rg.y - base < (uint32_t)kUB ? rg.y - base : (uint32_t)kUB;
         const uint32_t kofs = base - rg.x + 1u;
         for (uint32_t sub = 0; sub < cnt && live; sub += 64) {
             const uint32_t lm = __float_as_uint(s_c[sub + lane].y);
@@ -420,7 +427,30 @@ __device__ inline void blend_unit(const Splat* __restrict__ splats, const RayRec
                 // alpha <= a0 (w <= 1): the weights are needed only when some live
                 // pixel's CUTOFF entry can reach its threshold
                 if (__ballot(valid && cut && a0 >= thr) != 0ull) {
-                    const float w = chord_weight_flat(s_cut[E], dx, dy, p.ax, p.ay, strict);
+                    float w;
+                    if (kRegion) {
+                        // the planes that do not hold the whole ellipsoid on their visible side
+                        const uint32_t cuts = (__float_as_uint(c2.y) >> 16) & 0xffu;
+                        if (!strict && __popc(cuts) == 1) {
+                            // one plane: eq. (11) with that plane's terms
+                            const int kp = __ffs(cuts) - 1;
+                            CutRec rec = s_cut[E];
+                            float pax = p.ax, pay = p.ay;
+                            if (kp > 0) {
+                                const float2 x = s_ext[E * (kMaxPlanes - 1) + kp - 1];
+                                rec.c.z = x.x;
+                                rec.c.w = x.y;
+                                pax = s_rate[kp - 1].x;
+                                pay = s_rate[kp - 1].y;
+                            }
+                            w = chord_weight_flat(rec, dx, dy, pax, pay, false);
+                        } else {
+                            w = chord_weight_region(s_cut[E], s_ext + E * (kMaxPlanes - 1), p.plane_count, dx, dy,
+                                                    p.ax, p.ay, s_rate, strict, strict ? 0xffu : cuts);
+                        }
+                    } else {
+                        w = chord_weight_flat(s_cut[E], dx, dy, p.ax, p.ay, strict);
+                    }
                     alpha = cut ? fminf(kAlphaMax, a0 * w) : alpha;
                     if (kWalked) evc += (valid && cut && thr < 1.0f) ? 1u : 0u;
                 }
@@ -471,11 +501,8 @@ __device__ __forceinline__ void blend_block(const Splat* __restrict__ splats, co
 {
     uint32_t tile;
     int quad = -1;
-    // clip regions: one workgroup per tile (tile_of_block); a single plane:
-    // long lists as quadrant units (unit_of_block)
-    if (kRegion ? !tile_of_block(block, work, p.num_tiles, tile)
-                : !unit_of_block(block, work, p.num_tiles, tile, quad))
-        return;
+    // long lists as quadrant units, the others one workgroup per tile
+    if (!unit_of_block(block, work, p.num_tiles, tile, quad)) return;
     if (tile >= (uint32_t)p.num_tiles) return;
     constexpr int kB = batch_of<kRegion>();
     __shared__ float4 s_a[kB], s_b[kB];
@@ -483,16 +510,16 @@ __device__ __forceinline__ void blend_block(const Splat* __restrict__ splats, co
     __shared__ CutRec s_cut[kB];
     __shared__ float2 s_ext[kRegion ? kB * (kMaxPlanes - 1) : 1];
     __shared__ float2 s_rate[kMaxPlanes - 1];
-    __shared__ uint8_t s_list[kRegion ? 1 : 4 * 64];
-    if (!kRegion && quad >= 0) {
-        static_assert(kUnitBatch <= kTileBatch, "the units reuse the tile path's LDS");
-        blend_unit<kWalked>(splats, rays, vals, ranges[tile], (int)tile, quad, p, s_a, s_b, s_c, s_cut, s_list,
-                            image, final_T, n_contrib, n_walked, n_eval);
-        return;
-    }
+    __shared__ uint8_t s_list[4 * 64];
     if (kRegion) {
         // the further planes' per-frame rates; the first batch's barrier orders them before any visit
         if (threadIdx.x < kMaxPlanes - 1) s_rate[threadIdx.x] = make_float2(p.xax[threadIdx.x], p.xay[threadIdx.x]);
+    }
+    if (quad >= 0) {
+        static_assert(kUnitBatch <= kTileBatch, "the units reuse the tile path's LDS");
+        blend_unit<kWalked, kRegion>(splats, rays, ray_ext, vals, ranges[tile], (int)tile, quad, p, s_a, s_b, s_c,
+                                     s_cut, s_ext, s_rate, s_list, image, final_T, n_contrib, n_walked, n_eval);
+        return;
     }
     blend_tile<kWalked, kRegion>(splats, rays, ray_ext, vals, ranges[tile], (int)tile, p, s_a, s_b, s_c, s_cut, s_ext,
                                  s_rate, image, final_T, n_contrib, n_walked, n_eval);
@@ -577,7 +604,7 @@ hipError_t launch_blend(const Splat* splat, const RayRec* ray, const float2* ray
     const uint2* ranges = reinterpret_cast<const uint2*>(bins.ranges);
     const bool count = n_walked || n_eval;
     if (p.plane_enabled && p.plane_count > 1) {
-        const unsigned grid = (unsigned)tiles_grid(p.num_tiles);
+        const unsigned grid = (unsigned)blend_grid(p.num_tiles);
         if (count)
             hipLaunchKernelGGL(blend_region_kernel<true>, dim3(grid), dim3(kBlendThreads), 0, s, splat, ray, ray_ext,
                                bins.vals, ranges, bins.work, bins.overflow, p, image, final_T, n_contrib, n_walked,

@@ -439,6 +439,18 @@ def test_long_list_clip_modes(name, mode):
                  scenes.Plane(DENSE_NORMAL, 0.02, enabled=mode), min_long=4)
 
 
+@pytest.mark.parametrize("name,mode", [("rara", oracle.CLIP_RARA)] + CLIP_MODES)
+def test_long_list_box_region(name, mode):
+    """Long lists cut by a box (six half-spaces): the quadrant units with the
+    region weight, the one-plane weight for entries that only one face cuts,
+    and the strict miss policy over the whole region."""
+    box = scenes.box_region((-0.25, -0.2, -0.3), (0.2, 0.25, 0.15), enabled=mode)
+    g, o = _dense_check(_dense_scene(1, 4000, 0.03, -2.3), scenes.small_camera(72), box, min_long=4)
+    if mode != oracle.CLIP_HARD:   # hard clipping has no CUTOFF label
+        assert (o["label"] == 2).sum() >= 100
+        _check_plane_mask(g, o, _dense_scene(1, 4000, 0.03, -2.3), box)
+
+
 @pytest.mark.parametrize("seed,size", [(1, 72), (2, 100)])
 def test_long_list_plain(seed, size):
     """Long lists without a plane: lists of 4096 entries or more still run

@@ -168,11 +168,12 @@ def count_evals(fr, n):
 
 def preprocess_bytes(n, sh_degree, live, drawn, cut_drawn):
     """Algorithmic HBM bytes of one preprocess launch: mean and scale (24 B),
-    the label (1 B) and tiles_touched (4 B) of every Gaussian; the quaternion
-    (16 B) of every Gaussian that is not INVISIBLE; opacity (4 B), SH
-    coefficients (12 (D+1)^2 B) and the splat record, depth and rectangle
-    (60 B) of every drawn one; the 48 B ray record of a drawn CUTOFF one."""
-    return 29 * n + 16 * live + (4 + 12 * (sh_degree + 1) ** 2 + 60) * drawn + 48 * cut_drawn
+    the label (1 B), tiles_touched (4 B) and the tile record (16 B: rectangle
+    and listed-tile mask) of every Gaussian; the quaternion (16 B) of every
+    Gaussian that is not INVISIBLE; opacity (4 B), SH coefficients
+    (12 (D+1)^2 B) and the splat record and depth (52 B) of every drawn one;
+    the 48 B ray record of a drawn CUTOFF one."""
+    return 45 * n + 16 * live + (4 + 12 * (sh_degree + 1) ** 2 + 52) * drawn + 48 * cut_drawn
 
 
 def bin_sort_bytes(n, drawn, pairs, tiles):
@@ -180,13 +181,13 @@ def bin_sort_bytes(n, drawn, pairs, tiles):
     reading and writing its keys and values once: the first depth pass reads
     depth and tile count of every Gaussian and writes 8 B per drawn one, three
     more depth passes move 16 B per drawn Gaussian, the chunk sums read each
-    drawn Gaussian's index and rectangle and write the rectangle in depth order
-    (20 B), the emit reads index and rectangle (12 B per drawn Gaussian) and
+    drawn Gaussian's index and 16 B tile record and write the record in depth
+    order (36 B), the emit reads index and record (20 B per drawn Gaussian) and
     writes 8 B per pair, the tile passes move 16 B per pair except the last,
     which writes only the values (12 B per pair), and the ranges and schedule
     take 12 B per tile."""
     tile_passes = max(1, (max(1, int(tiles - 1).bit_length()) + 7) // 8)
-    return (8 * n + 8 * drawn + 48 * drawn + 32 * drawn + 8 * pairs + 16 * pairs * (tile_passes - 1) + 12 * pairs
+    return (8 * n + 8 * drawn + 48 * drawn + 56 * drawn + 8 * pairs + 16 * pairs * (tile_passes - 1) + 12 * pairs
             + 12 * tiles)
 
 

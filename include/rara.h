@@ -154,8 +154,23 @@ typedef struct {
  *        whitened-space ray set-up of eq. (4) (12 floats; layout private to the
  *        library, consumed by rara_render / rara_render_backward).
  *   depth [n] float            camera depth of drawn Gaussians.
- *   rect  [n][4] uint16        tile rectangle tx0, ty0, tx1, ty1 (half-open).
- *   tiles_touched [n] uint32   (tx1-tx0)(ty1-ty0) if drawn, else 0.
+ *   tiles_touched [n] uint32   number of tiles the Gaussian is listed in (its
+ *                              pair count) if drawn, else 0.
+ *   tile_rec [n][2] uint64     per drawn Gaussian (zeros otherwise): word 0 its
+ *                              tile rectangle tx0, ty0, tx1, ty1 (half-open; four
+ *                              uint16, lowest first), word 1 the listed-tile mask: for a
+ *                              rectangle of at most 64 tiles, bit k set when the
+ *                              k-th tile of the rectangle (row by row) is
+ *                              listed; 0 for a larger rectangle.  16-byte
+ *                              aligned.  A tile is listed when the Gaussian can reach
+ *                              alpha >= 1/255 in it: the minimum of its quadratic
+ *                              form (float32 conic) over the box of the tile's
+ *                              pixel centres is at most 1.02 * 2 ln(255 delta)
+ *                              + 0.02 (none when 255 delta <= 1; all when the
+ *                              float32 conic is not positive definite).  A
+ *                              larger rectangle lists every tile.  Tiles left
+ *                              out hold no pixel the 1/255 skip of Sec. 3.1
+ *                              would not skip, so the frame is unchanged.
  *   ray_ext [n][RARA_MAX_PLANES-1][2] float   optional (NULL with a single
  *                              plane; required by a clip region): for drawn
  *                              CUTOFF Gaussians, the ray terms of the region's
@@ -167,9 +182,9 @@ typedef struct {
     void* splat;
     void* ray;
     float* depth;
-    uint16_t* rect;
     uint32_t* tiles_touched;
     float* ray_ext;
+    uint64_t* tile_rec;
 } rara_projected;
 
 /* Binned, depth-sorted (tile, Gaussian) pairs (caller-allocated).
@@ -184,8 +199,8 @@ typedef struct {
  *                                entry is the number of long-list tiles.
  *   pair_start [n] uint32        optional (NULL: not written): for each drawn
  *                                Gaussian, the position of its first pair in emission
- *                                order (drawn Gaussians by depth, each one's tiles
- *                                row by row over its rectangle); not written for
+ *                                order (drawn Gaussians by depth, each one's listed
+ *                                tiles row by row over its rectangle); not written for
  *                                Gaussians that are not drawn.  Required by
  *                                rara_render_backward, which gives every (tile,
  *                                Gaussian) pair its own gradient slot; a frame that
@@ -344,7 +359,7 @@ rara_status rara_render_backward(const rara_gaussians* g, const rara_camera* cam
  * previous call's contents do no harm.
  * Errors: those of rara_bin_sort, and RARA_ERR_SCRATCH (before anything is
  * enqueued) when rara_workspace_bytes(RARA_WS_BIN_SORT, n, pair_capacity, W, H)
- * exceeds RARA_STATIC_WS_BYTES (it does not for 1M Gaussians and 5.6M pairs
+ * exceeds RARA_STATIC_WS_BYTES (it does not for 1M Gaussians and 5M pairs
  * of capacity); RARA_ERR_HIP when the array's address cannot be found. */
 #define RARA_STATIC_WS_BYTES ((size_t)64 << 20)
 rara_status rara_bin_sort_static(const rara_projected* proj, int64_t n, const rara_camera* cam,

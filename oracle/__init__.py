@@ -48,13 +48,15 @@ def lib():
         L.oracle_classify.argtypes = [_I64, _P, _P, _P, _P, _I32, _I32, _P, _P, _P]
         L.oracle_classify.restype = _I32
         L.oracle_project.argtypes = [_I64, _I32, _P, _P, _P, _P, _P, _I32, _I32, _D, _P, _I32,
-                                     _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+                                     _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I32, _P, _P]
         L.oracle_project.restype = None
         L.oracle_weight.argtypes = [_P, _P, _P, _P, _P, _D, _D, _I32, _P]
         L.oracle_weight.restype = _D
         L.oracle_weight_region.argtypes = [_P, _P, _P, _P, _P, _P, _I32, _D, _I32, _P]
         L.oracle_weight_region.restype = _D
-        L.oracle_lists.argtypes = [_I64, _P, _P, _P, _I32, _I32, _P, _P]
+        L.oracle_lists.argtypes = [_I64, _P, _P, _P, _P, _I32, _I32, _P, _P]
+        L.oracle_box_min.argtypes = [_D, _D, _D, _D, _D, _D, _D]
+        L.oracle_box_min.restype = _D
         L.oracle_lists.restype = _I64
         L.oracle_composite.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _I32, _I32, _P, _I32, _I32, _P,
                                        _P, _P, _D, _I32, _I64, _I64, _D, _P, _P, _P, _P, _P, _P]
@@ -119,19 +121,23 @@ def classify(scene, plane):
     return label, dep, rad
 
 
-def project(scene, cam, label, project_all: bool = False) -> dict:
-    """EWA projection, footprint, tile rectangle and colour per Gaussian."""
+def project(scene, cam, label, project_all: bool = False, cull: bool = True) -> dict:
+    """EWA projection, footprint, tile rectangle, listed tiles and colour per
+    Gaussian.  ``tmask`` bit k: the k-th tile of a rectangle of at most 64
+    tiles (row by row) is listed; ``tiles_touched`` counts the listed tiles.
+    ``cull=False`` lists every tile of the rectangle (the paper's binning)."""
     n = scene.n
     out = dict(
         drawn=np.zeros(n, np.uint8), mean2d=np.zeros((n, 2)), cov2d=np.zeros((n, 3)), conic=np.zeros((n, 3)),
         depth=np.zeros(n), depth32=np.zeros(n, np.float32), radius=np.zeros(n, np.int32),
         rect=np.zeros((n, 4), np.int32), tiles_touched=np.zeros(n, np.int32), rgb=np.zeros((n, 3)),
-        minv=np.zeros((n, 9)), lam_max=np.zeros(n))
+        minv=np.zeros((n, 9)), lam_max=np.zeros(n), tmask=np.zeros(n, np.uint64), cull_margin=np.zeros(n))
     lib().oracle_project(n, scene.sh_degree, _p(scene.mean), _p(scene.scale), _p(scene.quat), _p(scene.sh),
                          _p(cam_array(cam)), cam.width, cam.height, float(cam.near), _p(label), int(project_all),
                          _p(out["drawn"]), _p(out["mean2d"]), _p(out["cov2d"]), _p(out["conic"]), _p(out["depth"]),
                          _p(out["depth32"]), _p(out["radius"]), _p(out["rect"]), _p(out["tiles_touched"]),
-                         _p(out["rgb"]), _p(out["minv"]), _p(out["lam_max"]))
+                         _p(out["rgb"]), _p(out["minv"]), _p(out["lam_max"]), _p(scene.opacity), int(cull),
+                         _p(out["tmask"]), _p(out["cull_margin"]))
     return out
 
 
@@ -142,7 +148,7 @@ def tile_lists(proj: dict, cam):
     offsets = np.zeros(tx * ty + 1, np.int64)
     P = int(proj["tiles_touched"].astype(np.int64).sum())
     ids = np.zeros(max(P, 1), np.int32)
-    got = lib().oracle_lists(n, _p(proj["drawn"]), _p(proj["rect"]), _p(proj["depth32"]), tx, ty,
+    got = lib().oracle_lists(n, _p(proj["drawn"]), _p(proj["rect"]), _p(proj["tmask"]), _p(proj["depth32"]), tx, ty,
                              _p(offsets), _p(ids))
     assert got == P
     return offsets, ids[:P]
@@ -208,13 +214,18 @@ def weight_region(e, v, mu, quat, scale, planes, kappa: float = KAPPA, strict_mi
 
 # ------------------------------------------------------------ full render ----
 
+def box_min(A: float, B: float, C: float, x0: float, x1: float, y0: float, y1: float) -> float:
+    """Minimum of A x^2 + 2 B x y + C y^2 over the box [x0, x1] x [y0, y1]."""
+    return lib().oracle_box_min(A, B, C, x0, x1, y0, y1)
+
+
 def render(scene, cam, plane, bg=(0.0, 0.0, 0.0), kappa: float = KAPPA, trace_visible: bool = False,
-           tiles=None, tau_sil: float = 1e-3, events: bool = True) -> dict:
+           tiles=None, tau_sil: float = 1e-3, events: bool = True, cull: bool = True) -> dict:
     """Full oracle frame.  ``tiles`` = (first, last) row-major tile range to
     composite (default: all).  Returns labels, projection, lists, image
     [3][H][W], final_T, n_contrib, n_walked, per-pixel event flags and counters."""
     label, dep, rad = classify(scene, plane)
-    proj = project(scene, cam, label)
+    proj = project(scene, cam, label, cull=cull)
     offsets, ids = tile_lists(proj, cam)
     W, H = cam.width, cam.height
     T = (W + TILE - 1) // TILE * ((H + TILE - 1) // TILE)
@@ -241,9 +252,9 @@ def render(scene, cam, plane, bg=(0.0, 0.0, 0.0), kappa: float = KAPPA, trace_vi
 
 
 def boundary_events(scene, cam, plane, label, dep, rad, tol: float = 1e-6) -> dict:
-    """Gaussians within ``tol`` of a label, footprint or near-plane boundary
-    (where a float rounding difference may legitimately flip the decision),
-    with their tile rectangles."""
+    """Gaussians within ``tol`` of a label, footprint, listed-tile or
+    near-plane boundary (where a float rounding difference may legitimately
+    flip the decision), with their tile rectangles."""
     n = scene.n
     lab_b = np.zeros(n, bool)
     mode = clip_mode(plane)
@@ -263,9 +274,11 @@ def boundary_events(scene, cam, plane, label, dep, rad, tol: float = 1e-6) -> di
     rect_b = valid & (near_int(r3) | near_int(allp["mean2d"][:, 0] - rr) | near_int(allp["mean2d"][:, 0] + rr)
                       | near_int(allp["mean2d"][:, 1] - rr) | near_int(allp["mean2d"][:, 1] + rr))
     near_b = np.abs(allp["depth"] - cam.near) <= tol
-    ids = np.nonzero(lab_b | rect_b | near_b)[0]
+    cull_b = allp["cull_margin"] <= tol
+    ids = np.nonzero(lab_b | rect_b | near_b | cull_b)[0]
     return dict(n_label_boundary=int(lab_b.sum()), n_rect_boundary=int(rect_b.sum()),
-                n_near_boundary=int(near_b.sum()), boundary_ids=ids, boundary_rects=allp["rect"][ids])
+                n_near_boundary=int(near_b.sum()), n_cull_boundary=int(cull_b.sum()), boundary_ids=ids,
+                boundary_rects=allp["rect"][ids])
 
 
 def tile_mask(cam, rects) -> np.ndarray:

@@ -23,7 +23,8 @@
  *   oracle_weight_region - the same weight for a clip region that is the
  *                      intersection of several half-spaces (a box is six): the
  *                      extension to other clipping primitives of Sec. 6.
- *   oracle_lists     - depth-sorted per-tile lists (Sec. 3.1, "sorted by depth").
+ *   oracle_lists     - depth-sorted per-tile lists (Sec. 3.1, "sorted by depth"),
+ *                      over the tiles that oracle_project keeps (below).
  *   oracle_composite - Sec. 3.1 eq. (2) front-to-back compositing with the
  *                      opacity of eq. (12) and the 0.99 clamp of step 3 of
  *                      Algorithm 1.
@@ -48,7 +49,15 @@
  *     splatting convention), skip when alpha < 1/255, stop before a Gaussian
  *     that would take transmittance below 1e-4, dilation 0.3 px^2,
  *     footprint radius ceil(3 sqrt(lambda_max)), near plane 0.2, guard band
- *     1.3 in the Jacobian, pixel centres at integer image coordinates.
+ *     1.3 in the Jacobian, pixel centres at integer image coordinates;
+ *   - a tile of the footprint's rectangle is listed only when the Gaussian can
+ *     reach alpha >= 1/255 in it (the paper lists the whole rectangle; a tile
+ *     left out holds no pixel the 1/255 skip would not skip, so the image is
+ *     the same): for rectangles of at most 64 tiles, the minimum of the
+ *     quadratic form over the box of the tile's pixel centres must not exceed
+ *     1.02 * 2 ln(255 delta) + 0.02 (a margin over the float32 evaluation of
+ *     alpha), with the conic rounded to float32 as the renderer holds it;
+ *     larger rectangles keep every tile.
  */
 #include <math.h>
 #include <stdint.h>
@@ -196,6 +205,38 @@ static void camera_centre(const double* R, const double* t, double* e)
 }
 
 /*
+ * Minimum over the box [x0, x1] x [y0, y1] (coordinates relative to the
+ * projected centre) of q(x, y) = A x^2 + 2 B x y + C y^2, for a positive
+ * definite form: zero when the box holds the centre; otherwise the minimum of
+ * a convex function over a box lies on its boundary, and along each edge q is
+ * a parabola whose minimum is its stationary point (-B X / C on the edge
+ * x = X, -B Y / A on the edge y = Y, taken with the reciprocals 1/C and 1/A)
+ * clamped to the edge.
+ */
+double oracle_box_min(double A, double B, double C, double x0, double x1, double y0, double y1)
+{
+    if (x0 <= 0.0 && x1 >= 0.0 && y0 <= 0.0 && y1 >= 0.0) return 0.0;
+    double iA = 1.0 / A, iC = 1.0 / C;
+    double best = INFINITY;
+    double xs[2] = {x0, x1}, ys[2] = {y0, y1};
+    for (int k = 0; k < 2; k++) {
+        double X = xs[k];
+        double y = -B * X * iC;
+        y = y < y0 ? y0 : (y > y1 ? y1 : y);
+        double q = A * X * X + 2.0 * B * X * y + C * y * y;
+        if (q < best) best = q;
+        double Y = ys[k];
+        double x = -B * Y * iA;
+        x = x < x0 ? x0 : (x > x1 ? x1 : x);
+        q = A * x * x + 2.0 * B * x * Y + C * Y * Y;
+        if (q < best) best = q;
+    }
+    return best;
+}
+
+#define OR_CULL_MAX_TILES 64
+
+/*
  * EWA projection and splat set-up for every Gaussian with label != INVISIBLE
  * (or every Gaussian when project_all is set, used to find boundary cases).
  *   t = R_c mu + t_c; not drawn when t_z <= near.
@@ -208,13 +249,19 @@ static void camera_centre(const double* R, const double* t, double* e)
  *   tiles that contain a pixel of the box (half-open tile rectangle).
  *   colour = max(0, sum_lm Y_lm(dir) sh_lm + 0.5), dir = (mu - e)/|mu - e|.
  *   minv = M^-1 = S^-1 R^T (Sec. 3.3, M = R S), row-major.
+ *   listed tiles: with cull set, a rectangle of at most 64 tiles keeps the
+ *   tiles whose pixel-centre box the Gaussian reaches (see the readings
+ *   above), in tmask (bit k = the k-th tile of the rectangle, row by row);
+ *   tiles_touched counts the listed tiles.  cull_margin is the smallest
+ *   |q_min - threshold| over the tested tiles (infinity when none was tested).
  * Outputs are per Gaussian; rect = (tx0, ty0, tx1, ty1).
  */
 void oracle_project(int64_t n, int sh_degree, const float* mean, const float* scale, const float* quat,
                     const float* sh, const float* cam, int W, int H, double near_z, const uint8_t* label,
                     int project_all, uint8_t* drawn, double* mean2d, double* cov2d, double* conic,
                     double* depth, float* depth32, int32_t* radius, int32_t* rect, int32_t* tiles_touched,
-                    double* rgb, double* minv, double* lam_max)
+                    double* rgb, double* minv, double* lam_max, const float* opacity, int cull,
+                    uint64_t* tmask, double* cull_margin)
 {
     double Rc[9], tc[3], e[3];
     for (int k = 0; k < 9; k++) Rc[k] = cam[k];
@@ -230,6 +277,8 @@ void oracle_project(int64_t n, int sh_degree, const float* mean, const float* sc
     for (int64_t i = 0; i < n; i++) {
         drawn[i] = 0;
         tiles_touched[i] = 0;
+        tmask[i] = 0;
+        cull_margin[i] = INFINITY;
         rect[4 * i + 0] = rect[4 * i + 1] = rect[4 * i + 2] = rect[4 * i + 3] = 0;
         radius[i] = 0;
         double mu[3] = {mean[i], mean[n + i], mean[2 * n + i]};
@@ -291,6 +340,35 @@ void oracle_project(int64_t n, int sh_degree, const float* mean, const float* sc
         rect[4 * i] = tx0; rect[4 * i + 1] = ty0; rect[4 * i + 2] = tx1; rect[4 * i + 3] = ty1;
         tiles_touched[i] = (tx1 - tx0) * (ty1 - ty0);
         drawn[i] = 1;
+        if (tiles_touched[i] <= OR_CULL_MAX_TILES) {
+            /* the tiles of the rectangle that the Gaussian reaches (bit k: the
+             * k-th tile of the rectangle, row by row) */
+            int w = tx1 - tx0, area = tiles_touched[i];
+            uint64_t m = 0;
+            double A = (double)(float)conic[3 * i], B = (double)(float)conic[3 * i + 1];
+            double C = (double)(float)conic[3 * i + 2];
+            double s255 = 255.0 * (double)opacity[i];
+            if (!cull) {
+                m = area == 64 ? ~(uint64_t)0 : (((uint64_t)1 << area) - 1);
+            } else if (s255 > 1.0) {
+                if (!(A * C - B * B > 0.0)) {
+                    m = area == 64 ? ~(uint64_t)0 : (((uint64_t)1 << area) - 1);
+                } else {
+                    double tq = 2.0 * log(s255) * 1.02 + 0.02;
+                    for (int k = 0; k < area; k++) {
+                        int tx = tx0 + k % w, ty = ty0 + k / w;
+                        double bx1 = fmin((double)(tx * OR_TILE + OR_TILE - 1), (double)(W - 1));
+                        double by1 = fmin((double)(ty * OR_TILE + OR_TILE - 1), (double)(H - 1));
+                        double q = oracle_box_min(A, B, C, tx * OR_TILE - mx, bx1 - mx, ty * OR_TILE - my, by1 - my);
+                        double mg = fabs(q - tq);
+                        if (mg < cull_margin[i]) cull_margin[i] = mg;
+                        if (q <= tq) m |= (uint64_t)1 << k;
+                    }
+                }
+            }
+            tmask[i] = m;
+            tiles_touched[i] = __builtin_popcountll(m);
+        }
 
         /* colour from spherical harmonics in the viewing direction */
         double dir[3] = {mu[0] - e[0], mu[1] - e[1], mu[2] - e[2]};
@@ -438,9 +516,18 @@ double oracle_weight_region(const double* e, const double* v, const double* mu, 
 }
 
 /*
- * Per-tile lists: ids of drawn Gaussians whose tile rectangle contains the
- * tile, ordered by (float32 depth, index).  offsets has tiles+1 entries.
+ * Per-tile lists: ids of drawn Gaussians that list the tile (a tile of the
+ * rectangle, kept by tmask when the rectangle has at most 64 tiles), ordered
+ * by (float32 depth, index).  offsets has tiles+1 entries.
  */
+static int or_lists_tile(const int32_t* rect, const uint64_t* tmask, int64_t i, int tx, int ty)
+{
+    int w = rect[4 * i + 2] - rect[4 * i], h = rect[4 * i + 3] - rect[4 * i + 1];
+    if (w * h > OR_CULL_MAX_TILES) return 1;
+    int k = (ty - rect[4 * i + 1]) * w + (tx - rect[4 * i]);
+    return (int)((tmask[i] >> k) & 1u);
+}
+
 typedef struct { float key; int32_t id; } or_entry;
 static int cmp_entry(const void* a, const void* b)
 {
@@ -451,15 +538,16 @@ static int cmp_entry(const void* a, const void* b)
     return (x->id > y->id) - (x->id < y->id);
 }
 
-int64_t oracle_lists(int64_t n, const uint8_t* drawn, const int32_t* rect, const float* depth32, int tiles_x,
-                     int tiles_y, int64_t* offsets, int32_t* ids)
+int64_t oracle_lists(int64_t n, const uint8_t* drawn, const int32_t* rect, const uint64_t* tmask,
+                     const float* depth32, int tiles_x, int tiles_y, int64_t* offsets, int32_t* ids)
 {
     int64_t T = (int64_t)tiles_x * tiles_y;
     int64_t* count = (int64_t*)calloc((size_t)T, sizeof(int64_t));
     for (int64_t i = 0; i < n; i++) {
         if (!drawn[i]) continue;
         for (int ty = rect[4 * i + 1]; ty < rect[4 * i + 3]; ty++)
-            for (int tx = rect[4 * i]; tx < rect[4 * i + 2]; tx++) count[(int64_t)ty * tiles_x + tx]++;
+            for (int tx = rect[4 * i]; tx < rect[4 * i + 2]; tx++)
+                if (or_lists_tile(rect, tmask, i, tx, ty)) count[(int64_t)ty * tiles_x + tx]++;
     }
     offsets[0] = 0;
     for (int64_t t = 0; t < T; t++) offsets[t + 1] = offsets[t] + count[t];
@@ -470,6 +558,7 @@ int64_t oracle_lists(int64_t n, const uint8_t* drawn, const int32_t* rect, const
             if (!drawn[i]) continue;
             for (int ty = rect[4 * i + 1]; ty < rect[4 * i + 3]; ty++)
                 for (int tx = rect[4 * i]; tx < rect[4 * i + 2]; tx++) {
+                    if (!or_lists_tile(rect, tmask, i, tx, ty)) continue;
                     int64_t t = (int64_t)ty * tiles_x + tx;
                     ids[offsets[t] + count[t]++] = (int32_t)i;
                 }

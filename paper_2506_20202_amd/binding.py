@@ -47,8 +47,8 @@ class Plane(ctypes.Structure):
 
 
 class Projected(ctypes.Structure):
-    _fields_ = [("label", _P), ("splat", _P), ("ray", _P), ("depth", _P), ("rect", _P), ("tiles_touched", _P),
-                ("ray_ext", _P)]
+    _fields_ = [("label", _P), ("splat", _P), ("ray", _P), ("depth", _P), ("tiles_touched", _P), ("ray_ext", _P),
+                ("tile_rec", _P)]
 
 
 class Binned(ctypes.Structure):

@@ -81,14 +81,15 @@ int ceil_log2(int64_t v)
 
 bool proj_ok(const rara_projected* p)
 {
-    return p && p->label && p->splat && p->ray && p->depth && p->rect && p->tiles_touched;
+    return p && p->label && p->splat && p->ray && p->depth && p->tiles_touched && p->tile_rec &&
+           (reinterpret_cast<uintptr_t>(p->tile_rec) & 15u) == 0;
 }
 
 ProjPtrs proj_ptrs(const rara_projected* p)
 {
     return ProjPtrs{p->label, static_cast<Splat*>(p->splat), static_cast<RayRec*>(p->ray),
-                    reinterpret_cast<float2*>(p->ray_ext), p->depth, p->rect,
-                    p->tiles_touched};
+                    reinterpret_cast<float2*>(p->ray_ext), p->depth,
+                    p->tiles_touched, reinterpret_cast<ulonglong2*>(p->tile_rec)};
 }
 
 constexpr int kMaxDevices = 64;
@@ -196,7 +197,9 @@ size_t rara::bin_workspace_layout(int64_t n, int64_t cap, BinWorkspace* ws, char
         w.dvals[b] = reinterpret_cast<uint32_t*>(base + off);
         off += align((size_t)nn * 4);
     }
-    w.drect = reinterpret_cast<ushort4*>(w.dkeys[1]);   // 8 B per Gaussian over dkeys[1] and dvals[1]
+    // 16 B per Gaussian over dkeys[1], dvals[1] and 8 B more per Gaussian after them
+    w.drec = reinterpret_cast<ulonglong2*>(w.dkeys[1]);
+    off += align((size_t)nn * 8);
     w.tkeys = reinterpret_cast<uint32_t*>(base + off);
     off += align((size_t)cap * 4);
     w.tvals = reinterpret_cast<uint32_t*>(base + off);

@@ -210,11 +210,16 @@ __device__ inline void chord_backward(const CutRec& k, const Chord& c, float dx,
 constexpr int kBackBatch = 128;   // entries staged per batch (threads 0..127 stage)
 
 // Gradient slot of the pair (tile (tx, ty), Gaussian id): its position in
-// emission order, the Gaussian's first pair plus the tile's index in the
-// Gaussian's rectangle, row by row.
-__device__ inline uint32_t pair_slot(uint32_t first, ushort4 rc, int tx, int ty)
+// emission order, the Gaussian's first pair plus the number of its listed
+// tiles before this one, row by row over its rectangle.
+__device__ inline uint32_t pair_slot(uint32_t first, const ulonglong2& rec, int tx, int ty)
 {
-    return first + (uint32_t)(ty - rc.y) * (uint32_t)(rc.z - rc.x) + (uint32_t)(tx - rc.x);
+    // the record's rectangle: tx0, ty0, tx1, ty1 as uint16, lowest first
+    const int x0 = (int)(rec.x & 0xffffu), y0 = (int)((rec.x >> 16) & 0xffffu);
+    const int x1 = (int)((rec.x >> 32) & 0xffffu), y1 = (int)(rec.x >> 48);
+    const uint32_t w = (uint32_t)(x1 - x0);
+    const uint32_t k = (uint32_t)(ty - y0) * w + (uint32_t)(tx - x0);
+    return first + listed_rank(rec.y, (int)w * (y1 - y0), k);
 }
 
 // One tile, back to front.  Thread t of wave w = t / 64 owns pixel
@@ -227,7 +232,8 @@ __device__ inline uint32_t pair_slot(uint32_t first, ushort4 rc, int tx, int ty)
 // Entries past the largest n_contrib get zero slots.
 __device__ inline void blend_back_tile(const Splat* __restrict__ splats, const RayRec* __restrict__ rays,
                                        const uint32_t* __restrict__ vals, const uint32_t* __restrict__ pair_start,
-                                       const uint16_t* __restrict__ rect, const uint2 rg, int tile,
+                                       const ulonglong2* __restrict__ tile_rec,
+                                       const uint2 rg, int tile,
                                        const BackParams& bp, const float* __restrict__ final_T,
                                        const uint32_t* __restrict__ n_contrib, const float* __restrict__ dL_dimage,
                                        float* __restrict__ slots, float* __restrict__ plane_acc, float4* s_a,
@@ -288,8 +294,7 @@ __device__ inline void blend_back_tile(const Splat* __restrict__ splats, const R
                     s_cut[tid].b = r1;
                     s_cut[tid].c = r2;
                 }
-                const ushort4 rc = *reinterpret_cast<const ushort4*>(rect + 4 * (int64_t)id);
-                s_slot[tid] = pair_slot(pair_start[id], rc, tx, ty);
+                s_slot[tid] = pair_slot(pair_start[id], tile_rec[id], tx, ty);
             }
             s_c[tid] = sc;
         }
@@ -391,8 +396,7 @@ __device__ inline void blend_back_tile(const Splat* __restrict__ splats, const R
     // entries after the last composited one: zero slots
     for (uint32_t k = rg.x + kmax + (uint32_t)tid; k < rg.y; k += blockDim.x) {
         const uint32_t id = vals[k];
-        const ushort4 rc = *reinterpret_cast<const ushort4*>(rect + 4 * (int64_t)id);
-        float* dst = slots + (int64_t)pair_slot(pair_start[id], rc, tx, ty) * kAccRows;
+        float* dst = slots + (int64_t)pair_slot(pair_start[id], tile_rec[id], tx, ty) * kAccRows;
         for (int r = 0; r < kAccRows; ++r) dst[r] = 0.0f;
     }
     const float sx = wave_sum(pax), sy = wave_sum(pay);
@@ -405,7 +409,8 @@ __device__ inline void blend_back_tile(const Splat* __restrict__ splats, const R
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void blend_backward_kernel(
     const Splat* __restrict__ splats, const RayRec* __restrict__ rays, const uint32_t* __restrict__ vals,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ work, const uint32_t* __restrict__ pair_start,
-    const uint16_t* __restrict__ rect, const int32_t* __restrict__ overflow, BackParams bp,
+    const ulonglong2* __restrict__ tile_rec, const int32_t* __restrict__ overflow,
+    BackParams bp,
     const float* __restrict__ final_T, const uint32_t* __restrict__ n_contrib, const float* __restrict__ dL_dimage,
     float* __restrict__ slots, float* __restrict__ plane_acc)
 {
@@ -418,8 +423,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void b
     __shared__ uint32_t s_slot[kBackBatch];
     __shared__ float s_g[kBackBatch][kAccRows];
     __shared__ uint32_t s_red[4];
-    blend_back_tile(splats, rays, vals, pair_start, rect, ranges[tile], (int)tile, bp, final_T, n_contrib, dL_dimage,
-                    slots, plane_acc, s_a, s_b, s_c, s_cut, s_slot, s_g, s_red);
+    blend_back_tile(splats, rays, vals, pair_start, tile_rec, ranges[tile], (int)tile, bp, final_T, n_contrib,
+                    dL_dimage, slots, plane_acc, s_a, s_b, s_c, s_cut, s_slot, s_g, s_red);
 }
 
 __global__ __launch_bounds__(256) void fill_zero_kernel(float* __restrict__ p, int64_t count)
@@ -892,8 +897,8 @@ hipError_t launch_backward(const GaussPtrs& g, const CamParams& cam, const Plane
     if (g.n > 0)
         hipLaunchKernelGGL(blend_backward_kernel, dim3((unsigned)tiles_grid(rp.num_tiles)), dim3(256), 0, s,
                            proj.splat, proj.ray, bins.vals, reinterpret_cast<const uint2*>(bins.ranges), bins.work,
-                           bins.pair_start, proj.rect, bins.overflow, bp, final_T, n_contrib, dL_dimage, slots,
-                           plane_acc);
+                           bins.pair_start, proj.tile_rec, bins.overflow, bp, final_T, n_contrib,
+                           dL_dimage, slots, plane_acc);
     if (g.n > 0) {
         const dim3 grid((unsigned)((g.n + 255) / 256));
         hipLaunchKernelGGL(slot_sum_kernel, grid, dim3(256), 0, s, g.n, pl.enabled, proj.label, proj.tiles_touched,

@@ -66,16 +66,26 @@ __device__ inline uint32_t block_ballot_scan(uint32_t v, uint32_t& total)
     return before + p;
 }
 
+// Rectangle (tx0, ty0, tx1, ty1) and area of a tile record.
+__device__ inline ushort4 record_rect(const ulonglong2& r)
+{
+    return make_ushort4((unsigned short)r.x, (unsigned short)(r.x >> 16), (unsigned short)(r.x >> 32),
+                        (unsigned short)(r.x >> 48));
+}
+
+__device__ inline int rect_area(const ushort4& rc) { return (int)(rc.z - rc.x) * (int)(rc.w - rc.y); }
+
 // Per-chunk sums of the tile counts over the depth order (k < *count), chunk
 // b = the 256 Gaussians from b * 256; also gathers each drawn Gaussian's tile
-// rectangle into depth order (drect[k] = rect[order[k]]), so that the emit
-// reads rectangles in sequence instead of gathering them again.  The count is
-// the rectangle's area (tiles_touched of a drawn Gaussian).
-__global__ __launch_bounds__(256) void chunk_sum_kernel(const uint16_t* __restrict__ rect,
+// record (rectangle and listed-tile mask) into depth order (drec[k] =
+// tile_rec[order[k]]), so that the emit reads them in sequence instead of
+// gathering them again.  The count is the number of listed tiles
+// (tiles_touched of a drawn Gaussian).
+__global__ __launch_bounds__(256) void chunk_sum_kernel(const ulonglong2* __restrict__ tile_rec,
                                                         const uint32_t* __restrict__ order,
                                                         const int64_t* __restrict__ count,
                                                         uint32_t* __restrict__ chunk_sums,
-                                                        ushort4* __restrict__ drect)
+                                                        ulonglong2* __restrict__ drec)
 {
     const int64_t drawn = *count;
     if ((int64_t)blockIdx.x * kScanBlock >= drawn) {   // past the drawn Gaussians: uniform
@@ -85,9 +95,9 @@ __global__ __launch_bounds__(256) void chunk_sum_kernel(const uint16_t* __restri
     const int64_t k = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
     uint32_t v = 0u;
     if (k < drawn) {
-        const ushort4 rc = *reinterpret_cast<const ushort4*>(rect + 4 * (int64_t)order[k]);
-        drect[k] = rc;
-        v = (uint32_t)(rc.z - rc.x) * (uint32_t)(rc.w - rc.y);
+        const ulonglong2 r = tile_rec[order[k]];
+        drec[k] = r;
+        v = listed_count(r.y, rect_area(record_rect(r)));
     }
     uint32_t total;
     block_ballot_scan(v, total);
@@ -101,7 +111,7 @@ __global__ void no_pairs_kernel(int64_t* __restrict__ num_pairs, int32_t* __rest
     *overflow = 0;
 }
 
-// One (tile, index) pair per covered tile, Gaussians taken in depth order.
+// One (tile, index) pair per listed tile, Gaussians taken in depth order.
 // A workgroup owns 256 consecutive Gaussians of the depth order (chunk b) and
 // the contiguous run of pairs they emit, from the sum of the chunk sums before
 // it; the last workgroup also writes the pair count and the overflow flag.  A
@@ -110,7 +120,7 @@ __global__ void no_pairs_kernel(int64_t* __restrict__ num_pairs, int32_t* __rest
 // 256-pair step finds the Gaussian that owns pair e by a binary search over
 // the workgroup's inclusive pair offsets in LDS, so the work per thread does
 // not depend on footprint sizes and the stores of a step are consecutive.
-__global__ __launch_bounds__(256) void emit_kernel(const ushort4* __restrict__ drect,
+__global__ __launch_bounds__(256) void emit_kernel(const ulonglong2* __restrict__ drec,
                                                    const uint32_t* __restrict__ order,
                                                    const int64_t* __restrict__ count,
                                                    const uint32_t* __restrict__ chunk_sums, int64_t cap,
@@ -121,6 +131,7 @@ __global__ __launch_bounds__(256) void emit_kernel(const ushort4* __restrict__ d
     __shared__ uint32_t s_end[kScanBlock];   // inclusive end of each Gaussian's pairs inside the workgroup
     __shared__ uint32_t s_id[kScanBlock];
     __shared__ ushort4 s_rc[kScanBlock];
+    __shared__ uint64_t s_mk[kScanBlock];
     __shared__ uint64_t s_part[kScanBlock / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t b = blockIdx.x;
@@ -146,8 +157,10 @@ __global__ __launch_bounds__(256) void emit_kernel(const ushort4* __restrict__ d
     const int64_t k = b * kScanBlock + tid;
     const bool valid = k < drawn;
     const uint32_t id = valid ? order[k] : 0u;
-    const ushort4 rk = valid ? drect[k] : make_ushort4(0, 0, 1, 1);
-    const uint32_t v = valid ? (uint32_t)(rk.z - rk.x) * (uint32_t)(rk.w - rk.y) : 0u;
+    const ulonglong2 rec = valid ? drec[k] : make_ulonglong2(0ull, 0ull);
+    const ushort4 rk = valid ? record_rect(rec) : make_ushort4(0, 0, 1, 1);
+    const uint64_t mk = rec.y;
+    const uint32_t v = valid ? listed_count(mk, rect_area(rk)) : 0u;
     if (lane == 0) s_part[wave] = before;
     uint32_t total;
     const uint32_t pre = block_ballot_scan(v, total);   // its barrier orders s_part
@@ -163,6 +176,7 @@ __global__ __launch_bounds__(256) void emit_kernel(const ushort4* __restrict__ d
     s_end[tid] = pre + v;
     s_id[tid] = id;
     s_rc[tid] = v ? rk : make_ushort4(0, 0, 1, 1);
+    s_mk[tid] = mk;
     __syncthreads();
     for (uint32_t e = (uint32_t)tid; e < total; e += kScanBlock) {
         // owner = number of Gaussians whose pairs all precede e (s_end is non-decreasing, s_end[255] = total)
@@ -173,7 +187,8 @@ __global__ __launch_bounds__(256) void emit_kernel(const ushort4* __restrict__ d
         const uint32_t li = e - (own ? s_end[own - 1] : 0u);
         const ushort4 rc = s_rc[own];
         const uint32_t w = (uint32_t)(rc.z - rc.x);
-        const uint32_t row = li / w, col = li - row * w;
+        const uint32_t pos = listed_tile(s_mk[own], (int)w * (int)(rc.w - rc.y), li);   // in the rectangle
+        const uint32_t row = pos / w, col = pos - row * w;
         tkeys[base + e] = (uint32_t)((rc.y + row) * (uint32_t)tiles_x + rc.x + col);
         tvals[base + e] = s_id[own];
     }
@@ -378,8 +393,8 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
                                    nullptr, ws.depth_blocks, ws.hist, ws.digit_totals, nullptr, nullptr, nullptr,
                                    &first, nullptr, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.rect, ws.dvals[0],
-                           ws.dcount, ws.block_sums, ws.drect);
+        hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)nb), dim3(256), 0, s, proj.tile_rec, ws.dvals[0],
+                           ws.dcount, ws.block_sums, ws.drec);
     } else {
         hipLaunchKernelGGL(no_pairs_kernel, dim3(1), dim3(1), 0, s, out.num_pairs, out.overflow);
     }
@@ -394,7 +409,7 @@ hipError_t launch_bin(const ProjPtrs& proj, int64_t n, const CamParams& cam, int
     uint32_t* vb = last_reads_a ? alias_v : ws.tvals;
     // 3. pair offsets in depth order, pair count, overflow flag, emission
     if (n > 0)
-        hipLaunchKernelGGL(emit_kernel, dim3((unsigned)nb), dim3(256), 0, s, ws.drect, ws.dvals[0],
+        hipLaunchKernelGGL(emit_kernel, dim3((unsigned)nb), dim3(256), 0, s, ws.drec, ws.dvals[0],
                            ws.dcount, ws.block_sums, cap, cam.tiles_x, out.num_pairs, out.overflow, ka, va,
                            out.pair_start);
     // 4. tile digits; the last pass writes the 64-bit keys and the values, and

@@ -45,7 +45,8 @@ void destroy(rara_frame_graph* fg)
 
 bool proj_complete(const rara_projected* p)
 {
-    return p->label && p->splat && p->ray && p->depth && p->rect && p->tiles_touched;
+    return p->label && p->splat && p->ray && p->depth && p->tiles_touched && p->tile_rec &&
+           (reinterpret_cast<uintptr_t>(p->tile_rec) & 15u) == 0;
 }
 
 }  // namespace
@@ -82,7 +83,7 @@ rara_status rara_frame_graph_create(const rara_gaussians* g, const rara_camera* 
 
     const GaussPtrs gp{g->n, g->sh_degree, g->sh_layout, g->mean, g->scale, g->quat, g->opacity, g->sh};
     const ProjPtrs pp{proj->label, static_cast<Splat*>(proj->splat), static_cast<RayRec*>(proj->ray), nullptr,
-                      proj->depth, proj->rect, proj->tiles_touched};
+                      proj->depth, proj->tiles_touched, reinterpret_cast<ulonglong2*>(proj->tile_rec)};
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
         destroy(fg);

@@ -41,12 +41,21 @@ __device__ inline void sh_eval(int deg, double x, double y, double z, double* Y)
     Y[15] = -0.5900435899266435 * x * (xx - 3.0 * yy);
 }
 
+// What the listed-tile test needs of a drawn Gaussian (area 0: not drawn).
+struct Footprint {
+    double mx, my;
+    float ca, cb, cc, op;
+    int tx0, ty0, w, area;
+};
+
 // kDeg: the SH degree, fixed per launch so that every coefficient load of a
-// Gaussian is issued before the first one is used.
+// Gaussian is issued before the first one is used.  Writes every output but
+// tiles_touched and tile_rec, which the listed-tile pass writes.
 template <int kDeg, int kShMode>
-__device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl,
-                                               const ProjPtrs& out, int64_t i)
+__device__ __forceinline__ Footprint preprocess_one(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl,
+                                                    const ProjPtrs& out, int64_t i)
 {
+    Footprint fp{};
     const int64_t n = g.n;
 
     // every per-Gaussian input but the SH is loaded here, once: the output
@@ -163,6 +172,10 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
                     const int tx0 = (int)x0 >> 4, tx1 = ((int)x1 >> 4) + 1;
                     const int ty0 = (int)y0 >> 4, ty1 = ((int)y1 >> 4) + 1;
                     touched = (uint32_t)((tx1 - tx0) * (ty1 - ty0));
+                    fp.tx0 = tx0;
+                    fp.ty0 = ty0;
+                    fp.w = tx1 - tx0;
+                    fp.area = (int)touched;
 
                     // colour: SH in the direction from the camera centre to mu
                     double dir[3] = {mu[0] - cam.e[0], mu[1] - cam.e[1], mu[2] - cam.e[2]};
@@ -189,10 +202,13 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
                     // not hold a CUTOFF Gaussian's ellipsoid inside (see staged_word)
                     sp.label = label | (label == RARA_LABEL_CUTOFF ? cuts << 16 : 0u);
                     out.splat[i] = sp;
+                    fp.mx = mx;
+                    fp.my = my;
+                    fp.ca = sp.ca;
+                    fp.cb = sp.cb;
+                    fp.cc = sp.cc;
+                    fp.op = opf;
                     out.depth[i] = (float)tz;
-                    ushort4 rc = make_ushort4((unsigned short)tx0, (unsigned short)ty0, (unsigned short)tx1,
-                                              (unsigned short)ty1);
-                    *reinterpret_cast<ushort4*>(out.rect + 4 * i) = rc;
 
                     if (label == RARA_LABEL_CUTOFF) {
                         // M^-1 = S^-1 R^T: row a is column a of R divided by sigma_a
@@ -223,26 +239,211 @@ __device__ __forceinline__ void preprocess_one(const GaussPtrs& g, const CamPara
         }
     }
     out.label[i] = label;
-    out.tiles_touched[i] = touched;
+    (void)touched;
+    return fp;
+}
+
+constexpr int kPreThreads = 256;
+
+// Orders the LDS accesses of a wave's lanes before and after it (no other wave
+// takes part).
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The 16-byte tile record of a Gaussian: its rectangle (as in rect; zero when
+// not drawn) and its listed-tile mask, so that one gather fetches both.
+__device__ inline ulonglong2 tile_record(const Footprint& f, uint64_t mask)
+{
+    const uint64_t r = f.area > 0 ? ((uint64_t)(uint16_t)f.tx0 | (uint64_t)(uint16_t)f.ty0 << 16 |
+                                     (uint64_t)(uint16_t)(f.tx0 + f.w) << 32 |
+                                     (uint64_t)(uint16_t)(f.ty0 + f.area / f.w) << 48)
+                                  : 0ull;
+    return make_ulonglong2(r, mask);
+}
+
+// FP64 minimum of A x^2 + 2 B x y + C y^2 over the box [x0, x1] x [y0, y1]
+// (relative to the centre) of a positive definite form, iA = 1/A, iC = 1/C:
+// zero when the box holds the centre, else the least of the four edges' minima,
+// each at the edge's stationary point clamped to the edge.  Every operation is
+// rounded on its own (no fused multiply-add), so the result does not depend on
+// where the compiler inlines it.
+__device__ inline double edge_x_min(double A, double B, double C, double iC, double X, double y0, double y1)
+{
+#pragma clang fp contract(off)
+    double y = -B * X * iC;   // stationary point of q along x = X
+    y = y < y0 ? y0 : (y > y1 ? y1 : y);
+    return A * X * X + 2.0 * B * X * y + C * y * y;
+}
+
+__device__ inline double edge_y_min(double A, double B, double C, double iA, double Y, double x0, double x1)
+{
+#pragma clang fp contract(off)
+    double x = -B * Y * iA;   // stationary point of q along y = Y
+    x = x < x0 ? x0 : (x > x1 ? x1 : x);
+    return A * x * x + 2.0 * B * x * Y + C * Y * Y;
+}
+
+// Only the edges that face the centre can hold the minimum: at a minimum
+// inside the far edge x = X (X > 0 with the box right of the centre), dq/dy = 0
+// puts the point at y = -B X / C, where dq/dx = 2 X det / C > 0 would let q fall
+// into the box; a corner belongs to a facing edge too.  So the vertical edge
+// nearer the centre (when the centre is outside [x0, x1]) and the horizontal
+// one likewise are evaluated, and the other two cannot be lower.
+__device__ inline double box_min_fp64(double A, double B, double C, double iA, double iC, double x0, double x1,
+                                      double y0, double y1)
+{
+    const bool fx = x0 > 0.0 || x1 < 0.0, fy = y0 > 0.0 || y1 < 0.0;
+    if (!fx && !fy) return 0.0;   // the box holds the centre
+    const double ex = edge_x_min(A, B, C, iC, x0 > 0.0 ? x0 : x1, y0, y1);
+    const double ey = edge_y_min(A, B, C, iA, y0 > 0.0 ? y0 : y1, x0, x1);
+    return fmin(fx ? ex : INFINITY, fy ? ey : INFINITY);
+}
+
+// Listed tiles of every lane's Gaussian (every lane of the wave calls this):
+// for a drawn Gaussian whose rectangle has at most kMaskTiles tiles, bit k of
+// mask is set when its k-th tile (row by row) has a pixel-centre box on which
+// the float32 conic's quadratic form reaches 1.02 * 2 ln(255 delta) + 0.02 or
+// less; touched is the number of listed tiles (the whole rectangle when it is
+// larger).  The (Gaussian, tile) tests of the 64 lanes are dealt over the
+// lanes, 64 at a time, so that one large rectangle does not hold up its wave:
+// the lane of test e finds its Gaussian by a binary search over the wave's
+// inclusive test counts in LDS and ORs its bit into that Gaussian's LDS mask.
+__device__ inline void listed_tiles(const Footprint& f, int W, int H, uint64_t& mask, uint32_t& touched)
+{
+    __shared__ double s_g[kPreThreads][8];   // mx, my, A, B, C, 1/A, 1/C, threshold
+    __shared__ int s_r[kPreThreads][4];      // tx0, ty0, w, inclusive end of the wave's tests
+    __shared__ unsigned long long s_m[kPreThreads];
+    const int tid = threadIdx.x, lane = tid & 63, wb = tid & ~63;
+    mask = 0ull;
+    touched = (uint32_t)f.area;
+    uint32_t tests = 0u;
+    if (f.area > 0 && f.area <= kMaskTiles) {
+        const double A = (double)f.ca, B = (double)f.cb, C = (double)f.cc;
+        const double s255 = 255.0 * (double)f.op;
+        touched = 0u;
+        if (s255 > 1.0) {
+            bool pd;
+            {
+#pragma clang fp contract(off)
+                pd = A * C - B * B > 0.0;
+            }
+            if (!pd) {
+                mask = f.area == 64 ? ~0ull : ((1ull << f.area) - 1ull);
+                touched = (uint32_t)f.area;
+            } else {
+                tests = (uint32_t)f.area;
+                double t;
+                {
+#pragma clang fp contract(off)
+                    t = 2.0 * log(s255) * 1.02 + 0.02;
+                }
+                s_g[tid][0] = f.mx;
+                s_g[tid][1] = f.my;
+                s_g[tid][2] = A;
+                s_g[tid][3] = B;
+                s_g[tid][4] = C;
+                s_g[tid][5] = 1.0 / A;
+                s_g[tid][6] = 1.0 / C;
+                s_g[tid][7] = t;
+                s_r[tid][0] = f.tx0;
+                s_r[tid][1] = f.ty0;
+                s_r[tid][2] = f.w;
+            }
+        }
+    }
+    // inclusive prefix of the test counts over the wave
+    uint32_t incl = tests;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off, 64);
+        incl += lane >= off ? v : 0u;
+    }
+    const uint32_t total = __shfl(incl, 63, 64);
+    if (total == 0u) return;   // uniform over the wave: no rectangle to test
+    s_r[tid][3] = (int)incl;
+    s_m[tid] = 0ull;
+    // every LDS entry a wave reads below belongs to the wave itself: a
+    // wavefront-scope fence orders its lanes' writes before their reads
+    wave_sync();
+    // test e of the wave: its Gaussian's lane (the first lane whose inclusive
+    // end exceeds e) and tile li of that Gaussian's rectangle
+    auto test = [&](uint32_t e, int& o, uint32_t& li) {
+        int own = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+            if ((uint32_t)s_r[wb + own + step - 1][3] <= e) own += step;
+        o = wb + own;
+        li = e - (own ? (uint32_t)s_r[o - 1][3] : 0u);
+        const int w = s_r[o][2];
+        const int row = (int)li / w, col = (int)li - row * w;
+        const int tx = s_r[o][0] + col, ty = s_r[o][1] + row;
+        const double mx = s_g[o][0], my = s_g[o][1];
+        double x0, x1, y0, y1;
+        {
+#pragma clang fp contract(off)
+            x0 = (double)(tx * kTile) - mx;
+            x1 = fmin((double)(tx * kTile + kTile - 1), (double)(W - 1)) - mx;
+            y0 = (double)(ty * kTile) - my;
+            y1 = fmin((double)(ty * kTile + kTile - 1), (double)(H - 1)) - my;
+        }
+        return box_min_fp64(s_g[o][2], s_g[o][3], s_g[o][4], s_g[o][5], s_g[o][6], x0, x1, y0, y1) <= s_g[o][7];
+    };
+    // two tests per lane and step (e and e + 64): independent chains of LDS
+    // reads that overlap
+    for (uint32_t e0 = 0; e0 < total; e0 += 128) {
+        const uint32_t ea = e0 + (uint32_t)lane, eb = ea + 64u;
+        const uint32_t ca = ea < total ? ea : total - 1u, cb = eb < total ? eb : total - 1u;
+        int oa, ob;
+        uint32_t la, lb;
+        const bool ha = test(ca, oa, la) && ea < total;
+        const bool hb = test(cb, ob, lb) && eb < total;
+        if (ha) atomicOr(&s_m[oa], 1ull << la);
+        if (hb) atomicOr(&s_m[ob], 1ull << lb);
+    }
+    wave_sync();
+    if (tests) {
+        mask = s_m[tid];
+        touched = (uint32_t)__popcll(mask);
+    }
 }
 
 template <int kDeg, int kShMode>
-__global__ __launch_bounds__(256) void preprocess_kernel(GaussPtrs g, CamParams cam, PlaneParams pl, ProjPtrs out)
+__global__ __launch_bounds__(kPreThreads) void preprocess_kernel(GaussPtrs g, CamParams cam, PlaneParams pl,
+                                                                 ProjPtrs out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < g.n) preprocess_one<kDeg, kShMode>(g, cam, pl, out, i);
+    Footprint fp{};
+    if (i < g.n) fp = preprocess_one<kDeg, kShMode>(g, cam, pl, out, i);
+    uint64_t mask;
+    uint32_t touched;
+    listed_tiles(fp, cam.W, cam.H, mask, touched);
+    if (i < g.n) {
+        out.tiles_touched[i] = touched;
+        out.tile_rec[i] = tile_record(fp, mask);
+    }
 }
 
 // Frame-graph variant: camera and plane read from device memory.
 template <int kDeg, int kShMode>
-__global__ __launch_bounds__(256) void preprocess_fp_kernel(GaussPtrs g, const FrameParams* __restrict__ fp,
-                                                            ProjPtrs out)
+__global__ __launch_bounds__(kPreThreads) void preprocess_fp_kernel(GaussPtrs g, const FrameParams* __restrict__ fp,
+                                                                    ProjPtrs out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.n) return;
     // read through the pointer: a private copy of the plane arrays, indexed
     // by the plane number, would live in scratch memory
-    preprocess_one<kDeg, kShMode>(g, fp->cam, fp->plane, out, i);
+    Footprint f{};
+    if (i < g.n) f = preprocess_one<kDeg, kShMode>(g, fp->cam, fp->plane, out, i);
+    uint64_t mask;
+    uint32_t touched;
+    listed_tiles(f, fp->cam.W, fp->cam.H, mask, touched);
+    if (i < g.n) {
+        out.tiles_touched[i] = touched;
+        out.tile_rec[i] = tile_record(f, mask);
+    }
 }
 
 // Launches kernel<degree, SH mode> for the degree and SH mode of g (rows of
@@ -270,8 +471,8 @@ struct LaunchPre {
     static void go(const GaussPtrs& g, const CamParams& cam, const PlaneParams& pl, const ProjPtrs& out,
                    hipStream_t s)
     {
-        hipLaunchKernelGGL((preprocess_kernel<kDeg, kShMode>), dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s,
-                           g, cam, pl, out);
+        const dim3 grid((unsigned)((g.n + kPreThreads - 1) / kPreThreads));
+        hipLaunchKernelGGL((preprocess_kernel<kDeg, kShMode>), grid, dim3(kPreThreads), 0, s, g, cam, pl, out);
     }
 };
 
@@ -279,8 +480,8 @@ template <int kDeg, int kShMode>
 struct LaunchPreFp {
     static void go(const GaussPtrs& g, const FrameParams* fp, const ProjPtrs& out, hipStream_t s)
     {
-        hipLaunchKernelGGL((preprocess_fp_kernel<kDeg, kShMode>), dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0,
-                           s, g, fp, out);
+        const dim3 grid((unsigned)((g.n + kPreThreads - 1) / kPreThreads));
+        hipLaunchKernelGGL((preprocess_fp_kernel<kDeg, kShMode>), grid, dim3(kPreThreads), 0, s, g, fp, out);
     }
 };
 

@@ -10,6 +10,9 @@
 namespace rara {
 
 constexpr int kTile = 16;               // 16x16-pixel screen tiles
+// a tile rectangle of at most kMaskTiles tiles lists only the tiles the
+// Gaussian reaches (word 1 of ProjPtrs::tile_rec); a larger one lists every tile
+constexpr int kMaskTiles = 64;
 constexpr float kAlphaMax = 0.99f;      // Algorithm 1 step 3 clamp
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 1e-4f;
@@ -115,14 +118,44 @@ __device__ inline void load_sh(const GaussPtrs& g, int64_t i, float (&v)[3 * kCo
     }
 }
 
+// Position (row by row in the rectangle) of the n-th listed tile of a
+// rectangle with `area` tiles and listed-tile mask m.
+__device__ inline uint32_t listed_tile(uint64_t m, int area, uint32_t n)
+{
+    if (area > kMaskTiles) return n;
+    uint32_t k = 0;
+#pragma unroll
+    for (int half = 32; half > 0; half >>= 1) {
+        const uint32_t c = (uint32_t)__popcll(m & ((1ull << half) - 1ull));
+        if (n >= c) {
+            n -= c;
+            m >>= half;
+            k += (uint32_t)half;
+        }
+    }
+    return k;
+}
+
+// Number of listed tiles before rectangle position k (the inverse of listed_tile).
+__device__ inline uint32_t listed_rank(uint64_t m, int area, uint32_t k)
+{
+    return area > kMaskTiles ? k : (uint32_t)__popcll(m & ((1ull << k) - 1ull));
+}
+
+// Listed tiles of a rectangle of `area` tiles with mask m.
+__device__ inline uint32_t listed_count(uint64_t m, int area)
+{
+    return area > kMaskTiles ? (uint32_t)area : (uint32_t)__popcll(m);
+}
+
 struct ProjPtrs {
     uint8_t* label;
     Splat* splat;
     RayRec* ray;
     float2* ray_ext;   // [n][kMaxPlanes - 1] (dep, g0) of planes 1.. for a region, else unused
     float* depth;
-    uint16_t* rect;
     uint32_t* tiles_touched;
+    ulonglong2* tile_rec;   // [n] (rectangle, listed-tile mask of a rectangle of at most kMaskTiles tiles)
 };
 
 struct RenderParams {
@@ -183,8 +216,8 @@ struct BinWorkspace {
     int64_t* dcount;         // drawn-Gaussian count
     uint32_t* dkeys[2];      // depth keys, ping-pong [n]
     uint32_t* dvals[2];      // Gaussian indices, ping-pong [n]
-    ushort4* drect;          // [n] tile rectangles in depth order, over dkeys[1] and dvals[1] (free
-                             // once the depth sort has ended in buffer 0)
+    ulonglong2* drec;        // [n] tile records in depth order, from dkeys[1] on (dkeys[1] and dvals[1]
+                             // are free once the depth sort has ended in buffer 0)
     uint32_t* tkeys;         // tile keys [cap]
     uint32_t* tvals;         // Gaussian indices [cap]
     uint32_t* hist;          // [kRadix][max(depth_blocks, tile_blocks)]

@@ -76,8 +76,8 @@ class ProjectedBuffers:
         self.splat = torch.empty(m * B.SPLAT_BYTES // 4, dtype=torch.float32, device=device)
         self.ray = torch.empty(m * B.RAY_BYTES // 4, dtype=torch.float32, device=device)
         self.depth = torch.empty(m, dtype=torch.float32, device=device)
-        self.rect = torch.empty(m * 4, dtype=torch.int16, device=device)
         self.tiles_touched = torch.empty(m, dtype=torch.int32, device=device)
+        self.tile_rec = torch.empty(2 * m, dtype=torch.int64, device=device)   # 16 B per Gaussian
         self.ray_ext = None   # a clip region's further-plane terms, allocated on first use
         self.device = device
 
@@ -89,13 +89,14 @@ class ProjectedBuffers:
     def struct(self) -> B.Projected:
         p = B.Projected()
         p.label, p.splat, p.ray = _ptr(self.label), _ptr(self.splat), _ptr(self.ray)
-        p.depth, p.rect, p.tiles_touched = _ptr(self.depth), _ptr(self.rect), _ptr(self.tiles_touched)
+        p.depth, p.tiles_touched = _ptr(self.depth), _ptr(self.tiles_touched)
         p.ray_ext = _ptr(self.ray_ext)
+        p.tile_rec = _ptr(self.tile_rec)
         return p
 
     def nbytes(self) -> int:
         ext = self.ray_ext.numel() * 4 if self.ray_ext is not None else 0
-        return self.n * (1 + B.SPLAT_BYTES + B.RAY_BYTES + 4 + 8 + 4) + ext
+        return self.n * (1 + B.SPLAT_BYTES + B.RAY_BYTES + 4 + 4 + 16) + ext
 
 
 class BinBuffers:

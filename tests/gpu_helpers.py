@@ -41,7 +41,8 @@ def collect(fr, out, n):
         overflow=int(fr.bins.overflow.item()),
         label=fr.proj.label[:n].cpu().numpy(),
         tiles_touched=fr.proj.tiles_touched[:n].cpu().numpy().view(np.uint32),
-        rect=fr.proj.rect[: 4 * n].cpu().numpy().view(np.uint16).reshape(-1, 4).astype(np.int32),
+        tile_mask=fr.proj.tile_rec[: 2 * n].cpu().numpy().view(np.uint64).reshape(-1, 2)[:, 1],
+        rect=fr.proj.tile_rec[: 2 * n].cpu().numpy().view(np.uint16).reshape(-1, 8)[:, :4].astype(np.int32),
         depth=fr.proj.depth[:n].cpu().numpy(),
         keys=fr.bins.keys[:P].cpu().numpy().view(np.uint64),
         vals=fr.bins.vals[:P].cpu().numpy().view(np.uint32),
@@ -63,17 +64,19 @@ def tile_list(res, tile):
 
 
 def check_projection(g, o):
-    """Labels, drawn sets, rectangles and float32 depths identical to the
-    oracle except for Gaussians the oracle counts as within 1e-6 of a label,
-    footprint or near-plane boundary; projected floats to float32 rounding.
-    Returns the pixel mask of tiles touched by the (allowed) mismatches."""
+    """Labels, the sets of Gaussians listed in some tile, rectangles, listed-tile
+    masks and float32 depths identical to the oracle except for Gaussians the
+    oracle counts as within 1e-6 of a label, footprint, listed-tile or
+    near-plane boundary; projected floats to float32 rounding.  Returns the
+    pixel mask of tiles touched by the (allowed) mismatches."""
     import oracle
-    drawn = o["proj"]["drawn"].astype(bool)
+    drawn = o["proj"]["tiles_touched"] > 0
     gd = g["tiles_touched"] > 0
     mism = (g["label"] != o["label"]) | (gd != drawn)
     both = drawn & gd
     mism[both] |= (g["rect"][both] != o["proj"]["rect"][both]).any(axis=1)
     mism[both] |= g["depth"][both] != o["proj"]["depth32"][both]
+    mism[both] |= g["tile_mask"][both] != o["proj"]["tmask"][both]
     bad = np.nonzero(mism)[0]
     allowed = set(o.get("boundary_ids", np.zeros(0, int)).tolist())
     outside = [i for i in bad if i not in allowed]

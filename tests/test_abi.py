@@ -200,7 +200,7 @@ def test_static_bin_sort_rejects_frames_beyond_its_workspace(B):
     """rara_bin_sort_static (the entry point for callers that cannot allocate)
     checks its arguments like rara_bin_sort and refuses a frame whose
     workspace exceeds RARA_STATIC_WS_BYTES with RARA_ERR_SCRATCH, both before
-    anything reaches the GPU; the headline frame (1M Gaussians, 5.6M pairs of
+    anything reaches the GPU; the headline frame (1M Gaussians, 5M pairs of
     capacity at 1080p) fits."""
     lib = B.lib()
     hdr = open(HEADER).read()
@@ -210,7 +210,7 @@ def test_static_bin_sort_rejects_frames_beyond_its_workspace(B):
     assert "static workspace" in B.status_string(B.RARA_ERR_SCRATCH)
     cam = _cam(B)
     proj = B.Projected()
-    proj.label = proj.splat = proj.ray = proj.depth = proj.rect = proj.tiles_touched = 0x1000
+    proj.label = proj.splat = proj.ray = proj.depth = proj.tiles_touched = proj.tile_rec = 0x1000
     bins = B.Binned()
     assert lib.rara_bin_sort_static(ctypes.byref(proj), 10, ctypes.byref(cam), 100, ctypes.byref(bins), None) \
         == B.RARA_ERR_INVALID   # null outputs
@@ -221,7 +221,7 @@ def test_static_bin_sort_rejects_frames_beyond_its_workspace(B):
     assert B.workspace_bytes(B.RARA_WS_BIN_SORT, n, cap, 1920, 1080) > B.STATIC_WS_BYTES
     assert lib.rara_bin_sort_static(ctypes.byref(proj), n, ctypes.byref(cam), cap, ctypes.byref(bins), None) \
         == B.RARA_ERR_SCRATCH
-    assert B.workspace_bytes(B.RARA_WS_BIN_SORT, 1_000_000, 5_629_420, 1920, 1080) <= B.STATIC_WS_BYTES
+    assert B.workspace_bytes(B.RARA_WS_BIN_SORT, 1_000_000, 5_000_000, 1920, 1080) <= B.STATIC_WS_BYTES
 
 
 def test_render_batch_validation(B):
@@ -236,7 +236,7 @@ def test_render_batch_validation(B):
     assert lib.rara_render_batch(items, 17, None) == B.RARA_ERR_INVALID
     assert lib.rara_render_batch(items, 1, None) == B.RARA_ERR_INVALID   # null pointers
     proj, bins = B.Projected(), B.Binned()
-    proj.label = proj.splat = proj.ray = proj.depth = proj.rect = proj.tiles_touched = 0x1000
+    proj.label = proj.splat = proj.ray = proj.depth = proj.tiles_touched = proj.tile_rec = 0x1000
     bins.keys = bins.vals = bins.ranges = bins.num_pairs = bins.overflow = bins.work = 0x1000
     cam = _cam(B)
     box = B.make_plane(__import__("paper_2506_20202_amd.scenes", fromlist=["x"]).box_region((-1, -1, -1), (1, 1, 1)))
@@ -312,7 +312,7 @@ def test_clip_regions_are_validated_on_the_host(B):
     g.n = 10
     fake = ctypes.c_void_p(0x1000)
     full = B.Projected()
-    full.label = full.splat = full.ray = full.depth = full.rect = full.tiles_touched = 0x1000
+    full.label = full.splat = full.ray = full.depth = full.tiles_touched = full.tile_rec = 0x1000
     g.mean = g.scale = g.quat = g.opacity = g.sh = 0x1000
     assert lib.rara_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(box), ctypes.byref(full), None) \
         == B.RARA_ERR_INVALID

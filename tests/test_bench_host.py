@@ -49,11 +49,11 @@ def test_clip_order_strides_views_and_offsets():
 
 def test_stage_byte_models():
     """Per-stage algorithmic bytes: the preprocess of a scene where nothing is
-    live moves 29 B per Gaussian; one drawn SH3 Gaussian adds 16 + 4 + 192 +
-    60 B; the sort's tile passes follow the tile count (2 passes for the
+    live moves 45 B per Gaussian; one drawn SH3 Gaussian adds 16 + 4 + 192 +
+    52 B; the sort's tile passes follow the tile count (2 passes for the
     8160 tiles of 1080p, 1 for 64)."""
-    assert bench.preprocess_bytes(1000, 3, 0, 0, 0) == 29000
-    assert bench.preprocess_bytes(1, 3, 1, 1, 0) - 29 == 16 + 4 + 192 + 60
+    assert bench.preprocess_bytes(1000, 3, 0, 0, 0) == 45000
+    assert bench.preprocess_bytes(1, 3, 1, 1, 0) - 45 == 16 + 4 + 192 + 52
     assert bench.preprocess_bytes(1, 3, 1, 1, 1) - bench.preprocess_bytes(1, 3, 1, 1, 0) == 48
     one = bench.bin_sort_bytes(0, 0, 1, 64) - bench.bin_sort_bytes(0, 0, 0, 64)
     two = bench.bin_sort_bytes(0, 0, 1, 8160) - bench.bin_sort_bytes(0, 0, 0, 8160)

@@ -829,3 +829,117 @@ def test_box_render_matches_independent_marcher():
     assert ok.mean() > 0.9 and (o["label"] == 2).sum() >= 3
     err = np.abs(o["image"] - img).max(0)[ok]
     assert err.max() < 1e-5, err.max()
+
+
+# ------------------------------------------------------------ listed tiles ----
+
+def test_box_min_separable_closed_form():
+    """Listed-tile reading: with B = 0 the form is separable and convex in
+    each coordinate, so its minimum over a box is at the centre clamped into
+    the box, A clamp(0)^2 + C clamp(0)^2; a box holding the centre gives 0."""
+    rng = np.random.default_rng(5)
+    for _ in range(500):
+        A, C = rng.uniform(0.01, 3.0, 2)
+        x0, y0 = rng.uniform(-40.0, 40.0, 2)
+        x1, y1 = x0 + rng.uniform(0.0, 15.0), y0 + rng.uniform(0.0, 15.0)
+        want = A * float(np.clip(0.0, x0, x1)) ** 2 + C * float(np.clip(0.0, y0, y1)) ** 2
+        got = oracle.box_min(A, 0.0, C, x0, x1, y0, y1)
+        assert got == pytest.approx(want, rel=1e-12, abs=1e-300)
+    assert oracle.box_min(1.0, 0.4, 2.0, -3.0, 12.0, -0.5, 14.5) == 0.0
+
+
+def test_box_min_rotated_forms_against_dense_sampling():
+    """Rotated forms with eigenvalue ratios up to 1000: the minimum is no
+    larger than q at any point of a 301x301 grid over the box, and the grid's
+    best point lies within its spacing times the gradient bound of it."""
+    rng = np.random.default_rng(6)
+    for _ in range(300):
+        th = rng.uniform(0.0, math.pi)
+        l1 = rng.uniform(1e-3, 3.0)
+        l2 = l1 * rng.uniform(1.0, 1000.0) ** (1 if rng.uniform() < 0.5 else -1)
+        c, s = math.cos(th), math.sin(th)
+        A = l1 * c * c + l2 * s * s
+        B = (l1 - l2) * c * s
+        C = l1 * s * s + l2 * c * c
+        x0, y0 = rng.uniform(-30.0, 30.0, 2)
+        x1, y1 = x0 + 15.0, y0 + 15.0
+        gx = np.linspace(x0, x1, 301)
+        gy = np.linspace(y0, y1, 301)
+        X, Y = np.meshgrid(gx, gy)
+        q = A * X * X + 2.0 * B * X * Y + C * Y * Y
+        smin = float(q.min())
+        got = oracle.box_min(A, B, C, x0, x1, y0, y1)
+        assert got <= smin * (1.0 + 1e-12) + 1e-12
+        corner = max(abs(x0), abs(x1)) + max(abs(y0), abs(y1))
+        slack = 2.0 * max(l1, l2) * corner * (15.0 / 300.0) * math.sqrt(2.0)
+        assert smin - got <= slack
+
+
+def _listed_tile_scene():
+    sc = scenes.general_scene(seed=3, n=4000)
+    cam = scenes.general_views(count=4, width=200, height=120, radius=9.0)[1]
+    return sc, cam
+
+
+def test_listed_tiles_leave_out_only_tiles_no_pixel_reaches():
+    """Every (Gaussian, tile) pair that the listed-tile reading leaves out of
+    a rectangle has alpha = delta exp(-q/2) < 1/255 at every pixel centre of
+    the tile (FP64 conic, the one the compositor uses), so no pixel would
+    have taken it; pairs are left out on this scene, and a rectangle of more
+    than 64 tiles keeps all of them."""
+    sc, cam = _listed_tile_scene()
+    lab = np.ones(sc.n, np.uint8)
+    pc = oracle.project(sc, cam, lab)
+    pf = oracle.project(sc, cam, lab, cull=False)
+    np.testing.assert_array_equal(pc["rect"], pf["rect"])
+    area = (pf["rect"][:, 2] - pf["rect"][:, 0]) * (pf["rect"][:, 3] - pf["rect"][:, 1])
+    assert pc["tiles_touched"].sum() < 0.9 * pf["tiles_touched"].sum()
+    big = (pf["drawn"] == 1) & (area > 64)
+    np.testing.assert_array_equal(pc["tiles_touched"][big], area[big])
+    dropped = 0
+    for i in np.flatnonzero((pf["drawn"] == 1) & (area <= 64)):
+        tx0, ty0, tx1, ty1 = pf["rect"][i]
+        w = tx1 - tx0
+        gone = int(pf["tmask"][i]) & ~int(pc["tmask"][i])
+        assert int(pc["tmask"][i]) & ~int(pf["tmask"][i]) == 0
+        assert pc["tiles_touched"][i] == bin(int(pc["tmask"][i])).count("1")
+        A, B, C = pc["conic"][i]
+        mx, my = pc["mean2d"][i]
+        for k in range(int(area[i])):
+            if not (gone >> k) & 1:
+                continue
+            dropped += 1
+            tx, ty = tx0 + k % w, ty0 + k // w
+            xs = np.arange(tx * 16, min(tx * 16 + 16, cam.width)) - mx
+            ys = np.arange(ty * 16, min(ty * 16 + 16, cam.height)) - my
+            X, Y = np.meshgrid(xs, ys)
+            q = A * X * X + 2.0 * B * X * Y + C * Y * Y
+            alpha = float(sc.opacity[i]) * np.exp(-0.5 * q)
+            assert alpha.max() < 1.0 / 255.0, (i, k)
+    assert dropped > 100
+
+
+def test_listed_tiles_render_the_same_frame():
+    """The oracle frame over the listed tiles and over whole rectangles (the
+    paper's binning): the same image, transmittance and last contributor
+    (as a Gaussian id), bit for bit, with a plane that clips."""
+    sc, cam = _listed_tile_scene()
+    rng = np.random.default_rng(7)
+    n = _rand_unit(rng)
+    pl = scenes.Plane(n.astype(np.float32), float(np.float32(0.2)))
+    a = oracle.render(sc, cam, pl, events=False)
+    b = oracle.render(sc, cam, pl, events=False, cull=False)
+    assert (a["label"] == oracle.CUTOFF).sum() > 50
+    assert a["ids"].size < 0.9 * b["ids"].size
+    np.testing.assert_array_equal(a["image"], b["image"])
+    np.testing.assert_array_equal(a["final_T"], b["final_T"])
+
+    def last_ids(o):
+        tx = (cam.width + 15) // 16
+        ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+        tile = (ys // 16) * tx + xs // 16
+        nc = o["n_contrib"]
+        pos = o["offsets"][tile] + np.maximum(nc, 1) - 1
+        return np.where(nc > 0, o["ids"][np.minimum(pos, o["ids"].size - 1)], -1)
+
+    np.testing.assert_array_equal(last_ids(a), last_ids(b))

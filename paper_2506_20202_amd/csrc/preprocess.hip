@@ -271,20 +271,21 @@ __device__ inline ulonglong2 tile_record(const Footprint& f, uint64_t mask)
 // each at the edge's stationary point clamped to the edge.  Every operation is
 // rounded on its own (no fused multiply-add), so the result does not depend on
 // where the compiler inlines it.
-__device__ inline double edge_x_min(double A, double B, double C, double iC, double X, double y0, double y1)
+// B2 = 2 B (exact): the products are those of A X X + 2 B X y + C y y taken
+// left to right.  The clamp is fmin(fmax(.)), equal to the compare form for
+// y0 <= y1.
+__device__ inline double edge_x_min(double A, double B, double B2, double C, double iC, double X, double y0, double y1)
 {
 #pragma clang fp contract(off)
-    double y = -B * X * iC;   // stationary point of q along x = X
-    y = y < y0 ? y0 : (y > y1 ? y1 : y);
-    return A * X * X + 2.0 * B * X * y + C * y * y;
+    const double y = fmin(fmax(-B * X * iC, y0), y1);   // stationary point of q along x = X, clamped
+    return A * X * X + B2 * X * y + C * y * y;
 }
 
-__device__ inline double edge_y_min(double A, double B, double C, double iA, double Y, double x0, double x1)
+__device__ inline double edge_y_min(double A, double B, double B2, double C, double iA, double Y, double x0, double x1)
 {
 #pragma clang fp contract(off)
-    double x = -B * Y * iA;   // stationary point of q along y = Y
-    x = x < x0 ? x0 : (x > x1 ? x1 : x);
-    return A * x * x + 2.0 * B * x * Y + C * Y * Y;
+    const double x = fmin(fmax(-B * Y * iA, x0), x1);   // stationary point of q along y = Y, clamped
+    return A * x * x + B2 * x * Y + C * Y * Y;
 }
 
 // Only the edges that face the centre can hold the minimum: at a minimum
@@ -293,14 +294,54 @@ __device__ inline double edge_y_min(double A, double B, double C, double iA, dou
 // into the box; a corner belongs to a facing edge too.  So the vertical edge
 // nearer the centre (when the centre is outside [x0, x1]) and the horizontal
 // one likewise are evaluated, and the other two cannot be lower.
-__device__ inline double box_min_fp64(double A, double B, double C, double iA, double iC, double x0, double x1,
-                                      double y0, double y1)
+__device__ inline double box_min_fp64(double A, double B, double B2, double C, double iA, double iC, double x0,
+                                      double x1, double y0, double y1)
 {
     const bool fx = x0 > 0.0 || x1 < 0.0, fy = y0 > 0.0 || y1 < 0.0;
     if (!fx && !fy) return 0.0;   // the box holds the centre
-    const double ex = edge_x_min(A, B, C, iC, x0 > 0.0 ? x0 : x1, y0, y1);
-    const double ey = edge_y_min(A, B, C, iA, y0 > 0.0 ? y0 : y1, x0, x1);
+    const double ex = edge_x_min(A, B, B2, C, iC, x0 > 0.0 ? x0 : x1, y0, y1);
+    const double ey = edge_y_min(A, B, B2, C, iA, y0 > 0.0 ? y0 : y1, x0, x1);
     return fmin(fx ? ex : INFINITY, fy ? ey : INFINITY);
+}
+
+// Whether a Gaussian reaches tile (tx, ty): the box of the tile's pixel
+// centres, clipped to the W x H image and taken relative to the centre
+// (mx, my), against the threshold t.
+__device__ inline bool reaches_tile(double mx, double my, double A, double B, double C, double iA, double iC,
+                                    double t, int tx, int ty, int W, int H)
+{
+    double x0, x1, y0, y1;
+    {
+#pragma clang fp contract(off)
+        x0 = (double)(tx * kTile) - mx;
+        x1 = fmin((double)(tx * kTile + kTile - 1), (double)(W - 1)) - mx;
+        y0 = (double)(ty * kTile) - my;
+        y1 = fmin((double)(ty * kTile + kTile - 1), (double)(H - 1)) - my;
+    }
+    return box_min_fp64(A, B, 2.0 * B, C, iA, iC, x0, x1, y0, y1) <= t;
+}
+
+// Row of tile li in a rectangle w tiles wide (li < 64, w <= 64): (li + 1/2) / w
+// lies at least 1/128 from an integer, so the float product floors exactly.
+__device__ inline int rect_row(uint32_t li, int w)
+{
+    return (int)(((float)li + 0.5f) * __builtin_amdgcn_rcpf((float)w));
+}
+
+constexpr uint32_t kOwnTests = 4;   // tiles each lane tests itself
+
+// Exclusive prefix of v (below 128) over the wave, from one ballot per bit.
+__device__ inline uint32_t wave_prefix7(uint32_t v, uint32_t& total)
+{
+    uint32_t pre = 0u, tot = 0u;
+#pragma unroll
+    for (int b = 0; b < 7; ++b) {
+        const uint64_t m = __ballot((v >> b) & 1u);
+        pre += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << b;
+        tot += (uint32_t)__popcll(m) << b;
+    }
+    total = tot;
+    return pre;
 }
 
 // Listed tiles of every lane's Gaussian (every lane of the wave calls this):
@@ -308,19 +349,22 @@ __device__ inline double box_min_fp64(double A, double B, double C, double iA, d
 // mask is set when its k-th tile (row by row) has a pixel-centre box on which
 // the float32 conic's quadratic form reaches 1.02 * 2 ln(255 delta) + 0.02 or
 // less; touched is the number of listed tiles (the whole rectangle when it is
-// larger).  The (Gaussian, tile) tests of the 64 lanes are dealt over the
-// lanes, 64 at a time, so that one large rectangle does not hold up its wave:
-// the lane of test e finds its Gaussian by a binary search over the wave's
-// inclusive test counts in LDS and ORs its bit into that Gaussian's LDS mask.
+// larger).  Each lane tests the first kOwnTests tiles of its own rectangle
+// (most rectangles have no more); the rest of the wave's (Gaussian, tile)
+// tests are dealt over the lanes, two per lane and step, so that one large
+// rectangle does not hold up the wave: the lane of test e finds its Gaussian
+// by a binary search over the wave's inclusive test counts in LDS and ORs the
+// tile's bit into that Gaussian's LDS mask.
 __device__ inline void listed_tiles(const Footprint& f, int W, int H, uint64_t& mask, uint32_t& touched)
 {
     __shared__ double s_g[kPreThreads][8];   // mx, my, A, B, C, 1/A, 1/C, threshold
-    __shared__ int s_r[kPreThreads][4];      // tx0, ty0, w, inclusive end of the wave's tests
+    __shared__ int s_r[kPreThreads][4];      // tx0, ty0, w, inclusive end of the wave's shared tests
     __shared__ unsigned long long s_m[kPreThreads];
     const int tid = threadIdx.x, lane = tid & 63, wb = tid & ~63;
     mask = 0ull;
     touched = (uint32_t)f.area;
-    uint32_t tests = 0u;
+    bool tested = false;
+    uint32_t shared = 0u;   // tests past the lane's own ones
     if (f.area > 0 && f.area <= kMaskTiles) {
         const double A = (double)f.ca, B = (double)f.cb, C = (double)f.cc;
         const double s255 = 255.0 * (double)f.op;
@@ -335,80 +379,78 @@ __device__ inline void listed_tiles(const Footprint& f, int W, int H, uint64_t& 
                 mask = f.area == 64 ? ~0ull : ((1ull << f.area) - 1ull);
                 touched = (uint32_t)f.area;
             } else {
-                tests = (uint32_t)f.area;
+                tested = true;
                 double t;
                 {
 #pragma clang fp contract(off)
                     t = 2.0 * log(s255) * 1.02 + 0.02;
                 }
-                s_g[tid][0] = f.mx;
-                s_g[tid][1] = f.my;
-                s_g[tid][2] = A;
-                s_g[tid][3] = B;
-                s_g[tid][4] = C;
-                s_g[tid][5] = 1.0 / A;
-                s_g[tid][6] = 1.0 / C;
-                s_g[tid][7] = t;
-                s_r[tid][0] = f.tx0;
-                s_r[tid][1] = f.ty0;
-                s_r[tid][2] = f.w;
+                const double iA = 1.0 / A, iC = 1.0 / C;
+                const uint32_t own = (uint32_t)f.area < kOwnTests ? (uint32_t)f.area : kOwnTests;
+                int col = 0, row = 0;
+                for (uint32_t li = 0; li < own; ++li) {
+                    if (reaches_tile(f.mx, f.my, A, B, C, iA, iC, t, f.tx0 + col, f.ty0 + row, W, H))
+                        mask |= 1ull << li;
+                    if (++col == f.w) {
+                        col = 0;
+                        ++row;
+                    }
+                }
+                shared = (uint32_t)f.area - own;
+                if (shared) {
+                    s_g[tid][0] = f.mx;
+                    s_g[tid][1] = f.my;
+                    s_g[tid][2] = A;
+                    s_g[tid][3] = B;
+                    s_g[tid][4] = C;
+                    s_g[tid][5] = iA;
+                    s_g[tid][6] = iC;
+                    s_g[tid][7] = t;
+                    s_r[tid][0] = f.tx0;
+                    s_r[tid][1] = f.ty0;
+                    s_r[tid][2] = f.w;
+                }
             }
         }
     }
-    // inclusive prefix of the test counts over the wave
-    uint32_t incl = tests;
+    uint32_t total;
+    const uint32_t incl = wave_prefix7(shared, total) + shared;   // shared <= 60
+    if (total != 0u) {   // uniform over the wave
+        s_r[tid][3] = (int)incl;
+        s_m[tid] = 0ull;
+        // every LDS entry a wave reads below belongs to the wave itself: a
+        // wavefront-scope fence orders its lanes' writes before their reads
+        wave_sync();
+        // shared test e of the wave: its Gaussian's lane (the first lane whose
+        // inclusive end exceeds e) and tile li of that Gaussian's rectangle
+        auto test = [&](uint32_t e, int& o, uint32_t& li) {
+            int own = 0;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t v = __shfl_up(incl, off, 64);
-        incl += lane >= off ? v : 0u;
-    }
-    const uint32_t total = __shfl(incl, 63, 64);
-    if (total == 0u) return;   // uniform over the wave: no rectangle to test
-    s_r[tid][3] = (int)incl;
-    s_m[tid] = 0ull;
-    // every LDS entry a wave reads below belongs to the wave itself: a
-    // wavefront-scope fence orders its lanes' writes before their reads
-    wave_sync();
-    // test e of the wave: its Gaussian's lane (the first lane whose inclusive
-    // end exceeds e) and tile li of that Gaussian's rectangle
-    auto test = [&](uint32_t e, int& o, uint32_t& li) {
-        int own = 0;
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1)
-            if ((uint32_t)s_r[wb + own + step - 1][3] <= e) own += step;
-        o = wb + own;
-        li = e - (own ? (uint32_t)s_r[o - 1][3] : 0u);
-        const int w = s_r[o][2];
-        const int row = (int)li / w, col = (int)li - row * w;
-        const int tx = s_r[o][0] + col, ty = s_r[o][1] + row;
-        const double mx = s_g[o][0], my = s_g[o][1];
-        double x0, x1, y0, y1;
-        {
-#pragma clang fp contract(off)
-            x0 = (double)(tx * kTile) - mx;
-            x1 = fmin((double)(tx * kTile + kTile - 1), (double)(W - 1)) - mx;
-            y0 = (double)(ty * kTile) - my;
-            y1 = fmin((double)(ty * kTile + kTile - 1), (double)(H - 1)) - my;
+            for (int step = 32; step > 0; step >>= 1)
+                if ((uint32_t)s_r[wb + own + step - 1][3] <= e) own += step;
+            o = wb + own;
+            li = kOwnTests + e - (own ? (uint32_t)s_r[o - 1][3] : 0u);
+            const int w = s_r[o][2];
+            const int row = rect_row(li, w), col = (int)li - row * w;
+            return reaches_tile(s_g[o][0], s_g[o][1], s_g[o][2], s_g[o][3], s_g[o][4], s_g[o][5], s_g[o][6],
+                                s_g[o][7], s_r[o][0] + col, s_r[o][1] + row, W, H);
+        };
+        // two tests per lane and step (e and e + 64): independent chains of
+        // LDS reads that overlap
+        for (uint32_t e0 = 0; e0 < total; e0 += 128) {
+            const uint32_t ea = e0 + (uint32_t)lane, eb = ea + 64u;
+            const uint32_t ca = ea < total ? ea : total - 1u, cb = eb < total ? eb : total - 1u;
+            int oa, ob;
+            uint32_t la, lb;
+            const bool ha = test(ca, oa, la) && ea < total;
+            const bool hb = test(cb, ob, lb) && eb < total;
+            if (ha) atomicOr(&s_m[oa], 1ull << la);
+            if (hb) atomicOr(&s_m[ob], 1ull << lb);
         }
-        return box_min_fp64(s_g[o][2], s_g[o][3], s_g[o][4], s_g[o][5], s_g[o][6], x0, x1, y0, y1) <= s_g[o][7];
-    };
-    // two tests per lane and step (e and e + 64): independent chains of LDS
-    // reads that overlap
-    for (uint32_t e0 = 0; e0 < total; e0 += 128) {
-        const uint32_t ea = e0 + (uint32_t)lane, eb = ea + 64u;
-        const uint32_t ca = ea < total ? ea : total - 1u, cb = eb < total ? eb : total - 1u;
-        int oa, ob;
-        uint32_t la, lb;
-        const bool ha = test(ca, oa, la) && ea < total;
-        const bool hb = test(cb, ob, lb) && eb < total;
-        if (ha) atomicOr(&s_m[oa], 1ull << la);
-        if (hb) atomicOr(&s_m[ob], 1ull << lb);
+        wave_sync();
+        if (shared) mask |= s_m[tid];
     }
-    wave_sync();
-    if (tests) {
-        mask = s_m[tid];
-        touched = (uint32_t)__popcll(mask);
-    }
+    if (tested) touched = (uint32_t)__popcll(mask);
 }
 
 template <int kDeg, int kShMode>

@@ -876,7 +876,10 @@ def test_box_min_rotated_forms_against_dense_sampling():
 
 
 def _listed_tile_scene():
-    sc = scenes.general_scene(seed=3, n=4000)
+    """4,000 general-scene Gaussians and 16 large ones near the origin: a
+    few footprint rectangles of 33-64 tiles and of more than 64."""
+    sc = scenes.concat(scenes.general_scene(seed=3, n=4000, sh_degree=0),
+                       scenes.small_scene(7, n=16, spread=0.35, logscale_mean=0.0))
     cam = scenes.general_views(count=4, width=200, height=120, radius=9.0)[1]
     return sc, cam
 
@@ -943,3 +946,45 @@ def test_listed_tiles_render_the_same_frame():
         return np.where(nc > 0, o["ids"][np.minimum(pos, o["ids"].size - 1)], -1)
 
     np.testing.assert_array_equal(last_ids(a), last_ids(b))
+
+
+def test_listed_tile_masks_match_an_independent_edge_search():
+    """Every mask bit of a frame (rectangles of at most 64 tiles) against the
+    rule re-derived without the stationary-point formula: the minimum over
+    the tile's pixel-centre box (clipped to the image) is 0 when the box holds
+    the centre, else the least of 10,001 samples along each of its four
+    edges (a convex form's minimum over a box lies on its boundary).  Bits
+    within 1e-6 of the threshold are not judged."""
+    sc, cam = _listed_tile_scene()
+    p = oracle.project(sc, cam, np.ones(sc.n, np.uint8))
+    r = p["rect"][p["drawn"] == 1]
+    areas = (r[:, 2] - r[:, 0]) * (r[:, 3] - r[:, 1])
+    assert ((areas > 32) & (areas <= 64)).sum() >= 5 and (areas > 64).sum() >= 1
+    u = np.linspace(0.0, 1.0, 10001)
+    judged = kept = 0
+    for i in np.flatnonzero(p["drawn"] == 1):
+        tx0, ty0, tx1, ty1 = p["rect"][i]
+        w, area = tx1 - tx0, (tx1 - tx0) * (ty1 - ty0)
+        if area > 64:
+            continue
+        A, B, C = (float(np.float32(v)) for v in p["conic"][i])
+        s255 = 255.0 * float(sc.opacity[i])
+        t = 2.0 * math.log(s255) * 1.02 + 0.02 if s255 > 1.0 else -1.0
+        mx, my = p["mean2d"][i]
+        for k in range(area):
+            tx, ty = tx0 + k % w, ty0 + k // w
+            x0, x1 = tx * 16 - mx, min(tx * 16 + 15, cam.width - 1) - mx
+            y0, y1 = ty * 16 - my, min(ty * 16 + 15, cam.height - 1) - my
+            if x0 <= 0 <= x1 and y0 <= 0 <= y1:
+                qmin = 0.0
+            else:
+                xs = np.concatenate([x0 + (x1 - x0) * u, x0 + (x1 - x0) * u, np.full_like(u, x0), np.full_like(u, x1)])
+                ys = np.concatenate([np.full_like(u, y0), np.full_like(u, y1), y0 + (y1 - y0) * u, y0 + (y1 - y0) * u])
+                qmin = float((A * xs * xs + 2.0 * B * xs * ys + C * ys * ys).min())
+            if s255 > 1.0 and abs(qmin - t) <= 1e-6 * max(1.0, t):
+                continue
+            bit = (int(p["tmask"][i]) >> k) & 1
+            assert bit == (s255 > 1.0 and qmin <= t), (i, k, qmin, t)
+            judged += 1
+            kept += bit
+    assert judged > 5000 and 0.3 * judged < kept < 0.9 * judged

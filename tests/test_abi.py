@@ -316,6 +316,13 @@ def test_clip_regions_are_validated_on_the_host(B):
     g.mean = g.scale = g.quat = g.opacity = g.sh = 0x1000
     assert lib.rara_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(box), ctypes.byref(full), None) \
         == B.RARA_ERR_INVALID
+    # the tile records are required and 16-byte aligned (refused before any launch)
+    one = B.make_plane(scenes.tiny_plane(1))
+    for bad in (0, 0x1008):
+        full.tile_rec = bad
+        assert lib.rara_preprocess(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(one), ctypes.byref(full),
+                                   None) == B.RARA_ERR_INVALID
+    full.tile_rec = 0x1000
     bins = B.Binned()
     bins.keys = bins.vals = bins.ranges = bins.num_pairs = bins.overflow = bins.work = bins.pair_start = 0x1000
     img = (ctypes.c_float * 3)()

@@ -265,15 +265,13 @@ __device__ inline ulonglong2 tile_record(const Footprint& f, uint64_t mask)
     return make_ulonglong2(r, mask);
 }
 
-// FP64 minimum of A x^2 + 2 B x y + C y^2 over the box [x0, x1] x [y0, y1]
-// (relative to the centre) of a positive definite form, iA = 1/A, iC = 1/C:
-// zero when the box holds the centre, else the least of the four edges' minima,
-// each at the edge's stationary point clamped to the edge.  Every operation is
+// Minimum of q = A x^2 + 2 B x y + C y^2 (a positive definite form, relative
+// to the centre) along the edge x = X, y in [y0, y1]: q at the edge's
+// stationary point -B X / C (iC = 1/C) clamped to the edge.  Every operation is
 // rounded on its own (no fused multiply-add), so the result does not depend on
-// where the compiler inlines it.
-// B2 = 2 B (exact): the products are those of A X X + 2 B X y + C y y taken
-// left to right.  The clamp is fmin(fmax(.)), equal to the compare form for
-// y0 <= y1.
+// where the compiler inlines it; the products are those of A X X + 2 B X y +
+// C y y taken left to right (B2 = 2 B is exact), and fmin(fmax(.)) equals the
+// compare form of the clamp for y0 <= y1.
 __device__ inline double edge_x_min(double A, double B, double B2, double C, double iC, double X, double y0, double y1)
 {
 #pragma clang fp contract(off)
@@ -281,6 +279,7 @@ __device__ inline double edge_x_min(double A, double B, double B2, double C, dou
     return A * X * X + B2 * X * y + C * y * y;
 }
 
+// The same along the edge y = Y, x in [x0, x1], stationary at -B Y / A (iA = 1/A).
 __device__ inline double edge_y_min(double A, double B, double B2, double C, double iA, double Y, double x0, double x1)
 {
 #pragma clang fp contract(off)
@@ -288,7 +287,9 @@ __device__ inline double edge_y_min(double A, double B, double B2, double C, dou
     return A * x * x + B2 * x * Y + C * Y * Y;
 }
 
-// Only the edges that face the centre can hold the minimum: at a minimum
+// FP64 minimum of q over the box [x0, x1] x [y0, y1]: zero when the box holds
+// the centre.  Otherwise the minimum of the convex q lies on the boundary, and
+// only the edges that face the centre can hold it: at a minimum
 // inside the far edge x = X (X > 0 with the box right of the centre), dq/dy = 0
 // puts the point at y = -B X / C, where dq/dx = 2 X det / C > 0 would let q fall
 // into the box; a corner belongs to a facing edge too.  So the vertical edge

@@ -256,8 +256,8 @@ rara_status rara_preprocess(const rara_gaussians* g, const rara_camera* cam, con
 
 /* Tile binning and depth sort (the "sorted by depth" order of Sec. 3.1, per
  * 16x16 tile): exclusive scan of tiles_touched, one (tile|depth, index) pair
- * per drawn Gaussian and covered tile, LSD radix sort on the significant key
- * bits, and per-tile ranges.  Needs `ws_bytes` >= rara_workspace_bytes(
+ * per drawn Gaussian and listed tile (tile_rec), LSD radix sort on the
+ * significant key bits, and per-tile ranges.  Needs `ws_bytes` >= rara_workspace_bytes(
  * RARA_WS_BIN_SORT, n, pair_capacity, W, H) bytes of device workspace.
  * Overflow: if the frame has more than pair_capacity pairs, *num_pairs holds
  * the required count and *overflow is 1.  The sorted pairs, ranges and

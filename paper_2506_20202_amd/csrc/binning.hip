@@ -8,7 +8,8 @@
 //      ties stay in index order); the first pass reads all Gaussians in index
 //      order and keeps the drawn ones, so no separate compaction runs;
 //   3. exclusive scan of tiles_touched in that order and emission of one
-//      (tile, index) pair per covered tile -- the pairs are now in depth order;
+//      (tile, index) pair per listed tile (the tiles of the rectangle the
+//      Gaussian reaches) -- the pairs are now in depth order;
 //   4. ceil(log2(tiles) / 8) stable LSD passes on the tile digits, the last one
 //      writing the 64-bit keys;
 //   5. per-tile [start, end) ranges and the blend schedule.

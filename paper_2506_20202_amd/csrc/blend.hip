@@ -67,19 +67,32 @@ constexpr int kBlendThreads = 256;   // one workgroup per tile: four waves, one 
 // entries staged per batch, one per thread of the first 224: with 64 VGPRs
 // and under 20 KB of LDS a CU holds 8 workgroups (8 waves per SIMD)
 constexpr int kTileBatch = 224;
-constexpr int kBatchSlots = 256;     // s_c rows: four 64-entry ballots, the tail zero
+constexpr int kBatchSlots = 256;     // s_c rows: four 64-entry ballots, the tail zero (quadrant units)
 // the clip-region variant stages the further planes' terms too (56 B per
 // entry): 128-entry batches keep it under 20 KB of LDS
 constexpr int kRegionBatch = 128;
 template <bool kRegion> constexpr int batch_of() { return kRegion ? kRegionBatch : kTileBatch; }
 template <bool kRegion> constexpr int slots_of() { return kRegion ? kRegionBatch : kBatchSlots; }
+// entries per window of a whole-tile wave: four windows fill the batch arrays
+template <bool kRegion> constexpr uint32_t tile_window() { return (uint32_t)batch_of<kRegion>() / 4u; }
+static_assert(tile_window<false>() <= 64 && tile_window<true>() <= 64, "a window is one ballot");
+
+// Orders the LDS accesses of a wave's lanes before and after it (no other wave
+// takes part).
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // One tile: thread t of wave w = t / 64 owns pixel (t % 8, (t / 8) % 8) of the
-// 8x8 quadrant w.  Per batch, every thread stages one entry; after the
-// barrier each wave takes, per 64 staged entries, one ballot of the entries
-// that reach its quadrant and one of the CUTOFF entries, and visits the set
-// bits in order.  A wave re-takes its live pixels every 16 entries and stops
-// visiting once none is left; the workgroup stops when no wave has one.
+// 8x8 quadrant w.  Each wave walks the list on its own, in windows of
+// tile_window entries that its lanes stage into the wave's part of the batch
+// arrays (testing their reach of its quadrant only), so no wave waits for
+// another: per window, one ballot of the entries that reach the quadrant and
+// one of the CUTOFF entries, and the set bits visited in order.  A wave
+// re-takes its live pixels every 16 entries and stops once none is left.
 // kRegion: the clip region of p.plane_count half-spaces (chord_weight_region),
 // with each CUTOFF entry's further-plane terms staged in s_ext and the
 // per-frame rates of those planes in s_rate.
@@ -119,38 +132,40 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
     const bool strict = (p.plane_enabled & RARA_CLIP_STRICT_MISS) != 0;
     bool live = __ballot(thr < 1.0f) != 0ull;
 
-    constexpr int kB = batch_of<kRegion>();
-    for (uint32_t base = rg.x; base < rg.y; base += kB) {
-        if (!__syncthreads_or(live ? 1 : 0)) break;   // also: the previous batch has been read
-        const uint32_t idx = base + (uint32_t)tid;
+    constexpr uint32_t kW = tile_window<kRegion>();
+    // the region's per-frame plane rates, written by the first lanes of wave 0
+    if (kRegion) __syncthreads();
+    const uint32_t sub = (uint32_t)wave * kW;   // the wave's part of the batch arrays
+    for (uint32_t base = rg.x; base < rg.y && live; base += kW) {
+        const uint32_t idx = base + (uint32_t)lane;
+        const uint32_t slot = sub + (uint32_t)lane;
         float2 sc = make_float2(0.0f, 0.0f);   // label | quadrant mask << 8 = 0: reaches nothing
-        if (tid < kB && idx < rg.y) {
+        if ((uint32_t)lane < kW && idx < rg.y) {
             const uint32_t id = vals[idx];
             const Splat sp = splats[id];
             float4 sa, sb, c4;
             uint32_t qm;
-            stage_entry(sp, ox, oy, 0xfu, strict, sa, sb, c4, qm, id);
-            s_a[tid] = sa;
-            s_b[tid] = sb;
+            stage_entry(sp, ox, oy, 1u << wave, strict, sa, sb, c4, qm, id);
+            s_a[slot] = sa;
+            s_b[slot] = sb;
             sc = make_float2(c4.x, c4.y);
             if ((__float_as_uint(c4.y) & 0xffu) == RARA_LABEL_CUTOFF && plane_on) {
                 const float4* rr = reinterpret_cast<const float4*>(rays + id);
                 const float4 r0 = rr[0], r1 = rr[1], r2 = rr[2];
-                s_cut[tid].a = r0;
-                s_cut[tid].b = r1;
-                s_cut[tid].c = r2;
+                s_cut[slot].a = r0;
+                s_cut[slot].b = r1;
+                s_cut[slot].c = r2;
                 if (kRegion)
                     for (int k = 0; k < p.plane_count - 1; ++k)
-                        s_ext[tid * (kMaxPlanes - 1) + k] = ray_ext[(int64_t)id * (kMaxPlanes - 1) + k];
+                        s_ext[slot * (kMaxPlanes - 1) + k] = ray_ext[(int64_t)id * (kMaxPlanes - 1) + k];
             }
         }
-        if (tid < slots_of<kRegion>()) s_c[tid] = sc;
-        __syncthreads();
-        if (!live) continue;
-        const uint32_t cnt = rg.y - base < (uint32_t)kB ? rg.y - base : (uint32_t)kB;
-        const uint32_t kofs = base - rg.x + 1u;
-        for (uint32_t sub = 0; sub < cnt && live; sub += 64) {
-            const uint32_t lm = __float_as_uint(s_c[sub + lane].y);
+        if ((uint32_t)lane < kW) s_c[slot] = sc;
+        wave_sync();
+        // entry e of the arrays (e = sub + j) is list position kofs + e, 1-based (modulo 2^32)
+        const uint32_t kofs = base - rg.x + 1u - sub;
+        {
+            const uint32_t lm = (uint32_t)lane < kW ? __float_as_uint(s_c[sub + lane].y) : 0u;
             const uint64_t qb = __ballot((lm >> (8 + wave)) & 1u);
             const uint64_t cutb = __ballot(plane_on && (lm & 0xffu) == RARA_LABEL_CUTOFF);
             for (int chunk = 0; chunk < 64; chunk += 16) {
@@ -218,6 +233,7 @@ __device__ inline void blend_tile(const Splat* __restrict__ splats, const RayRec
                 if (!live) break;
             }
         }
+        wave_sync();   // the window has been read before the next one is staged
     }
 
     if (!inside) return;
@@ -512,7 +528,8 @@ __device__ __forceinline__ void blend_block(const Splat* __restrict__ splats, co
     __shared__ float2 s_rate[kMaxPlanes - 1];
     __shared__ uint8_t s_list[4 * 64];
     if (kRegion) {
-        // the further planes' per-frame rates; the first batch's barrier orders them before any visit
+        // the further planes' per-frame rates; a barrier orders them before any visit (the tile walk's
+        // opening one, or a unit's first batch)
         if (threadIdx.x < kMaxPlanes - 1) s_rate[threadIdx.x] = make_float2(p.xax[threadIdx.x], p.xay[threadIdx.x]);
     }
     if (quad >= 0) {

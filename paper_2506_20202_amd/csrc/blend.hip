@@ -77,15 +77,6 @@ template <bool kRegion> constexpr int slots_of() { return kRegion ? kRegionBatch
 template <bool kRegion> constexpr uint32_t tile_window() { return (uint32_t)batch_of<kRegion>() / 4u; }
 static_assert(tile_window<false>() <= 64 && tile_window<true>() <= 64, "a window is one ballot");
 
-// Orders the LDS accesses of a wave's lanes before and after it (no other wave
-// takes part).
-__device__ inline void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // One tile: thread t of wave w = t / 64 owns pixel (t % 8, (t / 8) % 8) of the
 // 8x8 quadrant w.  Each wave walks the list on its own, in windows of
 // tile_window entries that its lanes stage into the wave's part of the batch

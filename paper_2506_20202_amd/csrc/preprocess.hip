@@ -245,15 +245,6 @@ __device__ __forceinline__ Footprint preprocess_one(const GaussPtrs& g, const Ca
 
 constexpr int kPreThreads = 256;
 
-// Orders the LDS accesses of a wave's lanes before and after it (no other wave
-// takes part).
-__device__ inline void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // The 16-byte tile record of a Gaussian: its rectangle (as in rect; zero when
 // not drawn) and its listed-tile mask, so that one gather fetches both.
 __device__ inline ulonglong2 tile_record(const Footprint& f, uint64_t mask)

@@ -118,6 +118,15 @@ __device__ inline void load_sh(const GaussPtrs& g, int64_t i, float (&v)[3 * kCo
     }
 }
 
+// Orders the LDS accesses of a wave's lanes before and after it (no other wave
+// takes part).
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Position (row by row in the rectangle) of the n-th listed tile of a
 // rectangle with `area` tiles and listed-tile mask m.
 __device__ inline uint32_t listed_tile(uint64_t m, int area, uint32_t n)
